@@ -1,0 +1,327 @@
+"""Encrypted-statistics circuits of PP-STAT, oracle side.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/ref.py``).
+
+Each function below is one fixed sequence of CKKS operations.  The GPU library
+implements the same sequences independently; the two agree bit for bit because
+every operation is exact integer arithmetic on the same inputs and the sequence
+(including every level alignment and every constant) is fixed here:
+
+* binary operations on operands at different levels first bring the higher
+  one down to the lower level (``level_align``);
+* sums over lists fold left to right;
+* FP64 constants are formed exactly as written (e.g. ``1.0 / (B * n)``).
+
+Circuits (paper references):
+  mean_B      Mean(x, B) = sum x_i / (B n)                           Sec. 5.1
+  variance_B  Variance(x, B) = sum (x_i / (B sqrt n))^2 - Mean(x,B)^2  Sec. 5.1, Eq. 2
+  inv_sqrt    Chebyshev initial value (Alg. 3, Eq. 3) + Newton (Alg. 2, n = 2)
+  zscore      Alg. 4;  kurtosis Alg. 5;  skewness (mirror of Alg. 5, Sec. 5)
+  cv          Alg. 6 with a g_3-composition sign (Sec. 6.2)
+  pearson     Sec. 5.5: Cov * InvSqrt(Var x) * InvSqrt(Var y)
+
+Readings where the paper is silent or inconsistent:
+  * Newton (Alg. 2) is evaluated in a balanced order that costs two levels per
+    step: y2 = y*y, p1 = w2*y, p2 = p1*y2, y = 1.5 y - p2, with w2 = (B'/2) v
+    formed once.  Mathematically identical to Alg. 2 for n = 2.
+  * Alg. 3 squares the initial value for n == 1 (the text: Inv = InvSqrt^2);
+    for the inverse square root (n == 2) the Chebyshev value is used directly.
+  * Alg. 6 calls CryptoSqrt(var, B); since Variance(x, B) = Var/B^2 the factor
+    must be B^2, as in Alg. 4 and 5.  sqrt is evaluated as 2 * w2 * InvSqrt(v).
+  * The PCC circuit (deferred by the paper to another work) is
+    Cov * InvSqrt(Var x; Bx^2) * InvSqrt(Var y; By^2).
+  * Slots beyond the row count are zero; centred moments use a 1/n-valued row
+    mask (a constant when a ciphertext is full, a plaintext vector otherwise).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import cheb
+from .ref import Ciphertext, Oracle, galois_element
+
+
+@dataclass
+class InvSqrtCfg:
+    a: float = 1e-3
+    b: float = 1.0
+    degree: int = 7
+    iters: int = 3
+    coeffs: np.ndarray | None = None   # optional explicit c_0..c_d for B' = 1
+
+    def coeffs_for(self, Bp: float) -> np.ndarray:
+        if self.coeffs is not None:
+            base = np.asarray(self.coeffs, dtype=np.float64)
+            return base / math.sqrt(Bp)
+        return cheb.invsqrt_coeffs(self.a, self.b, self.degree, Bp)
+
+
+# ----------------------------------------------------------------------------
+# evaluators: encrypted (over the C oracle) and plain FP64 slots with levels
+# ----------------------------------------------------------------------------
+class EncEval:
+    """Evaluator over encrypted oracle ciphertexts."""
+
+    def __init__(self, O: Oracle, rlk, gkeys):
+        self.O, self.rlk, self.gkeys = O, rlk, gkeys
+        self.slots = O.P.slots
+
+    def level(self, x):
+        return x.level
+
+    def align(self, x, level):
+        return self.O.level_align(x, level)
+
+    def add(self, a, b):
+        return self.O.add(a, b)
+
+    def sub(self, a, b):
+        return self.O.sub(a, b)
+
+    def mul(self, a, b):
+        return self.O.mul(a, b, self.rlk)
+
+    def mul_const(self, a, c):
+        return self.O.mul_const(a, c)
+
+    def mul_int(self, a, k):
+        return self.O.mul_int(a, k)
+
+    def add_const(self, a, c):
+        return self.O.add_const(a, c)
+
+    def mul_vec(self, a, vec):
+        pt = self.O.encode(vec, a.level)
+        return self.O.mul_plain(a, pt)
+
+    def rotsum(self, a):
+        return self.O.rotsum(a, self.gkeys)
+
+
+class PlainEval:
+    """FP64 model: slot vectors carrying the same level bookkeeping."""
+
+    @dataclass
+    class V:
+        v: np.ndarray
+        level: int
+
+    def __init__(self, L, slots):
+        self.L, self.slots = L, slots
+
+    def fresh(self, values):
+        v = np.zeros(self.slots)
+        v[: len(values)] = values
+        return PlainEval.V(v, self.L)
+
+    def level(self, x):
+        return x.level
+
+    def align(self, x, level):
+        assert level <= x.level
+        return PlainEval.V(x.v, level)
+
+    def _chk(self, a, b):
+        assert a.level == b.level
+
+    def add(self, a, b):
+        self._chk(a, b)
+        return PlainEval.V(a.v + b.v, a.level)
+
+    def sub(self, a, b):
+        self._chk(a, b)
+        return PlainEval.V(a.v - b.v, a.level)
+
+    def mul(self, a, b):
+        self._chk(a, b)
+        assert a.level >= 1
+        return PlainEval.V(a.v * b.v, a.level - 1)
+
+    def mul_const(self, a, c):
+        assert a.level >= 1
+        return PlainEval.V(a.v * c, a.level - 1)
+
+    def mul_int(self, a, k):
+        return PlainEval.V(a.v * k, a.level)
+
+    def add_const(self, a, c):
+        return PlainEval.V(a.v + c, a.level)
+
+    def mul_vec(self, a, vec):
+        return PlainEval.V(a.v * np.asarray(vec), a.level - 1)
+
+    def rotsum(self, a):
+        return PlainEval.V(np.full(self.slots, a.v.sum()), a.level)
+
+
+# ----------------------------------------------------------------------------
+# circuits
+# ----------------------------------------------------------------------------
+class Circuits:
+    def __init__(self, ev):
+        self.ev = ev
+
+    # helpers ------------------------------------------------------------
+    def _lower(self, a, b):
+        ev = self.ev
+        m = min(ev.level(a), ev.level(b))
+        return ev.align(a, m), ev.align(b, m)
+
+    def addx(self, a, b):
+        return self.ev.add(*self._lower(a, b))
+
+    def subx(self, a, b):
+        return self.ev.sub(*self._lower(a, b))
+
+    def mulx(self, a, b):
+        return self.ev.mul(*self._lower(a, b))
+
+    def sumx(self, xs):
+        acc = xs[0]
+        for x in xs[1:]:
+            acc = self.addx(acc, x)
+        return acc
+
+    def mask_mean(self, zs, n):
+        """RotSum(sum_c Z_c * mask_c) with mask_c = 1/n on rows < n, else 0."""
+        S = self.ev.slots
+        terms = []
+        for c, z in enumerate(zs):
+            rows = min(S, n - c * S)
+            if rows == S:
+                terms.append(self.ev.mul_const(z, 1.0 / float(n)))
+            else:
+                vec = np.zeros(S)
+                vec[:rows] = 1.0 / float(n)
+                terms.append(self.ev.mul_vec(z, vec))
+        return self.ev.rotsum(self.sumx(terms))
+
+    # Sec. 5.1 -------------------------------------------------------------
+    def mean_B(self, X, n, B):
+        """Mean(x, B) = sum_i x_i / (B n)."""
+        c = 1.0 / (B * float(n))
+        return self.ev.rotsum(self.sumx([self.ev.mul_const(x, c) for x in X]))
+
+    def variance_B(self, X, n, B, mean_term):
+        """Variance(x, B) = sum (x_i / (B sqrt n))^2 - mean_term^2  (Eq. 2)."""
+        c = 1.0 / (B * math.sqrt(float(n)))
+        xs = [self.ev.mul_const(x, c) for x in X]
+        e2 = self.ev.rotsum(self.sumx([self.ev.mul(x, x) for x in xs]))
+        m2 = self.ev.mul(mean_term, mean_term)
+        return self.subx(e2, m2)
+
+    # Alg. 3 + Alg. 2 -------------------------------------------------------
+    def inv_sqrt(self, v, Bp, cfg: InvSqrtCfg):
+        """y ~ 1/sqrt(Bp v); returns (y, w2) with w2 = (Bp/2) v."""
+        ev = self.ev
+        a, b, d = cfg.a, cfg.b, cfg.degree
+        coeffs = cfg.coeffs_for(Bp)
+        t = ev.add_const(ev.mul_const(v, 2.0 / (b - a)), -(a + b) / (b - a))
+        T = {1: t}
+        for k in range(2, d + 1):
+            if k % 2 == 0:
+                m = k // 2
+                T[k] = ev.add_const(ev.mul_int(ev.mul(T[m], T[m]), 2), -1.0)
+            else:
+                m = (k - 1) // 2
+                T[k] = self.subx(ev.mul_int(self.mulx(T[m], T[m + 1]), 2), T[1])
+        y = self.sumx([ev.mul_const(T[k], float(coeffs[k])) for k in range(1, d + 1)])
+        y = ev.add_const(y, float(coeffs[0]))
+        w2 = ev.mul_const(v, Bp / 2.0)
+        for _ in range(cfg.iters):
+            y2 = ev.mul(y, y)
+            p1 = self.mulx(w2, y)
+            p2 = self.mulx(p1, y2)
+            y = self.subx(ev.mul_const(y, 1.5), p2)
+        return y, w2
+
+    def sqrt(self, v, Bp, cfg: InvSqrtCfg):
+        """sqrt(Bp v) = 2 * w2 * InvSqrt(v; Bp)."""
+        y, w2 = self.inv_sqrt(v, Bp, cfg)
+        return self.ev.mul_int(self.mulx(w2, y), 2)
+
+    def g3(self, x):
+        """g_3 at depth 3: u = x^2, w = u^2; each term puts its constant on x."""
+        ev = self.ev
+        u = ev.mul(x, x)
+        w = ev.mul(u, u)
+        a1 = ev.mul_const(x, 35.0 / 16.0)
+        a3 = self.mulx(ev.mul_const(x, -35.0 / 16.0), u)
+        a5 = self.mulx(ev.mul_const(x, 21.0 / 16.0), w)
+        a7 = self.mulx(self.mulx(ev.mul_const(x, -5.0 / 16.0), u), w)
+        return self.sumx([a1, a3, a5, a7])
+
+    def sign(self, x, k):
+        for _ in range(k):
+            x = self.g3(x)
+        return x
+
+    # statistics ------------------------------------------------------------
+    def _moments_prefix(self, X, n, B):
+        muB = self.mean_B(X, n, B)
+        var = self.variance_B(X, n, B, muB)
+        mu = self.ev.mul_const(muB, B)
+        return muB, var, mu
+
+    def zscore(self, X, n, B, cfg: InvSqrtCfg):
+        """Alg. 4: (X - mu) * InvSqrt(Variance(X, B); B^2), one output per ciphertext."""
+        _, var, mu = self._moments_prefix(X, n, B)
+        b, _ = self.inv_sqrt(var, B * B, cfg)
+        return [self.mulx(self.subx(x, mu), b) for x in X]
+
+    def kurtosis(self, X, n, B, cfg: InvSqrtCfg, excess=False):
+        """Alg. 5: Mean((X - mu)^4) * InvSqrt(Variance(X,B); B^2)^4."""
+        ev = self.ev
+        _, var, mu = self._moments_prefix(X, n, B)
+        x1 = [self.subx(x, mu) for x in X]
+        x2 = [ev.mul(x, x) for x in x1]
+        x4 = [ev.mul(x, x) for x in x2]
+        num = self.mask_mean(x4, n)
+        i, _ = self.inv_sqrt(var, B * B, cfg)
+        i2 = ev.mul(i, i)
+        i4 = ev.mul(i2, i2)
+        k = self.mulx(num, i4)
+        return ev.add_const(k, -3.0) if excess else k
+
+    def skewness(self, X, n, B, cfg: InvSqrtCfg):
+        """Mirror of Alg. 5: Mean((X - mu)^3) * InvSqrt(Variance(X,B); B^2)^3."""
+        ev = self.ev
+        _, var, mu = self._moments_prefix(X, n, B)
+        x1 = [self.subx(x, mu) for x in X]
+        x2 = [ev.mul(x, x) for x in x1]
+        x3 = [self.mulx(a, b) for a, b in zip(x2, x1)]
+        num = self.mask_mean(x3, n)
+        i, _ = self.inv_sqrt(var, B * B, cfg)
+        i2 = ev.mul(i, i)
+        i3 = self.mulx(i2, i)
+        return self.mulx(num, i3)
+
+    def cv(self, X, n, B_mean, B_var, cfg: InvSqrtCfg, sign_k=2):
+        """Alg. 6: Std * InvSqrt(mu * sign(mu); B_mean)^2 * sign(mu)."""
+        ev = self.ev
+        muB = self.mean_B(X, n, B_mean)
+        sg = self.sign(muB, sign_k)
+        ia, _ = self.inv_sqrt(self.mulx(muB, sg), B_mean, cfg)
+        mu_inv = ev.mul(ia, ia)
+        mean_term = muB if B_var == B_mean else ev.mul_const(muB, B_mean / B_var)
+        var = self.variance_B(X, n, B_var, mean_term)
+        sigma = self.sqrt(var, B_var * B_var, cfg)
+        return self.mulx(self.mulx(sigma, mu_inv), sg)
+
+    def pearson(self, X, Y, n, Bx, By, cfg: InvSqrtCfg):
+        """Sec. 5.5: Cov(X, Y) * InvSqrt(Var X; Bx^2) * InvSqrt(Var Y; By^2)."""
+        ev = self.ev
+        _, varx, mux = self._moments_prefix(X, n, Bx)
+        _, vary, muy = self._moments_prefix(Y, n, By)
+        prods = [self.mulx(self.subx(x, mux), self.subx(y, muy)) for x, y in zip(X, Y)]
+        cov = self.mask_mean(prods, n)
+        ix, _ = self.inv_sqrt(varx, Bx * Bx, cfg)
+        iy, _ = self.inv_sqrt(vary, By * By, cfg)
+        return self.mulx(cov, ev.mul(ix, iy))
+
+
+def rotsum_galois(N: int):
+    return [galois_element(1 << k, N) for k in range((N // 2).bit_length() - 1)]

@@ -1,0 +1,123 @@
+"""Pins of the oracle's CKKS operations: decryption identities, exact CRT
+checks of key switching and rescale, rotations (CPU only)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import ref
+
+
+@pytest.fixture(scope="module", params=["c1", "t1"])
+def env(request):
+    P = ref.Params.preset(request.param)
+    O = ref.Oracle(P)
+    sk, pk = O.keygen(1)
+    rlk = O.relin_key(sk, 2)
+    gk = O.rotation_keys(sk, 3, O.rotsum_steps() + [3, 5])
+    return P, O, sk, pk, rlk, gk
+
+
+def fresh_std(P):
+    """std of one slot's fresh public-key noise: N sigma sqrt(2/3) / Delta."""
+    return P.N * 3.2 * math.sqrt(2.0 / 3.0) / P.scale[P.L]
+
+
+def enc(O, pk, m, seed, level=None):
+    return O.encrypt(O.encode(m, level), pk, seed)
+
+
+def test_decrypt_encrypt(env):
+    P, O, sk, pk, *_ = env
+    m = np.random.default_rng(1).uniform(0, 1, P.slots)
+    ct = enc(O, pk, m, 10)
+    assert np.max(np.abs(O.decrypt(ct, sk) - m)) < 8 * fresh_std(P)
+    ct2 = O.encrypt_sk(O.encode(m), sk, 11)
+    assert np.max(np.abs(O.decrypt(ct2, sk) - m)) < 8 * fresh_std(P)
+
+
+def test_keyswitch_exact_crt(env):
+    """u0 + u1 s - d s' is a small integer polynomial (exact CRT over Q_l)."""
+    P, O, sk, pk, rlk, gk = env
+    l = P.L
+    rng = np.random.default_rng(2)
+    d = np.stack([rng.integers(0, P.q[i], P.N, dtype=np.uint64) for i in range(l + 1)])
+    u0, u1 = O.keyswitch(d, l, rlk)
+    res = np.zeros_like(u0)
+    for i in range(l + 1):
+        q = P.q[i]
+        s = sk.s_ntt[i]
+        s2 = ref._mulmod_vec(s, s, q)
+        lhs = (u0[i].astype(object) + ref._mulmod_vec(u1[i], s, q).astype(object)) % q
+        rhs = ref._mulmod_vec(d[i], s2, q).astype(object)
+        res[i] = ((lhs - rhs) % q).astype(np.uint64)
+    e = O.crt_centred(O.intt(res, list(range(l + 1))))
+    Q = 1
+    for q in P.q[: l + 1]:
+        Q *= q
+    ev = np.array([int(v) for v in e], dtype=np.float64)
+    assert np.max(np.abs(ev)) < 2 ** 12      # Q is at least 2^99 for both presets
+    assert Q > 2 ** 99
+    # ModDown rounds to nearest: no systematic offset (a floor would leave a
+    # mean near -(1 + sum s)/2 on every coefficient)
+    assert abs(ev.mean()) < 3.0
+
+
+def test_rescale_is_rounded_division(env):
+    """Rescale equals round(X / q_l) mod Q_{l-1}, X the CRT integer."""
+    P, O, sk, *_ = env
+    l = P.L
+    rng = np.random.default_rng(3)
+    X = np.stack([rng.integers(0, P.q[i], P.N, dtype=np.uint64) for i in range(l + 1)])
+    out = np.zeros((1, l, P.N), dtype=np.uint64)
+    ref.lib().orc_rescale(P.ref, ref._p(np.ascontiguousarray(X[None])), l, 1, ref._p(out))
+    xs = O.crt_centred(O.intt(X, list(range(l + 1))))
+    got = O.crt_centred(O.intt(out[0], list(range(l))))
+    ql = P.q[l]
+    Qm = 1
+    for q in P.q[:l]:
+        Qm *= q
+    for k in range(0, P.N, 97):
+        want = (2 * int(xs[k]) + ql) // (2 * ql)
+        assert (int(got[k]) - want) % Qm == 0
+
+
+def test_mul_add_const_ops(env):
+    P, O, sk, pk, rlk, gk = env
+    rng = np.random.default_rng(4)
+    a = rng.uniform(-1, 1, P.slots)
+    b = rng.uniform(-1, 1, P.slots)
+    ca, cb = enc(O, pk, a, 20), enc(O, pk, b, 21)
+    tol = 64 * fresh_std(P)
+    m = O.mul(ca, cb, rlk)
+    assert m.level == P.L - 1 and m.scale == P.scale[P.L - 1]
+    assert np.max(np.abs(O.decrypt(m, sk) - a * b)) < tol
+    assert np.max(np.abs(O.decrypt(O.mul_const(ca, -0.75), sk) + 0.75 * a)) < tol
+    assert np.max(np.abs(O.decrypt(O.add_const(ca, 0.25), sk) - (a + 0.25))) < tol
+    assert np.max(np.abs(O.decrypt(O.mul_int(ca, 3), sk) - 3 * a)) < tol
+    assert np.max(np.abs(O.decrypt(O.sub(ca, cb), sk) - (a - b))) < tol
+    pt = O.encode(b, P.L)
+    assert np.max(np.abs(O.decrypt(O.mul_plain(ca, pt), sk) - a * b)) < tol
+    al = O.level_align(ca, 0)
+    assert al.level == 0 and al.scale == P.scale[0]
+    assert np.max(np.abs(O.decrypt(al, sk) - a)) < tol
+    with pytest.raises(ref.LevelError):
+        O.add(ca, m)
+
+
+def test_rotations(env):
+    P, O, sk, pk, rlk, gk = env
+    m = np.random.default_rng(5).uniform(0, 1, P.slots)
+    ct = enc(O, pk, m, 30)
+    tol = 64 * fresh_std(P)
+    r3 = O.rotate(ct, 3, gk)
+    assert np.max(np.abs(O.decrypt(r3, sk) - np.roll(m, -3))) < tol
+    r35 = O.rotate(r3, 5, gk)
+    assert np.max(np.abs(O.decrypt(r35, sk) - np.roll(m, -8))) < tol
+    h = O.rotate_hoisted(ct, [3, 5], gk)
+    assert np.max(np.abs(O.decrypt(h[0], sk) - np.roll(m, -3))) < tol
+    assert np.max(np.abs(O.decrypt(h[1], sk) - np.roll(m, -5))) < tol
+    s = O.rotsum(ct, gk)
+    assert np.max(np.abs(O.decrypt(s, sk) - m.sum())) < m.sum() * 1e-4
+    with pytest.raises(KeyError):
+        O.rotate(ct, 7, gk)

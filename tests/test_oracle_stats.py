@@ -1,0 +1,170 @@
+"""Pins of the oracle's statistics layer: FP64 closed forms, the paper's
+Tab. 2 number, g_3, and the circuits (FP64 model and encrypted)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import cheb, circuits as C, ref, stats64 as S
+from paper_2508_12093_amd import synth
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+
+
+# --------------------------------------------------------------- closed forms
+def test_fp64_stat_closed_forms():
+    rng = np.random.default_rng(0)
+    x = rng.lognormal(0, 1, 5000)
+    z = S.zscore(x)
+    assert abs(z.mean()) < 1e-12 and abs(z.var() - 1) < 1e-12
+    assert abs(S.pearson(x, 3 * x + 2) - 1) < 1e-12
+    assert abs(S.pearson(x, -0.5 * x + 7) + 1) < 1e-12
+    sym = np.concatenate([x, -x])
+    assert abs(S.skewness(sym)) < 1e-12
+    two = np.array([-1.0, 1.0] * 100)
+    assert abs(S.kurtosis(two) - 1) < 1e-12 and abs(S.kurtosis(two, excess=True) + 2) < 1e-12
+    p = 0.2
+    b = np.array([1.0] * 200 + [0.0] * 800)
+    assert abs(S.kurtosis(b) - (1 - 3 * p * (1 - p)) / (p * (1 - p))) < 1e-12
+    assert abs(S.cv(4.0 * x) - S.cv(x)) < 1e-12
+    for f in (S.skewness, S.kurtosis, S.cv):
+        assert abs(f(2.5 * x) - f(x)) < 1e-10
+
+
+# --------------------------------------------------------- paper's numbers
+def test_tab2_cryptoinvsqrt_mre():
+    """Tab. 2: CryptoInvSqrt on the Exp-1 grid (B = 100, 6 Newton steps) has
+    MRE 5.08e-5.  The FP64 model with a degree-31 first-kind Chebyshev
+    initial value of Eq. 3 lands within 1% of it; degrees 30 and 32 do not."""
+    paper = GOLD["exp1_cryptoinvsqrt_mre"]["value"]
+    iters = GOLD["exp1_newton_iters"]["value"]
+    B = GOLD["exp1_B"]["value"]
+    g = GOLD["exp1_grid"]["value"]
+    grid = cheb.exp1_grid()
+    assert len(grid) == g["low"][2] + g["high"][2]
+    assert grid[0] == g["low"][0] and grid[-1] == g["high"][1]
+    assert abs(cheb.exp1_mre(31, iters, B) / paper - 1) < 0.01
+    for d in (30, 32):
+        assert abs(cheb.exp1_mre(d, iters, B) / paper - 1) > 0.1
+
+
+def test_g3_coefficients_and_shape():
+    gold = GOLD["g3_coeffs_times_16"]["value"]
+    for k, v in gold.items():
+        assert cheb.G3_COEFFS[int(k)] * 16 == v
+    x = np.linspace(-1, 1, 201)
+    assert np.allclose(cheb.g3(-x), -cheb.g3(x))
+    assert cheb.g3(1.0) == 1.0 and cheb.g3(-1.0) == -1.0
+    h = 1e-6       # g3'(x) = 35/16 (1 - x^2)^3
+    for t in (0.0, 0.3, 0.9):
+        d = (cheb.g3(t + h) - cheb.g3(t - h)) / (2 * h)
+        assert abs(d - 35 / 16 * (1 - t * t) ** 3) < 1e-6
+    assert 5e-5 < 1 - cheb.g3(cheb.g3(0.6)) < 1e-4
+
+
+def test_invsqrt_chebyshev_interpolates_and_newton_converges():
+    a, b, d = 1e-3, 1.0, 7
+    c = cheb.invsqrt_coeffs(a, b, d, 1.0)
+    nodes = np.cos(np.pi * (np.arange(d + 1) + 0.5) / (d + 1))
+    v = a + (b - a) * (nodes + 1) / 2
+    assert np.allclose(np.polynomial.chebyshev.chebval(nodes, c), 1 / np.sqrt(v), rtol=1e-12)
+    vs = np.linspace(0.0053, 1.0, 20000)
+    t = (2 * vs - a - b) / (b - a)
+    y0 = np.polynomial.chebyshev.chebval(t, c)
+    e2 = np.abs(cheb.newton_invsqrt(vs, y0, 2) * np.sqrt(vs) - 1)
+    e3 = np.abs(cheb.newton_invsqrt(vs, y0, 3) * np.sqrt(vs) - 1)
+    assert np.max(e3) < 5e-4                       # worst near v = 0.033
+    assert np.max(e3[vs >= 0.05]) < 1e-4
+    assert np.all(e3 <= 1.5 * e2 ** 2 * 1.01 + 1e-15)   # Newton's quadratic step
+    c20 = cheb.invsqrt_coeffs(a, b, d, 20.0)
+    assert np.allclose(c20, c / np.sqrt(20.0))
+
+
+# ------------------------------------------------------------- FP64 circuits
+def _levels_and_values(n=32768):
+    x, y = synth.binary_cost_pair(0, n)
+    ev = C.PlainEval(24, 32768)
+    cc = C.Circuits(ev)
+    cfg = C.InvSqrtCfg()
+    X, Y = [ev.fresh(x)], [ev.fresh(y)]
+    return x, y, {
+        "zscore": cc.zscore(Y, n, 20.0, cfg)[0],
+        "kurt": cc.kurtosis(Y, n, 20.0, cfg),
+        "skew": cc.skewness(Y, n, 20.0, cfg),
+        "cv": cc.cv(Y, n, 20.0, 20.0, cfg),
+        "pcc": cc.pearson(X, Y, n, 1.0, 20.0, cfg),
+    }
+
+
+def test_plain_circuits_match_fp64_and_depths():
+    x, y, r = _levels_and_values()
+    assert S.mre(r["zscore"].v, S.zscore(y)) < 1e-6
+    assert abs(r["kurt"].v[0] / S.kurtosis(y) - 1) < 1e-6
+    assert abs(r["skew"].v[0] / S.skewness(y) - 1) < 1e-6
+    assert abs(r["cv"].v[0] / S.cv(y) - 1) < 1e-6
+    assert abs(r["pcc"].v[0] / S.pearson(x, y) - 1) < 1e-5      # v_x = 0.16: Newton residual 1.2e-6
+    depth = {k: 24 - v.level for k, v in r.items()}
+    assert depth == {"zscore": 14, "kurt": 16, "skew": 16, "cv": 22, "pcc": 15}
+
+
+# ------------------------------------------------------ encrypted circuits
+@pytest.fixture(scope="module")
+def t2():
+    P = ref.Params.preset("t2")
+    O = ref.Oracle(P)
+    sk, pk = O.keygen(101)
+    rlk = O.relin_key(sk, 102)
+    gk = O.rotation_keys(sk, 103, O.rotsum_steps())
+    return P, O, sk, pk, C.Circuits(C.EncEval(O, rlk, gk))
+
+
+@pytest.mark.slow
+def test_encrypted_statistics_match_fp64(t2):
+    P, O, sk, pk, cc = t2
+    n = 1500                                   # ragged: 1500 of 2048 slots
+    x, y = synth.binary_cost_pair(0, n)
+    ex, ey = O.encrypt(O.encode(x), pk, 201), O.encrypt(O.encode(y), pk, 202)
+    cfg = C.InvSqrtCfg()
+    dec = lambda c: O.decrypt(c, sk)
+    assert abs(dec(cc.pearson([ex], [ey], n, 1.0, 20.0, cfg))[0] / S.pearson(x, y) - 1) < 1e-3
+    assert abs(dec(cc.kurtosis([ey], n, 20.0, cfg))[0] / S.kurtosis(y) - 1) < 1e-3
+    assert abs(dec(cc.skewness([ey], n, 20.0, cfg))[0] / S.skewness(y) - 1) < 1e-3
+    assert abs(dec(cc.cv([ey], n, 20.0, 20.0, cfg))[0] / S.cv(y) - 1) < 1e-3
+    z = dec(cc.zscore([ey], n, 20.0, cfg)[0])[:n]
+    assert S.mre(z, S.zscore(y)) < 1e-3
+
+
+@pytest.mark.slow
+def test_encrypted_closed_forms(t2):
+    P, O, sk, pk, cc = t2
+    n = P.slots
+    x = np.random.default_rng(8).uniform(0, 1, n)
+    ex = O.encrypt(O.encode(x), pk, 301)
+    ey = O.encrypt(O.encode(-2.0 * x + 1.5), pk, 302)
+    cfg = C.InvSqrtCfg()
+    pcc = O.decrypt(cc.pearson([ex], [ey], n, 1.0, 1.0, cfg), sk)[0]
+    assert abs(pcc + 1) < 1e-3
+    z = O.decrypt(cc.zscore([ex], n, 1.0, cfg)[0], sk)
+    assert abs(z.mean()) < 1e-3 and abs(z.var() - 1) < 1e-3
+    half = x[: n // 2]
+    sym = np.concatenate([half, 1.0 - half])   # symmetric about 0.5
+    es = O.encrypt(O.encode(sym), pk, 303)
+    assert abs(O.decrypt(cc.skewness([es], n, 1.0, cfg), sk)[0]) < 1e-3
+
+
+def test_config1_mean_variance():
+    """Config 1: N = 2^12, 2048 slots ~ U[0,1): Mean (B=1) and Variance (Eq. 2)."""
+    P = ref.Params.preset("c1")
+    O = ref.Oracle(P)
+    sk, pk = O.keygen(1)
+    rlk = O.relin_key(sk, 101)
+    gk = O.rotation_keys(sk, 102, O.rotsum_steps())
+    x = synth.uniform_column(1, P.slots)
+    ct = O.encrypt(O.encode(x), pk, 201)
+    cc = C.Circuits(C.EncEval(O, rlk, gk))
+    mu = cc.mean_B([ct], P.slots, 1.0)
+    var = cc.variance_B([ct], P.slots, 1.0, mu)
+    assert var.level == 0
+    assert abs(O.decrypt(mu, sk)[0] / S.mean(x) - 1) < 1e-3
+    assert abs(O.decrypt(var, sk)[0] / S.var(x) - 1) < 1e-3
