@@ -1,0 +1,313 @@
+/*
+ * ppstat.h -- C ABI of an MI355X (gfx950) implementation of the RNS-CKKS
+ * ciphertext arithmetic behind PP-STAT's encrypted statistics
+ * (H. Choi, "PP-STAT: An Efficient Privacy-Preserving Statistical Analysis
+ * Framework using Homomorphic Encryption", CIKM 2025).
+ *
+ * The paper's roles (Sec. 4): the client generates keys, encrypts its data
+ * with the public key and sends ciphertexts plus evaluation keys; the server
+ * evaluates statistics with pre-normalisation bounds B (Sec. 5.1); the client
+ * decrypts.  All three roles are available here.
+ *
+ * Conventions
+ *   - Every function returns PPST_OK (0) or a negative status; the message of
+ *     the last failure on the calling thread is ppst_last_error().
+ *   - Objects returned through `T** out` belong to the caller and are released
+ *     with the matching *_destroy function.  Inputs are borrowed for the call.
+ *   - Device work is enqueued on the context's HIP stream and is asynchronous;
+ *     functions that return host data (decode, export, *_sync) synchronise.
+ *     A context is used by one thread at a time.
+ *   - Polynomials are limb-major: limb i of a ciphertext polynomial at level l
+ *     holds N residues modulo q_i, i = 0..l, in the canonical NTT order in
+ *     which slot j holds a(psi_i^(2 brv(j) + 1)).  A ciphertext is
+ *     [2][l+1][N] uint64 words; every ciphertext at level l has the canonical
+ *     scale Delta_l (Delta_L = Delta, Delta_{l-1} = Delta_l^2 / q_l).
+ *   - Binary operations require equal levels (and hence scales); there is no
+ *     silent alignment: use ppst_level_align.
+ */
+#ifndef PPSTAT_H
+#define PPSTAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+enum {
+  PPST_OK = 0,
+  PPST_EINVAL = -1,   /* malformed argument (null pointer, size mismatch) */
+  PPST_ELEVEL = -2,   /* an operation would go below level 0 (Sec. 3.1: beyond the
+                         depth, decryption is not guaranteed) */
+  PPST_ESCALE = -3,   /* operands at different levels or scales */
+  PPST_ENOKEY = -4,   /* missing relinearisation or Galois key */
+  PPST_ENOMEM = -5,   /* device memory or serving budget exhausted */
+  PPST_EDEVICE = -6,  /* HIP runtime error */
+  PPST_EDOMAIN = -7   /* parameter outside the documented domain */
+};
+
+/* message of the last failure on this thread (valid until the next call) */
+const char* ppst_last_error(void);
+
+/* ------------------------------------------------------------- parameters */
+/* Ring degree N = 2^logN, L+1 ciphertext primes (q_0 of q0_bits bits, q_1..q_L
+ * chosen so that the scale stays at Delta), K special primes of p_bits bits
+ * for hybrid key switching with dnum digits, and the scale Delta.
+ * Presets: "c1" (N=2^12, 40/30/30-bit chain, Delta=2^30, one 60-bit special
+ * prime); "c2" (N=2^16, Delta=2^40, 24 scale primes + 60-bit q_0, 7 special
+ * primes, dnum=3: the paper's N, Delta and log2 PQ <= 1443 budget, Sec. 6.1);
+ * "t1", "t2" (N=2^12 test sets with the c2 prime shapes, L=6 and L=24). */
+typedef struct {
+  int32_t logN, L, K, dnum, q0_bits, p_bits;
+  double scale;
+} ppst_params;
+
+int ppst_params_preset(const char* name, ppst_params* out);
+
+/* Optional device-memory hooks.  alloc/free receive the context's stream and
+ * `user`; when absent the library allocates with hipMalloc and caches blocks
+ * per stream. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* stream, void* user);
+  void (*free)(void* ptr, size_t bytes, void* stream, void* user);
+  void* user;
+} ppst_device_hooks;
+
+/* Host-only derivations (no device needed): the combined prime list, the
+ * canonical scales and the 2N-th roots of a parameter set, following the
+ * prime rule of the presets (q_0 the largest prime < 2^q0_bits that is
+ * 1 mod 2N; q_L..q_1 the unused such prime nearest Delta_l^2 / Delta with
+ * Delta_{l-1} = Delta_l^2 / q_l; the K largest unused primes < 2^p_bits). */
+int ppst_params_derive(const ppst_params* params, uint64_t* primes, uint64_t* roots,
+                       double* scales, size_t cap);
+/* discrete-Gaussian sampler thresholds (19 entries), host only */
+int ppst_dg_thresholds(uint64_t* out, size_t cap);
+/* integer coefficients of the canonical-embedding encoding of n values at
+ * (level, Delta_level), host only (N outputs) */
+int ppst_encode_coeffs(const ppst_params* params, const double* values, size_t n, int32_t level,
+                       int64_t* out, size_t cap);
+/* SplitMix64 stream state for (seed, purpose, limb), host only */
+uint64_t ppst_stream_key(uint64_t seed, uint64_t purpose, uint64_t limb);
+
+typedef struct ppst_context ppst_context;
+typedef struct ppst_secret_key ppst_secret_key;
+typedef struct ppst_public_key ppst_public_key;
+typedef struct ppst_eval_keys ppst_eval_keys;
+typedef struct ppst_plaintext ppst_plaintext;
+typedef struct ppst_ciphertext ppst_ciphertext;
+
+/* Creates the primes, roots, twiddle and CRT tables on the current HIP device.
+ * stream: a hipStream_t to run on, or NULL for a private stream.
+ * hooks: may be NULL. */
+int ppst_context_create(const ppst_params* params, const ppst_device_hooks* hooks, void* stream,
+                        ppst_context** out);
+/* A second context sharing tables with `base`, running on its own stream. */
+int ppst_context_fork(const ppst_context* base, void* stream, ppst_context** out);
+int ppst_context_destroy(ppst_context* ctx);
+/* waits for all work enqueued on the context's stream */
+int ppst_sync(ppst_context* ctx);
+
+typedef struct {
+  int32_t logN, N, L, K, dnum, alpha, nprimes, slots;
+} ppst_info;
+int ppst_context_info(const ppst_context* ctx, ppst_info* out);
+/* combined prime list q_0..q_L, p_0..p_{K-1} (cap >= nprimes) */
+int ppst_context_primes(const ppst_context* ctx, uint64_t* out, size_t cap);
+/* canonical scales Delta_0..Delta_L (cap >= L+1) */
+int ppst_context_scales(const ppst_context* ctx, double* out, size_t cap);
+/* discrete-Gaussian thresholds of the sampler (19 entries), for auditing */
+int ppst_context_dg_table(const ppst_context* ctx, uint64_t* out, size_t cap);
+
+/* --------------------------------------------------------------- keys */
+/* Seeded key generation (client side, Sec. 4).  Randomness is a counter-based
+ * SplitMix64 stream keyed by (seed, purpose, limb): ternary s, uniform a
+ * drawn in NTT form, discrete Gaussian errors (sigma 3.2, |e| <= 19). */
+int ppst_keygen(ppst_context* ctx, uint64_t seed, ppst_secret_key** sk, ppst_public_key** pk);
+int ppst_secret_key_destroy(ppst_secret_key* sk);
+int ppst_public_key_destroy(ppst_public_key* pk);
+int ppst_evk_create(ppst_context* ctx, ppst_eval_keys** out);
+int ppst_evk_destroy(ppst_eval_keys* evk);
+/* relinearisation key (s^2 -> s) */
+int ppst_evk_add_relin(ppst_context* ctx, const ppst_secret_key* sk, uint64_t seed,
+                       ppst_eval_keys* evk);
+/* Galois keys for rotations by steps[i] slots (s(X^g) -> s, g = 5^r mod 2N) */
+int ppst_evk_add_galois(ppst_context* ctx, const ppst_secret_key* sk, const int32_t* steps,
+                        size_t n, uint64_t seed, ppst_eval_keys* evk);
+/* Galois keys for every power-of-two step below N/2 (what rotate-and-sum needs) */
+int ppst_evk_add_rotsum(ppst_context* ctx, const ppst_secret_key* sk, uint64_t seed,
+                        ppst_eval_keys* evk);
+/* copy a key to the host: galois = 0 selects the relinearisation key.
+ * Layout [dnum][2][nprimes][N] (b, a per digit, NTT form). */
+int ppst_evk_export(ppst_context* ctx, const ppst_eval_keys* evk, uint64_t galois, uint64_t* host,
+                    size_t cap_words);
+int ppst_pk_export(ppst_context* ctx, const ppst_public_key* pk, uint64_t* host, size_t cap_words);
+/* s in NTT form over every prime, [nprimes][N] */
+int ppst_sk_export(ppst_context* ctx, const ppst_secret_key* sk, uint64_t* host, size_t cap_words);
+
+/* ------------------------------------------------------------ plaintexts */
+/* Canonical-embedding encoding of n <= N/2 real values (the rest zero) at
+ * (level, Delta_level): coefficient k = round_half_away(Delta_level * p_k). */
+int ppst_encode(ppst_context* ctx, const double* values, size_t n, int32_t level,
+                ppst_plaintext** out);
+/* plaintext from signed integer coefficients (N of them), at a given scale */
+int ppst_plaintext_from_coeffs(ppst_context* ctx, const int64_t* coeffs, int32_t level,
+                               double scale, ppst_plaintext** out);
+/* integer coefficients of an encoded plaintext (N values) */
+int ppst_plaintext_coeffs(const ppst_plaintext* pt, int64_t* out, size_t cap);
+int ppst_plaintext_export(ppst_context* ctx, const ppst_plaintext* pt, uint64_t* host,
+                          size_t cap_words);
+/* decode slots (the centred lift uses q_0, or q_0 q_1 above level 0) */
+int ppst_decode(ppst_context* ctx, const ppst_plaintext* pt, double* out, size_t n);
+int ppst_plaintext_destroy(ppst_plaintext* pt);
+
+/* ----------------------------------------------------------- ciphertexts */
+/* public-key encryption (Sec. 4): (v b + e0 + m, v a + e1), v ternary */
+int ppst_encrypt(ppst_context* ctx, const ppst_public_key* pk, const ppst_plaintext* pt,
+                 uint64_t seed, ppst_ciphertext** out);
+/* secret-key encryption: (-a s + e + m, a) */
+int ppst_encrypt_sk(ppst_context* ctx, const ppst_secret_key* sk, const ppst_plaintext* pt,
+                    uint64_t seed, ppst_ciphertext** out);
+/* c0 + c1 s */
+int ppst_decrypt(ppst_context* ctx, const ppst_secret_key* sk, const ppst_ciphertext* ct,
+                 ppst_plaintext** out);
+int ppst_ciphertext_destroy(ppst_ciphertext* ct);
+int ppst_ct_info(const ppst_ciphertext* ct, int32_t* level, double* scale, int32_t* npoly);
+/* copy [npoly][level+1][N] words to / from the host */
+int ppst_ct_export(ppst_context* ctx, const ppst_ciphertext* ct, uint64_t* host, size_t cap_words);
+int ppst_ct_import(ppst_context* ctx, const uint64_t* host, int32_t level, double scale,
+                   int32_t npoly, ppst_ciphertext** out);
+/* device address of the residues (valid while the ciphertext lives) */
+int ppst_ct_device_ptr(const ppst_ciphertext* ct, uint64_t** out);
+
+/* ------------------------------------------------------------- evaluator */
+/* Add(C), Sub(C) (Sec. 3.1) */
+int ppst_add(ppst_context* ctx, const ppst_ciphertext* a, const ppst_ciphertext* b,
+             ppst_ciphertext** out);
+int ppst_sub(ppst_context* ctx, const ppst_ciphertext* a, const ppst_ciphertext* b,
+             ppst_ciphertext** out);
+/* Add(P) with a constant: adds round_half_away(c Delta_level) */
+int ppst_add_const(ppst_context* ctx, const ppst_ciphertext* a, double c, ppst_ciphertext** out);
+/* Mul(P) with a constant: multiply by round_half_away(c Delta_l), then rescale */
+int ppst_mul_const(ppst_context* ctx, const ppst_ciphertext* a, double c, ppst_ciphertext** out);
+/* multiply by a signed integer; no rescale, scale unchanged */
+int ppst_mul_int(ppst_context* ctx, const ppst_ciphertext* a, int64_t k, ppst_ciphertext** out);
+/* Mul(P) with a plaintext encoded at the ciphertext's level, then rescale */
+int ppst_mul_plain(ppst_context* ctx, const ppst_ciphertext* a, const ppst_plaintext* pt,
+                   ppst_ciphertext** out);
+/* Mul(C): tensor, relinearise (hybrid key switching), rescale: level l -> l-1 */
+int ppst_mul(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciphertext* a,
+             const ppst_ciphertext* b, ppst_ciphertext** out);
+/* the three steps of ppst_mul separately (tensor output has npoly = 3) */
+int ppst_tensor(ppst_context* ctx, const ppst_ciphertext* a, const ppst_ciphertext* b,
+                ppst_ciphertext** out);
+int ppst_relin(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciphertext* d,
+               ppst_ciphertext** out);
+int ppst_rescale(ppst_context* ctx, const ppst_ciphertext* a, ppst_ciphertext** out);
+/* Rot (Sec. 3.1): slot j of the result holds slot (j + r) mod N/2 */
+int ppst_rotate(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciphertext* a, int32_t r,
+                ppst_ciphertext** out);
+/* n rotations sharing one ModUp of c1 (the automorphism acts on the extended
+ * digits); a different but equally valid key switch than ppst_rotate */
+int ppst_rotate_hoisted(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciphertext* a,
+                        const int32_t* rs, size_t n, ppst_ciphertext** outs);
+/* rotate-and-sum: for k = 0..log2(N/2)-1, ct += rot(ct, 2^k); every slot then
+ * holds the sum of all slots (the sums of Eq. 2, Sec. 5.1) */
+int ppst_rotsum(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciphertext* a,
+                ppst_ciphertext** out);
+/* bring a ciphertext down to `level`: keep q_0..q_{level+1}, multiply by
+ * round(Delta_level q_{level+1} / Delta_l), rescale by q_{level+1} */
+int ppst_level_align(ppst_context* ctx, const ppst_ciphertext* a, int32_t level,
+                     ppst_ciphertext** out);
+/* n independent products a[i] * b[i] (same level): each stage of tensor,
+ * relinearisation and rescale runs once over the whole batch */
+int ppst_mul_batch(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciphertext* const* a,
+                   const ppst_ciphertext* const* b, size_t n, ppst_ciphertext** outs);
+
+/* ------------------------------------------------------------- statistics */
+/* CryptoInvSqrt configuration (Sec. 4, Alg. 2-3; Sec. 5.1, Eq. 3): Chebyshev
+ * initial value of degree `degree` for 1/sqrt(B' v) on [a, b] (first-kind
+ * interpolation), then `iters` Newton steps.  coeffs, when non-NULL, gives
+ * c_0..c_degree of 1/sqrt(v) on [a, b] (B' = 1), divided by sqrt(B') per call.
+ * sign_k: number of g_3 compositions of the sign in CV (Sec. 6.2). */
+typedef struct {
+  double a, b;
+  int32_t degree, iters, sign_k;
+  const double* coeffs;
+} ppst_invsqrt_cfg;
+/* a, b = 1e-3, 1; degree 7; 3 iterations; sign_k 2; coeffs NULL */
+int ppst_invsqrt_cfg_default(ppst_invsqrt_cfg* out);
+
+/* A column is `nct` ciphertexts at one level holding `nrows` values (slots
+ * past nrows are zero).  Each statistic writes ciphertexts whose every slot
+ * holds the result (ZNorm: one output per input ciphertext).
+ * Preconditions that cannot be checked on encrypted data (Var/B^2 and
+ * |mean|/B inside [a, b]) are the caller's (Sec. 5.1). */
+int ppst_stat_mean(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciphertext* const* col,
+                   size_t nct, size_t nrows, double B, ppst_ciphertext** out);          /* Mean/B */
+int ppst_stat_variance(ppst_context* ctx, const ppst_eval_keys* evk,
+                       const ppst_ciphertext* const* col, size_t nct, size_t nrows, double B,
+                       ppst_ciphertext** out);                                         /* Var/B^2 */
+int ppst_stat_zscore(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciphertext* const* col,
+                     size_t nct, size_t nrows, double B, const ppst_invsqrt_cfg* cfg,
+                     ppst_ciphertext** outs /* nct */);                                /* Alg. 4 */
+int ppst_stat_kurtosis(ppst_context* ctx, const ppst_eval_keys* evk,
+                       const ppst_ciphertext* const* col, size_t nct, size_t nrows, double B,
+                       const ppst_invsqrt_cfg* cfg, int32_t excess, ppst_ciphertext** out); /* Alg. 5 */
+int ppst_stat_skewness(ppst_context* ctx, const ppst_eval_keys* evk,
+                       const ppst_ciphertext* const* col, size_t nct, size_t nrows, double B,
+                       const ppst_invsqrt_cfg* cfg, ppst_ciphertext** out);
+int ppst_stat_cv(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciphertext* const* col,
+                 size_t nct, size_t nrows, double B_mean, double B_var, const ppst_invsqrt_cfg* cfg,
+                 ppst_ciphertext** out);                                               /* Alg. 6 */
+int ppst_stat_pearson(ppst_context* ctx, const ppst_eval_keys* evk,
+                      const ppst_ciphertext* const* colx, const ppst_ciphertext* const* coly,
+                      size_t nct, size_t nrows, double Bx, double By, const ppst_invsqrt_cfg* cfg,
+                      ppst_ciphertext** out);                                          /* Sec. 5.5 */
+
+/* ------------------------------------------------------------ raw kernels */
+/* In-place forward / inverse negacyclic NTT of `nlimbs` limbs of N words at
+ * device address `dev`; limb i uses combined prime first_prime + i (0..L are
+ * q_i, L+1.. the special primes).  Enqueued on the context stream. */
+int ppst_ntt_forward(ppst_context* ctx, uint64_t* dev, int32_t nlimbs, int32_t first_prime);
+int ppst_ntt_inverse(ppst_context* ctx, uint64_t* dev, int32_t nlimbs, int32_t first_prime);
+/* hipStream_t of the context */
+int ppst_context_stream(const ppst_context* ctx, void** stream);
+
+/* ---------------------------------------------------------------- serving */
+/* A server owns worker contexts (one HIP stream each) over resident columns
+ * and evaluation keys.  Queries are admitted while the number of in-flight
+ * queries is below `slots` and their estimated device memory fits within
+ * `hbm_budget` bytes; later queries wait in arrival order and are admitted as
+ * earlier ones finish, so their work overlaps on the device. */
+typedef struct ppst_server ppst_server;
+enum { PPST_Q_MEAN = 0, PPST_Q_VARIANCE = 1, PPST_Q_ZSCORE = 2, PPST_Q_CV = 3, PPST_Q_PEARSON = 4,
+       PPST_Q_SKEWNESS = 5, PPST_Q_KURTOSIS = 6 };
+typedef struct {
+  int32_t kind;
+  uint64_t col_x, col_y;     /* column handles; col_y only for Pearson */
+  double B, B2;              /* bounds: B (and By for Pearson, B_var for CV) */
+  ppst_invsqrt_cfg cfg;
+} ppst_query;
+typedef struct {
+  double t_submit, t_admit, t_done;   /* seconds, monotonic clock */
+  uint64_t bytes_reserved;
+} ppst_query_stats;
+int ppst_server_create(ppst_context* ctx, const ppst_eval_keys* evk, size_t hbm_budget,
+                       int32_t slots, ppst_server** out);
+/* the server keeps its own reference to the ciphertexts (they are copied) */
+int ppst_server_register_column(ppst_server* srv, const ppst_ciphertext* const* cts, size_t nct,
+                                size_t nrows, uint64_t* col_id);
+int ppst_server_submit(ppst_server* srv, const ppst_query* q, uint64_t* ticket);
+/* blocks until the query has finished; out receives the result ciphertext
+ * (ZNorm: the first output ciphertext).  Returns the query's own status. */
+int ppst_server_wait(ppst_server* srv, uint64_t ticket, ppst_ciphertext** out,
+                     ppst_query_stats* stats);
+int ppst_server_destroy(ppst_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PPSTAT_H */

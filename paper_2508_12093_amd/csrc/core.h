@@ -1,0 +1,255 @@
+// core.h -- internal types of the ppstat library (RNS-CKKS on gfx950).
+//
+// Layout conventions used everywhere:
+//   * a polynomial over a list of primes is limb-major: limb t occupies
+//     N consecutive uint64 residues in [0, q_t);
+//   * a ciphertext at level l is [npoly][l+1][N] (npoly = 2, or 3 after a
+//     tensor product), every polynomial in NTT form;
+//   * prime indices are "combined": 0..L are the ciphertext primes q_0..q_L,
+//     L+1..L+K the special primes p_0..p_{K-1} of hybrid key switching.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+namespace ppst {
+
+typedef uint64_t u64;
+typedef unsigned __int128 u128;
+
+constexpr int kMaxPrimes = 64;
+
+// -------------------------------------------------------------------------
+// errors: every entry point converts these into a status code + message
+// -------------------------------------------------------------------------
+enum Status {
+  ST_OK = 0, ST_EINVAL = -1, ST_ELEVEL = -2, ST_ESCALE = -3, ST_ENOKEY = -4, ST_ENOMEM = -5,
+  ST_EDEVICE = -6, ST_EDOMAIN = -7
+};
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define PPST_THROW(code, msg) throw ::ppst::Error((code), (msg))
+#define HIP_CHECK(expr)                                                          \
+  do {                                                                           \
+    hipError_t _e = (expr);                                                      \
+    if (_e != hipSuccess)                                                        \
+      PPST_THROW(::ppst::ST_EDEVICE, std::string(#expr " failed: ") + hipGetErrorString(_e)); \
+  } while (0)
+
+// -------------------------------------------------------------------------
+// host modular arithmetic (64-bit residues, 128-bit products)
+// -------------------------------------------------------------------------
+inline u64 h_mulmod(u64 a, u64 b, u64 q) { return (u64)(((u128)a * b) % q); }
+inline u64 h_addmod(u64 a, u64 b, u64 q) { u64 s = a + b; return s >= q ? s - q : s; }
+inline u64 h_submod(u64 a, u64 b, u64 q) { return a >= b ? a - b : a + (q - b); }
+u64 h_powmod(u64 b, u64 e, u64 q);
+inline u64 h_invmod(u64 a, u64 q) { return h_powmod(a % q, q - 2, q); }
+inline u64 h_signed_mod(int64_t x, u64 q) {
+  if (x >= 0) return (u64)x % q;
+  u64 m = (u64)(-(x + 1)) % q;
+  return q - 1 - m;
+}
+// floor(w * 2^64 / q): the Shoup companion of a constant w < q
+inline u64 shoup(u64 w, u64 q) { return (u64)(((u128)w << 64) / q); }
+
+// -------------------------------------------------------------------------
+// parameters
+// -------------------------------------------------------------------------
+struct ParamSpec {
+  int logN = 0, L = 0, K = 0, dnum = 0, q0_bits = 0, p_bits = 0;
+  double scale = 0.0;
+};
+
+struct Params {
+  ParamSpec spec;
+  int logN = 0, N = 0, L = 0, K = 0, dnum = 0, alpha = 0, nprimes = 0;
+  std::vector<u64> q;         // combined: q_0..q_L, p_0..p_{K-1}
+  std::vector<u64> psi;       // primitive 2N-th roots
+  std::vector<double> scale;  // Delta_l, l = 0..L
+  int slots() const { return N / 2; }
+  int digit_lo(int j) const { return j * alpha; }
+  int digit_hi(int j, int level) const {  // one past the last limb of digit j at level
+    int h = (j + 1) * alpha;
+    return h < level + 1 ? h : level + 1;
+  }
+  int beta(int level) const { return (level + 1 + alpha - 1) / alpha; }
+};
+
+Params make_params(const ParamSpec& s);
+bool preset_spec(const std::string& name, ParamSpec* out);
+bool is_prime_u64(u64 n);
+
+// -------------------------------------------------------------------------
+// seeded sampling specification (counter-based SplitMix64)
+// -------------------------------------------------------------------------
+enum Purpose : u64 {
+  P_SK = 1, P_PK_A = 2, P_PK_E = 3, P_KSK_A = 4, P_KSK_E = 5,
+  P_ENC_V = 6, P_ENC_E0 = 7, P_ENC_E1 = 8, P_SKE_A = 9, P_SKE_E = 10
+};
+inline u64 purpose_code(u64 tag, u64 keyid, u64 digit) { return (tag << 40) | (keyid << 8) | digit; }
+u64 stream_key(u64 seed, u64 purpose, u64 limb);
+constexpr int kDgMax = 19;                  // |e| <= 19 (about 6 sigma)
+void dg_thresholds(u64 thr[kDgMax]);        // cumulative thresholds, x = 0..18
+
+// -------------------------------------------------------------------------
+// encoding (host, extended precision)
+// -------------------------------------------------------------------------
+void encode_coeffs(const Params& P, const double* m, int n_used, double scale, int64_t* out);
+void decode_coeffs(const Params& P, const long double* coeffs, double scale, double* out, int n);
+
+// -------------------------------------------------------------------------
+// device prime descriptor: q and R = floor(2^128 / q) for 128-bit Barrett
+// -------------------------------------------------------------------------
+struct Mod {
+  u64 q;
+  u64 r_hi, r_lo;
+};
+
+// -------------------------------------------------------------------------
+// device memory: a caching pool on one stream, optionally backed by caller
+// hooks (e.g. a framework's caching allocator)
+// -------------------------------------------------------------------------
+struct Hooks {
+  void* (*alloc)(size_t bytes, void* stream, void* user) = nullptr;
+  void (*free)(void* ptr, size_t bytes, void* stream, void* user) = nullptr;
+  void* user = nullptr;
+};
+
+class Pool {
+ public:
+  Pool(hipStream_t s, const Hooks& h) : stream_(s), hooks_(h) {}
+  ~Pool();
+  void* get(size_t bytes);
+  void put(void* p, size_t bytes);
+  size_t in_use() const { return in_use_; }
+  size_t cached() const { return cached_; }
+  void trim();
+ private:
+  hipStream_t stream_;
+  Hooks hooks_;
+  std::mutex mu_;
+  std::multimap<size_t, void*> free_;
+  std::map<void*, size_t> sizes_;
+  size_t in_use_ = 0, cached_ = 0;
+};
+
+struct Buf {
+  u64* p = nullptr;
+  size_t bytes = 0;
+  std::shared_ptr<Pool> pool;
+  Buf() = default;
+  Buf(std::shared_ptr<Pool> pl, size_t nbytes) : bytes(nbytes), pool(std::move(pl)) {
+    p = (u64*)pool->get(nbytes);
+  }
+  Buf(const Buf&) = delete;
+  Buf& operator=(const Buf&) = delete;
+  Buf(Buf&& o) noexcept : p(o.p), bytes(o.bytes), pool(std::move(o.pool)) { o.p = nullptr; o.bytes = 0; }
+  Buf& operator=(Buf&& o) noexcept {
+    release();
+    p = o.p; bytes = o.bytes; pool = std::move(o.pool);
+    o.p = nullptr; o.bytes = 0;
+    return *this;
+  }
+  ~Buf() { release(); }
+  void release() {
+    if (p && pool) pool->put(p, bytes);
+    p = nullptr;
+    bytes = 0;
+  }
+};
+
+// -------------------------------------------------------------------------
+// per-device constant tables shared by every context of one parameter set
+// -------------------------------------------------------------------------
+struct Tables {
+  Buf mods;        // Mod[nprimes]
+  Buf fwd;         // [nprimes][N][2] (w, w') with w = psi^brv(k)
+  Buf inv;         // [nprimes][N][2] (w, w') with w = psi^-brv(k)
+  Buf ninv;        // [nprimes][2] (N^-1, Shoup)
+  // ModUp constants per (level, digit): see modup_consts()
+  std::map<std::pair<int, int>, std::shared_ptr<Buf>> modup;
+  // ModDown constants (one table for all levels)
+  Buf moddown;
+  // rescale constants per level
+  std::map<int, std::shared_ptr<Buf>> rescale;
+  std::mutex mu;
+};
+
+struct Shared {
+  Params P;
+  int device = 0;
+  Hooks hooks;
+  std::shared_ptr<Pool> const_pool;  // long-lived tables and keys
+  Tables tab;
+  u64 dg_thr[kDgMax];
+};
+
+struct Context;
+struct Ciphertext {
+  Buf buf;          // [npoly][level+1][N]
+  int level = 0;
+  double scale = 0;
+  int npoly = 2;
+  int N = 0;
+  u64* poly(int c) const { return buf.p + (size_t)c * (level + 1) * N; }
+};
+struct Plaintext {
+  Buf buf;          // [level+1][N], NTT form
+  int level = 0;
+  double scale = 0;
+  std::vector<int64_t> coeffs;   // integer coefficients when produced by encode
+};
+struct SecretKey {
+  std::vector<int8_t> s;   // ternary coefficients (host)
+  Buf s_ntt;               // [nprimes][N]
+};
+struct PublicKey {
+  Buf pk;                  // [2][L+1][N]
+};
+struct KsKey {
+  Buf k;                   // [dnum][2][nprimes][N]
+};
+struct EvalKeys {
+  std::shared_ptr<KsKey> relin;
+  std::map<u64, std::shared_ptr<KsKey>> galois;   // keyed by Galois element
+};
+
+struct Context {
+  std::shared_ptr<Shared> sh;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::shared_ptr<Pool> pool;    // temporaries and results on this stream
+  const Params& P() const { return sh->P; }
+};
+
+// -------------------------------------------------------------------------
+// kernel launchers (kernels.hip)
+// -------------------------------------------------------------------------
+// One NTT "task" is one limb: source/destination limb offsets (in units of N
+// words) relative to the base pointers of the launch, and its prime index.
+struct LimbTask {
+  uint32_t src, dst, prime;
+};
+
+void launch_ntt(const Shared& sh, const u64* src, u64* dst, const LimbTask* tasks_dev, int ntasks,
+                int nbatch, size_t batch_stride, bool inverse, hipStream_t st);
+// convenience: contiguous limbs with primes first_prime.. (or a map)
+void ntt_contig(Context& cx, u64* data, int nlimbs, const int* primes, bool inverse,
+                int nbatch = 1, size_t batch_stride = 0);
+
+std::string ntt_config_string(const Shared& sh);
+void ntt_select(Shared& sh, int variant);  // autotuner hook
+
+}  // namespace ppst

@@ -1,0 +1,64 @@
+// dev.h -- device-side modular arithmetic and kernel argument structs.
+#pragma once
+
+#include "core.h"
+
+namespace ppst {
+
+// high 64 bits of a 64x64 product
+__device__ __forceinline__ u64 mulhi(u64 a, u64 b) { return __umul64hi(a, b); }
+
+// a * w mod q with the Shoup companion wp = floor(w 2^64 / q); result in [0, 2q)
+__device__ __forceinline__ u64 mul_shoup_lazy(u64 a, u64 w, u64 wp, u64 q) {
+  return a * w - mulhi(a, wp) * q;
+}
+__device__ __forceinline__ u64 csub(u64 x, u64 q) { return x >= q ? x - q : x; }
+__device__ __forceinline__ u64 mul_shoup(u64 a, u64 w, u64 wp, u64 q) {
+  return csub(mul_shoup_lazy(a, w, wp, q), q);
+}
+__device__ __forceinline__ u64 addm(u64 a, u64 b, u64 q) { return csub(a + b, q); }
+__device__ __forceinline__ u64 subm(u64 a, u64 b, u64 q) { return a >= b ? a - b : a + q - b; }
+
+// x = hi 2^64 + lo, x < 2^124, reduced mod q (q < 2^62) with R = floor(2^128/q):
+// the quotient estimate hi(x R / 2^128) is at most 2 below floor(x/q).
+__device__ __forceinline__ u64 reduce128(u64 hi, u64 lo, const Mod& m) {
+  u64 t0 = mulhi(lo, m.r_lo);
+  u64 p1_lo = lo * m.r_hi, p1_hi = mulhi(lo, m.r_hi);
+  u64 p2_lo = hi * m.r_lo, p2_hi = mulhi(hi, m.r_lo);
+  u64 s = t0 + p1_lo;
+  u64 c = s < t0;
+  u64 s2 = s + p2_lo;
+  c += s2 < s;
+  u64 quo = p1_hi + p2_hi + c + hi * m.r_hi;
+  u64 r = lo - quo * m.q;
+  r = csub(r, m.q);
+  return csub(r, m.q);
+}
+__device__ __forceinline__ u64 mulm(u64 a, u64 b, const Mod& m) {
+  return reduce128(mulhi(a, b), a * b, m);
+}
+// 128-bit accumulator
+struct Acc {
+  u64 hi = 0, lo = 0;
+  __device__ __forceinline__ void mac(u64 a, u64 b) {
+    u64 l = a * b;
+    u64 h = mulhi(a, b);
+    lo += l;
+    hi += h + (lo < l);
+  }
+};
+// x < 2^64 reduced mod q by one Barrett step (floor(2^64/q) = r_hi)
+__device__ __forceinline__ u64 reduce64(u64 x, const Mod& m) {
+  u64 quo = mulhi(x, m.r_hi);
+  u64 r = x - quo * m.q;
+  r = csub(r, m.q);
+  return csub(r, m.q);
+}
+
+// limb t -> combined prime index: t < nq ? t : pofs + (t - nq)
+struct PrimeMap {
+  int nq, pofs;
+  __device__ __forceinline__ int operator()(int t) const { return t < nq ? t : pofs + (t - nq); }
+};
+
+}  // namespace ppst

@@ -1,0 +1,874 @@
+// eval.cpp -- context, tables, keys, encryption and the RNS-CKKS operations.
+#include "eval.h"
+
+#include <cmath>
+
+#include "kern.h"
+#include "tables.h"
+
+namespace ppst {
+
+// =========================================================== memory pool
+Pool::~Pool() { trim(); }
+
+void* Pool::get(size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  bytes = (bytes + 4095) & ~(size_t)4095;
+  {
+    std::lock_guard<std::mutex> g(mu_);
+    auto it = free_.lower_bound(bytes);
+    if (it != free_.end() && it->first <= bytes + bytes / 4) {
+      void* p = it->second;
+      size_t sz = it->first;
+      free_.erase(it);
+      cached_ -= sz;
+      in_use_ += sz;
+      // remember the real block size
+      sizes_[p] = sz;
+      return p;
+    }
+  }
+  void* p = nullptr;
+  auto try_alloc = [&]() -> bool {
+    if (hooks_.alloc) {
+      p = hooks_.alloc(bytes, (void*)stream_, hooks_.user);
+      return p != nullptr;
+    }
+    return hipMalloc(&p, bytes) == hipSuccess;
+  };
+  if (!try_alloc()) {
+    (void)hipGetLastError();
+    trim();
+    if (!try_alloc()) {
+      (void)hipGetLastError();
+      PPST_THROW(ST_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+  }
+  std::lock_guard<std::mutex> g(mu_);
+  in_use_ += bytes;
+  sizes_[p] = bytes;
+  return p;
+}
+
+void Pool::put(void* p, size_t) {
+  std::lock_guard<std::mutex> g(mu_);
+  auto it = sizes_.find(p);
+  size_t sz = it->second;
+  sizes_.erase(it);
+  in_use_ -= sz;
+  cached_ += sz;
+  free_.emplace(sz, p);
+}
+
+void Pool::trim() {
+  std::lock_guard<std::mutex> g(mu_);
+  if (!free_.empty()) (void)hipStreamSynchronize(stream_);
+  for (auto& kv : free_) {
+    if (hooks_.free) hooks_.free(kv.second, kv.first, (void*)stream_, hooks_.user);
+    else (void)hipFree(kv.second);
+  }
+  free_.clear();
+  cached_ = 0;
+}
+
+namespace {
+
+Buf dev_buf(const std::shared_ptr<Pool>& pool, size_t words) { return Buf(pool, words * 8); }
+
+Buf upload(const std::shared_ptr<Pool>& pool, const std::vector<u64>& v) {
+  Buf b = dev_buf(pool, v.size());
+  HIP_CHECK(hipMemcpy(b.p, v.data(), v.size() * 8, hipMemcpyHostToDevice));
+  return b;
+}
+
+unsigned brv(unsigned x, int bits) {
+  unsigned r = 0;
+  for (int i = 0; i < bits; ++i) r |= ((x >> i) & 1u) << (bits - 1 - i);
+  return r;
+}
+
+}  // namespace
+
+// ============================================================== tables
+void build_tables(Shared& sh) {
+  const Params& P = sh.P;
+  const int N = P.N, np = P.nprimes;
+  auto& pool = sh.const_pool;
+  std::vector<u64> mods(3 * np);
+  for (int i = 0; i < np; ++i) {
+    u128 R = (~(u128)0) / P.q[i];
+    mods[3 * i] = P.q[i];
+    mods[3 * i + 1] = (u64)(R >> 64);
+    mods[3 * i + 2] = (u64)R;
+  }
+  sh.tab.mods = upload(pool, mods);
+
+  std::vector<u64> fwd((size_t)np * N * 2), inv((size_t)np * N * 2), ninv(2 * np);
+  for (int i = 0; i < np; ++i) {
+    u64 q = P.q[i], psi = P.psi[i], ipsi = h_invmod(psi, q);
+    u64 a = 1, b = 1;
+    for (int k = 0; k < N; ++k) {
+      size_t pos = ((size_t)i * N + brv((unsigned)k, P.logN)) * 2;
+      fwd[pos] = a;
+      fwd[pos + 1] = shoup(a, q);
+      inv[pos] = b;
+      inv[pos + 1] = shoup(b, q);
+      a = h_mulmod(a, psi, q);
+      b = h_mulmod(b, ipsi, q);
+    }
+    u64 ni = h_invmod((u64)N % q, q);
+    ninv[2 * i] = ni;
+    ninv[2 * i + 1] = shoup(ni, q);
+  }
+  sh.tab.fwd = upload(pool, fwd);
+  sh.tab.inv = upload(pool, inv);
+  sh.tab.ninv = upload(pool, ninv);
+
+  // ModDown
+  const int L = P.L, K = P.K;
+  MdLayout lay(K, L);
+  std::vector<u64> md(lay.size());
+  for (int k = 0; k < K; ++k) {
+    u64 pk = P.q[L + 1 + k];
+    u64 ph = 1;
+    for (int k2 = 0; k2 < K; ++k2)
+      if (k2 != k) ph = h_mulmod(ph, P.q[L + 1 + k2] % pk, pk);
+    u64 phi = h_invmod(ph, pk);
+    md[lay.phinv(k)] = phi;
+    md[lay.phinv(k) + 1] = shoup(phi, pk);
+    for (int i = 0; i <= L; ++i) {
+      u64 qi = P.q[i], v = 1;
+      for (int k2 = 0; k2 < K; ++k2)
+        if (k2 != k) v = h_mulmod(v, P.q[L + 1 + k2] % qi, qi);
+      md[lay.phat(k, i)] = v;
+    }
+  }
+  for (int i = 0; i <= L; ++i) {
+    u64 qi = P.q[i], pm = 1;
+    for (int k = 0; k < K; ++k) pm = h_mulmod(pm, P.q[L + 1 + k] % qi, qi);
+    u64 pinv = h_invmod(pm, qi);
+    md[lay.pinv(i)] = pinv;
+    md[lay.pinv(i) + 1] = shoup(pinv, qi);
+  }
+  for (int p = 0; p < np; ++p) {   // h = (P - 1) / 2 reduced mod every prime
+    u64 q = P.q[p], pm = 1;
+    for (int k = 0; k < K; ++k) pm = h_mulmod(pm, P.q[L + 1 + k] % q, q);
+    md[lay.hmod(p)] = h_mulmod(h_submod(pm, 1, q), h_invmod(2, q), q);
+  }
+  sh.tab.moddown = upload(pool, md);
+
+  // ModUp per (level, digit)
+  for (int l = 0; l <= L; ++l) {
+    const int nl = l + 1, ne = nl + K;
+    for (int j = 0; j < P.beta(l); ++j) {
+      const int lo = P.digit_lo(j), hi = P.digit_hi(j, l);
+      std::vector<u64> t(2 * P.alpha + (size_t)P.alpha * ne, 0);
+      for (int i = lo; i < hi; ++i) {
+        u64 qi = P.q[i], qh = 1;
+        for (int i2 = lo; i2 < hi; ++i2)
+          if (i2 != i) qh = h_mulmod(qh, P.q[i2] % qi, qi);
+        u64 inv_ = h_invmod(qh, qi);
+        t[2 * (i - lo)] = inv_;
+        t[2 * (i - lo) + 1] = shoup(inv_, qi);
+        for (int tt = 0; tt < ne; ++tt) {
+          int p = tt < nl ? tt : L + 1 + (tt - nl);
+          u64 qt = P.q[p], v = 1;
+          for (int i2 = lo; i2 < hi; ++i2)
+            if (i2 != i) v = h_mulmod(v, P.q[i2] % qt, qt);
+          t[2 * P.alpha + (size_t)(i - lo) * ne + tt] = v;
+        }
+      }
+      sh.tab.modup[{l, j}] = std::make_shared<Buf>(upload(pool, t));
+    }
+  }
+  // rescale per level
+  for (int l = 1; l <= L; ++l) {
+    std::vector<u64> t(3 * (size_t)l);
+    u64 ql = P.q[l];
+    for (int i = 0; i < l; ++i) {
+      u64 qi = P.q[i];
+      u64 inv_ = h_invmod(ql % qi, qi);
+      t[3 * i] = inv_;
+      t[3 * i + 1] = shoup(inv_, qi);
+      t[3 * i + 2] = ql % qi;
+    }
+    sh.tab.rescale[l] = std::make_shared<Buf>(upload(pool, t));
+  }
+}
+
+const u64* modup_table(const Shared& sh, int level, int digit) {
+  auto it = sh.tab.modup.find({level, digit});
+  if (it == sh.tab.modup.end()) PPST_THROW(ST_EINVAL, "no ModUp table");
+  return it->second->p;
+}
+const u64* rescale_table(const Shared& sh, int level) {
+  auto it = sh.tab.rescale.find(level);
+  if (it == sh.tab.rescale.end()) PPST_THROW(ST_EINVAL, "no rescale table");
+  return it->second->p;
+}
+
+// ============================================================ contexts
+std::shared_ptr<Shared> make_shared_state(const ParamSpec& spec, const Hooks* hooks) {
+  auto sh = std::make_shared<Shared>();
+  sh->P = make_params(spec);
+  HIP_CHECK(hipGetDevice(&sh->device));
+  if (hooks) sh->hooks = *hooks;
+  sh->const_pool = std::make_shared<Pool>((hipStream_t)0, sh->hooks);
+  dg_thresholds(sh->dg_thr);
+  build_tables(*sh);
+  HIP_CHECK(hipDeviceSynchronize());
+  return sh;
+}
+
+std::unique_ptr<Context> make_context(std::shared_ptr<Shared> sh, hipStream_t stream) {
+  auto cx = std::make_unique<Context>();
+  cx->sh = std::move(sh);
+  if (stream) {
+    cx->stream = stream;
+  } else {
+    HIP_CHECK(hipStreamCreateWithFlags(&cx->stream, hipStreamNonBlocking));
+    cx->own_stream = true;
+  }
+  cx->pool = std::make_shared<Pool>(cx->stream, cx->sh->hooks);
+  return cx;
+}
+
+void destroy_context(Context* cx) {
+  if (!cx) return;
+  (void)hipStreamSynchronize(cx->stream);
+  cx->pool.reset();
+  if (cx->own_stream) (void)hipStreamDestroy(cx->stream);
+}
+
+u64 galois_elt(const Params& P, long r) {
+  const long n = P.N / 2;
+  long rr = ((r % n) + n) % n;
+  return h_powmod(5, (u64)rr, 2 * (u64)P.N);
+}
+
+// =============================================================== helpers
+namespace {
+
+inline size_t limb_words(const Params& P) { return (size_t)P.N; }
+
+void ntt_ct_limbs(Context& cx, u64* data, int nl, int npoly, size_t stride, bool inverse) {
+  NttLaunch L{};
+  L.src = data;
+  L.dst = data;
+  L.nlimbs = nl;
+  L.nbatch = npoly;
+  L.batch_stride = stride;
+  L.nq = nl;
+  L.pofs = cx.P().L + 1;
+  ntt(*cx.sh, L, inverse, cx.stream);
+}
+
+void require_same(const Ciphertext& a, const Ciphertext& b) {
+  if (a.level != b.level)
+    PPST_THROW(ST_ESCALE, "operands at different levels (" + std::to_string(a.level) + " vs " +
+                           std::to_string(b.level) + ")");
+  if (a.scale != b.scale) PPST_THROW(ST_ESCALE, "operands at different scales");
+  if (a.npoly != 2 || b.npoly != 2) PPST_THROW(ST_EINVAL, "expected degree-1 ciphertexts");
+}
+
+const KsKey& relin_key(const EvalKeys& evk) {
+  if (!evk.relin) PPST_THROW(ST_ENOKEY, "no relinearisation key");
+  return *evk.relin;
+}
+const KsKey& galois_key(const EvalKeys& evk, u64 g) {
+  auto it = evk.galois.find(g);
+  if (it == evk.galois.end()) PPST_THROW(ST_ENOKEY, "no Galois key for element " + std::to_string(g));
+  return *it->second;
+}
+
+// Hybrid key switching of nbatch inputs d (NTT form, level l, stride sd).
+// out (stride so) = (add0 + u0, add1 + u1) with u0 + u1 s ~ d s'.
+void keyswitch(Context& cx, const KsKey& key, const u64* d, size_t sd, int level,
+               const u64* add0, const u64* add1, size_t sa, u64* out, size_t so, int nbatch) {
+  const Params& P = cx.P();
+  const Shared& sh = *cx.sh;
+  const int N = P.N, nl = level + 1, K = P.K, ne = nl + K, beta = P.beta(level);
+  const size_t sx = (size_t)nl * N, sext = (size_t)beta * ne * N, su = 2 * (size_t)ne * N,
+               sc = 2 * (size_t)nl * N;
+  Buf x = dev_buf(cx.pool, sx * nbatch);
+  Buf ext = dev_buf(cx.pool, sext * nbatch);
+  Buf u = dev_buf(cx.pool, su * nbatch);
+  Buf conv = dev_buf(cx.pool, sc * nbatch);
+  // 1. coefficient form of the input
+  {
+    NttLaunch L{};
+    L.src = d;
+    L.dst = x.p;
+    L.nlimbs = nl;
+    L.nbatch = nbatch;
+    L.batch_stride = sd;
+    L.dst_stride = sx;
+    L.nq = nl;
+    L.pofs = P.L + 1;
+    ntt(sh, L, true, cx.stream);
+  }
+  // 2. ModUp of every digit, back to NTT form on the new limbs
+  for (int j = 0; j < beta; ++j) {
+    u64* ej = ext.p + (size_t)j * ne * N;
+    k_modup(sh, x.p, ej, level, j, nbatch, sx, sext, cx.stream);
+    NttLaunch L{};
+    L.src = ej;
+    L.dst = ej;
+    L.nlimbs = ne - (P.digit_hi(j, level) - P.digit_lo(j));
+    L.nbatch = nbatch;
+    L.batch_stride = sext;
+    L.nq = nl;
+    L.pofs = P.L + 1;
+    L.skip_lo = P.digit_lo(j);
+    L.skip_hi = P.digit_hi(j, level);
+    ntt(sh, L, false, cx.stream);
+  }
+  // 3. inner product with the key
+  k_ks_inner(sh, d, ext.p, key.k.p, u.p, level, nbatch, sd, sext, su, cx.stream);
+  // 4. ModDown: special limbs to coefficient form, convert, back to NTT form
+  {
+    NttLaunch L{};
+    L.dst = u.p + (size_t)nl * N;
+    L.src = L.dst;
+    L.nlimbs = K;
+    L.nbatch = 2 * nbatch;
+    L.batch_stride = (size_t)ne * N;   // [batch][2][ne][N] is [2 nbatch][ne][N]
+    L.nq = 0;
+    L.pofs = P.L + 1;
+    ntt(sh, L, true, cx.stream);
+  }
+  k_moddown_conv(sh, u.p, conv.p, level, nbatch, su, sc, cx.stream);
+  ntt_ct_limbs(cx, conv.p, nl, 2 * nbatch, sx, false);
+  k_moddown_final(sh, u.p, conv.p, add0, add1, out, level, nbatch, su, sc, sa, so, cx.stream);
+}
+
+// rescale nbatch ciphertexts of npoly polynomials (stride sa) into out (stride so)
+void rescale_raw(Context& cx, const u64* a, size_t sa, int level, int npoly, int nbatch, u64* out,
+                 size_t so) {
+  const Params& P = cx.P();
+  const Shared& sh = *cx.sh;
+  const int N = P.N;
+  const int rows = npoly * nbatch;
+  Buf top = dev_buf(cx.pool, (size_t)rows * N);
+  Buf tmp = dev_buf(cx.pool, (size_t)rows * level * N);
+  // rows r = b * npoly + c: source poly at a + b sa + c (level+1) N
+  for (int b = 0; b < nbatch; ++b)
+    k_copy_rows(sh, a + b * sa + (size_t)level * N, top.p + (size_t)b * npoly * N, npoly,
+                (size_t)(level + 1) * N, N, cx.stream);
+  {
+    NttLaunch L{};
+    L.src = top.p;
+    L.dst = top.p;
+    L.nlimbs = 1;
+    L.nbatch = rows;
+    L.batch_stride = N;
+    L.nq = 0;
+    L.pofs = level;     // every row is on q_level
+    ntt(sh, L, true, cx.stream);
+  }
+  k_rescale_conv(sh, top.p, tmp.p, level, rows, N, cx.stream);
+  ntt_ct_limbs(cx, tmp.p, level, rows, (size_t)level * N, false);
+  for (int b = 0; b < nbatch; ++b)
+    k_rescale_final(sh, a + b * sa, tmp.p + (size_t)b * npoly * level * N, out + b * so, level,
+                    npoly, (size_t)(level + 1) * N, (size_t)level * N, cx.stream);
+}
+
+void scalar_residues(const Params& P, int64_t k, int nl, std::vector<u64>& v, std::vector<u64>& vp) {
+  v.resize(nl);
+  vp.resize(nl);
+  for (int t = 0; t < nl; ++t) {
+    v[t] = h_signed_mod(k, P.q[t]);
+    vp[t] = shoup(v[t], P.q[t]);
+  }
+}
+
+}  // namespace
+
+// ================================================================= keys
+std::unique_ptr<SecretKey> keygen_secret(Context& cx, u64 seed) {
+  const Params& P = cx.P();
+  const Shared& sh = *cx.sh;
+  auto sk = std::make_unique<SecretKey>();
+  Buf s32(cx.pool, (size_t)P.N * 4);
+  k_sample_ternary(sh, (int32_t*)s32.p, seed, purpose_code(P_SK, 0, 0), cx.stream);
+  sk->s_ntt = dev_buf(sh.const_pool, (size_t)P.nprimes * P.N);
+  k_small_to_rns(sh, (int32_t*)s32.p, sk->s_ntt.p, P.nprimes, P.nprimes, 0, cx.stream);
+  NttLaunch L{};
+  L.src = L.dst = sk->s_ntt.p;
+  L.nlimbs = P.nprimes;
+  L.nq = P.nprimes;
+  L.pofs = 0;
+  ntt(sh, L, false, cx.stream);
+  std::vector<int32_t> h(P.N);
+  HIP_CHECK(hipMemcpyAsync(h.data(), s32.p, (size_t)P.N * 4, hipMemcpyDeviceToHost, cx.stream));
+  HIP_CHECK(hipStreamSynchronize(cx.stream));
+  sk->s.assign(h.begin(), h.end());
+  return sk;
+}
+
+std::unique_ptr<PublicKey> keygen_public(Context& cx, const SecretKey& sk, u64 seed) {
+  const Params& P = cx.P();
+  const Shared& sh = *cx.sh;
+  const int nq = P.L + 1, N = P.N;
+  auto pk = std::make_unique<PublicKey>();
+  pk->pk = dev_buf(sh.const_pool, 2 * (size_t)nq * N);
+  u64* b = pk->pk.p;
+  u64* a = b + (size_t)nq * N;
+  k_sample_uniform(sh, a, nq, nq, 0, seed, purpose_code(P_PK_A, 0, 0), cx.stream);
+  Buf e32(cx.pool, (size_t)N * 4);
+  Buf e = dev_buf(cx.pool, (size_t)nq * N);
+  k_sample_dg(sh, (int32_t*)e32.p, seed, purpose_code(P_PK_E, 0, 0), cx.stream);
+  k_small_to_rns(sh, (int32_t*)e32.p, e.p, nq, nq, 0, cx.stream);
+  ntt_ct_limbs(cx, e.p, nq, 1, 0, false);
+  k_keyform(sh, a, sk.s_ntt.p, e.p, nullptr, nullptr, b, nq, nq, 0, cx.stream);
+  HIP_CHECK(hipStreamSynchronize(cx.stream));
+  return pk;
+}
+
+namespace {
+
+std::shared_ptr<KsKey> keygen_ks(Context& cx, const SecretKey& sk, u64 seed, u64 keyid,
+                                 const u64* sp) {
+  const Params& P = cx.P();
+  const Shared& sh = *cx.sh;
+  const int np = P.nprimes, N = P.N;
+  auto key = std::make_shared<KsKey>();
+  key->k = dev_buf(sh.const_pool, (size_t)P.dnum * 2 * np * N);
+  Buf e32(cx.pool, (size_t)N * 4);
+  Buf e = dev_buf(cx.pool, (size_t)np * N);
+  std::vector<u64> pmod(np);
+  for (int t = 0; t < np; ++t) {
+    u64 q = P.q[t], v = 1;
+    for (int k = 0; k < P.K; ++k) v = h_mulmod(v, P.q[P.L + 1 + k] % q, q);
+    pmod[t] = v;
+  }
+  for (int j = 0; j < P.dnum; ++j) {
+    u64* b = key->k.p + (size_t)(2 * j) * np * N;
+    u64* a = key->k.p + (size_t)(2 * j + 1) * np * N;
+    k_sample_uniform(sh, a, np, np, 0, seed, purpose_code(P_KSK_A, keyid, j), cx.stream);
+    k_sample_dg(sh, (int32_t*)e32.p, seed, purpose_code(P_KSK_E, keyid, j), cx.stream);
+    k_small_to_rns(sh, (int32_t*)e32.p, e.p, np, np, 0, cx.stream);
+    NttLaunch L{};
+    L.src = L.dst = e.p;
+    L.nlimbs = np;
+    L.nq = np;
+    L.pofs = 0;
+    ntt(sh, L, false, cx.stream);
+    std::vector<u64> f(np, 0);
+    for (int t = 0; t <= P.L; ++t)
+      if (t / P.alpha == j) f[t] = pmod[t];
+    k_keyform(sh, a, sk.s_ntt.p, e.p, sp, f.data(), b, np, np, 0, cx.stream);
+  }
+  HIP_CHECK(hipStreamSynchronize(cx.stream));
+  return key;
+}
+
+}  // namespace
+
+std::shared_ptr<KsKey> keygen_relin(Context& cx, const SecretKey& sk, u64 seed) {
+  const Params& P = cx.P();
+  Buf s2 = dev_buf(cx.pool, (size_t)P.nprimes * P.N);
+  k_mul_poly(*cx.sh, sk.s_ntt.p, sk.s_ntt.p, s2.p, 1, P.nprimes, 0, 0, cx.stream);
+  return keygen_ks(cx, sk, seed, 0, s2.p);
+}
+
+std::shared_ptr<KsKey> keygen_galois(Context& cx, const SecretKey& sk, u64 seed, u64 g) {
+  const Params& P = cx.P();
+  Buf sp = dev_buf(cx.pool, (size_t)P.nprimes * P.N);
+  k_automorph(*cx.sh, sk.s_ntt.p, sp.p, P.nprimes, P.N, P.N, g, cx.stream);
+  return keygen_ks(cx, sk, seed, g, sp.p);
+}
+
+// ========================================================== plaintexts
+PtPtr plaintext_from_coeffs(Context& cx, const int64_t* coeffs, int level, double scale) {
+  const Params& P = cx.P();
+  if (level < 0 || level > P.L) PPST_THROW(ST_ELEVEL, "level out of range");
+  auto pt = std::make_shared<Plaintext>();
+  pt->level = level;
+  pt->scale = scale;
+  pt->coeffs.assign(coeffs, coeffs + P.N);
+  Buf c64(cx.pool, (size_t)P.N * 8);
+  HIP_CHECK(hipMemcpyAsync(c64.p, pt->coeffs.data(), (size_t)P.N * 8, hipMemcpyHostToDevice,
+                           cx.stream));
+  pt->buf = dev_buf(cx.pool, (size_t)(level + 1) * P.N);
+  k_int64_to_rns(*cx.sh, (const int64_t*)c64.p, pt->buf.p, level + 1, level + 1, 0, cx.stream);
+  ntt_ct_limbs(cx, pt->buf.p, level + 1, 1, 0, false);
+  // the host vector must stay alive until the copy has run
+  HIP_CHECK(hipStreamSynchronize(cx.stream));
+  return pt;
+}
+
+PtPtr encode(Context& cx, const double* v, size_t n, int level) {
+  const Params& P = cx.P();
+  if (level < 0 || level > P.L) PPST_THROW(ST_ELEVEL, "level out of range");
+  if (n > (size_t)P.slots()) PPST_THROW(ST_EINVAL, "more values than slots");
+  std::vector<int64_t> c(P.N);
+  encode_coeffs(P, v, (int)n, P.scale[level], c.data());
+  return plaintext_from_coeffs(cx, c.data(), level, P.scale[level]);
+}
+
+void decode(Context& cx, const Plaintext& pt, double* out, size_t n) {
+  const Params& P = cx.P();
+  const int N = P.N;
+  const int nl = pt.level >= 1 ? 2 : 1;
+  Buf tmp = dev_buf(cx.pool, (size_t)nl * N);
+  NttLaunch L{};
+  L.src = pt.buf.p;
+  L.dst = tmp.p;
+  L.nlimbs = nl;
+  L.nq = nl;
+  L.pofs = 0;
+  ntt(*cx.sh, L, true, cx.stream);
+  std::vector<u64> h((size_t)nl * N);
+  HIP_CHECK(hipMemcpyAsync(h.data(), tmp.p, h.size() * 8, hipMemcpyDeviceToHost, cx.stream));
+  HIP_CHECK(hipStreamSynchronize(cx.stream));
+  std::vector<long double> c(N);
+  const u64 q0 = P.q[0];
+  if (nl == 1) {
+    for (int k = 0; k < N; ++k)
+      c[k] = h[k] > q0 / 2 ? -(long double)(q0 - h[k]) : (long double)h[k];
+  } else {
+    // two-limb CRT, exact while |coefficient| < q_0 q_1 / 2
+    const u64 q1 = P.q[1];
+    const u64 q0inv = h_invmod(q0 % q1, q1);
+    const u128 Q = (u128)q0 * q1;
+    for (int k = 0; k < N; ++k) {
+      u64 x0 = h[k], x1 = h[(size_t)N + k];
+      u64 t = h_mulmod(h_submod(x1, x0 % q1, q1), q0inv, q1);
+      u128 X = (u128)x0 + (u128)q0 * t;
+      c[k] = X > Q / 2 ? -(long double)(Q - X) : (long double)X;
+    }
+  }
+  std::vector<double> all(P.slots());
+  decode_coeffs(P, c.data(), pt.scale, all.data(), P.slots());
+  for (size_t j = 0; j < n && j < all.size(); ++j) out[j] = all[j];
+}
+
+// ========================================================= ciphertexts
+CtPtr new_ct(Context& cx, int level, double scale, int npoly) {
+  const Params& P = cx.P();
+  auto ct = std::make_shared<Ciphertext>();
+  ct->level = level;
+  ct->scale = scale;
+  ct->npoly = npoly;
+  ct->N = P.N;
+  ct->buf = dev_buf(cx.pool, (size_t)npoly * (level + 1) * P.N);
+  return ct;
+}
+
+CtPtr encrypt_pk(Context& cx, const PublicKey& pk, const Plaintext& pt, u64 seed) {
+  const Params& P = cx.P();
+  const Shared& sh = *cx.sh;
+  const int nl = pt.level + 1, N = P.N;
+  Buf s32(cx.pool, (size_t)N * 4);
+  Buf v = dev_buf(cx.pool, (size_t)nl * N);
+  Buf e0 = dev_buf(cx.pool, (size_t)nl * N);
+  Buf e1 = dev_buf(cx.pool, (size_t)nl * N);
+  k_sample_ternary(sh, (int32_t*)s32.p, seed, purpose_code(P_ENC_V, 0, 0), cx.stream);
+  k_small_to_rns(sh, (int32_t*)s32.p, v.p, nl, nl, 0, cx.stream);
+  k_sample_dg(sh, (int32_t*)s32.p, seed, purpose_code(P_ENC_E0, 0, 0), cx.stream);
+  k_small_to_rns(sh, (int32_t*)s32.p, e0.p, nl, nl, 0, cx.stream);
+  k_sample_dg(sh, (int32_t*)s32.p, seed, purpose_code(P_ENC_E1, 0, 0), cx.stream);
+  k_small_to_rns(sh, (int32_t*)s32.p, e1.p, nl, nl, 0, cx.stream);
+  ntt_ct_limbs(cx, v.p, nl, 1, 0, false);
+  ntt_ct_limbs(cx, e0.p, nl, 1, 0, false);
+  ntt_ct_limbs(cx, e1.p, nl, 1, 0, false);
+  auto ct = new_ct(cx, pt.level, pt.scale);
+  const u64* b = pk.pk.p;
+  const u64* a = pk.pk.p + (size_t)(P.L + 1) * N;
+  k_fma3(sh, e0.p, v.p, b, pt.buf.p, ct->poly(0), nl, cx.stream);
+  k_fma3(sh, e1.p, v.p, a, nullptr, ct->poly(1), nl, cx.stream);
+  return ct;
+}
+
+CtPtr encrypt_sk(Context& cx, const SecretKey& sk, const Plaintext& pt, u64 seed) {
+  const Params& P = cx.P();
+  const Shared& sh = *cx.sh;
+  const int nl = pt.level + 1, N = P.N;
+  auto ct = new_ct(cx, pt.level, pt.scale);
+  k_sample_uniform(sh, ct->poly(1), nl, nl, 0, seed, purpose_code(P_SKE_A, 0, 0), cx.stream);
+  Buf e32(cx.pool, (size_t)N * 4);
+  Buf e = dev_buf(cx.pool, (size_t)nl * N);
+  k_sample_dg(sh, (int32_t*)e32.p, seed, purpose_code(P_SKE_E, 0, 0), cx.stream);
+  k_small_to_rns(sh, (int32_t*)e32.p, e.p, nl, nl, 0, cx.stream);
+  ntt_ct_limbs(cx, e.p, nl, 1, 0, false);
+  k_keyform(sh, ct->poly(1), sk.s_ntt.p, e.p, nullptr, nullptr, ct->poly(0), nl, nl, 0, cx.stream);
+  k_add(sh, ct->poly(0), pt.buf.p, ct->poly(0), 1, nl, 0, 0, 0, false, cx.stream);
+  return ct;
+}
+
+PtPtr decrypt(Context& cx, const SecretKey& sk, const Ciphertext& ct) {
+  if (ct.npoly != 2) PPST_THROW(ST_EINVAL, "decrypt expects a degree-1 ciphertext");
+  const Params& P = cx.P();
+  auto pt = std::make_shared<Plaintext>();
+  pt->level = ct.level;
+  pt->scale = ct.scale;
+  pt->buf = dev_buf(cx.pool, (size_t)(ct.level + 1) * P.N);
+  k_fma3(*cx.sh, ct.poly(0), ct.poly(1), sk.s_ntt.p, nullptr, pt->buf.p, ct.level + 1, cx.stream);
+  return pt;
+}
+
+// =========================================================== operations
+CtPtr copy_ct(Context& cx, const Ciphertext& a) {
+  auto out = new_ct(cx, a.level, a.scale, a.npoly);
+  HIP_CHECK(hipMemcpyAsync(out->buf.p, a.buf.p, (size_t)a.npoly * (a.level + 1) * a.N * 8,
+                           hipMemcpyDeviceToDevice, cx.stream));
+  return out;
+}
+
+CtPtr add(Context& cx, const Ciphertext& a, const Ciphertext& b) {
+  require_same(a, b);
+  auto out = new_ct(cx, a.level, a.scale);
+  size_t st = (size_t)(a.level + 1) * a.N;
+  k_add(*cx.sh, a.buf.p, b.buf.p, out->buf.p, 2, a.level + 1, st, st, st, false, cx.stream);
+  return out;
+}
+
+CtPtr sub(Context& cx, const Ciphertext& a, const Ciphertext& b) {
+  require_same(a, b);
+  auto out = new_ct(cx, a.level, a.scale);
+  size_t st = (size_t)(a.level + 1) * a.N;
+  k_add(*cx.sh, a.buf.p, b.buf.p, out->buf.p, 2, a.level + 1, st, st, st, true, cx.stream);
+  return out;
+}
+
+int64_t const_int(const Params& P, double c, int level) {
+  double v = c * P.scale[level];
+  if (!(std::fabs(v) < 9.0e18)) PPST_THROW(ST_EDOMAIN, "constant too large for the scale");
+  return llround(v);
+}
+
+CtPtr add_const(Context& cx, const Ciphertext& a, double c) {
+  const Params& P = cx.P();
+  int64_t k = const_int(P, c, a.level);
+  std::vector<u64> v, vp;
+  scalar_residues(P, k, a.level + 1, v, vp);
+  auto out = new_ct(cx, a.level, a.scale, a.npoly);
+  size_t per = (size_t)(a.level + 1) * a.N;
+  k_add_scalar(*cx.sh, a.poly(0), out->poly(0), a.level + 1, v.data(), cx.stream);
+  HIP_CHECK(hipMemcpyAsync(out->buf.p + per, a.buf.p + per, (a.npoly - 1) * per * 8,
+                           hipMemcpyDeviceToDevice, cx.stream));
+  return out;
+}
+
+CtPtr mul_int(Context& cx, const Ciphertext& a, int64_t k) {
+  const Params& P = cx.P();
+  std::vector<u64> v, vp;
+  scalar_residues(P, k, a.level + 1, v, vp);
+  auto out = new_ct(cx, a.level, a.scale, a.npoly);
+  size_t per = (size_t)(a.level + 1) * a.N;
+  k_mul_scalar(*cx.sh, a.buf.p, out->buf.p, a.npoly, a.level + 1, per, per, v.data(), vp.data(),
+               cx.stream);
+  return out;
+}
+
+CtPtr rescale(Context& cx, const Ciphertext& a) {
+  if (a.level < 1) PPST_THROW(ST_ELEVEL, "no level left to rescale");
+  const Params& P = cx.P();
+  auto out = new_ct(cx, a.level - 1, P.scale[a.level - 1], a.npoly);
+  rescale_raw(cx, a.buf.p, 0, a.level, a.npoly, 1, out->buf.p, 0);
+  return out;
+}
+
+CtPtr mul_const(Context& cx, const Ciphertext& a, double c) {
+  if (a.level < 1) PPST_THROW(ST_ELEVEL, "no level left for a constant product");
+  auto t = mul_int(cx, a, const_int(cx.P(), c, a.level));
+  return rescale(cx, *t);
+}
+
+CtPtr mul_plain(Context& cx, const Ciphertext& a, const Plaintext& pt) {
+  if (a.level < 1) PPST_THROW(ST_ELEVEL, "no level left for a plaintext product");
+  if (pt.level != a.level) PPST_THROW(ST_ESCALE, "plaintext level differs from the ciphertext's");
+  auto t = new_ct(cx, a.level, a.scale, a.npoly);
+  size_t per = (size_t)(a.level + 1) * a.N;
+  k_mul_poly(*cx.sh, a.buf.p, pt.buf.p, t->buf.p, a.npoly, a.level + 1, per, per, cx.stream);
+  return rescale(cx, *t);
+}
+
+CtPtr tensor(Context& cx, const Ciphertext& a, const Ciphertext& b) {
+  require_same(a, b);
+  auto d = new_ct(cx, a.level, a.scale * b.scale, 3);
+  k_tensor(*cx.sh, a.buf.p, b.buf.p, d->buf.p, a.level + 1, 1, 0, 0, 0, cx.stream);
+  return d;
+}
+
+CtPtr relin(Context& cx, const EvalKeys& evk, const Ciphertext& d) {
+  if (d.npoly != 3) PPST_THROW(ST_EINVAL, "relinearisation expects a degree-2 ciphertext");
+  const KsKey& key = relin_key(evk);
+  auto out = new_ct(cx, d.level, d.scale);
+  keyswitch(cx, key, d.poly(2), 0, d.level, d.poly(0), d.poly(1), 0, out->buf.p, 0, 1);
+  return out;
+}
+
+CtPtr mul(Context& cx, const EvalKeys& evk, const Ciphertext& a, const Ciphertext& b) {
+  require_same(a, b);
+  if (a.level < 1) PPST_THROW(ST_ELEVEL, "no level left for a product");
+  auto d = tensor(cx, a, b);
+  auto r = relin(cx, evk, *d);
+  d.reset();
+  return rescale(cx, *r);
+}
+
+CtPtr rotate(Context& cx, const EvalKeys& evk, const Ciphertext& a, long r) {
+  if (a.npoly != 2) PPST_THROW(ST_EINVAL, "rotation expects a degree-1 ciphertext");
+  const Params& P = cx.P();
+  u64 g = galois_elt(P, r);
+  if (g == 1) return copy_ct(cx, a);
+  const KsKey& key = galois_key(evk, g);
+  const size_t per = (size_t)(a.level + 1) * P.N;
+  Buf perm = dev_buf(cx.pool, 2 * per);
+  k_automorph(*cx.sh, a.buf.p, perm.p, 2 * (a.level + 1), P.N, P.N, g, cx.stream);
+  auto out = new_ct(cx, a.level, a.scale);
+  keyswitch(cx, key, perm.p + per, 0, a.level, perm.p, nullptr, 0, out->buf.p, 0, 1);
+  return out;
+}
+
+std::vector<CtPtr> rotate_hoisted(Context& cx, const EvalKeys& evk, const Ciphertext& a,
+                                  const std::vector<long>& rs) {
+  if (a.npoly != 2) PPST_THROW(ST_EINVAL, "rotation expects a degree-1 ciphertext");
+  const Params& P = cx.P();
+  const Shared& sh = *cx.sh;
+  const int level = a.level, N = P.N, nl = level + 1, K = P.K, ne = nl + K, beta = P.beta(level);
+  const size_t per = (size_t)nl * N, sext = (size_t)beta * ne * N;
+  std::vector<CtPtr> outs;
+  // shared ModUp of c1
+  Buf x = dev_buf(cx.pool, per);
+  Buf ext = dev_buf(cx.pool, sext);
+  {
+    NttLaunch L{};
+    L.src = a.poly(1);
+    L.dst = x.p;
+    L.nlimbs = nl;
+    L.nq = nl;
+    L.pofs = P.L + 1;
+    ntt(sh, L, true, cx.stream);
+  }
+  for (int j = 0; j < beta; ++j) {
+    u64* ej = ext.p + (size_t)j * ne * N;
+    k_modup(sh, x.p, ej, level, j, 1, per, sext, cx.stream);
+    NttLaunch L{};
+    L.src = ej;
+    L.dst = ej;
+    L.nlimbs = ne - (P.digit_hi(j, level) - P.digit_lo(j));
+    L.nq = nl;
+    L.pofs = P.L + 1;
+    L.skip_lo = P.digit_lo(j);
+    L.skip_hi = P.digit_hi(j, level);
+    ntt(sh, L, false, cx.stream);
+  }
+  x.release();
+  Buf pext = dev_buf(cx.pool, sext);
+  Buf pa = dev_buf(cx.pool, 2 * per);
+  Buf u = dev_buf(cx.pool, 2 * (size_t)ne * N);
+  Buf conv = dev_buf(cx.pool, 2 * per);
+  for (long r : rs) {
+    u64 g = galois_elt(P, r);
+    if (g == 1) {
+      outs.push_back(copy_ct(cx, a));
+      continue;
+    }
+    const KsKey& key = galois_key(evk, g);
+    k_automorph(sh, a.buf.p, pa.p, 2 * nl, N, N, g, cx.stream);
+    k_automorph(sh, ext.p, pext.p, beta * ne, N, N, g, cx.stream);
+    k_ks_inner(sh, pa.p + per, pext.p, key.k.p, u.p, level, 1, 0, 0, 0, cx.stream);
+    NttLaunch L{};
+    L.dst = u.p + per;
+    L.src = L.dst;
+    L.nlimbs = K;
+    L.nbatch = 2;
+    L.batch_stride = (size_t)ne * N;
+    L.nq = 0;
+    L.pofs = P.L + 1;
+    ntt(sh, L, true, cx.stream);
+    k_moddown_conv(sh, u.p, conv.p, level, 1, 0, 0, cx.stream);
+    ntt_ct_limbs(cx, conv.p, nl, 2, per, false);
+    auto out = new_ct(cx, level, a.scale);
+    k_moddown_final(sh, u.p, conv.p, pa.p, nullptr, out->buf.p, level, 1, 0, 0, 0, 0, cx.stream);
+    outs.push_back(out);
+  }
+  return outs;
+}
+
+CtPtr rotsum(Context& cx, const EvalKeys& evk, const Ciphertext& a) {
+  CtPtr ct = copy_ct(cx, a);
+  for (int k = 0; (1 << k) < cx.P().slots(); ++k) {
+    auto r = rotate(cx, evk, *ct, 1L << k);
+    ct = add(cx, *ct, *r);
+  }
+  return ct;
+}
+
+CtPtr level_align(Context& cx, const Ciphertext& a, int level) {
+  if (level == a.level) return copy_ct(cx, a);
+  if (level > a.level || level < 0) PPST_THROW(ST_ELEVEL, "cannot raise a ciphertext's level");
+  const Params& P = cx.P();
+  const int nl = level + 2;           // keep q_0 .. q_{level+1}
+  const int64_t K = llround((P.scale[level] * (double)P.q[level + 1]) / P.scale[a.level]);
+  std::vector<u64> v, vp;
+  scalar_residues(P, K, nl, v, vp);
+  auto t = new_ct(cx, level + 1, P.scale[level + 1], a.npoly);
+  k_mul_scalar(*cx.sh, a.buf.p, t->buf.p, a.npoly, nl, (size_t)(a.level + 1) * P.N,
+               (size_t)nl * P.N, v.data(), vp.data(), cx.stream);
+  auto out = new_ct(cx, level, P.scale[level], a.npoly);
+  rescale_raw(cx, t->buf.p, 0, level + 1, a.npoly, 1, out->buf.p, 0);
+  return out;
+}
+
+std::vector<CtPtr> mul_batch(Context& cx, const EvalKeys& evk,
+                             const std::vector<const Ciphertext*>& a,
+                             const std::vector<const Ciphertext*>& b) {
+  const size_t n = a.size();
+  if (n == 0) return {};
+  if (b.size() != n) PPST_THROW(ST_EINVAL, "batch operands differ in length");
+  const Params& P = cx.P();
+  const int level = a[0]->level;
+  for (size_t i = 0; i < n; ++i) {
+    require_same(*a[i], *b[i]);
+    if (a[i]->level != level) PPST_THROW(ST_ESCALE, "batch members at different levels");
+  }
+  if (level < 1) PPST_THROW(ST_ELEVEL, "no level left for a product");
+  const KsKey& key = relin_key(evk);
+  const int nl = level + 1, N = P.N;
+  const size_t per = (size_t)nl * N;
+  // gather operands into contiguous batch buffers
+  Buf A = dev_buf(cx.pool, 2 * per * n), B = dev_buf(cx.pool, 2 * per * n);
+  for (size_t i = 0; i < n; ++i) {
+    HIP_CHECK(hipMemcpyAsync(A.p + 2 * per * i, a[i]->buf.p, 2 * per * 8, hipMemcpyDeviceToDevice,
+                             cx.stream));
+    HIP_CHECK(hipMemcpyAsync(B.p + 2 * per * i, b[i]->buf.p, 2 * per * 8, hipMemcpyDeviceToDevice,
+                             cx.stream));
+  }
+  Buf D = dev_buf(cx.pool, 3 * per * n);
+  k_tensor(*cx.sh, A.p, B.p, D.p, nl, (int)n, 2 * per, 2 * per, 3 * per, cx.stream);
+  A.release();
+  B.release();
+  Buf R = dev_buf(cx.pool, 2 * per * n);
+  keyswitch(cx, key, D.p + 2 * per, 3 * per, level, D.p, D.p + per, 3 * per, R.p, 2 * per, (int)n);
+  D.release();
+  const size_t per2 = (size_t)level * N;
+  Buf O = dev_buf(cx.pool, 2 * per2 * n);
+  rescale_raw(cx, R.p, 2 * per, level, 2, (int)n, O.p, 2 * per2);
+  std::vector<CtPtr> outs;
+  for (size_t i = 0; i < n; ++i) {
+    auto o = new_ct(cx, level - 1, P.scale[level - 1]);
+    HIP_CHECK(hipMemcpyAsync(o->buf.p, O.p + 2 * per2 * i, 2 * per2 * 8, hipMemcpyDeviceToDevice,
+                             cx.stream));
+    outs.push_back(o);
+  }
+  return outs;
+}
+
+void ntt_raw(Context& cx, u64* data, int nlimbs, int first_prime, bool inverse) {
+  const Params& P = cx.P();
+  if (first_prime < 0 || first_prime + nlimbs > P.nprimes)
+    PPST_THROW(ST_EINVAL, "prime range out of bounds");
+  NttLaunch L{};
+  L.src = data;
+  L.dst = data;
+  L.nlimbs = nlimbs;
+  L.nq = 0;
+  L.pofs = first_prime;
+  ntt(*cx.sh, L, inverse, cx.stream);
+}
+
+}  // namespace ppst

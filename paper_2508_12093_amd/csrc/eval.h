@@ -1,0 +1,64 @@
+// eval.h -- the RNS-CKKS evaluator of the ppstat library (host orchestration
+// of the device kernels).  Every operation is enqueued on the context's
+// stream; nothing synchronises except the functions that return host data.
+#pragma once
+
+#include "core.h"
+
+namespace ppst {
+
+typedef std::shared_ptr<Ciphertext> CtPtr;
+typedef std::shared_ptr<Plaintext> PtPtr;
+
+std::shared_ptr<Shared> make_shared_state(const ParamSpec& spec, const Hooks* hooks);
+std::unique_ptr<Context> make_context(std::shared_ptr<Shared> sh, hipStream_t stream);
+void destroy_context(Context* cx);
+
+// galois element of a rotation by r slots: 5^(r mod N/2) mod 2N
+u64 galois_elt(const Params& P, long r);
+
+// ------------------------------------------------------------------ keys
+std::unique_ptr<SecretKey> keygen_secret(Context& cx, u64 seed);
+std::unique_ptr<PublicKey> keygen_public(Context& cx, const SecretKey& sk, u64 seed);
+std::shared_ptr<KsKey> keygen_relin(Context& cx, const SecretKey& sk, u64 seed);
+std::shared_ptr<KsKey> keygen_galois(Context& cx, const SecretKey& sk, u64 seed, u64 g);
+
+// ----------------------------------------------------------- plaintexts
+PtPtr encode(Context& cx, const double* v, size_t n, int level);
+PtPtr plaintext_from_coeffs(Context& cx, const int64_t* coeffs, int level, double scale);
+void decode(Context& cx, const Plaintext& pt, double* out, size_t n);
+
+// --------------------------------------------------------- ciphertexts
+CtPtr new_ct(Context& cx, int level, double scale, int npoly = 2);
+CtPtr encrypt_pk(Context& cx, const PublicKey& pk, const Plaintext& pt, u64 seed);
+CtPtr encrypt_sk(Context& cx, const SecretKey& sk, const Plaintext& pt, u64 seed);
+PtPtr decrypt(Context& cx, const SecretKey& sk, const Ciphertext& ct);
+
+// ------------------------------------------------------------ operations
+CtPtr add(Context& cx, const Ciphertext& a, const Ciphertext& b);
+CtPtr sub(Context& cx, const Ciphertext& a, const Ciphertext& b);
+int64_t const_int(const Params& P, double c, int level);
+CtPtr add_const(Context& cx, const Ciphertext& a, double c);
+CtPtr mul_int(Context& cx, const Ciphertext& a, int64_t k);
+CtPtr mul_const(Context& cx, const Ciphertext& a, double c);
+CtPtr mul_plain(Context& cx, const Ciphertext& a, const Plaintext& pt);
+CtPtr tensor(Context& cx, const Ciphertext& a, const Ciphertext& b);
+CtPtr relin(Context& cx, const EvalKeys& evk, const Ciphertext& d);
+CtPtr rescale(Context& cx, const Ciphertext& a);
+CtPtr mul(Context& cx, const EvalKeys& evk, const Ciphertext& a, const Ciphertext& b);
+CtPtr rotate(Context& cx, const EvalKeys& evk, const Ciphertext& a, long r);
+std::vector<CtPtr> rotate_hoisted(Context& cx, const EvalKeys& evk, const Ciphertext& a,
+                                  const std::vector<long>& rs);
+CtPtr rotsum(Context& cx, const EvalKeys& evk, const Ciphertext& a);
+CtPtr level_align(Context& cx, const Ciphertext& a, int level);
+CtPtr copy_ct(Context& cx, const Ciphertext& a);
+
+// many independent products a[i] * b[i] in one launch per stage, the key
+// read once per batch
+std::vector<CtPtr> mul_batch(Context& cx, const EvalKeys& evk, const std::vector<const Ciphertext*>& a,
+                             const std::vector<const Ciphertext*>& b);
+
+// raw NTT on device memory (canonical order), limb i on prime first_prime + i
+void ntt_raw(Context& cx, u64* data, int nlimbs, int first_prime, bool inverse);
+
+}  // namespace ppst

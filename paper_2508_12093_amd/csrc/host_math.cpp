@@ -1,0 +1,242 @@
+// host_math.cpp -- parameter generation, sampling specification and the
+// canonical-embedding encoder of the ppstat library (host side).
+#include <cmath>
+
+#include "core.h"
+
+namespace ppst {
+
+u64 h_powmod(u64 b, u64 e, u64 q) {
+  u64 r = 1 % q;
+  b %= q;
+  for (; e; e >>= 1) {
+    if (e & 1) r = h_mulmod(r, b, q);
+    b = h_mulmod(b, b, q);
+  }
+  return r;
+}
+
+// Miller-Rabin with the seven bases of Jaeschke / Sinclair, exact for all
+// 64-bit integers.
+bool is_prime_u64(u64 n) {
+  if (n < 4) return n == 2 || n == 3;
+  if (!(n & 1)) return false;
+  for (u64 p : {3ULL, 5ULL, 7ULL, 11ULL, 13ULL, 17ULL, 19ULL, 23ULL, 29ULL, 31ULL, 37ULL})
+    if (n % p == 0) return n == p;
+  u64 d = n - 1;
+  int r = 0;
+  while (!(d & 1)) { d >>= 1; ++r; }
+  static const u64 bases[7] = {2ULL, 325ULL, 9375ULL, 28178ULL, 450775ULL, 9780504ULL,
+                               1795265022ULL};
+  for (u64 a0 : bases) {
+    u64 a = a0 % n;
+    if (a == 0) continue;
+    u64 x = h_powmod(a, d, n);
+    if (x == 1 || x == n - 1) continue;
+    bool comp = true;
+    for (int i = 1; i < r && comp; ++i) {
+      x = h_mulmod(x, x, n);
+      if (x == n - 1) comp = false;
+    }
+    if (comp) return false;
+  }
+  return true;
+}
+
+namespace {
+
+bool used_in(const std::vector<u64>& v, u64 x) {
+  for (u64 y : v) if (y == x) return true;
+  return false;
+}
+
+// the largest unused prime p < 2^bits with p = 1 (mod 2N)
+u64 top_prime(int bits, u64 m, const std::vector<u64>& used) {
+  u64 lim = bits >= 64 ? ~0ULL : ((1ULL << bits) - 1);
+  u64 x = lim - ((lim - 1) % m);              // largest x <= lim with x = 1 mod m
+  for (; x > m; x -= m)
+    if (!used_in(used, x) && is_prime_u64(x)) return x;
+  PPST_THROW(ST_EINVAL, "no prime found");
+}
+
+// the unused prime p = 1 (mod 2N) closest to target; on a tie the smaller
+u64 closest_prime(double target, u64 m, const std::vector<u64>& used) {
+  u64 below = (u64)std::floor((target - 1.0) / (double)m) * m + 1;
+  u64 above = below + m;
+  while (below > m && (used_in(used, below) || !is_prime_u64(below))) below -= m;
+  while (used_in(used, above) || !is_prime_u64(above)) above += m;
+  double db = target - (double)below, da = (double)above - target;
+  return da < db ? above : below;
+}
+
+// smallest x >= 2 whose power x^((q-1)/2N) has order exactly 2N
+u64 root_2n(u64 q, u64 n) {
+  for (u64 x = 2;; ++x) {
+    u64 r = h_powmod(x, (q - 1) / (2 * n), q);
+    if (h_powmod(r, n, q) == q - 1) return r;
+  }
+}
+
+}  // namespace
+
+Params make_params(const ParamSpec& s) {
+  if (s.logN < 2 || s.logN > 17 || s.L < 0 || s.K < 1 || s.dnum < 1 ||
+      s.L + 1 + s.K > kMaxPrimes || s.scale <= 1.0)
+    PPST_THROW(ST_EINVAL, "invalid parameter specification");
+  Params P;
+  P.spec = s;
+  P.logN = s.logN;
+  P.N = 1 << s.logN;
+  P.L = s.L;
+  P.K = s.K;
+  P.dnum = s.dnum;
+  P.alpha = (s.L + 1 + s.dnum - 1) / s.dnum;
+  P.nprimes = s.L + 1 + s.K;
+  const u64 m = 2 * (u64)P.N;
+  std::vector<u64> used;
+  P.q.assign(P.nprimes, 0);
+  P.scale.assign(P.L + 1, 0.0);
+  P.q[0] = top_prime(s.q0_bits, m, used);
+  used.push_back(P.q[0]);
+  // scale chain: Delta_L = Delta, Delta_{l-1} = (Delta_l * Delta_l) / q_l
+  P.scale[P.L] = s.scale;
+  for (int l = P.L; l >= 1; --l) {
+    double sq = P.scale[l] * P.scale[l];
+    u64 p = closest_prime(sq / s.scale, m, used);
+    P.q[l] = p;
+    used.push_back(p);
+    P.scale[l - 1] = sq / (double)p;
+  }
+  for (int k = 0; k < P.K; ++k) {
+    u64 p = top_prime(s.p_bits, m, used);
+    P.q[P.L + 1 + k] = p;
+    used.push_back(p);
+  }
+  P.psi.resize(P.nprimes);
+  for (int i = 0; i < P.nprimes; ++i) {
+    if (P.q[i] >= (1ULL << 61)) PPST_THROW(ST_EINVAL, "primes must stay below 2^61");
+    P.psi[i] = root_2n(P.q[i], P.N);
+  }
+  return P;
+}
+
+bool preset_spec(const std::string& name, ParamSpec* out) {
+  ParamSpec s;
+  if (name == "c1") {          // N=2^12, 40-bit q0, two 30-bit primes, one 60-bit special prime
+    s = {12, 2, 1, 3, 40, 60, 1073741824.0};
+  } else if (name == "c2") {   // N=2^16, 60-bit q0, 24 primes near 2^40, 7 special primes
+    s = {16, 24, 7, 3, 60, 60, 1099511627776.0};
+  } else if (name == "t1") {   // N=2^12 with the c2 prime shapes, L=6
+    s = {12, 6, 3, 3, 60, 60, 1099511627776.0};
+  } else if (name == "t2") {   // N=2^12 with the full c2 chain, L=24
+    s = {12, 24, 7, 3, 60, 60, 1099511627776.0};
+  } else {
+    return false;
+  }
+  *out = s;
+  return true;
+}
+
+// ---------------------------------------------------------------- sampling
+// SplitMix64 step: advance the state by the golden-ratio increment, mix.
+static inline u64 splitmix(u64& state) {
+  state += 0x9E3779B97F4A7C15ULL;
+  u64 z = state;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+static inline u64 mix_once(u64 x) { return splitmix(x); }
+
+u64 stream_key(u64 seed, u64 purpose, u64 limb) {
+  return mix_once(mix_once(mix_once(seed) ^ purpose) ^ limb);
+}
+
+void dg_thresholds(u64 thr[kDgMax]) {
+  const double sigma = 3.2;
+  const double two_s2 = 2.0 * sigma * sigma;
+  double w[kDgMax + 1];
+  w[0] = 1.0;
+  for (int x = 1; x <= kDgMax; ++x) w[x] = 2.0 * std::exp(-((double)(x * x)) / two_s2);
+  double tot = 0.0;
+  for (int x = 0; x <= kDgMax; ++x) tot += w[x];
+  double c = 0.0;
+  for (int x = 0; x < kDgMax; ++x) {
+    c += w[x];
+    thr[x] = (u64)((c / tot) * 18446744073709551616.0);
+  }
+}
+
+// ---------------------------------------------------------------- encoding
+namespace {
+
+typedef long double ld;
+const ld kPi = 3.141592653589793238462643383279502884L;
+
+// in-place decimation-in-frequency FFT of length n (power of two);
+// output X_k = sum_j x_j exp(sign 2 pi i j k / n) lands at position brv(k)
+void dif_fft(std::vector<ld>& re, std::vector<ld>& im, int sign) {
+  const size_t n = re.size();
+  for (size_t len = n; len >= 2; len >>= 1) {
+    const size_t h = len / 2;
+    for (size_t j = 0; j < h; ++j) {
+      ld ang = (ld)sign * 2.0L * kPi * (ld)j / (ld)len;
+      ld c = cosl(ang), s = sinl(ang);
+      for (size_t i = 0; i < n; i += len) {
+        ld ur = re[i + j], ui = im[i + j];
+        ld vr = re[i + j + h], vi = im[i + j + h];
+        re[i + j] = ur + vr;
+        im[i + j] = ui + vi;
+        ld dr = ur - vr, di = ui - vi;
+        re[i + j + h] = dr * c - di * s;
+        im[i + j + h] = dr * s + di * c;
+      }
+    }
+  }
+}
+
+size_t bitrev(size_t x, int bits) {
+  size_t r = 0;
+  for (int b = 0; b < bits; ++b) r |= ((x >> b) & 1) << (bits - 1 - b);
+  return r;
+}
+
+}  // namespace
+
+// Canonical embedding inverse: slot j is the evaluation at zeta^(5^j),
+// zeta = exp(i pi / N); p_k = (2/N) Re sum_j m_j zeta^(-5^j k);
+// coefficient k = round_half_away(scale * p_k).
+void encode_coeffs(const Params& P, const double* m, int n_used, double scale, int64_t* out) {
+  const int N = P.N, n = N / 2;
+  if (n_used < 0 || n_used > n) PPST_THROW(ST_EINVAL, "more values than slots");
+  const size_t M2 = 2 * (size_t)N;
+  std::vector<ld> re(M2, 0.0L), im(M2, 0.0L);
+  u64 e = 1;
+  for (int j = 0; j < n_used; ++j) {
+    re[e] = (ld)m[j];
+    e = (e * 5) % M2;
+  }
+  dif_fft(re, im, -1);
+  const int bits = P.logN + 1;
+  for (int k = 0; k < N; ++k) {
+    ld v = (2.0L / (ld)N) * re[bitrev((size_t)k, bits)];
+    out[k] = llroundl((ld)scale * v);
+  }
+}
+
+// m_j = Re sum_k c_k zeta^(5^j k) / scale
+void decode_coeffs(const Params& P, const long double* c, double scale, double* out, int n) {
+  const int N = P.N;
+  const size_t M2 = 2 * (size_t)N;
+  std::vector<ld> re(M2, 0.0L), im(M2, 0.0L);
+  for (int k = 0; k < N; ++k) re[k] = c[k];
+  dif_fft(re, im, +1);
+  const int bits = P.logN + 1;
+  u64 e = 1;
+  for (int j = 0; j < n; ++j) {
+    out[j] = (double)(re[bitrev((size_t)e, bits)] / (ld)scale);
+    e = (e * 5) % M2;
+  }
+}
+
+}  // namespace ppst

@@ -1,0 +1,100 @@
+// kern.h -- host-side launchers of the device kernels (kernels.hip, ntt.hip).
+#pragma once
+
+#include "core.h"
+
+namespace ppst {
+
+constexpr int kMaxLimbArgs = 64;
+
+// ---------------------------------------------------------------- NTT
+// Transforms `nlimbs` limbs per batch item.  Limb u of batch item b sits at
+// src + b*batch_stride + t*N with t = u, or u + (skip_hi - skip_lo) when
+// u >= skip_lo (limbs [skip_lo, skip_hi) are left alone); its prime is
+// t < nq ? t : pofs + (t - nq).  In place when src == dst.
+struct NttLaunch {
+  const u64* src;
+  u64* dst;
+  int nlimbs;
+  int nbatch = 1;
+  size_t batch_stride = 0;      // source stride between batch items
+  size_t dst_stride = ~(size_t)0;  // destination stride (default: batch_stride)
+  int nq, pofs;
+  int skip_lo = 1 << 30, skip_hi = 1 << 30;
+};
+void ntt(const Shared& sh, const NttLaunch& L, bool inverse, hipStream_t st);
+
+// ------------------------------------------------------- element-wise
+// All element-wise launches work on `npoly` polynomials of `nl` limbs,
+// polynomial c at base + c * poly_stride; limb t uses prime map(t).
+void k_add(const Shared& sh, const u64* a, const u64* b, u64* out, int npoly, int nl,
+           size_t stride_a, size_t stride_b, size_t stride_o, bool sub, hipStream_t st);
+// out[c][t] = a[c][t] * k[t] mod q_t  (k reduced, Shoup companions precomputed)
+void k_mul_scalar(const Shared& sh, const u64* a, u64* out, int npoly, int nl, size_t stride_a,
+                  size_t stride_o, const u64* k, const u64* kp, hipStream_t st);
+// out[t] = a[t] + k[t] mod q_t on one polynomial
+void k_add_scalar(const Shared& sh, const u64* a, u64* out, int nl, const u64* k, hipStream_t st);
+// out[c][t] = a[c][t] * pt[t] mod q_t
+void k_mul_poly(const Shared& sh, const u64* a, const u64* pt, u64* out, int npoly, int nl,
+                size_t stride_a, size_t stride_o, hipStream_t st);
+// (d0, d1, d2) = (a0 b0, a0 b1 + a1 b0, a1 b1); a, b: [2][nl][N]; d: [3][nl][N]
+void k_tensor(const Shared& sh, const u64* a, const u64* b, u64* d, int nl, int nbatch,
+              size_t stride_a, size_t stride_b, size_t stride_d, hipStream_t st);
+// out[c][t][j] = in[c][t][perm_g(j)], the automorphism X -> X^g in NTT form
+void k_automorph(const Shared& sh, const u64* in, u64* out, int nrows, size_t row_stride_in,
+                 size_t row_stride_out, u64 g, hipStream_t st);
+
+// ------------------------------------------------------ key switching
+// ModUp of digit j at level l: x = coefficient-form limbs of the input (the
+// digit's limbs lo..hi-1 at x + t*N); writes every limb t of [0, nl+K) outside
+// the digit into ext + t*N (coefficient form).
+void k_modup(const Shared& sh, const u64* x, u64* ext, int level, int digit, int nbatch,
+             size_t stride_x, size_t stride_ext, hipStream_t st);
+// Inner product with the key: for t in [0, ne) (ne = nl + K),
+//   u0_t = sum_j e_{j,t} b_{j,p(t)},  u1_t = sum_j e_{j,t} a_{j,p(t)},
+// e_{j,t} = d_t for t in digit j (NTT form input), ext[j][t] otherwise.
+// ext: [beta][ne][N] per batch item; u: [2][ne][N] per batch item.
+void k_ks_inner(const Shared& sh, const u64* d, const u64* ext, const u64* key, u64* u, int level,
+                int nbatch, size_t stride_d, size_t stride_ext, size_t stride_u, hipStream_t st);
+// ModDown conversion: z = coefficient-form special limbs of u (u + nl*N, for
+// both polynomials); conv[c][i] = Conv_{P->q_i}(z + h) - h mod q_i.
+void k_moddown_conv(const Shared& sh, const u64* u, u64* conv, int level, int nbatch,
+                    size_t stride_u, size_t stride_conv, hipStream_t st);
+// out[c][i] = (u[c][i] - conv[c][i]) P^-1 mod q_i (+ add[c][i] when add_c != null)
+void k_moddown_final(const Shared& sh, const u64* u, const u64* conv, const u64* add0,
+                     const u64* add1, u64* out, int level, int nbatch, size_t stride_u,
+                     size_t stride_conv, size_t stride_add, size_t stride_out, hipStream_t st);
+
+// ------------------------------------------------------------ rescale
+// top: coefficient-form top limb of each of npoly polynomials (stride
+// top_stride); tmp[c][i] = centred(top_c) mod q_i for i < level.
+void k_rescale_conv(const Shared& sh, const u64* top, u64* tmp, int level, int npoly,
+                    size_t top_stride, hipStream_t st);
+// out[c][i] = (a[c][i] - tmp[c][i]) q_level^-1 mod q_i, i < level
+void k_rescale_final(const Shared& sh, const u64* a, const u64* tmp, u64* out, int level,
+                     int npoly, size_t stride_a, size_t stride_out, hipStream_t st);
+
+// ------------------------------------------------------- sampling etc.
+// signed 64-bit integers -> residues on limbs t of a map
+void k_int64_to_rns(const Shared& sh, const int64_t* s, u64* out, int nl, int nq, int pofs,
+                    hipStream_t st);
+// signed small integers (int32) -> residues on limbs t of a map
+void k_small_to_rns(const Shared& sh, const int32_t* s, u64* out, int nl, int nq, int pofs,
+                    hipStream_t st);
+// uniform residues: limb t (prime map(t)) from the stream (seed, purpose, stream_limb0 + prime)
+void k_sample_uniform(const Shared& sh, u64* out, int nl, int nq, int pofs, u64 seed, u64 purpose,
+                      hipStream_t st);
+void k_sample_ternary(const Shared& sh, int32_t* out, u64 seed, u64 purpose, hipStream_t st);
+void k_sample_dg(const Shared& sh, int32_t* out, u64 seed, u64 purpose, hipStream_t st);
+// out_t = e_t - a_t s_t + f_t sp_t (f_t = 0 skips the last term), on nl limbs (map)
+void k_keyform(const Shared& sh, const u64* a, const u64* s, const u64* e, const u64* sp,
+               const u64* f, u64* out, int nl, int nq, int pofs, hipStream_t st);
+// out = x + y * z (+ w when w != null) on nl limbs of the ciphertext primes
+void k_fma3(const Shared& sh, const u64* x, const u64* y, const u64* z, const u64* w, u64* out,
+            int nl, hipStream_t st);
+
+// limb-wise copy of nrows rows of N words (strided)
+void k_copy_rows(const Shared& sh, const u64* src, u64* dst, int nrows, size_t sstride,
+                 size_t dstride, hipStream_t st);
+
+}  // namespace ppst

@@ -1,0 +1,614 @@
+// kernels.hip -- element-wise, base-conversion, key-switching, rescale and
+// sampling kernels.  All of them are HBM-streaming: one thread per residue
+// (or per coefficient, looping over the limbs it produces), consecutive
+// threads on consecutive words of a limb.
+#include "dev.h"
+#include "kern.h"
+#include "tables.h"
+
+namespace ppst {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+inline dim3 grid_for(size_t n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); }
+
+struct ScalarArr {
+  u64 v[kMaxLimbArgs];
+  u64 vp[kMaxLimbArgs];
+};
+
+// ------------------------------------------------------------------ basic
+__global__ void k_add_kernel(const u64* __restrict__ a, const u64* __restrict__ b, u64* out,
+                             const Mod* mods, int logN, int nl, int npoly, size_t sa, size_t sb,
+                             size_t so, int sub) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t per = (size_t)nl << logN;
+  if (i >= per * npoly) return;
+  int c = (int)(i / per);
+  size_t r = i - (size_t)c * per;
+  int t = (int)(r >> logN);
+  u64 q = mods[t].q;
+  u64 x = a[c * sa + r], y = b[c * sb + r];
+  out[c * so + r] = sub ? subm(x, y, q) : addm(x, y, q);
+}
+
+__global__ void k_mul_scalar_kernel(const u64* __restrict__ a, u64* out, const Mod* mods, int logN,
+                                    int nl, int npoly, size_t sa, size_t so, ScalarArr k) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t per = (size_t)nl << logN;
+  if (i >= per * npoly) return;
+  int c = (int)(i / per);
+  size_t r = i - (size_t)c * per;
+  int t = (int)(r >> logN);
+  out[c * so + r] = mul_shoup(a[c * sa + r], k.v[t], k.vp[t], mods[t].q);
+}
+
+__global__ void k_add_scalar_kernel(const u64* __restrict__ a, u64* out, const Mod* mods, int logN,
+                                    int nl, ScalarArr k) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ((size_t)nl << logN)) return;
+  int t = (int)(i >> logN);
+  out[i] = addm(a[i], k.v[t], mods[t].q);
+}
+
+__global__ void k_mul_poly_kernel(const u64* __restrict__ a, const u64* __restrict__ pt, u64* out,
+                                  const Mod* mods, int logN, int nl, int npoly, size_t sa,
+                                  size_t so) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t per = (size_t)nl << logN;
+  if (i >= per * npoly) return;
+  int c = (int)(i / per);
+  size_t r = i - (size_t)c * per;
+  int t = (int)(r >> logN);
+  out[c * so + r] = mulm(a[c * sa + r], pt[r], mods[t]);
+}
+
+__global__ void k_tensor_kernel(const u64* __restrict__ a, const u64* __restrict__ b, u64* d,
+                                const Mod* mods, int logN, int nl, size_t sa, size_t sb,
+                                size_t sd) {
+  size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t per = (size_t)nl << logN;
+  if (r >= per) return;
+  const size_t bo = blockIdx.y;
+  a += bo * sa;
+  b += bo * sb;
+  d += bo * sd;
+  const Mod m = mods[r >> logN];
+  u64 a0 = a[r], a1 = a[per + r], b0 = b[r], b1 = b[per + r];
+  d[r] = mulm(a0, b0, m);
+  Acc acc;
+  acc.mac(a0, b1);
+  acc.mac(a1, b0);
+  d[per + r] = reduce128(acc.hi, acc.lo, m);
+  d[2 * per + r] = mulm(a1, b1, m);
+}
+
+// slot j of the output reads slot j' with 2 brv(j') + 1 = (2 brv(j) + 1) g mod 2N
+__global__ void k_automorph_kernel(const u64* __restrict__ in, u64* out, int logN, int nrows,
+                                   size_t sin, size_t sout, u64 g) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ((size_t)nrows << logN)) return;
+  int row = (int)(i >> logN);
+  uint32_t j = (uint32_t)(i & ((1u << logN) - 1));
+  uint32_t mask2 = (2u << logN) - 1;
+  uint32_t e = 2 * (__brev(j) >> (32 - logN)) + 1;
+  uint32_t e2 = (uint32_t)(((u64)e * g) & mask2);
+  uint32_t jp = __brev((e2 - 1) >> 1) >> (32 - logN);
+  out[row * sout + j] = in[row * sin + jp];
+}
+
+// ----------------------------------------------------------- key switching
+struct ModUpArgs {
+  const u64* x;       // coefficient-form input limbs (limb t at x + t N)
+  u64* ext;           // output limbs (limb t at ext + t N)
+  const Mod* mods;
+  const u64* cst;     // [alpha][2] (Qhat_i^-1 mod q_i, Shoup), then [alpha][ne] Qhat_i mod p(t)
+  size_t sx, sext;
+  int logN, lo, hi, nl, ne, pofs, alpha;
+};
+
+// one thread per coefficient: z_i = x_i Qhat_i^-1 mod q_i, then for every
+// target limb t outside the digit, y_t = sum_i z_i (Qhat_i mod t) mod t
+template <int MAXA>
+__global__ void __launch_bounds__(kBlock) k_modup_kernel(ModUpArgs a) {
+  const int N = 1 << a.logN;
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  const u64* x = a.x + blockIdx.y * a.sx;
+  u64* ext = a.ext + blockIdx.y * a.sext;
+  const int da = a.hi - a.lo;
+  u64 z[MAXA];
+#pragma unroll
+  for (int i = 0; i < MAXA; ++i) {
+    if (i < da) {
+      u64 q = a.mods[a.lo + i].q;
+      z[i] = mul_shoup(x[(size_t)(a.lo + i) * N + k], a.cst[2 * i], a.cst[2 * i + 1], q);
+    }
+  }
+  const u64* qhat = a.cst + 2 * a.alpha;
+  for (int t = 0; t < a.ne; ++t) {
+    if (t >= a.lo && t < a.hi) continue;
+    int p = t < a.nl ? t : a.pofs + (t - a.nl);
+    const Mod m = a.mods[p];
+    Acc acc;
+#pragma unroll
+    for (int i = 0; i < MAXA; ++i)
+      if (i < da) acc.mac(z[i], qhat[i * a.ne + t]);
+    ext[(size_t)t * N + k] = reduce128(acc.hi, acc.lo, m);
+  }
+}
+
+struct InnerArgs {
+  const u64* d;       // NTT-form input limbs [nl][N]
+  const u64* ext;     // [beta][ne][N]
+  const u64* key;     // [dnum][2][nprimes][N]
+  u64* u;             // [2][ne][N]
+  const Mod* mods;
+  size_t sd, sext, su;
+  int logN, nl, ne, beta, alpha, pofs, nprimes;
+};
+
+__global__ void __launch_bounds__(kBlock) k_ks_inner_kernel(InnerArgs a) {
+  const size_t N = (size_t)1 << a.logN;
+  size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= (size_t)a.ne * N) return;
+  const int t = (int)(r >> a.logN);
+  const size_t k = r & (N - 1);
+  const int p = t < a.nl ? t : a.pofs + (t - a.nl);
+  const Mod m = a.mods[p];
+  const u64* d = a.d + blockIdx.y * a.sd;
+  const u64* ext = a.ext + blockIdx.y * a.sext;
+  u64* u = a.u + blockIdx.y * a.su;
+  const int own = t < a.nl ? t / a.alpha : -1;   // digit holding limb t
+  Acc a0, a1;
+  for (int j = 0; j < a.beta; ++j) {
+    u64 e = (j == own) ? d[(size_t)t * N + k] : ext[((size_t)j * a.ne + t) * N + k];
+    const u64* kb = a.key + ((size_t)(2 * j) * a.nprimes + p) * N;
+    const u64* ka = a.key + ((size_t)(2 * j + 1) * a.nprimes + p) * N;
+    a0.mac(e, kb[k]);
+    a1.mac(e, ka[k]);
+  }
+  u[(size_t)t * N + k] = reduce128(a0.hi, a0.lo, m);
+  u[((size_t)a.ne + t) * N + k] = reduce128(a1.hi, a1.lo, m);
+}
+
+struct ModDownArgs {
+  const u64* u;       // [2][ne][N]; special limbs at nl.. in coefficient form
+  u64* conv;          // [2][nl][N]
+  const Mod* mods;
+  const u64* md;      // moddown table (see tables.h)
+  size_t su, sconv;
+  int logN, nl, ne, K, L;
+};
+
+template <int MAXK>
+__global__ void __launch_bounds__(kBlock) k_moddown_conv_kernel(ModDownArgs a) {
+  const int N = 1 << a.logN;
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  const int c = blockIdx.z;
+  const u64* u = a.u + blockIdx.y * a.su + (size_t)c * a.ne * N;
+  u64* conv = a.conv + blockIdx.y * a.sconv + (size_t)c * a.nl * N;
+  const MdLayout lay(a.K, a.L);
+  u64 w[MAXK];
+#pragma unroll
+  for (int i = 0; i < MAXK; ++i) {
+    if (i < a.K) {
+      const int p = a.L + 1 + i;
+      const u64 q = a.mods[p].q;
+      u64 z = addm(u[(size_t)(a.nl + i) * N + k], a.md[lay.hmod(p)], q);
+      w[i] = mul_shoup(z, a.md[lay.phinv(i)], a.md[lay.phinv(i) + 1], q);
+    }
+  }
+  for (int i = 0; i < a.nl; ++i) {
+    const Mod m = a.mods[i];
+    Acc acc;
+#pragma unroll
+    for (int j = 0; j < MAXK; ++j)
+      if (j < a.K) acc.mac(w[j], a.md[lay.phat(j, i)]);
+    u64 v = reduce128(acc.hi, acc.lo, m);
+    conv[(size_t)i * N + k] = subm(v, a.md[lay.hmod(i)], m.q);
+  }
+}
+
+__global__ void k_moddown_final_kernel(const u64* __restrict__ u, const u64* __restrict__ conv,
+                                       const u64* add0, const u64* add1, u64* out,
+                                       const Mod* mods, const u64* md, int K, int L, int logN,
+                                       int nl, int ne, size_t su, size_t sc, size_t sa,
+                                       size_t so) {
+  size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t per = (size_t)nl << logN;
+  if (r >= per) return;
+  const int c = blockIdx.z;
+  const size_t b = blockIdx.y;
+  const int i = (int)(r >> logN);
+  const u64 q = mods[i].q;
+  const MdLayout lay(K, L);
+  u64 x = u[b * su + (size_t)c * ((size_t)ne << logN) + r];
+  u64 y = conv[b * sc + (size_t)c * per + r];
+  u64 v = mul_shoup(subm(x, y, q), md[lay.pinv(i)], md[lay.pinv(i) + 1], q);
+  const u64* add = c ? add1 : add0;
+  if (add) v = addm(v, add[b * sa + r], q);
+  out[b * so + (size_t)c * per + r] = v;
+}
+
+// ------------------------------------------------------------------ rescale
+__global__ void k_rescale_conv_kernel(const u64* __restrict__ top, u64* tmp, const Mod* mods,
+                                      const u64* rc, int logN, int level, size_t ts) {
+  const size_t N = (size_t)1 << logN;
+  size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= (size_t)level * N) return;
+  const int c = blockIdx.y;
+  const int i = (int)(r >> logN);
+  const size_t k = r & (N - 1);
+  const u64 ql = mods[level].q;
+  u64 x = top[c * ts + k];
+  const Mod m = mods[i];
+  u64 v = reduce64(x, m);
+  if (x > (ql >> 1)) v = subm(v, rc[3 * i + 2], m.q);   // centred: x - q_l
+  tmp[((size_t)c * level << logN) + r] = v;
+}
+
+__global__ void k_rescale_final_kernel(const u64* __restrict__ a, const u64* __restrict__ tmp,
+                                       u64* out, const Mod* mods, const u64* rc, int logN,
+                                       int level, size_t sa, size_t so) {
+  size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t per = (size_t)level << logN;
+  if (r >= per) return;
+  const int c = blockIdx.y;
+  const int i = (int)(r >> logN);
+  const u64 q = mods[i].q;
+  u64 v = subm(a[c * sa + r], tmp[c * per + r], q);
+  out[c * so + r] = mul_shoup(v, rc[3 * i], rc[3 * i + 1], q);
+}
+
+// ----------------------------------------------------------------- sampling
+__device__ __forceinline__ u64 sm_mix(u64 z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+constexpr u64 kGamma = 0x9E3779B97F4A7C15ULL;
+// word i of the stream whose state starts at key
+__device__ __forceinline__ u64 sm_word(u64 key, u64 i) { return sm_mix(key + (i + 1) * kGamma); }
+
+__global__ void k_small_to_rns_kernel(const int32_t* s, u64* out, const Mod* mods, int logN,
+                                      int nl, int nq, int pofs) {
+  size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= ((size_t)nl << logN)) return;
+  int t = (int)(r >> logN);
+  int p = t < nq ? t : pofs + (t - nq);
+  u64 q = mods[p].q;
+  int32_t v = s[r & (((size_t)1 << logN) - 1)];
+  out[r] = v >= 0 ? (u64)v : q - (u64)(-(int64_t)v);
+}
+
+__global__ void k_int64_to_rns_kernel(const int64_t* s, u64* out, const Mod* mods, int logN,
+                                      int nl, int nq, int pofs) {
+  size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= ((size_t)nl << logN)) return;
+  int t = (int)(r >> logN);
+  int p = t < nq ? t : pofs + (t - nq);
+  const Mod m = mods[p];
+  int64_t v = s[r & (((size_t)1 << logN) - 1)];
+  if (v >= 0) {
+    out[r] = reduce64((u64)v, m);
+  } else {
+    u64 w = reduce64((u64)(-(v + 1)), m);    // (-v - 1) mod q, safe at INT64_MIN
+    out[r] = m.q - 1 - w;
+  }
+}
+
+struct KeyArr {
+  u64 k[kMaxLimbArgs];
+};
+
+__global__ void k_uniform_kernel(u64* out, const Mod* mods, int logN, int nl, int nq, int pofs,
+                                 KeyArr keys) {
+  size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= ((size_t)nl << logN)) return;
+  int t = (int)(r >> logN);
+  int p = t < nq ? t : pofs + (t - nq);
+  u64 k = r & (((size_t)1 << logN) - 1);
+  u64 hi = sm_word(keys.k[t], 2 * k), lo = sm_word(keys.k[t], 2 * k + 1);
+  const Mod m = mods[p];
+  // (hi 2^64 + lo) mod q = ((hi mod q) 2^64 + lo) mod q, first factor < 2^60
+  out[r] = reduce128(reduce64(hi, m), lo, m);
+}
+
+__global__ void k_ternary_kernel(int32_t* out, int N, u64 key) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  u64 u = sm_word(key, (u64)k);
+  out[k] = (int32_t)mulhi(u, 3) - 1;
+}
+
+struct DgArr {
+  u64 thr[kDgMax];
+};
+
+__global__ void k_dg_kernel(int32_t* out, int N, u64 key, DgArr d) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  u64 u = sm_word(key, 2 * (u64)k);
+  u64 sg = sm_word(key, 2 * (u64)k + 1);
+  int mag = kDgMax;
+  for (int x = kDgMax - 1; x >= 0; --x)
+    if (u < d.thr[x]) mag = x;
+  out[k] = (mag != 0 && (sg >> 63)) ? -mag : mag;
+}
+
+__global__ void k_keyform_kernel(const u64* a, const u64* s, const u64* e, const u64* sp,
+                                 ScalarArr f, u64* out, const Mod* mods, int logN, int nl,
+                                 int nq, int pofs, int use_sp) {
+  size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= ((size_t)nl << logN)) return;
+  int t = (int)(r >> logN);
+  int p = t < nq ? t : pofs + (t - nq);
+  const Mod m = mods[p];
+  size_t kk = r & (((size_t)1 << logN) - 1);
+  size_t so = ((size_t)p << logN) + kk;   // s and sp are indexed by prime
+  u64 v = subm(e[r], mulm(a[r], s[so], m), m.q);
+  if (use_sp && f.v[t]) v = addm(v, mul_shoup(sp[so], f.v[t], f.vp[t], m.q), m.q);
+  out[r] = v;
+}
+
+__global__ void k_fma3_kernel(const u64* x, const u64* y, const u64* z, const u64* w, u64* out,
+                              const Mod* mods, int logN, int nl) {
+  size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= ((size_t)nl << logN)) return;
+  const Mod m = mods[r >> logN];
+  u64 v = addm(x[r], mulm(y[r], z[r], m), m.q);
+  if (w) v = addm(v, w[r], m.q);
+  out[r] = v;
+}
+
+__global__ void k_copy_rows_kernel(const u64* src, u64* dst, int logN, int nrows, size_t ss,
+                                   size_t ds) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ((size_t)nrows << logN)) return;
+  size_t row = i >> logN, k = i & (((size_t)1 << logN) - 1);
+  dst[row * ds + k] = src[row * ss + k];
+}
+
+const Mod* M(const Shared& sh) { return (const Mod*)sh.tab.mods.p; }
+
+ScalarArr scalars(const Shared& sh, const u64* k, const u64* kp, int nl) {
+  ScalarArr s;
+  for (int t = 0; t < nl; ++t) { s.v[t] = k[t]; s.vp[t] = kp ? kp[t] : 0; }
+  return s;
+}
+
+}  // namespace
+
+#define LAUNCH_CHECK() HIP_CHECK(hipGetLastError())
+
+void k_add(const Shared& sh, const u64* a, const u64* b, u64* out, int npoly, int nl,
+           size_t sa, size_t sb, size_t so, bool sub, hipStream_t st) {
+  size_t n = (size_t)npoly * nl * sh.P.N;
+  hipLaunchKernelGGL(k_add_kernel, grid_for(n), dim3(kBlock), 0, st, a, b, out, M(sh), sh.P.logN,
+                     nl, npoly, sa, sb, so, (int)sub);
+  LAUNCH_CHECK();
+}
+
+void k_mul_scalar(const Shared& sh, const u64* a, u64* out, int npoly, int nl, size_t sa,
+                  size_t so, const u64* k, const u64* kp, hipStream_t st) {
+  if (nl > kMaxLimbArgs) PPST_THROW(ST_EINVAL, "too many limbs");
+  size_t n = (size_t)npoly * nl * sh.P.N;
+  hipLaunchKernelGGL(k_mul_scalar_kernel, grid_for(n), dim3(kBlock), 0, st, a, out, M(sh),
+                     sh.P.logN, nl, npoly, sa, so, scalars(sh, k, kp, nl));
+  LAUNCH_CHECK();
+}
+
+void k_add_scalar(const Shared& sh, const u64* a, u64* out, int nl, const u64* k, hipStream_t st) {
+  size_t n = (size_t)nl * sh.P.N;
+  hipLaunchKernelGGL(k_add_scalar_kernel, grid_for(n), dim3(kBlock), 0, st, a, out, M(sh),
+                     sh.P.logN, nl, scalars(sh, k, nullptr, nl));
+  LAUNCH_CHECK();
+}
+
+void k_mul_poly(const Shared& sh, const u64* a, const u64* pt, u64* out, int npoly, int nl,
+                size_t sa, size_t so, hipStream_t st) {
+  size_t n = (size_t)npoly * nl * sh.P.N;
+  hipLaunchKernelGGL(k_mul_poly_kernel, grid_for(n), dim3(kBlock), 0, st, a, pt, out, M(sh),
+                     sh.P.logN, nl, npoly, sa, so);
+  LAUNCH_CHECK();
+}
+
+void k_tensor(const Shared& sh, const u64* a, const u64* b, u64* d, int nl, int nbatch,
+              size_t sa, size_t sb, size_t sd, hipStream_t st) {
+  size_t n = (size_t)nl * sh.P.N;
+  dim3 g = grid_for(n);
+  g.y = nbatch;
+  hipLaunchKernelGGL(k_tensor_kernel, g, dim3(kBlock), 0, st, a, b, d, M(sh), sh.P.logN, nl, sa,
+                     sb, sd);
+  LAUNCH_CHECK();
+}
+
+void k_automorph(const Shared& sh, const u64* in, u64* out, int nrows, size_t sin, size_t sout,
+                 u64 g, hipStream_t st) {
+  size_t n = (size_t)nrows * sh.P.N;
+  hipLaunchKernelGGL(k_automorph_kernel, grid_for(n), dim3(kBlock), 0, st, in, out, sh.P.logN,
+                     nrows, sin, sout, g);
+  LAUNCH_CHECK();
+}
+
+void k_modup(const Shared& sh, const u64* x, u64* ext, int level, int digit, int nbatch,
+             size_t sx, size_t sext, hipStream_t st) {
+  const Params& P = sh.P;
+  ModUpArgs a;
+  a.x = x;
+  a.ext = ext;
+  a.mods = M(sh);
+  a.cst = modup_table(sh, level, digit);
+  a.sx = sx;
+  a.sext = sext;
+  a.logN = P.logN;
+  a.lo = P.digit_lo(digit);
+  a.hi = P.digit_hi(digit, level);
+  a.nl = level + 1;
+  a.ne = level + 1 + P.K;
+  a.pofs = P.L + 1;
+  a.alpha = P.alpha;
+  dim3 g = grid_for(P.N);
+  g.y = nbatch;
+  if (P.alpha <= 4) hipLaunchKernelGGL(k_modup_kernel<4>, g, dim3(kBlock), 0, st, a);
+  else if (P.alpha <= 9) hipLaunchKernelGGL(k_modup_kernel<9>, g, dim3(kBlock), 0, st, a);
+  else if (P.alpha <= 16) hipLaunchKernelGGL(k_modup_kernel<16>, g, dim3(kBlock), 0, st, a);
+  else PPST_THROW(ST_EINVAL, "digit size above 16 limbs");
+  LAUNCH_CHECK();
+}
+
+void k_ks_inner(const Shared& sh, const u64* d, const u64* ext, const u64* key, u64* u, int level,
+                int nbatch, size_t sd, size_t sext, size_t su, hipStream_t st) {
+  const Params& P = sh.P;
+  InnerArgs a;
+  a.d = d;
+  a.ext = ext;
+  a.key = key;
+  a.u = u;
+  a.mods = M(sh);
+  a.sd = sd;
+  a.sext = sext;
+  a.su = su;
+  a.logN = P.logN;
+  a.nl = level + 1;
+  a.ne = level + 1 + P.K;
+  a.beta = P.beta(level);
+  a.alpha = P.alpha;
+  a.pofs = P.L + 1;
+  a.nprimes = P.nprimes;
+  dim3 g = grid_for((size_t)a.ne * P.N);
+  g.y = nbatch;
+  hipLaunchKernelGGL(k_ks_inner_kernel, g, dim3(kBlock), 0, st, a);
+  LAUNCH_CHECK();
+}
+
+void k_moddown_conv(const Shared& sh, const u64* u, u64* conv, int level, int nbatch, size_t su,
+                    size_t sconv, hipStream_t st) {
+  const Params& P = sh.P;
+  ModDownArgs a;
+  a.u = u;
+  a.conv = conv;
+  a.mods = M(sh);
+  a.md = sh.tab.moddown.p;
+  a.su = su;
+  a.sconv = sconv;
+  a.logN = P.logN;
+  a.nl = level + 1;
+  a.ne = level + 1 + P.K;
+  a.K = P.K;
+  a.L = P.L;
+  dim3 g = grid_for(P.N);
+  g.y = nbatch;
+  g.z = 2;
+  if (P.K <= 4) hipLaunchKernelGGL(k_moddown_conv_kernel<4>, g, dim3(kBlock), 0, st, a);
+  else if (P.K <= 8) hipLaunchKernelGGL(k_moddown_conv_kernel<8>, g, dim3(kBlock), 0, st, a);
+  else PPST_THROW(ST_EINVAL, "more than 8 special primes");
+  LAUNCH_CHECK();
+}
+
+void k_moddown_final(const Shared& sh, const u64* u, const u64* conv, const u64* add0,
+                     const u64* add1, u64* out, int level, int nbatch, size_t su, size_t sc,
+                     size_t sa, size_t so, hipStream_t st) {
+  const Params& P = sh.P;
+  int nl = level + 1;
+  dim3 g = grid_for((size_t)nl * P.N);
+  g.y = nbatch;
+  g.z = 2;
+  hipLaunchKernelGGL(k_moddown_final_kernel, g, dim3(kBlock), 0, st, u, conv, add0, add1, out,
+                     M(sh), sh.tab.moddown.p, P.K, P.L, P.logN, nl, nl + P.K, su, sc, sa, so);
+  LAUNCH_CHECK();
+}
+
+void k_rescale_conv(const Shared& sh, const u64* top, u64* tmp, int level, int npoly,
+                    size_t top_stride, hipStream_t st) {
+  dim3 g = grid_for((size_t)level * sh.P.N);
+  g.y = npoly;
+  hipLaunchKernelGGL(k_rescale_conv_kernel, g, dim3(kBlock), 0, st, top, tmp, M(sh),
+                     rescale_table(sh, level), sh.P.logN, level, top_stride);
+  LAUNCH_CHECK();
+}
+
+void k_rescale_final(const Shared& sh, const u64* a, const u64* tmp, u64* out, int level,
+                     int npoly, size_t sa, size_t so, hipStream_t st) {
+  dim3 g = grid_for((size_t)level * sh.P.N);
+  g.y = npoly;
+  hipLaunchKernelGGL(k_rescale_final_kernel, g, dim3(kBlock), 0, st, a, tmp, out, M(sh),
+                     rescale_table(sh, level), sh.P.logN, level, sa, so);
+  LAUNCH_CHECK();
+}
+
+void k_int64_to_rns(const Shared& sh, const int64_t* s, u64* out, int nl, int nq, int pofs,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(k_int64_to_rns_kernel, grid_for((size_t)nl * sh.P.N), dim3(kBlock), 0, st, s,
+                     out, M(sh), sh.P.logN, nl, nq, pofs);
+  LAUNCH_CHECK();
+}
+
+void k_small_to_rns(const Shared& sh, const int32_t* s, u64* out, int nl, int nq, int pofs,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(k_small_to_rns_kernel, grid_for((size_t)nl * sh.P.N), dim3(kBlock), 0, st, s,
+                     out, M(sh), sh.P.logN, nl, nq, pofs);
+  LAUNCH_CHECK();
+}
+
+void k_sample_uniform(const Shared& sh, u64* out, int nl, int nq, int pofs, u64 seed, u64 purpose,
+                      hipStream_t st) {
+  if (nl > kMaxLimbArgs) PPST_THROW(ST_EINVAL, "too many limbs");
+  KeyArr keys;
+  for (int t = 0; t < nl; ++t) {
+    int p = t < nq ? t : pofs + (t - nq);
+    keys.k[t] = stream_key(seed, purpose, (u64)p);
+  }
+  hipLaunchKernelGGL(k_uniform_kernel, grid_for((size_t)nl * sh.P.N), dim3(kBlock), 0, st, out,
+                     M(sh), sh.P.logN, nl, nq, pofs, keys);
+  LAUNCH_CHECK();
+}
+
+void k_sample_ternary(const Shared& sh, int32_t* out, u64 seed, u64 purpose, hipStream_t st) {
+  hipLaunchKernelGGL(k_ternary_kernel, grid_for(sh.P.N), dim3(kBlock), 0, st, out, sh.P.N,
+                     stream_key(seed, purpose, 0));
+  LAUNCH_CHECK();
+}
+
+void k_sample_dg(const Shared& sh, int32_t* out, u64 seed, u64 purpose, hipStream_t st) {
+  DgArr d;
+  for (int i = 0; i < kDgMax; ++i) d.thr[i] = sh.dg_thr[i];
+  hipLaunchKernelGGL(k_dg_kernel, grid_for(sh.P.N), dim3(kBlock), 0, st, out, sh.P.N,
+                     stream_key(seed, purpose, 0), d);
+  LAUNCH_CHECK();
+}
+
+void k_keyform(const Shared& sh, const u64* a, const u64* s, const u64* e, const u64* sp,
+               const u64* f, u64* out, int nl, int nq, int pofs, hipStream_t st) {
+  if (nl > kMaxLimbArgs) PPST_THROW(ST_EINVAL, "too many limbs");
+  ScalarArr fa;
+  for (int t = 0; t < nl; ++t) {
+    int p = t < nq ? t : pofs + (t - nq);
+    u64 v = f ? f[t] : 0;
+    fa.v[t] = v;
+    fa.vp[t] = v ? shoup(v, sh.P.q[p]) : 0;
+  }
+  hipLaunchKernelGGL(k_keyform_kernel, grid_for((size_t)nl * sh.P.N), dim3(kBlock), 0, st, a, s,
+                     e, sp, fa, out, M(sh), sh.P.logN, nl, nq, pofs, sp ? 1 : 0);
+  LAUNCH_CHECK();
+}
+
+void k_fma3(const Shared& sh, const u64* x, const u64* y, const u64* z, const u64* w, u64* out,
+            int nl, hipStream_t st) {
+  hipLaunchKernelGGL(k_fma3_kernel, grid_for((size_t)nl * sh.P.N), dim3(kBlock), 0, st, x, y, z,
+                     w, out, M(sh), sh.P.logN, nl);
+  LAUNCH_CHECK();
+}
+
+void k_copy_rows(const Shared& sh, const u64* src, u64* dst, int nrows, size_t ss, size_t ds,
+                 hipStream_t st) {
+  hipLaunchKernelGGL(k_copy_rows_kernel, grid_for((size_t)nrows * sh.P.N), dim3(kBlock), 0, st,
+                     src, dst, sh.P.logN, nrows, ss, ds);
+  LAUNCH_CHECK();
+}
+
+}  // namespace ppst

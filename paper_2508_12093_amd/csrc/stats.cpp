@@ -1,0 +1,317 @@
+// stats.cpp -- the PP-STAT statistics as fixed sequences of CKKS operations.
+//
+// Paper references: Mean(x,B) and Variance(x,B) with pre-normalisation
+// scaling (Sec. 5.1, Eq. 2); CryptoInvSqrt = Chebyshev initial value
+// (Alg. 3, Eq. 3) + Newton iterations (Alg. 2); ZNorm (Alg. 4); kurtosis
+// (Alg. 5) and skewness (its mirror, Sec. 5); CV (Alg. 6); PCC (Sec. 5.5).
+//
+// Conventions that make the sequence reproducible bit for bit:
+//   * a binary operation on operands at different levels first brings the
+//     higher one down to the lower level (level_align);
+//   * sums over lists fold left to right;
+//   * FP64 constants are formed exactly as written below;
+//   * Newton (n = 2) runs in the balanced order y2 = y*y, p1 = w2*y,
+//     p2 = p1*y2, y = 1.5 y - p2 with w2 = (B'/2) v, two levels per step;
+//   * sqrt(v; B') = 2 * w2 * InvSqrt(v; B') (Alg. 6 reads CryptoSqrt(var, B);
+//     with Variance(x,B) = Var/B^2 the factor has to be B^2);
+//   * PCC = Cov * InvSqrt(Var x; Bx^2) * InvSqrt(Var y; By^2);
+//   * slots past the row count are zero; centred moments use a 1/n row mask,
+//     a constant when a ciphertext is full and a plaintext vector otherwise.
+#include "stats.h"
+
+#include <cmath>
+
+namespace ppst {
+
+namespace {
+
+struct Circ {
+  Context& cx;
+  const EvalKeys& evk;
+
+  CtPtr at(const CtPtr& a, int level) { return a->level == level ? a : level_align(cx, *a, level); }
+  CtPtr addx(const CtPtr& a, const CtPtr& b) {
+    int m = std::min(a->level, b->level);
+    return add(cx, *at(a, m), *at(b, m));
+  }
+  CtPtr subx(const CtPtr& a, const CtPtr& b) {
+    int m = std::min(a->level, b->level);
+    return sub(cx, *at(a, m), *at(b, m));
+  }
+  CtPtr mulx(const CtPtr& a, const CtPtr& b) {
+    int m = std::min(a->level, b->level);
+    return mul(cx, evk, *at(a, m), *at(b, m));
+  }
+  CtPtr sq(const CtPtr& a) { return mul(cx, evk, *a, *a); }
+  CtPtr mc(const CtPtr& a, double c) { return mul_const(cx, *a, c); }
+  CtPtr sum(const std::vector<CtPtr>& xs) {
+    CtPtr acc = xs[0];
+    for (size_t i = 1; i < xs.size(); ++i) acc = addx(acc, xs[i]);
+    return acc;
+  }
+  CtPtr rs(const CtPtr& a) { return rotsum(cx, evk, *a); }
+
+  CtPtr mask_mean(const std::vector<CtPtr>& zs, size_t n) {
+    const size_t S = (size_t)cx.P().slots();
+    std::vector<CtPtr> terms;
+    for (size_t c = 0; c < zs.size(); ++c) {
+      size_t rows = std::min(S, n - c * S);
+      if (rows == S) {
+        terms.push_back(mc(zs[c], 1.0 / (double)n));
+      } else {
+        std::vector<double> v(S, 0.0);
+        for (size_t j = 0; j < rows; ++j) v[j] = 1.0 / (double)n;
+        auto pt = encode(cx, v.data(), S, zs[c]->level);
+        terms.push_back(mul_plain(cx, *zs[c], *pt));
+      }
+    }
+    return rs(sum(terms));
+  }
+
+  CtPtr mean_B(const std::vector<CtPtr>& X, size_t n, double B) {
+    const double c = 1.0 / (B * (double)n);
+    std::vector<CtPtr> t;
+    for (auto& x : X) t.push_back(mc(x, c));
+    return rs(sum(t));
+  }
+
+  CtPtr variance_B(const std::vector<CtPtr>& X, size_t n, double B, const CtPtr& mean_term) {
+    const double c = 1.0 / (B * std::sqrt((double)n));
+    std::vector<CtPtr> sqs;
+    for (auto& x : X) {
+      auto xs = mc(x, c);
+      sqs.push_back(sq(xs));
+    }
+    auto e2 = rs(sum(sqs));
+    auto m2 = sq(mean_term);
+    return subx(e2, m2);
+  }
+
+  std::vector<double> coeffs(const InvSqrtCfg& cfg, double Bp) {
+    std::vector<double> base;
+    if (!cfg.coeffs.empty()) {
+      base = cfg.coeffs;
+    } else {
+      base = chebyshev_invsqrt(cfg.a, cfg.b, cfg.degree, 1.0);
+    }
+    const double r = std::sqrt(Bp);
+    for (auto& v : base) v = v / r;
+    return base;
+  }
+
+  std::pair<CtPtr, CtPtr> inv_sqrt(const CtPtr& v, double Bp, const InvSqrtCfg& cfg) {
+    const double a = cfg.a, b = cfg.b;
+    const int d = cfg.degree;
+    auto c = coeffs(cfg, Bp);
+    if ((int)c.size() != d + 1) PPST_THROW(ST_EINVAL, "coefficient table does not match the degree");
+    auto t = add_const(cx, *mc(v, 2.0 / (b - a)), -(a + b) / (b - a));
+    std::vector<CtPtr> T(d + 1);
+    T[1] = t;
+    for (int k = 2; k <= d; ++k) {
+      if (k % 2 == 0) {
+        int m = k / 2;
+        T[k] = add_const(cx, *mul_int(cx, *sq(T[m]), 2), -1.0);
+      } else {
+        int m = (k - 1) / 2;
+        T[k] = subx(mul_int(cx, *mulx(T[m], T[m + 1]), 2), T[1]);
+      }
+    }
+    std::vector<CtPtr> terms;
+    for (int k = 1; k <= d; ++k) terms.push_back(mc(T[k], c[k]));
+    auto y = add_const(cx, *sum(terms), c[0]);
+    T.clear();
+    auto w2 = mc(v, Bp / 2.0);
+    for (int it = 0; it < cfg.iters; ++it) {
+      auto y2 = sq(y);
+      auto p1 = mulx(w2, y);
+      auto p2 = mulx(p1, y2);
+      y = subx(mc(y, 1.5), p2);
+    }
+    return {y, w2};
+  }
+
+  CtPtr sqrt_(const CtPtr& v, double Bp, const InvSqrtCfg& cfg) {
+    auto yw = inv_sqrt(v, Bp, cfg);
+    return mul_int(cx, *mulx(yw.second, yw.first), 2);
+  }
+
+  CtPtr g3(const CtPtr& x) {
+    auto u = sq(x);
+    auto w = sq(u);
+    auto a1 = mc(x, 35.0 / 16.0);
+    auto a3 = mulx(mc(x, -35.0 / 16.0), u);
+    auto a5 = mulx(mc(x, 21.0 / 16.0), w);
+    auto a7 = mulx(mulx(mc(x, -5.0 / 16.0), u), w);
+    return sum({a1, a3, a5, a7});
+  }
+
+  void check_depth(const std::vector<CtPtr>& X, int need) {
+    for (auto& x : X)
+      if (x->level < need)
+        PPST_THROW(ST_ELEVEL, "statistic needs " + std::to_string(need) + " levels, input has " +
+                               std::to_string(x->level));
+  }
+};
+
+void check_column(const Params& P, const std::vector<CtPtr>& X, size_t nrows) {
+  if (X.empty()) PPST_THROW(ST_EINVAL, "empty column");
+  if (nrows == 0) PPST_THROW(ST_EINVAL, "row count is zero");
+  size_t need = (nrows + P.slots() - 1) / P.slots();
+  if (need != X.size())
+    PPST_THROW(ST_EINVAL, "row count does not match the number of ciphertexts");
+  for (auto& x : X)
+    if (x->level != X[0]->level) PPST_THROW(ST_ESCALE, "column ciphertexts at different levels");
+}
+
+void check_cfg(const InvSqrtCfg& cfg) {
+  if (!(cfg.a > 0.0) || !(cfg.b > cfg.a)) PPST_THROW(ST_EDOMAIN, "InvSqrt interval needs 0 < a < b");
+  if (cfg.degree < 1 || cfg.degree > 63) PPST_THROW(ST_EDOMAIN, "Chebyshev degree out of range");
+  if (cfg.iters < 0 || cfg.iters > 16) PPST_THROW(ST_EDOMAIN, "Newton iteration count out of range");
+}
+
+// levels consumed by InvSqrt: affine map, ladder, coefficient products, Newton
+int invsqrt_depth(const InvSqrtCfg& cfg) {
+  int ladder = 0;
+  while ((1 << ladder) < cfg.degree + 1) ++ladder;
+  return 1 + ladder + 1 + 2 * cfg.iters;
+}
+
+}  // namespace
+
+std::vector<double> chebyshev_invsqrt(double a, double b, int degree, double Bp) {
+  const int n = degree + 1;
+  std::vector<double> fx(n), th(n);
+  const double pi = 3.14159265358979323846;
+  for (int j = 0; j < n; ++j) {
+    th[j] = pi * ((double)j + 0.5) / (double)n;
+    double t = std::cos(th[j]);
+    double v = a + (b - a) * (t + 1.0) / 2.0;
+    fx[j] = 1.0 / std::sqrt(Bp * v);
+  }
+  std::vector<double> c(n);
+  for (int k = 0; k < n; ++k) {
+    double s = 0.0;
+    for (int j = 0; j < n; ++j) s += fx[j] * std::cos((double)k * th[j]);
+    c[k] = (k == 0 ? 1.0 : 2.0) * s / (double)n;
+  }
+  return c;
+}
+
+CtPtr stat_mean(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& X, size_t n, double B) {
+  check_column(cx.P(), X, n);
+  Circ c{cx, evk};
+  c.check_depth(X, 1);
+  return c.mean_B(X, n, B);
+}
+
+CtPtr stat_variance(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& X, size_t n,
+                    double B) {
+  check_column(cx.P(), X, n);
+  Circ c{cx, evk};
+  c.check_depth(X, 2);
+  auto mu = c.mean_B(X, n, B);
+  return c.variance_B(X, n, B, mu);
+}
+
+std::vector<CtPtr> stat_zscore(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& X,
+                               size_t n, double B, const InvSqrtCfg& cfg) {
+  check_column(cx.P(), X, n);
+  check_cfg(cfg);
+  Circ c{cx, evk};
+  c.check_depth(X, 3 + invsqrt_depth(cfg));
+  auto muB = c.mean_B(X, n, B);
+  auto var = c.variance_B(X, n, B, muB);
+  auto mu = c.mc(muB, B);
+  auto b = c.inv_sqrt(var, B * B, cfg).first;
+  std::vector<CtPtr> out;
+  for (auto& x : X) out.push_back(c.mulx(c.subx(x, mu), b));
+  return out;
+}
+
+CtPtr stat_kurtosis(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& X, size_t n,
+                    double B, const InvSqrtCfg& cfg, bool excess) {
+  check_column(cx.P(), X, n);
+  check_cfg(cfg);
+  Circ c{cx, evk};
+  c.check_depth(X, 5 + invsqrt_depth(cfg));
+  auto muB = c.mean_B(X, n, B);
+  auto var = c.variance_B(X, n, B, muB);
+  auto mu = c.mc(muB, B);
+  std::vector<CtPtr> x4;
+  for (auto& x : X) {
+    auto x1 = c.subx(x, mu);
+    auto x2 = c.sq(x1);
+    x4.push_back(c.sq(x2));
+  }
+  auto num = c.mask_mean(x4, n);
+  auto i = c.inv_sqrt(var, B * B, cfg).first;
+  auto i2 = c.sq(i);
+  auto i4 = c.sq(i2);
+  auto k = c.mulx(num, i4);
+  return excess ? add_const(cx, *k, -3.0) : k;
+}
+
+CtPtr stat_skewness(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& X, size_t n,
+                    double B, const InvSqrtCfg& cfg) {
+  check_column(cx.P(), X, n);
+  check_cfg(cfg);
+  Circ c{cx, evk};
+  c.check_depth(X, 5 + invsqrt_depth(cfg));
+  auto muB = c.mean_B(X, n, B);
+  auto var = c.variance_B(X, n, B, muB);
+  auto mu = c.mc(muB, B);
+  std::vector<CtPtr> x3;
+  for (auto& x : X) {
+    auto x1 = c.subx(x, mu);
+    auto x2 = c.sq(x1);
+    x3.push_back(c.mulx(x2, x1));
+  }
+  auto num = c.mask_mean(x3, n);
+  auto i = c.inv_sqrt(var, B * B, cfg).first;
+  auto i2 = c.sq(i);
+  auto i3 = c.mulx(i2, i);
+  return c.mulx(num, i3);
+}
+
+CtPtr stat_cv(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& X, size_t n,
+              double B_mean, double B_var, const InvSqrtCfg& cfg, int sign_k) {
+  check_column(cx.P(), X, n);
+  check_cfg(cfg);
+  if (sign_k < 0 || sign_k > 8) PPST_THROW(ST_EDOMAIN, "sign composition count out of range");
+  Circ c{cx, evk};
+  c.check_depth(X, 1 + 3 * sign_k + 1 + invsqrt_depth(cfg) + 3);
+  auto muB = c.mean_B(X, n, B_mean);
+  CtPtr sg = muB;
+  for (int k = 0; k < sign_k; ++k) sg = c.g3(sg);
+  auto ia = c.inv_sqrt(c.mulx(muB, sg), B_mean, cfg).first;
+  auto mu_inv = c.sq(ia);
+  CtPtr mean_term = (B_var == B_mean) ? muB : c.mc(muB, B_mean / B_var);
+  auto var = c.variance_B(X, n, B_var, mean_term);
+  auto sigma = c.sqrt_(var, B_var * B_var, cfg);
+  return c.mulx(c.mulx(sigma, mu_inv), sg);
+}
+
+CtPtr stat_pearson(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& X,
+                   const std::vector<CtPtr>& Y, size_t n, double Bx, double By,
+                   const InvSqrtCfg& cfg) {
+  check_column(cx.P(), X, n);
+  check_column(cx.P(), Y, n);
+  check_cfg(cfg);
+  Circ c{cx, evk};
+  c.check_depth(X, 3 + invsqrt_depth(cfg) + 1);
+  c.check_depth(Y, 3 + invsqrt_depth(cfg) + 1);
+  auto muBx = c.mean_B(X, n, Bx);
+  auto varx = c.variance_B(X, n, Bx, muBx);
+  auto mux = c.mc(muBx, Bx);
+  auto muBy = c.mean_B(Y, n, By);
+  auto vary = c.variance_B(Y, n, By, muBy);
+  auto muy = c.mc(muBy, By);
+  std::vector<CtPtr> prods;
+  for (size_t i = 0; i < X.size(); ++i) prods.push_back(c.mulx(c.subx(X[i], mux), c.subx(Y[i], muy)));
+  auto cov = c.mask_mean(prods, n);
+  auto ix = c.inv_sqrt(varx, Bx * Bx, cfg).first;
+  auto iy = c.inv_sqrt(vary, By * By, cfg).first;
+  return c.mulx(cov, c.mulx(ix, iy));
+}
+
+}  // namespace ppst

@@ -1,0 +1,32 @@
+// tables.h -- device-resident CRT constant tables of key switching and rescale.
+#pragma once
+
+#include "core.h"
+
+namespace ppst {
+
+// ModDown table layout (one table serves every level):
+//   [K][2]      (Phat_k^-1 mod p_k, Shoup companion), Phat_k = P / p_k
+//   [K][L+1]    Phat_k mod q_i
+//   [L+1][2]    (P^-1 mod q_i, Shoup companion)
+//   [nprimes]   h mod (prime), h = (P - 1) / 2, the rounding offset
+struct MdLayout {
+  int K, L;
+  __host__ __device__ MdLayout(int k, int l) : K(k), L(l) {}
+  __host__ __device__ int phinv(int k) const { return 2 * k; }
+  __host__ __device__ int phat(int k, int i) const { return 2 * K + k * (L + 1) + i; }
+  __host__ __device__ int pinv(int i) const { return 2 * K + K * (L + 1) + 2 * i; }
+  __host__ __device__ int hmod(int p) const { return 2 * K + K * (L + 1) + 2 * (L + 1) + p; }
+  __host__ __device__ int size() const { return hmod(L + 1 + K); }
+};
+
+// Build every table of a parameter set on the device (called once per Shared).
+void build_tables(Shared& sh);
+
+// ModUp table for (level, digit): [alpha][2] (Qhat_i^-1 mod q_i, Shoup) for
+// the digit's limbs i, then [alpha][ne] Qhat_i mod p(t) for every extended limb t.
+const u64* modup_table(const Shared& sh, int level, int digit);
+// Rescale table for dropping q_level: [level][3] = (q_level^-1 mod q_i, Shoup, q_level mod q_i)
+const u64* rescale_table(const Shared& sh, int level);
+
+}  // namespace ppst

@@ -1,0 +1,64 @@
+"""The C-ABI library loads, exports every declared symbol, and its host-side
+logic (parameters, sampler table, stream keys, encoder) matches the oracle's
+independent implementation (CPU only: no device call is made)."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import ref
+from paper_2508_12093_amd import ffi, synth
+
+PRESETS = ["c1", "c2", "t1", "t2"]
+
+
+def test_library_exports_every_declared_symbol():
+    L = ffi.lib()
+    names = ffi.header_symbols()
+    assert len(names) > 60
+    for n in names:
+        assert hasattr(L, n), n
+        assert n in ffi._SIGS, "binding misses " + n
+
+
+def test_status_of_bad_preset():
+    with pytest.raises(ffi.PpstError) as e:
+        ffi.ppst_params_preset("nope")
+    assert e.value.code == -1
+
+
+@pytest.mark.parametrize("name", PRESETS)
+def test_parameters_match_oracle(name):
+    p = ffi.ppst_params_preset(name)
+    spec = ref.PRESETS[name]
+    assert (p.logN, p.L, p.K, p.dnum, p.q0_bits, p.p_bits) == (
+        spec["logN"], spec["L"], spec["K"], spec["dnum"], spec["q0_bits"], spec["p_bits"])
+    assert p.scale == spec["delta"]
+    primes, roots, scales = ffi.ppst_params_derive(p)
+    P = ref.Params.preset(name)
+    assert primes == P.q
+    assert roots == P.psi
+    assert scales == P.scale           # bit-equal FP64 chains
+
+
+def test_sampler_tables_match_oracle():
+    lib_thr = ffi.ppst_dg_thresholds()
+    orc_thr = np.zeros(19, dtype=np.uint64)
+    ref.lib().orc_dg_table(ref._p(orc_thr))
+    assert np.array_equal(lib_thr, orc_thr)
+    for seed, purpose, limb in [(0, 1, 0), (7, (4 << 40) | (5 << 8) | 2, 13), (2 ** 63 + 5, 3, 31)]:
+        key = ffi.ppst_stream_key(seed, purpose, limb)
+        assert ref.lib().orc_splitmix64_next(key) == ref.lib().orc_stream_word(seed, purpose, limb, 0)
+
+
+@pytest.mark.parametrize("name,n", [("c1", 2048), ("c1", 1000), ("t2", 1500), ("c2", 32768)])
+def test_encoder_matches_oracle(name, n):
+    p = ffi.ppst_params_preset(name)
+    P = ref.Params.preset(name)
+    O = ref.Oracle(P)
+    x, y = synth.binary_cost_pair(3, n)
+    for vals in (y, synth.uniform_column(4, n, -1, 1)):
+        for level in (P.L, 0):
+            a = ffi.ppst_encode_coeffs(p, vals, level)
+            b = O.encode_coeffs(vals, P.scale[level])
+            assert np.array_equal(a, b), int(np.sum(a != b))

@@ -1,0 +1,207 @@
+"""GPU parity: every RNS-CKKS primitive of the library, called through the
+C-ABI, equals the oracle bit for bit from the same seeds (MI355X only)."""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(__file__))
+from gpu_common import Pair  # noqa: E402
+
+from oracle import ref  # noqa: E402
+from paper_2508_12093_amd import ffi, synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module", params=["c1", "t1"])
+def pair(request):
+    _torch()
+    print("\n[parity] preset", request.param, flush=True)
+    return Pair(request.param)
+
+
+# ------------------------------------------------------------------ NTT
+@pytest.mark.parametrize("name", ["c1", "t1", "c2"])
+def test_raw_ntt_matches_oracle(name):
+    torch = _torch()
+    print("\n[ntt] preset", name, flush=True)
+    ctx = ffi.ppst_context_create(name)
+    P = ref.Params.preset(name)
+    O = ref.Oracle(P)
+    info = ctx.info
+    rng = np.random.default_rng(1)
+    first = 0 if name != "c2" else 20          # c2: a prime window that spans q_20..p_2
+    nl = min(info.nprimes - first, 9)
+    a = np.stack([rng.integers(0, P.q[first + i], P.N, dtype=np.uint64) for i in range(nl)])
+    t = torch.from_numpy(a.view(np.int64).copy()).cuda()
+    torch.cuda.synchronize()
+    ffi.ppst_ntt_forward(ctx, t.data_ptr(), nl, first)
+    ffi.ppst_sync(ctx)
+    got = t.cpu().numpy().view(np.uint64)
+    want = O.ntt(a, list(range(first, first + nl)))
+    assert np.array_equal(got, want)
+    ffi.ppst_ntt_inverse(ctx, t.data_ptr(), nl, first)
+    ffi.ppst_sync(ctx)
+    assert np.array_equal(t.cpu().numpy().view(np.uint64), a)
+
+
+# ------------------------------------------------------------ keys / enc
+def test_keys_bit_exact(pair):
+    p = pair
+    assert np.array_equal(ffi.ppst_sk_export(p.ctx, p.sk), p.osk.s_ntt)
+    assert np.array_equal(ffi.ppst_pk_export(p.ctx, p.pk), p.opk)
+    assert np.array_equal(ffi.ppst_evk_export(p.ctx, p.evk, 0), p.orlk)
+    g = ref.galois_element(3, p.P.N)
+    assert np.array_equal(ffi.ppst_evk_export(p.ctx, p.evk, g), p.ogk[g])
+    assert np.array_equal(ffi.ppst_context_dg_table(p.ctx), ffi.ppst_dg_thresholds())
+
+
+def test_encrypt_decrypt(pair):
+    p = pair
+    m = synth.uniform_column(5, p.P.slots, -1, 1)
+    ct, oct_ = p.encrypt(m, 21)
+    p.same(ct, oct_)
+    for level in (0, 1):
+        c2, o2 = p.encrypt(m, 22, level)
+        p.same(c2, o2)
+    std = p.P.N * 3.2 * math.sqrt(2 / 3) / p.P.scale[p.P.L]
+    assert np.max(np.abs(p.decrypt(ct) - m)) < 8 * std
+    pt = ffi.ppst_encode(p.ctx, m, p.P.L)
+    cs = ffi.ppst_encrypt_sk(p.ctx, p.sk, pt, 23)
+    p.same(cs, p.O.encrypt_sk(p.O.encode(m), p.osk, 23))
+    # library decryption equals the oracle's c0 + c1 s
+    dec = ffi.ppst_plaintext_export(p.ctx, ffi.ppst_decrypt(p.ctx, p.sk, ct), p.P.L)
+    assert np.array_equal(dec, p.O.decrypt_ntt(oct_, p.osk))
+
+
+# --------------------------------------------------------------- ops
+def test_linear_ops(pair):
+    p = pair
+    a = synth.uniform_column(6, p.P.slots, -1, 1)
+    b = synth.uniform_column(7, p.P.slots, -1, 1)
+    ca, oa = p.encrypt(a, 31)
+    cb, ob = p.encrypt(b, 32)
+    p.same(ffi.ppst_add(p.ctx, ca, cb), p.O.add(oa, ob))
+    p.same(ffi.ppst_sub(p.ctx, ca, cb), p.O.sub(oa, ob))
+    p.same(ffi.ppst_add_const(p.ctx, ca, -0.3125), p.O.add_const(oa, -0.3125))
+    p.same(ffi.ppst_mul_int(p.ctx, ca, -3), p.O.mul_int(oa, -3))
+    p.same(ffi.ppst_mul_const(p.ctx, ca, 0.7071), p.O.mul_const(oa, 0.7071))
+    p.same(ffi.ppst_rescale(p.ctx, ca), p.O.rescale(oa))
+    for lvl in range(p.P.L):
+        p.same(ffi.ppst_level_align(p.ctx, ca, lvl), p.O.level_align(oa, lvl))
+    pt = ffi.ppst_encode(p.ctx, b, p.P.L)
+    p.same(ffi.ppst_mul_plain(p.ctx, ca, pt), p.O.mul_plain(oa, p.O.encode(b, p.P.L)))
+
+
+def test_mul_relin_rescale(pair):
+    p = pair
+    a = synth.uniform_column(8, p.P.slots, -1, 1)
+    b = synth.uniform_column(9, p.P.slots, -1, 1)
+    ca, oa = p.encrypt(a, 41)
+    cb, ob = p.encrypt(b, 42)
+    d = ffi.ppst_tensor(p.ctx, ca, cb)
+    od = p.O.tensor(oa, ob)
+    assert np.array_equal(ffi.ppst_ct_export(p.ctx, d), od)
+    r = ffi.ppst_relin(p.ctx, p.evk, d)
+    p.same(r, p.O.relin(od, p.P.L, p.orlk, oa.scale * ob.scale))
+    m = ffi.ppst_mul(p.ctx, p.evk, ca, cb)
+    om = p.O.mul(oa, ob, p.orlk)
+    p.same(m, om)
+    # every level down to 1
+    cur, ocur = m, om
+    while cur.level >= 1:
+        cur = ffi.ppst_mul(p.ctx, p.evk, cur, cur)
+        ocur = p.O.mul(ocur, ocur, p.orlk)
+        p.same(cur, ocur)
+    assert np.max(np.abs(p.decrypt(m) - a * b)) < 1e-3
+
+
+def test_rotations(pair):
+    p = pair
+    m = synth.uniform_column(10, p.P.slots, 0, 1)
+    ct, oct_ = p.encrypt(m, 51)
+    for r in p.steps:
+        p.same(ffi.ppst_rotate(p.ctx, p.evk, ct, r), p.O.rotate(oct_, r, p.ogk))
+    low, olow = ffi.ppst_level_align(p.ctx, ct, 1), p.O.level_align(oct_, 1)
+    p.same(ffi.ppst_rotate(p.ctx, p.evk, low, 3), p.O.rotate(olow, 3, p.ogk))
+    hs = ffi.ppst_rotate_hoisted(p.ctx, p.evk, ct, p.steps)
+    ohs = p.O.rotate_hoisted(oct_, p.steps, p.ogk)
+    for h, oh in zip(hs, ohs):
+        p.same(h, oh)
+    assert np.max(np.abs(p.decrypt(hs[1]) - np.roll(m, -3))) < 1e-3
+
+
+def test_rotsum(pair):
+    p = pair
+    p.add_rotsum_keys()
+    m = synth.uniform_column(11, p.P.slots, 0, 1) / p.P.slots
+    ct, oct_ = p.encrypt(m, 61)
+    s = ffi.ppst_rotsum(p.ctx, p.evk, ct)
+    p.same(s, p.O.rotsum(oct_, p.ogk))
+    assert abs(p.decrypt(s)[0] - m.sum()) < 1e-3
+
+
+def test_mul_batch_equals_single(pair):
+    p = pair
+    cts = [p.encrypt(synth.uniform_column(70 + i, p.P.slots, -1, 1), 70 + i)[0] for i in range(5)]
+    a, b = cts, cts[1:] + cts[:1]
+    outs = ffi.ppst_mul_batch(p.ctx, p.evk, a, b)
+    for x, y, o in zip(a, b, outs):
+        single = ffi.ppst_mul(p.ctx, p.evk, x, y)
+        assert np.array_equal(ffi.ppst_ct_export(p.ctx, o), ffi.ppst_ct_export(p.ctx, single))
+
+
+def test_error_statuses(pair):
+    p = pair
+    m = synth.uniform_column(12, 16, 0, 1)
+    ct, _ = p.encrypt(m, 81)
+    low = ffi.ppst_level_align(p.ctx, ct, 0)
+    with pytest.raises(ffi.PpstError) as e:
+        ffi.ppst_add(p.ctx, ct, low)
+    assert e.value.name == "ESCALE"
+    with pytest.raises(ffi.PpstError) as e:
+        ffi.ppst_mul(p.ctx, p.evk, low, low)
+    assert e.value.name == "ELEVEL"
+    with pytest.raises(ffi.PpstError) as e:
+        ffi.ppst_rotate(p.ctx, p.evk, ct, 7)
+    assert e.value.name == "ENOKEY"
+    with pytest.raises(ffi.PpstError) as e:
+        ffi.ppst_level_align(p.ctx, low, 1)
+    assert e.value.name == "ELEVEL"
+    with pytest.raises(ffi.PpstError) as e:
+        ffi.ppst_encode(p.ctx, np.zeros(p.P.slots + 1), p.P.L)
+    assert e.value.name == "EINVAL"
+
+
+# ---------------------------------------------------- full-size spot checks
+@pytest.fixture(scope="module")
+def c2pair():
+    _torch()
+    print("\n[parity] preset c2 (N=2^16, L=24)", flush=True)
+    return Pair("c2", steps=(1,))
+
+
+def test_c2_hmult_and_rotation_bit_exact(c2pair):
+    """N = 2^16, level 24 (the configuration the benchmark times): one
+    HMult+relin+rescale and one rotation against the oracle, all residues."""
+    p = c2pair
+    x, y = synth.binary_cost_pair(0)
+    cx, ox = p.encrypt(x, 91)
+    cy, oy = p.encrypt(y / 100.0, 92)
+    p.same(cx, ox)
+    m = ffi.ppst_mul(p.ctx, p.evk, cx, cy)
+    p.same(m, p.O.mul(ox, oy, p.orlk))
+    r = ffi.ppst_rotate(p.ctx, p.evk, cy, 1)
+    p.same(r, p.O.rotate(oy, 1, p.ogk))
+    assert np.max(np.abs(p.decrypt(m) - x * y / 100.0)) < 1e-4
+    assert np.max(np.abs(p.decrypt(r) - np.roll(y / 100.0, -1))) < 1e-4
