@@ -1,0 +1,251 @@
+#!/usr/bin/env python3
+"""Benchmark of the encrypted-statistics hot path on one MI355X.
+
+Headline metric: HMult+relin (+ rescale) per second at N = 2^16, level 24
+(the paper's N, Delta and modulus budget; 24 levels of 40-bit primes, 7
+special primes, dnum = 3).  One timed step is one batch of 64 independent
+ciphertext products (slot values ~ U[-1, 1)) through the per-ciphertext path;
+inputs are resident in HBM before the timed region.
+
+Reported beside it on the same JSON line: rotations/s at level 24, the
+batched and hoisted forms, p50/p99 latency of an encrypted Pearson
+correlation on two 32768-row columns (binary x, lognormal y, corr ~ 0.79) with
+its relative error, the roofline of the dominant kernel (forward NTT, timed
+with HIP events on the library's stream), and the CPU reference timed on the
+host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--pearson-runs", type=int, default=30)
+    ap.add_argument("--cpu-sample", type=int, default=12, help="oracle HMults timed on the host")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quick", action="store_true", help="short run for profiling")
+    return ap.parse_args()
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only (this build has no multi-GPU path); "
+              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2508_12093_amd import ffi, synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.quick:
+        args.steps, args.warmup, args.pearson_runs = min(args.steps, 3), 1, 3
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    sptr = ctypes.c_void_p(stream.cuda_stream)
+    ctx = ffi.ppst_context_create("c2", stream=sptr)
+    info = ctx.info
+    L, N = info.L, info.N
+    log("context N=%d L=%d K=%d dnum=%d" % (N, L, info.K, info.dnum))
+    log("NTT plan:", ffi.ppst_ntt_plan(ctx))
+
+    sk, pk = ffi.ppst_keygen(ctx, 1001)
+    evk = ffi.ppst_evk_create(ctx)
+    ffi.ppst_evk_add_relin(ctx, sk, 1002, evk)
+    ffi.ppst_evk_add_rotsum(ctx, sk, 1003, evk)
+    hoist_steps = list(range(1, 17))
+    ffi.ppst_evk_add_galois(ctx, sk, hoist_steps, 1003, evk)
+    log("keys ready")
+
+    B = args.batch
+    vals = synth.slot_batch(7, B, info.slots)
+    cts = [ffi.ppst_encrypt(ctx, pk, ffi.ppst_encode(ctx, vals[i], L), 2000 + i) for i in range(B)]
+    ffi.ppst_sync(ctx)
+    log("%d ciphertexts resident at level %d" % (B, L))
+
+    def sync():
+        ffi.ppst_sync(ctx)
+        torch.cuda.synchronize()
+
+    # ------------------------------------------------ headline: HMult+relin
+    def step_mul():
+        outs = [ffi.ppst_mul(ctx, evk, cts[i], cts[(i + 1) % B]) for i in range(B)]
+        return outs
+
+    for _ in range(args.warmup):
+        step_mul()
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        keep = step_mul()
+    sync()
+    t1 = time.perf_counter()
+    del keep
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    hmult_s = B * args.steps / (t1 - t0)
+    log("HMult+relin+rescale: %.3f ms / step of %d -> %.0f /s" % (ms_step, B, hmult_s))
+
+    # check one product against the plaintext
+    got = ffi.ppst_decode(ctx, ffi.ppst_decrypt(ctx, sk, ffi.ppst_mul(ctx, evk, cts[0], cts[1])))
+    hmult_err = float(np.max(np.abs(got - vals[0] * vals[1])))
+
+    def timed(fn, reps):
+        fn()
+        sync()
+        t = time.perf_counter()
+        for _ in range(reps):
+            keep = fn()
+        sync()
+        return (time.perf_counter() - t) / reps
+
+    # ------------------------------------------------------ rotations
+    rot_t = timed(lambda: [ffi.ppst_rotate(ctx, evk, cts[i], 1 + (i % 15)) for i in range(B)],
+                  max(1, args.steps // 2))
+    rot_s = B / rot_t
+    log("rotation: %.0f /s" % rot_s)
+
+    # ----------------------------------------------- batched / hoisted forms
+    bm_t = timed(lambda: ffi.ppst_mul_batch(ctx, evk, cts, cts[1:] + cts[:1]), max(1, args.steps // 2))
+    bm_s = B / bm_t
+    log("batched HMult: %.0f /s" % bm_s)
+    nh = min(B, 8)
+    ho_t = timed(lambda: [ffi.ppst_rotate_hoisted(ctx, evk, cts[i], hoist_steps) for i in range(nh)], 1)
+    ho_s = nh * len(hoist_steps) / ho_t
+    log("hoisted rotations: %.0f /s" % ho_s)
+
+    # --------------------------------------------- Pearson latency (config 2)
+    x, y = synth.binary_cost_pair(0)
+    n = len(x)
+    cx = ffi.ppst_encrypt(ctx, pk, ffi.ppst_encode(ctx, x, L), 3001)
+    cy = ffi.ppst_encrypt(ctx, pk, ffi.ppst_encode(ctx, y, L), 3002)
+    cfg = ffi.ppst_invsqrt_cfg_default()
+    lat = []
+    res = None
+    for r in range(args.pearson_runs + 1):
+        sync()
+        t = time.perf_counter()
+        res = ffi.ppst_stat_pearson(ctx, evk, [cx], [cy], n, 1.0, 20.0, cfg)
+        sync()
+        if r > 0:
+            lat.append((time.perf_counter() - t) * 1e3)
+    pcc = float(ffi.ppst_decode(ctx, ffi.ppst_decrypt(ctx, sk, res))[0])
+    ref_pcc = float(np.corrcoef(x, y)[0, 1])
+    lat = np.array(lat)
+    log("Pearson p50 %.2f ms p99 %.2f ms, value %.6f (fp64 %.6f)" % (
+        np.percentile(lat, 50), np.percentile(lat, 99), pcc, ref_pcc))
+
+    # ----------------------------------------- roofline: forward NTT kernel
+    nl = 2 * (L + 1)             # one ciphertext: 50 limbs of 512 KiB
+    rng = np.random.default_rng(5)
+    primes = ctx.primes
+    host = np.stack([rng.integers(0, primes[i % (L + 1)], N, dtype=np.uint64) for i in range(nl)])
+    # two polynomials over q_0..q_24: transform each 25-limb half
+    dev = torch.from_numpy(host.view(np.int64).copy()).cuda()
+    sync()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 50 if not args.quick else 10
+    half = (L + 1) * N * 8
+    for _ in range(3):
+        ffi.ppst_ntt_forward(ctx, dev.data_ptr(), L + 1, 0)
+    e0.record(stream)
+    for _ in range(reps):
+        ffi.ppst_ntt_forward(ctx, dev.data_ptr(), L + 1, 0)
+        ffi.ppst_ntt_forward(ctx, dev.data_ptr() + half, L + 1, 0)
+    e1.record(stream)
+    sync()
+    ntt_ms = e0.elapsed_time(e1) / (2 * reps)            # per 25-limb forward NTT (2 passes)
+    limbs = L + 1
+    alg_bytes = 2 * 2 * limbs * N * 8                    # each pass reads and writes every limb
+    ntt_gbs = alg_bytes / (ntt_ms * 1e-3) / 1e9
+    butterflies = limbs * (N // 2) * 16
+    log("forward NTT (25 limbs, 2 passes): %.1f us, %.0f GB/s algorithmic, %.1f G butterflies/s" % (
+        ntt_ms * 1e3, ntt_gbs, butterflies / (ntt_ms * 1e-3) / 1e9))
+
+    out = {
+        "metric": "HMult+relin/sec and rotations/sec at N=2^16; p50/p99 encrypted-Pearson latency",
+        "value": round(hmult_s, 2),
+        "unit": "HMult+relin/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {
+            "workload": "RNS-CKKS N=2^16, L=24 (q0 60-bit, 24x~40-bit, 7x60-bit special primes, "
+                        "dnum=3, Delta=2^40): %d independent HMult+relin+rescale at level 24 per "
+                        "step, slots ~U[-1,1); Pearson on two 32768-row columns" % B,
+            "ring_degree": N, "levels": L, "batch": B,
+        },
+        "rotations_per_s": round(rot_s, 2),
+        "hmult_batched_per_s": round(bm_s, 2),
+        "rotations_hoisted_per_s": round(ho_s, 2),
+        "pearson_p50_ms": round(float(np.percentile(lat, 50)), 3),
+        "pearson_p99_ms": round(float(np.percentile(lat, 99)), 3),
+        "pearson_runs": len(lat),
+        "pearson_value": pcc,
+        "pearson_rel_err": abs(pcc - ref_pcc) / abs(ref_pcc),
+        "hmult_max_slot_err": hmult_err,
+        "roofline": {
+            "kernel": "forward NTT, column pass + row pass, 25 limbs",
+            "bound": "hbm",
+            "achieved": round(ntt_gbs, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(ntt_gbs / HBM_PEAK_GBS, 4),
+            "traffic": None,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(count: int):
+    """The CPU reference (plain C oracle) timed on the host: `count` HMults at
+    N = 2^16, level 24."""
+    import numpy as np
+
+    from oracle import ref
+    from paper_2508_12093_amd import synth
+
+    P = ref.Params.preset("c2")
+    O = ref.Oracle(P)
+    sk, pk = O.keygen(1)
+    rlk = O.relin_key(sk, 2)
+    a = O.encrypt(O.encode(synth.uniform_column(1, P.slots, -1, 1)), pk, 3)
+    b = O.encrypt(O.encode(synth.uniform_column(2, P.slots, -1, 1)), pk, 4)
+    t = time.perf_counter()
+    for _ in range(count):
+        O.mul(a, b, rlk)
+    dt = time.perf_counter() - t
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(count / dt, 4), "unit": "HMult+relin/s", "cores": cores, "kind": "oracle",
+            "sample": "%d HMult+relin+rescale at N=2^16, level 24 (%.1f s)" % (count, dt)}
+
+
+if __name__ == "__main__":
+    main()

@@ -272,6 +272,16 @@ int ppst_stat_pearson(ppst_context* ctx, const ppst_eval_keys* evk,
  * q_i, L+1.. the special primes).  Enqueued on the context stream. */
 int ppst_ntt_forward(ppst_context* ctx, uint64_t* dev, int32_t nlimbs, int32_t first_prime);
 int ppst_ntt_inverse(ppst_context* ctx, uint64_t* dev, int32_t nlimbs, int32_t first_prime);
+/* Re-run the NTT autotuner (it also runs at context creation unless the
+ * environment sets PPST_NTT_AUTOTUNE=0 or forces PPST_NTT_PLAN="col,row"):
+ * every register-radix / workgroup-shape variant of the column and row passes
+ * is timed per limb-count bucket and the fastest is kept for this parameter
+ * set.  ppst_ntt_plan writes the choice as text. */
+int ppst_ntt_autotune(ppst_context* ctx);
+int ppst_ntt_plan(const ppst_context* ctx, char* buf, size_t cap);
+/* force one variant for every bucket and direction (col ignored at N = 2^12);
+ * returns PPST_EINVAL for an index outside the variant tables */
+int ppst_ntt_set_plan(ppst_context* ctx, int32_t col, int32_t row);
 /* hipStream_t of the context */
 int ppst_context_stream(const ppst_context* ctx, void** stream);
 

@@ -706,6 +706,30 @@ int ppst_ntt_inverse(ppst_context* ctx, uint64_t* dev, int32_t nlimbs, int32_t f
   });
 }
 
+int ppst_ntt_autotune(ppst_context* ctx) {
+  return guard([&] {
+    NEED(ctx);
+    HIP_CHECK(hipStreamSynchronize(ctx->cx->stream));
+    autotune_ntt(*ctx->cx->sh);
+  });
+}
+int ppst_ntt_set_plan(ppst_context* ctx, int32_t col, int32_t row) {
+  return guard([&] {
+    NEED(ctx);
+    HIP_CHECK(hipStreamSynchronize(ctx->cx->stream));
+    ntt_set_plan(*ctx->cx->sh, ctx->cx->P().logN == 16 ? col : 0, row);
+  });
+}
+int ppst_ntt_plan(const ppst_context* ctx, char* buf, size_t cap) {
+  return guard([&] {
+    NEED(ctx);
+    NEED(buf);
+    std::string s = ntt_plan_string(*ctx->cx->sh);
+    if (cap < s.size() + 1) PPST_THROW(ST_EINVAL, "buffer too small");
+    std::memcpy(buf, s.c_str(), s.size() + 1);
+  });
+}
+
 // -------------------------------------------------------------- serving
 int ppst_server_create(ppst_context* ctx, const ppst_eval_keys* evk, size_t hbm_budget,
                        int32_t slots, ppst_server** out) {

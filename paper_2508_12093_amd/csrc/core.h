@@ -187,8 +187,15 @@ struct Tables {
   std::mutex mu;
 };
 
+// NTT variant choice per [inverse][pass: 0 column, 1 row][limb-count bucket]
+struct NttPlan {
+  int v[2][2][5] = {};
+  bool tuned = false;
+};
+
 struct Shared {
   Params P;
+  NttPlan ntt_plan;
   int device = 0;
   Hooks hooks;
   std::shared_ptr<Pool> const_pool;  // long-lived tables and keys
@@ -237,19 +244,10 @@ struct Context {
 // -------------------------------------------------------------------------
 // kernel launchers (kernels.hip)
 // -------------------------------------------------------------------------
-// One NTT "task" is one limb: source/destination limb offsets (in units of N
-// words) relative to the base pointers of the launch, and its prime index.
-struct LimbTask {
-  uint32_t src, dst, prime;
-};
-
-void launch_ntt(const Shared& sh, const u64* src, u64* dst, const LimbTask* tasks_dev, int ntasks,
-                int nbatch, size_t batch_stride, bool inverse, hipStream_t st);
-// convenience: contiguous limbs with primes first_prime.. (or a map)
-void ntt_contig(Context& cx, u64* data, int nlimbs, const int* primes, bool inverse,
-                int nbatch = 1, size_t batch_stride = 0);
-
-std::string ntt_config_string(const Shared& sh);
-void ntt_select(Shared& sh, int variant);  // autotuner hook
+// NTT autotuner (ntt.hip): times the kernel variants on `scratch` (at least
+// max_limbs * N words) and records the fastest per limb-count bucket
+void ntt_autotune(Shared& sh, hipStream_t st, u64* scratch, int max_limbs);
+std::string ntt_plan_string(const Shared& sh);
+void ntt_set_plan(Shared& sh, int col, int row);
 
 }  // namespace ppst

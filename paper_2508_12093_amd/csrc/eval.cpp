@@ -2,6 +2,8 @@
 #include "eval.h"
 
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 
 #include "kern.h"
 #include "tables.h"
@@ -208,6 +210,19 @@ const u64* rescale_table(const Shared& sh, int level) {
 }
 
 // ============================================================ contexts
+void autotune_ntt(Shared& sh) {
+  const int max_limbs = 200;
+  hipStream_t st;
+  HIP_CHECK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  {
+    Buf scratch = dev_buf(sh.const_pool, (size_t)max_limbs * sh.P.N);
+    HIP_CHECK(hipMemsetAsync(scratch.p, 0, (size_t)max_limbs * sh.P.N * 8, st));
+    ntt_autotune(sh, st, scratch.p, max_limbs);
+    HIP_CHECK(hipStreamSynchronize(st));
+  }
+  HIP_CHECK(hipStreamDestroy(st));
+}
+
 std::shared_ptr<Shared> make_shared_state(const ParamSpec& spec, const Hooks* hooks) {
   auto sh = std::make_shared<Shared>();
   sh->P = make_params(spec);
@@ -217,6 +232,15 @@ std::shared_ptr<Shared> make_shared_state(const ParamSpec& spec, const Hooks* ho
   dg_thresholds(sh->dg_thr);
   build_tables(*sh);
   HIP_CHECK(hipDeviceSynchronize());
+  const char* force = std::getenv("PPST_NTT_PLAN");       // "col,row" variant indices
+  const char* tune = std::getenv("PPST_NTT_AUTOTUNE");
+  if (force) {
+    int c = 0, r = 0;
+    if (std::sscanf(force, "%d,%d", &c, &r) != 2) PPST_THROW(ST_EINVAL, "PPST_NTT_PLAN is col,row");
+    ntt_set_plan(*sh, c, r);
+  } else if (!(tune && tune[0] == '0')) {
+    autotune_ntt(*sh);
+  }
   return sh;
 }
 
@@ -308,9 +332,9 @@ void keyswitch(Context& cx, const KsKey& key, const u64* d, size_t sd, int level
     ntt(sh, L, true, cx.stream);
   }
   // 2. ModUp of every digit, back to NTT form on the new limbs
+  k_modup(sh, x.p, ext.p, level, nbatch, sx, sext, cx.stream);
   for (int j = 0; j < beta; ++j) {
     u64* ej = ext.p + (size_t)j * ne * N;
-    k_modup(sh, x.p, ej, level, j, nbatch, sx, sext, cx.stream);
     NttLaunch L{};
     L.src = ej;
     L.dst = ej;
@@ -743,9 +767,9 @@ std::vector<CtPtr> rotate_hoisted(Context& cx, const EvalKeys& evk, const Cipher
     L.pofs = P.L + 1;
     ntt(sh, L, true, cx.stream);
   }
+  k_modup(sh, x.p, ext.p, level, 1, per, sext, cx.stream);
   for (int j = 0; j < beta; ++j) {
     u64* ej = ext.p + (size_t)j * ne * N;
-    k_modup(sh, x.p, ej, level, j, 1, per, sext, cx.stream);
     NttLaunch L{};
     L.src = ej;
     L.dst = ej;

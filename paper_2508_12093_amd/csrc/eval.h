@@ -13,6 +13,8 @@ typedef std::shared_ptr<Plaintext> PtPtr;
 std::shared_ptr<Shared> make_shared_state(const ParamSpec& spec, const Hooks* hooks);
 std::unique_ptr<Context> make_context(std::shared_ptr<Shared> sh, hipStream_t stream);
 void destroy_context(Context* cx);
+// time the NTT kernel variants and keep the fastest per limb-count bucket
+void autotune_ntt(Shared& sh);
 
 // galois element of a rotation by r slots: 5^(r mod N/2) mod 2N
 u64 galois_elt(const Params& P, long r);

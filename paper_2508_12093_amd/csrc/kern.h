@@ -45,11 +45,11 @@ void k_automorph(const Shared& sh, const u64* in, u64* out, int nrows, size_t ro
                  size_t row_stride_out, u64 g, hipStream_t st);
 
 // ------------------------------------------------------ key switching
-// ModUp of digit j at level l: x = coefficient-form limbs of the input (the
-// digit's limbs lo..hi-1 at x + t*N); writes every limb t of [0, nl+K) outside
-// the digit into ext + t*N (coefficient form).
-void k_modup(const Shared& sh, const u64* x, u64* ext, int level, int digit, int nbatch,
-             size_t stride_x, size_t stride_ext, hipStream_t st);
+// ModUp of every digit j at level l: x = coefficient-form limbs of the input
+// (limb t at x + t*N); for digit j writes every limb t of [0, nl+K) outside the
+// digit into ext + (j*ne + t)*N (coefficient form).
+void k_modup(const Shared& sh, const u64* x, u64* ext, int level, int nbatch, size_t stride_x,
+             size_t stride_ext, hipStream_t st);
 // Inner product with the key: for t in [0, ne) (ne = nl + K),
 //   u0_t = sum_j e_{j,t} b_{j,p(t)},  u1_t = sum_j e_{j,t} a_{j,p(t)},
 // e_{j,t} = d_t for t in digit j (NTT form input), ext[j][t] otherwise.

@@ -102,35 +102,50 @@ __global__ void k_automorph_kernel(const u64* __restrict__ in, u64* out, int log
 // ----------------------------------------------------------- key switching
 struct ModUpArgs {
   const u64* x;       // coefficient-form input limbs (limb t at x + t N)
-  u64* ext;           // output limbs (limb t at ext + t N)
+  u64* ext;           // [beta][ne][N] output limbs per batch item
   const Mod* mods;
-  const u64* cst;     // [alpha][2] (Qhat_i^-1 mod q_i, Shoup), then [alpha][ne] Qhat_i mod p(t)
+  const u64* cst[8];  // per digit: [alpha][2] (Qhat_i^-1 mod q_i, Shoup), then [alpha][ne] Qhat_i mod p(t)
   size_t sx, sext;
-  int logN, lo, hi, nl, ne, pofs, alpha;
+  int logN, nl, ne, pofs, alpha, beta, nchunk, batch;
 };
 
-// one thread per coefficient: z_i = x_i Qhat_i^-1 mod q_i, then for every
-// target limb t outside the digit, y_t = sum_i z_i (Qhat_i mod t) mod t
+constexpr int kModUpChunk = 4;   // target limbs per thread
+
+// Thread (k, chunk, digit j): z_i = x_i Qhat_i^-1 mod q_i for the digit's limbs,
+// then y_t = sum_i z_i (Qhat_i mod t) mod t for the chunk's target limbs t
+// outside the digit (fast base conversion without correction).
 template <int MAXA>
 __global__ void __launch_bounds__(kBlock) k_modup_kernel(ModUpArgs a) {
   const int N = 1 << a.logN;
-  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= N) return;
-  const u64* x = a.x + blockIdx.y * a.sx;
-  u64* ext = a.ext + blockIdx.y * a.sext;
-  const int da = a.hi - a.lo;
+  const int chunk = blockIdx.y % a.nchunk;
+  const int j = blockIdx.y / a.nchunk;
+  const int lo = j * a.alpha;
+  const int hi = min(lo + a.alpha, a.nl);
+  const int da = hi - lo;
+  // the chunk's targets: the ne - da limbs outside [lo, hi), in order
+  const int tfirst = chunk * kModUpChunk;
+  const int ntarget = a.ne - da;
+  if (tfirst >= ntarget) return;
+  const u64* x = a.x + blockIdx.z * a.sx;
+  u64* ext = a.ext + blockIdx.z * a.sext + (size_t)j * a.ne * N;
+  const u64* cst = a.cst[j];
   u64 z[MAXA];
 #pragma unroll
   for (int i = 0; i < MAXA; ++i) {
     if (i < da) {
-      u64 q = a.mods[a.lo + i].q;
-      z[i] = mul_shoup(x[(size_t)(a.lo + i) * N + k], a.cst[2 * i], a.cst[2 * i + 1], q);
+      u64 q = a.mods[lo + i].q;
+      z[i] = mul_shoup(x[(size_t)(lo + i) * N + k], cst[2 * i], cst[2 * i + 1], q);
     }
   }
-  const u64* qhat = a.cst + 2 * a.alpha;
-  for (int t = 0; t < a.ne; ++t) {
-    if (t >= a.lo && t < a.hi) continue;
-    int p = t < a.nl ? t : a.pofs + (t - a.nl);
+  const u64* qhat = cst + 2 * a.alpha;
+#pragma unroll
+  for (int c = 0; c < kModUpChunk; ++c) {
+    const int u = tfirst + c;
+    if (u >= ntarget) break;
+    const int t = u < lo ? u : u + da;
+    const int p = t < a.nl ? t : a.pofs + (t - a.nl);
     const Mod m = a.mods[p];
     Acc acc;
 #pragma unroll
@@ -180,17 +195,24 @@ struct ModDownArgs {
   const Mod* mods;
   const u64* md;      // moddown table (see tables.h)
   size_t su, sconv;
-  int logN, nl, ne, K, L;
+  int logN, nl, ne, K, L, nchunk;
 };
 
+constexpr int kModDownChunk = 5;   // output limbs per thread
+
+// Thread (k, chunk, poly): w_k = (z_k + h) Phat_k^-1 mod p_k, then for the
+// chunk's limbs i: conv_i = sum_k w_k (Phat_k mod q_i) - h mod q_i.
 template <int MAXK>
 __global__ void __launch_bounds__(kBlock) k_moddown_conv_kernel(ModDownArgs a) {
   const int N = 1 << a.logN;
-  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= N) return;
-  const int c = blockIdx.z;
-  const u64* u = a.u + blockIdx.y * a.su + (size_t)c * a.ne * N;
-  u64* conv = a.conv + blockIdx.y * a.sconv + (size_t)c * a.nl * N;
+  const int chunk = blockIdx.y % a.nchunk;
+  const int c = blockIdx.y / a.nchunk;
+  const int ifirst = chunk * kModDownChunk;
+  if (ifirst >= a.nl) return;
+  const u64* u = a.u + blockIdx.z * a.su + (size_t)c * a.ne * N;
+  u64* conv = a.conv + blockIdx.z * a.sconv + (size_t)c * a.nl * N;
   const MdLayout lay(a.K, a.L);
   u64 w[MAXK];
 #pragma unroll
@@ -202,7 +224,10 @@ __global__ void __launch_bounds__(kBlock) k_moddown_conv_kernel(ModDownArgs a) {
       w[i] = mul_shoup(z, a.md[lay.phinv(i)], a.md[lay.phinv(i) + 1], q);
     }
   }
-  for (int i = 0; i < a.nl; ++i) {
+#pragma unroll
+  for (int cc = 0; cc < kModDownChunk; ++cc) {
+    const int i = ifirst + cc;
+    if (i >= a.nl) break;
     const Mod m = a.mods[i];
     Acc acc;
 #pragma unroll
@@ -435,25 +460,30 @@ void k_automorph(const Shared& sh, const u64* in, u64* out, int nrows, size_t si
   LAUNCH_CHECK();
 }
 
-void k_modup(const Shared& sh, const u64* x, u64* ext, int level, int digit, int nbatch,
-             size_t sx, size_t sext, hipStream_t st) {
+void k_modup(const Shared& sh, const u64* x, u64* ext, int level, int nbatch, size_t sx,
+             size_t sext, hipStream_t st) {
   const Params& P = sh.P;
   ModUpArgs a;
   a.x = x;
   a.ext = ext;
   a.mods = M(sh);
-  a.cst = modup_table(sh, level, digit);
   a.sx = sx;
   a.sext = sext;
   a.logN = P.logN;
-  a.lo = P.digit_lo(digit);
-  a.hi = P.digit_hi(digit, level);
   a.nl = level + 1;
   a.ne = level + 1 + P.K;
   a.pofs = P.L + 1;
   a.alpha = P.alpha;
+  a.beta = P.beta(level);
+  if (a.beta > 8) PPST_THROW(ST_EINVAL, "more than 8 digits");
+  for (int j = 0; j < a.beta; ++j) a.cst[j] = modup_table(sh, level, j);
+  // the first digit has the most targets: ne - alpha (or ne - nl when it is the only one)
+  int most = a.ne - std::min(a.alpha, a.nl);
+  for (int j = 0; j < a.beta; ++j) most = std::max(most, a.ne - (P.digit_hi(j, level) - P.digit_lo(j)));
+  a.nchunk = (most + kModUpChunk - 1) / kModUpChunk;
   dim3 g = grid_for(P.N);
-  g.y = nbatch;
+  g.y = a.nchunk * a.beta;
+  g.z = nbatch;
   if (P.alpha <= 4) hipLaunchKernelGGL(k_modup_kernel<4>, g, dim3(kBlock), 0, st, a);
   else if (P.alpha <= 9) hipLaunchKernelGGL(k_modup_kernel<9>, g, dim3(kBlock), 0, st, a);
   else if (P.alpha <= 16) hipLaunchKernelGGL(k_modup_kernel<16>, g, dim3(kBlock), 0, st, a);
@@ -501,9 +531,10 @@ void k_moddown_conv(const Shared& sh, const u64* u, u64* conv, int level, int nb
   a.ne = level + 1 + P.K;
   a.K = P.K;
   a.L = P.L;
+  a.nchunk = (a.nl + kModDownChunk - 1) / kModDownChunk;
   dim3 g = grid_for(P.N);
-  g.y = nbatch;
-  g.z = 2;
+  g.y = 2 * a.nchunk;
+  g.z = nbatch;
   if (P.K <= 4) hipLaunchKernelGGL(k_moddown_conv_kernel<4>, g, dim3(kBlock), 0, st, a);
   else if (P.K <= 8) hipLaunchKernelGGL(k_moddown_conv_kernel<8>, g, dim3(kBlock), 0, st, a);
   else PPST_THROW(ST_EINVAL, "more than 8 special primes");

@@ -55,6 +55,11 @@ __device__ __forceinline__ void bfly_gs(u64& x, u64& y, u64 w, u64 wp, u64 q, u6
 // otherwise sub-problem c = column (stride C), twiddle base 1.  Stage s of
 // the sub-problem uses twiddle index (base << s) + (e >> (LOGM - s)) for the
 // butterfly whose lower element is e.
+//
+// The stages run in register passes of up to LOGE stages: in a pass of ls
+// stages the sub-problem splits into M / 2^ls independent groups of 2^ls
+// elements; each of the T = M / E threads owns E / 2^ls groups (E registers)
+// and exchanges them through LDS between passes.
 template <int LOGM, int LOGE, int SB, bool ROWS, bool INV>
 __global__ void __launch_bounds__(SB * (1 << (LOGM - LOGE)))
 k_ntt_pass(NttArgs a) {
@@ -62,9 +67,8 @@ k_ntt_pass(NttArgs a) {
   constexpr int E = 1 << LOGE;
   constexpr int T = M / E;           // threads per sub-problem
   constexpr int NT = SB * T;         // threads per workgroup
-  constexpr int NP = LOGM / LOGE;    // passes
+  constexpr int NP = (LOGM + LOGE - 1) / LOGE;   // register passes
   constexpr int PAD = M + 1;         // LDS row pitch (breaks bank aliasing)
-  static_assert(LOGM % LOGE == 0, "passes must tile the stages");
   __shared__ u64 lds[SB * PAD];
 
   const int N = a.N;
@@ -76,7 +80,7 @@ k_ntt_pass(NttArgs a) {
   u64* dst = a.dst + (size_t)blockIdx.y * a.dst_stride + (size_t)t * N;
   const u64 q = a.mods[prime].q;
   const u64 q2 = 2 * q;
-  const u64* tw = a.tw + (size_t)prime * N * 2;
+  const ulonglong2* tw = (const ulonglong2*)(a.tw + (size_t)prime * N * 2);
   const int R = 1 << a.logR;
   const int C = N >> a.logR;
   const int tid = threadIdx.x;
@@ -102,36 +106,48 @@ k_ntt_pass(NttArgs a) {
   const int sp = tid / T;
   const int lane = tid - sp * T;
   u64* my = lds + sp * PAD;
-  const u64 base0 = ROWS ? (u64)(R + first + sp) : 1;
+  const uint32_t base0 = ROWS ? (uint32_t)(R + first + sp) : 1u;
 
 #pragma unroll
   for (int pi = 0; pi < NP; ++pi) {
     const int p = INV ? (NP - 1 - pi) : pi;
     const int s0 = p * LOGE;
-    const int si = M >> (s0 + LOGE);
-    const int lo = lane % si;
-    const int hi = lane / si;
-    const int e0 = hi * (M >> s0) + lo;
+    const int ls = (LOGM - s0) < LOGE ? (LOGM - s0) : LOGE;   // stages in this pass
+    const int GS = 1 << ls;                                    // group size
+    const int G = E / GS;                                      // groups per thread
+    const int si = M >> (s0 + ls);                             // element stride in a group
+    int e0[E];
     u64 x[E];
 #pragma unroll
-    for (int k = 0; k < E; ++k) x[k] = my[e0 + k * si];
+    for (int g = 0; g < G; ++g) {
+      const int gi = g * T + lane;
+      const int lo = gi % si, hi = gi / si;
+      e0[g] = hi * (M >> s0) + lo;
 #pragma unroll
-    for (int uu = 0; uu < LOGE; ++uu) {
-      const int u = INV ? (LOGE - 1 - uu) : uu;
+      for (int k = 0; k < GS; ++k) x[g * GS + k] = my[e0[g] + k * si];
+    }
+#pragma unroll
+    for (int uu = 0; uu < ls; ++uu) {
+      const int u = INV ? (ls - 1 - uu) : uu;
       const int s = s0 + u;
-      const int half = E >> (u + 1);
+      const int half = GS >> (u + 1);
 #pragma unroll
-      for (int k = 0; k < E; ++k) {
-        if (k & half) continue;
-        const int e = e0 + k * si;
-        const u64 idx = (base0 << s) + (u64)(e >> (LOGM - s));
-        const u64 w = tw[2 * idx], wp = tw[2 * idx + 1];
-        if (INV) bfly_gs(x[k], x[k + half], w, wp, q, q2);
-        else bfly_ct(x[k], x[k + half], w, wp, q, q2);
+      for (int g = 0; g < G; ++g) {
+#pragma unroll
+        for (int k = 0; k < GS; ++k) {
+          if (k & half) continue;
+          const int e = e0[g] + k * si;
+          const uint32_t idx = (base0 << s) + (uint32_t)(e >> (LOGM - s));
+          const ulonglong2 w = tw[idx];
+          if (INV) bfly_gs(x[g * GS + k], x[g * GS + k + half], w.x, w.y, q, q2);
+          else bfly_ct(x[g * GS + k], x[g * GS + k + half], w.x, w.y, q, q2);
+        }
       }
     }
 #pragma unroll
-    for (int k = 0; k < E; ++k) my[e0 + k * si] = x[k];
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int k = 0; k < GS; ++k) my[e0[g] + k * si] = x[g * GS + k];
     __syncthreads();
   }
 
@@ -164,6 +180,8 @@ k_ntt_pass(NttArgs a) {
   }
 }
 
+typedef void (*PassFn)(const NttArgs&, int, int, hipStream_t);
+
 template <int LOGM, int LOGE, int SB, bool ROWS, bool INV>
 void run_pass(const NttArgs& base, int nlimbs, int nbatch, hipStream_t st) {
   NttArgs a = base;
@@ -174,11 +192,77 @@ void run_pass(const NttArgs& base, int nlimbs, int nbatch, hipStream_t st) {
   hipLaunchKernelGGL((k_ntt_pass<LOGM, LOGE, SB, ROWS, INV>), grid, block, 0, st, a);
 }
 
+// Variant tables.  N = 2^16 runs a column pass and a row pass of 2^8 points;
+// N = 2^12 a single row pass of 2^12 points.  A variant fixes the register
+// radix (E = 2^LOGE elements per thread) and the sub-problems per workgroup.
+struct Variant {
+  const char* name;
+  PassFn fwd, inv;
+};
+#define V16C(LE, SB) {"col:E" #LE ",SB" #SB, run_pass<8, LE, SB, false, false>, run_pass<8, LE, SB, false, true>}
+#define V16R(LE, SB) {"row:E" #LE ",SB" #SB, run_pass<8, LE, SB, true, false>, run_pass<8, LE, SB, true, true>}
+#define V12(LE) {"full:E" #LE, run_pass<12, LE, 1, true, false>, run_pass<12, LE, 1, true, true>}
+const Variant kCol16[] = {V16C(4, 16), V16C(3, 16), V16C(2, 16), V16C(3, 8), V16C(2, 8)};
+const Variant kRow16[] = {V16R(4, 16), V16R(4, 4), V16R(3, 8), V16R(2, 4), V16R(3, 4), V16R(2, 8)};
+const Variant kFull12[] = {V12(4), V12(3), V12(2)};
+constexpr int kNCol16 = sizeof(kCol16) / sizeof(kCol16[0]);
+constexpr int kNRow16 = sizeof(kRow16) / sizeof(kRow16[0]);
+constexpr int kNFull12 = sizeof(kFull12) / sizeof(kFull12[0]);
+
 }  // namespace
+
+int ntt_bucket(int nlimbs_total) {
+  if (nlimbs_total <= 4) return 0;
+  if (nlimbs_total <= 16) return 1;
+  if (nlimbs_total <= 40) return 2;
+  if (nlimbs_total <= 128) return 3;
+  return 4;
+}
+
+static void launch_passes(const Shared& sh, NttArgs a, const NttLaunch& L, bool inverse,
+                          hipStream_t st) {
+  const Params& P = sh.P;
+  const int b = ntt_bucket(L.nlimbs * L.nbatch);
+  const NttPlan& plan = sh.ntt_plan;
+  if (P.logN == 16) {
+    a.logR = 8;
+    const Variant& c = kCol16[plan.v[inverse][0][b]];
+    const Variant& r = kRow16[plan.v[inverse][1][b]];
+    a.src = L.src;
+    a.dst = L.dst;
+    if (!inverse) {
+      c.fwd(a, L.nlimbs, L.nbatch, st);
+      a.src = L.dst;
+      a.batch_stride = a.dst_stride;
+      r.fwd(a, L.nlimbs, L.nbatch, st);
+    } else {
+      r.inv(a, L.nlimbs, L.nbatch, st);
+      a.src = L.dst;
+      a.batch_stride = a.dst_stride;
+      c.inv(a, L.nlimbs, L.nbatch, st);
+    }
+  } else if (P.logN == 12) {
+    a.logR = 0;
+    a.src = L.src;
+    a.dst = L.dst;
+    const Variant& f = kFull12[plan.v[inverse][1][b]];
+    (inverse ? f.inv : f.fwd)(a, L.nlimbs, L.nbatch, st);
+  } else {
+    PPST_THROW(ST_EINVAL, "NTT supports log2 N in {12, 16}");
+  }
+}
 
 void ntt(const Shared& sh, const NttLaunch& L, bool inverse, hipStream_t st) {
   const Params& P = sh.P;
   if (L.nlimbs <= 0 || L.nbatch <= 0) return;
+  // every limb must map onto a prime of the table (the map is monotone in t)
+  {
+    const int tmax = (L.nlimbs - 1) + ((L.nlimbs - 1) >= L.skip_lo ? (L.skip_hi - L.skip_lo) : 0);
+    const int pmax = tmax < L.nq ? tmax : L.pofs + (tmax - L.nq);
+    const int pmin = 0 < L.nq ? 0 : L.pofs - L.nq;
+    if (pmax >= P.nprimes || pmin < 0 || L.skip_hi < L.skip_lo)
+      PPST_THROW(ST_EINVAL, "NTT limb map leaves the prime table");
+  }
   NttArgs a{};
   a.mods = (const Mod*)sh.tab.mods.p;
   a.tw = inverse ? sh.tab.inv.p : sh.tab.fwd.p;
@@ -191,30 +275,93 @@ void ntt(const Shared& sh, const NttLaunch& L, bool inverse, hipStream_t st) {
   a.pofs = L.pofs;
   a.skip_lo = L.skip_lo;
   a.skip_hi = L.skip_hi;
-  if (P.logN == 16) {
-    a.logR = 8;
-    if (!inverse) {
-      a.src = L.src; a.dst = L.dst;
-      run_pass<8, 4, 16, false, false>(a, L.nlimbs, L.nbatch, st);
-      a.src = L.dst;
-      a.batch_stride = a.dst_stride;
-      run_pass<8, 4, 16, true, false>(a, L.nlimbs, L.nbatch, st);
-    } else {
-      a.src = L.src; a.dst = L.dst;
-      run_pass<8, 4, 16, true, true>(a, L.nlimbs, L.nbatch, st);
-      a.src = L.dst;
-      a.batch_stride = a.dst_stride;
-      run_pass<8, 4, 16, false, true>(a, L.nlimbs, L.nbatch, st);
-    }
-  } else if (P.logN == 12) {
-    a.logR = 0;
-    a.src = L.src; a.dst = L.dst;
-    if (!inverse) run_pass<12, 4, 1, true, false>(a, L.nlimbs, L.nbatch, st);
-    else run_pass<12, 4, 1, true, true>(a, L.nlimbs, L.nbatch, st);
-  } else {
-    PPST_THROW(ST_EINVAL, "NTT supports log2 N in {12, 16}");
-  }
+  launch_passes(sh, a, L, inverse, st);
   HIP_CHECK(hipGetLastError());
+}
+
+// Autotuner: times every column and row variant (both directions) on a
+// scratch buffer of each bucket's representative limb count and keeps the
+// fastest.  Runs on the given stream; the buffer holds zeros and at least
+// max_limbs limbs; the timed limbs use primes 0..nlc-1 only (nb batches of
+// nlc <= nprimes limbs, nb * nlc <= max_limbs).
+void ntt_autotune(Shared& sh, hipStream_t st, u64* scratch, int max_limbs) {
+  const Params& P = sh.P;
+  static const int reps[5] = {2, 12, 25, 64, 200};
+  hipEvent_t e0, e1;
+  HIP_CHECK(hipEventCreate(&e0));
+  HIP_CHECK(hipEventCreate(&e1));
+  for (int b = 0; b < 5; ++b) {
+    // reps[b] limbs as nb batches of nlc limbs on primes 0..nlc-1
+    const int nlc = std::min(reps[b], P.nprimes);
+    const int nb = std::max(1, std::min((reps[b] + nlc - 1) / nlc, max_limbs / nlc));
+    for (int inv = 0; inv < 2; ++inv) {
+      NttArgs a{};
+      a.mods = (const Mod*)sh.tab.mods.p;
+      a.tw = inv ? sh.tab.inv.p : sh.tab.fwd.p;
+      a.ninv = sh.tab.ninv.p;
+      a.N = P.N;
+      a.logN = P.logN;
+      a.nq = 0;
+      a.pofs = 0;
+      a.skip_lo = a.skip_hi = 1 << 30;
+      a.src = scratch;
+      a.dst = scratch;
+      a.batch_stride = a.dst_stride = (size_t)nlc * P.N;
+      const int passes = P.logN == 16 ? 2 : 1;
+      for (int pass = 0; pass < passes; ++pass) {
+        const Variant* tab = P.logN == 16 ? (pass == 0 ? kCol16 : kRow16) : kFull12;
+        const int nv = P.logN == 16 ? (pass == 0 ? kNCol16 : kNRow16) : kNFull12;
+        a.logR = P.logN == 16 ? 8 : 0;
+        float best = 1e30f;
+        int best_i = 0;
+        for (int v = 0; v < nv; ++v) {
+          PassFn f = inv ? tab[v].inv : tab[v].fwd;
+          f(a, nlc, nb, st);   // warm
+          HIP_CHECK(hipEventRecord(e0, st));
+          for (int r = 0; r < 5; ++r) f(a, nlc, nb, st);
+          HIP_CHECK(hipEventRecord(e1, st));
+          HIP_CHECK(hipEventSynchronize(e1));
+          float ms = 0;
+          HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+          if (ms < best) { best = ms; best_i = v; }
+        }
+        sh.ntt_plan.v[inv][P.logN == 16 ? pass : 1][b] = best_i;
+      }
+    }
+  }
+  HIP_CHECK(hipEventDestroy(e0));
+  HIP_CHECK(hipEventDestroy(e1));
+  sh.ntt_plan.tuned = true;
+}
+
+std::string ntt_plan_string(const Shared& sh) {
+  const Params& P = sh.P;
+  std::string s;
+  for (int inv = 0; inv < 2; ++inv)
+    for (int b = 0; b < 5; ++b) {
+      s += inv ? "inv" : "fwd";
+      s += "[b" + std::to_string(b) + "] ";
+      if (P.logN == 16) {
+        s += kCol16[sh.ntt_plan.v[inv][0][b]].name;
+        s += " ";
+        s += kRow16[sh.ntt_plan.v[inv][1][b]].name;
+      } else {
+        s += kFull12[sh.ntt_plan.v[inv][1][b]].name;
+      }
+      s += "; ";
+    }
+  return s;
+}
+
+void ntt_set_plan(Shared& sh, int col, int row) {
+  const Params& P = sh.P;
+  const int ncol = P.logN == 16 ? kNCol16 : 1, nrow = P.logN == 16 ? kNRow16 : kNFull12;
+  if (col < 0 || col >= ncol || row < 0 || row >= nrow) PPST_THROW(ST_EINVAL, "no such NTT variant");
+  for (int inv = 0; inv < 2; ++inv)
+    for (int b = 0; b < 5; ++b) {
+      sh.ntt_plan.v[inv][0][b] = col;
+      sh.ntt_plan.v[inv][1][b] = row;
+    }
 }
 
 }  // namespace ppst

@@ -134,6 +134,9 @@ _SIGS = {
     "ppst_stat_skewness": (ctypes.c_int, [_vp, _vp, _pp, _sz, _sz, _dbl, _cfgp, _pp]),
     "ppst_stat_cv": (ctypes.c_int, [_vp, _vp, _pp, _sz, _sz, _dbl, _dbl, _cfgp, _pp]),
     "ppst_stat_pearson": (ctypes.c_int, [_vp, _vp, _pp, _pp, _sz, _sz, _dbl, _dbl, _cfgp, _pp]),
+    "ppst_ntt_autotune": (ctypes.c_int, [_vp]),
+    "ppst_ntt_plan": (ctypes.c_int, [_vp, ctypes.c_char_p, _sz]),
+    "ppst_ntt_set_plan": (ctypes.c_int, [_vp, _i32, _i32]),
     "ppst_ntt_forward": (ctypes.c_int, [_vp, _vp, _i32, _i32]),
     "ppst_ntt_inverse": (ctypes.c_int, [_vp, _vp, _i32, _i32]),
     "ppst_server_create": (ctypes.c_int, [_vp, _vp, _sz, _i32, _pp]),
@@ -563,6 +566,20 @@ def ppst_stat_pearson(ctx, evk, colx, coly, nrows, Bx, By, cfg=None):
     _chk(lib().ppst_stat_pearson(ctx, evk, _ptrs(colx), _ptrs(coly), len(colx), nrows, Bx, By,
                                  ctypes.byref(cfg), ctypes.byref(out)))
     return Ciphertext(out.value, ctx)
+
+
+def ppst_ntt_autotune(ctx: Context):
+    _chk(lib().ppst_ntt_autotune(ctx))
+
+
+def ppst_ntt_plan(ctx: Context) -> str:
+    buf = ctypes.create_string_buffer(4096)
+    _chk(lib().ppst_ntt_plan(ctx, buf, 4096))
+    return buf.value.decode()
+
+
+def ppst_ntt_set_plan(ctx: Context, col: int, row: int):
+    _chk(lib().ppst_ntt_set_plan(ctx, col, row))
 
 
 def ppst_ntt_forward(ctx: Context, dev_ptr: int, nlimbs: int, first_prime: int):

@@ -55,6 +55,35 @@ def test_raw_ntt_matches_oracle(name):
     assert np.array_equal(t.cpu().numpy().view(np.uint64), a)
 
 
+@pytest.mark.parametrize("name,ncol,nrow", [("c1", 1, 3), ("c2", 5, 6)])
+def test_every_ntt_variant_matches_oracle(name, ncol, nrow):
+    """Each register-radix / workgroup-shape variant the autotuner can pick
+    gives the canonical NTT (bit-exact) and inverts; an index past the
+    tables is rejected."""
+    torch = _torch()
+    ctx = ffi.ppst_context_create(name)
+    P = ref.Params.preset(name)
+    O = ref.Oracle(P)
+    rng = np.random.default_rng(2)
+    nl = 3
+    a = np.stack([rng.integers(0, P.q[i], P.N, dtype=np.uint64) for i in range(nl)])
+    want = O.ntt(a, list(range(nl)))
+    print("\n[ntt-variants]", name, ffi.ppst_ntt_plan(ctx)[:120], flush=True)
+    for c in range(ncol):
+        for r in range(nrow):
+            ffi.ppst_ntt_set_plan(ctx, c, r)
+            t = torch.from_numpy(a.view(np.int64).copy()).cuda()
+            torch.cuda.synchronize()
+            ffi.ppst_ntt_forward(ctx, t.data_ptr(), nl, 0)
+            ffi.ppst_sync(ctx)
+            assert np.array_equal(t.cpu().numpy().view(np.uint64), want), (c, r)
+            ffi.ppst_ntt_inverse(ctx, t.data_ptr(), nl, 0)
+            ffi.ppst_sync(ctx)
+            assert np.array_equal(t.cpu().numpy().view(np.uint64), a), (c, r)
+    with pytest.raises(ffi.PpstError):
+        ffi.ppst_ntt_set_plan(ctx, 0, nrow)
+
+
 # ------------------------------------------------------------ keys / enc
 def test_keys_bit_exact(pair):
     p = pair
