@@ -27,6 +27,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# ALU ceiling of the NTT: 256 CUs x 64 lanes x 2.4 GHz = 39.32 T VALU lane-slots/s;
+# 32-bit multiplies issue at half that rate (19.66 T/s); one Shoup modular
+# multiplication (the twiddle product of a butterfly) needs 10 of them.
+BFLY_PEAK_G = 256 * 64 * 2.4e9 / 2 / 10 / 1e9
+# HBM bytes per launch pair from FETCH_SIZE + WRITE_SIZE counters (rocprofv3
+# --pmc, one counter per run), scaled by the same counters on a plain copy of
+# known size; null when the kernels change after the counters were taken.
+NTT_TRAFFIC_BYTES = 79693047   # profiles/ntt_fwd_c2_25limbs_traffic.md
 
 
 def parse():
@@ -36,9 +44,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--pearson-runs", type=int, default=30)
-    ap.add_argument("--cpu-sample", type=int, default=12, help="oracle HMults timed on the host")
+    ap.add_argument("--cpu-sample", type=int, default=60, help="oracle HMults timed on the host")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="short run for profiling")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="only the roofline kernel and a copy of known size")
     return ap.parse_args()
 
 
@@ -58,6 +68,9 @@ def main():
     from paper_2508_12093_amd import ffi, synth
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.kernels_only:
+        kernels_only(args)
+        return
     if args.quick:
         args.steps, args.warmup, args.pearson_runs = min(args.steps, 3), 1, 3
     stream = torch.cuda.Stream()
@@ -154,32 +167,7 @@ def main():
     log("Pearson p50 %.2f ms p99 %.2f ms, value %.6f (fp64 %.6f)" % (
         np.percentile(lat, 50), np.percentile(lat, 99), pcc, ref_pcc))
 
-    # ----------------------------------------- roofline: forward NTT kernel
-    nl = 2 * (L + 1)             # one ciphertext: 50 limbs of 512 KiB
-    rng = np.random.default_rng(5)
-    primes = ctx.primes
-    host = np.stack([rng.integers(0, primes[i % (L + 1)], N, dtype=np.uint64) for i in range(nl)])
-    # two polynomials over q_0..q_24: transform each 25-limb half
-    dev = torch.from_numpy(host.view(np.int64).copy()).cuda()
-    sync()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps = 50 if not args.quick else 10
-    half = (L + 1) * N * 8
-    for _ in range(3):
-        ffi.ppst_ntt_forward(ctx, dev.data_ptr(), L + 1, 0)
-    e0.record(stream)
-    for _ in range(reps):
-        ffi.ppst_ntt_forward(ctx, dev.data_ptr(), L + 1, 0)
-        ffi.ppst_ntt_forward(ctx, dev.data_ptr() + half, L + 1, 0)
-    e1.record(stream)
-    sync()
-    ntt_ms = e0.elapsed_time(e1) / (2 * reps)            # per 25-limb forward NTT (2 passes)
-    limbs = L + 1
-    alg_bytes = 2 * 2 * limbs * N * 8                    # each pass reads and writes every limb
-    ntt_gbs = alg_bytes / (ntt_ms * 1e-3) / 1e9
-    butterflies = limbs * (N // 2) * 16
-    log("forward NTT (25 limbs, 2 passes): %.1f us, %.0f GB/s algorithmic, %.1f G butterflies/s" % (
-        ntt_ms * 1e3, ntt_gbs, butterflies / (ntt_ms * 1e-3) / 1e9))
+    rf = measure_ntt(ctx, stream, reps=10 if args.quick else 50)
 
     out = {
         "metric": "HMult+relin/sec and rotations/sec at N=2^16; p50/p99 encrypted-Pearson latency",
@@ -209,19 +197,78 @@ def main():
         "pearson_value": pcc,
         "pearson_rel_err": abs(pcc - ref_pcc) / abs(ref_pcc),
         "hmult_max_slot_err": hmult_err,
-        "roofline": {
-            "kernel": "forward NTT, column pass + row pass, 25 limbs",
-            "bound": "hbm",
-            "achieved": round(ntt_gbs, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(ntt_gbs / HBM_PEAK_GBS, 4),
-            "traffic": None,
-        },
+        "roofline": rf,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
     print(json.dumps(out), flush=True)
+
+
+def measure_ntt(ctx, stream, reps: int):
+    """Forward NTT (column pass + row pass) of one 25-limb polynomial at
+    N = 2^16, timed with HIP events on the library's stream."""
+    import numpy as np
+    import torch
+
+    from paper_2508_12093_amd import ffi
+
+    info = ctx.info
+    L, N = info.L, info.N
+    limbs = L + 1
+    rng = np.random.default_rng(5)
+    primes = ctx.primes
+    host = np.stack([rng.integers(0, primes[i % limbs], N, dtype=np.uint64) for i in range(2 * limbs)])
+    dev = torch.from_numpy(host.view(np.int64).copy()).cuda()
+    ffi.ppst_sync(ctx)
+    torch.cuda.synchronize()
+    half = limbs * N * 8
+    for _ in range(3):
+        ffi.ppst_ntt_forward(ctx, dev.data_ptr(), limbs, 0)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        ffi.ppst_ntt_forward(ctx, dev.data_ptr(), limbs, 0)
+        ffi.ppst_ntt_forward(ctx, dev.data_ptr() + half, limbs, 0)
+    e1.record(stream)
+    ffi.ppst_sync(ctx)
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / (2 * reps)           # per 25-limb forward NTT
+    butterflies = limbs * (N // 2) * info.logN               # N/2 log2 N per limb
+    alg_bytes = 2 * 2 * limbs * N * 8                        # each pass reads and writes every limb
+    g_bfly = butterflies / sec / 1e9
+    log("forward NTT (25 limbs, 2 passes): %.1f us, %.1f G butterflies/s, %.0f GB/s algorithmic" % (
+        sec * 1e6, g_bfly, alg_bytes / sec / 1e9))
+    return {
+        "kernel": "forward NTT of 25 limbs at N=2^16 (column pass + row pass)",
+        "bound": "alu",
+        "achieved": round(g_bfly, 1),
+        "peak": round(BFLY_PEAK_G, 1),
+        "unit": "G butterflies/s",
+        "frac": round(g_bfly / BFLY_PEAK_G, 4),
+        "traffic": NTT_TRAFFIC_BYTES,
+        "us_per_launch_pair": round(sec * 1e6, 2),
+        "hbm_algorithmic_GBs": round(alg_bytes / sec / 1e9, 1),
+        "hbm_frac": round(alg_bytes / sec / 1e9 / HBM_PEAK_GBS, 4),
+    }
+
+
+def kernels_only(args):
+    """Only the roofline kernel and a plain copy of known size (for
+    rocprofv3 kernel statistics and FETCH_SIZE / WRITE_SIZE counters)."""
+    import torch
+
+    from paper_2508_12093_amd import ffi
+
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    ctx = ffi.ppst_context_create("c2", stream=ctypes.c_void_p(stream.cuda_stream))
+    rf = measure_ntt(ctx, stream, reps=20)
+    n = 64 << 20                                             # 64 Mi int64 = 512 MiB
+    a = torch.ones(n, dtype=torch.int64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"roofline": rf, "copy_bytes_each_way": n * 8}), flush=True)
 
 
 def cpu_baseline(count: int):
