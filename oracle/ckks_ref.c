@@ -618,8 +618,10 @@ void orc_decrypt(const orc_params* P, const u64* s_ntt, const u64* ct, int level
  * When `g` != 0 the extended digits are permuted by X -> X^g after ModUp
  * (the hoisted-rotation form); g = 0 means no permutation.
  */
-static void keyswitch_core(const orc_params* P, int level, const u64* d, const u64* key,
-                           u64 g, u64* out0, u64* out1) {
+/* ModUp of d, optional automorphism, inner product with the key: the two
+ * accumulators over q_0..q_l, p_0..p_{K-1} (NTT form, [ne][N] each) */
+static void ks_accumulate(const orc_params* P, int level, const u64* d, const u64* key,
+                          u64 g, u64* acc0, u64* acc1) {
     int N = P->N, L = P->L, K = P->K, np = L + 1 + K;
     int nl = level + 1;
     int ne = nl + K;                       /* extended limbs: q_0..q_l, p_0..p_{K-1} */
@@ -634,8 +636,8 @@ static void keyswitch_core(const orc_params* P, int level, const u64* d, const u
     seq_pidx(qidx, nl);
     orc_intt(P, xc, nl, qidx);
 
-    u64* acc0 = (u64*)calloc((size_t)ne * N, sizeof(u64));
-    u64* acc1 = (u64*)calloc((size_t)ne * N, sizeof(u64));
+    memset(acc0, 0, sizeof(u64) * (size_t)ne * N);
+    memset(acc1, 0, sizeof(u64) * (size_t)ne * N);
     u64* ext = (u64*)malloc(sizeof(u64) * (size_t)ne * N);
     u64* tmp = (u64*)malloc(sizeof(u64) * (size_t)ne * N);
 
@@ -689,8 +691,18 @@ static void keyswitch_core(const orc_params* P, int level, const u64* d, const u
             }
         }
     }
-    /* ModDown of both accumulators, rounding: out = (u + h - Conv(u + h)) / P
-     * with h = (P-1)/2 on every coefficient, so the division rounds to nearest. */
+    free(xc); free(ext); free(tmp);
+}
+
+/* ModDown of both accumulators, rounding: out = (u + h - Conv(u + h)) / P
+ * with h = (P-1)/2 on every coefficient, so the division rounds to nearest. */
+static void ks_moddown(const orc_params* P, int level, u64* acc0, u64* acc1, u64* out0, u64* out1) {
+    int N = P->N, L = P->L, K = P->K;
+    int nl = level + 1;
+    int ne = nl + K;
+    int32_t ext_pidx[ORC_MAXP];
+    for (int t = 0; t < nl; t++) ext_pidx[t] = t;
+    for (int k = 0; k < K; k++) ext_pidx[nl + k] = L + 1 + k;
     int32_t pp[ORC_MAXP];
     for (int k = 0; k < K; k++) pp[k] = L + 1 + k;
     u64 hmod[ORC_MAXP];                    /* h mod (each prime of Q_l u P) */
@@ -744,7 +756,16 @@ static void keyswitch_core(const orc_params* P, int level, const u64* d, const u
             free(conv);
         }
     }
-    free(xc); free(acc0); free(acc1); free(ext); free(tmp);
+}
+
+static void keyswitch_core(const orc_params* P, int level, const u64* d, const u64* key,
+                           u64 g, u64* out0, u64* out1) {
+    size_t ne = (size_t)(level + 1 + P->K) * P->N;
+    u64* acc0 = (u64*)malloc(sizeof(u64) * ne);
+    u64* acc1 = (u64*)malloc(sizeof(u64) * ne);
+    ks_accumulate(P, level, d, key, g, acc0, acc1);
+    ks_moddown(P, level, acc0, acc1, out0, out1);
+    free(acc0); free(acc1);
 }
 
 void orc_keyswitch(const orc_params* P, int level, const u64* d, const u64* key, u64* out0, u64* out1) {

@@ -105,22 +105,31 @@ void build_tables(Shared& sh) {
   }
   sh.tab.mods = upload(pool, mods);
 
+  // Twiddle pairs: (w, floor(w 2^64 / q)) for the 64-bit integer path;
+  // (double w, double w/q) bit patterns for primes below 2^50, which the NTT
+  // runs in FP64 (ntt.hip).
   std::vector<u64> fwd((size_t)np * N * 2), inv((size_t)np * N * 2), ninv(2 * np);
+  auto pair = [](u64 w, u64 q, u64* out) {
+    if (q < (1ULL << 50)) {
+      double d = (double)w, s = (double)w / (double)q;
+      std::memcpy(out, &d, 8);
+      std::memcpy(out + 1, &s, 8);
+    } else {
+      out[0] = w;
+      out[1] = shoup(w, q);
+    }
+  };
   for (int i = 0; i < np; ++i) {
     u64 q = P.q[i], psi = P.psi[i], ipsi = h_invmod(psi, q);
     u64 a = 1, b = 1;
     for (int k = 0; k < N; ++k) {
       size_t pos = ((size_t)i * N + brv((unsigned)k, P.logN)) * 2;
-      fwd[pos] = a;
-      fwd[pos + 1] = shoup(a, q);
-      inv[pos] = b;
-      inv[pos + 1] = shoup(b, q);
+      pair(a, q, &fwd[pos]);
+      pair(b, q, &inv[pos]);
       a = h_mulmod(a, psi, q);
       b = h_mulmod(b, ipsi, q);
     }
-    u64 ni = h_invmod((u64)N % q, q);
-    ninv[2 * i] = ni;
-    ninv[2 * i + 1] = shoup(ni, q);
+    pair(h_invmod((u64)N % q, q), q, &ninv[2 * i]);
   }
   sh.tab.fwd = upload(pool, fwd);
   sh.tab.inv = upload(pool, inv);
@@ -151,6 +160,12 @@ void build_tables(Shared& sh) {
     u64 pinv = h_invmod(pm, qi);
     md[lay.pinv(i)] = pinv;
     md[lay.pinv(i) + 1] = shoup(pinv, qi);
+  }
+  for (int i = 0; i <= L; ++i) {   // P mod q_i
+    u64 qi = P.q[i], pm = 1;
+    for (int k = 0; k < K; ++k) pm = h_mulmod(pm, P.q[L + 1 + k] % qi, qi);
+    md[lay.pmod(i)] = pm;
+    md[lay.pmod(i) + 1] = shoup(pm, qi);
   }
   for (int p = 0; p < np; ++p) {   // h = (P - 1) / 2 reduced mod every prime
     u64 q = P.q[p], pm = 1;
@@ -305,20 +320,18 @@ const KsKey& galois_key(const EvalKeys& evk, u64 g) {
   return *it->second;
 }
 
-// Hybrid key switching of nbatch inputs d (NTT form, level l, stride sd).
-// out (stride so) = (add0 + u0, add1 + u1) with u0 + u1 s ~ d s'.
-void keyswitch(Context& cx, const KsKey& key, const u64* d, size_t sd, int level,
-               const u64* add0, const u64* add1, size_t sa, u64* out, size_t so, int nbatch) {
+// Hybrid key switching, first half: coefficient form of the input d (NTT
+// form, level l, nbatch items at stride sd), ModUp of every digit back to NTT
+// form, inner product with the key.  Returns the accumulators u,
+// [nbatch][2][ne][N] over q_0..q_l, p_0..p_{K-1}.
+Buf ks_accumulate(Context& cx, const KsKey& key, const u64* d, size_t sd, int level, int nbatch) {
   const Params& P = cx.P();
   const Shared& sh = *cx.sh;
   const int N = P.N, nl = level + 1, K = P.K, ne = nl + K, beta = P.beta(level);
-  const size_t sx = (size_t)nl * N, sext = (size_t)beta * ne * N, su = 2 * (size_t)ne * N,
-               sc = 2 * (size_t)nl * N;
+  const size_t sx = (size_t)nl * N, sext = (size_t)beta * ne * N, su = 2 * (size_t)ne * N;
   Buf x = dev_buf(cx.pool, sx * nbatch);
   Buf ext = dev_buf(cx.pool, sext * nbatch);
   Buf u = dev_buf(cx.pool, su * nbatch);
-  Buf conv = dev_buf(cx.pool, sc * nbatch);
-  // 1. coefficient form of the input
   {
     NttLaunch L{};
     L.src = d;
@@ -331,8 +344,8 @@ void keyswitch(Context& cx, const KsKey& key, const u64* d, size_t sd, int level
     L.pofs = P.L + 1;
     ntt(sh, L, true, cx.stream);
   }
-  // 2. ModUp of every digit, back to NTT form on the new limbs
   k_modup(sh, x.p, ext.p, level, nbatch, sx, sext, cx.stream);
+  x.release();
   for (int j = 0; j < beta; ++j) {
     u64* ej = ext.p + (size_t)j * ne * N;
     NttLaunch L{};
@@ -347,9 +360,19 @@ void keyswitch(Context& cx, const KsKey& key, const u64* d, size_t sd, int level
     L.skip_hi = P.digit_hi(j, level);
     ntt(sh, L, false, cx.stream);
   }
-  // 3. inner product with the key
   k_ks_inner(sh, d, ext.p, key.k.p, u.p, level, nbatch, sd, sext, su, cx.stream);
-  // 4. ModDown: special limbs to coefficient form, convert, back to NTT form
+  return u;
+}
+
+// Second half, plain: out (stride so) = (add0 + u0/P, add1 + u1/P) with the
+// rounding ModDown, for relinearisation and rotation.
+void ks_moddown(Context& cx, Buf& u, int level, const u64* add0, const u64* add1, size_t sa,
+                u64* out, size_t so, int nbatch) {
+  const Params& P = cx.P();
+  const Shared& sh = *cx.sh;
+  const int N = P.N, nl = level + 1, K = P.K, ne = nl + K;
+  const size_t sx = (size_t)nl * N, su = 2 * (size_t)ne * N, sc = 2 * (size_t)nl * N;
+  Buf conv = dev_buf(cx.pool, sc * nbatch);
   {
     NttLaunch L{};
     L.dst = u.p + (size_t)nl * N;
@@ -364,6 +387,41 @@ void keyswitch(Context& cx, const KsKey& key, const u64* d, size_t sd, int level
   k_moddown_conv(sh, u.p, conv.p, level, nbatch, su, sc, cx.stream);
   ntt_ct_limbs(cx, conv.p, nl, 2 * nbatch, sx, false);
   k_moddown_final(sh, u.p, conv.p, add0, add1, out, level, nbatch, su, sc, sa, so, cx.stream);
+}
+
+void keyswitch(Context& cx, const KsKey& key, const u64* d, size_t sd, int level,
+               const u64* add0, const u64* add1, size_t sa, u64* out, size_t so, int nbatch) {
+  Buf u = ks_accumulate(cx, key, d, sd, level, nbatch);
+  ks_moddown(cx, u, level, add0, add1, sa, out, so, nbatch);
+}
+
+// Second half for a product: rescale(d + ModDown(u)) in one pass, bit-exact
+// with relinearisation followed by rescale (kern.h, k_mdr_*).  D is the
+// tensor [3][nl][N] per item (stride sd); out [2][l][N] per item (stride so).
+void ks_moddown_rescale(Context& cx, Buf& u, const u64* D, size_t sd, int level, u64* out,
+                        size_t so, int nbatch) {
+  const Params& P = cx.P();
+  const Shared& sh = *cx.sh;
+  const int N = P.N, nl = level + 1, K = P.K, ne = nl + K;
+  const size_t su = 2 * (size_t)ne * N, sc = 2 * (size_t)level * N;
+  k_mdr_prep(sh, u.p, D, level, nbatch, su, sd, cx.stream);
+  {
+    NttLaunch L{};                    // limbs q_l, p_0..p_{K-1} of both polynomials
+    L.src = u.p;
+    L.dst = u.p;
+    L.nlimbs = K + 1;
+    L.nbatch = 2 * nbatch;
+    L.batch_stride = (size_t)ne * N;
+    L.nq = nl;
+    L.pofs = P.L + 1;
+    L.skip_lo = 0;
+    L.skip_hi = level;
+    ntt(sh, L, true, cx.stream);
+  }
+  Buf corr = dev_buf(cx.pool, sc * nbatch);
+  k_mdr_corr(sh, u.p, corr.p, level, nbatch, su, sc, cx.stream);
+  ntt_ct_limbs(cx, corr.p, level, 2 * nbatch, (size_t)level * N, false);
+  k_mdr_final(sh, u.p, D, corr.p, out, level, nbatch, su, sd, sc, so, cx.stream);
 }
 
 // rescale nbatch ciphertexts of npoly polynomials (stride sa) into out (stride so)
@@ -727,10 +785,13 @@ CtPtr relin(Context& cx, const EvalKeys& evk, const Ciphertext& d) {
 CtPtr mul(Context& cx, const EvalKeys& evk, const Ciphertext& a, const Ciphertext& b) {
   require_same(a, b);
   if (a.level < 1) PPST_THROW(ST_ELEVEL, "no level left for a product");
+  const KsKey& key = relin_key(evk);
+  const Params& P = cx.P();
   auto d = tensor(cx, a, b);
-  auto r = relin(cx, evk, *d);
-  d.reset();
-  return rescale(cx, *r);
+  Buf u = ks_accumulate(cx, key, d->poly(2), 0, a.level, 1);
+  auto out = new_ct(cx, a.level - 1, P.scale[a.level - 1]);
+  ks_moddown_rescale(cx, u, d->buf.p, 0, a.level, out->buf.p, 0, 1);
+  return out;
 }
 
 CtPtr rotate(Context& cx, const EvalKeys& evk, const Ciphertext& a, long r) {
@@ -866,12 +927,12 @@ std::vector<CtPtr> mul_batch(Context& cx, const EvalKeys& evk,
   k_tensor(*cx.sh, A.p, B.p, D.p, nl, (int)n, 2 * per, 2 * per, 3 * per, cx.stream);
   A.release();
   B.release();
-  Buf R = dev_buf(cx.pool, 2 * per * n);
-  keyswitch(cx, key, D.p + 2 * per, 3 * per, level, D.p, D.p + per, 3 * per, R.p, 2 * per, (int)n);
-  D.release();
+  Buf u = ks_accumulate(cx, key, D.p + 2 * per, 3 * per, level, (int)n);
   const size_t per2 = (size_t)level * N;
   Buf O = dev_buf(cx.pool, 2 * per2 * n);
-  rescale_raw(cx, R.p, 2 * per, level, 2, (int)n, O.p, 2 * per2);
+  ks_moddown_rescale(cx, u, D.p, 3 * per, level, O.p, 2 * per2, (int)n);
+  u.release();
+  D.release();
   std::vector<CtPtr> outs;
   for (size_t i = 0; i < n; ++i) {
     auto o = new_ct(cx, level - 1, P.scale[level - 1]);

@@ -65,6 +65,25 @@ void k_moddown_final(const Shared& sh, const u64* u, const u64* conv, const u64*
                      const u64* add1, u64* out, int level, int nbatch, size_t stride_u,
                      size_t stride_conv, size_t stride_add, size_t stride_out, hipStream_t st);
 
+// --------------------------------------- ModDown and rescale in one pass
+// After the key-switch inner product u (NTT form, [2][ne][N]) of a product
+// whose tensor is d ([3][nl][N]), these three kernels produce
+// rescale(d + ModDown(u)) bit for bit, with one NTT of the correction
+// instead of a forward NTT after ModDown and an inverse + forward NTT pair
+// inside rescale:
+//   prep:  u[c][l] += (P mod q_l) d[c][l]                      (NTT form)
+//   (iNTT of limbs q_l, p_0..p_{K-1} of u)
+//   corr:  c_l = (u_l + h - Conv_l) P^-1 mod q_l, t = centred(c_l),
+//          corr_i = (h - Conv_i) P^-1 - t  mod q_i, i < l       (coefficient form)
+//   (NTT of corr)
+//   final: out_i = (d_i + u_i P^-1 + corr_i) q_l^-1 mod q_i
+void k_mdr_prep(const Shared& sh, u64* u, const u64* d, int level, int nbatch, size_t su,
+                size_t sd, hipStream_t st);
+void k_mdr_corr(const Shared& sh, const u64* u, u64* corr, int level, int nbatch, size_t su,
+                size_t sc, hipStream_t st);
+void k_mdr_final(const Shared& sh, const u64* u, const u64* d, const u64* corr, u64* out, int level,
+                 int nbatch, size_t su, size_t sd, size_t sc, size_t so, hipStream_t st);
+
 // ------------------------------------------------------------ rescale
 // top: coefficient-form top limb of each of npoly polynomials (stride
 // top_stride); tmp[c][i] = centred(top_c) mod q_i for i < level.

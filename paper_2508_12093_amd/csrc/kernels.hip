@@ -259,6 +259,98 @@ __global__ void k_moddown_final_kernel(const u64* __restrict__ u, const u64* __r
   out[b * so + (size_t)c * per + r] = v;
 }
 
+// ------------------------------------------- ModDown and rescale together
+__global__ void k_mdr_prep_kernel(u64* u, const u64* d, const Mod* mods, const u64* md, int K,
+                                  int L, int logN, int level, int ne, int nl, size_t su,
+                                  size_t sd) {
+  const size_t N = (size_t)1 << logN;
+  size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  const int c = blockIdx.y;
+  const size_t b = blockIdx.z;
+  const MdLayout lay(K, L);
+  const u64 q = mods[level].q;
+  u64* ul = u + b * su + ((size_t)c * ne + level) * N;
+  const u64* dl = d + b * sd + ((size_t)c * nl + level) * N;
+  ul[k] = addm(ul[k], mul_shoup(dl[k], md[lay.pmod(level)], md[lay.pmod(level) + 1], q), q);
+}
+
+constexpr int kMdrChunk = 6;   // output limbs per thread
+
+template <int MAXK>
+__global__ void __launch_bounds__(kBlock)
+k_mdr_corr_kernel(const u64* u, u64* corr, const Mod* mods, const u64* md, const u64* rc, int K,
+                  int L, int logN, int level, int ne, int nchunk, size_t su, size_t sc) {
+  const int N = 1 << logN;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  const int chunk = blockIdx.y % nchunk;
+  const int c = blockIdx.y / nchunk;
+  const int ifirst = chunk * kMdrChunk;
+  if (ifirst >= level) return;
+  const u64* uc = u + blockIdx.z * su + (size_t)c * ne * N;
+  u64* cc = corr + blockIdx.z * sc + (size_t)c * level * N;
+  const MdLayout lay(K, L);
+  const int nl = level + 1;
+  u64 w[MAXK];
+#pragma unroll
+  for (int j = 0; j < MAXK; ++j) {
+    if (j < K) {
+      const int p = L + 1 + j;
+      const u64 q = mods[p].q;
+      u64 z = addm(uc[(size_t)(nl + j) * N + k], md[lay.hmod(p)], q);
+      w[j] = mul_shoup(z, md[lay.phinv(j)], md[lay.phinv(j) + 1], q);
+    }
+  }
+  // the q_l limb of d + ModDown(u), in coefficient form, and its centred lift
+  const Mod ml = mods[level];
+  u64 cl;
+  {
+    Acc acc;
+#pragma unroll
+    for (int j = 0; j < MAXK; ++j)
+      if (j < K) acc.mac(w[j], md[lay.phat(j, level)]);
+    u64 conv = reduce128(acc.hi, acc.lo, ml);
+    u64 v = subm(addm(uc[(size_t)level * N + k], md[lay.hmod(level)], ml.q), conv, ml.q);
+    cl = mul_shoup(v, md[lay.pinv(level)], md[lay.pinv(level) + 1], ml.q);
+  }
+  const bool neg = cl > (ml.q >> 1);
+#pragma unroll
+  for (int ii = 0; ii < kMdrChunk; ++ii) {
+    const int i = ifirst + ii;
+    if (i >= level) break;
+    const Mod m = mods[i];
+    Acc acc;
+#pragma unroll
+    for (int j = 0; j < MAXK; ++j)
+      if (j < K) acc.mac(w[j], md[lay.phat(j, i)]);
+    u64 conv = reduce128(acc.hi, acc.lo, m);
+    u64 v = mul_shoup(subm(md[lay.hmod(i)], conv, m.q), md[lay.pinv(i)], md[lay.pinv(i) + 1], m.q);
+    u64 t = reduce64(cl, m);
+    if (neg) t = subm(t, rc[3 * i + 2], m.q);       // t = c_l - q_l when c_l > q_l / 2
+    cc[(size_t)i * N + k] = subm(v, t, m.q);
+  }
+}
+
+__global__ void k_mdr_final_kernel(const u64* __restrict__ u, const u64* __restrict__ d,
+                                   const u64* __restrict__ corr, u64* out, const Mod* mods,
+                                   const u64* md, const u64* rc, int K, int L, int logN, int level,
+                                   int ne, int nl, size_t su, size_t sd, size_t sc, size_t so) {
+  const size_t N = (size_t)1 << logN;
+  size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= (size_t)level * N) return;
+  const int c = blockIdx.y;
+  const size_t b = blockIdx.z;
+  const int i = (int)(r >> logN);
+  const u64 q = mods[i].q;
+  const MdLayout lay(K, L);
+  u64 x = u[b * su + (size_t)c * ne * N + r];
+  u64 v = mul_shoup(x, md[lay.pinv(i)], md[lay.pinv(i) + 1], q);
+  v = addm(v, d[b * sd + (size_t)c * nl * N + r], q);
+  v = addm(v, corr[b * sc + (size_t)c * level * N + r], q);
+  out[b * so + (size_t)c * level * N + r] = mul_shoup(v, rc[3 * i], rc[3 * i + 1], q);
+}
+
 // ------------------------------------------------------------------ rescale
 __global__ void k_rescale_conv_kernel(const u64* __restrict__ top, u64* tmp, const Mod* mods,
                                       const u64* rc, int logN, int level, size_t ts) {
@@ -551,6 +643,48 @@ void k_moddown_final(const Shared& sh, const u64* u, const u64* conv, const u64*
   g.z = 2;
   hipLaunchKernelGGL(k_moddown_final_kernel, g, dim3(kBlock), 0, st, u, conv, add0, add1, out,
                      M(sh), sh.tab.moddown.p, P.K, P.L, P.logN, nl, nl + P.K, su, sc, sa, so);
+  LAUNCH_CHECK();
+}
+
+void k_mdr_prep(const Shared& sh, u64* u, const u64* d, int level, int nbatch, size_t su,
+                size_t sd, hipStream_t st) {
+  const Params& P = sh.P;
+  dim3 g = grid_for(P.N);
+  g.y = 2;
+  g.z = nbatch;
+  hipLaunchKernelGGL(k_mdr_prep_kernel, g, dim3(kBlock), 0, st, u, d, M(sh), sh.tab.moddown.p, P.K,
+                     P.L, P.logN, level, level + 1 + P.K, level + 1, su, sd);
+  LAUNCH_CHECK();
+}
+
+void k_mdr_corr(const Shared& sh, const u64* u, u64* corr, int level, int nbatch, size_t su,
+                size_t sc, hipStream_t st) {
+  const Params& P = sh.P;
+  const int nchunk = (level + kMdrChunk - 1) / kMdrChunk;
+  dim3 g = grid_for(P.N);
+  g.y = 2 * nchunk;
+  g.z = nbatch;
+  const u64* rc = rescale_table(sh, level);
+  if (P.K <= 4)
+    hipLaunchKernelGGL(k_mdr_corr_kernel<4>, g, dim3(kBlock), 0, st, u, corr, M(sh),
+                       sh.tab.moddown.p, rc, P.K, P.L, P.logN, level, level + 1 + P.K, nchunk, su, sc);
+  else if (P.K <= 8)
+    hipLaunchKernelGGL(k_mdr_corr_kernel<8>, g, dim3(kBlock), 0, st, u, corr, M(sh),
+                       sh.tab.moddown.p, rc, P.K, P.L, P.logN, level, level + 1 + P.K, nchunk, su, sc);
+  else
+    PPST_THROW(ST_EINVAL, "more than 8 special primes");
+  LAUNCH_CHECK();
+}
+
+void k_mdr_final(const Shared& sh, const u64* u, const u64* d, const u64* corr, u64* out, int level,
+                 int nbatch, size_t su, size_t sd, size_t sc, size_t so, hipStream_t st) {
+  const Params& P = sh.P;
+  dim3 g = grid_for((size_t)level * P.N);
+  g.y = 2;
+  g.z = nbatch;
+  hipLaunchKernelGGL(k_mdr_final_kernel, g, dim3(kBlock), 0, st, u, d, corr, out, M(sh),
+                     sh.tab.moddown.p, rescale_table(sh, level), P.K, P.L, P.logN, level,
+                     level + 1 + P.K, level + 1, su, sd, sc, so);
   LAUNCH_CHECK();
 }
 

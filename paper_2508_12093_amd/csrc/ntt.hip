@@ -34,21 +34,87 @@ struct NttArgs {
   int N, logN, logR, nq, pofs, skip_lo, skip_hi, blocks_per_limb;
 };
 
-// Forward CT butterfly on lazy values in [0, 4q)
-__device__ __forceinline__ void bfly_ct(u64& x, u64& y, u64 w, u64 wp, u64 q, u64 q2) {
-  u64 a = x >= q2 ? x - q2 : x;
-  u64 t = mul_shoup_lazy(y, w, wp, q);
-  x = a + t;
-  y = a - t + q2;
-}
-// Inverse GS butterfly on lazy values in [0, 2q)
-__device__ __forceinline__ void bfly_gs(u64& x, u64& y, u64 w, u64 wp, u64 q, u64 q2) {
-  u64 a = x + y;
-  a = a >= q2 ? a - q2 : a;
-  u64 d = x - y + q2;
-  y = mul_shoup_lazy(d, w, wp, q);
-  x = a;
-}
+// ----------------------------------------------------------------------
+// Butterfly arithmetic.  Two interchangeable policies, chosen per workgroup
+// by the size of its prime (the choice is uniform over a workgroup):
+//
+// IntArith: 64-bit residues, Shoup twiddle products (w, w' = floor(w 2^64/q))
+//   with Harvey's lazy ranges [0, 4q) forward and [0, 2q) inverse.
+// FpArith (q < 2^50): residues held as exact integers in FP64.  The twiddle
+//   product y w mod q is  h = fl(y w),  l = fma(y, w, -h)  (so h + l = y w
+//   exactly),  k = rint(y * (w/q)),  r = fma(-k, q, h) + l  = y w - k q exactly,
+//   with |r| < q because k is the nearest integer to y w / q up to a rounding
+//   error far below 1/2.  Table entries are (w, w/q) as doubles.
+// Both produce the same canonical residues at the end of a transform.
+// ----------------------------------------------------------------------
+struct IntArith {
+  typedef u64 T;
+  u64 q, q2;
+  __device__ __forceinline__ explicit IntArith(u64 q_) : q(q_), q2(2 * q_) {}
+  __device__ __forceinline__ T in(u64 v) const { return v; }
+  __device__ __forceinline__ u64 out_fwd(T v) const { v = v >= q2 ? v - q2 : v; return csub(v, q); }
+  __device__ __forceinline__ u64 out_inv(T v, u64 ni, u64 nip) const { return mul_shoup(v, ni, nip, q); }
+  __device__ __forceinline__ T keep(T v) const { return v; }       // value carried between passes
+  // forward CT on [0, 4q)
+  __device__ __forceinline__ void ct(T& x, T& y, ulonglong2 w) const {
+    u64 a = x >= q2 ? x - q2 : x;
+    u64 t = mul_shoup_lazy(y, w.x, w.y, q);
+    x = a + t;
+    y = a - t + q2;
+  }
+  // inverse GS on [0, 2q)
+  __device__ __forceinline__ void gs(T& x, T& y, ulonglong2 w) const {
+    u64 a = x + y;
+    a = a >= q2 ? a - q2 : a;
+    u64 d = x - y + q2;
+    y = mul_shoup_lazy(d, w.x, w.y, q);
+    x = a;
+  }
+};
+
+struct FpArith {
+  typedef double T;
+  double q, q2;
+  __device__ __forceinline__ explicit FpArith(u64 q_) : q((double)q_), q2(2.0 * (double)q_) {}
+  // y w - k q with k = rint(y w / q): exact, in (-q, q)
+  __device__ __forceinline__ double mulmod(double y, double w, double ws) const {
+    double h = y * w;
+    double l = __fma_rn(y, w, -h);
+    double k = rint(y * ws);
+    double r = __fma_rn(-k, q, h);
+    return r + l;
+  }
+  __device__ __forceinline__ T in(u64 v) const { return (double)v; }
+  __device__ __forceinline__ u64 out_fwd(T v) const {
+    v = v >= q2 ? v - q2 : v;
+    v = v >= q ? v - q : v;
+    return (u64)v;
+  }
+  __device__ __forceinline__ u64 out_inv(T v, u64 ni, u64 nis) const {
+    double r = mulmod(v, __longlong_as_double((long long)ni), __longlong_as_double((long long)nis));
+    r = r < 0.0 ? r + q : r;
+    return (u64)r;
+  }
+  // forward CT: x, y in [0, 4q) -> (0, 4q)
+  __device__ __forceinline__ void ct(T& x, T& y, ulonglong2 w) const {
+    double a = x >= q2 ? x - q2 : x;
+    double r = mulmod(y, __longlong_as_double((long long)w.x), __longlong_as_double((long long)w.y));
+    double aq = a + q;
+    x = aq + r;
+    y = aq - r;
+  }
+  // inverse GS: x, y in [0, 2q) -> [0, 2q), (0, 2q)
+  __device__ __forceinline__ void gs(T& x, T& y, ulonglong2 w) const {
+    double s = x + y;
+    s = s >= q2 ? s - q2 : s;
+    double r = mulmod(x - y, __longlong_as_double((long long)w.x), __longlong_as_double((long long)w.y));
+    y = r + q;
+    x = s;
+  }
+};
+
+// primes below this bound take the FP64 path (values stay below 2^53)
+constexpr u64 kFpPrimeBound = 1ULL << 50;
 
 // One pass of LOGM stages over SB independent sub-problems of M = 2^LOGM
 // points.  ROWS: sub-problem r = row (contiguous), twiddle base R + r;
@@ -60,31 +126,20 @@ __device__ __forceinline__ void bfly_gs(u64& x, u64& y, u64 w, u64 wp, u64 q, u6
 // stages the sub-problem splits into M / 2^ls independent groups of 2^ls
 // elements; each of the T = M / E threads owns E / 2^ls groups (E registers)
 // and exchanges them through LDS between passes.
-template <int LOGM, int LOGE, int SB, bool ROWS, bool INV>
-__global__ void __launch_bounds__(SB * (1 << (LOGM - LOGE)))
-k_ntt_pass(NttArgs a) {
+template <class A, int LOGM, int LOGE, int SB, bool ROWS, bool INV>
+__device__ __forceinline__ void ntt_body(const A ar, typename A::T* lds, const u64* src, u64* dst,
+                                         const ulonglong2* tw, const u64* ninv2, int N, int logR,
+                                         int first, bool last) {
+  typedef typename A::T T;
   constexpr int M = 1 << LOGM;
   constexpr int E = 1 << LOGE;
-  constexpr int T = M / E;           // threads per sub-problem
-  constexpr int NT = SB * T;         // threads per workgroup
+  constexpr int TPS = M / E;         // threads per sub-problem
+  constexpr int NT = SB * TPS;       // threads per workgroup
   constexpr int NP = (LOGM + LOGE - 1) / LOGE;   // register passes
   constexpr int PAD = M + 1;         // LDS row pitch (breaks bank aliasing)
-  __shared__ u64 lds[SB * PAD];
-
-  const int N = a.N;
-  const int limb_u = blockIdx.x / a.blocks_per_limb;
-  const int grp = blockIdx.x - limb_u * a.blocks_per_limb;
-  const int t = limb_u >= a.skip_lo ? limb_u + (a.skip_hi - a.skip_lo) : limb_u;
-  const int prime = t < a.nq ? t : a.pofs + (t - a.nq);
-  const u64* src = a.src + (size_t)blockIdx.y * a.batch_stride + (size_t)t * N;
-  u64* dst = a.dst + (size_t)blockIdx.y * a.dst_stride + (size_t)t * N;
-  const u64 q = a.mods[prime].q;
-  const u64 q2 = 2 * q;
-  const ulonglong2* tw = (const ulonglong2*)(a.tw + (size_t)prime * N * 2);
-  const int R = 1 << a.logR;
-  const int C = N >> a.logR;
+  const int R = 1 << logR;
+  const int C = N >> logR;
   const int tid = threadIdx.x;
-  const int first = grp * SB;        // first sub-problem of this workgroup
 
   // ---- load SB sub-problems into LDS (coalesced along memory)
   if (ROWS) {
@@ -92,20 +147,20 @@ k_ntt_pass(NttArgs a) {
 #pragma unroll 4
     for (int idx = tid; idx < SB * M; idx += NT) {
       int sp = idx / M, e = idx - sp * M;
-      lds[sp * PAD + e] = g[idx];
+      lds[sp * PAD + e] = ar.in(g[idx]);
     }
   } else {
 #pragma unroll 4
     for (int idx = tid; idx < SB * M; idx += NT) {
       int e = idx / SB, sp = idx - e * SB;
-      lds[sp * PAD + e] = src[(size_t)e * C + first + sp];
+      lds[sp * PAD + e] = ar.in(src[(size_t)e * C + first + sp]);
     }
   }
   __syncthreads();
 
-  const int sp = tid / T;
-  const int lane = tid - sp * T;
-  u64* my = lds + sp * PAD;
+  const int sp = tid / TPS;
+  const int lane = tid - sp * TPS;
+  T* my = lds + sp * PAD;
   const uint32_t base0 = ROWS ? (uint32_t)(R + first + sp) : 1u;
 
 #pragma unroll
@@ -117,10 +172,10 @@ k_ntt_pass(NttArgs a) {
     const int G = E / GS;                                      // groups per thread
     const int si = M >> (s0 + ls);                             // element stride in a group
     int e0[E];
-    u64 x[E];
+    T x[E];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      const int gi = g * T + lane;
+      const int gi = g * TPS + lane;
       const int lo = gi % si, hi = gi / si;
       e0[g] = hi * (M >> s0) + lo;
 #pragma unroll
@@ -139,8 +194,8 @@ k_ntt_pass(NttArgs a) {
           const int e = e0[g] + k * si;
           const uint32_t idx = (base0 << s) + (uint32_t)(e >> (LOGM - s));
           const ulonglong2 w = tw[idx];
-          if (INV) bfly_gs(x[g * GS + k], x[g * GS + k + half], w.x, w.y, q, q2);
-          else bfly_ct(x[g * GS + k], x[g * GS + k + half], w.x, w.y, q, q2);
+          if (INV) ar.gs(x[g * GS + k], x[g * GS + k + half], w);
+          else ar.ct(x[g * GS + k], x[g * GS + k + half], w);
         }
       }
     }
@@ -152,32 +207,48 @@ k_ntt_pass(NttArgs a) {
   }
 
   // ---- store; finish the reduction where this pass is the last one
-  const bool last = INV ? !ROWS || a.logR == 0 : ROWS;
-  const u64 ni = a.ninv[2 * prime], nip = a.ninv[2 * prime + 1];
+  const u64 ni = ninv2[0], nip = ninv2[1];
   if (ROWS) {
     u64* g = dst + (size_t)first * M;
 #pragma unroll 4
     for (int idx = tid; idx < SB * M; idx += NT) {
       int s2 = idx / M, e = idx - s2 * M;
-      u64 v = lds[s2 * PAD + e];
-      if (last) {
-        if (INV) v = mul_shoup(v, ni, nip, q);
-        else { v = v >= q2 ? v - q2 : v; v = csub(v, q); }
-      }
-      g[idx] = v;
+      T v = lds[s2 * PAD + e];
+      g[idx] = last ? (INV ? ar.out_inv(v, ni, nip) : ar.out_fwd(v)) : (u64)v;
     }
   } else {
 #pragma unroll 4
     for (int idx = tid; idx < SB * M; idx += NT) {
       int e = idx / SB, s2 = idx - e * SB;
-      u64 v = lds[s2 * PAD + e];
-      if (last) {
-        if (INV) v = mul_shoup(v, ni, nip, q);
-        else { v = v >= q2 ? v - q2 : v; v = csub(v, q); }
-      }
-      dst[(size_t)e * C + first + s2] = v;
+      T v = lds[s2 * PAD + e];
+      dst[(size_t)e * C + first + s2] = last ? (INV ? ar.out_inv(v, ni, nip) : ar.out_fwd(v)) : (u64)v;
     }
   }
+}
+
+template <int LOGM, int LOGE, int SB, bool ROWS, bool INV>
+__global__ void __launch_bounds__(SB * (1 << (LOGM - LOGE)))
+k_ntt_pass(NttArgs a) {
+  constexpr int M = 1 << LOGM;
+  __shared__ u64 lds[SB * (M + 1)];
+  const int N = a.N;
+  const int limb_u = blockIdx.x / a.blocks_per_limb;
+  const int grp = blockIdx.x - limb_u * a.blocks_per_limb;
+  const int t = limb_u >= a.skip_lo ? limb_u + (a.skip_hi - a.skip_lo) : limb_u;
+  const int prime = t < a.nq ? t : a.pofs + (t - a.nq);
+  const u64* src = a.src + (size_t)blockIdx.y * a.batch_stride + (size_t)t * N;
+  u64* dst = a.dst + (size_t)blockIdx.y * a.dst_stride + (size_t)t * N;
+  const u64 q = a.mods[prime].q;
+  const ulonglong2* tw = (const ulonglong2*)(a.tw + (size_t)prime * N * 2);
+  const u64* ni = a.ninv + 2 * prime;
+  const bool last = INV ? (!ROWS || a.logR == 0) : ROWS;
+  const int first = grp * SB;        // first sub-problem of this workgroup
+  if (q < kFpPrimeBound)
+    ntt_body<FpArith, LOGM, LOGE, SB, ROWS, INV>(FpArith(q), (double*)lds, src, dst, tw, ni, N,
+                                                  a.logR, first, last);
+  else
+    ntt_body<IntArith, LOGM, LOGE, SB, ROWS, INV>(IntArith(q), lds, src, dst, tw, ni, N, a.logR,
+                                                   first, last);
 }
 
 typedef void (*PassFn)(const NttArgs&, int, int, hipStream_t);

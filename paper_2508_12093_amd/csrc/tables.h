@@ -10,6 +10,7 @@ namespace ppst {
 //   [K][L+1]    Phat_k mod q_i
 //   [L+1][2]    (P^-1 mod q_i, Shoup companion)
 //   [nprimes]   h mod (prime), h = (P - 1) / 2, the rounding offset
+//   [L+1][2]    (P mod q_i, Shoup companion)
 struct MdLayout {
   int K, L;
   __host__ __device__ MdLayout(int k, int l) : K(k), L(l) {}
@@ -17,7 +18,8 @@ struct MdLayout {
   __host__ __device__ int phat(int k, int i) const { return 2 * K + k * (L + 1) + i; }
   __host__ __device__ int pinv(int i) const { return 2 * K + K * (L + 1) + 2 * i; }
   __host__ __device__ int hmod(int p) const { return 2 * K + K * (L + 1) + 2 * (L + 1) + p; }
-  __host__ __device__ int size() const { return hmod(L + 1 + K); }
+  __host__ __device__ int pmod(int i) const { return hmod(L + 1 + K) + 2 * i; }
+  __host__ __device__ int size() const { return pmod(L + 1); }
 };
 
 // Build every table of a parameter set on the device (called once per Shared).
