@@ -58,7 +58,10 @@ const char* ppst_last_error(void);
  * Presets: "c1" (N=2^12, 40/30/30-bit chain, Delta=2^30, one 60-bit special
  * prime); "c2" (N=2^16, Delta=2^40, 24 scale primes + 60-bit q_0, 7 special
  * primes, dnum=3: the paper's N, Delta and log2 PQ <= 1443 budget, Sec. 6.1);
- * "t1", "t2" (N=2^12 test sets with the c2 prime shapes, L=6 and L=24). */
+ * "t1", "t2" (N=2^12 test sets with the c2 prime shapes, L=6 and L=24).
+ * Every prime must stay below 2^60 (q0_bits, p_bits <= 60 and Delta well
+ * below 2^60), K <= 8, dnum <= 8 and ceil((L+1)/dnum) <= 16; other sets are
+ * rejected with PPST_EINVAL. */
 typedef struct {
   int32_t logN, L, K, dnum, q0_bits, p_bits;
   double scale;

@@ -178,8 +178,8 @@ struct Tables {
   Buf fwd;         // [nprimes][N][2] (w, w') with w = psi^brv(k)
   Buf inv;         // [nprimes][N][2] (w, w') with w = psi^-brv(k)
   Buf ninv;        // [nprimes][2] (N^-1, Shoup)
-  // ModUp constants per (level, digit): see modup_consts()
-  std::map<std::pair<int, int>, std::shared_ptr<Buf>> modup;
+  // ModUp constants per level: see modup_table()
+  std::map<int, std::shared_ptr<Buf>> modup;
   // ModDown constants (one table for all levels)
   Buf moddown;
   // rescale constants per level

@@ -47,6 +47,44 @@ struct Acc {
     hi += h + (lo < l);
   }
 };
+// Sum of products of residues below 2^60 in base 2^30: x = x1 2^30 + x0 and
+// y = y1 2^30 + y0 with every half below 2^30, so each partial product is
+// below 2^60 and a1 (two partials per term) holds 8 terms without overflow;
+// a0 and a2 hold 16.  Each term costs four 32x32+64 multiply-adds and no
+// carry handling.  Call fold() after every 8 terms to keep a1 in range.
+constexpr uint32_t kMask30 = (1u << 30) - 1;
+struct Split30 {
+  uint32_t lo = 0, hi = 0;
+  Split30() = default;
+  __device__ __forceinline__ explicit Split30(u64 x)
+      : lo((uint32_t)x & kMask30), hi((uint32_t)(x >> 30)) {}
+};
+struct Acc30 {
+  u64 a0 = 0, a1 = 0, a2 = 0;
+  __device__ __forceinline__ void mac(Split30 x, Split30 y) {
+    a0 += (u64)x.lo * y.lo;
+    a1 += (u64)x.lo * y.hi;
+    a1 += (u64)x.hi * y.lo;
+    a2 += (u64)x.hi * y.hi;
+  }
+  __device__ __forceinline__ void fold() {
+    a1 += a0 >> 30;
+    a0 &= kMask30;
+    a2 += a1 >> 30;
+    a1 &= kMask30;
+  }
+  // the sum a0 + a1 2^30 + a2 2^60 (below 2^124 for up to 16 terms) mod q
+  __device__ __forceinline__ u64 reduce(const Mod& m) const {
+    const u64 t1 = a1 << 30, t2 = a2 << 60;
+    u64 lo = a0 + t1;
+    u64 c = lo < t1;
+    lo += t2;
+    c += lo < t2;
+    const u64 hi = (a1 >> 34) + (a2 >> 4) + c;
+    return reduce128(hi, lo, m);
+  }
+};
+
 // x < 2^64 reduced mod q by one Barrett step (floor(2^64/q) = r_hi)
 __device__ __forceinline__ u64 reduce64(u64 x, const Mod& m) {
   u64 quo = mulhi(x, m.r_hi);

@@ -177,9 +177,11 @@ void build_tables(Shared& sh) {
   // ModUp per (level, digit)
   for (int l = 0; l <= L; ++l) {
     const int nl = l + 1, ne = nl + K;
+    const size_t dw = modup_digit_words(ne);
+    std::vector<u64> all(dw * P.beta(l), 0);
     for (int j = 0; j < P.beta(l); ++j) {
       const int lo = P.digit_lo(j), hi = P.digit_hi(j, l);
-      std::vector<u64> t(2 * P.alpha + (size_t)P.alpha * ne, 0);
+      u64* t = all.data() + dw * j;
       for (int i = lo; i < hi; ++i) {
         u64 qi = P.q[i], qh = 1;
         for (int i2 = lo; i2 < hi; ++i2)
@@ -192,11 +194,11 @@ void build_tables(Shared& sh) {
           u64 qt = P.q[p], v = 1;
           for (int i2 = lo; i2 < hi; ++i2)
             if (i2 != i) v = h_mulmod(v, P.q[i2] % qt, qt);
-          t[2 * P.alpha + (size_t)(i - lo) * ne + tt] = v;
+          t[2 * kMaxAlpha + (size_t)tt * kMaxAlpha + (i - lo)] = v;
         }
       }
-      sh.tab.modup[{l, j}] = std::make_shared<Buf>(upload(pool, t));
     }
+    sh.tab.modup[l] = std::make_shared<Buf>(upload(pool, all));
   }
   // rescale per level
   for (int l = 1; l <= L; ++l) {
@@ -213,8 +215,8 @@ void build_tables(Shared& sh) {
   }
 }
 
-const u64* modup_table(const Shared& sh, int level, int digit) {
-  auto it = sh.tab.modup.find({level, digit});
+const u64* modup_table(const Shared& sh, int level) {
+  auto it = sh.tab.modup.find(level);
   if (it == sh.tab.modup.end()) PPST_THROW(ST_EINVAL, "no ModUp table");
   return it->second->p;
 }
@@ -397,9 +399,10 @@ void keyswitch(Context& cx, const KsKey& key, const u64* d, size_t sd, int level
 
 // Second half for a product: rescale(d + ModDown(u)) in one pass, bit-exact
 // with relinearisation followed by rescale (kern.h, k_mdr_*).  D is the
-// tensor [3][nl][N] per item (stride sd); out [2][l][N] per item (stride so).
-void ks_moddown_rescale(Context& cx, Buf& u, const u64* D, size_t sd, int level, u64* out,
-                        size_t so, int nbatch) {
+// tensor [3][nl][N] per item (stride sd); out: one device pointer per item,
+// each [2][l][N].
+void ks_moddown_rescale(Context& cx, Buf& u, const u64* D, size_t sd, int level,
+                        u64* const* out, int nbatch) {
   const Params& P = cx.P();
   const Shared& sh = *cx.sh;
   const int N = P.N, nl = level + 1, K = P.K, ne = nl + K;
@@ -421,7 +424,7 @@ void ks_moddown_rescale(Context& cx, Buf& u, const u64* D, size_t sd, int level,
   Buf corr = dev_buf(cx.pool, sc * nbatch);
   k_mdr_corr(sh, u.p, corr.p, level, nbatch, su, sc, cx.stream);
   ntt_ct_limbs(cx, corr.p, level, 2 * nbatch, (size_t)level * N, false);
-  k_mdr_final(sh, u.p, D, corr.p, out, level, nbatch, su, sd, sc, so, cx.stream);
+  k_mdr_final(sh, u.p, D, corr.p, out, level, nbatch, su, sd, sc, cx.stream);
 }
 
 // rescale nbatch ciphertexts of npoly polynomials (stride sa) into out (stride so)
@@ -770,7 +773,9 @@ CtPtr mul_plain(Context& cx, const Ciphertext& a, const Plaintext& pt) {
 CtPtr tensor(Context& cx, const Ciphertext& a, const Ciphertext& b) {
   require_same(a, b);
   auto d = new_ct(cx, a.level, a.scale * b.scale, 3);
-  k_tensor(*cx.sh, a.buf.p, b.buf.p, d->buf.p, a.level + 1, 1, 0, 0, 0, cx.stream);
+  const u64* pa = a.buf.p;
+  const u64* pb = b.buf.p;
+  k_tensor(*cx.sh, &pa, &pb, d->buf.p, a.level + 1, 1, 0, cx.stream);
   return d;
 }
 
@@ -790,7 +795,8 @@ CtPtr mul(Context& cx, const EvalKeys& evk, const Ciphertext& a, const Ciphertex
   auto d = tensor(cx, a, b);
   Buf u = ks_accumulate(cx, key, d->poly(2), 0, a.level, 1);
   auto out = new_ct(cx, a.level - 1, P.scale[a.level - 1]);
-  ks_moddown_rescale(cx, u, d->buf.p, 0, a.level, out->buf.p, 0, 1);
+  u64* op = out->buf.p;
+  ks_moddown_rescale(cx, u, d->buf.p, 0, a.level, &op, 1);
   return out;
 }
 
@@ -915,31 +921,21 @@ std::vector<CtPtr> mul_batch(Context& cx, const EvalKeys& evk,
   const KsKey& key = relin_key(evk);
   const int nl = level + 1, N = P.N;
   const size_t per = (size_t)nl * N;
-  // gather operands into contiguous batch buffers
-  Buf A = dev_buf(cx.pool, 2 * per * n), B = dev_buf(cx.pool, 2 * per * n);
+  std::vector<const u64*> pa(n), pb(n);
   for (size_t i = 0; i < n; ++i) {
-    HIP_CHECK(hipMemcpyAsync(A.p + 2 * per * i, a[i]->buf.p, 2 * per * 8, hipMemcpyDeviceToDevice,
-                             cx.stream));
-    HIP_CHECK(hipMemcpyAsync(B.p + 2 * per * i, b[i]->buf.p, 2 * per * 8, hipMemcpyDeviceToDevice,
-                             cx.stream));
+    pa[i] = a[i]->buf.p;
+    pb[i] = b[i]->buf.p;
   }
   Buf D = dev_buf(cx.pool, 3 * per * n);
-  k_tensor(*cx.sh, A.p, B.p, D.p, nl, (int)n, 2 * per, 2 * per, 3 * per, cx.stream);
-  A.release();
-  B.release();
+  k_tensor(*cx.sh, pa.data(), pb.data(), D.p, nl, (int)n, 3 * per, cx.stream);
   Buf u = ks_accumulate(cx, key, D.p + 2 * per, 3 * per, level, (int)n);
-  const size_t per2 = (size_t)level * N;
-  Buf O = dev_buf(cx.pool, 2 * per2 * n);
-  ks_moddown_rescale(cx, u, D.p, 3 * per, level, O.p, 2 * per2, (int)n);
-  u.release();
-  D.release();
   std::vector<CtPtr> outs;
+  std::vector<u64*> po(n);
   for (size_t i = 0; i < n; ++i) {
-    auto o = new_ct(cx, level - 1, P.scale[level - 1]);
-    HIP_CHECK(hipMemcpyAsync(o->buf.p, O.p + 2 * per2 * i, 2 * per2 * 8, hipMemcpyDeviceToDevice,
-                             cx.stream));
-    outs.push_back(o);
+    outs.push_back(new_ct(cx, level - 1, P.scale[level - 1]));
+    po[i] = outs.back()->buf.p;
   }
+  ks_moddown_rescale(cx, u, D.p, 3 * per, level, po.data(), (int)n);
   return outs;
 }
 

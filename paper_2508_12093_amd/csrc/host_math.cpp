@@ -3,6 +3,7 @@
 #include <cmath>
 
 #include "core.h"
+#include "tables.h"
 
 namespace ppst {
 
@@ -91,6 +92,9 @@ Params make_params(const ParamSpec& s) {
   P.K = s.K;
   P.dnum = s.dnum;
   P.alpha = (s.L + 1 + s.dnum - 1) / s.dnum;
+  // key-switching kernels keep a digit's limbs and the special primes in registers
+  if (s.K > kMaxSpecial || P.alpha > kMaxAlpha || s.dnum > 8)
+    PPST_THROW(ST_EINVAL, "at most 8 special primes, 8 digits and 16 limbs per digit");
   P.nprimes = s.L + 1 + s.K;
   const u64 m = 2 * (u64)P.N;
   std::vector<u64> used;
@@ -114,7 +118,7 @@ Params make_params(const ParamSpec& s) {
   }
   P.psi.resize(P.nprimes);
   for (int i = 0; i < P.nprimes; ++i) {
-    if (P.q[i] >= (1ULL << 61)) PPST_THROW(ST_EINVAL, "primes must stay below 2^61");
+    if (P.q[i] >= (1ULL << 60)) PPST_THROW(ST_EINVAL, "primes must stay below 2^60");
     P.psi[i] = root_2n(P.q[i], P.N);
   }
   return P;

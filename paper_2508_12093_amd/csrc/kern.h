@@ -37,9 +37,12 @@ void k_add_scalar(const Shared& sh, const u64* a, u64* out, int nl, const u64* k
 // out[c][t] = a[c][t] * pt[t] mod q_t
 void k_mul_poly(const Shared& sh, const u64* a, const u64* pt, u64* out, int npoly, int nl,
                 size_t stride_a, size_t stride_o, hipStream_t st);
-// (d0, d1, d2) = (a0 b0, a0 b1 + a1 b0, a1 b1); a, b: [2][nl][N]; d: [3][nl][N]
-void k_tensor(const Shared& sh, const u64* a, const u64* b, u64* d, int nl, int nbatch,
-              size_t stride_a, size_t stride_b, size_t stride_d, hipStream_t st);
+// batch items per launch of the kernels that take operand pointer arrays
+constexpr int kPtrBatch = 64;
+// (d0, d1, d2) = (a0 b0, a0 b1 + a1 b0, a1 b1); a[i], b[i]: [2][nl][N] (host
+// arrays of nbatch device pointers); d: [3][nl][N] per item at stride_d
+void k_tensor(const Shared& sh, const u64* const* a, const u64* const* b, u64* d, int nl,
+              int nbatch, size_t stride_d, hipStream_t st);
 // out[c][t][j] = in[c][t][perm_g(j)], the automorphism X -> X^g in NTT form
 void k_automorph(const Shared& sh, const u64* in, u64* out, int nrows, size_t row_stride_in,
                  size_t row_stride_out, u64 g, hipStream_t st);
@@ -81,8 +84,10 @@ void k_mdr_prep(const Shared& sh, u64* u, const u64* d, int level, int nbatch, s
                 size_t sd, hipStream_t st);
 void k_mdr_corr(const Shared& sh, const u64* u, u64* corr, int level, int nbatch, size_t su,
                 size_t sc, hipStream_t st);
-void k_mdr_final(const Shared& sh, const u64* u, const u64* d, const u64* corr, u64* out, int level,
-                 int nbatch, size_t su, size_t sd, size_t sc, size_t so, hipStream_t st);
+// out: host array of nbatch device pointers, each [2][level][N]
+void k_mdr_final(const Shared& sh, const u64* u, const u64* d, const u64* corr,
+                 u64* const* out, int level, int nbatch, size_t su, size_t sd, size_t sc,
+                 hipStream_t st);
 
 // ------------------------------------------------------------ rescale
 // top: coefficient-form top limb of each of npoly polynomials (stride

@@ -65,18 +65,25 @@ __global__ void k_mul_poly_kernel(const u64* __restrict__ a, const u64* __restri
   out[c * so + r] = mulm(a[c * sa + r], pt[r], mods[t]);
 }
 
-__global__ void k_tensor_kernel(const u64* __restrict__ a, const u64* __restrict__ b, u64* d,
-                                const Mod* mods, int logN, int nl, size_t sa, size_t sb,
+// operand pointers of up to kPtrBatch batch items, passed by value
+struct PtrBatch {
+  const u64* p[kPtrBatch];
+};
+struct OutBatch {
+  u64* p[kPtrBatch];
+};
+
+__global__ void k_tensor_kernel(PtrBatch a, PtrBatch b, u64* d, const Mod* mods, int logN, int nl,
                                 size_t sd) {
   size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   size_t per = (size_t)nl << logN;
   if (r >= per) return;
-  const size_t bo = blockIdx.y;
-  a += bo * sa;
-  b += bo * sb;
+  const int bo = blockIdx.y;
+  const u64* pa = a.p[bo];
+  const u64* pb = b.p[bo];
   d += bo * sd;
   const Mod m = mods[r >> logN];
-  u64 a0 = a[r], a1 = a[per + r], b0 = b[r], b1 = b[per + r];
+  u64 a0 = pa[r], a1 = pa[per + r], b0 = pb[r], b1 = pb[per + r];
   d[r] = mulm(a0, b0, m);
   Acc acc;
   acc.mac(a0, b1);
@@ -101,21 +108,22 @@ __global__ void k_automorph_kernel(const u64* __restrict__ in, u64* out, int log
 
 // ----------------------------------------------------------- key switching
 struct ModUpArgs {
-  const u64* x;       // coefficient-form input limbs (limb t at x + t N)
-  u64* ext;           // [beta][ne][N] output limbs per batch item
-  const Mod* mods;
-  const u64* cst[8];  // per digit: [alpha][2] (Qhat_i^-1 mod q_i, Shoup), then [alpha][ne] Qhat_i mod p(t)
   size_t sx, sext;
-  int logN, nl, ne, pofs, alpha, beta, nchunk, batch;
+  int logN, nl, ne, pofs, alpha, nchunk;
 };
 
-constexpr int kModUpChunk = 4;   // target limbs per thread
+constexpr int kModUpChunk = 8;   // target limbs per thread
 
 // Thread (k, chunk, digit j): z_i = x_i Qhat_i^-1 mod q_i for the digit's limbs,
 // then y_t = sum_i z_i (Qhat_i mod t) mod t for the chunk's target limbs t
-// outside the digit (fast base conversion without correction).
+// outside the digit (fast base conversion without correction).  The loops run
+// to MAXA with z_i = 0 past the digit (the table rows there are zero), so the
+// loads of a thread issue together; the restrict-qualified table is read
+// through the scalar unit.
 template <int MAXA>
-__global__ void __launch_bounds__(kBlock) k_modup_kernel(ModUpArgs a) {
+__global__ void __launch_bounds__(kBlock)
+k_modup_kernel(const u64* __restrict__ xin, u64* __restrict__ extout,
+               const Mod* __restrict__ mods, const u64* __restrict__ tab, ModUpArgs a) {
   const int N = 1 << a.logN;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= N) return;
@@ -128,30 +136,32 @@ __global__ void __launch_bounds__(kBlock) k_modup_kernel(ModUpArgs a) {
   const int tfirst = chunk * kModUpChunk;
   const int ntarget = a.ne - da;
   if (tfirst >= ntarget) return;
-  const u64* x = a.x + blockIdx.z * a.sx;
-  u64* ext = a.ext + blockIdx.z * a.sext + (size_t)j * a.ne * N;
-  const u64* cst = a.cst[j];
-  u64 z[MAXA];
+  const u64* x = xin + blockIdx.z * a.sx;
+  u64* ext = extout + blockIdx.z * a.sext + (size_t)j * a.ne * N;
+  const u64* cst = tab + modup_digit_words(a.ne) * j;
+  u64 xv[MAXA];
+#pragma unroll
+  for (int i = 0; i < MAXA; ++i) xv[i] = x[(size_t)(lo + min(i, da - 1)) * N + k];
+  Split30 z[MAXA];
 #pragma unroll
   for (int i = 0; i < MAXA; ++i) {
-    if (i < da) {
-      u64 q = a.mods[lo + i].q;
-      z[i] = mul_shoup(x[(size_t)(lo + i) * N + k], cst[2 * i], cst[2 * i + 1], q);
-    }
+    const u64 q = mods[lo + min(i, da - 1)].q;
+    const u64 v = mul_shoup(xv[i], cst[2 * i], cst[2 * i + 1], q);
+    z[i] = Split30(i < da ? v : 0);
   }
-  const u64* qhat = cst + 2 * a.alpha;
-#pragma unroll
   for (int c = 0; c < kModUpChunk; ++c) {
     const int u = tfirst + c;
     if (u >= ntarget) break;
     const int t = u < lo ? u : u + da;
     const int p = t < a.nl ? t : a.pofs + (t - a.nl);
-    const Mod m = a.mods[p];
-    Acc acc;
+    const u64* qhat = cst + 2 * kMaxAlpha + (size_t)t * kMaxAlpha;
+    Acc30 acc;
 #pragma unroll
-    for (int i = 0; i < MAXA; ++i)
-      if (i < da) acc.mac(z[i], qhat[i * a.ne + t]);
-    ext[(size_t)t * N + k] = reduce128(acc.hi, acc.lo, m);
+    for (int i = 0; i < MAXA; ++i) {
+      acc.mac(z[i], Split30(qhat[i]));
+      if ((i & 7) == 7) acc.fold();
+    }
+    ext[(size_t)t * N + k] = acc.reduce(mods[p]);
   }
 }
 
@@ -162,8 +172,10 @@ struct InnerArgs {
   u64* u;             // [2][ne][N]
   const Mod* mods;
   size_t sd, sext, su;
-  int logN, nl, ne, beta, alpha, pofs, nprimes;
+  int logN, nl, ne, beta, alpha, pofs, nprimes, nbatch;
 };
+
+constexpr int kInnerItems = 4;   // batch items per thread: one key load serves all
 
 __global__ void __launch_bounds__(kBlock) k_ks_inner_kernel(InnerArgs a) {
   const size_t N = (size_t)1 << a.logN;
@@ -172,38 +184,76 @@ __global__ void __launch_bounds__(kBlock) k_ks_inner_kernel(InnerArgs a) {
   const int t = (int)(r >> a.logN);
   const size_t k = r & (N - 1);
   const int p = t < a.nl ? t : a.pofs + (t - a.nl);
-  const Mod m = a.mods[p];
-  const u64* d = a.d + blockIdx.y * a.sd;
-  const u64* ext = a.ext + blockIdx.y * a.sext;
-  u64* u = a.u + blockIdx.y * a.su;
+  const int b0 = blockIdx.y * kInnerItems;
+  const int nb = min(kInnerItems, a.nbatch - b0);
   const int own = t < a.nl ? t / a.alpha : -1;   // digit holding limb t
-  Acc a0, a1;
+  Acc30 s0[kInnerItems], s1[kInnerItems];
   for (int j = 0; j < a.beta; ++j) {
-    u64 e = (j == own) ? d[(size_t)t * N + k] : ext[((size_t)j * a.ne + t) * N + k];
-    const u64* kb = a.key + ((size_t)(2 * j) * a.nprimes + p) * N;
-    const u64* ka = a.key + ((size_t)(2 * j + 1) * a.nprimes + p) * N;
-    a0.mac(e, kb[k]);
-    a1.mac(e, ka[k]);
+    const Split30 kb(a.key[((size_t)(2 * j) * a.nprimes + p) * N + k]);
+    const Split30 ka(a.key[((size_t)(2 * j + 1) * a.nprimes + p) * N + k]);
+    const u64* src = (j == own) ? a.d + (size_t)t * N + k : a.ext + ((size_t)j * a.ne + t) * N + k;
+    const size_t stride = (j == own) ? a.sd : a.sext;
+    u64 ev[kInnerItems];
+#pragma unroll
+    for (int q = 0; q < kInnerItems; ++q) ev[q] = src[(size_t)(b0 + min(q, nb - 1)) * stride];
+#pragma unroll
+    for (int q = 0; q < kInnerItems; ++q) {
+      const Split30 e(ev[q]);
+      s0[q].mac(e, kb);
+      s1[q].mac(e, ka);
+    }
+    if ((j & 7) == 7) {
+#pragma unroll
+      for (int q = 0; q < kInnerItems; ++q) {
+        s0[q].fold();
+        s1[q].fold();
+      }
+    }
   }
-  u[(size_t)t * N + k] = reduce128(a0.hi, a0.lo, m);
-  u[((size_t)a.ne + t) * N + k] = reduce128(a1.hi, a1.lo, m);
+  const Mod m = a.mods[p];
+#pragma unroll
+  for (int q = 0; q < kInnerItems; ++q) {
+    if (q < nb) {
+      u64* u = a.u + (size_t)(b0 + q) * a.su;
+      u[(size_t)t * N + k] = s0[q].reduce(m);
+      u[((size_t)a.ne + t) * N + k] = s1[q].reduce(m);
+    }
+  }
 }
 
 struct ModDownArgs {
-  const u64* u;       // [2][ne][N]; special limbs at nl.. in coefficient form
-  u64* conv;          // [2][nl][N]
-  const Mod* mods;
-  const u64* md;      // moddown table (see tables.h)
   size_t su, sconv;
   int logN, nl, ne, K, L, nchunk;
 };
 
-constexpr int kModDownChunk = 5;   // output limbs per thread
+constexpr int kModDownChunk = 8;   // output limbs per thread
 
-// Thread (k, chunk, poly): w_k = (z_k + h) Phat_k^-1 mod p_k, then for the
-// chunk's limbs i: conv_i = sum_k w_k (Phat_k mod q_i) - h mod q_i.
+// w_k = (z_k + h) Phat_k^-1 mod p_k for the special limbs z of one polynomial
+// in coefficient form (w_k = 0 for k >= K), split for Acc30.
 template <int MAXK>
-__global__ void __launch_bounds__(kBlock) k_moddown_conv_kernel(ModDownArgs a) {
+__device__ __forceinline__ void moddown_weights(const u64* __restrict__ u, int nl, int K, int L,
+                                                int N, int k, const Mod* __restrict__ mods,
+                                                const u64* __restrict__ md, Split30* w) {
+  const MdLayout lay(K, L);
+  u64 zv[MAXK];
+#pragma unroll
+  for (int i = 0; i < MAXK; ++i) zv[i] = u[(size_t)(nl + min(i, K - 1)) * N + k];
+#pragma unroll
+  for (int i = 0; i < MAXK; ++i) {
+    const int p = L + 1 + min(i, K - 1);
+    const u64 q = mods[p].q;
+    const u64 z = addm(zv[i], md[lay.hmod(p)], q);
+    const u64 v = mul_shoup(z, md[lay.phinv(i)], md[lay.phinv(i) + 1], q);
+    w[i] = Split30(i < K ? v : 0);
+  }
+}
+
+// Thread (k, chunk, poly): conv_i = sum_k w_k (Phat_k mod q_i) - h mod q_i for
+// the chunk's limbs i.
+template <int MAXK>
+__global__ void __launch_bounds__(kBlock)
+k_moddown_conv_kernel(const u64* __restrict__ uin, u64* __restrict__ convout,
+                      const Mod* __restrict__ mods, const u64* __restrict__ md, ModDownArgs a) {
   const int N = 1 << a.logN;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= N) return;
@@ -211,30 +261,20 @@ __global__ void __launch_bounds__(kBlock) k_moddown_conv_kernel(ModDownArgs a) {
   const int c = blockIdx.y / a.nchunk;
   const int ifirst = chunk * kModDownChunk;
   if (ifirst >= a.nl) return;
-  const u64* u = a.u + blockIdx.z * a.su + (size_t)c * a.ne * N;
-  u64* conv = a.conv + blockIdx.z * a.sconv + (size_t)c * a.nl * N;
+  const u64* u = uin + blockIdx.z * a.su + (size_t)c * a.ne * N;
+  u64* conv = convout + blockIdx.z * a.sconv + (size_t)c * a.nl * N;
   const MdLayout lay(a.K, a.L);
-  u64 w[MAXK];
-#pragma unroll
-  for (int i = 0; i < MAXK; ++i) {
-    if (i < a.K) {
-      const int p = a.L + 1 + i;
-      const u64 q = a.mods[p].q;
-      u64 z = addm(u[(size_t)(a.nl + i) * N + k], a.md[lay.hmod(p)], q);
-      w[i] = mul_shoup(z, a.md[lay.phinv(i)], a.md[lay.phinv(i) + 1], q);
-    }
-  }
-#pragma unroll
+  Split30 w[MAXK];
+  moddown_weights<MAXK>(u, a.nl, a.K, a.L, N, k, mods, md, w);
   for (int cc = 0; cc < kModDownChunk; ++cc) {
     const int i = ifirst + cc;
     if (i >= a.nl) break;
-    const Mod m = a.mods[i];
-    Acc acc;
+    const Mod m = mods[i];
+    Acc30 acc;
 #pragma unroll
-    for (int j = 0; j < MAXK; ++j)
-      if (j < a.K) acc.mac(w[j], a.md[lay.phat(j, i)]);
-    u64 v = reduce128(acc.hi, acc.lo, m);
-    conv[(size_t)i * N + k] = subm(v, a.md[lay.hmod(i)], m.q);
+    for (int j = 0; j < MAXK; ++j) acc.mac(w[j], Split30(md[lay.phat(j, i)]));
+    u64 v = acc.reduce(m);
+    conv[(size_t)i * N + k] = subm(v, md[lay.hmod(i)], m.q);
   }
 }
 
@@ -275,12 +315,13 @@ __global__ void k_mdr_prep_kernel(u64* u, const u64* d, const Mod* mods, const u
   ul[k] = addm(ul[k], mul_shoup(dl[k], md[lay.pmod(level)], md[lay.pmod(level) + 1], q), q);
 }
 
-constexpr int kMdrChunk = 6;   // output limbs per thread
+constexpr int kMdrChunk = 8;   // output limbs per thread
 
 template <int MAXK>
 __global__ void __launch_bounds__(kBlock)
-k_mdr_corr_kernel(const u64* u, u64* corr, const Mod* mods, const u64* md, const u64* rc, int K,
-                  int L, int logN, int level, int ne, int nchunk, size_t su, size_t sc) {
+k_mdr_corr_kernel(const u64* __restrict__ u, u64* __restrict__ corr, const Mod* __restrict__ mods,
+                  const u64* __restrict__ md, const u64* __restrict__ rc, int K, int L, int logN,
+                  int level, int ne, int nchunk, size_t su, size_t sc) {
   const int N = 1 << logN;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= N) return;
@@ -292,39 +333,28 @@ k_mdr_corr_kernel(const u64* u, u64* corr, const Mod* mods, const u64* md, const
   u64* cc = corr + blockIdx.z * sc + (size_t)c * level * N;
   const MdLayout lay(K, L);
   const int nl = level + 1;
-  u64 w[MAXK];
-#pragma unroll
-  for (int j = 0; j < MAXK; ++j) {
-    if (j < K) {
-      const int p = L + 1 + j;
-      const u64 q = mods[p].q;
-      u64 z = addm(uc[(size_t)(nl + j) * N + k], md[lay.hmod(p)], q);
-      w[j] = mul_shoup(z, md[lay.phinv(j)], md[lay.phinv(j) + 1], q);
-    }
-  }
+  Split30 w[MAXK];
+  moddown_weights<MAXK>(uc, nl, K, L, N, k, mods, md, w);
   // the q_l limb of d + ModDown(u), in coefficient form, and its centred lift
   const Mod ml = mods[level];
   u64 cl;
   {
-    Acc acc;
+    Acc30 acc;
 #pragma unroll
-    for (int j = 0; j < MAXK; ++j)
-      if (j < K) acc.mac(w[j], md[lay.phat(j, level)]);
-    u64 conv = reduce128(acc.hi, acc.lo, ml);
+    for (int j = 0; j < MAXK; ++j) acc.mac(w[j], Split30(md[lay.phat(j, level)]));
+    u64 conv = acc.reduce(ml);
     u64 v = subm(addm(uc[(size_t)level * N + k], md[lay.hmod(level)], ml.q), conv, ml.q);
     cl = mul_shoup(v, md[lay.pinv(level)], md[lay.pinv(level) + 1], ml.q);
   }
   const bool neg = cl > (ml.q >> 1);
-#pragma unroll
   for (int ii = 0; ii < kMdrChunk; ++ii) {
     const int i = ifirst + ii;
     if (i >= level) break;
     const Mod m = mods[i];
-    Acc acc;
+    Acc30 acc;
 #pragma unroll
-    for (int j = 0; j < MAXK; ++j)
-      if (j < K) acc.mac(w[j], md[lay.phat(j, i)]);
-    u64 conv = reduce128(acc.hi, acc.lo, m);
+    for (int j = 0; j < MAXK; ++j) acc.mac(w[j], Split30(md[lay.phat(j, i)]));
+    u64 conv = acc.reduce(m);
     u64 v = mul_shoup(subm(md[lay.hmod(i)], conv, m.q), md[lay.pinv(i)], md[lay.pinv(i) + 1], m.q);
     u64 t = reduce64(cl, m);
     if (neg) t = subm(t, rc[3 * i + 2], m.q);       // t = c_l - q_l when c_l > q_l / 2
@@ -333,9 +363,9 @@ k_mdr_corr_kernel(const u64* u, u64* corr, const Mod* mods, const u64* md, const
 }
 
 __global__ void k_mdr_final_kernel(const u64* __restrict__ u, const u64* __restrict__ d,
-                                   const u64* __restrict__ corr, u64* out, const Mod* mods,
+                                   const u64* __restrict__ corr, OutBatch out, const Mod* mods,
                                    const u64* md, const u64* rc, int K, int L, int logN, int level,
-                                   int ne, int nl, size_t su, size_t sd, size_t sc, size_t so) {
+                                   int ne, int nl, size_t su, size_t sd, size_t sc) {
   const size_t N = (size_t)1 << logN;
   size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= (size_t)level * N) return;
@@ -348,7 +378,7 @@ __global__ void k_mdr_final_kernel(const u64* __restrict__ u, const u64* __restr
   u64 v = mul_shoup(x, md[lay.pinv(i)], md[lay.pinv(i) + 1], q);
   v = addm(v, d[b * sd + (size_t)c * nl * N + r], q);
   v = addm(v, corr[b * sc + (size_t)c * level * N + r], q);
-  out[b * so + (size_t)c * level * N + r] = mul_shoup(v, rc[3 * i], rc[3 * i + 1], q);
+  out.p[b][(size_t)c * level * N + r] = mul_shoup(v, rc[3 * i], rc[3 * i + 1], q);
 }
 
 // ------------------------------------------------------------------ rescale
@@ -534,14 +564,22 @@ void k_mul_poly(const Shared& sh, const u64* a, const u64* pt, u64* out, int npo
   LAUNCH_CHECK();
 }
 
-void k_tensor(const Shared& sh, const u64* a, const u64* b, u64* d, int nl, int nbatch,
-              size_t sa, size_t sb, size_t sd, hipStream_t st) {
+void k_tensor(const Shared& sh, const u64* const* a, const u64* const* b, u64* d, int nl,
+              int nbatch, size_t sd, hipStream_t st) {
   size_t n = (size_t)nl * sh.P.N;
-  dim3 g = grid_for(n);
-  g.y = nbatch;
-  hipLaunchKernelGGL(k_tensor_kernel, g, dim3(kBlock), 0, st, a, b, d, M(sh), sh.P.logN, nl, sa,
-                     sb, sd);
-  LAUNCH_CHECK();
+  for (int b0 = 0; b0 < nbatch; b0 += kPtrBatch) {
+    const int nb = std::min(kPtrBatch, nbatch - b0);
+    PtrBatch pa{}, pb{};
+    for (int i = 0; i < nb; ++i) {
+      pa.p[i] = a[b0 + i];
+      pb.p[i] = b[b0 + i];
+    }
+    dim3 g = grid_for(n);
+    g.y = nb;
+    hipLaunchKernelGGL(k_tensor_kernel, g, dim3(kBlock), 0, st, pa, pb, d + (size_t)b0 * sd, M(sh),
+                       sh.P.logN, nl, sd);
+    LAUNCH_CHECK();
+  }
 }
 
 void k_automorph(const Shared& sh, const u64* in, u64* out, int nrows, size_t sin, size_t sout,
@@ -556,9 +594,6 @@ void k_modup(const Shared& sh, const u64* x, u64* ext, int level, int nbatch, si
              size_t sext, hipStream_t st) {
   const Params& P = sh.P;
   ModUpArgs a;
-  a.x = x;
-  a.ext = ext;
-  a.mods = M(sh);
   a.sx = sx;
   a.sext = sext;
   a.logN = P.logN;
@@ -566,20 +601,23 @@ void k_modup(const Shared& sh, const u64* x, u64* ext, int level, int nbatch, si
   a.ne = level + 1 + P.K;
   a.pofs = P.L + 1;
   a.alpha = P.alpha;
-  a.beta = P.beta(level);
-  if (a.beta > 8) PPST_THROW(ST_EINVAL, "more than 8 digits");
-  for (int j = 0; j < a.beta; ++j) a.cst[j] = modup_table(sh, level, j);
-  // the first digit has the most targets: ne - alpha (or ne - nl when it is the only one)
-  int most = a.ne - std::min(a.alpha, a.nl);
-  for (int j = 0; j < a.beta; ++j) most = std::max(most, a.ne - (P.digit_hi(j, level) - P.digit_lo(j)));
+  const int beta = P.beta(level);
+  const u64* tab = modup_table(sh, level);
+  // the digit with the fewest limbs has the most targets
+  int most = 0;
+  for (int j = 0; j < beta; ++j) most = std::max(most, a.ne - (P.digit_hi(j, level) - P.digit_lo(j)));
   a.nchunk = (most + kModUpChunk - 1) / kModUpChunk;
   dim3 g = grid_for(P.N);
-  g.y = a.nchunk * a.beta;
+  g.y = a.nchunk * beta;
   g.z = nbatch;
-  if (P.alpha <= 4) hipLaunchKernelGGL(k_modup_kernel<4>, g, dim3(kBlock), 0, st, a);
-  else if (P.alpha <= 9) hipLaunchKernelGGL(k_modup_kernel<9>, g, dim3(kBlock), 0, st, a);
-  else if (P.alpha <= 16) hipLaunchKernelGGL(k_modup_kernel<16>, g, dim3(kBlock), 0, st, a);
-  else PPST_THROW(ST_EINVAL, "digit size above 16 limbs");
+  if (P.alpha <= 4)
+    hipLaunchKernelGGL(k_modup_kernel<4>, g, dim3(kBlock), 0, st, x, ext, M(sh), tab, a);
+  else if (P.alpha <= 9)
+    hipLaunchKernelGGL(k_modup_kernel<9>, g, dim3(kBlock), 0, st, x, ext, M(sh), tab, a);
+  else if (P.alpha <= kMaxAlpha)
+    hipLaunchKernelGGL(k_modup_kernel<16>, g, dim3(kBlock), 0, st, x, ext, M(sh), tab, a);
+  else
+    PPST_THROW(ST_EINVAL, "digit size above 16 limbs");
   LAUNCH_CHECK();
 }
 
@@ -602,8 +640,9 @@ void k_ks_inner(const Shared& sh, const u64* d, const u64* ext, const u64* key, 
   a.alpha = P.alpha;
   a.pofs = P.L + 1;
   a.nprimes = P.nprimes;
+  a.nbatch = nbatch;
   dim3 g = grid_for((size_t)a.ne * P.N);
-  g.y = nbatch;
+  g.y = (nbatch + kInnerItems - 1) / kInnerItems;
   hipLaunchKernelGGL(k_ks_inner_kernel, g, dim3(kBlock), 0, st, a);
   LAUNCH_CHECK();
 }
@@ -612,10 +651,6 @@ void k_moddown_conv(const Shared& sh, const u64* u, u64* conv, int level, int nb
                     size_t sconv, hipStream_t st) {
   const Params& P = sh.P;
   ModDownArgs a;
-  a.u = u;
-  a.conv = conv;
-  a.mods = M(sh);
-  a.md = sh.tab.moddown.p;
   a.su = su;
   a.sconv = sconv;
   a.logN = P.logN;
@@ -627,9 +662,13 @@ void k_moddown_conv(const Shared& sh, const u64* u, u64* conv, int level, int nb
   dim3 g = grid_for(P.N);
   g.y = 2 * a.nchunk;
   g.z = nbatch;
-  if (P.K <= 4) hipLaunchKernelGGL(k_moddown_conv_kernel<4>, g, dim3(kBlock), 0, st, a);
-  else if (P.K <= 8) hipLaunchKernelGGL(k_moddown_conv_kernel<8>, g, dim3(kBlock), 0, st, a);
-  else PPST_THROW(ST_EINVAL, "more than 8 special primes");
+  const u64* md = sh.tab.moddown.p;
+  if (P.K <= 4)
+    hipLaunchKernelGGL(k_moddown_conv_kernel<4>, g, dim3(kBlock), 0, st, u, conv, M(sh), md, a);
+  else if (P.K <= kMaxSpecial)
+    hipLaunchKernelGGL(k_moddown_conv_kernel<8>, g, dim3(kBlock), 0, st, u, conv, M(sh), md, a);
+  else
+    PPST_THROW(ST_EINVAL, "more than 8 special primes");
   LAUNCH_CHECK();
 }
 
@@ -676,16 +715,23 @@ void k_mdr_corr(const Shared& sh, const u64* u, u64* corr, int level, int nbatch
   LAUNCH_CHECK();
 }
 
-void k_mdr_final(const Shared& sh, const u64* u, const u64* d, const u64* corr, u64* out, int level,
-                 int nbatch, size_t su, size_t sd, size_t sc, size_t so, hipStream_t st) {
+void k_mdr_final(const Shared& sh, const u64* u, const u64* d, const u64* corr,
+                 u64* const* out, int level, int nbatch, size_t su, size_t sd, size_t sc,
+                 hipStream_t st) {
   const Params& P = sh.P;
-  dim3 g = grid_for((size_t)level * P.N);
-  g.y = 2;
-  g.z = nbatch;
-  hipLaunchKernelGGL(k_mdr_final_kernel, g, dim3(kBlock), 0, st, u, d, corr, out, M(sh),
-                     sh.tab.moddown.p, rescale_table(sh, level), P.K, P.L, P.logN, level,
-                     level + 1 + P.K, level + 1, su, sd, sc, so);
-  LAUNCH_CHECK();
+  for (int b0 = 0; b0 < nbatch; b0 += kPtrBatch) {
+    const int nb = std::min(kPtrBatch, nbatch - b0);
+    OutBatch po{};
+    for (int i = 0; i < nb; ++i) po.p[i] = out[b0 + i];
+    dim3 g = grid_for((size_t)level * P.N);
+    g.y = 2;
+    g.z = nb;
+    hipLaunchKernelGGL(k_mdr_final_kernel, g, dim3(kBlock), 0, st, u + (size_t)b0 * su,
+                       d + (size_t)b0 * sd, corr + (size_t)b0 * sc, po, M(sh), sh.tab.moddown.p,
+                       rescale_table(sh, level), P.K, P.L, P.logN, level, level + 1 + P.K,
+                       level + 1, su, sd, sc);
+    LAUNCH_CHECK();
+  }
 }
 
 void k_rescale_conv(const Shared& sh, const u64* top, u64* tmp, int level, int npoly,

@@ -5,29 +5,41 @@
 
 namespace ppst {
 
-// ModDown table layout (one table serves every level):
-//   [K][2]      (Phat_k^-1 mod p_k, Shoup companion), Phat_k = P / p_k
-//   [K][L+1]    Phat_k mod q_i
-//   [L+1][2]    (P^-1 mod q_i, Shoup companion)
-//   [nprimes]   h mod (prime), h = (P - 1) / 2, the rounding offset
-//   [L+1][2]    (P mod q_i, Shoup companion)
+constexpr int kMaxAlpha = 16;     // limbs per key-switching digit
+constexpr int kMaxSpecial = 8;    // special primes
+
+// ModDown table layout (one table serves every level); the rows of the first
+// two blocks are padded with zeros to kMaxSpecial so that kernels can run
+// their loops over special primes to a compile-time bound:
+//   [kMaxSpecial][2]      (Phat_k^-1 mod p_k, Shoup companion), Phat_k = P / p_k
+//   [L+1][kMaxSpecial]    Phat_k mod q_i (the K values of one q_i contiguous)
+//   [L+1][2]              (P^-1 mod q_i, Shoup companion)
+//   [nprimes]             h mod (prime), h = (P - 1) / 2, the rounding offset
+//   [L+1][2]              (P mod q_i, Shoup companion)
 struct MdLayout {
   int K, L;
   __host__ __device__ MdLayout(int k, int l) : K(k), L(l) {}
   __host__ __device__ int phinv(int k) const { return 2 * k; }
-  __host__ __device__ int phat(int k, int i) const { return 2 * K + k * (L + 1) + i; }
-  __host__ __device__ int pinv(int i) const { return 2 * K + K * (L + 1) + 2 * i; }
-  __host__ __device__ int hmod(int p) const { return 2 * K + K * (L + 1) + 2 * (L + 1) + p; }
+  __host__ __device__ int phat(int k, int i) const { return 2 * kMaxSpecial + i * kMaxSpecial + k; }
+  __host__ __device__ int pinv(int i) const { return 2 * kMaxSpecial + kMaxSpecial * (L + 1) + 2 * i; }
+  __host__ __device__ int hmod(int p) const { return pinv(L + 1) + p; }
   __host__ __device__ int pmod(int i) const { return hmod(L + 1 + K) + 2 * i; }
   __host__ __device__ int size() const { return pmod(L + 1); }
 };
 
+// ModUp table of one level: for each digit j, [kMaxAlpha][2] (Qhat_i^-1 mod
+// q_i, Shoup) for the digit's limbs i, then [ne][kMaxAlpha] Qhat_i mod p(t)
+// for every extended limb t (one target's values contiguous); entries past
+// the digit's limbs are zero.
+__host__ __device__ inline size_t modup_digit_words(int ne) {
+  return 2 * kMaxAlpha + (size_t)kMaxAlpha * ne;
+}
+
 // Build every table of a parameter set on the device (called once per Shared).
 void build_tables(Shared& sh);
 
-// ModUp table for (level, digit): [alpha][2] (Qhat_i^-1 mod q_i, Shoup) for
-// the digit's limbs i, then [alpha][ne] Qhat_i mod p(t) for every extended limb t.
-const u64* modup_table(const Shared& sh, int level, int digit);
+// ModUp table of a level: [beta][modup_digit_words(ne)]
+const u64* modup_table(const Shared& sh, int level);
 // Rescale table for dropping q_level: [level][3] = (q_level^-1 mod q_i, Shoup, q_level mod q_i)
 const u64* rescale_table(const Shared& sh, int level);
 
