@@ -93,6 +93,18 @@ __device__ __forceinline__ u64 reduce64(u64 x, const Mod& m) {
   return csub(r, m.q);
 }
 
+// Automorphism X -> X^g in canonical NTT order: output slot j takes input
+// slot j' with 2 brv(j') + 1 = (2 brv(j) + 1) g mod 2N.  g = 0 stands for the
+// identity.  The map sends every aligned block of 2^s slots onto one aligned
+// block (the low bits of 2 brv(j) + 1 come from the high bits of j), so
+// permuted reads of a row stay inside one row.
+__device__ __forceinline__ uint32_t galois_src(uint32_t j, uint32_t g, int logN) {
+  if (g == 0) return j;
+  const uint32_t e = 2 * (__brev(j) >> (32 - logN)) + 1;
+  const uint32_t e2 = (e * g) & ((2u << logN) - 1);
+  return __brev((e2 - 1) >> 1) >> (32 - logN);
+}
+
 // limb t -> combined prime index: t < nq ? t : pofs + (t - nq)
 struct PrimeMap {
   int nq, pofs;

@@ -322,11 +322,33 @@ const KsKey& galois_key(const EvalKeys& evk, u64 g) {
   return *it->second;
 }
 
+// Forward NTT of the ModUp output [nbatch][beta][ne][N] in one launch: it is
+// [nbatch * beta][ne][N] with each digit's own limbs skipped.
+void ntt_ext_digits(Context& cx, u64* ext, int level, int nbatch) {
+  const Params& P = cx.P();
+  const int nl = level + 1, ne = nl + P.K, beta = P.beta(level);
+  NttLaunch L{};
+  L.src = ext;
+  L.dst = ext;
+  int most = 0;
+  for (int j = 0; j < beta; ++j) most = std::max(most, ne - (P.digit_hi(j, level) - P.digit_lo(j)));
+  L.nlimbs = most;
+  L.nbatch = nbatch * beta;
+  L.batch_stride = (size_t)ne * P.N;
+  L.nq = nl;
+  L.pofs = P.L + 1;
+  L.digit_alpha = P.alpha;
+  L.digit_count = beta;
+  L.digit_total = ne;
+  ntt(*cx.sh, L, false, cx.stream);
+}
+
 // Hybrid key switching, first half: coefficient form of the input d (NTT
 // form, level l, nbatch items at stride sd), ModUp of every digit back to NTT
 // form, inner product with the key.  Returns the accumulators u,
 // [nbatch][2][ne][N] over q_0..q_l, p_0..p_{K-1}.
-Buf ks_accumulate(Context& cx, const KsKey& key, const u64* d, size_t sd, int level, int nbatch) {
+Buf ks_accumulate(Context& cx, const KsKey& key, const u64* d, size_t sd, int level, int nbatch,
+                  uint32_t g = 0) {
   const Params& P = cx.P();
   const Shared& sh = *cx.sh;
   const int N = P.N, nl = level + 1, K = P.K, ne = nl + K, beta = P.beta(level);
@@ -344,32 +366,20 @@ Buf ks_accumulate(Context& cx, const KsKey& key, const u64* d, size_t sd, int le
     L.dst_stride = sx;
     L.nq = nl;
     L.pofs = P.L + 1;
+    L.galois = g;
     ntt(sh, L, true, cx.stream);
   }
   k_modup(sh, x.p, ext.p, level, nbatch, sx, sext, cx.stream);
   x.release();
-  for (int j = 0; j < beta; ++j) {
-    u64* ej = ext.p + (size_t)j * ne * N;
-    NttLaunch L{};
-    L.src = ej;
-    L.dst = ej;
-    L.nlimbs = ne - (P.digit_hi(j, level) - P.digit_lo(j));
-    L.nbatch = nbatch;
-    L.batch_stride = sext;
-    L.nq = nl;
-    L.pofs = P.L + 1;
-    L.skip_lo = P.digit_lo(j);
-    L.skip_hi = P.digit_hi(j, level);
-    ntt(sh, L, false, cx.stream);
-  }
-  k_ks_inner(sh, d, ext.p, key.k.p, u.p, level, nbatch, sd, sext, su, cx.stream);
+  ntt_ext_digits(cx, ext.p, level, nbatch);
+  k_ks_inner(sh, d, ext.p, key.k.p, u.p, level, nbatch, sd, sext, su, g, 0, cx.stream);
   return u;
 }
 
 // Second half, plain: out (stride so) = (add0 + u0/P, add1 + u1/P) with the
 // rounding ModDown, for relinearisation and rotation.
 void ks_moddown(Context& cx, Buf& u, int level, const u64* add0, const u64* add1, size_t sa,
-                u64* out, size_t so, int nbatch) {
+                u64* out, size_t so, int nbatch, uint32_t gadd = 0) {
   const Params& P = cx.P();
   const Shared& sh = *cx.sh;
   const int N = P.N, nl = level + 1, K = P.K, ne = nl + K;
@@ -388,13 +398,17 @@ void ks_moddown(Context& cx, Buf& u, int level, const u64* add0, const u64* add1
   }
   k_moddown_conv(sh, u.p, conv.p, level, nbatch, su, sc, cx.stream);
   ntt_ct_limbs(cx, conv.p, nl, 2 * nbatch, sx, false);
-  k_moddown_final(sh, u.p, conv.p, add0, add1, out, level, nbatch, su, sc, sa, so, cx.stream);
+  k_moddown_final(sh, u.p, conv.p, add0, add1, out, level, nbatch, su, sc, sa, so, gadd,
+                  cx.stream);
 }
 
+// g != 0: switch the key of the automorphism X -> X^g applied to d and add0
+// (the permutation is folded into their reads)
 void keyswitch(Context& cx, const KsKey& key, const u64* d, size_t sd, int level,
-               const u64* add0, const u64* add1, size_t sa, u64* out, size_t so, int nbatch) {
-  Buf u = ks_accumulate(cx, key, d, sd, level, nbatch);
-  ks_moddown(cx, u, level, add0, add1, sa, out, so, nbatch);
+               const u64* add0, const u64* add1, size_t sa, u64* out, size_t so, int nbatch,
+               uint32_t g = 0) {
+  Buf u = ks_accumulate(cx, key, d, sd, level, nbatch, g);
+  ks_moddown(cx, u, level, add0, add1, sa, out, so, nbatch, g);
 }
 
 // Second half for a product: rescale(d + ModDown(u)) in one pass, bit-exact
@@ -806,11 +820,9 @@ CtPtr rotate(Context& cx, const EvalKeys& evk, const Ciphertext& a, long r) {
   u64 g = galois_elt(P, r);
   if (g == 1) return copy_ct(cx, a);
   const KsKey& key = galois_key(evk, g);
-  const size_t per = (size_t)(a.level + 1) * P.N;
-  Buf perm = dev_buf(cx.pool, 2 * per);
-  k_automorph(*cx.sh, a.buf.p, perm.p, 2 * (a.level + 1), P.N, P.N, g, cx.stream);
   auto out = new_ct(cx, a.level, a.scale);
-  keyswitch(cx, key, perm.p + per, 0, a.level, perm.p, nullptr, 0, out->buf.p, 0, 1);
+  keyswitch(cx, key, a.poly(1), 0, a.level, a.poly(0), nullptr, 0, out->buf.p, 0, 1,
+            (uint32_t)g);
   return out;
 }
 
@@ -835,21 +847,8 @@ std::vector<CtPtr> rotate_hoisted(Context& cx, const EvalKeys& evk, const Cipher
     ntt(sh, L, true, cx.stream);
   }
   k_modup(sh, x.p, ext.p, level, 1, per, sext, cx.stream);
-  for (int j = 0; j < beta; ++j) {
-    u64* ej = ext.p + (size_t)j * ne * N;
-    NttLaunch L{};
-    L.src = ej;
-    L.dst = ej;
-    L.nlimbs = ne - (P.digit_hi(j, level) - P.digit_lo(j));
-    L.nq = nl;
-    L.pofs = P.L + 1;
-    L.skip_lo = P.digit_lo(j);
-    L.skip_hi = P.digit_hi(j, level);
-    ntt(sh, L, false, cx.stream);
-  }
   x.release();
-  Buf pext = dev_buf(cx.pool, sext);
-  Buf pa = dev_buf(cx.pool, 2 * per);
+  ntt_ext_digits(cx, ext.p, level, 1);
   Buf u = dev_buf(cx.pool, 2 * (size_t)ne * N);
   Buf conv = dev_buf(cx.pool, 2 * per);
   for (long r : rs) {
@@ -859,9 +858,8 @@ std::vector<CtPtr> rotate_hoisted(Context& cx, const EvalKeys& evk, const Cipher
       continue;
     }
     const KsKey& key = galois_key(evk, g);
-    k_automorph(sh, a.buf.p, pa.p, 2 * nl, N, N, g, cx.stream);
-    k_automorph(sh, ext.p, pext.p, beta * ne, N, N, g, cx.stream);
-    k_ks_inner(sh, pa.p + per, pext.p, key.k.p, u.p, level, 1, 0, 0, 0, cx.stream);
+    k_ks_inner(sh, a.poly(1), ext.p, key.k.p, u.p, level, 1, 0, 0, 0, (uint32_t)g, (uint32_t)g,
+               cx.stream);
     NttLaunch L{};
     L.dst = u.p + per;
     L.src = L.dst;
@@ -874,7 +872,8 @@ std::vector<CtPtr> rotate_hoisted(Context& cx, const EvalKeys& evk, const Cipher
     k_moddown_conv(sh, u.p, conv.p, level, 1, 0, 0, cx.stream);
     ntt_ct_limbs(cx, conv.p, nl, 2, per, false);
     auto out = new_ct(cx, level, a.scale);
-    k_moddown_final(sh, u.p, conv.p, pa.p, nullptr, out->buf.p, level, 1, 0, 0, 0, 0, cx.stream);
+    k_moddown_final(sh, u.p, conv.p, a.poly(0), nullptr, out->buf.p, level, 1, 0, 0, 0, 0,
+                    (uint32_t)g, cx.stream);
     outs.push_back(out);
   }
   return outs;

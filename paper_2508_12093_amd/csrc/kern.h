@@ -21,6 +21,14 @@ struct NttLaunch {
   size_t dst_stride = ~(size_t)0;  // destination stride (default: batch_stride)
   int nq, pofs;
   int skip_lo = 1 << 30, skip_hi = 1 << 30;
+  // Digit mode (digit_alpha > 0): batch item b holds the extension of digit
+  // j = b % digit_count, whose own limbs [j alpha, min((j+1) alpha, nq)) are
+  // skipped; items have digit_total limbs and nlimbs must be the largest
+  // count of transformed limbs over the digits.
+  int digit_alpha = 0, digit_count = 1, digit_total = 0;
+  // inverse, out-of-place only: transform the input permuted by X -> X^galois
+  // (canonical NTT order); 0 for none
+  uint32_t galois = 0;
 };
 void ntt(const Shared& sh, const NttLaunch& L, bool inverse, hipStream_t st);
 
@@ -56,17 +64,21 @@ void k_modup(const Shared& sh, const u64* x, u64* ext, int level, int nbatch, si
 // Inner product with the key: for t in [0, ne) (ne = nl + K),
 //   u0_t = sum_j e_{j,t} b_{j,p(t)},  u1_t = sum_j e_{j,t} a_{j,p(t)},
 // e_{j,t} = d_t for t in digit j (NTT form input), ext[j][t] otherwise.
-// ext: [beta][ne][N] per batch item; u: [2][ne][N] per batch item.
+// ext: [beta][ne][N] per batch item; u: [2][ne][N] per batch item.  With
+// gd / gext nonzero, d / ext are read through X -> X^g (canonical NTT order).
 void k_ks_inner(const Shared& sh, const u64* d, const u64* ext, const u64* key, u64* u, int level,
-                int nbatch, size_t stride_d, size_t stride_ext, size_t stride_u, hipStream_t st);
+                int nbatch, size_t stride_d, size_t stride_ext, size_t stride_u, uint32_t gd,
+                uint32_t gext, hipStream_t st);
 // ModDown conversion: z = coefficient-form special limbs of u (u + nl*N, for
 // both polynomials); conv[c][i] = Conv_{P->q_i}(z + h) - h mod q_i.
 void k_moddown_conv(const Shared& sh, const u64* u, u64* conv, int level, int nbatch,
                     size_t stride_u, size_t stride_conv, hipStream_t st);
-// out[c][i] = (u[c][i] - conv[c][i]) P^-1 mod q_i (+ add[c][i] when add_c != null)
+// out[c][i] = (u[c][i] - conv[c][i]) P^-1 mod q_i (+ add[c][i] when add_c != null;
+// add is read through X -> X^gadd when gadd != 0)
 void k_moddown_final(const Shared& sh, const u64* u, const u64* conv, const u64* add0,
                      const u64* add1, u64* out, int level, int nbatch, size_t stride_u,
-                     size_t stride_conv, size_t stride_add, size_t stride_out, hipStream_t st);
+                     size_t stride_conv, size_t stride_add, size_t stride_out, uint32_t gadd,
+                     hipStream_t st);
 
 // --------------------------------------- ModDown and rescale in one pass
 // After the key-switch inner product u (NTT form, [2][ne][N]) of a product

@@ -92,18 +92,14 @@ __global__ void k_tensor_kernel(PtrBatch a, PtrBatch b, u64* d, const Mod* mods,
   d[2 * per + r] = mulm(a1, b1, m);
 }
 
-// slot j of the output reads slot j' with 2 brv(j') + 1 = (2 brv(j) + 1) g mod 2N
+// slot j of the output reads slot galois_src(j)
 __global__ void k_automorph_kernel(const u64* __restrict__ in, u64* out, int logN, int nrows,
-                                   size_t sin, size_t sout, u64 g) {
+                                   size_t sin, size_t sout, uint32_t g) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ((size_t)nrows << logN)) return;
   int row = (int)(i >> logN);
   uint32_t j = (uint32_t)(i & ((1u << logN) - 1));
-  uint32_t mask2 = (2u << logN) - 1;
-  uint32_t e = 2 * (__brev(j) >> (32 - logN)) + 1;
-  uint32_t e2 = (uint32_t)(((u64)e * g) & mask2);
-  uint32_t jp = __brev((e2 - 1) >> 1) >> (32 - logN);
-  out[row * sout + j] = in[row * sin + jp];
+  out[row * sout + j] = in[row * sin + galois_src(j, g, logN)];
 }
 
 // ----------------------------------------------------------- key switching
@@ -173,6 +169,7 @@ struct InnerArgs {
   const Mod* mods;
   size_t sd, sext, su;
   int logN, nl, ne, beta, alpha, pofs, nprimes, nbatch;
+  uint32_t gd, gext;  // read d / ext through X -> X^g (0: as stored)
 };
 
 constexpr int kInnerItems = 4;   // batch items per thread: one key load serves all
@@ -187,11 +184,13 @@ __global__ void __launch_bounds__(kBlock) k_ks_inner_kernel(InnerArgs a) {
   const int b0 = blockIdx.y * kInnerItems;
   const int nb = min(kInnerItems, a.nbatch - b0);
   const int own = t < a.nl ? t / a.alpha : -1;   // digit holding limb t
+  const size_t kd = galois_src((uint32_t)k, a.gd, a.logN);
+  const size_t kx = galois_src((uint32_t)k, a.gext, a.logN);
   Acc30 s0[kInnerItems], s1[kInnerItems];
   for (int j = 0; j < a.beta; ++j) {
     const Split30 kb(a.key[((size_t)(2 * j) * a.nprimes + p) * N + k]);
     const Split30 ka(a.key[((size_t)(2 * j + 1) * a.nprimes + p) * N + k]);
-    const u64* src = (j == own) ? a.d + (size_t)t * N + k : a.ext + ((size_t)j * a.ne + t) * N + k;
+    const u64* src = (j == own) ? a.d + (size_t)t * N + kd : a.ext + ((size_t)j * a.ne + t) * N + kx;
     const size_t stride = (j == own) ? a.sd : a.sext;
     u64 ev[kInnerItems];
 #pragma unroll
@@ -282,7 +281,7 @@ __global__ void k_moddown_final_kernel(const u64* __restrict__ u, const u64* __r
                                        const u64* add0, const u64* add1, u64* out,
                                        const Mod* mods, const u64* md, int K, int L, int logN,
                                        int nl, int ne, size_t su, size_t sc, size_t sa,
-                                       size_t so) {
+                                       size_t so, uint32_t gadd) {
   size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   size_t per = (size_t)nl << logN;
   if (r >= per) return;
@@ -295,7 +294,10 @@ __global__ void k_moddown_final_kernel(const u64* __restrict__ u, const u64* __r
   u64 y = conv[b * sc + (size_t)c * per + r];
   u64 v = mul_shoup(subm(x, y, q), md[lay.pinv(i)], md[lay.pinv(i) + 1], q);
   const u64* add = c ? add1 : add0;
-  if (add) v = addm(v, add[b * sa + r], q);
+  if (add) {
+    const size_t kk = galois_src((uint32_t)(r & (((size_t)1 << logN) - 1)), gadd, logN);
+    v = addm(v, add[b * sa + ((size_t)i << logN) + kk], q);
+  }
   out[b * so + (size_t)c * per + r] = v;
 }
 
@@ -622,9 +624,12 @@ void k_modup(const Shared& sh, const u64* x, u64* ext, int level, int nbatch, si
 }
 
 void k_ks_inner(const Shared& sh, const u64* d, const u64* ext, const u64* key, u64* u, int level,
-                int nbatch, size_t sd, size_t sext, size_t su, hipStream_t st) {
+                int nbatch, size_t sd, size_t sext, size_t su, uint32_t gd, uint32_t gext,
+                hipStream_t st) {
   const Params& P = sh.P;
   InnerArgs a;
+  a.gd = gd;
+  a.gext = gext;
   a.d = d;
   a.ext = ext;
   a.key = key;
@@ -674,14 +679,15 @@ void k_moddown_conv(const Shared& sh, const u64* u, u64* conv, int level, int nb
 
 void k_moddown_final(const Shared& sh, const u64* u, const u64* conv, const u64* add0,
                      const u64* add1, u64* out, int level, int nbatch, size_t su, size_t sc,
-                     size_t sa, size_t so, hipStream_t st) {
+                     size_t sa, size_t so, uint32_t gadd, hipStream_t st) {
   const Params& P = sh.P;
   int nl = level + 1;
   dim3 g = grid_for((size_t)nl * P.N);
   g.y = nbatch;
   g.z = 2;
   hipLaunchKernelGGL(k_moddown_final_kernel, g, dim3(kBlock), 0, st, u, conv, add0, add1, out,
-                     M(sh), sh.tab.moddown.p, P.K, P.L, P.logN, nl, nl + P.K, su, sc, sa, so);
+                     M(sh), sh.tab.moddown.p, P.K, P.L, P.logN, nl, nl + P.K, su, sc, sa, so,
+                     gadd);
   LAUNCH_CHECK();
 }
 

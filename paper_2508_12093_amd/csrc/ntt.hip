@@ -32,6 +32,8 @@ struct NttArgs {
   const u64* ninv;   // [nprimes][2]
   size_t batch_stride, dst_stride;
   int N, logN, logR, nq, pofs, skip_lo, skip_hi, blocks_per_limb;
+  int dalpha, dcount, dtotal;
+  uint32_t galois;   // inverse transforms: read the input through X -> X^galois (0: none)
 };
 
 // ----------------------------------------------------------------------
@@ -129,7 +131,7 @@ constexpr u64 kFpPrimeBound = 1ULL << 50;
 template <class A, int LOGM, int LOGE, int SB, bool ROWS, bool INV>
 __device__ __forceinline__ void ntt_body(const A ar, typename A::T* lds, const u64* src, u64* dst,
                                          const ulonglong2* tw, const u64* ninv2, int N, int logR,
-                                         int first, bool last) {
+                                         int first, bool last, uint32_t galois, int logN) {
   typedef typename A::T T;
   constexpr int M = 1 << LOGM;
   constexpr int E = 1 << LOGE;
@@ -142,7 +144,13 @@ __device__ __forceinline__ void ntt_body(const A ar, typename A::T* lds, const u
   const int tid = threadIdx.x;
 
   // ---- load SB sub-problems into LDS (coalesced along memory)
-  if (ROWS) {
+  if (ROWS && INV && galois != 0) {
+#pragma unroll 4
+    for (int idx = tid; idx < SB * M; idx += NT) {
+      int sp = idx / M, e = idx - sp * M;
+      lds[sp * PAD + e] = ar.in(src[galois_src((uint32_t)(first * M + idx), galois, logN)]);
+    }
+  } else if (ROWS) {
     const u64* g = src + (size_t)first * M;
 #pragma unroll 4
     for (int idx = tid; idx < SB * M; idx += NT) {
@@ -234,7 +242,13 @@ k_ntt_pass(NttArgs a) {
   const int N = a.N;
   const int limb_u = blockIdx.x / a.blocks_per_limb;
   const int grp = blockIdx.x - limb_u * a.blocks_per_limb;
-  const int t = limb_u >= a.skip_lo ? limb_u + (a.skip_hi - a.skip_lo) : limb_u;
+  int skip_lo = a.skip_lo, skip_hi = a.skip_hi;
+  if (a.dalpha > 0) {            // block-uniform: the whole workgroup leaves together
+    skip_lo = (int)(blockIdx.y % a.dcount) * a.dalpha;
+    skip_hi = min(skip_lo + a.dalpha, a.nq);
+    if (limb_u >= a.dtotal - (skip_hi - skip_lo)) return;
+  }
+  const int t = limb_u >= skip_lo ? limb_u + (skip_hi - skip_lo) : limb_u;
   const int prime = t < a.nq ? t : a.pofs + (t - a.nq);
   const u64* src = a.src + (size_t)blockIdx.y * a.batch_stride + (size_t)t * N;
   u64* dst = a.dst + (size_t)blockIdx.y * a.dst_stride + (size_t)t * N;
@@ -245,10 +259,10 @@ k_ntt_pass(NttArgs a) {
   const int first = grp * SB;        // first sub-problem of this workgroup
   if (q < kFpPrimeBound)
     ntt_body<FpArith, LOGM, LOGE, SB, ROWS, INV>(FpArith(q), (double*)lds, src, dst, tw, ni, N,
-                                                  a.logR, first, last);
+                                                  a.logR, first, last, a.galois, a.logN);
   else
     ntt_body<IntArith, LOGM, LOGE, SB, ROWS, INV>(IntArith(q), lds, src, dst, tw, ni, N, a.logR,
-                                                   first, last);
+                                                   first, last, a.galois, a.logN);
 }
 
 typedef void (*PassFn)(const NttArgs&, int, int, hipStream_t);
@@ -328,7 +342,17 @@ void ntt(const Shared& sh, const NttLaunch& L, bool inverse, hipStream_t st) {
   if (L.nlimbs <= 0 || L.nbatch <= 0) return;
   // every limb must map onto a prime of the table (the map is monotone in t)
   {
-    const int tmax = (L.nlimbs - 1) + ((L.nlimbs - 1) >= L.skip_lo ? (L.skip_hi - L.skip_lo) : 0);
+    int tmax = (L.nlimbs - 1) + ((L.nlimbs - 1) >= L.skip_lo ? (L.skip_hi - L.skip_lo) : 0);
+    if (L.digit_alpha > 0) {
+      int most = 0;
+      for (int j = 0; j < L.digit_count; ++j) {
+        const int lo = j * L.digit_alpha, hi = std::min(lo + L.digit_alpha, L.nq);
+        if (hi <= lo) PPST_THROW(ST_EINVAL, "NTT digit mode: empty digit");
+        most = std::max(most, L.digit_total - (hi - lo));
+      }
+      if (L.nlimbs != most) PPST_THROW(ST_EINVAL, "NTT digit mode: limb count mismatch");
+      tmax = L.digit_total - 1;
+    }
     const int pmax = tmax < L.nq ? tmax : L.pofs + (tmax - L.nq);
     const int pmin = 0 < L.nq ? 0 : L.pofs - L.nq;
     if (pmax >= P.nprimes || pmin < 0 || L.skip_hi < L.skip_lo)
@@ -346,6 +370,12 @@ void ntt(const Shared& sh, const NttLaunch& L, bool inverse, hipStream_t st) {
   a.pofs = L.pofs;
   a.skip_lo = L.skip_lo;
   a.skip_hi = L.skip_hi;
+  a.dalpha = L.digit_alpha;
+  a.dcount = L.digit_count;
+  a.dtotal = L.digit_total;
+  if (L.galois != 0 && (!inverse || L.src == L.dst || L.galois >= 2u * (uint32_t)P.N || !(L.galois & 1)))
+    PPST_THROW(ST_EINVAL, "NTT: a Galois read needs an out-of-place inverse transform and odd g < 2N");
+  a.galois = L.galois;
   launch_passes(sh, a, L, inverse, st);
   HIP_CHECK(hipGetLastError());
 }
@@ -375,6 +405,10 @@ void ntt_autotune(Shared& sh, hipStream_t st, u64* scratch, int max_limbs) {
       a.nq = 0;
       a.pofs = 0;
       a.skip_lo = a.skip_hi = 1 << 30;
+      a.dalpha = 0;
+      a.dcount = 1;
+      a.dtotal = 0;
+      a.galois = 0;
       a.src = scratch;
       a.dst = scratch;
       a.batch_stride = a.dst_stride = (size_t)nlc * P.N;
