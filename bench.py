@@ -145,6 +145,9 @@ def main():
     ho_t = timed(lambda: [ffi.ppst_rotate_hoisted(ctx, evk, cts[i], hoist_steps) for i in range(nh)], 1)
     ho_s = nh * len(hoist_steps) / ho_t
     log("hoisted rotations: %.0f /s" % ho_s)
+    hb_t = timed(lambda: ffi.ppst_rotate_hoisted_batch(ctx, evk, cts, hoist_steps), 1)
+    hb_s = B * len(hoist_steps) / hb_t
+    log("batched hoisted rotations (%d x %d): %.0f /s" % (B, len(hoist_steps), hb_s))
 
     # --------------------------------------------- Pearson latency (config 2)
     x, y = synth.binary_cost_pair(0)
@@ -191,6 +194,7 @@ def main():
         "rotations_per_s": round(rot_s, 2),
         "hmult_batched_per_s": round(bm_s, 2),
         "rotations_hoisted_per_s": round(ho_s, 2),
+        "rotations_hoisted_batched_per_s": round(hb_s, 2),
         "pearson_p50_ms": round(float(np.percentile(lat, 50)), 3),
         "pearson_p99_ms": round(float(np.percentile(lat, 99)), 3),
         "pearson_runs": len(lat),

@@ -215,6 +215,15 @@ int ppst_rotate(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciphert
  * digits); a different but equally valid key switch than ppst_rotate */
 int ppst_rotate_hoisted(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciphertext* a,
                         const int32_t* rs, size_t n, ppst_ciphertext** outs);
+/* ppst_rotate_hoisted over n ciphertexts of one level: all ModUps first, then
+ * each rotation over the whole batch, so a Galois key is read once per group
+ * of ciphertexts.  outs[i * m + k] = rotation of cts[i] by rs[k], bit-identical
+ * to ppst_rotate_hoisted(cts[i], rs).  Device memory: about
+ * n (beta (l+1+K) + 2 (l+1+K) + 2 (l+1)) limbs of scratch besides the n m
+ * outputs (beta = ceil((l+1)/alpha) digits). */
+int ppst_rotate_hoisted_batch(ppst_context* ctx, const ppst_eval_keys* evk,
+                              const ppst_ciphertext* const* cts, size_t n, const int32_t* rs,
+                              size_t m, ppst_ciphertext** outs);
 /* rotate-and-sum: for k = 0..log2(N/2)-1, ct += rot(ct, 2^k); every slot then
  * holds the sum of all slots (the sums of Eq. 2, Sec. 5.1) */
 int ppst_rotsum(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciphertext* a,

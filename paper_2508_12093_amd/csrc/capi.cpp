@@ -593,6 +593,24 @@ int ppst_rotate_hoisted(ppst_context* ctx, const ppst_eval_keys* evk, const ppst
     for (size_t i = 0; i < n; ++i) outs[i] = wrap(v[i]);
   });
 }
+int ppst_rotate_hoisted_batch(ppst_context* ctx, const ppst_eval_keys* evk,
+                              const ppst_ciphertext* const* cts, size_t n, const int32_t* rs,
+                              size_t m, ppst_ciphertext** outs) {
+  return guard([&] {
+    NEED(ctx); NEED(evk);
+    if (n) NEED(cts);
+    if (m) NEED(rs);
+    if (n && m) NEED(outs);
+    std::vector<const Ciphertext*> v;
+    for (size_t i = 0; i < n; ++i) {
+      NEED(cts[i]);
+      v.push_back(cts[i]->c.get());
+    }
+    std::vector<long> r(rs, rs + m);
+    auto o = rotate_hoisted_batch(*ctx->cx, evk->e, v, r);
+    for (size_t i = 0; i < o.size(); ++i) outs[i] = wrap(o[i]);
+  });
+}
 int ppst_rotsum(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciphertext* a,
                 ppst_ciphertext** out) {
   return guard([&] {

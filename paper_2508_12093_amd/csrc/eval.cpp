@@ -879,6 +879,91 @@ std::vector<CtPtr> rotate_hoisted(Context& cx, const EvalKeys& evk, const Cipher
   return outs;
 }
 
+std::vector<CtPtr> rotate_hoisted_batch(Context& cx, const EvalKeys& evk,
+                                        const std::vector<const Ciphertext*>& cts,
+                                        const std::vector<long>& rs) {
+  const size_t n = cts.size(), m = rs.size();
+  if (n == 0 || m == 0) return {};
+  const Params& P = cx.P();
+  const Shared& sh = *cx.sh;
+  const int level = cts[0]->level;
+  for (const Ciphertext* c : cts) {
+    if (c->npoly != 2) PPST_THROW(ST_EINVAL, "rotation expects a degree-1 ciphertext");
+    if (c->level != level) PPST_THROW(ST_ESCALE, "batch members at different levels");
+  }
+  const int N = P.N, nl = level + 1, K = P.K, ne = nl + K, beta = P.beta(level);
+  const size_t per = (size_t)nl * N, sext = (size_t)beta * ne * N;
+  std::vector<const KsKey*> keys(m, nullptr);
+  std::vector<u64> gs(m);
+  for (size_t r = 0; r < m; ++r) {
+    gs[r] = galois_elt(P, rs[r]);
+    if (gs[r] != 1) keys[r] = &galois_key(evk, gs[r]);
+  }
+  std::vector<CtPtr> outs(n * m);
+  // ModUp of every c1, with each digit's own limbs copied in beside the
+  // extension so that the inner product reads one buffer
+  Buf ext = dev_buf(cx.pool, sext * n);
+  {
+    Buf x = dev_buf(cx.pool, per);
+    for (size_t i = 0; i < n; ++i) {
+      NttLaunch L{};
+      L.src = cts[i]->poly(1);
+      L.dst = x.p;
+      L.nlimbs = nl;
+      L.nq = nl;
+      L.pofs = P.L + 1;
+      ntt(sh, L, true, cx.stream);
+      u64* ei = ext.p + sext * i;
+      k_modup(sh, x.p, ei, level, 1, per, sext, cx.stream);
+      for (int j = 0; j < beta; ++j) {
+        const int lo = P.digit_lo(j), hi = P.digit_hi(j, level);
+        HIP_CHECK(hipMemcpyAsync(ei + ((size_t)j * ne + lo) * N, cts[i]->poly(1) + (size_t)lo * N,
+                                 (size_t)(hi - lo) * N * 8, hipMemcpyDeviceToDevice, cx.stream));
+      }
+    }
+    ntt_ext_digits(cx, ext.p, level, (int)n);   // the copied own limbs are skipped
+  }
+  // one rotation at a time over chunks of the batch: the key is read once
+  // per group of items of the inner product
+  const int chunk = (int)std::min<size_t>(n, kPtrBatch);
+  const size_t su = 2 * (size_t)ne * N, sc = 2 * per;
+  Buf u = dev_buf(cx.pool, su * chunk);
+  Buf conv = dev_buf(cx.pool, sc * chunk);
+  for (size_t r = 0; r < m; ++r) {
+    if (gs[r] == 1) {
+      for (size_t i = 0; i < n; ++i) outs[i * m + r] = copy_ct(cx, *cts[i]);
+      continue;
+    }
+    const uint32_t g = (uint32_t)gs[r];
+    for (size_t b0 = 0; b0 < n; b0 += chunk) {
+      const int nb = (int)std::min<size_t>(chunk, n - b0);
+      k_ks_inner(sh, nullptr, ext.p + sext * b0, keys[r]->k.p, u.p, level, nb, 0, sext, su, g, g,
+                 cx.stream);
+      NttLaunch L{};
+      L.dst = u.p + per;
+      L.src = L.dst;
+      L.nlimbs = K;
+      L.nbatch = 2 * nb;
+      L.batch_stride = (size_t)ne * N;
+      L.nq = 0;
+      L.pofs = P.L + 1;
+      ntt(sh, L, true, cx.stream);
+      k_moddown_conv(sh, u.p, conv.p, level, nb, su, sc, cx.stream);
+      ntt_ct_limbs(cx, conv.p, nl, 2 * nb, per, false);
+      std::vector<const u64*> add(nb);
+      std::vector<u64*> po(nb);
+      for (int i = 0; i < nb; ++i) {
+        auto o = new_ct(cx, level, cts[b0 + i]->scale);
+        add[i] = cts[b0 + i]->poly(0);
+        po[i] = o->buf.p;
+        outs[(b0 + i) * m + r] = o;
+      }
+      k_moddown_final_ptr(sh, u.p, conv.p, add.data(), po.data(), level, nb, su, sc, g, cx.stream);
+    }
+  }
+  return outs;
+}
+
 CtPtr rotsum(Context& cx, const EvalKeys& evk, const Ciphertext& a) {
   CtPtr ct = copy_ct(cx, a);
   for (int k = 0; (1 << k) < cx.P().slots(); ++k) {

@@ -51,6 +51,11 @@ CtPtr mul(Context& cx, const EvalKeys& evk, const Ciphertext& a, const Ciphertex
 CtPtr rotate(Context& cx, const EvalKeys& evk, const Ciphertext& a, long r);
 std::vector<CtPtr> rotate_hoisted(Context& cx, const EvalKeys& evk, const Ciphertext& a,
                                   const std::vector<long>& rs);
+// rotate_hoisted for many ciphertexts of one level: every ModUp first, then
+// each rotation over the whole batch (outputs ordered [ciphertext][rotation])
+std::vector<CtPtr> rotate_hoisted_batch(Context& cx, const EvalKeys& evk,
+                                        const std::vector<const Ciphertext*>& cts,
+                                        const std::vector<long>& rs);
 CtPtr rotsum(Context& cx, const EvalKeys& evk, const Ciphertext& a);
 CtPtr level_align(Context& cx, const Ciphertext& a, int level);
 CtPtr copy_ct(Context& cx, const Ciphertext& a);

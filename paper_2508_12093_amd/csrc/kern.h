@@ -63,7 +63,8 @@ void k_modup(const Shared& sh, const u64* x, u64* ext, int level, int nbatch, si
              size_t stride_ext, hipStream_t st);
 // Inner product with the key: for t in [0, ne) (ne = nl + K),
 //   u0_t = sum_j e_{j,t} b_{j,p(t)},  u1_t = sum_j e_{j,t} a_{j,p(t)},
-// e_{j,t} = d_t for t in digit j (NTT form input), ext[j][t] otherwise.
+// e_{j,t} = d_t for t in digit j (NTT form input), ext[j][t] otherwise (also
+// for t in digit j when d is null).
 // ext: [beta][ne][N] per batch item; u: [2][ne][N] per batch item.  With
 // gd / gext nonzero, d / ext are read through X -> X^g (canonical NTT order).
 void k_ks_inner(const Shared& sh, const u64* d, const u64* ext, const u64* key, u64* u, int level,
@@ -100,6 +101,12 @@ void k_mdr_corr(const Shared& sh, const u64* u, u64* corr, int level, int nbatch
 void k_mdr_final(const Shared& sh, const u64* u, const u64* d, const u64* corr,
                  u64* const* out, int level, int nbatch, size_t su, size_t sd, size_t sc,
                  hipStream_t st);
+
+// k_moddown_final for nbatch items with the addend (c0 only) and the output
+// given as host arrays of device pointers ([nl][N] and [2][nl][N])
+void k_moddown_final_ptr(const Shared& sh, const u64* u, const u64* conv,
+                         const u64* const* add0, u64* const* out, int level, int nbatch,
+                         size_t stride_u, size_t stride_conv, uint32_t gadd, hipStream_t st);
 
 // ------------------------------------------------------------ rescale
 // top: coefficient-form top limb of each of npoly polynomials (stride

@@ -172,9 +172,10 @@ struct InnerArgs {
   uint32_t gd, gext;  // read d / ext through X -> X^g (0: as stored)
 };
 
-constexpr int kInnerItems = 4;   // batch items per thread: one key load serves all
-
+// ITEMS batch items per thread: one key load serves all of them
+template <int ITEMS>
 __global__ void __launch_bounds__(kBlock) k_ks_inner_kernel(InnerArgs a) {
+  constexpr int kInnerItems = ITEMS;
   const size_t N = (size_t)1 << a.logN;
   size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= (size_t)a.ne * N) return;
@@ -183,7 +184,8 @@ __global__ void __launch_bounds__(kBlock) k_ks_inner_kernel(InnerArgs a) {
   const int p = t < a.nl ? t : a.pofs + (t - a.nl);
   const int b0 = blockIdx.y * kInnerItems;
   const int nb = min(kInnerItems, a.nbatch - b0);
-  const int own = t < a.nl ? t / a.alpha : -1;   // digit holding limb t
+  // digit holding limb t; with d == null the digits' own limbs are read from ext too
+  const int own = (a.d != nullptr && t < a.nl) ? t / a.alpha : -1;
   const size_t kd = galois_src((uint32_t)k, a.gd, a.logN);
   const size_t kx = galois_src((uint32_t)k, a.gext, a.logN);
   Acc30 s0[kInnerItems], s1[kInnerItems];
@@ -299,6 +301,31 @@ __global__ void k_moddown_final_kernel(const u64* __restrict__ u, const u64* __r
     v = addm(v, add[b * sa + ((size_t)i << logN) + kk], q);
   }
   out[b * so + (size_t)c * per + r] = v;
+}
+
+// k_moddown_final over batch items whose addend and output ciphertexts are
+// separate allocations: out_b[c][i] = (u - conv) P^-1 + add_b[c][i] read
+// through X -> X^gadd
+__global__ void k_moddown_final_ptr_kernel(const u64* __restrict__ u, const u64* __restrict__ conv,
+                                           PtrBatch add, OutBatch out, const Mod* mods,
+                                           const u64* md, int K, int L, int logN, int nl, int ne,
+                                           size_t su, size_t sc, uint32_t gadd) {
+  size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t per = (size_t)nl << logN;
+  if (r >= per) return;
+  const int c = blockIdx.z;
+  const int b = blockIdx.y;
+  const int i = (int)(r >> logN);
+  const u64 q = mods[i].q;
+  const MdLayout lay(K, L);
+  u64 x = u[b * su + (size_t)c * ((size_t)ne << logN) + r];
+  u64 y = conv[b * sc + (size_t)c * per + r];
+  u64 v = mul_shoup(subm(x, y, q), md[lay.pinv(i)], md[lay.pinv(i) + 1], q);
+  if (c == 0) {
+    const size_t kk = galois_src((uint32_t)(r & (((size_t)1 << logN) - 1)), gadd, logN);
+    v = addm(v, add.p[b][((size_t)i << logN) + kk], q);
+  }
+  out.p[b][(size_t)c * per + r] = v;
 }
 
 // ------------------------------------------- ModDown and rescale together
@@ -647,8 +674,16 @@ void k_ks_inner(const Shared& sh, const u64* d, const u64* ext, const u64* key, 
   a.nprimes = P.nprimes;
   a.nbatch = nbatch;
   dim3 g = grid_for((size_t)a.ne * P.N);
-  g.y = (nbatch + kInnerItems - 1) / kInnerItems;
-  hipLaunchKernelGGL(k_ks_inner_kernel, g, dim3(kBlock), 0, st, a);
+  if (nbatch >= 4) {
+    g.y = (nbatch + 3) / 4;
+    hipLaunchKernelGGL(k_ks_inner_kernel<4>, g, dim3(kBlock), 0, st, a);
+  } else if (nbatch >= 2) {
+    g.y = (nbatch + 1) / 2;
+    hipLaunchKernelGGL(k_ks_inner_kernel<2>, g, dim3(kBlock), 0, st, a);
+  } else {
+    g.y = nbatch;
+    hipLaunchKernelGGL(k_ks_inner_kernel<1>, g, dim3(kBlock), 0, st, a);
+  }
   LAUNCH_CHECK();
 }
 
@@ -689,6 +724,29 @@ void k_moddown_final(const Shared& sh, const u64* u, const u64* conv, const u64*
                      M(sh), sh.tab.moddown.p, P.K, P.L, P.logN, nl, nl + P.K, su, sc, sa, so,
                      gadd);
   LAUNCH_CHECK();
+}
+
+void k_moddown_final_ptr(const Shared& sh, const u64* u, const u64* conv,
+                         const u64* const* add0, u64* const* out, int level, int nbatch,
+                         size_t su, size_t sc, uint32_t gadd, hipStream_t st) {
+  const Params& P = sh.P;
+  const int nl = level + 1;
+  for (int b0 = 0; b0 < nbatch; b0 += kPtrBatch) {
+    const int nb = std::min(kPtrBatch, nbatch - b0);
+    PtrBatch pa{};
+    OutBatch po{};
+    for (int i = 0; i < nb; ++i) {
+      pa.p[i] = add0[b0 + i];
+      po.p[i] = out[b0 + i];
+    }
+    dim3 g = grid_for((size_t)nl * P.N);
+    g.y = nb;
+    g.z = 2;
+    hipLaunchKernelGGL(k_moddown_final_ptr_kernel, g, dim3(kBlock), 0, st, u + (size_t)b0 * su,
+                       conv + (size_t)b0 * sc, pa, po, M(sh), sh.tab.moddown.p, P.K, P.L, P.logN,
+                       nl, nl + P.K, su, sc, gadd);
+    LAUNCH_CHECK();
+  }
 }
 
 void k_mdr_prep(const Shared& sh, u64* u, const u64* d, int level, int nbatch, size_t su,

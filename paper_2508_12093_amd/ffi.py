@@ -126,6 +126,7 @@ _SIGS = {
     "ppst_rotsum": (ctypes.c_int, [_vp, _vp, _vp, _pp]),
     "ppst_level_align": (ctypes.c_int, [_vp, _vp, _i32, _pp]),
     "ppst_mul_batch": (ctypes.c_int, [_vp, _vp, _pp, _pp, _sz, _pp]),
+    "ppst_rotate_hoisted_batch": (ctypes.c_int, [_vp, _vp, _pp, _sz, _vp, _sz, _pp]),
     "ppst_invsqrt_cfg_default": (ctypes.c_int, [_cfgp]),
     "ppst_stat_mean": (ctypes.c_int, [_vp, _vp, _pp, _sz, _sz, _dbl, _pp]),
     "ppst_stat_variance": (ctypes.c_int, [_vp, _vp, _pp, _sz, _sz, _dbl, _pp]),
@@ -503,6 +504,16 @@ def ppst_mul_batch(ctx, evk, a, b):
     outs = (ctypes.c_void_p * len(a))()
     _chk(lib().ppst_mul_batch(ctx, evk, _ptrs(a), _ptrs(b), len(a), outs))
     return [Ciphertext(outs[i], ctx) for i in range(len(a))]
+
+
+def ppst_rotate_hoisted_batch(ctx, evk, cts, steps):
+    """Rotations of every ciphertext by every step; result[i][k] = cts[i]
+    rotated by steps[k]."""
+    s = np.ascontiguousarray(steps, dtype=np.int32)
+    n, m = len(cts), len(s)
+    outs = (ctypes.c_void_p * max(1, n * m))()
+    _chk(lib().ppst_rotate_hoisted_batch(ctx, evk, _ptrs(cts), n, _p(s), m, outs))
+    return [[Ciphertext(outs[i * m + k], ctx) for k in range(m)] for i in range(n)]
 
 
 def ppst_invsqrt_cfg_default(coeffs=None, **kw) -> InvSqrtCfg:

@@ -190,6 +190,22 @@ def test_mul_batch_equals_single(pair):
         assert np.array_equal(ffi.ppst_ct_export(p.ctx, o), ffi.ppst_ct_export(p.ctx, single))
 
 
+def test_rotate_hoisted_batch_equals_single(pair):
+    """Batched hoisted rotations equal the one-ciphertext hoisted form bit for
+    bit (which the oracle pins in test_rotations), for every ciphertext and
+    step, including a step that is the identity."""
+    p = pair
+    cts = [p.encrypt(synth.uniform_column(90 + i, p.P.slots, -1, 1), 90 + i)[0] for i in range(5)]
+    steps = list(p.steps) + [p.P.slots]
+    outs = ffi.ppst_rotate_hoisted_batch(p.ctx, p.evk, cts, steps)
+    assert len(outs) == len(cts) and all(len(o) == len(steps) for o in outs)
+    for ct, row in zip(cts, outs):
+        single = ffi.ppst_rotate_hoisted(p.ctx, p.evk, ct, steps)
+        for o, s1 in zip(row, single):
+            assert np.array_equal(ffi.ppst_ct_export(p.ctx, o), ffi.ppst_ct_export(p.ctx, s1))
+    assert ffi.ppst_rotate_hoisted_batch(p.ctx, p.evk, [], steps) == []
+
+
 def test_error_statuses(pair):
     p = pair
     m = synth.uniform_column(12, 16, 0, 1)
