@@ -141,6 +141,23 @@ def main():
     bm_t = timed(lambda: ffi.ppst_mul_batch(ctx, evk, cts, cts[1:] + cts[:1]), max(1, args.steps // 2))
     bm_s = B / bm_t
     log("batched HMult: %.0f /s" % bm_s)
+
+    # the same two steps recorded once into HIP graphs and replayed
+    def record(fn):
+        ffi.ppst_graph_begin(ctx)
+        try:
+            outs = fn()
+        finally:
+            g = ffi.ppst_graph_end(ctx)
+        return g, outs
+
+    g_plain, keep_p = record(step_mul)
+    gp_t = timed(g_plain.launch, max(1, args.steps // 2))
+    g_batch, keep_b = record(lambda: ffi.ppst_mul_batch(ctx, evk, cts, cts[1:] + cts[:1]))
+    gb_t = timed(g_batch.launch, max(1, args.steps // 2))
+    gp_s, gb_s = B / gp_t, B / gb_t
+    log("graph-replayed HMult: plain %.0f /s, batched %.0f /s" % (gp_s, gb_s))
+    del g_plain, g_batch, keep_p, keep_b
     nh = min(B, 8)
     ho_t = timed(lambda: [ffi.ppst_rotate_hoisted(ctx, evk, cts[i], hoist_steps) for i in range(nh)], 1)
     ho_s = nh * len(hoist_steps) / ho_t
@@ -193,6 +210,8 @@ def main():
         },
         "rotations_per_s": round(rot_s, 2),
         "hmult_batched_per_s": round(bm_s, 2),
+        "hmult_graph_per_s": round(gp_s, 2),
+        "hmult_batched_graph_per_s": round(gb_s, 2),
         "rotations_hoisted_per_s": round(ho_s, 2),
         "rotations_hoisted_batched_per_s": round(hb_s, 2),
         "pearson_p50_ms": round(float(np.percentile(lat, 50)), 3),

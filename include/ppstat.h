@@ -237,6 +237,28 @@ int ppst_level_align(ppst_context* ctx, const ppst_ciphertext* a, int32_t level,
 int ppst_mul_batch(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciphertext* const* a,
                    const ppst_ciphertext* const* b, size_t n, ppst_ciphertext** outs);
 
+/* ----------------------------------------------------------------- graphs */
+/* Recording of evaluation work into a HIP graph (stream capture on the
+ * context's stream), for callers that replay a fixed sequence many times.
+ * Between ppst_graph_begin and ppst_graph_end the evaluation calls (add, sub,
+ * add_const, mul_const, mul_int, mul_plain, mul, tensor, relin, rescale,
+ * rotate, rotate_hoisted(_batch), rotsum, level_align, mul_batch) are
+ * recorded, not run: their output handles are valid at once, and each
+ * ppst_graph_launch writes them again.  Calls that wait for the device or
+ * move data to or from the host (keygen, encode, encrypt, decrypt, exports,
+ * imports, statistics, ppst_sync, context create/fork/destroy) fail with
+ * PPST_EINVAL while a recording is open.  Device memory handed out while
+ * recording is owned by the graph until ppst_graph_destroy, so releasing a
+ * recorded output early is safe; the recorded inputs must stay alive for as
+ * long as the graph is launched.  Launches are asynchronous on the
+ * context's stream; ppst_graph_destroy waits for them and must come before
+ * the context's destruction. */
+typedef struct ppst_graph ppst_graph;
+int ppst_graph_begin(ppst_context* ctx);
+int ppst_graph_end(ppst_context* ctx, ppst_graph** out);
+int ppst_graph_launch(ppst_graph* g);
+int ppst_graph_destroy(ppst_graph* g);
+
 /* ------------------------------------------------------------- statistics */
 /* CryptoInvSqrt configuration (Sec. 4, Alg. 2-3; Sec. 5.1, Eq. 3): Chebyshev
  * initial value of degree `degree` for 1/sqrt(B' v) on [a, b] (first-kind

@@ -28,6 +28,9 @@ struct ppst_ciphertext {
 struct ppst_server {
   std::unique_ptr<Server> s;
 };
+struct ppst_graph {
+  std::unique_ptr<Graph> g;
+};
 
 namespace {
 
@@ -56,6 +59,14 @@ int guard(F&& f) {
   } while (0)
 
 ppst_ciphertext* wrap(CtPtr c) { return new ppst_ciphertext{std::move(c)}; }
+
+// calls that wait for the device or move data to or from the host cannot be
+// recorded into a graph
+#define NOT_RECORDING(ctx)                                                       \
+  do {                                                                           \
+    if ((ctx)->cx->recording)                                                    \
+      PPST_THROW(ST_EINVAL, "not allowed while a graph recording is open");      \
+  } while (0)
 
 std::vector<CtPtr> column(const ppst_ciphertext* const* col, size_t nct) {
   NEED(col);
@@ -177,6 +188,7 @@ int ppst_context_create(const ppst_params* params, const ppst_device_hooks* hook
 int ppst_context_fork(const ppst_context* base, void* stream, ppst_context** out) {
   return guard([&] {
     NEED(base);
+    NOT_RECORDING(base);
     NEED(out);
     *out = new ppst_context{make_context(base->cx->sh, (hipStream_t)stream)};
   });
@@ -185,6 +197,7 @@ int ppst_context_fork(const ppst_context* base, void* stream, ppst_context** out
 int ppst_context_destroy(ppst_context* ctx) {
   return guard([&] {
     if (!ctx) return;
+    NOT_RECORDING(ctx);
     destroy_context(ctx->cx.get());
     delete ctx;
   });
@@ -193,6 +206,7 @@ int ppst_context_destroy(ppst_context* ctx) {
 int ppst_sync(ppst_context* ctx) {
   return guard([&] {
     NEED(ctx);
+    NOT_RECORDING(ctx);
     HIP_CHECK(hipStreamSynchronize(ctx->cx->stream));
   });
 }
@@ -254,6 +268,7 @@ int ppst_context_stream(const ppst_context* ctx, void** stream) {
 int ppst_keygen(ppst_context* ctx, uint64_t seed, ppst_secret_key** sk, ppst_public_key** pk) {
   return guard([&] {
     NEED(ctx);
+    NOT_RECORDING(ctx);
     NEED(sk);
     NEED(pk);
     auto s = keygen_secret(*ctx->cx, seed);
@@ -299,6 +314,7 @@ int ppst_evk_add_relin(ppst_context* ctx, const ppst_secret_key* sk, uint64_t se
                        ppst_eval_keys* evk) {
   return guard([&] {
     NEED(ctx);
+    NOT_RECORDING(ctx);
     NEED(sk);
     NEED(evk);
     evk->e.relin = keygen_relin(*ctx->cx, *sk->k, seed);
@@ -309,6 +325,7 @@ int ppst_evk_add_galois(ppst_context* ctx, const ppst_secret_key* sk, const int3
                         size_t n, uint64_t seed, ppst_eval_keys* evk) {
   return guard([&] {
     NEED(ctx);
+    NOT_RECORDING(ctx);
     NEED(sk);
     NEED(evk);
     if (n) NEED(steps);
@@ -325,6 +342,7 @@ int ppst_evk_add_rotsum(ppst_context* ctx, const ppst_secret_key* sk, uint64_t s
                         ppst_eval_keys* evk) {
   return guard([&] {
     NEED(ctx);
+    NOT_RECORDING(ctx);
     NEED(sk);
     NEED(evk);
     const Params& P = ctx->cx->P();
@@ -339,6 +357,7 @@ int ppst_evk_export(ppst_context* ctx, const ppst_eval_keys* evk, uint64_t galoi
                     size_t cap_words) {
   return guard([&] {
     NEED(ctx);
+    NOT_RECORDING(ctx);
     NEED(evk);
     const Params& P = ctx->cx->P();
     const KsKey* k = nullptr;
@@ -357,6 +376,7 @@ int ppst_evk_export(ppst_context* ctx, const ppst_eval_keys* evk, uint64_t galoi
 int ppst_pk_export(ppst_context* ctx, const ppst_public_key* pk, uint64_t* host, size_t cap_words) {
   return guard([&] {
     NEED(ctx);
+    NOT_RECORDING(ctx);
     NEED(pk);
     const Params& P = ctx->cx->P();
     copy_out(*ctx->cx, pk->k->pk.p, 2 * (size_t)(P.L + 1) * P.N, host, cap_words);
@@ -366,6 +386,7 @@ int ppst_pk_export(ppst_context* ctx, const ppst_public_key* pk, uint64_t* host,
 int ppst_sk_export(ppst_context* ctx, const ppst_secret_key* sk, uint64_t* host, size_t cap_words) {
   return guard([&] {
     NEED(ctx);
+    NOT_RECORDING(ctx);
     NEED(sk);
     const Params& P = ctx->cx->P();
     copy_out(*ctx->cx, sk->k->s_ntt.p, (size_t)P.nprimes * P.N, host, cap_words);
@@ -377,6 +398,7 @@ int ppst_encode(ppst_context* ctx, const double* values, size_t n, int32_t level
                 ppst_plaintext** out) {
   return guard([&] {
     NEED(ctx);
+    NOT_RECORDING(ctx);
     NEED(out);
     if (n) NEED(values);
     *out = new ppst_plaintext{encode(*ctx->cx, values, n, level)};
@@ -387,6 +409,7 @@ int ppst_plaintext_from_coeffs(ppst_context* ctx, const int64_t* coeffs, int32_t
                                double scale, ppst_plaintext** out) {
   return guard([&] {
     NEED(ctx);
+    NOT_RECORDING(ctx);
     NEED(coeffs);
     NEED(out);
     *out = new ppst_plaintext{plaintext_from_coeffs(*ctx->cx, coeffs, level, scale)};
@@ -407,6 +430,7 @@ int ppst_plaintext_export(ppst_context* ctx, const ppst_plaintext* pt, uint64_t*
                           size_t cap_words) {
   return guard([&] {
     NEED(ctx);
+    NOT_RECORDING(ctx);
     NEED(pt);
     copy_out(*ctx->cx, pt->p->buf.p, (size_t)(pt->p->level + 1) * ctx->cx->P().N, host, cap_words);
   });
@@ -415,6 +439,7 @@ int ppst_plaintext_export(ppst_context* ctx, const ppst_plaintext* pt, uint64_t*
 int ppst_decode(ppst_context* ctx, const ppst_plaintext* pt, double* out, size_t n) {
   return guard([&] {
     NEED(ctx);
+    NOT_RECORDING(ctx);
     NEED(pt);
     if (n) NEED(out);
     decode(*ctx->cx, *pt->p, out, n);
@@ -430,6 +455,7 @@ int ppst_encrypt(ppst_context* ctx, const ppst_public_key* pk, const ppst_plaint
                  uint64_t seed, ppst_ciphertext** out) {
   return guard([&] {
     NEED(ctx);
+    NOT_RECORDING(ctx);
     NEED(pk);
     NEED(pt);
     NEED(out);
@@ -441,6 +467,7 @@ int ppst_encrypt_sk(ppst_context* ctx, const ppst_secret_key* sk, const ppst_pla
                     uint64_t seed, ppst_ciphertext** out) {
   return guard([&] {
     NEED(ctx);
+    NOT_RECORDING(ctx);
     NEED(sk);
     NEED(pt);
     NEED(out);
@@ -452,6 +479,7 @@ int ppst_decrypt(ppst_context* ctx, const ppst_secret_key* sk, const ppst_cipher
                  ppst_plaintext** out) {
   return guard([&] {
     NEED(ctx);
+    NOT_RECORDING(ctx);
     NEED(sk);
     NEED(ct);
     NEED(out);
@@ -475,6 +503,7 @@ int ppst_ct_info(const ppst_ciphertext* ct, int32_t* level, double* scale, int32
 int ppst_ct_export(ppst_context* ctx, const ppst_ciphertext* ct, uint64_t* host, size_t cap_words) {
   return guard([&] {
     NEED(ctx);
+    NOT_RECORDING(ctx);
     NEED(ct);
     const Ciphertext& c = *ct->c;
     copy_out(*ctx->cx, c.buf.p, (size_t)c.npoly * (c.level + 1) * c.N, host, cap_words);
@@ -485,6 +514,7 @@ int ppst_ct_import(ppst_context* ctx, const uint64_t* host, int32_t level, doubl
                    int32_t npoly, ppst_ciphertext** out) {
   return guard([&] {
     NEED(ctx);
+    NOT_RECORDING(ctx);
     NEED(host);
     NEED(out);
     const Params& P = ctx->cx->P();
@@ -635,6 +665,29 @@ int ppst_mul_batch(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciph
 }
 
 // ----------------------------------------------------------- statistics
+// ---------------------------------------------------------------- graphs
+int ppst_graph_begin(ppst_context* ctx) {
+  return guard([&] {
+    NEED(ctx);
+    graph_begin(*ctx->cx);
+  });
+}
+int ppst_graph_end(ppst_context* ctx, ppst_graph** out) {
+  return guard([&] {
+    NEED(ctx); NEED(out);
+    *out = new ppst_graph{graph_end(*ctx->cx)};
+  });
+}
+int ppst_graph_launch(ppst_graph* g) {
+  return guard([&] {
+    NEED(g);
+    graph_launch(*g->g);
+  });
+}
+int ppst_graph_destroy(ppst_graph* g) {
+  return guard([&] { delete g; });
+}
+
 int ppst_invsqrt_cfg_default(ppst_invsqrt_cfg* out) {
   return guard([&] {
     NEED(out);
@@ -651,6 +704,7 @@ int ppst_stat_mean(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciph
                    size_t nct, size_t nrows, double B, ppst_ciphertext** out) {
   return guard([&] {
     NEED(ctx); NEED(evk); NEED(out);
+    NOT_RECORDING(ctx);
     *out = wrap(stat_mean(*ctx->cx, evk->e, column(col, nct), nrows, B));
   });
 }
@@ -659,6 +713,7 @@ int ppst_stat_variance(ppst_context* ctx, const ppst_eval_keys* evk,
                        ppst_ciphertext** out) {
   return guard([&] {
     NEED(ctx); NEED(evk); NEED(out);
+    NOT_RECORDING(ctx);
     *out = wrap(stat_variance(*ctx->cx, evk->e, column(col, nct), nrows, B));
   });
 }
@@ -667,6 +722,7 @@ int ppst_stat_zscore(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ci
                      ppst_ciphertext** outs) {
   return guard([&] {
     NEED(ctx); NEED(evk); NEED(outs);
+    NOT_RECORDING(ctx);
     auto v = stat_zscore(*ctx->cx, evk->e, column(col, nct), nrows, B, cfg_from(cfg));
     for (size_t i = 0; i < v.size(); ++i) outs[i] = wrap(v[i]);
   });
@@ -676,6 +732,7 @@ int ppst_stat_kurtosis(ppst_context* ctx, const ppst_eval_keys* evk,
                        const ppst_invsqrt_cfg* cfg, int32_t excess, ppst_ciphertext** out) {
   return guard([&] {
     NEED(ctx); NEED(evk); NEED(out);
+    NOT_RECORDING(ctx);
     *out = wrap(stat_kurtosis(*ctx->cx, evk->e, column(col, nct), nrows, B, cfg_from(cfg),
                               excess != 0));
   });
@@ -685,6 +742,7 @@ int ppst_stat_skewness(ppst_context* ctx, const ppst_eval_keys* evk,
                        const ppst_invsqrt_cfg* cfg, ppst_ciphertext** out) {
   return guard([&] {
     NEED(ctx); NEED(evk); NEED(out);
+    NOT_RECORDING(ctx);
     *out = wrap(stat_skewness(*ctx->cx, evk->e, column(col, nct), nrows, B, cfg_from(cfg)));
   });
 }
@@ -693,6 +751,7 @@ int ppst_stat_cv(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_cipher
                  ppst_ciphertext** out) {
   return guard([&] {
     NEED(ctx); NEED(evk); NEED(out);
+    NOT_RECORDING(ctx);
     int k = cfg ? cfg->sign_k : 2;
     *out = wrap(stat_cv(*ctx->cx, evk->e, column(col, nct), nrows, B_mean, B_var, cfg_from(cfg), k));
   });
@@ -703,6 +762,7 @@ int ppst_stat_pearson(ppst_context* ctx, const ppst_eval_keys* evk,
                       ppst_ciphertext** out) {
   return guard([&] {
     NEED(ctx); NEED(evk); NEED(out);
+    NOT_RECORDING(ctx);
     *out = wrap(stat_pearson(*ctx->cx, evk->e, column(colx, nct), column(coly, nct), nrows, Bx, By,
                              cfg_from(cfg)));
   });
@@ -727,6 +787,7 @@ int ppst_ntt_inverse(ppst_context* ctx, uint64_t* dev, int32_t nlimbs, int32_t f
 int ppst_ntt_autotune(ppst_context* ctx) {
   return guard([&] {
     NEED(ctx);
+    NOT_RECORDING(ctx);
     HIP_CHECK(hipStreamSynchronize(ctx->cx->stream));
     autotune_ntt(*ctx->cx->sh);
   });
@@ -753,6 +814,7 @@ int ppst_server_create(ppst_context* ctx, const ppst_eval_keys* evk, size_t hbm_
                        int32_t slots, ppst_server** out) {
   return guard([&] {
     NEED(ctx); NEED(evk); NEED(out);
+    NOT_RECORDING(ctx);
     auto keys = std::make_shared<const EvalKeys>(evk->e);
     *out = new ppst_server{std::make_unique<Server>(*ctx->cx, keys, hbm_budget, slots)};
   });

@@ -136,6 +136,13 @@ class Pool {
   size_t in_use() const { return in_use_; }
   size_t cached() const { return cached_; }
   void trim();
+  // Graph recording: every block handed out between begin_capture and
+  // end_capture is pinned for the graph (end_capture returns them); a pinned
+  // block released by its owner is not reused until unpin(), so the memory a
+  // graph writes on each launch stays out of other hands.
+  void begin_capture();
+  std::vector<void*> end_capture();
+  void unpin(const std::vector<void*>& blocks);
  private:
   hipStream_t stream_;
   Hooks hooks_;
@@ -143,6 +150,9 @@ class Pool {
   std::multimap<size_t, void*> free_;
   std::map<void*, size_t> sizes_;
   size_t in_use_ = 0, cached_ = 0;
+  bool capturing_ = false;
+  std::vector<void*> captured_;
+  std::map<void*, bool> pinned_;   // block -> released by its owner
 };
 
 struct Buf {
@@ -238,6 +248,7 @@ struct Context {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::shared_ptr<Pool> pool;    // temporaries and results on this stream
+  bool recording = false;        // a graph recording is open on the stream
   const Params& P() const { return sh->P; }
 };
 

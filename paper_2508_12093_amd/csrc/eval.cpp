@@ -27,6 +27,10 @@ void* Pool::get(size_t bytes) {
       in_use_ += sz;
       // remember the real block size
       sizes_[p] = sz;
+      if (capturing_) {
+        captured_.push_back(p);
+        pinned_[p] = false;
+      }
       return p;
     }
   }
@@ -40,6 +44,8 @@ void* Pool::get(size_t bytes) {
   };
   if (!try_alloc()) {
     (void)hipGetLastError();
+    if (capturing_)   // no synchronisation is possible while a recording is open
+      PPST_THROW(ST_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
     trim();
     if (!try_alloc()) {
       (void)hipGetLastError();
@@ -49,17 +55,58 @@ void* Pool::get(size_t bytes) {
   std::lock_guard<std::mutex> g(mu_);
   in_use_ += bytes;
   sizes_[p] = bytes;
+  if (capturing_) {
+    captured_.push_back(p);
+    pinned_[p] = false;
+  }
   return p;
 }
 
 void Pool::put(void* p, size_t) {
   std::lock_guard<std::mutex> g(mu_);
+  auto pin = pinned_.find(p);
+  if (pin != pinned_.end()) {   // the graph still writes this block
+    pin->second = true;
+    return;
+  }
   auto it = sizes_.find(p);
   size_t sz = it->second;
   sizes_.erase(it);
   in_use_ -= sz;
   cached_ += sz;
   free_.emplace(sz, p);
+}
+
+void Pool::begin_capture() {
+  std::lock_guard<std::mutex> g(mu_);
+  capturing_ = true;
+  captured_.clear();
+}
+
+std::vector<void*> Pool::end_capture() {
+  std::lock_guard<std::mutex> g(mu_);
+  capturing_ = false;
+  std::vector<void*> v;
+  v.swap(captured_);
+  return v;
+}
+
+void Pool::unpin(const std::vector<void*>& blocks) {
+  std::lock_guard<std::mutex> g(mu_);
+  for (void* p : blocks) {
+    auto pin = pinned_.find(p);
+    if (pin == pinned_.end()) continue;
+    const bool released = pin->second;
+    pinned_.erase(pin);
+    if (released) {
+      auto it = sizes_.find(p);
+      size_t sz = it->second;
+      sizes_.erase(it);
+      in_use_ -= sz;
+      cached_ += sz;
+      free_.emplace(sz, p);
+    }
+  }
 }
 
 void Pool::trim() {
@@ -1021,6 +1068,53 @@ std::vector<CtPtr> mul_batch(Context& cx, const EvalKeys& evk,
   }
   ks_moddown_rescale(cx, u, D.p, 3 * per, level, po.data(), (int)n);
   return outs;
+}
+
+// ============================================================ graphs
+void graph_begin(Context& cx) {
+  if (cx.recording) PPST_THROW(ST_EINVAL, "a graph recording is already open");
+  cx.pool->begin_capture();
+  hipError_t e = hipStreamBeginCapture(cx.stream, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) {
+    cx.pool->unpin(cx.pool->end_capture());
+    PPST_THROW(ST_EDEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+  }
+  cx.recording = true;
+}
+
+std::unique_ptr<Graph> graph_end(Context& cx) {
+  if (!cx.recording) PPST_THROW(ST_EINVAL, "no graph recording is open");
+  cx.recording = false;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(cx.stream, &g);
+  std::vector<void*> blocks = cx.pool->end_capture();
+  if (e != hipSuccess || g == nullptr) {
+    if (g) (void)hipGraphDestroy(g);
+    // nothing of the recording ever ran: wait for earlier work, then release
+    (void)hipStreamSynchronize(cx.stream);
+    cx.pool->unpin(blocks);
+    PPST_THROW(ST_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  }
+  auto out = std::make_unique<Graph>();
+  out->graph = g;
+  out->stream = cx.stream;
+  out->pool = cx.pool;
+  out->blocks = std::move(blocks);
+  e = hipGraphInstantiate(&out->exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    out->exec = nullptr;
+    PPST_THROW(ST_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  return out;
+}
+
+void graph_launch(Graph& g) { HIP_CHECK(hipGraphLaunch(g.exec, g.stream)); }
+
+Graph::~Graph() {
+  (void)hipStreamSynchronize(stream);
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (pool) pool->unpin(blocks);
 }
 
 void ntt_raw(Context& cx, u64* data, int nlimbs, int first_prime, bool inverse) {

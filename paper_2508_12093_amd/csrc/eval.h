@@ -65,6 +65,24 @@ CtPtr copy_ct(Context& cx, const Ciphertext& a);
 std::vector<CtPtr> mul_batch(Context& cx, const EvalKeys& evk, const std::vector<const Ciphertext*>& a,
                              const std::vector<const Ciphertext*>& b);
 
+// Recording of evaluation calls into a HIP graph (stream capture on the
+// context's stream).  The graph owns every block handed out while recording
+// until it is destroyed; destruction waits for its launches.
+struct Graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t stream = nullptr;
+  std::shared_ptr<Pool> pool;
+  std::vector<void*> blocks;
+  Graph() = default;
+  Graph(const Graph&) = delete;
+  Graph& operator=(const Graph&) = delete;
+  ~Graph();
+};
+void graph_begin(Context& cx);
+std::unique_ptr<Graph> graph_end(Context& cx);
+void graph_launch(Graph& g);
+
 // raw NTT on device memory (canonical order), limb i on prime first_prime + i
 void ntt_raw(Context& cx, u64* data, int nlimbs, int first_prime, bool inverse);
 

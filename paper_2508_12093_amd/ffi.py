@@ -127,6 +127,10 @@ _SIGS = {
     "ppst_level_align": (ctypes.c_int, [_vp, _vp, _i32, _pp]),
     "ppst_mul_batch": (ctypes.c_int, [_vp, _vp, _pp, _pp, _sz, _pp]),
     "ppst_rotate_hoisted_batch": (ctypes.c_int, [_vp, _vp, _pp, _sz, _vp, _sz, _pp]),
+    "ppst_graph_begin": (ctypes.c_int, [_vp]),
+    "ppst_graph_end": (ctypes.c_int, [_vp, _pp]),
+    "ppst_graph_launch": (ctypes.c_int, [_vp]),
+    "ppst_graph_destroy": (ctypes.c_int, [_vp]),
     "ppst_invsqrt_cfg_default": (ctypes.c_int, [_cfgp]),
     "ppst_stat_mean": (ctypes.c_int, [_vp, _vp, _pp, _sz, _sz, _dbl, _pp]),
     "ppst_stat_variance": (ctypes.c_int, [_vp, _vp, _pp, _sz, _sz, _dbl, _pp]),
@@ -514,6 +518,24 @@ def ppst_rotate_hoisted_batch(ctx, evk, cts, steps):
     outs = (ctypes.c_void_p * max(1, n * m))()
     _chk(lib().ppst_rotate_hoisted_batch(ctx, evk, _ptrs(cts), n, _p(s), m, outs))
     return [[Ciphertext(outs[i * m + k], ctx) for k in range(m)] for i in range(n)]
+
+
+class Graph(_Handle):
+    """A recorded sequence of evaluation calls (ppst_graph_*)."""
+    _destroy = "ppst_graph_destroy"
+
+    def launch(self):
+        _chk(lib().ppst_graph_launch(self))
+
+
+def ppst_graph_begin(ctx):
+    _chk(lib().ppst_graph_begin(ctx))
+
+
+def ppst_graph_end(ctx) -> Graph:
+    out = _out()
+    _chk(lib().ppst_graph_end(ctx, ctypes.byref(out)))
+    return Graph(out.value, ctx)
 
 
 def ppst_invsqrt_cfg_default(coeffs=None, **kw) -> InvSqrtCfg:
