@@ -49,6 +49,10 @@ def parse():
     ap.add_argument("--quick", action="store_true", help="short run for profiling")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the roofline kernel and a copy of known size")
+    ap.add_argument("--serving-queries", type=int, default=200,
+                    help="queries per load point of the serving loop (0: skip)")
+    ap.add_argument("--serving-loads", type=str, default="0.6",
+                    help="offered loads as fractions of the measured saturation rate")
     return ap.parse_args()
 
 
@@ -188,6 +192,10 @@ def main():
         np.percentile(lat, 50), np.percentile(lat, 99), pcc, ref_pcc))
 
     rf = measure_ntt(ctx, stream, reps=10 if args.quick else 50)
+    serving = None
+    if args.serving_queries > 0:
+        loads = [float(v) for v in args.serving_loads.split(",") if v]
+        serving = serving_bench(ctx, pk, sk, evk, args.serving_queries, loads)
 
     out = {
         "metric": "HMult+relin/sec and rotations/sec at N=2^16; p50/p99 encrypted-Pearson latency",
@@ -222,9 +230,119 @@ def main():
         "hmult_max_slot_err": hmult_err,
         "roofline": rf,
     }
+    if serving is not None:
+        out["serving"] = serving
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
     print(json.dumps(out), flush=True)
+
+
+SERVING_ROWS = [1 << 10, 1 << 12, 1 << 14, 1 << 16, 1 << 18, 1 << 20]
+
+
+def serving_bench(ctx, pk, sk, evk, nq: int, loads, seed: int = 4):
+    """Continuous-batching server over resident columns of 2^10..2^20 rows
+    (1..32 ciphertexts): x ~ Bernoulli(0.3), y = (lognormal(0, 1) + s x) / 4
+    with corr ~ 0.5.  Query kinds uniform over mean, variance, z-score, CV and
+    Pearson, column sizes uniform over the six; first every query at once
+    (saturation throughput), then Poisson arrivals at the given fractions of
+    that rate.  Latency = arrival to result ready (server timestamps)."""
+    import threading
+
+    import numpy as np
+
+    from paper_2508_12093_amd import ffi, synth
+
+    def fp64(kind, B, x, y):
+        """The statistic each query kind returns (mean / B, Var / B^2, z_0, CV, PCC)."""
+        m, v = y.mean(), y.var()
+        return {ffi.Q_MEAN: m / B, ffi.Q_VARIANCE: v / (B * B), ffi.Q_ZSCORE: (y[0] - m) / np.sqrt(v),
+                ffi.Q_CV: np.sqrt(v) / m, ffi.Q_PEARSON: float(np.corrcoef(x, y)[0, 1])}[kind]
+
+    info = ctx.info
+    slots, L = info.slots, info.L
+    srv = ffi.ppst_server_create(ctx, evk, 96 << 30, 8)
+    cols = {}
+    for i, n in enumerate(SERVING_ROWS):
+        x, y = synth.lognormal_bernoulli_pair(seed + i, n)
+        y = y / 4.0
+        cx = [ffi.ppst_encrypt(ctx, pk, ffi.ppst_encode(ctx, v, L), 10000 * (i + 1) + k)
+              for k, v in enumerate(synth.split_column(x, slots))]
+        cy = [ffi.ppst_encrypt(ctx, pk, ffi.ppst_encode(ctx, v, L), 10000 * (i + 1) + 5000 + k)
+              for k, v in enumerate(synth.split_column(y, slots))]
+        cols[n] = (ffi.ppst_server_register_column(srv, cx, n), ffi.ppst_server_register_column(srv, cy, n), x, y)
+        del cx, cy
+    ffi.ppst_sync(ctx)
+    cfg = ffi.ppst_invsqrt_cfg_default()
+    # (kind, column, bounds): Var/B^2 inside [1e-3, 1] and mean/B_mean inside [0.6, 1.1]
+    kinds = [(ffi.Q_MEAN, "y", 1.0, 1.0), (ffi.Q_VARIANCE, "y", 2.0, 2.0), (ffi.Q_ZSCORE, "y", 2.0, 2.0),
+             (ffi.Q_CV, "y", 0.8, 2.0), (ffi.Q_PEARSON, "x", 1.0, 2.0)]
+    rng = np.random.default_rng(seed)
+
+    def plan(count):
+        return [(kinds[rng.integers(len(kinds))], SERVING_ROWS[rng.integers(len(SERVING_ROWS))])
+                for _ in range(count)]
+
+    def submit(q):
+        (kind, which, B, B2), n = q
+        xid, yid = cols[n][0], cols[n][1]
+        return ffi.ppst_server_submit(srv, kind, xid if which == "x" else yid, yid, B, B2, cfg)
+
+    def run(queries, rate):
+        tickets = [None] * len(queries)
+        gaps = rng.exponential(1.0 / rate, len(queries)) if rate else np.zeros(len(queries))
+
+        def feeder():
+            t0 = time.perf_counter()
+            at = 0.0
+            for i, q in enumerate(queries):
+                at += gaps[i]
+                d = t0 + at - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                tickets[i] = submit(q)
+
+        th = threading.Thread(target=feeder)
+        t_start = time.perf_counter()
+        th.start()
+        res = []
+        for i in range(len(queries)):
+            while tickets[i] is None:
+                time.sleep(1e-4)
+            res.append(ffi.ppst_server_wait(srv, tickets[i]))
+        th.join()
+        wall = time.perf_counter() - t_start
+        assert all(r[0] == 0 for r in res), "a served query failed"
+        lat = np.array([(r[2].t_done - r[2].t_submit) * 1e3 for r in res])
+        return res, lat, wall
+
+    # warm-up: every (kind, size) once
+    run([(k, n) for k in kinds for n in SERVING_ROWS], None)
+    sat_q = plan(nq)
+    res, lat, wall = run(sat_q, None)
+    sat_rate = len(sat_q) / wall
+    log("serving: saturation %.1f queries/s over %d queries" % (sat_rate, len(sat_q)))
+    # spot-check decrypted values of the saturation run against FP64
+    errs = []
+    for (q, r) in list(zip(sat_q, res))[:12]:
+        (kind, which, B, B2), n = q
+        x, y = cols[n][2], cols[n][3]
+        got = float(ffi.ppst_decode(ctx, ffi.ppst_decrypt(ctx, sk, r[1]))[0])
+        want = fp64(kind, B, x, y)
+        errs.append(abs(got - want) / max(abs(want), 1.0))   # relative, absolute below 1
+    points = []
+    for f in loads:
+        rate = f * sat_rate
+        _, lat, wall = run(plan(nq), rate)
+        points.append({"offered_qps": round(rate, 2), "achieved_qps": round(nq / wall, 2),
+                       "p50_ms": round(float(np.percentile(lat, 50)), 2),
+                       "p99_ms": round(float(np.percentile(lat, 99)), 2), "queries": nq})
+        log("serving: offered %.1f q/s -> p50 %.1f ms, p99 %.1f ms" % (
+            rate, points[-1]["p50_ms"], points[-1]["p99_ms"]))
+    del srv
+    return {"saturation_qps": round(sat_rate, 2), "queries_per_point": nq,
+            "rows": SERVING_ROWS, "kinds": "mean,variance,zscore,cv,pearson", "slots": 8,
+            "loads": points, "spot_max_err": float(max(errs))}
 
 
 def measure_ntt(ctx, stream, reps: int):
