@@ -234,7 +234,105 @@ __device__ __forceinline__ void ntt_body(const A ar, typename A::T* lds, const u
   }
 }
 
-template <int LOGM, int LOGE, int SB, bool ROWS, bool INV>
+// The same transform as ntt_body with no LDS staging at either end: the
+// first register pass loads its elements straight from global memory and the
+// last one stores straight to it, saving two LDS round trips and two
+// barriers.  Columns map column-fastest onto threads (a wave covers SB
+// adjacent columns of 64/SB rows), so both ends stay coalesced; rows map as
+// in ntt_body.
+template <class A, int LOGM, int LOGE, int SB, bool ROWS, bool INV>
+__device__ __forceinline__ void ntt_body_dio(const A ar, typename A::T* lds, const u64* src,
+                                             u64* dst, const ulonglong2* tw, const u64* ninv2,
+                                             int N, int logR, int first, bool last,
+                                             uint32_t galois, int logN) {
+  typedef typename A::T T;
+  constexpr int M = 1 << LOGM;
+  constexpr int E = 1 << LOGE;
+  constexpr int TPS = M / E;         // threads per sub-problem
+  constexpr int NP = (LOGM + LOGE - 1) / LOGE;   // register passes
+  constexpr int PAD = M + 1;
+  const int R = 1 << logR;
+  const int C = N >> logR;
+  const int tid = threadIdx.x;
+  const int sp = ROWS ? tid / TPS : tid % SB;
+  const int lane = ROWS ? tid - sp * TPS : tid / SB;
+  T* my = lds + sp * PAD;
+  const uint32_t base0 = ROWS ? (uint32_t)(R + first + sp) : 1u;
+  const size_t rowbase = ROWS ? (size_t)(first + sp) * M : 0;
+  const int col = first + sp;
+  const u64 ni = ninv2[0], nip = ninv2[1];
+
+#pragma unroll
+  for (int pi = 0; pi < NP; ++pi) {
+    const int p = INV ? (NP - 1 - pi) : pi;
+    const int s0 = p * LOGE;
+    const int ls = (LOGM - s0) < LOGE ? (LOGM - s0) : LOGE;   // stages in this pass
+    const int GS = 1 << ls;                                    // group size
+    const int G = E / GS;                                      // groups per thread
+    const int si = M >> (s0 + ls);                             // element stride in a group
+    int e0[E];
+    T x[E];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int gi = g * TPS + lane;
+      const int lo = gi % si, hi = gi / si;
+      e0[g] = hi * (M >> s0) + lo;
+    }
+    if (pi == 0) {
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int k = 0; k < GS; ++k) {
+          const int e = e0[g] + k * si;
+          size_t at = ROWS ? rowbase + e : (size_t)e * C + col;
+          if (ROWS && INV && galois != 0) at = galois_src((uint32_t)at, galois, logN);
+          x[g * GS + k] = ar.in(src[at]);
+        }
+    } else {
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int k = 0; k < GS; ++k) x[g * GS + k] = my[e0[g] + k * si];
+    }
+#pragma unroll
+    for (int uu = 0; uu < ls; ++uu) {
+      const int u = INV ? (ls - 1 - uu) : uu;
+      const int s = s0 + u;
+      const int half = GS >> (u + 1);
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+#pragma unroll
+        for (int k = 0; k < GS; ++k) {
+          if (k & half) continue;
+          const int e = e0[g] + k * si;
+          const uint32_t idx = (base0 << s) + (uint32_t)(e >> (LOGM - s));
+          const ulonglong2 w = tw[idx];
+          if (INV) ar.gs(x[g * GS + k], x[g * GS + k + half], w);
+          else ar.ct(x[g * GS + k], x[g * GS + k + half], w);
+        }
+      }
+    }
+    if (pi == NP - 1) {
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int k = 0; k < GS; ++k) {
+          const int e = e0[g] + k * si;
+          const size_t at = ROWS ? rowbase + e : (size_t)e * C + col;
+          const T v = x[g * GS + k];
+          dst[at] = last ? (INV ? ar.out_inv(v, ni, nip) : ar.out_fwd(v)) : (u64)v;
+        }
+    } else {
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int k = 0; k < GS; ++k) my[e0[g] + k * si] = x[g * GS + k];
+      __syncthreads();
+    }
+  }
+}
+
+template <int LOGM, int LOGE, int SB, bool ROWS, bool INV, bool DIO>
 __global__ void __launch_bounds__(SB * (1 << (LOGM - LOGE)))
 k_ntt_pass(NttArgs a) {
   constexpr int M = 1 << LOGM;
@@ -257,24 +355,33 @@ k_ntt_pass(NttArgs a) {
   const u64* ni = a.ninv + 2 * prime;
   const bool last = INV ? (!ROWS || a.logR == 0) : ROWS;
   const int first = grp * SB;        // first sub-problem of this workgroup
-  if (q < kFpPrimeBound)
-    ntt_body<FpArith, LOGM, LOGE, SB, ROWS, INV>(FpArith(q), (double*)lds, src, dst, tw, ni, N,
-                                                  a.logR, first, last, a.galois, a.logN);
-  else
-    ntt_body<IntArith, LOGM, LOGE, SB, ROWS, INV>(IntArith(q), lds, src, dst, tw, ni, N, a.logR,
-                                                   first, last, a.galois, a.logN);
+  if (DIO) {
+    if (q < kFpPrimeBound)
+      ntt_body_dio<FpArith, LOGM, LOGE, SB, ROWS, INV>(FpArith(q), (double*)lds, src, dst, tw, ni,
+                                                        N, a.logR, first, last, a.galois, a.logN);
+    else
+      ntt_body_dio<IntArith, LOGM, LOGE, SB, ROWS, INV>(IntArith(q), lds, src, dst, tw, ni, N,
+                                                         a.logR, first, last, a.galois, a.logN);
+  } else {
+    if (q < kFpPrimeBound)
+      ntt_body<FpArith, LOGM, LOGE, SB, ROWS, INV>(FpArith(q), (double*)lds, src, dst, tw, ni, N,
+                                                    a.logR, first, last, a.galois, a.logN);
+    else
+      ntt_body<IntArith, LOGM, LOGE, SB, ROWS, INV>(IntArith(q), lds, src, dst, tw, ni, N,
+                                                     a.logR, first, last, a.galois, a.logN);
+  }
 }
 
 typedef void (*PassFn)(const NttArgs&, int, int, hipStream_t);
 
-template <int LOGM, int LOGE, int SB, bool ROWS, bool INV>
+template <int LOGM, int LOGE, int SB, bool ROWS, bool INV, bool DIO>
 void run_pass(const NttArgs& base, int nlimbs, int nbatch, hipStream_t st) {
   NttArgs a = base;
   const int nsub = ROWS ? (1 << a.logR) : (a.N >> a.logR);
   a.blocks_per_limb = nsub / SB;
   dim3 grid(a.blocks_per_limb * nlimbs, nbatch);
   dim3 block(SB * (1 << (LOGM - LOGE)));
-  hipLaunchKernelGGL((k_ntt_pass<LOGM, LOGE, SB, ROWS, INV>), grid, block, 0, st, a);
+  hipLaunchKernelGGL((k_ntt_pass<LOGM, LOGE, SB, ROWS, INV, DIO>), grid, block, 0, st, a);
 }
 
 // Variant tables.  N = 2^16 runs a column pass and a row pass of 2^8 points;
@@ -284,12 +391,22 @@ struct Variant {
   const char* name;
   PassFn fwd, inv;
 };
-#define V16C(LE, SB) {"col:E" #LE ",SB" #SB, run_pass<8, LE, SB, false, false>, run_pass<8, LE, SB, false, true>}
-#define V16R(LE, SB) {"row:E" #LE ",SB" #SB, run_pass<8, LE, SB, true, false>, run_pass<8, LE, SB, true, true>}
-#define V12(LE) {"full:E" #LE, run_pass<12, LE, 1, true, false>, run_pass<12, LE, 1, true, true>}
-const Variant kCol16[] = {V16C(4, 16), V16C(3, 16), V16C(2, 16), V16C(3, 8), V16C(2, 8)};
-const Variant kRow16[] = {V16R(4, 16), V16R(4, 4), V16R(3, 8), V16R(2, 4), V16R(3, 4), V16R(2, 8)};
-const Variant kFull12[] = {V12(4), V12(3), V12(2)};
+// "D" variants load the first register pass from and store the last one to
+// global memory directly (ntt_body_dio).
+#define V16C(LE, SB, D) {D ? "col:E" #LE ",SB" #SB ",D" : "col:E" #LE ",SB" #SB, \
+                         run_pass<8, LE, SB, false, false, D>, run_pass<8, LE, SB, false, true, D>}
+#define V16R(LE, SB, D) {D ? "row:E" #LE ",SB" #SB ",D" : "row:E" #LE ",SB" #SB, \
+                         run_pass<8, LE, SB, true, false, D>, run_pass<8, LE, SB, true, true, D>}
+#define V12(LE, D) {D ? "full:E" #LE ",D" : "full:E" #LE, run_pass<12, LE, 1, true, false, D>, \
+                    run_pass<12, LE, 1, true, true, D>}
+const Variant kCol16[] = {V16C(4, 16, false), V16C(3, 16, false), V16C(2, 16, false),
+                          V16C(3, 8, false),  V16C(2, 8, false),  V16C(3, 16, true),
+                          V16C(2, 16, true),  V16C(2, 8, true),   V16C(4, 16, true)};
+const Variant kRow16[] = {V16R(4, 16, false), V16R(4, 4, false), V16R(3, 8, false),
+                          V16R(2, 4, false),  V16R(3, 4, false), V16R(2, 8, false),
+                          V16R(3, 4, true),   V16R(2, 4, true),  V16R(3, 8, true),
+                          V16R(4, 4, true)};
+const Variant kFull12[] = {V12(4, false), V12(3, false), V12(2, false), V12(4, true), V12(3, true)};
 constexpr int kNCol16 = sizeof(kCol16) / sizeof(kCol16[0]);
 constexpr int kNRow16 = sizeof(kRow16) / sizeof(kRow16[0]);
 constexpr int kNFull12 = sizeof(kFull12) / sizeof(kFull12[0]);

@@ -55,7 +55,7 @@ def test_raw_ntt_matches_oracle(name):
     assert np.array_equal(t.cpu().numpy().view(np.uint64), a)
 
 
-@pytest.mark.parametrize("name,ncol,nrow", [("c1", 1, 3), ("c2", 5, 6)])
+@pytest.mark.parametrize("name,ncol,nrow", [("c1", 1, 5), ("c2", 9, 10)])
 def test_every_ntt_variant_matches_oracle(name, ncol, nrow):
     """Each register-radix / workgroup-shape variant the autotuner can pick
     gives the canonical NTT (bit-exact) and inverts; an index past the
@@ -190,6 +190,22 @@ def test_mul_batch_equals_single(pair):
         assert np.array_equal(ffi.ppst_ct_export(p.ctx, o), ffi.ppst_ct_export(p.ctx, single))
 
 
+def test_rotation_under_every_ntt_variant(pair):
+    """Rotations read their input through the Galois permutation inside the
+    first pass of the inverse NTT; every variant of that pass (LDS-staged and
+    direct-load) gives the oracle's ciphertext."""
+    p = pair
+    m = synth.uniform_column(95, p.P.slots, -1, 1)
+    ct, oct_ = p.encrypt(m, 95)
+    want = p.O.rotate(oct_, 3, p.ogk)
+    nrow = 5                                   # N = 2^12: one pass, five variants
+    for r in range(nrow):
+        ffi.ppst_ntt_set_plan(p.ctx, 0, r)
+        p.same(ffi.ppst_rotate(p.ctx, p.evk, ct, 3), want)
+        p.same(ffi.ppst_mul(p.ctx, p.evk, ct, ct), p.O.mul(oct_, oct_, p.orlk))
+    ffi.ppst_ntt_autotune(p.ctx)
+
+
 def test_rotate_hoisted_batch_equals_single(pair):
     """Batched hoisted rotations equal the one-ciphertext hoisted form bit for
     bit (which the oracle pins in test_rotations), for every ciphertext and
@@ -245,8 +261,17 @@ def test_c2_hmult_and_rotation_bit_exact(c2pair):
     cy, oy = p.encrypt(y / 100.0, 92)
     p.same(cx, ox)
     m = ffi.ppst_mul(p.ctx, p.evk, cx, cy)
-    p.same(m, p.O.mul(ox, oy, p.orlk))
+    om = p.O.mul(ox, oy, p.orlk)
+    p.same(m, om)
     r = ffi.ppst_rotate(p.ctx, p.evk, cy, 1)
-    p.same(r, p.O.rotate(oy, 1, p.ogk))
+    orot = p.O.rotate(oy, 1, p.ogk)
+    p.same(r, orot)
     assert np.max(np.abs(p.decrypt(m) - x * y / 100.0)) < 1e-4
     assert np.max(np.abs(p.decrypt(r) - np.roll(y / 100.0, -1))) < 1e-4
+    # the same under fixed plans: LDS-staged passes, then direct-load passes
+    # (the Galois read sits in the first inverse row pass)
+    for col, row in [(2, 4), (6, 6), (5, 9)]:
+        ffi.ppst_ntt_set_plan(p.ctx, col, row)
+        p.same(ffi.ppst_mul(p.ctx, p.evk, cx, cy), om)
+        p.same(ffi.ppst_rotate(p.ctx, p.evk, cy, 1), orot)
+    ffi.ppst_ntt_autotune(p.ctx)
