@@ -484,8 +484,8 @@ void ks_moddown_rescale(Context& cx, Buf& u, const u64* D, size_t sd, int level,
   }
   Buf corr = dev_buf(cx.pool, sc * nbatch);
   k_mdr_corr(sh, u.p, corr.p, level, nbatch, su, sc, cx.stream);
-  ntt_ct_limbs(cx, corr.p, level, 2 * nbatch, (size_t)level * N, false);
-  k_mdr_final(sh, u.p, D, corr.p, out, level, nbatch, su, sd, sc, cx.stream);
+  MdrTail tail{u.p, D, su, sd, rescale_table(sh, level), out};
+  ntt_fwd_mdr_final(sh, corr.p, level, nbatch, tail, cx.stream);
 }
 
 // rescale nbatch ciphertexts of npoly polynomials (stride sa) into out (stride so)

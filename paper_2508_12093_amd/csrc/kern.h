@@ -32,6 +32,27 @@ struct NttLaunch {
 };
 void ntt(const Shared& sh, const NttLaunch& L, bool inverse, hipStream_t st);
 
+// batch items per launch of the kernels that take operand pointer arrays
+constexpr int kPtrBatch = 64;
+struct OutPtrs {
+  u64* p[kPtrBatch];
+};
+
+// Forward NTT of the ModDown+rescale correction corr [nbatch][2][level][N]
+// (coefficient form, primes q_0..q_{level-1}) whose last pass stores, in
+// place of corr_i, out_i = ((u_i P^-1 mod q_i) + d_i + corr_i) q_l^-1 mod q_i
+// into out[b] ([2][level][N]); u: [nbatch][2][ne][N] at stride su, d:
+// [nbatch][3][nl][N] at stride sd, rc: the rescale table of the level.
+struct MdrTail {
+  const u64* u;
+  const u64* d;
+  size_t su, sd;
+  const u64* rc;
+  u64* const* out;
+};
+void ntt_fwd_mdr_final(const Shared& sh, u64* corr, int level, int nbatch, const MdrTail& tail,
+                       hipStream_t st);
+
 // ------------------------------------------------------- element-wise
 // All element-wise launches work on `npoly` polynomials of `nl` limbs,
 // polynomial c at base + c * poly_stride; limb t uses prime map(t).
@@ -45,8 +66,6 @@ void k_add_scalar(const Shared& sh, const u64* a, u64* out, int nl, const u64* k
 // out[c][t] = a[c][t] * pt[t] mod q_t
 void k_mul_poly(const Shared& sh, const u64* a, const u64* pt, u64* out, int npoly, int nl,
                 size_t stride_a, size_t stride_o, hipStream_t st);
-// batch items per launch of the kernels that take operand pointer arrays
-constexpr int kPtrBatch = 64;
 // (d0, d1, d2) = (a0 b0, a0 b1 + a1 b0, a1 b1); a[i], b[i]: [2][nl][N] (host
 // arrays of nbatch device pointers); d: [3][nl][N] per item at stride_d
 void k_tensor(const Shared& sh, const u64* const* a, const u64* const* b, u64* d, int nl,
@@ -83,24 +102,19 @@ void k_moddown_final(const Shared& sh, const u64* u, const u64* conv, const u64*
 
 // --------------------------------------- ModDown and rescale in one pass
 // After the key-switch inner product u (NTT form, [2][ne][N]) of a product
-// whose tensor is d ([3][nl][N]), these three kernels produce
-// rescale(d + ModDown(u)) bit for bit, with one NTT of the correction
-// instead of a forward NTT after ModDown and an inverse + forward NTT pair
-// inside rescale:
+// whose tensor is d ([3][nl][N]), these steps produce rescale(d + ModDown(u))
+// bit for bit, with one NTT of the correction instead of a forward NTT after
+// ModDown and an inverse + forward NTT pair inside rescale:
 //   prep:  u[c][l] += (P mod q_l) d[c][l]                      (NTT form)
 //   (iNTT of limbs q_l, p_0..p_{K-1} of u)
 //   corr:  c_l = (u_l + h - Conv_l) P^-1 mod q_l, t = centred(c_l),
 //          corr_i = (h - Conv_i) P^-1 - t  mod q_i, i < l       (coefficient form)
-//   (NTT of corr)
+//   (NTT of corr, whose last pass stores, in ntt_fwd_mdr_final)
 //   final: out_i = (d_i + u_i P^-1 + corr_i) q_l^-1 mod q_i
 void k_mdr_prep(const Shared& sh, u64* u, const u64* d, int level, int nbatch, size_t su,
                 size_t sd, hipStream_t st);
 void k_mdr_corr(const Shared& sh, const u64* u, u64* corr, int level, int nbatch, size_t su,
                 size_t sc, hipStream_t st);
-// out: host array of nbatch device pointers, each [2][level][N]
-void k_mdr_final(const Shared& sh, const u64* u, const u64* d, const u64* corr,
-                 u64* const* out, int level, int nbatch, size_t su, size_t sd, size_t sc,
-                 hipStream_t st);
 
 // k_moddown_final for nbatch items with the addend (c0 only) and the output
 // given as host arrays of device pointers ([nl][N] and [2][nl][N])

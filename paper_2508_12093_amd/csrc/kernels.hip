@@ -391,25 +391,6 @@ k_mdr_corr_kernel(const u64* __restrict__ u, u64* __restrict__ corr, const Mod* 
   }
 }
 
-__global__ void k_mdr_final_kernel(const u64* __restrict__ u, const u64* __restrict__ d,
-                                   const u64* __restrict__ corr, OutBatch out, const Mod* mods,
-                                   const u64* md, const u64* rc, int K, int L, int logN, int level,
-                                   int ne, int nl, size_t su, size_t sd, size_t sc) {
-  const size_t N = (size_t)1 << logN;
-  size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= (size_t)level * N) return;
-  const int c = blockIdx.y;
-  const size_t b = blockIdx.z;
-  const int i = (int)(r >> logN);
-  const u64 q = mods[i].q;
-  const MdLayout lay(K, L);
-  u64 x = u[b * su + (size_t)c * ne * N + r];
-  u64 v = mul_shoup(x, md[lay.pinv(i)], md[lay.pinv(i) + 1], q);
-  v = addm(v, d[b * sd + (size_t)c * nl * N + r], q);
-  v = addm(v, corr[b * sc + (size_t)c * level * N + r], q);
-  out.p[b][(size_t)c * level * N + r] = mul_shoup(v, rc[3 * i], rc[3 * i + 1], q);
-}
-
 // ------------------------------------------------------------------ rescale
 __global__ void k_rescale_conv_kernel(const u64* __restrict__ top, u64* tmp, const Mod* mods,
                                       const u64* rc, int logN, int level, size_t ts) {
@@ -777,25 +758,6 @@ void k_mdr_corr(const Shared& sh, const u64* u, u64* corr, int level, int nbatch
   else
     PPST_THROW(ST_EINVAL, "more than 8 special primes");
   LAUNCH_CHECK();
-}
-
-void k_mdr_final(const Shared& sh, const u64* u, const u64* d, const u64* corr,
-                 u64* const* out, int level, int nbatch, size_t su, size_t sd, size_t sc,
-                 hipStream_t st) {
-  const Params& P = sh.P;
-  for (int b0 = 0; b0 < nbatch; b0 += kPtrBatch) {
-    const int nb = std::min(kPtrBatch, nbatch - b0);
-    OutBatch po{};
-    for (int i = 0; i < nb; ++i) po.p[i] = out[b0 + i];
-    dim3 g = grid_for((size_t)level * P.N);
-    g.y = 2;
-    g.z = nb;
-    hipLaunchKernelGGL(k_mdr_final_kernel, g, dim3(kBlock), 0, st, u + (size_t)b0 * su,
-                       d + (size_t)b0 * sd, corr + (size_t)b0 * sc, po, M(sh), sh.tab.moddown.p,
-                       rescale_table(sh, level), P.K, P.L, P.logN, level, level + 1 + P.K,
-                       level + 1, su, sd, sc);
-    LAUNCH_CHECK();
-  }
 }
 
 void k_rescale_conv(const Shared& sh, const u64* top, u64* tmp, int level, int npoly,

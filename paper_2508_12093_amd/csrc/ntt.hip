@@ -19,6 +19,7 @@
 // fits one workgroup and runs as a single row pass.
 #include "dev.h"
 #include "kern.h"
+#include "tables.h"
 
 namespace ppst {
 
@@ -240,11 +241,20 @@ __device__ __forceinline__ void ntt_body(const A ar, typename A::T* lds, const u
 // barriers.  Columns map column-fastest onto threads (a wave covers SB
 // adjacent columns of 64/SB rows), so both ends stay coalesced; rows map as
 // in ntt_body.
-template <class A, int LOGM, int LOGE, int SB, bool ROWS, bool INV>
+// Stores finished elements of a limb.  A store may load operands of its own
+// for element slot i (0..E-1) before the last pass's butterflies
+// (prefetch), so that their latency overlaps the arithmetic.
+struct PlainStore {
+  u64* dst;
+  __device__ __forceinline__ void prefetch(int, size_t) {}
+  __device__ __forceinline__ void put(int, size_t at, u64 v) const { dst[at] = v; }
+};
+
+template <class A, int LOGM, int LOGE, int SB, bool ROWS, bool INV, class Store = PlainStore>
 __device__ __forceinline__ void ntt_body_dio(const A ar, typename A::T* lds, const u64* src,
-                                             u64* dst, const ulonglong2* tw, const u64* ninv2,
-                                             int N, int logR, int first, bool last,
-                                             uint32_t galois, int logN) {
+                                             Store& store, const ulonglong2* tw,
+                                             const u64* ninv2, int N, int logR, int first,
+                                             bool last, uint32_t galois, int logN) {
   typedef typename A::T T;
   constexpr int M = 1 << LOGM;
   constexpr int E = 1 << LOGE;
@@ -294,6 +304,15 @@ __device__ __forceinline__ void ntt_body_dio(const A ar, typename A::T* lds, con
 #pragma unroll
         for (int k = 0; k < GS; ++k) x[g * GS + k] = my[e0[g] + k * si];
     }
+    if (pi == NP - 1) {
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int k = 0; k < GS; ++k) {
+          const int e = e0[g] + k * si;
+          store.prefetch(g * GS + k, ROWS ? rowbase + e : (size_t)e * C + col);
+        }
+    }
 #pragma unroll
     for (int uu = 0; uu < ls; ++uu) {
       const int u = INV ? (ls - 1 - uu) : uu;
@@ -320,7 +339,7 @@ __device__ __forceinline__ void ntt_body_dio(const A ar, typename A::T* lds, con
           const int e = e0[g] + k * si;
           const size_t at = ROWS ? rowbase + e : (size_t)e * C + col;
           const T v = x[g * GS + k];
-          dst[at] = last ? (INV ? ar.out_inv(v, ni, nip) : ar.out_fwd(v)) : (u64)v;
+          store.put(g * GS + k, at, last ? (INV ? ar.out_inv(v, ni, nip) : ar.out_fwd(v)) : (u64)v);
         }
     } else {
 #pragma unroll
@@ -356,11 +375,13 @@ k_ntt_pass(NttArgs a) {
   const bool last = INV ? (!ROWS || a.logR == 0) : ROWS;
   const int first = grp * SB;        // first sub-problem of this workgroup
   if (DIO) {
+    PlainStore store{dst};
     if (q < kFpPrimeBound)
-      ntt_body_dio<FpArith, LOGM, LOGE, SB, ROWS, INV>(FpArith(q), (double*)lds, src, dst, tw, ni,
-                                                        N, a.logR, first, last, a.galois, a.logN);
+      ntt_body_dio<FpArith, LOGM, LOGE, SB, ROWS, INV>(FpArith(q), (double*)lds, src, store, tw,
+                                                        ni, N, a.logR, first, last, a.galois,
+                                                        a.logN);
     else
-      ntt_body_dio<IntArith, LOGM, LOGE, SB, ROWS, INV>(IntArith(q), lds, src, dst, tw, ni, N,
+      ntt_body_dio<IntArith, LOGM, LOGE, SB, ROWS, INV>(IntArith(q), lds, src, store, tw, ni, N,
                                                          a.logR, first, last, a.galois, a.logN);
   } else {
     if (q < kFpPrimeBound)
@@ -370,6 +391,81 @@ k_ntt_pass(NttArgs a) {
       ntt_body<IntArith, LOGM, LOGE, SB, ROWS, INV>(IntArith(q), lds, src, dst, tw, ni, N,
                                                      a.logR, first, last, a.galois, a.logN);
   }
+}
+
+// ---- forward row pass that finishes the fused ModDown + rescale
+// The element stored for limb i (prime q_i, i < level) of polynomial c of
+// batch item b is, instead of the transformed correction corr_i itself,
+//   out_i = ((u_i P^-1 mod q_i) + d_i + corr_i) q_l^-1 mod q_i,
+// the same operations in the same order as the separate final kernel.
+struct MdrEpi {
+  const u64* u;      // [item][2][ne][N]  key-switch accumulators (NTT form)
+  const u64* d;      // [item][3][nl][N]  tensor (d0, d1 used)
+  size_t su, sd;
+  OutPtrs out;       // item b writes [2][level][N] at out.p[b]
+  const u64* md;     // ModDown table
+  const u64* rc;     // rescale table of the level
+  int K, L, level, ne, nl;
+};
+
+template <int E>
+struct MdrStore {
+  const u64* u;
+  const u64* d;
+  u64* out;
+  u64 q, pinv, pinvs, qlinv, qlinvs;
+  u64 pu[E], pd[E];
+  __device__ __forceinline__ void prefetch(int i, size_t at) {
+    pu[i] = u[at];
+    pd[i] = d[at];
+  }
+  __device__ __forceinline__ void put(int i, size_t at, u64 corr) const {
+    u64 v = mul_shoup(pu[i], pinv, pinvs, q);
+    v = addm(v, pd[i], q);
+    v = addm(v, corr, q);
+    out[at] = mul_shoup(v, qlinv, qlinvs, q);
+  }
+};
+
+template <int LOGM, int LOGE, int SB>
+__global__ void __launch_bounds__(SB * (1 << (LOGM - LOGE)))
+k_ntt_row_mdr(NttArgs a, MdrEpi e) {
+  constexpr int M = 1 << LOGM;
+  __shared__ u64 lds[SB * (M + 1)];
+  const int N = a.N;
+  const int t = blockIdx.x / a.blocks_per_limb;          // limb = prime index, t < level
+  const int grp = blockIdx.x - t * a.blocks_per_limb;
+  const int item = blockIdx.y >> 1, c = blockIdx.y & 1;
+  const u64* src = a.src + (size_t)blockIdx.y * a.batch_stride + (size_t)t * N;
+  const u64 q = a.mods[t].q;
+  const ulonglong2* tw = (const ulonglong2*)(a.tw + (size_t)t * N * 2);
+  const u64* ni = a.ninv + 2 * t;
+  const MdLayout lay(e.K, e.L);
+  MdrStore<(1 << LOGE)> store;
+  store.u = e.u + (size_t)item * e.su + ((size_t)c * e.ne + t) * N;
+  store.d = e.d + (size_t)item * e.sd + ((size_t)c * e.nl + t) * N;
+  store.out = e.out.p[item] + ((size_t)c * e.level + t) * N;
+  store.q = q;
+  store.pinv = e.md[lay.pinv(t)];
+  store.pinvs = e.md[lay.pinv(t) + 1];
+  store.qlinv = e.rc[3 * t];
+  store.qlinvs = e.rc[3 * t + 1];
+  const int first = grp * SB;
+  if (q < kFpPrimeBound)
+    ntt_body_dio<FpArith, LOGM, LOGE, SB, true, false>(FpArith(q), (double*)lds, src, store, tw,
+                                                        ni, N, a.logR, first, true, 0u, a.logN);
+  else
+    ntt_body_dio<IntArith, LOGM, LOGE, SB, true, false>(IntArith(q), lds, src, store, tw, ni, N,
+                                                         a.logR, first, true, 0u, a.logN);
+}
+
+template <int LOGM, int LOGE, int SB>
+void run_row_mdr(const NttArgs& base, const MdrEpi& e, int nlimbs, int nbatch, hipStream_t st) {
+  NttArgs a = base;
+  a.blocks_per_limb = (1 << a.logR) / SB;
+  dim3 grid(a.blocks_per_limb * nlimbs, nbatch);
+  dim3 block(SB * (1 << (LOGM - LOGE)));
+  hipLaunchKernelGGL((k_ntt_row_mdr<LOGM, LOGE, SB>), grid, block, 0, st, a, e);
 }
 
 typedef void (*PassFn)(const NttArgs&, int, int, hipStream_t);
@@ -494,6 +590,76 @@ void ntt(const Shared& sh, const NttLaunch& L, bool inverse, hipStream_t st) {
     PPST_THROW(ST_EINVAL, "NTT: a Galois read needs an out-of-place inverse transform and odd g < 2N");
   a.galois = L.galois;
   launch_passes(sh, a, L, inverse, st);
+  HIP_CHECK(hipGetLastError());
+}
+
+typedef void (*MdrFn)(const NttArgs&, const MdrEpi&, int, int, hipStream_t);
+
+// the fused row pass matching a row variant of the plan (same register radix
+// and workgroup shape where one exists)
+static MdrFn mdr_variant(int logN, int row_index) {
+  if (logN == 12) {
+    const int le = (row_index == 0 || row_index == 3) ? 4 : 3;
+    return le == 4 ? run_row_mdr<12, 4, 1> : run_row_mdr<12, 3, 1>;
+  }
+  switch (row_index) {
+    case 1: case 9: return run_row_mdr<8, 4, 4>;
+    case 2: case 8: return run_row_mdr<8, 3, 8>;
+    case 3: case 7: return run_row_mdr<8, 2, 4>;
+    default: return run_row_mdr<8, 3, 4>;
+  }
+}
+
+void ntt_fwd_mdr_final(const Shared& sh, u64* corr, int level, int nbatch, const MdrTail& tail,
+                       hipStream_t st) {
+  const Params& P = sh.P;
+  if (level < 1 || nbatch <= 0) return;
+  const size_t N = P.N;
+  NttArgs a{};
+  a.mods = (const Mod*)sh.tab.mods.p;
+  a.tw = sh.tab.fwd.p;
+  a.ninv = sh.tab.ninv.p;
+  a.N = P.N;
+  a.logN = P.logN;
+  a.nq = level;
+  a.pofs = P.L + 1;
+  a.skip_lo = a.skip_hi = 1 << 30;
+  a.dalpha = 0;
+  a.dcount = 1;
+  a.dtotal = 0;
+  a.galois = 0;
+  a.batch_stride = a.dst_stride = (size_t)level * N;
+  const int b = ntt_bucket(level * 2 * nbatch);
+  const NttPlan& plan = sh.ntt_plan;
+  if (P.logN == 16) {
+    a.logR = 8;
+    a.src = corr;
+    a.dst = corr;
+    kCol16[plan.v[0][0][b]].fwd(a, level, 2 * nbatch, st);
+  } else if (P.logN == 12) {
+    a.logR = 0;
+  } else {
+    PPST_THROW(ST_EINVAL, "NTT supports log2 N in {12, 16}");
+  }
+  const MdrFn f = mdr_variant(P.logN, plan.v[0][1][b]);
+  MdrEpi e{};
+  e.su = tail.su;
+  e.sd = tail.sd;
+  e.md = sh.tab.moddown.p;
+  e.rc = tail.rc;
+  e.K = P.K;
+  e.L = P.L;
+  e.level = level;
+  e.ne = level + 1 + P.K;
+  e.nl = level + 1;
+  for (int b0 = 0; b0 < nbatch; b0 += kPtrBatch) {
+    const int nb = std::min(kPtrBatch, nbatch - b0);
+    for (int i = 0; i < nb; ++i) e.out.p[i] = tail.out[b0 + i];
+    e.u = tail.u + (size_t)b0 * tail.su;
+    e.d = tail.d + (size_t)b0 * tail.sd;
+    a.src = corr + (size_t)b0 * 2 * level * N;
+    f(a, e, level, 2 * nb, st);
+  }
   HIP_CHECK(hipGetLastError());
 }
 

@@ -270,7 +270,7 @@ def test_c2_hmult_and_rotation_bit_exact(c2pair):
     assert np.max(np.abs(p.decrypt(r) - np.roll(y / 100.0, -1))) < 1e-4
     # the same under fixed plans: LDS-staged passes, then direct-load passes
     # (the Galois read sits in the first inverse row pass)
-    for col, row in [(2, 4), (6, 6), (5, 9)]:
+    for col, row in [(2, 4), (6, 6), (5, 9), (0, 1), (7, 2), (8, 3)]:
         ffi.ppst_ntt_set_plan(p.ctx, col, row)
         p.same(ffi.ppst_mul(p.ctx, p.evk, cx, cy), om)
         p.same(ffi.ppst_rotate(p.ctx, p.evk, cy, 1), orot)
