@@ -34,7 +34,7 @@ BFLY_PEAK_G = 256 * 64 * 2.4e9 / 2 / 10 / 1e9
 # HBM bytes per launch pair from FETCH_SIZE + WRITE_SIZE counters (rocprofv3
 # --pmc, one counter per run), scaled by the same counters on a plain copy of
 # known size; null when the kernels change after the counters were taken.
-NTT_TRAFFIC_BYTES = 79693047   # profiles/ntt_fwd_c2_25limbs_traffic.md
+NTT_TRAFFIC_BYTES = 79906202   # profiles/ntt_fwd_c2_25limbs_traffic.md
 
 
 def parse():
@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--quick", action="store_true", help="short run for profiling")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the roofline kernel and a copy of known size")
+    ap.add_argument("--only", choices=["plain", "batched"], default=None,
+                    help="time one form of the 64-product step alone (for kernel profiles)")
     ap.add_argument("--serving-queries", type=int, default=200,
                     help="queries per load point of the serving loop (0: skip)")
     ap.add_argument("--serving-loads", type=str, default="0.6",
@@ -108,6 +110,21 @@ def main():
     def step_mul():
         outs = [ffi.ppst_mul(ctx, evk, cts[i], cts[(i + 1) % B]) for i in range(B)]
         return outs
+
+    if args.only:
+        fn = step_mul if args.only == "plain" else (
+            lambda: ffi.ppst_mul_batch(ctx, evk, cts, cts[1:] + cts[:1]))
+        fn()
+        sync()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            keep = fn()
+        sync()
+        rate = B * args.steps / (time.perf_counter() - t)
+        del keep
+        log("%s HMult+relin+rescale: %.0f /s" % (args.only, rate))
+        print(json.dumps({"only": args.only, "hmult_per_s": round(rate, 2), "steps": args.steps}))
+        return
 
     for _ in range(args.warmup):
         step_mul()
@@ -213,11 +230,11 @@ def main():
     log("Pearson p50 %.2f ms p99 %.2f ms, value %.6f (fp64 %.6f)" % (
         np.percentile(lat, 50), np.percentile(lat, 99), pcc, ref_pcc))
 
-    rf = measure_ntt(ctx, stream, reps=10 if args.quick else 50)
     serving = None
     if args.serving_queries > 0:
         loads = [float(v) for v in args.serving_loads.split(",") if v]
         serving = serving_bench(ctx, pk, sk, evk, args.serving_queries, loads)
+    rf = measure_ntt(ctx, stream, reps=10 if args.quick else 50)
 
     out = {
         "metric": "HMult+relin/sec and rotations/sec at N=2^16; p50/p99 encrypted-Pearson latency",
@@ -368,9 +385,16 @@ def serving_bench(ctx, pk, sk, evk, nq: int, loads, seed: int = 4):
             "loads": points, "spot_max_err": float(max(errs))}
 
 
+# The roofline kernel is timed under a fixed variant pair (the one the
+# autotuner picks for 25-limb forward transforms on MI355X in most runs), so
+# that the same kernels appear in the rocprofv3 profiles of --kernels-only.
+NTT_COL_VARIANT, NTT_ROW_VARIANT = 5, 6      # col:E3,SB16,D / row:E3,SB4,D
+
+
 def measure_ntt(ctx, stream, reps: int):
     """Forward NTT (column pass + row pass) of one 25-limb polynomial at
-    N = 2^16, timed with HIP events on the library's stream."""
+    N = 2^16, timed with HIP events on the library's stream.  Leaves the
+    context on the fixed plan."""
     import numpy as np
     import torch
 
@@ -381,6 +405,8 @@ def measure_ntt(ctx, stream, reps: int):
     limbs = L + 1
     rng = np.random.default_rng(5)
     primes = ctx.primes
+    ffi.ppst_ntt_set_plan(ctx, NTT_COL_VARIANT, NTT_ROW_VARIANT)
+    plan = ffi.ppst_ntt_plan(ctx).split(";")[0]
     host = np.stack([rng.integers(0, primes[i % limbs], N, dtype=np.uint64) for i in range(2 * limbs)])
     dev = torch.from_numpy(host.view(np.int64).copy()).cuda()
     ffi.ppst_sync(ctx)
@@ -403,7 +429,7 @@ def measure_ntt(ctx, stream, reps: int):
     log("forward NTT (25 limbs, 2 passes): %.1f us, %.1f G butterflies/s, %.0f GB/s algorithmic" % (
         sec * 1e6, g_bfly, alg_bytes / sec / 1e9))
     return {
-        "kernel": "forward NTT of 25 limbs at N=2^16 (column pass + row pass)",
+        "kernel": "forward NTT of 25 limbs at N=2^16 (column pass + row pass; %s)" % plan.strip(),
         "bound": "alu",
         "achieved": round(g_bfly, 1),
         "peak": round(BFLY_PEAK_G, 1),
@@ -425,6 +451,7 @@ def kernels_only(args):
 
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
+    os.environ["PPST_NTT_AUTOTUNE"] = "0"      # the profile holds only the timed launches
     ctx = ffi.ppst_context_create("c2", stream=ctypes.c_void_p(stream.cuda_stream))
     rf = measure_ntt(ctx, stream, reps=20)
     n = 64 << 20                                             # 64 Mi int64 = 512 MiB
