@@ -655,7 +655,10 @@ void k_ks_inner(const Shared& sh, const u64* d, const u64* ext, const u64* key, 
   a.nprimes = P.nprimes;
   a.nbatch = nbatch;
   dim3 g = grid_for((size_t)a.ne * P.N);
-  if (nbatch >= 4) {
+  if (nbatch >= 8) {
+    g.y = (nbatch + 7) / 8;
+    hipLaunchKernelGGL(k_ks_inner_kernel<8>, g, dim3(kBlock), 0, st, a);
+  } else if (nbatch >= 4) {
     g.y = (nbatch + 3) / 4;
     hipLaunchKernelGGL(k_ks_inner_kernel<4>, g, dim3(kBlock), 0, st, a);
   } else if (nbatch >= 2) {

@@ -35,7 +35,25 @@ struct NttArgs {
   int N, logN, logR, nq, pofs, skip_lo, skip_hi, blocks_per_limb;
   int dalpha, dcount, dtotal;
   uint32_t galois;   // inverse transforms: read the input through X -> X^galois (0: none)
+  int nbatch;        // batch items of the launch (set by the launcher)
 };
+
+// Workgroup -> (limb, group, batch item) of a one-dimensional grid, batch
+// item fastest: the workgroups that share a prime's twiddle rows run back to
+// back (blocks are dealt round-robin to the 8 XCDs, so each XCD sees every
+// eighth item of the same tile while its twiddles sit in that XCD's L2).
+struct BlockPos {
+  int limb, grp, item;
+};
+__device__ __forceinline__ BlockPos block_pos(int blocks_per_limb, int nbatch) {
+  const unsigned b = blockIdx.x;
+  const unsigned tile = b / (unsigned)nbatch;
+  BlockPos p;
+  p.item = (int)(b - tile * (unsigned)nbatch);
+  p.limb = (int)(tile / (unsigned)blocks_per_limb);
+  p.grp = (int)(tile - (unsigned)p.limb * (unsigned)blocks_per_limb);
+  return p;
+}
 
 // ----------------------------------------------------------------------
 // Butterfly arithmetic.  Two interchangeable policies, chosen per workgroup
@@ -357,18 +375,19 @@ k_ntt_pass(NttArgs a) {
   constexpr int M = 1 << LOGM;
   __shared__ u64 lds[SB * (M + 1)];
   const int N = a.N;
-  const int limb_u = blockIdx.x / a.blocks_per_limb;
-  const int grp = blockIdx.x - limb_u * a.blocks_per_limb;
+  const BlockPos bp = block_pos(a.blocks_per_limb, a.nbatch);
+  const int limb_u = bp.limb;
+  const int grp = bp.grp;
   int skip_lo = a.skip_lo, skip_hi = a.skip_hi;
   if (a.dalpha > 0) {            // block-uniform: the whole workgroup leaves together
-    skip_lo = (int)(blockIdx.y % a.dcount) * a.dalpha;
+    skip_lo = (bp.item % a.dcount) * a.dalpha;
     skip_hi = min(skip_lo + a.dalpha, a.nq);
     if (limb_u >= a.dtotal - (skip_hi - skip_lo)) return;
   }
   const int t = limb_u >= skip_lo ? limb_u + (skip_hi - skip_lo) : limb_u;
   const int prime = t < a.nq ? t : a.pofs + (t - a.nq);
-  const u64* src = a.src + (size_t)blockIdx.y * a.batch_stride + (size_t)t * N;
-  u64* dst = a.dst + (size_t)blockIdx.y * a.dst_stride + (size_t)t * N;
+  const u64* src = a.src + (size_t)bp.item * a.batch_stride + (size_t)t * N;
+  u64* dst = a.dst + (size_t)bp.item * a.dst_stride + (size_t)t * N;
   const u64 q = a.mods[prime].q;
   const ulonglong2* tw = (const ulonglong2*)(a.tw + (size_t)prime * N * 2);
   const u64* ni = a.ninv + 2 * prime;
@@ -433,10 +452,11 @@ k_ntt_row_mdr(NttArgs a, MdrEpi e) {
   constexpr int M = 1 << LOGM;
   __shared__ u64 lds[SB * (M + 1)];
   const int N = a.N;
-  const int t = blockIdx.x / a.blocks_per_limb;          // limb = prime index, t < level
-  const int grp = blockIdx.x - t * a.blocks_per_limb;
-  const int item = blockIdx.y >> 1, c = blockIdx.y & 1;
-  const u64* src = a.src + (size_t)blockIdx.y * a.batch_stride + (size_t)t * N;
+  const BlockPos bp = block_pos(a.blocks_per_limb, a.nbatch);
+  const int t = bp.limb;                                 // limb = prime index, t < level
+  const int grp = bp.grp;
+  const int item = bp.item >> 1, c = bp.item & 1;
+  const u64* src = a.src + (size_t)bp.item * a.batch_stride + (size_t)t * N;
   const u64 q = a.mods[t].q;
   const ulonglong2* tw = (const ulonglong2*)(a.tw + (size_t)t * N * 2);
   const u64* ni = a.ninv + 2 * t;
@@ -463,7 +483,8 @@ template <int LOGM, int LOGE, int SB>
 void run_row_mdr(const NttArgs& base, const MdrEpi& e, int nlimbs, int nbatch, hipStream_t st) {
   NttArgs a = base;
   a.blocks_per_limb = (1 << a.logR) / SB;
-  dim3 grid(a.blocks_per_limb * nlimbs, nbatch);
+  a.nbatch = nbatch;
+  dim3 grid(a.blocks_per_limb * nlimbs * nbatch);
   dim3 block(SB * (1 << (LOGM - LOGE)));
   hipLaunchKernelGGL((k_ntt_row_mdr<LOGM, LOGE, SB>), grid, block, 0, st, a, e);
 }
@@ -475,7 +496,8 @@ void run_pass(const NttArgs& base, int nlimbs, int nbatch, hipStream_t st) {
   NttArgs a = base;
   const int nsub = ROWS ? (1 << a.logR) : (a.N >> a.logR);
   a.blocks_per_limb = nsub / SB;
-  dim3 grid(a.blocks_per_limb * nlimbs, nbatch);
+  a.nbatch = nbatch;
+  dim3 grid(a.blocks_per_limb * nlimbs * nbatch);
   dim3 block(SB * (1 << (LOGM - LOGE)));
   hipLaunchKernelGGL((k_ntt_pass<LOGM, LOGE, SB, ROWS, INV, DIO>), grid, block, 0, st, a);
 }
