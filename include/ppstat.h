@@ -215,6 +215,12 @@ int ppst_rotate(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciphert
  * digits); a different but equally valid key switch than ppst_rotate */
 int ppst_rotate_hoisted(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciphertext* a,
                         const int32_t* rs, size_t n, ppst_ciphertext** outs);
+/* ppst_rotate of n ciphertexts of one level by the same step r as one key
+ * switch over the batch (the Galois key read once per group of items);
+ * outs[i] is bit-identical to ppst_rotate(cts[i], r). */
+int ppst_rotate_batch(ppst_context* ctx, const ppst_eval_keys* evk,
+                      const ppst_ciphertext* const* cts, size_t n, int32_t r,
+                      ppst_ciphertext** outs);
 /* ppst_rotate_hoisted over n ciphertexts of one level: all ModUps first, then
  * each rotation over the whole batch, so a Galois key is read once per group
  * of ciphertexts.  outs[i * m + k] = rotation of cts[i] by rs[k], bit-identical

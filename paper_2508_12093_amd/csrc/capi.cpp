@@ -641,6 +641,24 @@ int ppst_rotate_hoisted_batch(ppst_context* ctx, const ppst_eval_keys* evk,
     for (size_t i = 0; i < o.size(); ++i) outs[i] = wrap(o[i]);
   });
 }
+int ppst_rotate_batch(ppst_context* ctx, const ppst_eval_keys* evk,
+                      const ppst_ciphertext* const* cts, size_t n, int32_t r,
+                      ppst_ciphertext** outs) {
+  return guard([&] {
+    NEED(ctx); NEED(evk);
+    if (n) {
+      NEED(cts);
+      NEED(outs);
+    }
+    std::vector<const Ciphertext*> v;
+    for (size_t i = 0; i < n; ++i) {
+      NEED(cts[i]);
+      v.push_back(cts[i]->c.get());
+    }
+    auto o = rotate_batch(*ctx->cx, evk->e, v, r);
+    for (size_t i = 0; i < o.size(); ++i) outs[i] = wrap(o[i]);
+  });
+}
 int ppst_rotsum(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciphertext* a,
                 ppst_ciphertext** out) {
   return guard([&] {

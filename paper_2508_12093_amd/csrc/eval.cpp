@@ -1011,6 +1011,72 @@ std::vector<CtPtr> rotate_hoisted_batch(Context& cx, const EvalKeys& evk,
   return outs;
 }
 
+std::vector<CtPtr> rotate_batch(Context& cx, const EvalKeys& evk,
+                                const std::vector<const Ciphertext*>& cts, long r) {
+  const size_t n = cts.size();
+  if (n == 0) return {};
+  const Params& P = cx.P();
+  const Shared& sh = *cx.sh;
+  const int level = cts[0]->level;
+  for (const Ciphertext* c : cts) {
+    if (c->npoly != 2) PPST_THROW(ST_EINVAL, "rotation expects a degree-1 ciphertext");
+    if (c->level != level) PPST_THROW(ST_ESCALE, "batch members at different levels");
+  }
+  const u64 g = galois_elt(P, r);
+  std::vector<CtPtr> outs;
+  if (g == 1) {
+    for (const Ciphertext* c : cts) outs.push_back(copy_ct(cx, *c));
+    return outs;
+  }
+  const KsKey& key = galois_key(evk, g);
+  const int N = P.N, nl = level + 1, K = P.K, ne = nl + K;
+  const size_t per = (size_t)nl * N, su = 2 * (size_t)ne * N, sc = 2 * per;
+  // the c1 polynomials side by side (one copy each), then one key switch
+  Buf d = dev_buf(cx.pool, per * n);
+  for (size_t i = 0; i < n; ++i)
+    HIP_CHECK(hipMemcpyAsync(d.p + per * i, cts[i]->poly(1), per * 8, hipMemcpyDeviceToDevice,
+                             cx.stream));
+  Buf u = ks_accumulate(cx, key, d.p, per, level, (int)n, (uint32_t)g);
+  d.release();
+  {
+    NttLaunch L{};
+    L.dst = u.p + per;
+    L.src = L.dst;
+    L.nlimbs = K;
+    L.nbatch = 2 * (int)n;
+    L.batch_stride = (size_t)ne * N;
+    L.nq = 0;
+    L.pofs = P.L + 1;
+    ntt(sh, L, true, cx.stream);
+  }
+  Buf conv = dev_buf(cx.pool, sc * n);
+  k_moddown_conv(sh, u.p, conv.p, level, (int)n, su, sc, cx.stream);
+  ntt_ct_limbs(cx, conv.p, nl, 2 * (int)n, per, false);
+  std::vector<const u64*> add(n);
+  std::vector<u64*> po(n);
+  for (size_t i = 0; i < n; ++i) {
+    outs.push_back(new_ct(cx, level, cts[i]->scale));
+    add[i] = cts[i]->poly(0);
+    po[i] = outs.back()->buf.p;
+  }
+  k_moddown_final_ptr(sh, u.p, conv.p, add.data(), po.data(), level, (int)n, su, sc, (uint32_t)g,
+                      cx.stream);
+  return outs;
+}
+
+std::vector<CtPtr> rotsum_batch(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& cts) {
+  std::vector<CtPtr> cur;
+  for (const CtPtr& c : cts) cur.push_back(copy_ct(cx, *c));
+  if (cur.empty()) return cur;
+  for (int k = 0; (1 << k) < cx.P().slots(); ++k) {
+    std::vector<const Ciphertext*> v;
+    for (const CtPtr& c : cur) v.push_back(c.get());
+    auto r = rotate_batch(cx, evk, v, 1L << k);
+    for (size_t i = 0; i < cur.size(); ++i) cur[i] = add(cx, *cur[i], *r[i]);
+  }
+  return cur;
+}
+
 CtPtr rotsum(Context& cx, const EvalKeys& evk, const Ciphertext& a) {
   CtPtr ct = copy_ct(cx, a);
   for (int k = 0; (1 << k) < cx.P().slots(); ++k) {

@@ -56,7 +56,13 @@ std::vector<CtPtr> rotate_hoisted(Context& cx, const EvalKeys& evk, const Cipher
 std::vector<CtPtr> rotate_hoisted_batch(Context& cx, const EvalKeys& evk,
                                         const std::vector<const Ciphertext*>& cts,
                                         const std::vector<long>& rs);
+// rotate() of several ciphertexts of one level by the same step: one key
+// switch over the batch (the key read once per group of items)
+std::vector<CtPtr> rotate_batch(Context& cx, const EvalKeys& evk,
+                                const std::vector<const Ciphertext*>& cts, long r);
 CtPtr rotsum(Context& cx, const EvalKeys& evk, const Ciphertext& a);
+// rotsum() of several ciphertexts of one level, each step batched
+std::vector<CtPtr> rotsum_batch(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& cts);
 CtPtr level_align(Context& cx, const Ciphertext& a, int level);
 CtPtr copy_ct(Context& cx, const Ciphertext& a);
 

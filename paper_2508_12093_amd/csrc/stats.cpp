@@ -145,6 +145,120 @@ struct Circ {
     return sum({a1, a3, a5, a7});
   }
 
+  // ---- the same sequences over several independent operands ("lanes"):
+  // every lane performs exactly the operations of the one-operand helpers
+  // above, and the products and RotSums of equal level run as one batch.
+  std::vector<CtPtr> mulx_n(const std::vector<CtPtr>& a, const std::vector<CtPtr>& b) {
+    std::vector<CtPtr> A, B;
+    bool same = true;
+    for (size_t i = 0; i < a.size(); ++i) {
+      int m = std::min(a[i]->level, b[i]->level);
+      A.push_back(at(a[i], m));
+      B.push_back(at(b[i], m));
+      same = same && A[i]->level == A[0]->level;
+    }
+    if (!same || A.size() < 2) {
+      std::vector<CtPtr> out;
+      for (size_t i = 0; i < A.size(); ++i) out.push_back(mul(cx, evk, *A[i], *B[i]));
+      return out;
+    }
+    std::vector<const Ciphertext*> pa, pb;
+    for (size_t i = 0; i < A.size(); ++i) {
+      pa.push_back(A[i].get());
+      pb.push_back(B[i].get());
+    }
+    return mul_batch(cx, evk, pa, pb);
+  }
+  std::vector<CtPtr> rs_n(const std::vector<CtPtr>& xs) {
+    bool same = true;
+    for (auto& x : xs) same = same && x->level == xs[0]->level;
+    if (same && xs.size() > 1) return rotsum_batch(cx, evk, xs);
+    std::vector<CtPtr> out;
+    for (auto& x : xs) out.push_back(rs(x));
+    return out;
+  }
+
+  std::vector<CtPtr> mean_B_n(const std::vector<std::vector<CtPtr>>& Xs, size_t n,
+                              const std::vector<double>& Bs) {
+    std::vector<CtPtr> sums;
+    for (size_t l = 0; l < Xs.size(); ++l) {
+      const double c = 1.0 / (Bs[l] * (double)n);
+      std::vector<CtPtr> t;
+      for (auto& x : Xs[l]) t.push_back(mc(x, c));
+      sums.push_back(sum(t));
+    }
+    return rs_n(sums);
+  }
+
+  std::vector<CtPtr> variance_B_n(const std::vector<std::vector<CtPtr>>& Xs, size_t n,
+                                  const std::vector<double>& Bs,
+                                  const std::vector<CtPtr>& mean_terms) {
+    std::vector<CtPtr> xs;
+    std::vector<size_t> first;
+    for (size_t l = 0; l < Xs.size(); ++l) {
+      const double c = 1.0 / (Bs[l] * std::sqrt((double)n));
+      first.push_back(xs.size());
+      for (auto& x : Xs[l]) xs.push_back(mc(x, c));
+    }
+    auto sqs = mulx_n(xs, xs);
+    std::vector<CtPtr> sums;
+    for (size_t l = 0; l < Xs.size(); ++l)
+      sums.push_back(sum(std::vector<CtPtr>(sqs.begin() + first[l], sqs.begin() + first[l] + Xs[l].size())));
+    auto e2 = rs_n(sums);
+    auto m2 = mulx_n(mean_terms, mean_terms);
+    std::vector<CtPtr> out;
+    for (size_t l = 0; l < Xs.size(); ++l) out.push_back(subx(e2[l], m2[l]));
+    return out;
+  }
+
+  std::vector<std::pair<CtPtr, CtPtr>> inv_sqrt_n(const std::vector<CtPtr>& vs,
+                                                  const std::vector<double>& Bps,
+                                                  const InvSqrtCfg& cfg) {
+    const double a = cfg.a, b = cfg.b;
+    const int d = cfg.degree;
+    const size_t nl = vs.size();
+    std::vector<std::vector<double>> c(nl);
+    std::vector<std::vector<CtPtr>> T(nl, std::vector<CtPtr>(d + 1));
+    for (size_t l = 0; l < nl; ++l) {
+      c[l] = coeffs(cfg, Bps[l]);
+      if ((int)c[l].size() != d + 1) PPST_THROW(ST_EINVAL, "coefficient table does not match the degree");
+      T[l][1] = add_const(cx, *mc(vs[l], 2.0 / (b - a)), -(a + b) / (b - a));
+    }
+    auto lane = [&](int k) {
+      std::vector<CtPtr> v;
+      for (size_t l = 0; l < nl; ++l) v.push_back(T[l][k]);
+      return v;
+    };
+    for (int k = 2; k <= d; ++k) {
+      if (k % 2 == 0) {
+        const int m = k / 2;
+        auto p = mulx_n(lane(m), lane(m));
+        for (size_t l = 0; l < nl; ++l) T[l][k] = add_const(cx, *mul_int(cx, *p[l], 2), -1.0);
+      } else {
+        const int m = (k - 1) / 2;
+        auto p = mulx_n(lane(m), lane(m + 1));
+        for (size_t l = 0; l < nl; ++l) T[l][k] = subx(mul_int(cx, *p[l], 2), T[l][1]);
+      }
+    }
+    std::vector<CtPtr> y(nl), w2(nl);
+    for (size_t l = 0; l < nl; ++l) {
+      std::vector<CtPtr> terms;
+      for (int k = 1; k <= d; ++k) terms.push_back(mc(T[l][k], c[l][k]));
+      y[l] = add_const(cx, *sum(terms), c[l][0]);
+      T[l].clear();
+      w2[l] = mc(vs[l], Bps[l] / 2.0);
+    }
+    for (int it = 0; it < cfg.iters; ++it) {
+      auto y2 = mulx_n(y, y);
+      auto p1 = mulx_n(w2, y);
+      auto p2 = mulx_n(p1, y2);
+      for (size_t l = 0; l < nl; ++l) y[l] = subx(mc(y[l], 1.5), p2[l]);
+    }
+    std::vector<std::pair<CtPtr, CtPtr>> out;
+    for (size_t l = 0; l < nl; ++l) out.push_back({y[l], w2[l]});
+    return out;
+  }
+
   void check_depth(const std::vector<CtPtr>& X, int need) {
     for (auto& x : X)
       if (x->level < need)
@@ -300,18 +414,20 @@ CtPtr stat_pearson(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& X
   Circ c{cx, evk};
   c.check_depth(X, 3 + invsqrt_depth(cfg) + 1);
   c.check_depth(Y, 3 + invsqrt_depth(cfg) + 1);
-  auto muBx = c.mean_B(X, n, Bx);
-  auto varx = c.variance_B(X, n, Bx, muBx);
-  auto mux = c.mc(muBx, Bx);
-  auto muBy = c.mean_B(Y, n, By);
-  auto vary = c.variance_B(Y, n, By, muBy);
-  auto muy = c.mc(muBy, By);
-  std::vector<CtPtr> prods;
-  for (size_t i = 0; i < X.size(); ++i) prods.push_back(c.mulx(c.subx(X[i], mux), c.subx(Y[i], muy)));
-  auto cov = c.mask_mean(prods, n);
-  auto ix = c.inv_sqrt(varx, Bx * Bx, cfg).first;
-  auto iy = c.inv_sqrt(vary, By * By, cfg).first;
-  return c.mulx(cov, c.mulx(ix, iy));
+  // the x and y moments and inverse square roots side by side (each lane is
+  // the one-column sequence), then the covariance
+  auto muB = c.mean_B_n({X, Y}, n, {Bx, By});
+  auto var = c.variance_B_n({X, Y}, n, {Bx, By}, muB);
+  auto mux = c.mc(muB[0], Bx);
+  auto muy = c.mc(muB[1], By);
+  std::vector<CtPtr> dx, dy;
+  for (size_t i = 0; i < X.size(); ++i) {
+    dx.push_back(c.subx(X[i], mux));
+    dy.push_back(c.subx(Y[i], muy));
+  }
+  auto cov = c.mask_mean(c.mulx_n(dx, dy), n);
+  auto is = c.inv_sqrt_n(var, {Bx * Bx, By * By}, cfg);
+  return c.mulx(cov, c.mulx(is[0].first, is[1].first));
 }
 
 }  // namespace ppst

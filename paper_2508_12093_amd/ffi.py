@@ -127,6 +127,7 @@ _SIGS = {
     "ppst_level_align": (ctypes.c_int, [_vp, _vp, _i32, _pp]),
     "ppst_mul_batch": (ctypes.c_int, [_vp, _vp, _pp, _pp, _sz, _pp]),
     "ppst_rotate_hoisted_batch": (ctypes.c_int, [_vp, _vp, _pp, _sz, _vp, _sz, _pp]),
+    "ppst_rotate_batch": (ctypes.c_int, [_vp, _vp, _pp, _sz, ctypes.c_int32, _pp]),
     "ppst_graph_begin": (ctypes.c_int, [_vp]),
     "ppst_graph_end": (ctypes.c_int, [_vp, _pp]),
     "ppst_graph_launch": (ctypes.c_int, [_vp]),
@@ -508,6 +509,12 @@ def ppst_mul_batch(ctx, evk, a, b):
     outs = (ctypes.c_void_p * len(a))()
     _chk(lib().ppst_mul_batch(ctx, evk, _ptrs(a), _ptrs(b), len(a), outs))
     return [Ciphertext(outs[i], ctx) for i in range(len(a))]
+
+
+def ppst_rotate_batch(ctx, evk, cts, r):
+    outs = (ctypes.c_void_p * max(1, len(cts)))()
+    _chk(lib().ppst_rotate_batch(ctx, evk, _ptrs(cts), len(cts), r, outs))
+    return [Ciphertext(outs[i], ctx) for i in range(len(cts))]
 
 
 def ppst_rotate_hoisted_batch(ctx, evk, cts, steps):

@@ -190,6 +190,22 @@ def test_mul_batch_equals_single(pair):
         assert np.array_equal(ffi.ppst_ct_export(p.ctx, o), ffi.ppst_ct_export(p.ctx, single))
 
 
+def test_rotate_batch_equals_single(pair):
+    """Several ciphertexts rotated by one step in one key switch equal the
+    oracle's rotations bit for bit (and the identity step copies)."""
+    p = pair
+    cts, octs = [], []
+    for i in range(3):
+        c, o = p.encrypt(synth.uniform_column(97 + i, p.P.slots, -1, 1), 97 + i)
+        cts.append(c)
+        octs.append(o)
+    for r in (3, p.P.slots):
+        outs = ffi.ppst_rotate_batch(p.ctx, p.evk, cts, r)
+        for o, oc in zip(outs, octs):
+            p.same(o, p.O.rotate(oc, r, p.ogk) if r != p.P.slots else oc)
+    assert ffi.ppst_rotate_batch(p.ctx, p.evk, [], 3) == []
+
+
 def test_rotation_under_every_ntt_variant(pair):
     """Rotations read their input through the Galois permutation inside the
     first pass of the inverse NTT; every variant of that pass (LDS-staged and
