@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--quick", action="store_true", help="short run for profiling")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the roofline kernel and a copy of known size")
-    ap.add_argument("--only", choices=["plain", "batched"], default=None,
+    ap.add_argument("--only", choices=["plain", "batched", "pearson"], default=None,
                     help="time one form of the 64-product step alone (for kernel profiles)")
     ap.add_argument("--serving-queries", type=int, default=200,
                     help="queries per load point of the serving loop (0: skip)")
@@ -111,6 +111,21 @@ def main():
         outs = [ffi.ppst_mul(ctx, evk, cts[i], cts[(i + 1) % B]) for i in range(B)]
         return outs
 
+    if args.only == "pearson":
+        x, y = synth.binary_cost_pair(0)
+        cx = ffi.ppst_encrypt(ctx, pk, ffi.ppst_encode(ctx, x, L), 3001)
+        cy = ffi.ppst_encrypt(ctx, pk, ffi.ppst_encode(ctx, y, L), 3002)
+        cfg = ffi.ppst_invsqrt_cfg_default()
+        ffi.ppst_stat_pearson(ctx, evk, [cx], [cy], len(x), 1.0, 20.0, cfg)
+        sync()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            res = ffi.ppst_stat_pearson(ctx, evk, [cx], [cy], len(x), 1.0, 20.0, cfg)
+        sync()
+        ms = (time.perf_counter() - t) * 1e3 / args.steps
+        log("Pearson: %.2f ms" % ms)
+        print(json.dumps({"only": "pearson", "ms": round(ms, 3), "steps": args.steps}))
+        return
     if args.only:
         fn = step_mul if args.only == "plain" else (
             lambda: ffi.ppst_mul_batch(ctx, evk, cts, cts[1:] + cts[:1]))

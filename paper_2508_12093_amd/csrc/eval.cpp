@@ -423,15 +423,16 @@ Buf ks_accumulate(Context& cx, const KsKey& key, const u64* d, size_t sd, int le
   return u;
 }
 
-// Second half, plain: out (stride so) = (add0 + u0/P, add1 + u1/P) with the
-// rounding ModDown, for relinearisation and rotation.
-void ks_moddown(Context& cx, Buf& u, int level, const u64* add0, const u64* add1, size_t sa,
-                u64* out, size_t so, int nbatch, uint32_t gadd = 0) {
+// Second half, plain: for each item b, out[b] = (u/P rounded) + (add0[b],
+// add1[b]) [+ acc[b]] with the rounding ModDown; the final step runs in the
+// last pass of the conversion's NTT.  add0 is read through X -> X^gadd.
+void ks_moddown_ptr(Context& cx, Buf& u, int level, int nbatch, const u64* const* add0,
+                    const u64* const* add1, const u64* const* acc, u64* const* out,
+                    uint32_t gadd) {
   const Params& P = cx.P();
   const Shared& sh = *cx.sh;
   const int N = P.N, nl = level + 1, K = P.K, ne = nl + K;
-  const size_t sx = (size_t)nl * N, su = 2 * (size_t)ne * N, sc = 2 * (size_t)nl * N;
-  Buf conv = dev_buf(cx.pool, sc * nbatch);
+  const size_t su = 2 * (size_t)ne * N, sc = 2 * (size_t)nl * N;
   {
     NttLaunch L{};
     L.dst = u.p + (size_t)nl * N;
@@ -443,10 +444,23 @@ void ks_moddown(Context& cx, Buf& u, int level, const u64* add0, const u64* add1
     L.pofs = P.L + 1;
     ntt(sh, L, true, cx.stream);
   }
+  Buf conv = dev_buf(cx.pool, sc * nbatch);
   k_moddown_conv(sh, u.p, conv.p, level, nbatch, su, sc, cx.stream);
-  ntt_ct_limbs(cx, conv.p, nl, 2 * nbatch, sx, false);
-  k_moddown_final(sh, u.p, conv.p, add0, add1, out, level, nbatch, su, sc, sa, so, gadd,
-                  cx.stream);
+  MdTail t{u.p, su, add0, add1, acc, out, gadd};
+  ntt_fwd_md_final(sh, conv.p, level, nbatch, t, cx.stream);
+}
+
+// the same with addends and outputs at fixed strides (sa, so) from one base
+void ks_moddown(Context& cx, Buf& u, int level, const u64* add0, const u64* add1, size_t sa,
+                u64* out, size_t so, int nbatch, uint32_t gadd = 0) {
+  std::vector<const u64*> a0(nbatch), a1(nbatch);
+  std::vector<u64*> o(nbatch);
+  for (int b = 0; b < nbatch; ++b) {
+    a0[b] = add0 ? add0 + (size_t)b * sa : nullptr;
+    a1[b] = add1 ? add1 + (size_t)b * sa : nullptr;
+    o[b] = out + (size_t)b * so;
+  }
+  ks_moddown_ptr(cx, u, level, nbatch, a0.data(), a1.data(), nullptr, o.data(), gadd);
 }
 
 // g != 0: switch the key of the automorphism X -> X^g applied to d and add0
@@ -897,7 +911,6 @@ std::vector<CtPtr> rotate_hoisted(Context& cx, const EvalKeys& evk, const Cipher
   x.release();
   ntt_ext_digits(cx, ext.p, level, 1);
   Buf u = dev_buf(cx.pool, 2 * (size_t)ne * N);
-  Buf conv = dev_buf(cx.pool, 2 * per);
   for (long r : rs) {
     u64 g = galois_elt(P, r);
     if (g == 1) {
@@ -907,20 +920,10 @@ std::vector<CtPtr> rotate_hoisted(Context& cx, const EvalKeys& evk, const Cipher
     const KsKey& key = galois_key(evk, g);
     k_ks_inner(sh, a.poly(1), ext.p, key.k.p, u.p, level, 1, 0, 0, 0, (uint32_t)g, (uint32_t)g,
                cx.stream);
-    NttLaunch L{};
-    L.dst = u.p + per;
-    L.src = L.dst;
-    L.nlimbs = K;
-    L.nbatch = 2;
-    L.batch_stride = (size_t)ne * N;
-    L.nq = 0;
-    L.pofs = P.L + 1;
-    ntt(sh, L, true, cx.stream);
-    k_moddown_conv(sh, u.p, conv.p, level, 1, 0, 0, cx.stream);
-    ntt_ct_limbs(cx, conv.p, nl, 2, per, false);
     auto out = new_ct(cx, level, a.scale);
-    k_moddown_final(sh, u.p, conv.p, a.poly(0), nullptr, out->buf.p, level, 1, 0, 0, 0, 0,
-                    (uint32_t)g, cx.stream);
+    const u64* add0 = a.poly(0);
+    u64* op = out->buf.p;
+    ks_moddown_ptr(cx, u, level, 1, &add0, nullptr, nullptr, &op, (uint32_t)g);
     outs.push_back(out);
   }
   return outs;
@@ -973,9 +976,8 @@ std::vector<CtPtr> rotate_hoisted_batch(Context& cx, const EvalKeys& evk,
   // one rotation at a time over chunks of the batch: the key is read once
   // per group of items of the inner product
   const int chunk = (int)std::min<size_t>(n, kPtrBatch);
-  const size_t su = 2 * (size_t)ne * N, sc = 2 * per;
+  const size_t su = 2 * (size_t)ne * N;
   Buf u = dev_buf(cx.pool, su * chunk);
-  Buf conv = dev_buf(cx.pool, sc * chunk);
   for (size_t r = 0; r < m; ++r) {
     if (gs[r] == 1) {
       for (size_t i = 0; i < n; ++i) outs[i * m + r] = copy_ct(cx, *cts[i]);
@@ -986,17 +988,6 @@ std::vector<CtPtr> rotate_hoisted_batch(Context& cx, const EvalKeys& evk,
       const int nb = (int)std::min<size_t>(chunk, n - b0);
       k_ks_inner(sh, nullptr, ext.p + sext * b0, keys[r]->k.p, u.p, level, nb, 0, sext, su, g, g,
                  cx.stream);
-      NttLaunch L{};
-      L.dst = u.p + per;
-      L.src = L.dst;
-      L.nlimbs = K;
-      L.nbatch = 2 * nb;
-      L.batch_stride = (size_t)ne * N;
-      L.nq = 0;
-      L.pofs = P.L + 1;
-      ntt(sh, L, true, cx.stream);
-      k_moddown_conv(sh, u.p, conv.p, level, nb, su, sc, cx.stream);
-      ntt_ct_limbs(cx, conv.p, nl, 2 * nb, per, false);
       std::vector<const u64*> add(nb);
       std::vector<u64*> po(nb);
       for (int i = 0; i < nb; ++i) {
@@ -1005,14 +996,19 @@ std::vector<CtPtr> rotate_hoisted_batch(Context& cx, const EvalKeys& evk,
         po[i] = o->buf.p;
         outs[(b0 + i) * m + r] = o;
       }
-      k_moddown_final_ptr(sh, u.p, conv.p, add.data(), po.data(), level, nb, su, sc, g, cx.stream);
+      ks_moddown_ptr(cx, u, level, nb, add.data(), nullptr, nullptr, po.data(), g);
     }
   }
   return outs;
 }
 
-std::vector<CtPtr> rotate_batch(Context& cx, const EvalKeys& evk,
-                                const std::vector<const Ciphertext*>& cts, long r) {
+namespace {
+
+// rotate_batch; with accumulate, each output is cts[i] + rot(cts[i], r) (the
+// sum formed in the last pass of the ModDown conversion's NTT)
+std::vector<CtPtr> rotate_batch_impl(Context& cx, const EvalKeys& evk,
+                                     const std::vector<const Ciphertext*>& cts, long r,
+                                     bool accumulate) {
   const size_t n = cts.size();
   if (n == 0) return {};
   const Params& P = cx.P();
@@ -1025,45 +1021,47 @@ std::vector<CtPtr> rotate_batch(Context& cx, const EvalKeys& evk,
   const u64 g = galois_elt(P, r);
   std::vector<CtPtr> outs;
   if (g == 1) {
-    for (const Ciphertext* c : cts) outs.push_back(copy_ct(cx, *c));
+    for (const Ciphertext* c : cts) outs.push_back(accumulate ? add(cx, *c, *c) : copy_ct(cx, *c));
     return outs;
   }
   const KsKey& key = galois_key(evk, g);
-  const int N = P.N, nl = level + 1, K = P.K, ne = nl + K;
-  const size_t per = (size_t)nl * N, su = 2 * (size_t)ne * N, sc = 2 * per;
-  // the c1 polynomials side by side (one copy each), then one key switch
-  Buf d = dev_buf(cx.pool, per * n);
-  for (size_t i = 0; i < n; ++i)
-    HIP_CHECK(hipMemcpyAsync(d.p + per * i, cts[i]->poly(1), per * 8, hipMemcpyDeviceToDevice,
-                             cx.stream));
-  Buf u = ks_accumulate(cx, key, d.p, per, level, (int)n, (uint32_t)g);
-  d.release();
-  {
-    NttLaunch L{};
-    L.dst = u.p + per;
-    L.src = L.dst;
-    L.nlimbs = K;
-    L.nbatch = 2 * (int)n;
-    L.batch_stride = (size_t)ne * N;
-    L.nq = 0;
-    L.pofs = P.L + 1;
-    ntt(sh, L, true, cx.stream);
+  const int N = P.N, nl = level + 1;
+  const size_t per = (size_t)nl * N;
+  // the c1 polynomials side by side (one copy each unless there is one),
+  // then one key switch
+  Buf d;
+  const u64* dp = cts[0]->poly(1);
+  if (n > 1) {
+    d = dev_buf(cx.pool, per * n);
+    for (size_t i = 0; i < n; ++i)
+      HIP_CHECK(hipMemcpyAsync(d.p + per * i, cts[i]->poly(1), per * 8, hipMemcpyDeviceToDevice,
+                               cx.stream));
+    dp = d.p;
   }
-  Buf conv = dev_buf(cx.pool, sc * n);
-  k_moddown_conv(sh, u.p, conv.p, level, (int)n, su, sc, cx.stream);
-  ntt_ct_limbs(cx, conv.p, nl, 2 * (int)n, per, false);
-  std::vector<const u64*> add(n);
+  Buf u = ks_accumulate(cx, key, dp, per, level, (int)n, (uint32_t)g);
+  d.release();
+  std::vector<const u64*> add0(n), acc(n);
   std::vector<u64*> po(n);
   for (size_t i = 0; i < n; ++i) {
     outs.push_back(new_ct(cx, level, cts[i]->scale));
-    add[i] = cts[i]->poly(0);
+    add0[i] = cts[i]->poly(0);
+    acc[i] = cts[i]->buf.p;
     po[i] = outs.back()->buf.p;
   }
-  k_moddown_final_ptr(sh, u.p, conv.p, add.data(), po.data(), level, (int)n, su, sc, (uint32_t)g,
-                      cx.stream);
+  ks_moddown_ptr(cx, u, level, (int)n, add0.data(), nullptr, accumulate ? acc.data() : nullptr,
+                 po.data(), (uint32_t)g);
   return outs;
 }
 
+}  // namespace
+
+std::vector<CtPtr> rotate_batch(Context& cx, const EvalKeys& evk,
+                                const std::vector<const Ciphertext*>& cts, long r) {
+  return rotate_batch_impl(cx, evk, cts, r, false);
+}
+
+// ct <- ct + rot(ct, 2^k), k = 0.., with the addition fused into each
+// rotation's last pass (the same residues as a separate add)
 std::vector<CtPtr> rotsum_batch(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& cts) {
   std::vector<CtPtr> cur;
   for (const CtPtr& c : cts) cur.push_back(copy_ct(cx, *c));
@@ -1071,8 +1069,7 @@ std::vector<CtPtr> rotsum_batch(Context& cx, const EvalKeys& evk, const std::vec
   for (int k = 0; (1 << k) < cx.P().slots(); ++k) {
     std::vector<const Ciphertext*> v;
     for (const CtPtr& c : cur) v.push_back(c.get());
-    auto r = rotate_batch(cx, evk, v, 1L << k);
-    for (size_t i = 0; i < cur.size(); ++i) cur[i] = add(cx, *cur[i], *r[i]);
+    cur = rotate_batch_impl(cx, evk, v, 1L << k, true);
   }
   return cur;
 }
@@ -1080,8 +1077,8 @@ std::vector<CtPtr> rotsum_batch(Context& cx, const EvalKeys& evk, const std::vec
 CtPtr rotsum(Context& cx, const EvalKeys& evk, const Ciphertext& a) {
   CtPtr ct = copy_ct(cx, a);
   for (int k = 0; (1 << k) < cx.P().slots(); ++k) {
-    auto r = rotate(cx, evk, *ct, 1L << k);
-    ct = add(cx, *ct, *r);
+    std::vector<const Ciphertext*> v{ct.get()};
+    ct = rotate_batch_impl(cx, evk, v, 1L << k, true)[0];
   }
   return ct;
 }

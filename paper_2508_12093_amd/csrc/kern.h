@@ -37,6 +37,9 @@ constexpr int kPtrBatch = 64;
 struct OutPtrs {
   u64* p[kPtrBatch];
 };
+struct PtrsIn {
+  const u64* p[kPtrBatch];
+};
 
 // Forward NTT of the ModDown+rescale correction corr [nbatch][2][level][N]
 // (coefficient form, primes q_0..q_{level-1}) whose last pass stores, in
@@ -52,6 +55,25 @@ struct MdrTail {
 };
 void ntt_fwd_mdr_final(const Shared& sh, u64* corr, int level, int nbatch, const MdrTail& tail,
                        hipStream_t st);
+
+// Forward NTT of the ModDown conversion conv [nbatch][2][nl][N] (coefficient
+// form, primes q_0..q_l) whose last pass stores, in place of conv_i,
+//   out_i = ((u_i - conv_i) P^-1 mod q_i) [+ add_c,i(X^gadd)] [+ acc_c,i]
+// into out[b] ([2][nl][N]).  u: [nbatch][2][ne][N] at stride su; add0/add1:
+// per-item [nl][N] addends of c0/c1 (array or entries may be null), read
+// through X -> X^gadd when gadd != 0; acc: per-item [2][nl][N] running sums
+// (array or entries may be null).
+struct MdTail {
+  const u64* u;
+  size_t su;
+  const u64* const* add0;
+  const u64* const* add1;
+  const u64* const* acc;
+  u64* const* out;
+  uint32_t gadd;
+};
+void ntt_fwd_md_final(const Shared& sh, u64* conv, int level, int nbatch, const MdTail& tail,
+                      hipStream_t st);
 
 // ------------------------------------------------------- element-wise
 // All element-wise launches work on `npoly` polynomials of `nl` limbs,
@@ -93,12 +115,6 @@ void k_ks_inner(const Shared& sh, const u64* d, const u64* ext, const u64* key, 
 // both polynomials); conv[c][i] = Conv_{P->q_i}(z + h) - h mod q_i.
 void k_moddown_conv(const Shared& sh, const u64* u, u64* conv, int level, int nbatch,
                     size_t stride_u, size_t stride_conv, hipStream_t st);
-// out[c][i] = (u[c][i] - conv[c][i]) P^-1 mod q_i (+ add[c][i] when add_c != null;
-// add is read through X -> X^gadd when gadd != 0)
-void k_moddown_final(const Shared& sh, const u64* u, const u64* conv, const u64* add0,
-                     const u64* add1, u64* out, int level, int nbatch, size_t stride_u,
-                     size_t stride_conv, size_t stride_add, size_t stride_out, uint32_t gadd,
-                     hipStream_t st);
 
 // --------------------------------------- ModDown and rescale in one pass
 // After the key-switch inner product u (NTT form, [2][ne][N]) of a product
@@ -116,11 +132,6 @@ void k_mdr_prep(const Shared& sh, u64* u, const u64* d, int level, int nbatch, s
 void k_mdr_corr(const Shared& sh, const u64* u, u64* corr, int level, int nbatch, size_t su,
                 size_t sc, hipStream_t st);
 
-// k_moddown_final for nbatch items with the addend (c0 only) and the output
-// given as host arrays of device pointers ([nl][N] and [2][nl][N])
-void k_moddown_final_ptr(const Shared& sh, const u64* u, const u64* conv,
-                         const u64* const* add0, u64* const* out, int level, int nbatch,
-                         size_t stride_u, size_t stride_conv, uint32_t gadd, hipStream_t st);
 
 // ------------------------------------------------------------ rescale
 // top: coefficient-form top limb of each of npoly polynomials (stride

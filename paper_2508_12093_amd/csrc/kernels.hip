@@ -69,9 +69,6 @@ __global__ void k_mul_poly_kernel(const u64* __restrict__ a, const u64* __restri
 struct PtrBatch {
   const u64* p[kPtrBatch];
 };
-struct OutBatch {
-  u64* p[kPtrBatch];
-};
 
 __global__ void k_tensor_kernel(PtrBatch a, PtrBatch b, u64* d, const Mod* mods, int logN, int nl,
                                 size_t sd) {
@@ -277,55 +274,6 @@ k_moddown_conv_kernel(const u64* __restrict__ uin, u64* __restrict__ convout,
     u64 v = acc.reduce(m);
     conv[(size_t)i * N + k] = subm(v, md[lay.hmod(i)], m.q);
   }
-}
-
-__global__ void k_moddown_final_kernel(const u64* __restrict__ u, const u64* __restrict__ conv,
-                                       const u64* add0, const u64* add1, u64* out,
-                                       const Mod* mods, const u64* md, int K, int L, int logN,
-                                       int nl, int ne, size_t su, size_t sc, size_t sa,
-                                       size_t so, uint32_t gadd) {
-  size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  size_t per = (size_t)nl << logN;
-  if (r >= per) return;
-  const int c = blockIdx.z;
-  const size_t b = blockIdx.y;
-  const int i = (int)(r >> logN);
-  const u64 q = mods[i].q;
-  const MdLayout lay(K, L);
-  u64 x = u[b * su + (size_t)c * ((size_t)ne << logN) + r];
-  u64 y = conv[b * sc + (size_t)c * per + r];
-  u64 v = mul_shoup(subm(x, y, q), md[lay.pinv(i)], md[lay.pinv(i) + 1], q);
-  const u64* add = c ? add1 : add0;
-  if (add) {
-    const size_t kk = galois_src((uint32_t)(r & (((size_t)1 << logN) - 1)), gadd, logN);
-    v = addm(v, add[b * sa + ((size_t)i << logN) + kk], q);
-  }
-  out[b * so + (size_t)c * per + r] = v;
-}
-
-// k_moddown_final over batch items whose addend and output ciphertexts are
-// separate allocations: out_b[c][i] = (u - conv) P^-1 + add_b[c][i] read
-// through X -> X^gadd
-__global__ void k_moddown_final_ptr_kernel(const u64* __restrict__ u, const u64* __restrict__ conv,
-                                           PtrBatch add, OutBatch out, const Mod* mods,
-                                           const u64* md, int K, int L, int logN, int nl, int ne,
-                                           size_t su, size_t sc, uint32_t gadd) {
-  size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  size_t per = (size_t)nl << logN;
-  if (r >= per) return;
-  const int c = blockIdx.z;
-  const int b = blockIdx.y;
-  const int i = (int)(r >> logN);
-  const u64 q = mods[i].q;
-  const MdLayout lay(K, L);
-  u64 x = u[b * su + (size_t)c * ((size_t)ne << logN) + r];
-  u64 y = conv[b * sc + (size_t)c * per + r];
-  u64 v = mul_shoup(subm(x, y, q), md[lay.pinv(i)], md[lay.pinv(i) + 1], q);
-  if (c == 0) {
-    const size_t kk = galois_src((uint32_t)(r & (((size_t)1 << logN) - 1)), gadd, logN);
-    v = addm(v, add.p[b][((size_t)i << logN) + kk], q);
-  }
-  out.p[b][(size_t)c * per + r] = v;
 }
 
 // ------------------------------------------- ModDown and rescale together
@@ -694,43 +642,6 @@ void k_moddown_conv(const Shared& sh, const u64* u, u64* conv, int level, int nb
   else
     PPST_THROW(ST_EINVAL, "more than 8 special primes");
   LAUNCH_CHECK();
-}
-
-void k_moddown_final(const Shared& sh, const u64* u, const u64* conv, const u64* add0,
-                     const u64* add1, u64* out, int level, int nbatch, size_t su, size_t sc,
-                     size_t sa, size_t so, uint32_t gadd, hipStream_t st) {
-  const Params& P = sh.P;
-  int nl = level + 1;
-  dim3 g = grid_for((size_t)nl * P.N);
-  g.y = nbatch;
-  g.z = 2;
-  hipLaunchKernelGGL(k_moddown_final_kernel, g, dim3(kBlock), 0, st, u, conv, add0, add1, out,
-                     M(sh), sh.tab.moddown.p, P.K, P.L, P.logN, nl, nl + P.K, su, sc, sa, so,
-                     gadd);
-  LAUNCH_CHECK();
-}
-
-void k_moddown_final_ptr(const Shared& sh, const u64* u, const u64* conv,
-                         const u64* const* add0, u64* const* out, int level, int nbatch,
-                         size_t su, size_t sc, uint32_t gadd, hipStream_t st) {
-  const Params& P = sh.P;
-  const int nl = level + 1;
-  for (int b0 = 0; b0 < nbatch; b0 += kPtrBatch) {
-    const int nb = std::min(kPtrBatch, nbatch - b0);
-    PtrBatch pa{};
-    OutBatch po{};
-    for (int i = 0; i < nb; ++i) {
-      pa.p[i] = add0[b0 + i];
-      po.p[i] = out[b0 + i];
-    }
-    dim3 g = grid_for((size_t)nl * P.N);
-    g.y = nb;
-    g.z = 2;
-    hipLaunchKernelGGL(k_moddown_final_ptr_kernel, g, dim3(kBlock), 0, st, u + (size_t)b0 * su,
-                       conv + (size_t)b0 * sc, pa, po, M(sh), sh.tab.moddown.p, P.K, P.L, P.logN,
-                       nl, nl + P.K, su, sc, gadd);
-    LAUNCH_CHECK();
-  }
 }
 
 void k_mdr_prep(const Shared& sh, u64* u, const u64* d, int level, int nbatch, size_t su,

@@ -489,6 +489,91 @@ void run_row_mdr(const NttArgs& base, const MdrEpi& e, int nlimbs, int nbatch, h
   hipLaunchKernelGGL((k_ntt_row_mdr<LOGM, LOGE, SB>), grid, block, 0, st, a, e);
 }
 
+// ---- forward row pass that finishes a plain ModDown
+// For limb i of polynomial c of item b the stored element is
+//   v = ((u_i - conv_i) P^-1 mod q_i) [+ add_c,i read through X -> X^g] [+ acc_c,i]
+// (the final step of ModDown, the (d0, d1) or rotated c0 addend of
+// relinearisation and rotation, and the running sum of RotSum), in the order
+// of the separate final and addition kernels.
+struct MdEpi {
+  const u64* u;      // [item][2][ne][N] accumulators
+  size_t su;
+  PtrsIn add0, add1; // per item [nl][N] or null
+  PtrsIn acc;        // per item [2][nl][N] or null
+  OutPtrs out;       // per item [2][nl][N]
+  const u64* md;     // ModDown table
+  uint32_t gadd;
+  int K, L, nl, ne, logN;
+};
+
+template <int E>
+struct MdStore {
+  const u64* u;
+  const u64* add;
+  const u64* acc;
+  u64* out;
+  u64 q, pinv, pinvs;
+  uint32_t gadd;
+  int logN;
+  u64 pu[E], pa[E], pc[E];
+  __device__ __forceinline__ void prefetch(int i, size_t at) {
+    pu[i] = u[at];
+    pa[i] = add ? add[galois_src((uint32_t)at, gadd, logN)] : 0;
+    pc[i] = acc ? acc[at] : 0;
+  }
+  __device__ __forceinline__ void put(int i, size_t at, u64 conv) const {
+    u64 v = mul_shoup(subm(pu[i], conv, q), pinv, pinvs, q);
+    if (add) v = addm(v, pa[i], q);
+    if (acc) v = addm(pc[i], v, q);
+    out[at] = v;
+  }
+};
+
+template <int LOGM, int LOGE, int SB>
+__global__ void __launch_bounds__(SB * (1 << (LOGM - LOGE)))
+k_ntt_row_md(NttArgs a, MdEpi e) {
+  constexpr int M = 1 << LOGM;
+  __shared__ u64 lds[SB * (M + 1)];
+  const int N = a.N;
+  const BlockPos bp = block_pos(a.blocks_per_limb, a.nbatch);
+  const int t = bp.limb;                                 // limb = prime index, t < nl
+  const int grp = bp.grp;
+  const int item = bp.item >> 1, c = bp.item & 1;
+  const u64* src = a.src + (size_t)bp.item * a.batch_stride + (size_t)t * N;
+  const u64 q = a.mods[t].q;
+  const ulonglong2* tw = (const ulonglong2*)(a.tw + (size_t)t * N * 2);
+  const u64* ni = a.ninv + 2 * t;
+  const MdLayout lay(e.K, e.L);
+  MdStore<(1 << LOGE)> store;
+  store.u = e.u + (size_t)item * e.su + ((size_t)c * e.ne + t) * N;
+  const u64* add = c ? e.add1.p[item] : e.add0.p[item];
+  store.add = add ? add + (size_t)t * N : nullptr;
+  store.acc = e.acc.p[item] ? e.acc.p[item] + ((size_t)c * e.nl + t) * N : nullptr;
+  store.out = e.out.p[item] + ((size_t)c * e.nl + t) * N;
+  store.q = q;
+  store.pinv = e.md[lay.pinv(t)];
+  store.pinvs = e.md[lay.pinv(t) + 1];
+  store.gadd = e.gadd;
+  store.logN = e.logN;
+  const int first = grp * SB;
+  if (q < kFpPrimeBound)
+    ntt_body_dio<FpArith, LOGM, LOGE, SB, true, false>(FpArith(q), (double*)lds, src, store, tw,
+                                                        ni, N, a.logR, first, true, 0u, a.logN);
+  else
+    ntt_body_dio<IntArith, LOGM, LOGE, SB, true, false>(IntArith(q), lds, src, store, tw, ni, N,
+                                                         a.logR, first, true, 0u, a.logN);
+}
+
+template <int LOGM, int LOGE, int SB>
+void run_row_md(const NttArgs& base, const MdEpi& e, int nlimbs, int nbatch, hipStream_t st) {
+  NttArgs a = base;
+  a.blocks_per_limb = (1 << a.logR) / SB;
+  a.nbatch = nbatch;
+  dim3 grid(a.blocks_per_limb * nlimbs * nbatch);
+  dim3 block(SB * (1 << (LOGM - LOGE)));
+  hipLaunchKernelGGL((k_ntt_row_md<LOGM, LOGE, SB>), grid, block, 0, st, a, e);
+}
+
 typedef void (*PassFn)(const NttArgs&, int, int, hipStream_t);
 
 template <int LOGM, int LOGE, int SB, bool ROWS, bool INV, bool DIO>
@@ -681,6 +766,78 @@ void ntt_fwd_mdr_final(const Shared& sh, u64* corr, int level, int nbatch, const
     e.d = tail.d + (size_t)b0 * tail.sd;
     a.src = corr + (size_t)b0 * 2 * level * N;
     f(a, e, level, 2 * nb, st);
+  }
+  HIP_CHECK(hipGetLastError());
+}
+
+typedef void (*MdFn)(const NttArgs&, const MdEpi&, int, int, hipStream_t);
+
+static MdFn md_variant(int logN, int row_index) {
+  if (logN == 12) {
+    const int le = (row_index == 0 || row_index == 3) ? 4 : 3;
+    return le == 4 ? run_row_md<12, 4, 1> : run_row_md<12, 3, 1>;
+  }
+  switch (row_index) {
+    case 1: case 9: return run_row_md<8, 4, 4>;
+    case 2: case 8: return run_row_md<8, 3, 8>;
+    case 3: case 7: return run_row_md<8, 2, 4>;
+    default: return run_row_md<8, 3, 4>;
+  }
+}
+
+void ntt_fwd_md_final(const Shared& sh, u64* conv, int level, int nbatch, const MdTail& tail,
+                      hipStream_t st) {
+  const Params& P = sh.P;
+  if (nbatch <= 0) return;
+  const int nl = level + 1;
+  const size_t N = P.N;
+  NttArgs a{};
+  a.mods = (const Mod*)sh.tab.mods.p;
+  a.tw = sh.tab.fwd.p;
+  a.ninv = sh.tab.ninv.p;
+  a.N = P.N;
+  a.logN = P.logN;
+  a.nq = nl;
+  a.pofs = P.L + 1;
+  a.skip_lo = a.skip_hi = 1 << 30;
+  a.dalpha = 0;
+  a.dcount = 1;
+  a.dtotal = 0;
+  a.galois = 0;
+  a.batch_stride = a.dst_stride = (size_t)nl * N;
+  const int b = ntt_bucket(nl * 2 * nbatch);
+  const NttPlan& plan = sh.ntt_plan;
+  if (P.logN == 16) {
+    a.logR = 8;
+    a.src = conv;
+    a.dst = conv;
+    kCol16[plan.v[0][0][b]].fwd(a, nl, 2 * nbatch, st);
+  } else if (P.logN == 12) {
+    a.logR = 0;
+  } else {
+    PPST_THROW(ST_EINVAL, "NTT supports log2 N in {12, 16}");
+  }
+  const MdFn f = md_variant(P.logN, plan.v[0][1][b]);
+  MdEpi e{};
+  e.su = tail.su;
+  e.md = sh.tab.moddown.p;
+  e.gadd = tail.gadd;
+  e.K = P.K;
+  e.L = P.L;
+  e.nl = nl;
+  e.ne = nl + P.K;
+  e.logN = P.logN;
+  for (int b0 = 0; b0 < nbatch; b0 += kPtrBatch) {
+    const int nb = std::min(kPtrBatch, nbatch - b0);
+    for (int i = 0; i < nb; ++i) {
+      e.out.p[i] = tail.out[b0 + i];
+      e.add0.p[i] = tail.add0 ? tail.add0[b0 + i] : nullptr;
+      e.add1.p[i] = tail.add1 ? tail.add1[b0 + i] : nullptr;
+      e.acc.p[i] = tail.acc ? tail.acc[b0 + i] : nullptr;
+    }
+    e.u = tail.u + (size_t)b0 * tail.su;
+    a.src = conv + (size_t)b0 * 2 * nl * N;
+    f(a, e, nl, 2 * nb, st);
   }
   HIP_CHECK(hipGetLastError());
 }
