@@ -367,19 +367,21 @@ def serving_bench(ctx, pk, sk, evk, nq: int, loads, seed: int = 4):
             res.append(ffi.ppst_server_wait(srv, tickets[i]))
         th.join()
         wall = time.perf_counter() - t_start
-        assert all(r[0] == 0 for r in res), "a served query failed"
-        lat = np.array([(r[2].t_done - r[2].t_submit) * 1e3 for r in res])
-        return res, lat, wall
+        failed = [r[0] for r in res if r[0] != 0]
+        if failed:
+            log("serving: %d of %d queries failed (first status %d)" % (len(failed), len(res), failed[0]))
+        lat = np.array([(r[2].t_done - r[2].t_submit) * 1e3 for r in res if r[0] == 0])
+        return res, lat, wall, len(failed)
 
     # warm-up: every (kind, size) once
     run([(k, n) for k in kinds for n in SERVING_ROWS], None)
     sat_q = plan(nq)
-    res, lat, wall = run(sat_q, None)
+    res, lat, wall, nfail = run(sat_q, None)
     sat_rate = len(sat_q) / wall
     log("serving: saturation %.1f queries/s over %d queries" % (sat_rate, len(sat_q)))
     # spot-check decrypted values of the saturation run against FP64
     errs = []
-    for (q, r) in list(zip(sat_q, res))[:12]:
+    for (q, r) in [qr for qr in zip(sat_q, res) if qr[1][0] == 0][:12]:
         (kind, which, B, B2), n = q
         x, y = cols[n][2], cols[n][3]
         got = float(ffi.ppst_decode(ctx, ffi.ppst_decrypt(ctx, sk, r[1]))[0])
@@ -388,16 +390,18 @@ def serving_bench(ctx, pk, sk, evk, nq: int, loads, seed: int = 4):
     points = []
     for f in loads:
         rate = f * sat_rate
-        _, lat, wall = run(plan(nq), rate)
+        _, lat, wall, nf = run(plan(nq), rate)
+        nfail += nf
         points.append({"offered_qps": round(rate, 2), "achieved_qps": round(nq / wall, 2),
                        "p50_ms": round(float(np.percentile(lat, 50)), 2),
-                       "p99_ms": round(float(np.percentile(lat, 99)), 2), "queries": nq})
+                       "p99_ms": round(float(np.percentile(lat, 99)), 2), "queries": nq,
+                       "failed": nf})
         log("serving: offered %.1f q/s -> p50 %.1f ms, p99 %.1f ms" % (
             rate, points[-1]["p50_ms"], points[-1]["p99_ms"]))
     del srv
     return {"saturation_qps": round(sat_rate, 2), "queries_per_point": nq,
             "rows": SERVING_ROWS, "kinds": "mean,variance,zscore,cv,pearson", "slots": 8,
-            "loads": points, "spot_max_err": float(max(errs))}
+            "loads": points, "failed": nfail, "spot_max_err": float(max(errs)) if errs else None}
 
 
 # The roofline kernel is timed under a fixed variant pair (the one the

@@ -127,9 +127,23 @@ struct Hooks {
   void* user = nullptr;
 };
 
+class Pool;
+// Every pool of one set of device tables (all contexts forked from one
+// another, the key pool): when an allocation fails after a pool has freed its
+// own cache, the others free theirs too.
+class PoolRegistry {
+ public:
+  void add(const std::shared_ptr<Pool>& p);
+  void trim_others(const Pool* except);
+ private:
+  std::mutex mu_;
+  std::vector<std::weak_ptr<Pool>> pools_;
+};
+
 class Pool {
  public:
-  Pool(hipStream_t s, const Hooks& h) : stream_(s), hooks_(h) {}
+  Pool(hipStream_t s, const Hooks& h, std::shared_ptr<PoolRegistry> reg = nullptr)
+      : stream_(s), hooks_(h), registry_(std::move(reg)) {}
   ~Pool();
   void* get(size_t bytes);
   void put(void* p, size_t bytes);
@@ -146,6 +160,7 @@ class Pool {
  private:
   hipStream_t stream_;
   Hooks hooks_;
+  std::shared_ptr<PoolRegistry> registry_;
   std::mutex mu_;
   std::multimap<size_t, void*> free_;
   std::map<void*, size_t> sizes_;
@@ -208,6 +223,7 @@ struct Shared {
   NttPlan ntt_plan;
   int device = 0;
   Hooks hooks;
+  std::shared_ptr<PoolRegistry> pools = std::make_shared<PoolRegistry>();
   std::shared_ptr<Pool> const_pool;  // long-lived tables and keys
   Tables tab;
   u64 dg_thr[kDgMax];

@@ -1,6 +1,7 @@
 // eval.cpp -- context, tables, keys, encryption and the RNS-CKKS operations.
 #include "eval.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -47,7 +48,13 @@ void* Pool::get(size_t bytes) {
     if (capturing_)   // no synchronisation is possible while a recording is open
       PPST_THROW(ST_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
     trim();
-    if (!try_alloc()) {
+    bool ok = try_alloc();
+    if (!ok && registry_) {   // the caches of the other contexts' pools
+      (void)hipGetLastError();
+      registry_->trim_others(this);
+      ok = try_alloc();
+    }
+    if (!ok) {
       (void)hipGetLastError();
       PPST_THROW(ST_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
     }
@@ -109,8 +116,24 @@ void Pool::unpin(const std::vector<void*>& blocks) {
   }
 }
 
+void PoolRegistry::add(const std::shared_ptr<Pool>& p) {
+  std::lock_guard<std::mutex> g(mu_);
+  pools_.erase(std::remove_if(pools_.begin(), pools_.end(),
+                              [](const std::weak_ptr<Pool>& w) { return w.expired(); }),
+               pools_.end());
+  pools_.push_back(p);
+}
+
+void PoolRegistry::trim_others(const Pool* except) {
+  std::lock_guard<std::mutex> g(mu_);
+  for (auto& w : pools_)
+    if (auto p = w.lock())
+      if (p.get() != except) p->trim();
+}
+
 void Pool::trim() {
   std::lock_guard<std::mutex> g(mu_);
+  if (capturing_) return;   // a recording stream cannot be synchronised
   if (!free_.empty()) (void)hipStreamSynchronize(stream_);
   for (auto& kv : free_) {
     if (hooks_.free) hooks_.free(kv.second, kv.first, (void*)stream_, hooks_.user);
@@ -292,7 +315,8 @@ std::shared_ptr<Shared> make_shared_state(const ParamSpec& spec, const Hooks* ho
   sh->P = make_params(spec);
   HIP_CHECK(hipGetDevice(&sh->device));
   if (hooks) sh->hooks = *hooks;
-  sh->const_pool = std::make_shared<Pool>((hipStream_t)0, sh->hooks);
+  sh->const_pool = std::make_shared<Pool>((hipStream_t)0, sh->hooks, sh->pools);
+  sh->pools->add(sh->const_pool);
   dg_thresholds(sh->dg_thr);
   build_tables(*sh);
   HIP_CHECK(hipDeviceSynchronize());
@@ -317,7 +341,8 @@ std::unique_ptr<Context> make_context(std::shared_ptr<Shared> sh, hipStream_t st
     HIP_CHECK(hipStreamCreateWithFlags(&cx->stream, hipStreamNonBlocking));
     cx->own_stream = true;
   }
-  cx->pool = std::make_shared<Pool>(cx->stream, cx->sh->hooks);
+  cx->pool = std::make_shared<Pool>(cx->stream, cx->sh->hooks, cx->sh->pools);
+  cx->sh->pools->add(cx->pool);
   return cx;
 }
 

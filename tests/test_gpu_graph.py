@@ -88,3 +88,17 @@ def test_recording_refuses_host_calls(t1):
     with pytest.raises(ffi.PpstError) as e:
         ffi.ppst_graph_end(p.ctx)
     assert e.value.name == "EINVAL"
+
+
+def test_forked_contexts_overlap_and_agree(t1):
+    """Products issued round-robin on contexts forked onto their own streams
+    (as the 4-stream benchmark does) equal the one-stream results."""
+    p = t1
+    cts = [p.encrypt(synth.uniform_column(320 + i, p.P.slots, -1, 1), 320 + i)[0] for i in range(6)]
+    forks = [ffi.ppst_context_fork(p.ctx) for _ in range(3)]
+    got = [ffi.ppst_mul(forks[i % 3], p.evk, cts[i], cts[(i + 1) % 6]) for i in range(6)]
+    for f in forks:
+        ffi.ppst_sync(f)
+    for i in range(6):
+        want = ffi.ppst_mul(p.ctx, p.evk, cts[i], cts[(i + 1) % 6])
+        assert np.array_equal(_exp(p, got[i]), _exp(p, want)), i
