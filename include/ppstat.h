@@ -106,7 +106,10 @@ typedef struct ppst_ciphertext ppst_ciphertext;
  * hooks: may be NULL. */
 int ppst_context_create(const ppst_params* params, const ppst_device_hooks* hooks, void* stream,
                         ppst_context** out);
-/* A second context sharing tables with `base`, running on its own stream. */
+/* A second context sharing tables with `base`, running on its own stream.
+ * Work on different contexts is not ordered: an object made on one context
+ * may be used on another after ppst_sync of the first, and must not be
+ * destroyed while another context's queued work still reads it. */
 int ppst_context_fork(const ppst_context* base, void* stream, ppst_context** out);
 int ppst_context_destroy(ppst_context* ctx);
 /* waits for all work enqueued on the context's stream */
@@ -248,7 +251,8 @@ int ppst_mul_batch(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciph
  * context's stream), for callers that replay a fixed sequence many times.
  * Between ppst_graph_begin and ppst_graph_end the evaluation calls (add, sub,
  * add_const, mul_const, mul_int, mul_plain, mul, tensor, relin, rescale,
- * rotate, rotate_hoisted(_batch), rotsum, level_align, mul_batch) are
+ * rotate, rotate_batch, rotate_hoisted(_batch), rotsum, level_align,
+ * mul_batch) are
  * recorded, not run: their output handles are valid at once, and each
  * ppst_graph_launch writes them again.  Calls that wait for the device or
  * move data to or from the host (keygen, encode, encrypt, decrypt, exports,

@@ -207,6 +207,8 @@ struct Tables {
   std::map<int, std::shared_ptr<Buf>> modup;
   // ModDown constants (one table for all levels)
   Buf moddown;
+  // host copy of (P mod q_i, Shoup companion), i = 0..L, for kernel arguments
+  std::vector<u64> pmod_host;
   // rescale constants per level
   std::map<int, std::shared_ptr<Buf>> rescale;
   std::mutex mu;

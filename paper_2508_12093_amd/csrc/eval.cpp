@@ -236,6 +236,8 @@ void build_tables(Shared& sh) {
     for (int k = 0; k < K; ++k) pm = h_mulmod(pm, P.q[L + 1 + k] % qi, qi);
     md[lay.pmod(i)] = pm;
     md[lay.pmod(i) + 1] = shoup(pm, qi);
+    sh.tab.pmod_host.push_back(pm);
+    sh.tab.pmod_host.push_back(shoup(pm, qi));
   }
   for (int p = 0; p < np; ++p) {   // h = (P - 1) / 2 reduced mod every prime
     u64 q = P.q[p], pm = 1;
@@ -419,8 +421,11 @@ void ntt_ext_digits(Context& cx, u64* ext, int level, int nbatch) {
 // form, level l, nbatch items at stride sd), ModUp of every digit back to NTT
 // form, inner product with the key.  Returns the accumulators u,
 // [nbatch][2][ne][N] over q_0..q_l, p_0..p_{K-1}.
+// With prep_d (products), limb q_l of u also receives (P mod q_l) times the
+// tensor's d0, d1 (prep_d: [nbatch][3][nl][N] at stride sd), the first step
+// of the fused ModDown + rescale.
 Buf ks_accumulate(Context& cx, const KsKey& key, const u64* d, size_t sd, int level, int nbatch,
-                  uint32_t g = 0) {
+                  uint32_t g = 0, const u64* prep_d = nullptr) {
   const Params& P = cx.P();
   const Shared& sh = *cx.sh;
   const int N = P.N, nl = level + 1, K = P.K, ne = nl + K, beta = P.beta(level);
@@ -444,7 +449,8 @@ Buf ks_accumulate(Context& cx, const KsKey& key, const u64* d, size_t sd, int le
   k_modup(sh, x.p, ext.p, level, nbatch, sx, sext, cx.stream);
   x.release();
   ntt_ext_digits(cx, ext.p, level, nbatch);
-  k_ks_inner(sh, d, ext.p, key.k.p, u.p, level, nbatch, sd, sext, su, g, 0, cx.stream);
+  k_ks_inner(sh, d, ext.p, key.k.p, u.p, level, nbatch, sd, sext, su, g, 0, cx.stream, prep_d,
+             sd);
   return u;
 }
 
@@ -507,7 +513,6 @@ void ks_moddown_rescale(Context& cx, Buf& u, const u64* D, size_t sd, int level,
   const Shared& sh = *cx.sh;
   const int N = P.N, nl = level + 1, K = P.K, ne = nl + K;
   const size_t su = 2 * (size_t)ne * N, sc = 2 * (size_t)level * N;
-  k_mdr_prep(sh, u.p, D, level, nbatch, su, sd, cx.stream);
   {
     NttLaunch L{};                    // limbs q_l, p_0..p_{K-1} of both polynomials
     L.src = u.p;
@@ -893,7 +898,7 @@ CtPtr mul(Context& cx, const EvalKeys& evk, const Ciphertext& a, const Ciphertex
   const KsKey& key = relin_key(evk);
   const Params& P = cx.P();
   auto d = tensor(cx, a, b);
-  Buf u = ks_accumulate(cx, key, d->poly(2), 0, a.level, 1);
+  Buf u = ks_accumulate(cx, key, d->poly(2), 0, a.level, 1, 0, d->buf.p);
   auto out = new_ct(cx, a.level - 1, P.scale[a.level - 1]);
   u64* op = out->buf.p;
   ks_moddown_rescale(cx, u, d->buf.p, 0, a.level, &op, 1);
@@ -1147,7 +1152,7 @@ std::vector<CtPtr> mul_batch(Context& cx, const EvalKeys& evk,
   }
   Buf D = dev_buf(cx.pool, 3 * per * n);
   k_tensor(*cx.sh, pa.data(), pb.data(), D.p, nl, (int)n, 3 * per, cx.stream);
-  Buf u = ks_accumulate(cx, key, D.p + 2 * per, 3 * per, level, (int)n);
+  Buf u = ks_accumulate(cx, key, D.p + 2 * per, 3 * per, level, (int)n, 0, D.p);
   std::vector<CtPtr> outs;
   std::vector<u64*> po(n);
   for (size_t i = 0; i < n; ++i) {

@@ -108,9 +108,12 @@ void k_modup(const Shared& sh, const u64* x, u64* ext, int level, int nbatch, si
 // for t in digit j when d is null).
 // ext: [beta][ne][N] per batch item; u: [2][ne][N] per batch item.  With
 // gd / gext nonzero, d / ext are read through X -> X^g (canonical NTT order).
+// With prep_d non-null (products), limb q_l of u[c] also receives
+// (P mod q_l) prep_d[c][l] (prep_d: [nbatch][3][nl][N] at stride prep_sd).
 void k_ks_inner(const Shared& sh, const u64* d, const u64* ext, const u64* key, u64* u, int level,
                 int nbatch, size_t stride_d, size_t stride_ext, size_t stride_u, uint32_t gd,
-                uint32_t gext, hipStream_t st);
+                uint32_t gext, hipStream_t st, const u64* prep_d = nullptr,
+                size_t prep_sd = 0);
 // ModDown conversion: z = coefficient-form special limbs of u (u + nl*N, for
 // both polynomials); conv[c][i] = Conv_{P->q_i}(z + h) - h mod q_i.
 void k_moddown_conv(const Shared& sh, const u64* u, u64* conv, int level, int nbatch,
@@ -121,14 +124,12 @@ void k_moddown_conv(const Shared& sh, const u64* u, u64* conv, int level, int nb
 // whose tensor is d ([3][nl][N]), these steps produce rescale(d + ModDown(u))
 // bit for bit, with one NTT of the correction instead of a forward NTT after
 // ModDown and an inverse + forward NTT pair inside rescale:
-//   prep:  u[c][l] += (P mod q_l) d[c][l]                      (NTT form)
+//   prep:  u[c][l] += (P mod q_l) d[c][l]  (NTT form; in the inner product)
 //   (iNTT of limbs q_l, p_0..p_{K-1} of u)
 //   corr:  c_l = (u_l + h - Conv_l) P^-1 mod q_l, t = centred(c_l),
 //          corr_i = (h - Conv_i) P^-1 - t  mod q_i, i < l       (coefficient form)
 //   (NTT of corr, whose last pass stores, in ntt_fwd_mdr_final)
 //   final: out_i = (d_i + u_i P^-1 + corr_i) q_l^-1 mod q_i
-void k_mdr_prep(const Shared& sh, u64* u, const u64* d, int level, int nbatch, size_t su,
-                size_t sd, hipStream_t st);
 void k_mdr_corr(const Shared& sh, const u64* u, u64* corr, int level, int nbatch, size_t su,
                 size_t sc, hipStream_t st);
 

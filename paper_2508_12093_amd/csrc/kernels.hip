@@ -167,6 +167,11 @@ struct InnerArgs {
   size_t sd, sext, su;
   int logN, nl, ne, beta, alpha, pofs, nprimes, nbatch;
   uint32_t gd, gext;  // read d / ext through X -> X^g (0: as stored)
+  // products: limb q_l of u also receives (P mod q_l) d_c,l, with the tensor
+  // d at pd ([item][3][nl][N], stride spd; null otherwise)
+  const u64* pd;
+  size_t spd;
+  u64 pmod, pmods;    // P mod q_l and its Shoup companion
 };
 
 // ITEMS batch items per thread: one key load serves all of them
@@ -209,12 +214,19 @@ __global__ void __launch_bounds__(kBlock) k_ks_inner_kernel(InnerArgs a) {
     }
   }
   const Mod m = a.mods[p];
+  const bool prep = a.pd != nullptr && t == a.nl - 1;
 #pragma unroll
   for (int q = 0; q < kInnerItems; ++q) {
     if (q < nb) {
       u64* u = a.u + (size_t)(b0 + q) * a.su;
-      u[(size_t)t * N + k] = s0[q].reduce(m);
-      u[((size_t)a.ne + t) * N + k] = s1[q].reduce(m);
+      u64 v0 = s0[q].reduce(m), v1 = s1[q].reduce(m);
+      if (prep) {
+        const u64* d = a.pd + (size_t)(b0 + q) * a.spd + (size_t)t * N + k;
+        v0 = addm(v0, mul_shoup(d[0], a.pmod, a.pmods, m.q), m.q);
+        v1 = addm(v1, mul_shoup(d[(size_t)a.nl * N], a.pmod, a.pmods, m.q), m.q);
+      }
+      u[(size_t)t * N + k] = v0;
+      u[((size_t)a.ne + t) * N + k] = v1;
     }
   }
 }
@@ -277,21 +289,6 @@ k_moddown_conv_kernel(const u64* __restrict__ uin, u64* __restrict__ convout,
 }
 
 // ------------------------------------------- ModDown and rescale together
-__global__ void k_mdr_prep_kernel(u64* u, const u64* d, const Mod* mods, const u64* md, int K,
-                                  int L, int logN, int level, int ne, int nl, size_t su,
-                                  size_t sd) {
-  const size_t N = (size_t)1 << logN;
-  size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= N) return;
-  const int c = blockIdx.y;
-  const size_t b = blockIdx.z;
-  const MdLayout lay(K, L);
-  const u64 q = mods[level].q;
-  u64* ul = u + b * su + ((size_t)c * ne + level) * N;
-  const u64* dl = d + b * sd + ((size_t)c * nl + level) * N;
-  ul[k] = addm(ul[k], mul_shoup(dl[k], md[lay.pmod(level)], md[lay.pmod(level) + 1], q), q);
-}
-
 constexpr int kMdrChunk = 8;   // output limbs per thread
 
 template <int MAXK>
@@ -581,11 +578,18 @@ void k_modup(const Shared& sh, const u64* x, u64* ext, int level, int nbatch, si
 
 void k_ks_inner(const Shared& sh, const u64* d, const u64* ext, const u64* key, u64* u, int level,
                 int nbatch, size_t sd, size_t sext, size_t su, uint32_t gd, uint32_t gext,
-                hipStream_t st) {
+                hipStream_t st, const u64* prep_d, size_t prep_sd) {
   const Params& P = sh.P;
   InnerArgs a;
   a.gd = gd;
   a.gext = gext;
+  a.pd = prep_d;
+  a.spd = prep_sd;
+  a.pmod = a.pmods = 0;
+  if (prep_d) {
+    a.pmod = sh.tab.pmod_host[2 * level];
+    a.pmods = sh.tab.pmod_host[2 * level + 1];
+  }
   a.d = d;
   a.ext = ext;
   a.key = key;
@@ -641,17 +645,6 @@ void k_moddown_conv(const Shared& sh, const u64* u, u64* conv, int level, int nb
     hipLaunchKernelGGL(k_moddown_conv_kernel<8>, g, dim3(kBlock), 0, st, u, conv, M(sh), md, a);
   else
     PPST_THROW(ST_EINVAL, "more than 8 special primes");
-  LAUNCH_CHECK();
-}
-
-void k_mdr_prep(const Shared& sh, u64* u, const u64* d, int level, int nbatch, size_t su,
-                size_t sd, hipStream_t st) {
-  const Params& P = sh.P;
-  dim3 g = grid_for(P.N);
-  g.y = 2;
-  g.z = nbatch;
-  hipLaunchKernelGGL(k_mdr_prep_kernel, g, dim3(kBlock), 0, st, u, d, M(sh), sh.tab.moddown.p, P.K,
-                     P.L, P.logN, level, level + 1 + P.K, level + 1, su, sd);
   LAUNCH_CHECK();
 }
 
