@@ -532,35 +532,34 @@ void ks_moddown_rescale(Context& cx, Buf& u, const u64* D, size_t sd, int level,
   ntt_fwd_mdr_final(sh, corr.p, level, nbatch, tail, cx.stream);
 }
 
-// rescale nbatch ciphertexts of npoly polynomials (stride sa) into out (stride so)
-void rescale_raw(Context& cx, const u64* a, size_t sa, int level, int npoly, int nbatch, u64* out,
-                 size_t so) {
+// Rescale npoly polynomials at `level` (polynomial c at a + c pstride) into
+// out ([npoly][level][N]).  With k (host arrays of level+1 constant residues
+// and Shoup companions) the input is first multiplied by that constant; the
+// result is bit for bit rescale(k a).  The dropped limb is transformed out of
+// place, so the input is never copied or modified.
+void rescale_raw(Context& cx, const u64* a, size_t pstride, int level, int npoly, u64* out,
+                 const u64* k = nullptr, const u64* kp = nullptr) {
   const Params& P = cx.P();
   const Shared& sh = *cx.sh;
   const int N = P.N;
-  const int rows = npoly * nbatch;
-  Buf top = dev_buf(cx.pool, (size_t)rows * N);
-  Buf tmp = dev_buf(cx.pool, (size_t)rows * level * N);
-  // rows r = b * npoly + c: source poly at a + b sa + c (level+1) N
-  for (int b = 0; b < nbatch; ++b)
-    k_copy_rows(sh, a + b * sa + (size_t)level * N, top.p + (size_t)b * npoly * N, npoly,
-                (size_t)(level + 1) * N, N, cx.stream);
+  Buf top = dev_buf(cx.pool, (size_t)npoly * N);
+  Buf tmp = dev_buf(cx.pool, (size_t)npoly * level * N);
   {
     NttLaunch L{};
-    L.src = top.p;
+    L.src = a + (size_t)level * N;
     L.dst = top.p;
     L.nlimbs = 1;
-    L.nbatch = rows;
-    L.batch_stride = N;
+    L.nbatch = npoly;
+    L.batch_stride = pstride;
+    L.dst_stride = N;
     L.nq = 0;
     L.pofs = level;     // every row is on q_level
     ntt(sh, L, true, cx.stream);
   }
-  k_rescale_conv(sh, top.p, tmp.p, level, rows, N, cx.stream);
-  ntt_ct_limbs(cx, tmp.p, level, rows, (size_t)level * N, false);
-  for (int b = 0; b < nbatch; ++b)
-    k_rescale_final(sh, a + b * sa, tmp.p + (size_t)b * npoly * level * N, out + b * so, level,
-                    npoly, (size_t)(level + 1) * N, (size_t)level * N, cx.stream);
+  const u64 kl[2] = {k ? k[level] : 0, k ? kp[level] : 0};
+  k_rescale_conv(sh, top.p, tmp.p, level, npoly, N, cx.stream, k ? kl : nullptr);
+  RsTail tail{a, pstride, out, (size_t)level * N, rescale_table(sh, level), k, kp};
+  ntt_fwd_rescale_final(sh, tmp.p, level, npoly, tail, cx.stream);
 }
 
 void scalar_residues(const Params& P, int64_t k, int nl, std::vector<u64>& v, std::vector<u64>& vp) {
@@ -856,14 +855,19 @@ CtPtr rescale(Context& cx, const Ciphertext& a) {
   if (a.level < 1) PPST_THROW(ST_ELEVEL, "no level left to rescale");
   const Params& P = cx.P();
   auto out = new_ct(cx, a.level - 1, P.scale[a.level - 1], a.npoly);
-  rescale_raw(cx, a.buf.p, 0, a.level, a.npoly, 1, out->buf.p, 0);
+  rescale_raw(cx, a.buf.p, (size_t)(a.level + 1) * a.N, a.level, a.npoly, out->buf.p);
   return out;
 }
 
 CtPtr mul_const(Context& cx, const Ciphertext& a, double c) {
   if (a.level < 1) PPST_THROW(ST_ELEVEL, "no level left for a constant product");
-  auto t = mul_int(cx, a, const_int(cx.P(), c, a.level));
-  return rescale(cx, *t);
+  const Params& P = cx.P();
+  std::vector<u64> v, vp;
+  scalar_residues(P, const_int(P, c, a.level), a.level + 1, v, vp);
+  auto out = new_ct(cx, a.level - 1, P.scale[a.level - 1], a.npoly);
+  rescale_raw(cx, a.buf.p, (size_t)(a.level + 1) * a.N, a.level, a.npoly, out->buf.p, v.data(),
+              vp.data());
+  return out;
 }
 
 CtPtr mul_plain(Context& cx, const Ciphertext& a, const Plaintext& pt) {
@@ -1121,11 +1125,10 @@ CtPtr level_align(Context& cx, const Ciphertext& a, int level) {
   const int64_t K = llround((P.scale[level] * (double)P.q[level + 1]) / P.scale[a.level]);
   std::vector<u64> v, vp;
   scalar_residues(P, K, nl, v, vp);
-  auto t = new_ct(cx, level + 1, P.scale[level + 1], a.npoly);
-  k_mul_scalar(*cx.sh, a.buf.p, t->buf.p, a.npoly, nl, (size_t)(a.level + 1) * P.N,
-               (size_t)nl * P.N, v.data(), vp.data(), cx.stream);
+  // limbs q_0..q_{level+1} of a, multiplied by K and rescaled by q_{level+1}
   auto out = new_ct(cx, level, P.scale[level], a.npoly);
-  rescale_raw(cx, t->buf.p, 0, level + 1, a.npoly, 1, out->buf.p, 0);
+  rescale_raw(cx, a.buf.p, (size_t)(a.level + 1) * P.N, level + 1, a.npoly, out->buf.p, v.data(),
+              vp.data());
   return out;
 }
 

@@ -75,6 +75,23 @@ struct MdTail {
 void ntt_fwd_md_final(const Shared& sh, u64* conv, int level, int nbatch, const MdTail& tail,
                       hipStream_t st);
 
+// Forward NTT of a rescale's correction corr [npoly][l][N] (coefficient form,
+// primes q_0..q_{l-1}) whose last pass stores, for limb i of polynomial c,
+//   out_c,i = ((k_i a_c,i or a_c,i) - corr_c,i) q_l^-1 mod q_i
+// (a_c at a + c sa, out_c at out + c so; k, kp: host arrays of l constant
+// residues and their Shoup companions, or null; rc: the rescale table of l).
+struct RsTail {
+  const u64* a;
+  size_t sa;
+  u64* out;
+  size_t so;
+  const u64* rc;
+  const u64* k;
+  const u64* kp;
+};
+void ntt_fwd_rescale_final(const Shared& sh, u64* corr, int level, int npoly, const RsTail& tail,
+                           hipStream_t st);
+
 // ------------------------------------------------------- element-wise
 // All element-wise launches work on `npoly` polynomials of `nl` limbs,
 // polynomial c at base + c * poly_stride; limb t uses prime map(t).
@@ -136,12 +153,11 @@ void k_mdr_corr(const Shared& sh, const u64* u, u64* corr, int level, int nbatch
 
 // ------------------------------------------------------------ rescale
 // top: coefficient-form top limb of each of npoly polynomials (stride
-// top_stride); tmp[c][i] = centred(top_c) mod q_i for i < level.
+// top_stride); tmp[c][i] = centred(x_c) mod q_i for i < level, where
+// x_c = top_c, or k top_c mod q_level when kl (host: k and its Shoup
+// companion) is given.
 void k_rescale_conv(const Shared& sh, const u64* top, u64* tmp, int level, int npoly,
-                    size_t top_stride, hipStream_t st);
-// out[c][i] = (a[c][i] - tmp[c][i]) q_level^-1 mod q_i, i < level
-void k_rescale_final(const Shared& sh, const u64* a, const u64* tmp, u64* out, int level,
-                     int npoly, size_t stride_a, size_t stride_out, hipStream_t st);
+                    size_t top_stride, hipStream_t st, const u64* kl = nullptr);
 
 // ------------------------------------------------------- sampling etc.
 // signed 64-bit integers -> residues on limbs t of a map
@@ -161,9 +177,5 @@ void k_keyform(const Shared& sh, const u64* a, const u64* s, const u64* e, const
 // out = x + y * z (+ w when w != null) on nl limbs of the ciphertext primes
 void k_fma3(const Shared& sh, const u64* x, const u64* y, const u64* z, const u64* w, u64* out,
             int nl, hipStream_t st);
-
-// limb-wise copy of nrows rows of N words (strided)
-void k_copy_rows(const Shared& sh, const u64* src, u64* dst, int nrows, size_t sstride,
-                 size_t dstride, hipStream_t st);
 
 }  // namespace ppst

@@ -338,7 +338,8 @@ k_mdr_corr_kernel(const u64* __restrict__ u, u64* __restrict__ corr, const Mod* 
 
 // ------------------------------------------------------------------ rescale
 __global__ void k_rescale_conv_kernel(const u64* __restrict__ top, u64* tmp, const Mod* mods,
-                                      const u64* rc, int logN, int level, size_t ts) {
+                                      const u64* rc, int logN, int level, size_t ts, int mulk,
+                                      u64 kl, u64 klp) {
   const size_t N = (size_t)1 << logN;
   size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= (size_t)level * N) return;
@@ -347,23 +348,11 @@ __global__ void k_rescale_conv_kernel(const u64* __restrict__ top, u64* tmp, con
   const size_t k = r & (N - 1);
   const u64 ql = mods[level].q;
   u64 x = top[c * ts + k];
+  if (mulk) x = mul_shoup(x, kl, klp, ql);
   const Mod m = mods[i];
   u64 v = reduce64(x, m);
   if (x > (ql >> 1)) v = subm(v, rc[3 * i + 2], m.q);   // centred: x - q_l
   tmp[((size_t)c * level << logN) + r] = v;
-}
-
-__global__ void k_rescale_final_kernel(const u64* __restrict__ a, const u64* __restrict__ tmp,
-                                       u64* out, const Mod* mods, const u64* rc, int logN,
-                                       int level, size_t sa, size_t so) {
-  size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  size_t per = (size_t)level << logN;
-  if (r >= per) return;
-  const int c = blockIdx.y;
-  const int i = (int)(r >> logN);
-  const u64 q = mods[i].q;
-  u64 v = subm(a[c * sa + r], tmp[c * per + r], q);
-  out[c * so + r] = mul_shoup(v, rc[3 * i], rc[3 * i + 1], q);
 }
 
 // ----------------------------------------------------------------- sampling
@@ -465,14 +454,6 @@ __global__ void k_fma3_kernel(const u64* x, const u64* y, const u64* z, const u6
   u64 v = addm(x[r], mulm(y[r], z[r], m), m.q);
   if (w) v = addm(v, w[r], m.q);
   out[r] = v;
-}
-
-__global__ void k_copy_rows_kernel(const u64* src, u64* dst, int logN, int nrows, size_t ss,
-                                   size_t ds) {
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ((size_t)nrows << logN)) return;
-  size_t row = i >> logN, k = i & (((size_t)1 << logN) - 1);
-  dst[row * ds + k] = src[row * ss + k];
 }
 
 const Mod* M(const Shared& sh) { return (const Mod*)sh.tab.mods.p; }
@@ -668,20 +649,12 @@ void k_mdr_corr(const Shared& sh, const u64* u, u64* corr, int level, int nbatch
 }
 
 void k_rescale_conv(const Shared& sh, const u64* top, u64* tmp, int level, int npoly,
-                    size_t top_stride, hipStream_t st) {
+                    size_t top_stride, hipStream_t st, const u64* kl) {
   dim3 g = grid_for((size_t)level * sh.P.N);
   g.y = npoly;
   hipLaunchKernelGGL(k_rescale_conv_kernel, g, dim3(kBlock), 0, st, top, tmp, M(sh),
-                     rescale_table(sh, level), sh.P.logN, level, top_stride);
-  LAUNCH_CHECK();
-}
-
-void k_rescale_final(const Shared& sh, const u64* a, const u64* tmp, u64* out, int level,
-                     int npoly, size_t sa, size_t so, hipStream_t st) {
-  dim3 g = grid_for((size_t)level * sh.P.N);
-  g.y = npoly;
-  hipLaunchKernelGGL(k_rescale_final_kernel, g, dim3(kBlock), 0, st, a, tmp, out, M(sh),
-                     rescale_table(sh, level), sh.P.logN, level, sa, so);
+                     rescale_table(sh, level), sh.P.logN, level, top_stride, kl ? 1 : 0,
+                     kl ? kl[0] : 0, kl ? kl[1] : 0);
   LAUNCH_CHECK();
 }
 
@@ -745,13 +718,6 @@ void k_fma3(const Shared& sh, const u64* x, const u64* y, const u64* z, const u6
             int nl, hipStream_t st) {
   hipLaunchKernelGGL(k_fma3_kernel, grid_for((size_t)nl * sh.P.N), dim3(kBlock), 0, st, x, y, z,
                      w, out, M(sh), sh.P.logN, nl);
-  LAUNCH_CHECK();
-}
-
-void k_copy_rows(const Shared& sh, const u64* src, u64* dst, int nrows, size_t ss, size_t ds,
-                 hipStream_t st) {
-  hipLaunchKernelGGL(k_copy_rows_kernel, grid_for((size_t)nrows * sh.P.N), dim3(kBlock), 0, st,
-                     src, dst, sh.P.logN, nrows, ss, ds);
   LAUNCH_CHECK();
 }
 

@@ -574,6 +574,78 @@ void run_row_md(const NttArgs& base, const MdEpi& e, int nlimbs, int nbatch, hip
   hipLaunchKernelGGL((k_ntt_row_md<LOGM, LOGE, SB>), grid, block, 0, st, a, e);
 }
 
+// ---- forward row pass that finishes a rescale
+// For limb i < l of polynomial c the stored element is
+//   ((k_i a_c,i or a_c,i) - corr_i) q_l^-1 mod q_i
+// where corr is the transformed centred lift of the dropped limb and k an
+// optional constant multiplier (Mul(P) by a constant, level alignment) —
+// the operations of the separate scalar-product and final kernels.
+struct RsEpi {
+  const u64* a;      // polynomial c at a + c sa (limbs 0..l)
+  size_t sa;
+  u64* out;          // polynomial c at out + c so (limbs 0..l-1)
+  size_t so;
+  const u64* rc;     // rescale table of level l
+  int mulk;
+  u64 k[kMaxPrimes], kp[kMaxPrimes];
+};
+
+template <int E>
+struct RsStore {
+  const u64* a;
+  u64* out;
+  u64 q, qlinv, qlinvs, k, kp;
+  int mulk;
+  u64 pa[E];
+  __device__ __forceinline__ void prefetch(int i, size_t at) { pa[i] = a[at]; }
+  __device__ __forceinline__ void put(int i, size_t at, u64 corr) const {
+    const u64 x = mulk ? mul_shoup(pa[i], k, kp, q) : pa[i];
+    out[at] = mul_shoup(subm(x, corr, q), qlinv, qlinvs, q);
+  }
+};
+
+template <int LOGM, int LOGE, int SB>
+__global__ void __launch_bounds__(SB * (1 << (LOGM - LOGE)))
+k_ntt_row_rs(NttArgs a, RsEpi e) {
+  constexpr int M = 1 << LOGM;
+  __shared__ u64 lds[SB * (M + 1)];
+  const int N = a.N;
+  const BlockPos bp = block_pos(a.blocks_per_limb, a.nbatch);
+  const int t = bp.limb;                                 // limb = prime index, t < l
+  const int grp = bp.grp;
+  const int c = bp.item;
+  const u64* src = a.src + (size_t)c * a.batch_stride + (size_t)t * N;
+  const u64 q = a.mods[t].q;
+  const ulonglong2* tw = (const ulonglong2*)(a.tw + (size_t)t * N * 2);
+  const u64* ni = a.ninv + 2 * t;
+  RsStore<(1 << LOGE)> store;
+  store.a = e.a + (size_t)c * e.sa + (size_t)t * N;
+  store.out = e.out + (size_t)c * e.so + (size_t)t * N;
+  store.q = q;
+  store.qlinv = e.rc[3 * t];
+  store.qlinvs = e.rc[3 * t + 1];
+  store.mulk = e.mulk;
+  store.k = e.k[t];
+  store.kp = e.kp[t];
+  const int first = grp * SB;
+  if (q < kFpPrimeBound)
+    ntt_body_dio<FpArith, LOGM, LOGE, SB, true, false>(FpArith(q), (double*)lds, src, store, tw,
+                                                        ni, N, a.logR, first, true, 0u, a.logN);
+  else
+    ntt_body_dio<IntArith, LOGM, LOGE, SB, true, false>(IntArith(q), lds, src, store, tw, ni, N,
+                                                         a.logR, first, true, 0u, a.logN);
+}
+
+template <int LOGM, int LOGE, int SB>
+void run_row_rs(const NttArgs& base, const RsEpi& e, int nlimbs, int nbatch, hipStream_t st) {
+  NttArgs a = base;
+  a.blocks_per_limb = (1 << a.logR) / SB;
+  a.nbatch = nbatch;
+  dim3 grid(a.blocks_per_limb * nlimbs * nbatch);
+  dim3 block(SB * (1 << (LOGM - LOGE)));
+  hipLaunchKernelGGL((k_ntt_row_rs<LOGM, LOGE, SB>), grid, block, 0, st, a, e);
+}
+
 typedef void (*PassFn)(const NttArgs&, int, int, hipStream_t);
 
 template <int LOGM, int LOGE, int SB, bool ROWS, bool INV, bool DIO>
@@ -839,6 +911,68 @@ void ntt_fwd_md_final(const Shared& sh, u64* conv, int level, int nbatch, const 
     a.src = conv + (size_t)b0 * 2 * nl * N;
     f(a, e, nl, 2 * nb, st);
   }
+  HIP_CHECK(hipGetLastError());
+}
+
+typedef void (*RsFn)(const NttArgs&, const RsEpi&, int, int, hipStream_t);
+
+static RsFn rs_variant(int logN, int row_index) {
+  if (logN == 12) {
+    const int le = (row_index == 0 || row_index == 3) ? 4 : 3;
+    return le == 4 ? run_row_rs<12, 4, 1> : run_row_rs<12, 3, 1>;
+  }
+  switch (row_index) {
+    case 1: case 9: return run_row_rs<8, 4, 4>;
+    case 2: case 8: return run_row_rs<8, 3, 8>;
+    case 3: case 7: return run_row_rs<8, 2, 4>;
+    default: return run_row_rs<8, 3, 4>;
+  }
+}
+
+void ntt_fwd_rescale_final(const Shared& sh, u64* corr, int level, int npoly, const RsTail& tail,
+                           hipStream_t st) {
+  const Params& P = sh.P;
+  if (level < 1 || npoly <= 0) return;
+  if (level > kMaxPrimes) PPST_THROW(ST_EINVAL, "too many limbs");
+  const size_t N = P.N;
+  NttArgs a{};
+  a.mods = (const Mod*)sh.tab.mods.p;
+  a.tw = sh.tab.fwd.p;
+  a.ninv = sh.tab.ninv.p;
+  a.N = P.N;
+  a.logN = P.logN;
+  a.nq = level;
+  a.pofs = P.L + 1;
+  a.skip_lo = a.skip_hi = 1 << 30;
+  a.dalpha = 0;
+  a.dcount = 1;
+  a.dtotal = 0;
+  a.galois = 0;
+  a.batch_stride = a.dst_stride = (size_t)level * N;
+  a.src = corr;
+  a.dst = corr;
+  const int b = ntt_bucket(level * npoly);
+  const NttPlan& plan = sh.ntt_plan;
+  if (P.logN == 16) {
+    a.logR = 8;
+    kCol16[plan.v[0][0][b]].fwd(a, level, npoly, st);
+  } else if (P.logN == 12) {
+    a.logR = 0;
+  } else {
+    PPST_THROW(ST_EINVAL, "NTT supports log2 N in {12, 16}");
+  }
+  RsEpi e{};
+  e.a = tail.a;
+  e.sa = tail.sa;
+  e.out = tail.out;
+  e.so = tail.so;
+  e.rc = tail.rc;
+  e.mulk = tail.k != nullptr;
+  for (int i = 0; i < level && tail.k; ++i) {
+    e.k[i] = tail.k[i];
+    e.kp[i] = tail.kp[i];
+  }
+  rs_variant(P.logN, plan.v[0][1][b])(a, e, level, npoly, st);
   HIP_CHECK(hipGetLastError());
 }
 
