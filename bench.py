@@ -245,6 +245,27 @@ def main():
     log("Pearson p50 %.2f ms p99 %.2f ms, value %.6f (fp64 %.6f)" % (
         np.percentile(lat, 50), np.percentile(lat, 99), pcc, ref_pcc))
 
+    # ------------------- CryptoInvSqrt replay of Sec. 6.2, Exp. 1 (Tab. 2 row)
+    # 32768-point grid on [0.001, 100], B = 100, Eq. 3's degree-31 Chebyshev
+    # initial value on [0, 2] and six Newton steps: 20 levels, no bootstrap.
+    grid = synth.exp1_grid(info.slots)
+    cg = ffi.ppst_encrypt(ctx, pk, ffi.ppst_encode(ctx, grid, L), 3003)
+    e1cfg = ffi.ppst_invsqrt_cfg_default(a=0.0, b=2.0, degree=31, iters=6)
+    e1lat, e1 = [], None
+    for r in range(args.pearson_runs + 1):
+        sync()
+        t = time.perf_counter()
+        e1 = ffi.ppst_stat_invsqrt(ctx, evk, [cg], 100.0, e1cfg)[0]
+        sync()
+        if r > 0:
+            e1lat.append((time.perf_counter() - t) * 1e3)
+    e1v = ffi.ppst_decode(ctx, ffi.ppst_decrypt(ctx, sk, e1))
+    e1_mre = float(np.mean(np.abs(e1v * np.sqrt(grid) - 1.0)))
+    e1_p50 = float(np.percentile(e1lat, 50))
+    log("Exp. 1 CryptoInvSqrt (32768 points, degree 31, 6 Newton): p50 %.2f ms, MRE %.3e" % (
+        e1_p50, e1_mre))
+    del cg, e1
+
     serving = None
     if args.serving_queries > 0:
         loads = [float(v) for v in args.serving_loads.split(",") if v]
@@ -283,6 +304,8 @@ def main():
         "pearson_value": pcc,
         "pearson_rel_err": abs(pcc - ref_pcc) / abs(ref_pcc),
         "hmult_max_slot_err": hmult_err,
+        "exp1_invsqrt_p50_ms": round(e1_p50, 3),
+        "exp1_invsqrt_mre": e1_mre,
         "roofline": rf,
     }
     if serving is not None:

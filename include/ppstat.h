@@ -283,6 +283,16 @@ typedef struct {
 /* a, b = 1e-3, 1; degree 7; 3 iterations; sign_k 2; coeffs NULL */
 int ppst_invsqrt_cfg_default(ppst_invsqrt_cfg* out);
 
+/* CryptoInvSqrt slot by slot (Sec. 4, Alg. 2-3; Sec. 6.2, Exp. 1): each of
+ * the nct ciphertexts x (one level) is scaled to v = x/B and its inverse
+ * square root InvSqrt(v; B) ~ 1/sqrt(x) written to outs[i] (caller frees).
+ * Consumes 1 + (1 + ceil(log2(degree + 1)) + 1 + 2 iters) levels; a Chebyshev
+ * degree of up to 511 holds degree + 1 ciphertexts per input while it runs.
+ * B > 0; the interval needs 0 <= a < b (a = 0, b = 2 is Eq. 1's domain map). */
+int ppst_stat_invsqrt(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciphertext* const* x,
+                      size_t nct, double B, const ppst_invsqrt_cfg* cfg,
+                      ppst_ciphertext** outs /* nct */);
+
 /* A column is `nct` ciphertexts at one level holding `nrows` values (slots
  * past nrows are zero).  Each statistic writes ciphertexts whose every slot
  * holds the result (ZNorm: one output per input ciphertext).

@@ -61,17 +61,23 @@ def g3(x):
 G3_COEFFS = {1: 35.0 / 16.0, 3: -35.0 / 16.0, 5: 21.0 / 16.0, 7: -5.0 / 16.0}
 
 
-def exp1_grid() -> np.ndarray:
-    """Experiment 1 (Sec. 6.2): 16384 points on [0.001, 1] and 16384 on [1, 100]."""
-    return np.concatenate([np.linspace(0.001, 1.0, 16384), np.linspace(1.0, 100.0, 16384)])
+def exp1_grid(n: int = 32768) -> np.ndarray:
+    """Experiment 1 (Sec. 6.2): n/2 evenly spaced points on [0.001, 1] and
+    n/2 on [1, 100] (16384 each in the paper)."""
+    h = n // 2
+    return np.concatenate([np.linspace(0.001, 1.0, h), np.linspace(1.0, 100.0, n - h)])
+
+
+def exp1_model(v: np.ndarray, degree: int = 31, iters: int = 6, B: float = 100.0) -> np.ndarray:
+    """FP64 model of Tab. 2's CryptoInvSqrt row: Chebyshev initial value of
+    Eq. 3 on x = v/B - 1, then `iters` Newton steps on v."""
+    c = paper_invsqrt_coeffs(degree, B)
+    return newton_invsqrt(v, C.chebval(v / B - 1.0, c), iters)
 
 
 def exp1_mre(degree: int = 31, iters: int = 6, B: float = 100.0) -> float:
-    """FP64 model of Tab. 2's CryptoInvSqrt row: Chebyshev initial value of
-    Eq. 3 on x = v/B - 1, then `iters` Newton steps on v; MRE over the grid."""
+    """MRE of ``exp1_model`` against 1/sqrt(v) over the Exp. 1 grid."""
     v = exp1_grid()
-    c = paper_invsqrt_coeffs(degree, B)
-    y0 = C.chebval(v / B - 1.0, c)
-    y = newton_invsqrt(v, y0, iters)
+    y = exp1_model(v, degree, iters, B)
     ref = 1.0 / np.sqrt(v)
     return float(np.mean(np.abs(y - ref) / np.abs(ref)))

@@ -16,6 +16,7 @@ Circuits (paper references):
   mean_B      Mean(x, B) = sum x_i / (B n)                           Sec. 5.1
   variance_B  Variance(x, B) = sum (x_i / (B sqrt n))^2 - Mean(x,B)^2  Sec. 5.1, Eq. 2
   inv_sqrt    Chebyshev initial value (Alg. 3, Eq. 3) + Newton (Alg. 2, n = 2)
+  invsqrt     CryptoInvSqrt of x / B slot by slot (Sec. 6.2, Exp. 1)
   zscore      Alg. 4;  kurtosis Alg. 5;  skewness (mirror of Alg. 5, Sec. 5)
   cv          Alg. 6 with a g_3-composition sign (Sec. 6.2)
   pearson     Sec. 5.5: Cov * InvSqrt(Var x) * InvSqrt(Var y)
@@ -237,6 +238,12 @@ class Circuits:
             p2 = self.mulx(p1, y2)
             y = self.subx(ev.mul_const(y, 1.5), p2)
         return y, w2
+
+    def invsqrt(self, X, B, cfg: InvSqrtCfg):
+        """CryptoInvSqrt of every slot (Sec. 4, Alg. 2-3; Sec. 6.2, Exp. 1):
+        v = x / B (the scaling of the input domain), y = InvSqrt(v; B), so
+        y ~ 1/sqrt(x).  One output per input ciphertext."""
+        return [self.inv_sqrt(self.ev.mul_const(x, 1.0 / B), B, cfg)[0] for x in X]
 
     def sqrt(self, v, Bp, cfg: InvSqrtCfg):
         """sqrt(Bp v) = 2 * w2 * InvSqrt(v; Bp)."""

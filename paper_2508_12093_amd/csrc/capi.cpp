@@ -735,6 +735,15 @@ int ppst_stat_variance(ppst_context* ctx, const ppst_eval_keys* evk,
     *out = wrap(stat_variance(*ctx->cx, evk->e, column(col, nct), nrows, B));
   });
 }
+int ppst_stat_invsqrt(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciphertext* const* x,
+                      size_t nct, double B, const ppst_invsqrt_cfg* cfg, ppst_ciphertext** outs) {
+  return guard([&] {
+    NEED(ctx); NEED(evk); NEED(outs);
+    NOT_RECORDING(ctx);
+    auto v = stat_invsqrt(*ctx->cx, evk->e, column(x, nct), B, cfg_from(cfg));
+    for (size_t i = 0; i < v.size(); ++i) outs[i] = wrap(v[i]);
+  });
+}
 int ppst_stat_zscore(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciphertext* const* col,
                      size_t nct, size_t nrows, double B, const ppst_invsqrt_cfg* cfg,
                      ppst_ciphertext** outs) {

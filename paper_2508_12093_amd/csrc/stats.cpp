@@ -278,8 +278,9 @@ void check_column(const Params& P, const std::vector<CtPtr>& X, size_t nrows) {
 }
 
 void check_cfg(const InvSqrtCfg& cfg) {
-  if (!(cfg.a > 0.0) || !(cfg.b > cfg.a)) PPST_THROW(ST_EDOMAIN, "InvSqrt interval needs 0 < a < b");
-  if (cfg.degree < 1 || cfg.degree > 63) PPST_THROW(ST_EDOMAIN, "Chebyshev degree out of range");
+  if (!(cfg.a >= 0.0) || !(cfg.b > cfg.a)) PPST_THROW(ST_EDOMAIN, "InvSqrt interval needs 0 <= a < b");
+  if (cfg.degree < 1 || cfg.degree > kMaxChebDegree)
+    PPST_THROW(ST_EDOMAIN, "Chebyshev degree out of range");
   if (cfg.iters < 0 || cfg.iters > 16) PPST_THROW(ST_EDOMAIN, "Newton iteration count out of range");
 }
 
@@ -325,6 +326,23 @@ CtPtr stat_variance(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& 
   c.check_depth(X, 2);
   auto mu = c.mean_B(X, n, B);
   return c.variance_B(X, n, B, mu);
+}
+
+std::vector<CtPtr> stat_invsqrt(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& X,
+                                double B, const InvSqrtCfg& cfg) {
+  if (X.empty()) PPST_THROW(ST_EINVAL, "no input ciphertexts");
+  if (!(B > 0.0) || !std::isfinite(B)) PPST_THROW(ST_EDOMAIN, "B must be positive");
+  for (auto& x : X)
+    if (x->level != X[0]->level) PPST_THROW(ST_ESCALE, "input ciphertexts at different levels");
+  check_cfg(cfg);
+  Circ c{cx, evk};
+  c.check_depth(X, 1 + invsqrt_depth(cfg));
+  std::vector<CtPtr> vs;
+  for (auto& x : X) vs.push_back(c.mc(x, 1.0 / B));
+  auto r = c.inv_sqrt_n(vs, std::vector<double>(X.size(), B), cfg);
+  std::vector<CtPtr> out;
+  for (auto& p : r) out.push_back(p.first);
+  return out;
 }
 
 std::vector<CtPtr> stat_zscore(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& X,

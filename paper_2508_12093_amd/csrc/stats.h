@@ -5,6 +5,11 @@
 
 namespace ppst {
 
+// Largest Chebyshev degree of the InvSqrt initial value (2^9 - 1, Sec. 5.1).
+// The ladder keeps every T_k of a ciphertext until the weighted sum, so a
+// degree-d initial value holds d + 1 ciphertexts per input at once.
+constexpr int kMaxChebDegree = 511;
+
 struct InvSqrtCfg {
   double a = 1e-3, b = 1.0;    // interval of the Chebyshev initial value
   int degree = 7;              // Chebyshev degree
@@ -19,6 +24,9 @@ std::vector<double> chebyshev_invsqrt(double a, double b, int degree, double Bp)
 CtPtr stat_mean(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& X, size_t n, double B);
 CtPtr stat_variance(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& X, size_t n,
                     double B);
+// CryptoInvSqrt slot by slot: InvSqrt(x / B; B) ~ 1/sqrt(x), one output per input
+std::vector<CtPtr> stat_invsqrt(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& X,
+                                double B, const InvSqrtCfg& cfg);
 std::vector<CtPtr> stat_zscore(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& X,
                                size_t n, double B, const InvSqrtCfg& cfg);
 CtPtr stat_kurtosis(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& X, size_t n,

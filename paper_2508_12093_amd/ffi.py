@@ -135,6 +135,7 @@ _SIGS = {
     "ppst_invsqrt_cfg_default": (ctypes.c_int, [_cfgp]),
     "ppst_stat_mean": (ctypes.c_int, [_vp, _vp, _pp, _sz, _sz, _dbl, _pp]),
     "ppst_stat_variance": (ctypes.c_int, [_vp, _vp, _pp, _sz, _sz, _dbl, _pp]),
+    "ppst_stat_invsqrt": (ctypes.c_int, [_vp, _vp, _pp, _sz, _dbl, _cfgp, _pp]),
     "ppst_stat_zscore": (ctypes.c_int, [_vp, _vp, _pp, _sz, _sz, _dbl, _cfgp, _pp]),
     "ppst_stat_kurtosis": (ctypes.c_int, [_vp, _vp, _pp, _sz, _sz, _dbl, _cfgp, _i32, _pp]),
     "ppst_stat_skewness": (ctypes.c_int, [_vp, _vp, _pp, _sz, _sz, _dbl, _cfgp, _pp]),
@@ -567,6 +568,13 @@ def ppst_stat_variance(ctx, evk, col, nrows, B):
     out = _out()
     _chk(lib().ppst_stat_variance(ctx, evk, _ptrs(col), len(col), nrows, B, ctypes.byref(out)))
     return Ciphertext(out.value, ctx)
+
+
+def ppst_stat_invsqrt(ctx, evk, xs, B, cfg=None):
+    outs = (ctypes.c_void_p * len(xs))()
+    cfg = cfg or ppst_invsqrt_cfg_default()
+    _chk(lib().ppst_stat_invsqrt(ctx, evk, _ptrs(xs), len(xs), B, ctypes.byref(cfg), outs))
+    return [Ciphertext(outs[i], ctx) for i in range(len(xs))]
 
 
 def ppst_stat_zscore(ctx, evk, col, nrows, B, cfg=None):

@@ -6,6 +6,7 @@ from here, so every side sees the same numbers for the same seed.
 
 Workloads (sizes as the paper's experiments, data synthetic because the
 paper's datasets are not available here):
+  * ``exp1_grid``          the evenly spaced [0.001, 100] grid of Sec. 6.2 (Exp. 1)
   * ``uniform_column``     values ~ U[lo, hi) (Sec. 6.3 draws on [0,100] / [0,20])
   * ``binary_cost_pair``   a binary attribute x ~ Bernoulli(p) and a heavy-tailed
                            cost y = (exp(N(9, 0.8)) + s x) / 1000 with s chosen
@@ -19,6 +20,13 @@ from __future__ import annotations
 import math
 
 import numpy as np
+
+
+def exp1_grid(n: int = 32768) -> np.ndarray:
+    """The inverse-square-root test grid of Sec. 6.2 (Exp. 1): n/2 evenly
+    spaced points on [0.001, 1] and n/2 on [1, 100] (32768 in the paper)."""
+    h = n // 2
+    return np.concatenate([np.linspace(0.001, 1.0, h), np.linspace(1.0, 100.0, n - h)])
 
 
 def uniform_column(seed: int, n: int, lo: float = 0.0, hi: float = 1.0) -> np.ndarray:

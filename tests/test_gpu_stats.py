@@ -112,6 +112,31 @@ def test_t2_closed_forms(t2):
     assert abs(p.decrypt(ffi.ppst_stat_skewness(p.ctx, p.evk, [cs], n, 1.0, p.cfg))[0]) < TOL
 
 
+def _exp1_cfgs():
+    """Exp. 1 (Sec. 6.2): Eq. 3's degree-31 Chebyshev initial value on the
+    domain map [0, 2] -> [-1, 1], six Newton steps; the same table both sides."""
+    base = cheb.paper_invsqrt_coeffs(31, 1.0)
+    return (ffi.ppst_invsqrt_cfg_default(coeffs=base, a=0.0, b=2.0, degree=31, iters=6),
+            C.InvSqrtCfg(a=0.0, b=2.0, degree=31, iters=6, coeffs=base))
+
+
+def test_t2_invsqrt_bit_exact(t2):
+    """CryptoInvSqrt on two ciphertexts (evaluated side by side by the
+    library, one after the other by the oracle): bit-exact, 20 levels."""
+    p = t2
+    cfg, ocfg = _exp1_cfgs()
+    v = cheb.exp1_grid(p.P.slots)
+    c1, o1 = p.encrypt(v, 701)
+    c2_, o2 = p.encrypt(v[::-1].copy(), 702)
+    print("[stats] invsqrt degree 31, 6 Newton steps", flush=True)
+    got = ffi.ppst_stat_invsqrt(p.ctx, p.evk, [c1, c2_], 100.0, cfg)
+    want = p.cc.invsqrt([o1, o2], 100.0, ocfg)
+    assert want[0].level == p.P.L - 20
+    p.same(got[0], want[0])
+    p.same(got[1], want[1])
+    assert np.max(np.abs(p.decrypt(got[0]) / cheb.exp1_model(v) - 1)) < 1e-4
+
+
 def test_t2_depth_errors(t2):
     p = t2
     x = synth.uniform_column(9, 100)
@@ -165,3 +190,20 @@ def test_c2_config2_statistics_within_tolerance(c2):
         assert rel(got[k], want[k]) < TOL, k
     z = dec(ffi.ppst_stat_zscore(ctx, evk, [cy], n, 20.0, cfg)[0])
     assert S.mre(z, S.zscore(y)) < TOL
+
+
+def test_c2_exp1_invsqrt_replay(c2):
+    """Tab. 2's CryptoInvSqrt row at the paper's parameters without
+    bootstrapping: the 32768-point grid on [0.001, 100], B = 100, degree 31,
+    six Newton steps fit 20 of the 24 levels; the decrypted MRE against
+    1/sqrt(x) equals the FP64 model's (5.11e-5; printed 5.08e-5)."""
+    ctx, sk, pk, evk = c2
+    cfg, _ = _exp1_cfgs()
+    v = cheb.exp1_grid()
+    ct = ffi.ppst_encrypt(ctx, pk, ffi.ppst_encode(ctx, v, 24), 801)
+    y = ffi.ppst_stat_invsqrt(ctx, evk, [ct], 100.0, cfg)[0]
+    got = ffi.ppst_decode(ctx, ffi.ppst_decrypt(ctx, sk, y))
+    ref = 1.0 / np.sqrt(v)
+    mre, model = S.mre(got, ref), S.mre(cheb.exp1_model(v), ref)
+    print("[stats] Exp. 1 replay: MRE %.4e (FP64 model %.4e)" % (mre, model), flush=True)
+    assert abs(mre - model) < 1e-6

@@ -108,6 +108,26 @@ def test_plain_circuits_match_fp64_and_depths():
     assert depth == {"zscore": 14, "kurt": 16, "skew": 16, "cv": 22, "pcc": 15}
 
 
+def _exp1_cfg():
+    """Exp. 1 (Sec. 6.2): Eq. 3's Chebyshev initial value, degree 31 on the
+    domain map [0, 2] -> [-1, 1], six Newton steps."""
+    return C.InvSqrtCfg(a=0.0, b=2.0, degree=31, iters=6,
+                        coeffs=cheb.paper_invsqrt_coeffs(31, 1.0))
+
+
+def test_plain_invsqrt_circuit_is_exp1_model():
+    """The CryptoInvSqrt circuit (v = x/B, then InvSqrt(v; B)) in FP64 with
+    levels equals the closed-form Tab. 2 model slot by slot, reaches the
+    printed MRE, and consumes 20 of the 24 levels (no bootstrapping)."""
+    v = cheb.exp1_grid()
+    assert np.array_equal(v, synth.exp1_grid())     # the benchmark's input
+    ev = C.PlainEval(24, len(v))
+    y = C.Circuits(ev).invsqrt([ev.fresh(v)], 100.0, _exp1_cfg())[0]
+    assert np.max(np.abs(y.v / cheb.exp1_model(v) - 1)) < 1e-9
+    assert abs(S.mre(y.v, 1.0 / np.sqrt(v)) / GOLD["exp1_cryptoinvsqrt_mre"]["value"] - 1) < 0.01
+    assert 24 - y.level == 20
+
+
 # ------------------------------------------------------ encrypted circuits
 @pytest.fixture(scope="module")
 def t2():
@@ -151,6 +171,24 @@ def test_encrypted_closed_forms(t2):
     sym = np.concatenate([half, 1.0 - half])   # symmetric about 0.5
     es = O.encrypt(O.encode(sym), pk, 303)
     assert abs(O.decrypt(cc.skewness([es], n, 1.0, cfg), sk)[0]) < 1e-3
+
+
+@pytest.mark.slow
+def test_encrypted_invsqrt_exp1(t2):
+    """Encrypted CryptoInvSqrt on a 2048-point version of the Exp. 1 grid:
+    each slot within 1e-4 of the FP64 model (the ladder and the unconverged
+    Newton steps near x = 0.001 amplify the encryption noise to about 3e-5;
+    elsewhere 1e-8), MRE against 1/sqrt(x) that of the model to 1e-6, 20
+    levels consumed."""
+    P, O, sk, pk, cc = t2
+    v = cheb.exp1_grid(P.slots)
+    y = cc.invsqrt([O.encrypt(O.encode(v), pk, 401)], 100.0, _exp1_cfg())[0]
+    assert y.level == P.L - 20
+    got = O.decrypt(y, sk)
+    model = cheb.exp1_model(v)
+    assert np.max(np.abs(got / model - 1)) < 1e-4
+    ref = 1.0 / np.sqrt(v)
+    assert abs(S.mre(got, ref) - S.mre(model, ref)) < 1e-6
 
 
 def test_config1_mean_variance():
