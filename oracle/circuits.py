@@ -42,7 +42,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import cheb
-from .ref import Ciphertext, Oracle, galois_element
+from .ref import Ciphertext, Oracle
 
 
 @dataclass
@@ -328,7 +328,3 @@ class Circuits:
         ix, _ = self.inv_sqrt(varx, Bx * Bx, cfg)
         iy, _ = self.inv_sqrt(vary, By * By, cfg)
         return self.mulx(cov, ev.mul(ix, iy))
-
-
-def rotsum_galois(N: int):
-    return [galois_element(1 << k, N) for k in range((N // 2).bit_length() - 1)]

@@ -892,6 +892,58 @@ void orc_rotate_hoisted(const orc_params* P, int level, const u64* ct, const u64
     free(u0); free(u1); free(pc0);
 }
 
+/* One step of rotate-and-sum with every key switch hoisted: the extended
+ * digits of c1 are formed once, each rotation r (Galois element gs[r])
+ * permutes them and takes its inner product with its key, the products are
+ * added in the extended basis and one rounding ModDown divides the sum by P:
+ *   out = (c0 + sum_r phi_r(c0), c1) + ModDown(sum_r u_r).
+ * Up to the rounding of that single ModDown this is ct + sum_r rot_r(ct). */
+void orc_rotsum_step(const orc_params* P, int level, const u64* ct, const u64* const* keys,
+                     const u64* gs, int nk, u64* out) {
+    int N = P->N, L = P->L, K = P->K, nl = level + 1, ne = nl + K;
+    size_t sz = (size_t)ne * N;
+    u64* acc0 = (u64*)calloc(sz, sizeof(u64));
+    u64* acc1 = (u64*)calloc(sz, sizeof(u64));
+    u64* t0 = (u64*)malloc(sizeof(u64) * sz);
+    u64* t1 = (u64*)malloc(sizeof(u64) * sz);
+    for (int r = 0; r < nk; r++) {
+        ks_accumulate(P, level, ct + (size_t)nl * N, keys[r], gs[r], t0, t1);
+        for (int t = 0; t < ne; t++) {
+            u64 q = P->q[t < nl ? t : L + 1 + (t - nl)];
+            for (int k = 0; k < N; k++) {
+                size_t o = (size_t)t * N + k;
+                acc0[o] = addmod(acc0[o], t0[o], q);
+                acc1[o] = addmod(acc1[o], t1[o], q);
+            }
+        }
+    }
+    u64* u0 = (u64*)malloc(sizeof(u64) * (size_t)nl * N);
+    u64* u1 = (u64*)malloc(sizeof(u64) * (size_t)nl * N);
+    ks_moddown(P, level, acc0, acc1, u0, u1);
+    int32_t qidx[ORC_MAXP];
+    seq_pidx(qidx, nl);
+    u64* pc0 = t0;   /* reuse: nl*N <= ne*N */
+    for (int i = 0; i < nl; i++) {
+        u64 q = P->q[i];
+        for (int k = 0; k < N; k++) {
+            size_t o = (size_t)i * N + k;
+            out[o] = addmod(ct[o], u0[o], q);
+            out[(size_t)nl * N + o] = addmod(ct[(size_t)nl * N + o], u1[o], q);
+        }
+    }
+    for (int r = 0; r < nk; r++) {
+        orc_automorph_ntt(P, ct, pc0, nl, qidx, gs[r]);
+        for (int i = 0; i < nl; i++) {
+            u64 q = P->q[i];
+            for (int k = 0; k < N; k++) {
+                size_t o = (size_t)i * N + k;
+                out[o] = addmod(out[o], pc0[o], q);
+            }
+        }
+    }
+    free(acc0); free(acc1); free(t0); free(t1); free(u0); free(u1);
+}
+
 /* ------------------------------------------------------------------ */
 /* small helpers for the Python front end                              */
 /* ------------------------------------------------------------------ */

@@ -107,6 +107,7 @@ def lib():
             "orc_tensor": (None, [PP, vp, vp, ctypes.c_int, vp]),
             "orc_rescale": (None, [PP, vp, ctypes.c_int, ctypes.c_int, vp]),
             "orc_rotate_hoisted": (None, [PP, ctypes.c_int, vp, vp, u64, vp]),
+            "orc_rotsum_step": (None, [PP, ctypes.c_int, vp, vp, vp, ctypes.c_int, vp]),
             "orc_round_half_away": (i64, [dbl]),
             "orc_mulmod_vec": (None, [vp, vp, vp, ctypes.c_int, u64]),
             "orc_splitmix64_next": (u64, [u64]),
@@ -252,8 +253,19 @@ class Oracle:
         return {galois_element(r, self.P.N): self.galois_key(sk, seed, galois_element(r, self.P.N))
                 for r in steps}
 
+    def rotsum_plan(self):
+        """Steps (s, radix) of RotSum over the N/2 slots: radix 4 while two or
+        more bits of the slot index remain, then radix 2."""
+        plan, b = [], 0
+        while (1 << b) < self.P.slots:
+            rad = 4 if (1 << (b + 2)) <= self.P.slots else 2
+            plan.append((1 << b, rad))
+            b += 2 if rad == 4 else 1
+        return plan
+
     def rotsum_steps(self):
-        return [1 << k for k in range(self.P.logN - 1)]
+        """Rotation steps whose Galois keys RotSum needs: k s, 0 < k < radix."""
+        return [k * s for s, rad in self.rotsum_plan() for k in range(1, rad)]
 
     # ------------------------------------------------------------- encoding
     def encode_coeffs(self, m, scale: float) -> np.ndarray:
@@ -483,12 +495,25 @@ class Oracle:
             outs.append(Ciphertext(out, a.level, a.scale))
         return outs
 
+    def rotsum_step(self, a: Ciphertext, s: int, radix: int, gkeys: dict) -> Ciphertext:
+        """ct + sum_{0<k<radix} rot(ct, k s), the key switches hoisted: one
+        ModUp of c1, the permuted inner products added in the extended basis,
+        one ModDown (``orc_rotsum_step``)."""
+        P = self.P
+        gs = np.array([galois_element(k * s, P.N) for k in range(1, radix)], dtype=np.uint64)
+        keys = [np.ascontiguousarray(gkeys[int(g)]) for g in gs]
+        ptrs = (ctypes.c_void_p * len(keys))(*[k.ctypes.data for k in keys])
+        out = np.zeros_like(a.data)
+        self.L.orc_rotsum_step(P.ref, a.level, _p(np.ascontiguousarray(a.data)), ptrs, _p(gs),
+                               len(keys), _p(out))
+        return Ciphertext(out, a.level, a.scale)
+
     def rotsum(self, a: Ciphertext, gkeys: dict) -> Ciphertext:
-        """For k = 0..log2(slots)-1: ct <- ct + rot(ct, 2^k); every slot then
-        holds the sum of all slots."""
+        """Rotate-and-sum: every slot ends up holding the sum of all slots.
+        Steps of ``rotsum_plan``: ct <- ct + sum_{0<k<radix} rot(ct, k s)."""
         ct = a
-        for r in self.rotsum_steps():
-            ct = self.add(ct, self.rotate(ct, r, gkeys))
+        for s, rad in self.rotsum_plan():
+            ct = self.rotsum_step(ct, s, rad, gkeys)
         return ct
 
 

@@ -121,3 +121,39 @@ def test_rotations(env):
     assert np.max(np.abs(O.decrypt(s, sk) - m.sum())) < m.sum() * 1e-4
     with pytest.raises(KeyError):
         O.rotate(ct, 7, gk)
+
+
+def test_rotsum_plan_covers_every_slot_once(env):
+    """RotSum's steps multiply out to every shift 0..slots-1 exactly once:
+    the product over steps of (1 + X^s + ... + X^{(radix-1) s}) is
+    1 + X + ... + X^{slots-1}."""
+    P, O = env[0], env[1]
+    poly = np.zeros(P.slots, dtype=np.int64)
+    poly[0] = 1
+    for s, rad in O.rotsum_plan():
+        nxt = np.zeros_like(poly)
+        for k in range(rad):
+            nxt += np.roll(poly, k * s)
+        poly = nxt
+    assert np.array_equal(poly, np.ones(P.slots, dtype=np.int64))
+    assert sorted(set(O.rotsum_steps())) == sorted(O.rotsum_steps())
+
+
+def test_rotsum_step_sums_rotations(env):
+    """The hoisted step ct + rot(ct, s) + rot(ct, 2s) + rot(ct, 3s) (one
+    ModUp, one ModDown) decrypts to the slot-wise sum of the rotated
+    messages, and agrees with separate rotations up to the noise."""
+    P, O, sk, pk, rlk, gk = env
+    m = np.random.default_rng(6).uniform(-1, 1, P.slots)
+    ct = enc(O, pk, m, 31)
+    s = 1
+    want = sum(np.roll(m, -k * s) for k in range(4))
+    got = O.rotsum_step(ct, s, 4, gk)
+    tol = 64 * fresh_std(P)
+    assert np.max(np.abs(O.decrypt(got, sk) - want)) < 4 * tol
+    sep = ct
+    for k in range(1, 4):
+        sep = O.add(sep, O.rotate(ct, k * s, gk))
+    assert np.max(np.abs(O.decrypt(got, sk) - O.decrypt(sep, sk))) < 4 * tol
+    two = O.rotsum_step(ct, 2, 2, gk)
+    assert np.max(np.abs(O.decrypt(two, sk) - (m + np.roll(m, -2)))) < 2 * tol
