@@ -141,7 +141,8 @@ int ppst_evk_add_relin(ppst_context* ctx, const ppst_secret_key* sk, uint64_t se
 /* Galois keys for rotations by steps[i] slots (s(X^g) -> s, g = 5^r mod 2N) */
 int ppst_evk_add_galois(ppst_context* ctx, const ppst_secret_key* sk, const int32_t* steps,
                         size_t n, uint64_t seed, ppst_eval_keys* evk);
-/* Galois keys for every power-of-two step below N/2 (what rotate-and-sum needs) */
+/* Galois keys that rotate-and-sum needs: steps k 4^i (k = 1, 2, 3) while
+ * 4^(i+1) <= N/2, then k = 1 for a last odd power of two (22 keys at N = 2^16) */
 int ppst_evk_add_rotsum(ppst_context* ctx, const ppst_secret_key* sk, uint64_t seed,
                         ppst_eval_keys* evk);
 /* copy a key to the host: galois = 0 selects the relinearisation key.
@@ -233,8 +234,11 @@ int ppst_rotate_batch(ppst_context* ctx, const ppst_eval_keys* evk,
 int ppst_rotate_hoisted_batch(ppst_context* ctx, const ppst_eval_keys* evk,
                               const ppst_ciphertext* const* cts, size_t n, const int32_t* rs,
                               size_t m, ppst_ciphertext** outs);
-/* rotate-and-sum: for k = 0..log2(N/2)-1, ct += rot(ct, 2^k); every slot then
- * holds the sum of all slots (the sums of Eq. 2, Sec. 5.1) */
+/* rotate-and-sum: every slot ends up holding the sum of all N/2 slots (the
+ * sums of Eq. 2, Sec. 5.1).  Steps of two bits, ct += rot(ct, s) + rot(ct, 2s)
+ * + rot(ct, 3s) for s = 1, 4, 16, ..., then ct += rot(ct, s) for a last odd
+ * bit; each step's key switches share one ModUp of c1 and one rounding
+ * ModDown of the summed inner products (keys: ppst_evk_add_rotsum). */
 int ppst_rotsum(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciphertext* a,
                 ppst_ciphertext** out);
 /* bring a ciphertext down to `level`: keep q_0..q_{level+1}, multiply by

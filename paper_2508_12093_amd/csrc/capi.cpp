@@ -346,10 +346,11 @@ int ppst_evk_add_rotsum(ppst_context* ctx, const ppst_secret_key* sk, uint64_t s
     NEED(sk);
     NEED(evk);
     const Params& P = ctx->cx->P();
-    for (int k = 0; (1 << k) < P.slots(); ++k) {
-      u64 g = galois_elt(P, 1L << k);
-      if (!evk->e.galois.count(g)) evk->e.galois[g] = keygen_galois(*ctx->cx, *sk->k, seed, g);
-    }
+    for (const auto& st : rotsum_plan(P))
+      for (int k = 1; k < st.second; ++k) {
+        u64 g = galois_elt(P, k * st.first);
+        if (!evk->e.galois.count(g)) evk->e.galois[g] = keygen_galois(*ctx->cx, *sk->k, seed, g);
+      }
   });
 }
 

@@ -457,9 +457,9 @@ Buf ks_accumulate(Context& cx, const KsKey& key, const u64* d, size_t sd, int le
 // Second half, plain: for each item b, out[b] = (u/P rounded) + (add0[b],
 // add1[b]) [+ acc[b]] with the rounding ModDown; the final step runs in the
 // last pass of the conversion's NTT.  add0 is read through X -> X^gadd.
-void ks_moddown_ptr(Context& cx, Buf& u, int level, int nbatch, const u64* const* add0,
-                    const u64* const* add1, const u64* const* acc, u64* const* out,
-                    uint32_t gadd) {
+void ks_moddown_multi(Context& cx, Buf& u, int level, int nbatch, const u64* const* add0,
+                      const u64* const* add1, const u64* const* acc, u64* const* out,
+                      const uint32_t* gadd, int ngadd) {
   const Params& P = cx.P();
   const Shared& sh = *cx.sh;
   const int N = P.N, nl = level + 1, K = P.K, ne = nl + K;
@@ -477,8 +477,15 @@ void ks_moddown_ptr(Context& cx, Buf& u, int level, int nbatch, const u64* const
   }
   Buf conv = dev_buf(cx.pool, sc * nbatch);
   k_moddown_conv(sh, u.p, conv.p, level, nbatch, su, sc, cx.stream);
-  MdTail t{u.p, su, add0, add1, acc, out, gadd};
+  MdTail t{u.p, su, add0, add1, acc, out, {}, ngadd};
+  for (int r = 0; r < ngadd && r < kMaxGadd; ++r) t.gadd[r] = gadd[r];
   ntt_fwd_md_final(sh, conv.p, level, nbatch, t, cx.stream);
+}
+
+void ks_moddown_ptr(Context& cx, Buf& u, int level, int nbatch, const u64* const* add0,
+                    const u64* const* add1, const u64* const* acc, u64* const* out,
+                    uint32_t gadd) {
+  ks_moddown_multi(cx, u, level, nbatch, add0, add1, acc, out, &gadd, 1);
 }
 
 // the same with addends and outputs at fixed strides (sa, so) from one base
@@ -1094,27 +1101,99 @@ std::vector<CtPtr> rotate_batch(Context& cx, const EvalKeys& evk,
   return rotate_batch_impl(cx, evk, cts, r, false);
 }
 
-// ct <- ct + rot(ct, 2^k), k = 0.., with the addition fused into each
-// rotation's last pass (the same residues as a separate add)
+std::vector<std::pair<long, int>> rotsum_plan(const Params& P) {
+  std::vector<std::pair<long, int>> plan;
+  int b = 0;
+  while ((1L << b) < P.slots()) {
+    const int rad = (1L << (b + 2)) <= P.slots() ? 4 : 2;
+    plan.emplace_back(1L << b, rad);
+    b += rad == 4 ? 2 : 1;
+  }
+  return plan;
+}
+
+namespace {
+
+// One hoisted rotate-and-sum step for every item: out_i = ct_i +
+// sum_{0<k<radix} rot(ct_i, k s), with one ModUp of each c1, the radix - 1
+// permuted inner products added in the extended basis and one ModDown whose
+// last pass adds c0's permutations and the item itself.
+std::vector<CtPtr> rotsum_step(Context& cx, const EvalKeys& evk,
+                               const std::vector<const Ciphertext*>& cts, long s, int radix) {
+  const Params& P = cx.P();
+  const Shared& sh = *cx.sh;
+  const size_t n = cts.size();
+  const int level = cts[0]->level;
+  const int N = P.N, nl = level + 1, ne = nl + P.K, beta = P.beta(level);
+  const size_t per = (size_t)nl * N, sext = (size_t)beta * ne * N, su = 2 * (size_t)ne * N;
+  const int nk = radix - 1;
+  if (nk < 1 || nk > kMaxHoistKeys || nk > kMaxGadd) PPST_THROW(ST_EINVAL, "radix out of range");
+  const u64* keys[kMaxHoistKeys];
+  uint32_t gs[kMaxHoistKeys];
+  for (int k = 0; k < nk; ++k) {
+    const u64 g = galois_elt(P, (k + 1) * s);
+    if (g == 1) PPST_THROW(ST_EINVAL, "rotate-and-sum step wraps around");
+    gs[k] = (uint32_t)g;
+    keys[k] = galois_key(evk, g).k.p;
+  }
+  std::vector<CtPtr> outs(n);
+  const int chunk = (int)std::min<size_t>(n, kPtrBatch);
+  Buf ext = dev_buf(cx.pool, sext * chunk);
+  Buf x = dev_buf(cx.pool, per);
+  Buf u = dev_buf(cx.pool, su * chunk);
+  for (size_t b0 = 0; b0 < n; b0 += chunk) {
+    const int nb = (int)std::min<size_t>(chunk, n - b0);
+    std::vector<const u64*> d(nb), add(nb), acc(nb);
+    std::vector<u64*> po(nb);
+    for (int i = 0; i < nb; ++i) {
+      const Ciphertext& c = *cts[b0 + i];
+      NttLaunch L{};
+      L.src = c.poly(1);
+      L.dst = x.p;
+      L.nlimbs = nl;
+      L.nq = nl;
+      L.pofs = P.L + 1;
+      ntt(sh, L, true, cx.stream);
+      k_modup(sh, x.p, ext.p + sext * i, level, 1, per, sext, cx.stream);
+      d[i] = c.poly(1);
+      add[i] = c.poly(0);
+      acc[i] = c.buf.p;
+      outs[b0 + i] = new_ct(cx, level, c.scale);
+      po[i] = outs[b0 + i]->buf.p;
+    }
+    ntt_ext_digits(cx, ext.p, level, nb);   // the digits' own limbs are skipped
+    k_ks_inner_multi(sh, d.data(), ext.p, keys, gs, nk, u.p, level, nb, sext, su, cx.stream);
+    ks_moddown_multi(cx, u, level, nb, add.data(), nullptr, acc.data(), po.data(), gs, nk);
+  }
+  return outs;
+}
+
+}  // namespace
+
 std::vector<CtPtr> rotsum_batch(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& cts) {
-  std::vector<CtPtr> cur;
-  for (const CtPtr& c : cts) cur.push_back(copy_ct(cx, *c));
+  std::vector<CtPtr> cur = cts;
   if (cur.empty()) return cur;
-  for (int k = 0; (1 << k) < cx.P().slots(); ++k) {
+  for (const CtPtr& c : cur) {
+    if (c->npoly != 2) PPST_THROW(ST_EINVAL, "rotate-and-sum expects degree-1 ciphertexts");
+    if (c->level != cur[0]->level) PPST_THROW(ST_ESCALE, "batch members at different levels");
+  }
+  for (const auto& st : rotsum_plan(cx.P())) {
     std::vector<const Ciphertext*> v;
     for (const CtPtr& c : cur) v.push_back(c.get());
-    cur = rotate_batch_impl(cx, evk, v, 1L << k, true);
+    cur = rotsum_step(cx, evk, v, st.first, st.second);
   }
   return cur;
 }
 
 CtPtr rotsum(Context& cx, const EvalKeys& evk, const Ciphertext& a) {
-  CtPtr ct = copy_ct(cx, a);
-  for (int k = 0; (1 << k) < cx.P().slots(); ++k) {
-    std::vector<const Ciphertext*> v{ct.get()};
-    ct = rotate_batch_impl(cx, evk, v, 1L << k, true)[0];
+  if (a.npoly != 2) PPST_THROW(ST_EINVAL, "rotate-and-sum expects a degree-1 ciphertext");
+  std::vector<const Ciphertext*> v{&a};
+  CtPtr cur;
+  for (const auto& st : rotsum_plan(cx.P())) {
+    cur = rotsum_step(cx, evk, v, st.first, st.second)[0];
+    v = {cur.get()};
   }
-  return ct;
+  return cur ? cur : copy_ct(cx, a);
 }
 
 CtPtr level_align(Context& cx, const Ciphertext& a, int level) {

@@ -60,9 +60,16 @@ std::vector<CtPtr> rotate_hoisted_batch(Context& cx, const EvalKeys& evk,
 // switch over the batch (the key read once per group of items)
 std::vector<CtPtr> rotate_batch(Context& cx, const EvalKeys& evk,
                                 const std::vector<const Ciphertext*>& cts, long r);
+// Rotate-and-sum (every slot ends up holding the sum of all N/2 slots) in
+// the steps of rotsum_plan: ct <- ct + sum_{0<k<radix} rot(ct, k s), each
+// step's key switches hoisted (one ModUp of c1, the permuted inner products
+// added in the extended basis, one ModDown).
 CtPtr rotsum(Context& cx, const EvalKeys& evk, const Ciphertext& a);
 // rotsum() of several ciphertexts of one level, each step batched
 std::vector<CtPtr> rotsum_batch(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& cts);
+// (s, radix) per step: radix 4 while two or more bits of the slot index
+// remain, then radix 2; the Galois keys needed are those of k s, 0 < k < radix
+std::vector<std::pair<long, int>> rotsum_plan(const Params& P);
 CtPtr level_align(Context& cx, const Ciphertext& a, int level);
 CtPtr copy_ct(Context& cx, const Ciphertext& a);
 

@@ -231,6 +231,87 @@ __global__ void __launch_bounds__(kBlock) k_ks_inner_kernel(InnerArgs a) {
   }
 }
 
+struct InnerMultiArgs {
+  PtrsIn d;                         // per item: NTT-form input [nl][N]
+  const u64* ext;                   // [item][beta][ne][N]
+  const u64* key[kMaxHoistKeys];    // [dnum][2][nprimes][N] each
+  uint32_t g[kMaxHoistKeys];
+  u64* u;                           // [item][2][ne][N]
+  const Mod* mods;
+  size_t sext, su;
+  int logN, nl, ne, beta, alpha, pofs, nprimes, nbatch, nkeys;
+};
+
+// Several keys' inner products summed per output element.  Acc30 takes at
+// most 8 terms between folds and 16 in all, so the running sums are folded
+// before a key would pass 8 terms and reduced into r0/r1 before 16.
+template <int ITEMS>
+__global__ void __launch_bounds__(kBlock) k_ks_inner_multi_kernel(InnerMultiArgs a) {
+  const size_t N = (size_t)1 << a.logN;
+  size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= (size_t)a.ne * N) return;
+  const int t = (int)(r >> a.logN);
+  const uint32_t k = (uint32_t)(r & (N - 1));
+  const int p = t < a.nl ? t : a.pofs + (t - a.nl);
+  const int b0 = blockIdx.y * ITEMS;
+  const int nb = min(ITEMS, a.nbatch - b0);
+  const int own = t < a.nl ? t / a.alpha : -1;
+  const Mod m = a.mods[p];
+  Acc30 s0[ITEMS], s1[ITEMS];
+  u64 r0[ITEMS], r1[ITEMS];
+#pragma unroll
+  for (int q = 0; q < ITEMS; ++q) r0[q] = r1[q] = 0;
+  int since = 0, total = 0;
+  for (int h = 0; h < a.nkeys; ++h) {
+    if (total + a.beta > 16) {
+#pragma unroll
+      for (int q = 0; q < ITEMS; ++q) {
+        r0[q] = addm(r0[q], s0[q].reduce(m), m.q);
+        r1[q] = addm(r1[q], s1[q].reduce(m), m.q);
+        s0[q] = Acc30();
+        s1[q] = Acc30();
+      }
+      total = since = 0;
+    } else if (since + a.beta > 8) {
+#pragma unroll
+      for (int q = 0; q < ITEMS; ++q) {
+        s0[q].fold();
+        s1[q].fold();
+      }
+      since = 0;
+    }
+    const size_t kk = galois_src(k, a.g[h], a.logN);
+    const u64* key = a.key[h];
+    for (int j = 0; j < a.beta; ++j) {
+      const Split30 kb(key[((size_t)(2 * j) * a.nprimes + p) * N + k]);
+      const Split30 ka(key[((size_t)(2 * j + 1) * a.nprimes + p) * N + k]);
+      u64 ev[ITEMS];
+#pragma unroll
+      for (int q = 0; q < ITEMS; ++q) {
+        const int b = b0 + min(q, nb - 1);
+        ev[q] = (j == own) ? a.d.p[b][(size_t)t * N + kk]
+                           : a.ext[(size_t)b * a.sext + ((size_t)j * a.ne + t) * N + kk];
+      }
+#pragma unroll
+      for (int q = 0; q < ITEMS; ++q) {
+        const Split30 e(ev[q]);
+        s0[q].mac(e, kb);
+        s1[q].mac(e, ka);
+      }
+    }
+    since += a.beta;
+    total += a.beta;
+  }
+#pragma unroll
+  for (int q = 0; q < ITEMS; ++q) {
+    if (q < nb) {
+      u64* u = a.u + (size_t)(b0 + q) * a.su;
+      u[(size_t)t * N + k] = addm(r0[q], s0[q].reduce(m), m.q);
+      u[((size_t)a.ne + t) * N + k] = addm(r1[q], s1[q].reduce(m), m.q);
+    }
+  }
+}
+
 struct ModDownArgs {
   size_t su, sconv;
   int logN, nl, ne, K, L, nchunk;
@@ -554,6 +635,48 @@ void k_modup(const Shared& sh, const u64* x, u64* ext, int level, int nbatch, si
     hipLaunchKernelGGL(k_modup_kernel<16>, g, dim3(kBlock), 0, st, x, ext, M(sh), tab, a);
   else
     PPST_THROW(ST_EINVAL, "digit size above 16 limbs");
+  LAUNCH_CHECK();
+}
+
+void k_ks_inner_multi(const Shared& sh, const u64* const* d, const u64* ext,
+                      const u64* const* keys, const uint32_t* g, int nkeys, u64* u, int level,
+                      int nbatch, size_t sext, size_t su, hipStream_t st) {
+  const Params& P = sh.P;
+  if (nkeys < 1 || nkeys > kMaxHoistKeys) PPST_THROW(ST_EINVAL, "hoisted key count out of range");
+  if (nbatch < 1 || nbatch > kPtrBatch) PPST_THROW(ST_EINVAL, "batch out of range");
+  if (P.beta(level) > 8) PPST_THROW(ST_EINVAL, "more than 8 digits");
+  InnerMultiArgs a{};
+  for (int i = 0; i < nbatch; ++i) {
+    if (!d[i]) PPST_THROW(ST_EINVAL, "missing input polynomial");
+    a.d.p[i] = d[i];
+  }
+  for (int h = 0; h < nkeys; ++h) {
+    if (!keys[h] || g[h] == 0 || (g[h] & 1) == 0 || g[h] >= 2u * (uint32_t)P.N)
+      PPST_THROW(ST_EINVAL, "hoisted key or Galois element invalid");
+    a.key[h] = keys[h];
+    a.g[h] = g[h];
+  }
+  a.ext = ext;
+  a.u = u;
+  a.mods = M(sh);
+  a.sext = sext;
+  a.su = su;
+  a.logN = P.logN;
+  a.nl = level + 1;
+  a.ne = level + 1 + P.K;
+  a.beta = P.beta(level);
+  a.alpha = P.alpha;
+  a.pofs = P.L + 1;
+  a.nprimes = P.nprimes;
+  a.nbatch = nbatch;
+  a.nkeys = nkeys;
+  dim3 gr = grid_for((size_t)a.ne * P.N);
+  if (nbatch >= 2) {
+    gr.y = (nbatch + 1) / 2;
+    hipLaunchKernelGGL(k_ks_inner_multi_kernel<2>, gr, dim3(kBlock), 0, st, a);
+  } else {
+    hipLaunchKernelGGL(k_ks_inner_multi_kernel<1>, gr, dim3(kBlock), 0, st, a);
+  }
   LAUNCH_CHECK();
 }
 
