@@ -457,9 +457,9 @@ Buf ks_accumulate(Context& cx, const KsKey& key, const u64* d, size_t sd, int le
 // Second half, plain: for each item b, out[b] = (u/P rounded) + (add0[b],
 // add1[b]) [+ acc[b]] with the rounding ModDown; the final step runs in the
 // last pass of the conversion's NTT.  add0 is read through X -> X^gadd.
-void ks_moddown_multi(Context& cx, Buf& u, int level, int nbatch, const u64* const* add0,
-                      const u64* const* add1, const u64* const* acc, u64* const* out,
-                      const uint32_t* gadd, int ngadd) {
+void ks_moddown_ptr(Context& cx, Buf& u, int level, int nbatch, const u64* const* add0,
+                    const u64* const* add1, const u64* const* acc, u64* const* out,
+                    uint32_t gadd) {
   const Params& P = cx.P();
   const Shared& sh = *cx.sh;
   const int N = P.N, nl = level + 1, K = P.K, ne = nl + K;
@@ -477,15 +477,8 @@ void ks_moddown_multi(Context& cx, Buf& u, int level, int nbatch, const u64* con
   }
   Buf conv = dev_buf(cx.pool, sc * nbatch);
   k_moddown_conv(sh, u.p, conv.p, level, nbatch, su, sc, cx.stream);
-  MdTail t{u.p, su, add0, add1, acc, out, {}, ngadd};
-  for (int r = 0; r < ngadd && r < kMaxGadd; ++r) t.gadd[r] = gadd[r];
+  MdTail t{u.p, su, add0, add1, acc, out, gadd};
   ntt_fwd_md_final(sh, conv.p, level, nbatch, t, cx.stream);
-}
-
-void ks_moddown_ptr(Context& cx, Buf& u, int level, int nbatch, const u64* const* add0,
-                    const u64* const* add1, const u64* const* acc, u64* const* out,
-                    uint32_t gadd) {
-  ks_moddown_multi(cx, u, level, nbatch, add0, add1, acc, out, &gadd, 1);
 }
 
 // the same with addends and outputs at fixed strides (sa, so) from one base
@@ -1116,8 +1109,8 @@ namespace {
 
 // One hoisted rotate-and-sum step for every item: out_i = ct_i +
 // sum_{0<k<radix} rot(ct_i, k s), with one ModUp of each c1, the radix - 1
-// permuted inner products added in the extended basis and one ModDown whose
-// last pass adds c0's permutations and the item itself.
+// permuted inner products (and P times c0's permutations) added in the
+// extended basis, and one ModDown whose last pass adds the item itself.
 std::vector<CtPtr> rotsum_step(Context& cx, const EvalKeys& evk,
                                const std::vector<const Ciphertext*>& cts, long s, int radix) {
   const Params& P = cx.P();
@@ -1127,7 +1120,7 @@ std::vector<CtPtr> rotsum_step(Context& cx, const EvalKeys& evk,
   const int N = P.N, nl = level + 1, ne = nl + P.K, beta = P.beta(level);
   const size_t per = (size_t)nl * N, sext = (size_t)beta * ne * N, su = 2 * (size_t)ne * N;
   const int nk = radix - 1;
-  if (nk < 1 || nk > kMaxHoistKeys || nk > kMaxGadd) PPST_THROW(ST_EINVAL, "radix out of range");
+  if (nk < 1 || nk > kMaxHoistKeys) PPST_THROW(ST_EINVAL, "radix out of range");
   const u64* keys[kMaxHoistKeys];
   uint32_t gs[kMaxHoistKeys];
   for (int k = 0; k < nk; ++k) {
@@ -1162,8 +1155,11 @@ std::vector<CtPtr> rotsum_step(Context& cx, const EvalKeys& evk,
       po[i] = outs[b0 + i]->buf.p;
     }
     ntt_ext_digits(cx, ext.p, level, nb);   // the digits' own limbs are skipped
-    k_ks_inner_multi(sh, d.data(), ext.p, keys, gs, nk, u.p, level, nb, sext, su, cx.stream);
-    ks_moddown_multi(cx, u, level, nb, add.data(), nullptr, acc.data(), po.data(), gs, nk);
+    // c0's permutations enter u0 as P sum_r c0(X^g_r) (exact through ModDown);
+    // the ModDown's last pass adds the input itself
+    k_ks_inner_multi(sh, d.data(), ext.p, keys, gs, nk, u.p, level, nb, sext, su, cx.stream,
+                     add.data());
+    ks_moddown_ptr(cx, u, level, nb, nullptr, nullptr, acc.data(), po.data(), 0);
   }
   return outs;
 }

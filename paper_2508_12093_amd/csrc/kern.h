@@ -58,13 +58,11 @@ void ntt_fwd_mdr_final(const Shared& sh, u64* corr, int level, int nbatch, const
 
 // Forward NTT of the ModDown conversion conv [nbatch][2][nl][N] (coefficient
 // form, primes q_0..q_l) whose last pass stores, in place of conv_i,
-//   out_i = ((u_i - conv_i) P^-1 mod q_i) [+ sum_r add_c,i(X^gadd_r)] [+ acc_c,i]
+//   out_i = ((u_i - conv_i) P^-1 mod q_i) [+ add_c,i(X^gadd)] [+ acc_c,i]
 // into out[b] ([2][nl][N]).  u: [nbatch][2][ne][N] at stride su; add0/add1:
-// per-item [nl][N] addends of c0/c1 (array or entries may be null), each read
-// through X -> X^g for every g of gadd[0..ngadd) (g = 0: as stored) and the
-// reads summed; acc: per-item [2][nl][N] running sums (array or entries may
-// be null).
-constexpr int kMaxGadd = 7;
+// per-item [nl][N] addends of c0/c1 (array or entries may be null), read
+// through X -> X^gadd when gadd != 0; acc: per-item [2][nl][N] running sums
+// (array or entries may be null).
 struct MdTail {
   const u64* u;
   size_t su;
@@ -72,8 +70,7 @@ struct MdTail {
   const u64* const* add1;
   const u64* const* acc;
   u64* const* out;
-  uint32_t gadd[kMaxGadd];
-  int ngadd;
+  uint32_t gadd;
 };
 void ntt_fwd_md_final(const Shared& sh, u64* conv, int level, int nbatch, const MdTail& tail,
                       hipStream_t st);
@@ -139,11 +136,15 @@ void k_ks_inner(const Shared& sh, const u64* d, const u64* ext, const u64* key, 
 //   u0_t = sum_r sum_j e_{j,t}(X^g_r) b^(r)_{j,p(t)},  u1_t likewise with a^(r),
 // e_{j,t} = d_t (per item: d[b], NTT form [nl][N]) for t in digit j, ext[j][t]
 // otherwise; ext: [nbatch][beta][ne][N] at stride sext; u: [nbatch][2][ne][N]
-// at stride su.  nkeys <= kMaxHoistKeys, nbatch <= kPtrBatch.
+// at stride su.  nkeys <= kMaxHoistKeys, nbatch <= kPtrBatch.  With w
+// (per-item NTT-form [nl][N], entries may be null), limb q_t of u0 also
+// receives (P mod q_t) sum_r w_t(X^g_r): after ModDown that is exactly
+// sum_r w(X^g_r) added to c0 (P w vanishes modulo the special primes).
 constexpr int kMaxHoistKeys = 7;
 void k_ks_inner_multi(const Shared& sh, const u64* const* d, const u64* ext,
                       const u64* const* keys, const uint32_t* g, int nkeys, u64* u, int level,
-                      int nbatch, size_t sext, size_t su, hipStream_t st);
+                      int nbatch, size_t sext, size_t su, hipStream_t st,
+                      const u64* const* w = nullptr);
 // ModDown conversion: z = coefficient-form special limbs of u (u + nl*N, for
 // both polynomials); conv[c][i] = Conv_{P->q_i}(z + h) - h mod q_i.
 void k_moddown_conv(const Shared& sh, const u64* u, u64* conv, int level, int nbatch,

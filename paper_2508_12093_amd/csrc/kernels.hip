@@ -238,6 +238,10 @@ struct InnerMultiArgs {
   uint32_t g[kMaxHoistKeys];
   u64* u;                           // [item][2][ne][N]
   const Mod* mods;
+  // per item (or null): limb q_t of u0 also receives (P mod q_t) times the
+  // sum of w's limb t read through every g (w in NTT form [nl][N])
+  PtrsIn w;
+  const u64* pmod;                  // (P mod q_i, Shoup companion), i = 0..L
   size_t sext, su;
   int logN, nl, ne, beta, alpha, pofs, nprimes, nbatch, nkeys;
 };
@@ -302,11 +306,22 @@ __global__ void __launch_bounds__(kBlock) k_ks_inner_multi_kernel(InnerMultiArgs
     since += a.beta;
     total += a.beta;
   }
+  u64 wsum[ITEMS];
+#pragma unroll
+  for (int q = 0; q < ITEMS; ++q) {
+    wsum[q] = 0;
+    const u64* w = a.w.p[b0 + min(q, nb - 1)];
+    if (w && t < a.nl) {
+      for (int h = 0; h < a.nkeys; ++h)
+        wsum[q] = addm(wsum[q], w[(size_t)t * N + galois_src(k, a.g[h], a.logN)], m.q);
+      wsum[q] = mul_shoup(wsum[q], a.pmod[2 * t], a.pmod[2 * t + 1], m.q);
+    }
+  }
 #pragma unroll
   for (int q = 0; q < ITEMS; ++q) {
     if (q < nb) {
       u64* u = a.u + (size_t)(b0 + q) * a.su;
-      u[(size_t)t * N + k] = addm(r0[q], s0[q].reduce(m), m.q);
+      u[(size_t)t * N + k] = addm(addm(r0[q], s0[q].reduce(m), m.q), wsum[q], m.q);
       u[((size_t)a.ne + t) * N + k] = addm(r1[q], s1[q].reduce(m), m.q);
     }
   }
@@ -640,7 +655,7 @@ void k_modup(const Shared& sh, const u64* x, u64* ext, int level, int nbatch, si
 
 void k_ks_inner_multi(const Shared& sh, const u64* const* d, const u64* ext,
                       const u64* const* keys, const uint32_t* g, int nkeys, u64* u, int level,
-                      int nbatch, size_t sext, size_t su, hipStream_t st) {
+                      int nbatch, size_t sext, size_t su, hipStream_t st, const u64* const* w) {
   const Params& P = sh.P;
   if (nkeys < 1 || nkeys > kMaxHoistKeys) PPST_THROW(ST_EINVAL, "hoisted key count out of range");
   if (nbatch < 1 || nbatch > kPtrBatch) PPST_THROW(ST_EINVAL, "batch out of range");
@@ -649,7 +664,9 @@ void k_ks_inner_multi(const Shared& sh, const u64* const* d, const u64* ext,
   for (int i = 0; i < nbatch; ++i) {
     if (!d[i]) PPST_THROW(ST_EINVAL, "missing input polynomial");
     a.d.p[i] = d[i];
+    a.w.p[i] = w ? w[i] : nullptr;
   }
+  a.pmod = sh.tab.moddown.p + MdLayout(P.K, P.L).pmod(0);
   for (int h = 0; h < nkeys; ++h) {
     if (!keys[h] || g[h] == 0 || (g[h] & 1) == 0 || g[h] >= 2u * (uint32_t)P.N)
       PPST_THROW(ST_EINVAL, "hoisted key or Galois element invalid");

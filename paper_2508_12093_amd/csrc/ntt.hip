@@ -502,8 +502,7 @@ struct MdEpi {
   PtrsIn acc;        // per item [2][nl][N] or null
   OutPtrs out;       // per item [2][nl][N]
   const u64* md;     // ModDown table
-  uint32_t gadd[kMaxGadd];   // each addend is read through every one of these
-  int ngadd;
+  uint32_t gadd;
   int K, L, nl, ne, logN;
 };
 
@@ -514,18 +513,12 @@ struct MdStore {
   const u64* acc;
   u64* out;
   u64 q, pinv, pinvs;
-  uint32_t gadd[kMaxGadd];
-  int ngadd;
+  uint32_t gadd;
   int logN;
   u64 pu[E], pa[E], pc[E];
   __device__ __forceinline__ void prefetch(int i, size_t at) {
     pu[i] = u[at];
-    u64 v = 0;
-    if (add) {
-      v = add[galois_src((uint32_t)at, gadd[0], logN)];
-      for (int r = 1; r < ngadd; ++r) v = addm(v, add[galois_src((uint32_t)at, gadd[r], logN)], q);
-    }
-    pa[i] = v;
+    pa[i] = add ? add[galois_src((uint32_t)at, gadd, logN)] : 0;
     pc[i] = acc ? acc[at] : 0;
   }
   __device__ __forceinline__ void put(int i, size_t at, u64 conv) const {
@@ -560,8 +553,7 @@ k_ntt_row_md(NttArgs a, MdEpi e) {
   store.q = q;
   store.pinv = e.md[lay.pinv(t)];
   store.pinvs = e.md[lay.pinv(t) + 1];
-  for (int r = 0; r < kMaxGadd; ++r) store.gadd[r] = e.gadd[r];
-  store.ngadd = e.ngadd;
+  store.gadd = e.gadd;
   store.logN = e.logN;
   const int first = grp * SB;
   if (q < kFpPrimeBound)
@@ -901,9 +893,7 @@ void ntt_fwd_md_final(const Shared& sh, u64* conv, int level, int nbatch, const 
   MdEpi e{};
   e.su = tail.su;
   e.md = sh.tab.moddown.p;
-  if (tail.ngadd < 1 || tail.ngadd > kMaxGadd) PPST_THROW(ST_EINVAL, "addend Galois list size");
-  for (int r = 0; r < kMaxGadd; ++r) e.gadd[r] = r < tail.ngadd ? tail.gadd[r] : 0;
-  e.ngadd = tail.ngadd;
+  e.gadd = tail.gadd;
   e.K = P.K;
   e.L = P.L;
   e.nl = nl;
