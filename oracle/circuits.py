@@ -19,7 +19,8 @@ Circuits (paper references):
   invsqrt     CryptoInvSqrt of x / B slot by slot (Sec. 6.2, Exp. 1)
   zscore      Alg. 4;  kurtosis Alg. 5;  skewness (mirror of Alg. 5, Sec. 5)
   cv          Alg. 6 with a g_3-composition sign (Sec. 6.2)
-  pearson     Sec. 5.5: Cov * InvSqrt(Var x) * InvSqrt(Var y)
+  pearson     Sec. 5.5: Cov_B * InvSqrt(Var_B x) * InvSqrt(Var_B y), Eq. 2's
+              pre-scaled moments, the five slot sums summed together
 
 Readings where the paper is silent or inconsistent:
   * Newton (Alg. 2) is evaluated in a balanced order that costs two levels per
@@ -30,7 +31,8 @@ Readings where the paper is silent or inconsistent:
   * Alg. 6 calls CryptoSqrt(var, B); since Variance(x, B) = Var/B^2 the factor
     must be B^2, as in Alg. 4 and 5.  sqrt is evaluated as 2 * w2 * InvSqrt(v).
   * The PCC circuit (deferred by the paper to another work) is
-    Cov * InvSqrt(Var x; Bx^2) * InvSqrt(Var y; By^2).
+    Cov * InvSqrt(Var x) * InvSqrt(Var y) with the moments in Eq. 2's
+    pre-scaled form, Cov_B = E[xy]/(Bx By) - Mean(x, Bx) Mean(y, By).
   * Slots beyond the row count are zero; centred moments use a 1/n-valued row
     mask (a constant when a ciphertext is full, a plaintext vector otherwise).
 """
@@ -319,12 +321,26 @@ class Circuits:
         return self.mulx(self.mulx(sigma, mu_inv), sg)
 
     def pearson(self, X, Y, n, Bx, By, cfg: InvSqrtCfg):
-        """Sec. 5.5: Cov(X, Y) * InvSqrt(Var X; Bx^2) * InvSqrt(Var Y; By^2)."""
+        """Sec. 5.5, Cov(X, Y) / (sd X sd Y), with every moment in Eq. 2's
+        pre-scaled form: Mean(x, Bx) = sum x_i / (Bx n), Var_B = sum (x_i /
+        (Bx sqrt n))^2 - Mean^2 and Cov_B = sum (x_i / (Bx sqrt n)) (y_i /
+        (By sqrt n)) - Mean(x) Mean(y) = Cov / (Bx By); then
+        PCC = Cov_B * InvSqrt(Var_B x; 1) * InvSqrt(Var_B y; 1).  None of the
+        five slot sums depends on another, so they are formed first, brought
+        to one level and summed together."""
         ev = self.ev
-        _, varx, mux = self._moments_prefix(X, n, Bx)
-        _, vary, muy = self._moments_prefix(Y, n, By)
-        prods = [self.mulx(self.subx(x, mux), self.subx(y, muy)) for x, y in zip(X, Y)]
-        cov = self.mask_mean(prods, n)
-        ix, _ = self.inv_sqrt(varx, Bx * Bx, cfg)
-        iy, _ = self.inv_sqrt(vary, By * By, cfg)
+        sx = self.sumx([ev.mul_const(x, 1.0 / (Bx * float(n))) for x in X])
+        sy = self.sumx([ev.mul_const(y, 1.0 / (By * float(n))) for y in Y])
+        xs = [ev.mul_const(x, 1.0 / (Bx * math.sqrt(float(n)))) for x in X]
+        ys = [ev.mul_const(y, 1.0 / (By * math.sqrt(float(n)))) for y in Y]
+        sxx = self.sumx([ev.mul(a, a) for a in xs])
+        syy = self.sumx([ev.mul(b, b) for b in ys])
+        sxy = self.sumx([ev.mul(a, b) for a, b in zip(xs, ys)])
+        lv = ev.level(sxx)
+        mx, my, exx, eyy, exy = [ev.rotsum(ev.align(v, lv)) for v in (sx, sy, sxx, syy, sxy)]
+        varx = self.subx(exx, ev.mul(mx, mx))
+        vary = self.subx(eyy, ev.mul(my, my))
+        cov = self.subx(exy, ev.mul(mx, my))
+        ix, _ = self.inv_sqrt(varx, 1.0, cfg)
+        iy, _ = self.inv_sqrt(vary, 1.0, cfg)
         return self.mulx(cov, ev.mul(ix, iy))
