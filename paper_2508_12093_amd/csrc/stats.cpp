@@ -428,23 +428,42 @@ CtPtr stat_pearson(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& X
                    const InvSqrtCfg& cfg) {
   check_column(cx.P(), X, n);
   check_column(cx.P(), Y, n);
+  if (X.size() != Y.size() || X[0]->level != Y[0]->level)
+    PPST_THROW(ST_EINVAL, "the two columns differ in length or level");
   check_cfg(cfg);
   Circ c{cx, evk};
-  c.check_depth(X, 3 + invsqrt_depth(cfg) + 1);
-  c.check_depth(Y, 3 + invsqrt_depth(cfg) + 1);
-  // the x and y moments and inverse square roots side by side (each lane is
-  // the one-column sequence), then the covariance
-  auto muB = c.mean_B_n({X, Y}, n, {Bx, By});
-  auto var = c.variance_B_n({X, Y}, n, {Bx, By}, muB);
-  auto mux = c.mc(muB[0], Bx);
-  auto muy = c.mc(muB[1], By);
-  std::vector<CtPtr> dx, dy;
-  for (size_t i = 0; i < X.size(); ++i) {
-    dx.push_back(c.subx(X[i], mux));
-    dy.push_back(c.subx(Y[i], muy));
+  c.check_depth(X, 5 + invsqrt_depth(cfg));
+  // Eq. 2's pre-scaled moments: Mean(x, B), E[x^2]/B^2 and E[xy]/(Bx By) are
+  // five independent slot sums, summed together at one level (one batched
+  // RotSum); Var_B = E2 - Mean^2, Cov_B = Exy - Mean(x) Mean(y) = Cov/(Bx By)
+  const double nd = (double)n;
+  std::vector<CtPtr> px, py, xs, ys;
+  for (auto& x : X) {
+    px.push_back(c.mc(x, 1.0 / (Bx * nd)));
+    xs.push_back(c.mc(x, 1.0 / (Bx * std::sqrt(nd))));
   }
-  auto cov = c.mask_mean(c.mulx_n(dx, dy), n);
-  auto is = c.inv_sqrt_n(var, {Bx * Bx, By * By}, cfg);
+  for (auto& y : Y) {
+    py.push_back(c.mc(y, 1.0 / (By * nd)));
+    ys.push_back(c.mc(y, 1.0 / (By * std::sqrt(nd))));
+  }
+  auto sx = c.sum(px), sy = c.sum(py);
+  const size_t m = X.size();
+  std::vector<CtPtr> lhs, rhs;
+  for (size_t i = 0; i < m; ++i) { lhs.push_back(xs[i]); rhs.push_back(xs[i]); }
+  for (size_t i = 0; i < m; ++i) { lhs.push_back(ys[i]); rhs.push_back(ys[i]); }
+  for (size_t i = 0; i < m; ++i) { lhs.push_back(xs[i]); rhs.push_back(ys[i]); }
+  auto pr = c.mulx_n(lhs, rhs);
+  auto part = [&](size_t k) {
+    return c.sum(std::vector<CtPtr>(pr.begin() + k * m, pr.begin() + (k + 1) * m));
+  };
+  auto sxx = part(0), syy = part(1), sxy = part(2);
+  const int lv = sxx->level;
+  auto r = c.rs_n({c.at(sx, lv), c.at(sy, lv), sxx, syy, sxy});
+  auto mm = c.mulx_n({r[0], r[1], r[0]}, {r[0], r[1], r[1]});
+  auto varx = c.subx(r[2], mm[0]);
+  auto vary = c.subx(r[3], mm[1]);
+  auto cov = c.subx(r[4], mm[2]);
+  auto is = c.inv_sqrt_n({varx, vary}, {1.0, 1.0}, cfg);
   return c.mulx(cov, c.mulx(is[0].first, is[1].first));
 }
 
