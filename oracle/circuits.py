@@ -93,6 +93,9 @@ class EncEval:
     def mul_int(self, a, k):
         return self.O.mul_int(a, k)
 
+    def lincomb(self, xs, cs, level):
+        return self.O.lincomb(xs, cs, level)
+
     def add_const(self, a, c):
         return self.O.add_const(a, c)
 
@@ -149,6 +152,10 @@ class PlainEval:
 
     def mul_int(self, a, k):
         return PlainEval.V(a.v * k, a.level)
+
+    def lincomb(self, xs, cs, level):
+        assert all(x.level > level for x in xs)
+        return PlainEval.V(sum(c * x.v for x, c in zip(xs, cs)), level)
 
     def add_const(self, a, c):
         return PlainEval.V(a.v + c, a.level)
@@ -231,7 +238,8 @@ class Circuits:
             else:
                 m = (k - 1) // 2
                 T[k] = self.subx(ev.mul_int(self.mulx(T[m], T[m + 1]), 2), T[1])
-        y = self.sumx([ev.mul_const(T[k], float(coeffs[k])) for k in range(1, d + 1)])
+        y = ev.lincomb([T[k] for k in range(1, d + 1)], [float(coeffs[k]) for k in range(1, d + 1)],
+                       min(ev.level(T[k]) for k in range(1, d + 1)) - 1)
         y = ev.add_const(y, float(coeffs[0]))
         w2 = ev.mul_const(v, Bp / 2.0)
         for _ in range(cfg.iters):

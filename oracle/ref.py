@@ -393,6 +393,29 @@ class Oracle:
         self.L.orc_mul_int(self.P.ref, _p(a.data), k, a.level, 2, _p(out))
         return self.rescale(Ciphertext(out, a.level, a.scale))
 
+    def lincomb_int(self, a: Ciphertext, c: float, level: int) -> int:
+        """The integer that carries c * a to scale Delta_{level+1}^2 at level
+        level + 1: round_half_away(c Delta_{level+1} (Delta_{level+1} / Delta_l))."""
+        D = self.P.scale
+        return round_half_away(float(c) * D[level + 1] * (D[level + 1] / D[a.level]))
+
+    def lincomb(self, cts, cs, level: int) -> Ciphertext:
+        """sum_k c_k ct_k at `level` with one rescale: every ct_k (level >
+        `level`) is cut to q_0..q_{level+1}, multiplied by the integer of
+        ``lincomb_int``, the products added, and the sum rescaled by
+        q_{level+1} (scale Delta_{level+1}^2 / q_{level+1} = Delta_level)."""
+        if not cts or len(cts) != len(cs):
+            raise ValueError("need matching ciphertexts and constants")
+        lv1 = level + 1
+        acc = None
+        for a, c in zip(cts, cs):
+            if a.level < lv1:
+                raise LevelError("a term is below the combination's level + 1")
+            cut = Ciphertext(np.ascontiguousarray(a.data[:, : lv1 + 1, :]), lv1, self.P.scale[lv1])
+            t = self.mul_int(cut, self.lincomb_int(a, c, level))
+            acc = t if acc is None else self.add(acc, t)
+        return self.rescale(acc)
+
     def mul_plain(self, a: Ciphertext, pt: Plaintext) -> Ciphertext:
         """Mul(P) by a plaintext vector encoded at (l, Delta_l), then rescale."""
         if pt.level != a.level:

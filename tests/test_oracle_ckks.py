@@ -105,6 +105,27 @@ def test_mul_add_const_ops(env):
         O.add(ca, m)
 
 
+def test_lincomb(env):
+    """sum_k c_k ct_k with one rescale: a single term one level up is exactly
+    Mul(P) by the constant; terms at different levels decrypt to the
+    weighted sum of their messages."""
+    P, O, sk, pk, rlk, gk = env
+    rng = np.random.default_rng(9)
+    a, b = rng.uniform(-1, 1, P.slots), rng.uniform(-1, 1, P.slots)
+    ca, cb = enc(O, pk, a, 40), enc(O, pk, b, 41)
+    one = O.lincomb([ca], [-0.75], P.L - 1)
+    ref_ = O.mul_const(ca, -0.75)
+    assert one.level == ref_.level and one.scale == ref_.scale
+    assert np.array_equal(one.data, ref_.data)
+    tol = 64 * fresh_std(P)
+    cb_low = O.level_align(cb, P.L - 1)            # a term one level lower
+    out = O.lincomb([ca, cb_low, ca], [0.5, -1.25, 0.125], P.L - 2)
+    assert out.level == P.L - 2 and out.scale == P.scale[P.L - 2]
+    assert np.max(np.abs(O.decrypt(out, sk) - (0.625 * a - 1.25 * b))) < 4 * tol
+    with pytest.raises(ref.LevelError):
+        O.lincomb([cb_low], [1.0], P.L - 1)
+
+
 def test_rotations(env):
     P, O, sk, pk, rlk, gk = env
     m = np.random.default_rng(5).uniform(0, 1, P.slots)
