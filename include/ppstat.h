@@ -245,6 +245,14 @@ int ppst_rotsum(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciphert
  * round(Delta_level q_{level+1} / Delta_l), rescale by q_{level+1} */
 int ppst_level_align(ppst_context* ctx, const ppst_ciphertext* a, int32_t level,
                      ppst_ciphertext** out);
+/* sum_i cs[i] cts[i] at `level` with a single rescale (the Chebyshev sum of
+ * Alg. 3 uses it): every cts[i] (level > `level`, any mix of levels) is cut
+ * to q_0..q_{level+1} and multiplied by round(cs[i] Delta_{level+1}
+ * (Delta_{level+1} / Delta_{l_i})); the products are added and the sum is
+ * rescaled by q_{level+1}.  One term one level up gives exactly
+ * ppst_mul_const.  ELEVEL when a term is not above `level`. */
+int ppst_lincomb(ppst_context* ctx, const ppst_ciphertext* const* cts, const double* cs, size_t n,
+                 int32_t level, ppst_ciphertext** out);
 /* n independent products a[i] * b[i] (same level): each stage of tensor,
  * relinearisation and rescale runs once over the whole batch */
 int ppst_mul_batch(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciphertext* const* a,

@@ -579,6 +579,18 @@ UNARY_OP(ppst_level_align(ppst_context* ctx, const ppst_ciphertext* a, int32_t l
                           ppst_ciphertext** out),
          level_align(*ctx->cx, *a->c, level))
 
+int ppst_lincomb(ppst_context* ctx, const ppst_ciphertext* const* cts, const double* cs, size_t n,
+                 int32_t level, ppst_ciphertext** out) {
+  return guard([&] {
+    NEED(ctx); NEED(cts); NEED(cs); NEED(out);
+    std::vector<const Ciphertext*> v;
+    for (size_t i = 0; i < n; ++i) {
+      NEED(cts[i]);
+      v.push_back(cts[i]->c.get());
+    }
+    *out = wrap(lincomb(*ctx->cx, v, std::vector<double>(cs, cs + n), level));
+  });
+}
 int ppst_mul_plain(ppst_context* ctx, const ppst_ciphertext* a, const ppst_plaintext* pt,
                    ppst_ciphertext** out) {
   return guard([&] {

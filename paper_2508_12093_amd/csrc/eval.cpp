@@ -870,6 +870,40 @@ CtPtr mul_const(Context& cx, const Ciphertext& a, double c) {
   return out;
 }
 
+CtPtr lincomb(Context& cx, const std::vector<const Ciphertext*>& cts,
+              const std::vector<double>& cs, int level) {
+  const Params& P = cx.P();
+  if (cts.empty() || cts.size() != cs.size())
+    PPST_THROW(ST_EINVAL, "need matching ciphertexts and constants");
+  if (level < 0) PPST_THROW(ST_ELEVEL, "combination level below 0");
+  const int lv1 = level + 1, nl = lv1 + 1, N = P.N;
+  const size_t nt = cts.size();
+  std::vector<const u64*> src(nt);
+  std::vector<size_t> ps(nt);
+  std::vector<u64> k(nt * nl), kp(nt * nl);
+  for (size_t j = 0; j < nt; ++j) {
+    const Ciphertext& a = *cts[j];
+    if (a.npoly != 2) PPST_THROW(ST_EINVAL, "linear combination of degree-1 ciphertexts only");
+    if (a.level < lv1) PPST_THROW(ST_ELEVEL, "a term is below the combination's level + 1");
+    const double v = cs[j] * P.scale[lv1] * (P.scale[lv1] / P.scale[a.level]);
+    if (!(std::fabs(v) < 9.0e18)) PPST_THROW(ST_EDOMAIN, "constant too large for the scale");
+    std::vector<u64> r, rp;
+    scalar_residues(P, llround(v), nl, r, rp);
+    for (int t = 0; t < nl; ++t) {
+      k[j * nl + t] = r[t];
+      kp[j * nl + t] = rp[t];
+    }
+    src[j] = a.buf.p;
+    ps[j] = (size_t)(a.level + 1) * N;
+  }
+  Buf sum = dev_buf(cx.pool, 2 * (size_t)nl * N);
+  k_lincomb(*cx.sh, src.data(), ps.data(), k.data(), kp.data(), (int)nt, nl, sum.p, (size_t)nl * N,
+            cx.stream);
+  auto out = new_ct(cx, level, P.scale[level], 2);
+  rescale_raw(cx, sum.p, (size_t)nl * N, lv1, 2, out->buf.p);
+  return out;
+}
+
 CtPtr mul_plain(Context& cx, const Ciphertext& a, const Plaintext& pt) {
   if (a.level < 1) PPST_THROW(ST_ELEVEL, "no level left for a plaintext product");
   if (pt.level != a.level) PPST_THROW(ST_ESCALE, "plaintext level differs from the ciphertext's");

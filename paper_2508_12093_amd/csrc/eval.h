@@ -71,6 +71,12 @@ std::vector<CtPtr> rotsum_batch(Context& cx, const EvalKeys& evk, const std::vec
 // remain, then radix 2; the Galois keys needed are those of k s, 0 < k < radix
 std::vector<std::pair<long, int>> rotsum_plan(const Params& P);
 CtPtr level_align(Context& cx, const Ciphertext& a, int level);
+// sum_k cs[k] cts[k] at `level` with one rescale: each term (level > level)
+// cut to q_0..q_{level+1}, multiplied by round(c Delta_{level+1}
+// (Delta_{level+1} / Delta_term)), the products added, then rescaled by
+// q_{level+1}
+CtPtr lincomb(Context& cx, const std::vector<const Ciphertext*>& cts,
+              const std::vector<double>& cs, int level);
 CtPtr copy_ct(Context& cx, const Ciphertext& a);
 
 // many independent products a[i] * b[i] in one launch per stage, the key

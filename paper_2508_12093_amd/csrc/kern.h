@@ -100,6 +100,12 @@ void k_add(const Shared& sh, const u64* a, const u64* b, u64* out, int npoly, in
 // out[c][t] = a[c][t] * k[t] mod q_t  (k reduced, Shoup companions precomputed)
 void k_mul_scalar(const Shared& sh, const u64* a, u64* out, int npoly, int nl, size_t stride_a,
                   size_t stride_o, const u64* k, const u64* kp, hipStream_t st);
+// out[c][t] = sum_k K_k,t src_k[c][t] mod q_t for both polynomials c and limbs
+// t < nl (prime t): src[k] with polynomial stride ps[k]; K: host arrays
+// k[term][nl] of residues and kp[term][nl] of Shoup companions; out at
+// polynomial stride so.
+void k_lincomb(const Shared& sh, const u64* const* src, const size_t* ps, const u64* k,
+               const u64* kp, int nterm, int nl, u64* out, size_t so, hipStream_t st);
 // out[t] = a[t] + k[t] mod q_t on one polynomial
 void k_add_scalar(const Shared& sh, const u64* a, u64* out, int nl, const u64* k, hipStream_t st);
 // out[c][t] = a[c][t] * pt[t] mod q_t

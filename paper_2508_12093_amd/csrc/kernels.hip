@@ -65,6 +65,40 @@ __global__ void k_mul_poly_kernel(const u64* __restrict__ a, const u64* __restri
   out[c * so + r] = mulm(a[c * sa + r], pt[r], mods[t]);
 }
 
+// up to kLinTerms weighted terms over up to kLinLimbs limbs per launch
+constexpr int kLinTerms = 6;
+constexpr int kLinLimbs = 32;
+struct LinArgs {
+  const u64* src[kLinTerms];    // term k: [2][l_k+1][N], poly stride ps[k]
+  size_t ps[kLinTerms];
+  u64 k[kLinTerms][kLinLimbs][2];   // (K_k mod q_t, Shoup companion), t = t0 + i
+  u64* out;                     // [2][nl][N] (poly stride so)
+  size_t so;
+  int nterm, t0, nlimbs, accumulate;
+};
+
+__global__ void k_lincomb_kernel(LinArgs a, const Mod* __restrict__ mods, int logN) {
+  const size_t N = (size_t)1 << logN;
+  const size_t per = (size_t)a.nlimbs << logN;
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= per) return;
+  const int c = blockIdx.y;
+  const int li = (int)(i >> logN);
+  const int t = a.t0 + li;
+  const size_t off = ((size_t)t << logN) + (i & (N - 1));
+  const u64 q = mods[t].q;
+  u64 v[kLinTerms];
+#pragma unroll
+  for (int k = 0; k < kLinTerms; ++k)
+    v[k] = k < a.nterm ? a.src[k][c * a.ps[k] + off] : 0;
+  u64* o = a.out + c * a.so + off;
+  u64 s = a.accumulate ? *o : 0;
+#pragma unroll
+  for (int k = 0; k < kLinTerms; ++k)
+    if (k < a.nterm) s = addm(s, mul_shoup(v[k], a.k[k][li][0], a.k[k][li][1], q), q);
+  *o = s;
+}
+
 // operand pointers of up to kPtrBatch batch items, passed by value
 struct PtrBatch {
   const u64* p[kPtrBatch];
@@ -570,6 +604,35 @@ void k_add(const Shared& sh, const u64* a, const u64* b, u64* out, int npoly, in
   hipLaunchKernelGGL(k_add_kernel, grid_for(n), dim3(kBlock), 0, st, a, b, out, M(sh), sh.P.logN,
                      nl, npoly, sa, sb, so, (int)sub);
   LAUNCH_CHECK();
+}
+
+void k_lincomb(const Shared& sh, const u64* const* src, const size_t* ps, const u64* k,
+               const u64* kp, int nterm, int nl, u64* out, size_t so, hipStream_t st) {
+  if (nterm < 1 || nl < 1) PPST_THROW(ST_EINVAL, "empty linear combination");
+  for (int t0 = 0; t0 < nl; t0 += kLinLimbs) {
+    const int nlim = std::min(kLinLimbs, nl - t0);
+    for (int k0 = 0; k0 < nterm; k0 += kLinTerms) {
+      LinArgs a{};
+      a.nterm = std::min(kLinTerms, nterm - k0);
+      for (int j = 0; j < a.nterm; ++j) {
+        a.src[j] = src[k0 + j];
+        a.ps[j] = ps[k0 + j];
+        for (int i = 0; i < nlim; ++i) {
+          a.k[j][i][0] = k[(size_t)(k0 + j) * nl + t0 + i];
+          a.k[j][i][1] = kp[(size_t)(k0 + j) * nl + t0 + i];
+        }
+      }
+      a.out = out;
+      a.so = so;
+      a.t0 = t0;
+      a.nlimbs = nlim;
+      a.accumulate = k0 > 0;
+      dim3 g = grid_for((size_t)nlim * sh.P.N);
+      g.y = 2;
+      hipLaunchKernelGGL(k_lincomb_kernel, g, dim3(kBlock), 0, st, a, M(sh), sh.P.logN);
+      LAUNCH_CHECK();
+    }
+  }
 }
 
 void k_mul_scalar(const Shared& sh, const u64* a, u64* out, int npoly, int nl, size_t sa,

@@ -43,6 +43,18 @@ struct Circ {
     return mul(cx, evk, *at(a, m), *at(b, m));
   }
   CtPtr sq(const CtPtr& a) { return mul(cx, evk, *a, *a); }
+  // sum_{k=1..d} c_k T_k with one rescale, one level below the lowest T_k
+  CtPtr weighted(const std::vector<CtPtr>& T, const std::vector<double>& c, int d) {
+    std::vector<const Ciphertext*> ts;
+    std::vector<double> cs;
+    int low = T[1]->level;
+    for (int k = 1; k <= d; ++k) {
+      ts.push_back(T[k].get());
+      cs.push_back(c[k]);
+      low = std::min(low, T[k]->level);
+    }
+    return lincomb(cx, ts, cs, low - 1);
+  }
   CtPtr mc(const CtPtr& a, double c) { return mul_const(cx, *a, c); }
   CtPtr sum(const std::vector<CtPtr>& xs) {
     CtPtr acc = xs[0];
@@ -116,9 +128,7 @@ struct Circ {
         T[k] = subx(mul_int(cx, *mulx(T[m], T[m + 1]), 2), T[1]);
       }
     }
-    std::vector<CtPtr> terms;
-    for (int k = 1; k <= d; ++k) terms.push_back(mc(T[k], c[k]));
-    auto y = add_const(cx, *sum(terms), c[0]);
+    auto y = add_const(cx, *weighted(T, c, d), c[0]);
     T.clear();
     auto w2 = mc(v, Bp / 2.0);
     for (int it = 0; it < cfg.iters; ++it) {
@@ -242,9 +252,7 @@ struct Circ {
     }
     std::vector<CtPtr> y(nl), w2(nl);
     for (size_t l = 0; l < nl; ++l) {
-      std::vector<CtPtr> terms;
-      for (int k = 1; k <= d; ++k) terms.push_back(mc(T[l][k], c[l][k]));
-      y[l] = add_const(cx, *sum(terms), c[l][0]);
+      y[l] = add_const(cx, *weighted(T[l], c[l], d), c[l][0]);
       T[l].clear();
       w2[l] = mc(vs[l], Bps[l] / 2.0);
     }

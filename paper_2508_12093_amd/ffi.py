@@ -125,6 +125,7 @@ _SIGS = {
     "ppst_rotate_hoisted": (ctypes.c_int, [_vp, _vp, _vp, _vp, _sz, _pp]),
     "ppst_rotsum": (ctypes.c_int, [_vp, _vp, _vp, _pp]),
     "ppst_level_align": (ctypes.c_int, [_vp, _vp, _i32, _pp]),
+    "ppst_lincomb": (ctypes.c_int, [_vp, _pp, _vp, _sz, _i32, _pp]),
     "ppst_mul_batch": (ctypes.c_int, [_vp, _vp, _pp, _pp, _sz, _pp]),
     "ppst_rotate_hoisted_batch": (ctypes.c_int, [_vp, _vp, _pp, _sz, _vp, _sz, _pp]),
     "ppst_rotate_batch": (ctypes.c_int, [_vp, _vp, _pp, _sz, ctypes.c_int32, _pp]),
@@ -490,6 +491,13 @@ ppst_rescale = _unary("ppst_rescale")
 ppst_rotate = _unary("ppst_rotate")
 ppst_rotsum = _unary("ppst_rotsum")
 ppst_level_align = _unary("ppst_level_align")
+
+
+def ppst_lincomb(ctx, cts, cs, level):
+    out = _out()
+    c = np.ascontiguousarray(cs, dtype=np.float64)
+    _chk(lib().ppst_lincomb(ctx, _ptrs(cts), c.ctypes.data, len(cts), level, ctypes.byref(out)))
+    return Ciphertext(out.value, ctx)
 
 
 def ppst_rotate_hoisted(ctx, evk, ct, steps):

@@ -132,6 +132,30 @@ def test_linear_ops(pair):
     p.same(ffi.ppst_mul_plain(p.ctx, ca, pt), p.O.mul_plain(oa, p.O.encode(b, p.P.L)))
 
 
+def test_lincomb(pair):
+    """Weighted sums with one rescale: one term equals Mul(P) by the
+    constant; eight terms over three levels (two launches of the term loop)
+    equal the oracle's bit for bit; a term below level + 1 is refused."""
+    p = pair
+    L = p.P.L
+    cts, octs = [], []
+    for i in range(3):
+        c, o = p.encrypt(synth.uniform_column(40 + i, p.P.slots, -1, 1), 60 + i)
+        cts.append(c)
+        octs.append(o)
+    p.same(ffi.ppst_lincomb(p.ctx, [cts[0]], [0.7071], L - 1), p.O.mul_const(octs[0], 0.7071))
+    if L >= 2:
+        low = [ffi.ppst_level_align(p.ctx, c, L - 1) for c in cts]
+        olow = [p.O.level_align(o, L - 1) for o in octs]
+        terms = [cts[0], low[1], cts[2], low[0], cts[1], low[2], cts[0], low[1]]
+        oterms = [octs[0], olow[1], octs[2], olow[0], octs[1], olow[2], octs[0], olow[1]]
+        cs = [0.5, -1.25, 0.125, 3.0, -0.0625, 0.75, 2.5e-3, -7.0]
+        p.same(ffi.ppst_lincomb(p.ctx, terms, cs, L - 2), p.O.lincomb(oterms, cs, L - 2))
+        with pytest.raises(ffi.PpstError) as e:
+            ffi.ppst_lincomb(p.ctx, [low[0]], [1.0], L - 1)
+        assert e.value.name == "ELEVEL"
+
+
 def test_mul_relin_rescale(pair):
     p = pair
     a = synth.uniform_column(8, p.P.slots, -1, 1)
