@@ -246,7 +246,7 @@ class Circuits:
             y2 = ev.mul(y, y)
             p1 = self.mulx(w2, y)
             p2 = self.mulx(p1, y2)
-            y = self.subx(ev.mul_const(y, 1.5), p2)
+            y = self.subx(ev.lincomb([y], [1.5], ev.level(p2)), p2)
         return y, w2
 
     def invsqrt(self, X, B, cfg: InvSqrtCfg):
