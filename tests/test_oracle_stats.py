@@ -105,7 +105,7 @@ def test_plain_circuits_match_fp64_and_depths():
     assert abs(r["cv"].v[0] / S.cv(y) - 1) < 1e-6
     assert abs(r["pcc"].v[0] / S.pearson(x, y) - 1) < 1e-5      # v_x = 0.16: Newton residual 1.2e-6
     depth = {k: 24 - v.level for k, v in r.items()}
-    assert depth == {"zscore": 14, "kurt": 16, "skew": 16, "cv": 22, "pcc": 16}
+    assert depth == {"zscore": 14, "kurt": 16, "skew": 15, "cv": 22, "pcc": 16}
 
 
 def _exp1_cfg():
