@@ -43,6 +43,20 @@ struct Circ {
     return mul(cx, evk, *at(a, m), *at(b, m));
   }
   CtPtr sq(const CtPtr& a) { return mul(cx, evk, *a, *a); }
+  // level_align results of one ciphertext, kept per level (T_1 is subtracted
+  // from every odd Chebyshev term, several of which share a level)
+  struct LevelCache {
+    Circ* c;
+    std::map<int, CtPtr> at_level;
+    CtPtr get(const CtPtr& a, int level) {
+      if (a->level == level) return a;
+      auto it = at_level.find(level);
+      if (it != at_level.end()) return it->second;
+      return at_level[level] = c->at(a, level);
+    }
+  };
+  // c a brought to `level` (below a's) with one rescale
+  CtPtr lin1(const CtPtr& a, double c, int level) { return lincomb(cx, {a.get()}, {c}, level); }
   // sum_{k=1..d} c_k T_k with one rescale, one level below the lowest T_k
   CtPtr weighted(const std::vector<CtPtr>& T, const std::vector<double>& c, int d) {
     std::vector<const Ciphertext*> ts;
@@ -119,13 +133,15 @@ struct Circ {
     auto t = add_const(cx, *mc(v, 2.0 / (b - a)), -(a + b) / (b - a));
     std::vector<CtPtr> T(d + 1);
     T[1] = t;
+    LevelCache t1{this};
     for (int k = 2; k <= d; ++k) {
       if (k % 2 == 0) {
         int m = k / 2;
         T[k] = add_const(cx, *mul_int(cx, *sq(T[m]), 2), -1.0);
       } else {
         int m = (k - 1) / 2;
-        T[k] = subx(mul_int(cx, *mulx(T[m], T[m + 1]), 2), T[1]);
+        auto p = mul_int(cx, *mulx(T[m], T[m + 1]), 2);
+        T[k] = subx(p, t1.get(T[1], p->level));
       }
     }
     auto y = add_const(cx, *weighted(T, c, d), c[0]);
@@ -135,7 +151,7 @@ struct Circ {
       auto y2 = sq(y);
       auto p1 = mulx(w2, y);
       auto p2 = mulx(p1, y2);
-      y = subx(mc(y, 1.5), p2);
+      y = subx(lin1(y, 1.5, p2->level), p2);
     }
     return {y, w2};
   }
@@ -239,6 +255,7 @@ struct Circ {
       for (size_t l = 0; l < nl; ++l) v.push_back(T[l][k]);
       return v;
     };
+    std::vector<LevelCache> t1(nl, LevelCache{this});
     for (int k = 2; k <= d; ++k) {
       if (k % 2 == 0) {
         const int m = k / 2;
@@ -247,7 +264,10 @@ struct Circ {
       } else {
         const int m = (k - 1) / 2;
         auto p = mulx_n(lane(m), lane(m + 1));
-        for (size_t l = 0; l < nl; ++l) T[l][k] = subx(mul_int(cx, *p[l], 2), T[l][1]);
+        for (size_t l = 0; l < nl; ++l) {
+          auto q = mul_int(cx, *p[l], 2);
+          T[l][k] = subx(q, t1[l].get(T[l][1], q->level));
+        }
       }
     }
     std::vector<CtPtr> y(nl), w2(nl);
@@ -260,7 +280,7 @@ struct Circ {
       auto y2 = mulx_n(y, y);
       auto p1 = mulx_n(w2, y);
       auto p2 = mulx_n(p1, y2);
-      for (size_t l = 0; l < nl; ++l) y[l] = subx(mc(y[l], 1.5), p2[l]);
+      for (size_t l = 0; l < nl; ++l) y[l] = subx(lin1(y[l], 1.5, p2[l]->level), p2[l]);
     }
     std::vector<std::pair<CtPtr, CtPtr>> out;
     for (size_t l = 0; l < nl; ++l) out.push_back({y[l], w2[l]});
@@ -386,8 +406,8 @@ CtPtr stat_kurtosis(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& 
   auto num = c.mask_mean(x4, n);
   auto i = c.inv_sqrt(var, B * B, cfg).first;
   auto i2 = c.sq(i);
-  auto i4 = c.sq(i2);
-  auto k = c.mulx(num, i4);
+  // (num i^2) i^2 keeps every partial product near the result's size
+  auto k = c.mulx(c.mulx(num, i2), i2);
   return excess ? add_const(cx, *k, -3.0) : k;
 }
 
@@ -396,7 +416,7 @@ CtPtr stat_skewness(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& 
   check_column(cx.P(), X, n);
   check_cfg(cfg);
   Circ c{cx, evk};
-  c.check_depth(X, 5 + invsqrt_depth(cfg));
+  c.check_depth(X, 4 + invsqrt_depth(cfg));
   auto muB = c.mean_B(X, n, B);
   auto var = c.variance_B(X, n, B, muB);
   auto mu = c.mc(muB, B);
@@ -409,8 +429,7 @@ CtPtr stat_skewness(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& 
   auto num = c.mask_mean(x3, n);
   auto i = c.inv_sqrt(var, B * B, cfg).first;
   auto i2 = c.sq(i);
-  auto i3 = c.mulx(i2, i);
-  return c.mulx(num, i3);
+  return c.mulx(c.mulx(num, i), i2);
 }
 
 CtPtr stat_cv(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& X, size_t n,
