@@ -750,9 +750,12 @@ void k_ks_inner_multi(const Shared& sh, const u64* const* d, const u64* ext,
   a.nprimes = P.nprimes;
   a.nbatch = nbatch;
   a.nkeys = nkeys;
+  // items per thread: the keys are read once per group of items
   dim3 gr = grid_for((size_t)a.ne * P.N);
-  if (nbatch >= 2) {
-    gr.y = (nbatch + 1) / 2;
+  if (nbatch >= 3) {
+    gr.y = (nbatch + 2) / 3;
+    hipLaunchKernelGGL(k_ks_inner_multi_kernel<3>, gr, dim3(kBlock), 0, st, a);
+  } else if (nbatch == 2) {
     hipLaunchKernelGGL(k_ks_inner_multi_kernel<2>, gr, dim3(kBlock), 0, st, a);
   } else {
     hipLaunchKernelGGL(k_ks_inner_multi_kernel<1>, gr, dim3(kBlock), 0, st, a);
