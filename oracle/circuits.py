@@ -229,7 +229,10 @@ class Circuits:
         ev = self.ev
         a, b, d = cfg.a, cfg.b, cfg.degree
         coeffs = cfg.coeffs_for(Bp)
-        t = ev.add_const(ev.mul_const(v, 2.0 / (b - a)), -(a + b) / (b - a))
+        # the affine map onto [-1, 1]; a pure shift (b - a = 2, Eq. 1's
+        # x - 1 on [0, 2]) needs no product and no level
+        g = 2.0 / (b - a)
+        t = ev.add_const(v if g == 1.0 else ev.mul_const(v, g), -(a + b) / (b - a))
         T = {1: t}
         for k in range(2, d + 1):
             if k % 2 == 0:
@@ -276,10 +279,24 @@ class Circuits:
             x = self.g3(x)
         return x
 
+    def moments_B(self, X, n, B_mean, B_var):
+        """Mean(x, B_mean) and Variance(x, B_var) (Eq. 2) with one RotSum for
+        both: the variance's slot sum sum (x_i / (B_var sqrt n))^2 does not
+        need the mean, so the mean's sum is brought to its level and the two
+        are summed together; Var = E2 - m^2 with m = Mean(x, B_var)."""
+        ev = self.ev
+        s1 = self.sumx([ev.mul_const(x, 1.0 / (B_mean * float(n))) for x in X])
+        c = 1.0 / (B_var * math.sqrt(float(n)))
+        xs = [ev.mul_const(x, c) for x in X]
+        s2 = self.sumx([ev.mul(x, x) for x in xs])
+        muB = ev.rotsum(ev.align(s1, ev.level(s2)))
+        e2 = ev.rotsum(s2)
+        m = muB if B_var == B_mean else ev.mul_const(muB, B_mean / B_var)
+        return muB, self.subx(e2, ev.mul(m, m))
+
     # statistics ------------------------------------------------------------
     def _moments_prefix(self, X, n, B):
-        muB = self.mean_B(X, n, B)
-        var = self.variance_B(X, n, B, muB)
+        muB, var = self.moments_B(X, n, B, B)
         mu = self.ev.mul_const(muB, B)
         return muB, var, mu
 
@@ -319,12 +336,10 @@ class Circuits:
     def cv(self, X, n, B_mean, B_var, cfg: InvSqrtCfg, sign_k=2):
         """Alg. 6: Std * InvSqrt(mu * sign(mu); B_mean)^2 * sign(mu)."""
         ev = self.ev
-        muB = self.mean_B(X, n, B_mean)
+        muB, var = self.moments_B(X, n, B_mean, B_var)
         sg = self.sign(muB, sign_k)
         ia, _ = self.inv_sqrt(self.mulx(muB, sg), B_mean, cfg)
         mu_inv = ev.mul(ia, ia)
-        mean_term = muB if B_var == B_mean else ev.mul_const(muB, B_mean / B_var)
-        var = self.variance_B(X, n, B_var, mean_term)
         sigma = self.sqrt(var, B_var * B_var, cfg)
         return self.mulx(self.mulx(sigma, mu_inv), sg)
 
