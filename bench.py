@@ -249,7 +249,7 @@ def main():
 
     # ------------------- CryptoInvSqrt replay of Sec. 6.2, Exp. 1 (Tab. 2 row)
     # 32768-point grid on [0.001, 100], B = 100, Eq. 3's degree-31 Chebyshev
-    # initial value on [0, 2] and six Newton steps: 20 levels, no bootstrap.
+    # initial value on [0, 2] and six Newton steps: 19 levels, no bootstrap.
     grid = synth.exp1_grid(info.slots)
     cg = ffi.ppst_encrypt(ctx, pk, ffi.ppst_encode(ctx, grid, L), 3003)
     e1cfg = ffi.ppst_invsqrt_cfg_default(a=0.0, b=2.0, degree=31, iters=6)

@@ -55,6 +55,12 @@ struct Circ {
       return at_level[level] = c->at(a, level);
     }
   };
+  // the InvSqrt argument mapped onto [-1, 1]; a pure shift (b - a = 2, Eq. 1's
+  // x - 1 on [0, 2]) needs no product and no level
+  CtPtr affine(const CtPtr& v, double a, double b) {
+    const double g = 2.0 / (b - a);
+    return add_const(cx, g == 1.0 ? *v : *mc(v, g), -(a + b) / (b - a));
+  }
   // c a brought to `level` (below a's) with one rescale
   CtPtr lin1(const CtPtr& a, double c, int level) { return lincomb(cx, {a.get()}, {c}, level); }
   // sum_{k=1..d} c_k T_k with one rescale, one level below the lowest T_k
@@ -113,6 +119,23 @@ struct Circ {
     return subx(e2, m2);
   }
 
+  // Mean(x, B_mean) and Variance(x, B_var) with one two-lane RotSum: the
+  // variance's slot sum does not need the mean, so the mean's sum is brought
+  // to its level and both are summed together; Var = E2 - m^2 with
+  // m = Mean(x, B_var)
+  std::pair<CtPtr, CtPtr> moments(const std::vector<CtPtr>& X, size_t n, double B_mean,
+                                  double B_var) {
+    std::vector<CtPtr> t, xs;
+    for (auto& x : X) t.push_back(mc(x, 1.0 / (B_mean * (double)n)));
+    auto s1 = sum(t);
+    const double c = 1.0 / (B_var * std::sqrt((double)n));
+    for (auto& x : X) xs.push_back(mc(x, c));
+    auto s2 = sum(mulx_n(xs, xs));
+    auto r = rs_n({at(s1, s2->level), s2});
+    CtPtr m = (B_var == B_mean) ? r[0] : mc(r[0], B_mean / B_var);
+    return {r[0], subx(r[1], sq(m))};
+  }
+
   std::vector<double> coeffs(const InvSqrtCfg& cfg, double Bp) {
     std::vector<double> base;
     if (!cfg.coeffs.empty()) {
@@ -130,7 +153,7 @@ struct Circ {
     const int d = cfg.degree;
     auto c = coeffs(cfg, Bp);
     if ((int)c.size() != d + 1) PPST_THROW(ST_EINVAL, "coefficient table does not match the degree");
-    auto t = add_const(cx, *mc(v, 2.0 / (b - a)), -(a + b) / (b - a));
+    auto t = affine(v, a, b);
     std::vector<CtPtr> T(d + 1);
     T[1] = t;
     LevelCache t1{this};
@@ -204,39 +227,6 @@ struct Circ {
     return out;
   }
 
-  std::vector<CtPtr> mean_B_n(const std::vector<std::vector<CtPtr>>& Xs, size_t n,
-                              const std::vector<double>& Bs) {
-    std::vector<CtPtr> sums;
-    for (size_t l = 0; l < Xs.size(); ++l) {
-      const double c = 1.0 / (Bs[l] * (double)n);
-      std::vector<CtPtr> t;
-      for (auto& x : Xs[l]) t.push_back(mc(x, c));
-      sums.push_back(sum(t));
-    }
-    return rs_n(sums);
-  }
-
-  std::vector<CtPtr> variance_B_n(const std::vector<std::vector<CtPtr>>& Xs, size_t n,
-                                  const std::vector<double>& Bs,
-                                  const std::vector<CtPtr>& mean_terms) {
-    std::vector<CtPtr> xs;
-    std::vector<size_t> first;
-    for (size_t l = 0; l < Xs.size(); ++l) {
-      const double c = 1.0 / (Bs[l] * std::sqrt((double)n));
-      first.push_back(xs.size());
-      for (auto& x : Xs[l]) xs.push_back(mc(x, c));
-    }
-    auto sqs = mulx_n(xs, xs);
-    std::vector<CtPtr> sums;
-    for (size_t l = 0; l < Xs.size(); ++l)
-      sums.push_back(sum(std::vector<CtPtr>(sqs.begin() + first[l], sqs.begin() + first[l] + Xs[l].size())));
-    auto e2 = rs_n(sums);
-    auto m2 = mulx_n(mean_terms, mean_terms);
-    std::vector<CtPtr> out;
-    for (size_t l = 0; l < Xs.size(); ++l) out.push_back(subx(e2[l], m2[l]));
-    return out;
-  }
-
   std::vector<std::pair<CtPtr, CtPtr>> inv_sqrt_n(const std::vector<CtPtr>& vs,
                                                   const std::vector<double>& Bps,
                                                   const InvSqrtCfg& cfg) {
@@ -248,7 +238,7 @@ struct Circ {
     for (size_t l = 0; l < nl; ++l) {
       c[l] = coeffs(cfg, Bps[l]);
       if ((int)c[l].size() != d + 1) PPST_THROW(ST_EINVAL, "coefficient table does not match the degree");
-      T[l][1] = add_const(cx, *mc(vs[l], 2.0 / (b - a)), -(a + b) / (b - a));
+      T[l][1] = affine(vs[l], a, b);
     }
     auto lane = [&](int k) {
       std::vector<CtPtr> v;
@@ -316,7 +306,8 @@ void check_cfg(const InvSqrtCfg& cfg) {
 int invsqrt_depth(const InvSqrtCfg& cfg) {
   int ladder = 0;
   while ((1 << ladder) < cfg.degree + 1) ++ladder;
-  return 1 + ladder + 1 + 2 * cfg.iters;
+  const int affine = 2.0 / (cfg.b - cfg.a) == 1.0 ? 0 : 1;
+  return affine + ladder + 1 + 2 * cfg.iters;
 }
 
 }  // namespace
@@ -378,11 +369,10 @@ std::vector<CtPtr> stat_zscore(Context& cx, const EvalKeys& evk, const std::vect
   check_column(cx.P(), X, n);
   check_cfg(cfg);
   Circ c{cx, evk};
-  c.check_depth(X, 3 + invsqrt_depth(cfg));
-  auto muB = c.mean_B(X, n, B);
-  auto var = c.variance_B(X, n, B, muB);
-  auto mu = c.mc(muB, B);
-  auto b = c.inv_sqrt(var, B * B, cfg).first;
+  c.check_depth(X, 4 + invsqrt_depth(cfg));
+  auto mv = c.moments(X, n, B, B);
+  auto mu = c.mc(mv.first, B);
+  auto b = c.inv_sqrt(mv.second, B * B, cfg).first;
   std::vector<CtPtr> out;
   for (auto& x : X) out.push_back(c.mulx(c.subx(x, mu), b));
   return out;
@@ -393,10 +383,10 @@ CtPtr stat_kurtosis(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& 
   check_column(cx.P(), X, n);
   check_cfg(cfg);
   Circ c{cx, evk};
-  c.check_depth(X, 5 + invsqrt_depth(cfg));
-  auto muB = c.mean_B(X, n, B);
-  auto var = c.variance_B(X, n, B, muB);
-  auto mu = c.mc(muB, B);
+  c.check_depth(X, 6 + invsqrt_depth(cfg));
+  auto mv = c.moments(X, n, B, B);
+  auto var = mv.second;
+  auto mu = c.mc(mv.first, B);
   std::vector<CtPtr> x4;
   for (auto& x : X) {
     auto x1 = c.subx(x, mu);
@@ -416,10 +406,10 @@ CtPtr stat_skewness(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& 
   check_column(cx.P(), X, n);
   check_cfg(cfg);
   Circ c{cx, evk};
-  c.check_depth(X, 4 + invsqrt_depth(cfg));
-  auto muB = c.mean_B(X, n, B);
-  auto var = c.variance_B(X, n, B, muB);
-  auto mu = c.mc(muB, B);
+  c.check_depth(X, 5 + invsqrt_depth(cfg));
+  auto mv = c.moments(X, n, B, B);
+  auto var = mv.second;
+  auto mu = c.mc(mv.first, B);
   std::vector<CtPtr> x3;
   for (auto& x : X) {
     auto x1 = c.subx(x, mu);
@@ -438,15 +428,14 @@ CtPtr stat_cv(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& X, siz
   check_cfg(cfg);
   if (sign_k < 0 || sign_k > 8) PPST_THROW(ST_EDOMAIN, "sign composition count out of range");
   Circ c{cx, evk};
-  c.check_depth(X, 1 + 3 * sign_k + 1 + invsqrt_depth(cfg) + 3);
-  auto muB = c.mean_B(X, n, B_mean);
+  c.check_depth(X, 2 + 3 * sign_k + 1 + invsqrt_depth(cfg) + 3);
+  auto mv = c.moments(X, n, B_mean, B_var);
+  auto muB = mv.first;
   CtPtr sg = muB;
   for (int k = 0; k < sign_k; ++k) sg = c.g3(sg);
   auto ia = c.inv_sqrt(c.mulx(muB, sg), B_mean, cfg).first;
   auto mu_inv = c.sq(ia);
-  CtPtr mean_term = (B_var == B_mean) ? muB : c.mc(muB, B_mean / B_var);
-  auto var = c.variance_B(X, n, B_var, mean_term);
-  auto sigma = c.sqrt_(var, B_var * B_var, cfg);
+  auto sigma = c.sqrt_(mv.second, B_var * B_var, cfg);
   return c.mulx(c.mulx(sigma, mu_inv), sg);
 }
 
