@@ -494,7 +494,9 @@ def serving_bench(ctx, pk, sk, evk, nq: int, loads, seed: int = 4):
                        "failed": nf})
         log("serving: offered %.1f q/s -> p50 %.1f ms, p99 %.1f ms" % (
             rate, points[-1]["p50_ms"], points[-1]["p99_ms"]))
+    t = time.perf_counter()
     del srv
+    log("serving: server closed in %.1f s" % (time.perf_counter() - t))
     return {"saturation_qps": round(sat_rate, 2), "queries_per_point": nq,
             "rows": SERVING_ROWS, "kinds": "mean,variance,zscore,cv,pearson", "slots": 8,
             "loads": points, "failed": nfail, "spot_max_err": float(max(errs)) if errs else None}

@@ -158,13 +158,33 @@ class Pool {
   std::vector<void*> end_capture();
   void unpin(const std::vector<void*>& blocks);
  private:
+  // Blocks up to kSlabBlockMax bytes are carved from slabs of kSlabBytes (one
+  // device allocation serves many ciphertexts); larger ones are allocations
+  // of their own.  A slab is returned to the device by trim() once none of
+  // its blocks is in use.
+  static constexpr size_t kSlabBytes = (size_t)256 << 20;
+  static constexpr size_t kSlabBlockMax = (size_t)32 << 20;
+  struct Slab {
+    char* base;
+    size_t offset;
+    int inuse;      // carved blocks currently handed out (or pinned)
+    bool dead;
+  };
+  void* raw_alloc(size_t bytes);
+  void raw_free(void* p, size_t bytes);
+  void* alloc_retry(size_t bytes);
+  void* hand_out(void* p, size_t bytes);   // bookkeeping of a block leaving the pool (mu_ held)
+
   hipStream_t stream_;
   Hooks hooks_;
   std::shared_ptr<PoolRegistry> registry_;
   std::mutex mu_;
   std::multimap<size_t, void*> free_;
   std::map<void*, size_t> sizes_;
-  size_t in_use_ = 0, cached_ = 0;
+  std::map<void*, int> slab_of_;   // carved block -> slab index
+  std::vector<Slab> slabs_;
+  int cur_ = -1;                   // slab being carved
+  size_t in_use_ = 0, cached_ = 0, nalloc_ = 0;
   bool capturing_ = false;
   std::vector<void*> captured_;
   std::map<void*, bool> pinned_;   // block -> released by its owner

@@ -12,61 +12,105 @@
 namespace ppst {
 
 // =========================================================== memory pool
-Pool::~Pool() { trim(); }
+Pool::~Pool() {
+  if (std::getenv("PPST_POOL_LOG"))
+    std::fprintf(stderr, "[ppstat] pool: %zu device allocations (%zu slabs), %zu blocks (%zu bytes) cached at exit\n",
+                 nalloc_, slabs_.size(), free_.size(), cached_);
+  trim();
+}
 
-void* Pool::get(size_t bytes) {
-  if (bytes == 0) bytes = 256;
-  bytes = (bytes + 4095) & ~(size_t)4095;
-  {
-    std::lock_guard<std::mutex> g(mu_);
-    auto it = free_.lower_bound(bytes);
-    if (it != free_.end() && it->first <= bytes + bytes / 4) {
-      void* p = it->second;
-      size_t sz = it->first;
-      free_.erase(it);
-      cached_ -= sz;
-      in_use_ += sz;
-      // remember the real block size
-      sizes_[p] = sz;
-      if (capturing_) {
-        captured_.push_back(p);
-        pinned_[p] = false;
-      }
-      return p;
-    }
-  }
+namespace {
+// Block sizes come in classes so that cached blocks are reused across
+// requests of similar size (ciphertexts of neighbouring levels, batches of
+// different lengths) instead of piling up one block per distinct size:
+// 4 KiB granules up to 64 KiB, then four classes per power of two
+// (2^k, 1.25, 1.5, 1.75 x 2^k), at most 25 % above the request.
+size_t size_class(size_t bytes) {
+  if (bytes <= ((size_t)1 << 16)) return (bytes + 4095) & ~(size_t)4095;
+  const int k = 63 - __builtin_clzll((unsigned long long)bytes);
+  const size_t step = ((size_t)1 << k) / 4;
+  return (bytes + step - 1) / step * step;
+}
+}  // namespace
+
+void* Pool::raw_alloc(size_t bytes) {
   void* p = nullptr;
-  auto try_alloc = [&]() -> bool {
-    if (hooks_.alloc) {
-      p = hooks_.alloc(bytes, (void*)stream_, hooks_.user);
-      return p != nullptr;
-    }
-    return hipMalloc(&p, bytes) == hipSuccess;
-  };
-  if (!try_alloc()) {
+  if (hooks_.alloc) return hooks_.alloc(bytes, (void*)stream_, hooks_.user);
+  if (hipMalloc(&p, bytes) != hipSuccess) {
     (void)hipGetLastError();
-    if (capturing_)   // no synchronisation is possible while a recording is open
-      PPST_THROW(ST_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
-    trim();
-    bool ok = try_alloc();
-    if (!ok && registry_) {   // the caches of the other contexts' pools
-      (void)hipGetLastError();
-      registry_->trim_others(this);
-      ok = try_alloc();
-    }
-    if (!ok) {
-      (void)hipGetLastError();
-      PPST_THROW(ST_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
-    }
+    return nullptr;
   }
-  std::lock_guard<std::mutex> g(mu_);
+  return p;
+}
+
+void Pool::raw_free(void* p, size_t bytes) {
+  if (hooks_.free) hooks_.free(p, bytes, (void*)stream_, hooks_.user);
+  else (void)hipFree(p);
+}
+
+// a device allocation; on failure this pool's cache is released, then the
+// other pools' of the same tables, before giving up
+void* Pool::alloc_retry(size_t bytes) {
+  void* p = raw_alloc(bytes);
+  if (p) return p;
+  if (capturing_)   // no synchronisation is possible while a recording is open
+    PPST_THROW(ST_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  if (std::getenv("PPST_POOL_LOG"))
+    std::fprintf(stderr, "[ppstat] allocation of %zu bytes failed; freeing %zu cached bytes\n",
+                 bytes, cached_);
+  trim();
+  p = raw_alloc(bytes);
+  if (!p && registry_) {
+    registry_->trim_others(this);
+    p = raw_alloc(bytes);
+  }
+  if (!p) PPST_THROW(ST_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  return p;
+}
+
+void* Pool::hand_out(void* p, size_t bytes) {
   in_use_ += bytes;
   sizes_[p] = bytes;
+  auto s = slab_of_.find(p);
+  if (s != slab_of_.end()) ++slabs_[s->second].inuse;
   if (capturing_) {
     captured_.push_back(p);
     pinned_[p] = false;
   }
   return p;
+}
+
+void* Pool::get(size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  bytes = size_class(bytes);
+  std::unique_lock<std::mutex> g(mu_);
+  auto it = free_.find(bytes);
+  if (it != free_.end()) {
+    void* p = it->second;
+    free_.erase(it);
+    cached_ -= bytes;
+    return hand_out(p, bytes);
+  }
+  if (bytes <= kSlabBlockMax) {
+    if (cur_ < 0 || slabs_[cur_].offset + bytes > kSlabBytes) {
+      g.unlock();
+      char* base = (char*)alloc_retry(kSlabBytes);
+      g.lock();
+      ++nalloc_;
+      slabs_.push_back(Slab{base, 0, 0, false});
+      cur_ = (int)slabs_.size() - 1;
+    }
+    Slab& sl = slabs_[cur_];
+    void* p = sl.base + sl.offset;
+    sl.offset += bytes;
+    slab_of_[p] = cur_;
+    return hand_out(p, bytes);
+  }
+  g.unlock();
+  void* p = alloc_retry(bytes);
+  g.lock();
+  ++nalloc_;
+  return hand_out(p, bytes);
 }
 
 void Pool::put(void* p, size_t) {
@@ -82,6 +126,8 @@ void Pool::put(void* p, size_t) {
   in_use_ -= sz;
   cached_ += sz;
   free_.emplace(sz, p);
+  auto s = slab_of_.find(p);
+  if (s != slab_of_.end()) --slabs_[s->second].inuse;
 }
 
 void Pool::begin_capture() {
@@ -112,6 +158,8 @@ void Pool::unpin(const std::vector<void*>& blocks) {
       in_use_ -= sz;
       cached_ += sz;
       free_.emplace(sz, p);
+      auto s = slab_of_.find(p);
+      if (s != slab_of_.end()) --slabs_[s->second].inuse;
     }
   }
 }
@@ -131,16 +179,32 @@ void PoolRegistry::trim_others(const Pool* except) {
       if (p.get() != except) p->trim();
 }
 
+// Returns every cached block of its own and every slab none of whose blocks
+// is in use; blocks of slabs still in use stay cached.
 void Pool::trim() {
   std::lock_guard<std::mutex> g(mu_);
   if (capturing_) return;   // a recording stream cannot be synchronised
   if (!free_.empty()) (void)hipStreamSynchronize(stream_);
-  for (auto& kv : free_) {
-    if (hooks_.free) hooks_.free(kv.second, kv.first, (void*)stream_, hooks_.user);
-    else (void)hipFree(kv.second);
+  for (auto it = free_.begin(); it != free_.end();) {
+    auto s = slab_of_.find(it->second);
+    if (s == slab_of_.end()) {
+      raw_free(it->second, it->first);
+    } else if (slabs_[s->second].inuse == 0) {
+      slab_of_.erase(s);
+    } else {
+      ++it;
+      continue;
+    }
+    cached_ -= it->first;
+    it = free_.erase(it);
   }
-  free_.clear();
-  cached_ = 0;
+  for (size_t i = 0; i < slabs_.size(); ++i) {
+    Slab& sl = slabs_[i];
+    if (sl.dead || sl.inuse != 0) continue;
+    raw_free(sl.base, kSlabBytes);
+    sl.dead = true;
+    if (cur_ == (int)i) cur_ = -1;
+  }
 }
 
 namespace {
@@ -1241,6 +1305,8 @@ CtPtr level_align(Context& cx, const Ciphertext& a, int level) {
   return out;
 }
 
+constexpr size_t kMulChunk = 16;
+
 std::vector<CtPtr> mul_batch(Context& cx, const EvalKeys& evk,
                              const std::vector<const Ciphertext*>& a,
                              const std::vector<const Ciphertext*>& b) {
@@ -1262,16 +1328,20 @@ std::vector<CtPtr> mul_batch(Context& cx, const EvalKeys& evk,
     pa[i] = a[i]->buf.p;
     pb[i] = b[i]->buf.p;
   }
-  Buf D = dev_buf(cx.pool, 3 * per * n);
-  k_tensor(*cx.sh, pa.data(), pb.data(), D.p, nl, (int)n, 3 * per, cx.stream);
-  Buf u = ks_accumulate(cx, key, D.p + 2 * per, 3 * per, level, (int)n, 0, D.p);
   std::vector<CtPtr> outs;
-  std::vector<u64*> po(n);
-  for (size_t i = 0; i < n; ++i) {
-    outs.push_back(new_ct(cx, level - 1, P.scale[level - 1]));
-    po[i] = outs.back()->buf.p;
+  for (size_t i = 0; i < n; ++i) outs.push_back(new_ct(cx, level - 1, P.scale[level - 1]));
+  // groups of kMulChunk products: the inner product already reads the key
+  // once per 8 items, and the key-switching scratch (about 130 MiB per
+  // product at level 24) stays bounded for long batches
+  for (size_t b0 = 0; b0 < n; b0 += kMulChunk) {
+    const int nb = (int)std::min<size_t>(kMulChunk, n - b0);
+    Buf D = dev_buf(cx.pool, 3 * per * nb);
+    k_tensor(*cx.sh, pa.data() + b0, pb.data() + b0, D.p, nl, nb, 3 * per, cx.stream);
+    Buf u = ks_accumulate(cx, key, D.p + 2 * per, 3 * per, level, nb, 0, D.p);
+    std::vector<u64*> po(nb);
+    for (int i = 0; i < nb; ++i) po[i] = outs[b0 + i]->buf.p;
+    ks_moddown_rescale(cx, u, D.p, 3 * per, level, po.data(), nb);
   }
-  ks_moddown_rescale(cx, u, D.p, 3 * per, level, po.data(), (int)n);
   return outs;
 }
 
