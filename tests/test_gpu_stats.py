@@ -137,6 +137,25 @@ def test_t2_invsqrt_bit_exact(t2):
     assert np.max(np.abs(p.decrypt(got[0]) / cheb.exp1_model(v) - 1)) < 1e-4
 
 
+def test_t2_invsqrt_degree_63_and_limits(t2):
+    """A degree-63 Chebyshev ladder (62 products, its 63-term weighted sum
+    over eleven launches of six terms) stays bit-exact; degree 512 and a
+    negative interval start are refused."""
+    p = t2
+    base = cheb.invsqrt_coeffs(0.05, 1.0, 63, 1.0)
+    cfg = ffi.ppst_invsqrt_cfg_default(coeffs=base, a=0.05, b=1.0, degree=63, iters=2)
+    ocfg = C.InvSqrtCfg(a=0.05, b=1.0, degree=63, iters=2, coeffs=base)
+    v = synth.uniform_column(21, p.P.slots, 0.05, 1.0)
+    c, o = p.encrypt(v, 711)
+    got = ffi.ppst_stat_invsqrt(p.ctx, p.evk, [c], 1.0, cfg)[0]
+    p.same(got, p.cc.invsqrt([o], 1.0, ocfg)[0])
+    assert np.max(np.abs(p.decrypt(got) * np.sqrt(v) - 1)) < 1e-3
+    for bad in (ffi.ppst_invsqrt_cfg_default(degree=512), ffi.ppst_invsqrt_cfg_default(a=-0.5)):
+        with pytest.raises(ffi.PpstError) as e:
+            ffi.ppst_stat_invsqrt(p.ctx, p.evk, [c], 1.0, bad)
+        assert e.value.name == "EDOMAIN"
+
+
 def test_t2_depth_errors(t2):
     p = t2
     x = synth.uniform_column(9, 100)
