@@ -298,9 +298,11 @@ int ppst_invsqrt_cfg_default(ppst_invsqrt_cfg* out);
 /* CryptoInvSqrt slot by slot (Sec. 4, Alg. 2-3; Sec. 6.2, Exp. 1): each of
  * the nct ciphertexts x (one level) is scaled to v = x/B and its inverse
  * square root InvSqrt(v; B) ~ 1/sqrt(x) written to outs[i] (caller frees).
- * Consumes 1 + (1 + ceil(log2(degree + 1)) + 1 + 2 iters) levels; a Chebyshev
- * degree of up to 511 holds degree + 1 ciphertexts per input while it runs.
- * B > 0; the interval needs 0 <= a < b (a = 0, b = 2 is Eq. 1's domain map). */
+ * Consumes 1 + (m + ceil(log2(degree + 1)) + 1 + 2 iters) levels, m = 0 when
+ * b - a = 2 (the map onto [-1, 1] is then a shift, as Eq. 1's x - 1 on
+ * [0, 2]) and 1 otherwise; a Chebyshev degree of up to 511 holds degree + 1
+ * ciphertexts per input while it runs.  B > 0; the interval needs
+ * 0 <= a < b. */
 int ppst_stat_invsqrt(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciphertext* const* x,
                       size_t nct, double B, const ppst_invsqrt_cfg* cfg,
                       ppst_ciphertext** outs /* nct */);
@@ -309,7 +311,11 @@ int ppst_stat_invsqrt(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_c
  * past nrows are zero).  Each statistic writes ciphertexts whose every slot
  * holds the result (ZNorm: one output per input ciphertext).
  * Preconditions that cannot be checked on encrypted data (Var/B^2 and
- * |mean|/B inside [a, b]) are the caller's (Sec. 5.1). */
+ * |mean|/B inside [a, b]) are the caller's (Sec. 5.1).  ZNorm, kurtosis,
+ * skewness and CV form the mean and the variance's slot sum with one
+ * two-lane rotate-and-sum; PCC forms all five of its slot sums (both means,
+ * both second moments, the cross moment) with one five-lane rotate-and-sum,
+ * so its two columns must have the same length and level (EINVAL). */
 int ppst_stat_mean(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciphertext* const* col,
                    size_t nct, size_t nrows, double B, ppst_ciphertext** out);          /* Mean/B */
 int ppst_stat_variance(ppst_context* ctx, const ppst_eval_keys* evk,
