@@ -1134,13 +1134,10 @@ std::vector<CtPtr> rotate_hoisted_batch(Context& cx, const EvalKeys& evk,
   return outs;
 }
 
-namespace {
-
-// rotate_batch; with accumulate, each output is cts[i] + rot(cts[i], r) (the
-// sum formed in the last pass of the ModDown conversion's NTT)
-std::vector<CtPtr> rotate_batch_impl(Context& cx, const EvalKeys& evk,
-                                     const std::vector<const Ciphertext*>& cts, long r,
-                                     bool accumulate) {
+// one key switch over the batch: the c1 polynomials side by side, the
+// automorphism folded into the reads
+std::vector<CtPtr> rotate_batch(Context& cx, const EvalKeys& evk,
+                                const std::vector<const Ciphertext*>& cts, long r) {
   const size_t n = cts.size();
   if (n == 0) return {};
   const Params& P = cx.P();
@@ -1153,7 +1150,7 @@ std::vector<CtPtr> rotate_batch_impl(Context& cx, const EvalKeys& evk,
   const u64 g = galois_elt(P, r);
   std::vector<CtPtr> outs;
   if (g == 1) {
-    for (const Ciphertext* c : cts) outs.push_back(accumulate ? add(cx, *c, *c) : copy_ct(cx, *c));
+    for (const Ciphertext* c : cts) outs.push_back(copy_ct(cx, *c));
     return outs;
   }
   const KsKey& key = galois_key(evk, g);
@@ -1172,24 +1169,15 @@ std::vector<CtPtr> rotate_batch_impl(Context& cx, const EvalKeys& evk,
   }
   Buf u = ks_accumulate(cx, key, dp, per, level, (int)n, (uint32_t)g);
   d.release();
-  std::vector<const u64*> add0(n), acc(n);
+  std::vector<const u64*> add0(n);
   std::vector<u64*> po(n);
   for (size_t i = 0; i < n; ++i) {
     outs.push_back(new_ct(cx, level, cts[i]->scale));
     add0[i] = cts[i]->poly(0);
-    acc[i] = cts[i]->buf.p;
     po[i] = outs.back()->buf.p;
   }
-  ks_moddown_ptr(cx, u, level, (int)n, add0.data(), nullptr, accumulate ? acc.data() : nullptr,
-                 po.data(), (uint32_t)g);
+  ks_moddown_ptr(cx, u, level, (int)n, add0.data(), nullptr, nullptr, po.data(), (uint32_t)g);
   return outs;
-}
-
-}  // namespace
-
-std::vector<CtPtr> rotate_batch(Context& cx, const EvalKeys& evk,
-                                const std::vector<const Ciphertext*>& cts, long r) {
-  return rotate_batch_impl(cx, evk, cts, r, false);
 }
 
 std::vector<std::pair<long, int>> rotsum_plan(const Params& P) {
