@@ -382,6 +382,10 @@ int ppst_server_create(ppst_context* ctx, const ppst_eval_keys* evk, size_t hbm_
 int ppst_server_register_column(ppst_server* srv, const ppst_ciphertext* const* cts, size_t nct,
                                 size_t nrows, uint64_t* col_id);
 int ppst_server_submit(ppst_server* srv, const ppst_query* q, uint64_t* ticket);
+/* *done = 1 once the query has finished, 0 while it is pending or running;
+ * never blocks.  The result stays with the server until ppst_server_wait
+ * collects it.  EINVAL for an unknown (or already collected) ticket. */
+int ppst_server_poll(ppst_server* srv, uint64_t ticket, int32_t* done);
 /* blocks until the query has finished; out receives the result ciphertext
  * (ZNorm: the first output ciphertext).  Returns the query's own status. */
 int ppst_server_wait(ppst_server* srv, uint64_t ticket, ppst_ciphertext** out,

@@ -885,6 +885,13 @@ int ppst_server_submit(ppst_server* srv, const ppst_query* q, uint64_t* ticket) 
     *ticket = srv->s->submit(Q);
   });
 }
+int ppst_server_poll(ppst_server* srv, uint64_t ticket, int32_t* done) {
+  return guard([&] {
+    NEED(srv);
+    NEED(done);
+    *done = srv->s->poll(ticket) ? 1 : 0;
+  });
+}
 int ppst_server_wait(ppst_server* srv, uint64_t ticket, ppst_ciphertext** out,
                      ppst_query_stats* stats) {
   int status = PPST_OK;

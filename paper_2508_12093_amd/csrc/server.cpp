@@ -147,6 +147,13 @@ void Server::worker(int idx) {
   }
 }
 
+bool Server::poll(u64 ticket) {
+  std::lock_guard<std::mutex> g(mu_);
+  auto it = states_.find(ticket);
+  if (it == states_.end()) PPST_THROW(ST_EINVAL, "unknown ticket");
+  return it->second->done;
+}
+
 int Server::wait(u64 ticket, CtPtr* out, QueryState* stats) {
   std::unique_lock<std::mutex> g(mu_);
   auto it = states_.find(ticket);

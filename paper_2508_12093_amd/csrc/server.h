@@ -42,6 +42,8 @@ class Server {
   u64 submit(const Query& q);
   // blocks; returns the query's status and moves the result out
   int wait(u64 ticket, CtPtr* out, QueryState* stats);
+  // whether the query has finished (its result stays until wait() collects it)
+  bool poll(u64 ticket);
   size_t estimate_bytes(const Query& q) const;
 
  private:

@@ -151,6 +151,7 @@ _SIGS = {
     "ppst_server_register_column": (ctypes.c_int, [_vp, _pp, _sz, _sz, ctypes.POINTER(_u64)]),
     "ppst_server_submit": (ctypes.c_int, [_vp, ctypes.POINTER(Query), ctypes.POINTER(_u64)]),
     "ppst_server_wait": (ctypes.c_int, [_vp, _u64, _pp, ctypes.POINTER(QueryStats)]),
+    "ppst_server_poll": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32)]),
     "ppst_server_destroy": (ctypes.c_int, [_vp]),
 }
 
@@ -668,6 +669,12 @@ def ppst_server_submit(srv: Server, kind: int, col_x: int, col_y: int = 0, B: fl
     t = _u64()
     _chk(lib().ppst_server_submit(srv, ctypes.byref(q), ctypes.byref(t)))
     return t.value
+
+
+def ppst_server_poll(srv, ticket) -> bool:
+    done = ctypes.c_int32(0)
+    _chk(lib().ppst_server_poll(srv, ticket, ctypes.byref(done)))
+    return bool(done.value)
 
 
 def ppst_server_wait(srv: Server, ticket: int):

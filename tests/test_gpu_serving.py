@@ -139,3 +139,22 @@ def test_bad_queries(env):
     assert rc == -7 and ct is None            # EDOMAIN from the worker, server keeps going
     t = ffi.ppst_server_submit(srv, ffi.Q_MEAN, cid, 0, 1.0, 1.0, cfg)
     assert ffi.ppst_server_wait(srv, t)[0] == 0
+    with pytest.raises(ffi.PpstError) as e:      # collected already
+        ffi.ppst_server_poll(srv, t)
+    assert e.value.name == "EINVAL"
+
+
+def test_poll_does_not_block(env):
+    """ppst_server_poll reports pending work without blocking and turns true
+    once the query is done; the result is then collected by wait."""
+    ctx, sk, evk, cols = env
+    cfg = ffi.ppst_invsqrt_cfg_default()
+    n, x, y, cx, cy = cols["b"]
+    srv = ffi.ppst_server_create(ctx, evk, 8 << 30, 1)
+    cid = ffi.ppst_server_register_column(srv, cx, n)
+    ts = [ffi.ppst_server_submit(srv, ffi.Q_ZSCORE, cid, 0, 1.0, 1.0, cfg) for _ in range(3)]
+    assert not ffi.ppst_server_poll(srv, ts[-1])   # one slot: the last one is still queued
+    rc, ct, st = ffi.ppst_server_wait(srv, ts[-1])
+    assert rc == 0
+    assert all(ffi.ppst_server_poll(srv, t) for t in ts[:-1])   # served before it, in order
+    assert all(ffi.ppst_server_wait(srv, t)[0] == 0 for t in ts[:-1])
