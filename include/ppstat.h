@@ -254,7 +254,8 @@ int ppst_level_align(ppst_context* ctx, const ppst_ciphertext* a, int32_t level,
 int ppst_lincomb(ppst_context* ctx, const ppst_ciphertext* const* cts, const double* cs, size_t n,
                  int32_t level, ppst_ciphertext** out);
 /* n independent products a[i] * b[i] (same level): each stage of tensor,
- * relinearisation and rescale runs once over the whole batch */
+ * relinearisation and rescale runs once per group of 16 products (the key
+ * is read once per 8 products inside the inner product) */
 int ppst_mul_batch(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciphertext* const* a,
                    const ppst_ciphertext* const* b, size_t n, ppst_ciphertext** outs);
 

@@ -79,8 +79,8 @@ CtPtr lincomb(Context& cx, const std::vector<const Ciphertext*>& cts,
               const std::vector<double>& cs, int level);
 CtPtr copy_ct(Context& cx, const Ciphertext& a);
 
-// many independent products a[i] * b[i] in one launch per stage, the key
-// read once per batch
+// many independent products a[i] * b[i], one launch per stage for each group
+// of 16 products (the inner product reads the key once per 8 of them)
 std::vector<CtPtr> mul_batch(Context& cx, const EvalKeys& evk, const std::vector<const Ciphertext*>& a,
                              const std::vector<const Ciphertext*>& b);
 
