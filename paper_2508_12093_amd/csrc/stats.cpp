@@ -149,34 +149,7 @@ struct Circ {
   }
 
   std::pair<CtPtr, CtPtr> inv_sqrt(const CtPtr& v, double Bp, const InvSqrtCfg& cfg) {
-    const double a = cfg.a, b = cfg.b;
-    const int d = cfg.degree;
-    auto c = coeffs(cfg, Bp);
-    if ((int)c.size() != d + 1) PPST_THROW(ST_EINVAL, "coefficient table does not match the degree");
-    auto t = affine(v, a, b);
-    std::vector<CtPtr> T(d + 1);
-    T[1] = t;
-    LevelCache t1{this};
-    for (int k = 2; k <= d; ++k) {
-      if (k % 2 == 0) {
-        int m = k / 2;
-        T[k] = add_const(cx, *mul_int(cx, *sq(T[m]), 2), -1.0);
-      } else {
-        int m = (k - 1) / 2;
-        auto p = mul_int(cx, *mulx(T[m], T[m + 1]), 2);
-        T[k] = subx(p, t1.get(T[1], p->level));
-      }
-    }
-    auto y = add_const(cx, *weighted(T, c, d), c[0]);
-    T.clear();
-    auto w2 = mc(v, Bp / 2.0);
-    for (int it = 0; it < cfg.iters; ++it) {
-      auto y2 = sq(y);
-      auto p1 = mulx(w2, y);
-      auto p2 = mulx(p1, y2);
-      y = subx(lin1(y, 1.5, p2->level), p2);
-    }
-    return {y, w2};
+    return inv_sqrt_n({v}, {Bp}, cfg)[0];
   }
 
   CtPtr sqrt_(const CtPtr& v, double Bp, const InvSqrtCfg& cfg) {
@@ -240,25 +213,26 @@ struct Circ {
       if ((int)c[l].size() != d + 1) PPST_THROW(ST_EINVAL, "coefficient table does not match the degree");
       T[l][1] = affine(vs[l], a, b);
     }
-    auto lane = [&](int k) {
-      std::vector<CtPtr> v;
-      for (size_t l = 0; l < nl; ++l) v.push_back(T[l][k]);
-      return v;
-    };
+    // T_k = 2 T_m T_{m+1} - T_1 (k = 2m + 1) or 2 T_m^2 - 1 (k = 2m): the terms
+    // with 2^w < k <= 2^(w+1) need only earlier ones and share a level, so
+    // each such wave is one batch of products over all lanes
     std::vector<LevelCache> t1(nl, LevelCache{this});
-    for (int k = 2; k <= d; ++k) {
-      if (k % 2 == 0) {
-        const int m = k / 2;
-        auto p = mulx_n(lane(m), lane(m));
-        for (size_t l = 0; l < nl; ++l) T[l][k] = add_const(cx, *mul_int(cx, *p[l], 2), -1.0);
-      } else {
-        const int m = (k - 1) / 2;
-        auto p = mulx_n(lane(m), lane(m + 1));
+    for (int w = 0; (1 << w) < d; ++w) {
+      const int lo = (1 << w) + 1, hi = std::min(1 << (w + 1), d);
+      std::vector<CtPtr> A, B;
+      for (int k = lo; k <= hi; ++k)
         for (size_t l = 0; l < nl; ++l) {
-          auto q = mul_int(cx, *p[l], 2);
-          T[l][k] = subx(q, t1[l].get(T[l][1], q->level));
+          const int m = k / 2;
+          A.push_back(T[l][m]);
+          B.push_back(T[l][(k % 2) ? m + 1 : m]);
         }
-      }
+      auto p = mulx_n(A, B);
+      size_t i = 0;
+      for (int k = lo; k <= hi; ++k)
+        for (size_t l = 0; l < nl; ++l, ++i) {
+          auto q = mul_int(cx, *p[i], 2);
+          T[l][k] = (k % 2) ? subx(q, t1[l].get(T[l][1], q->level)) : add_const(cx, *q, -1.0);
+        }
     }
     std::vector<CtPtr> y(nl), w2(nl);
     for (size_t l = 0; l < nl; ++l) {
@@ -267,8 +241,12 @@ struct Circ {
       w2[l] = mc(vs[l], Bps[l] / 2.0);
     }
     for (int it = 0; it < cfg.iters; ++it) {
-      auto y2 = mulx_n(y, y);
-      auto p1 = mulx_n(w2, y);
+      // y^2 and w2 y side by side, then their product
+      std::vector<CtPtr> A(y), B(y);
+      A.insert(A.end(), w2.begin(), w2.end());
+      B.insert(B.end(), y.begin(), y.end());
+      auto r = mulx_n(A, B);
+      std::vector<CtPtr> y2(r.begin(), r.begin() + nl), p1(r.begin() + nl, r.end());
       auto p2 = mulx_n(p1, y2);
       for (size_t l = 0; l < nl; ++l) y[l] = subx(lin1(y[l], 1.5, p2[l]->level), p2[l]);
     }
