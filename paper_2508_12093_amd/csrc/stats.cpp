@@ -157,14 +157,15 @@ struct Circ {
     return mul_int(cx, *mulx(yw.second, yw.first), 2);
   }
 
+  // u = x^2, w = u^2; terms 35/16 x, (-35/16 x) u, (21/16 x) w,
+  // ((-5/16 x) u) w; the products of one level run as one batch
   CtPtr g3(const CtPtr& x) {
     auto u = sq(x);
-    auto w = sq(u);
     auto a1 = mc(x, 35.0 / 16.0);
-    auto a3 = mulx(mc(x, -35.0 / 16.0), u);
-    auto a5 = mulx(mc(x, 21.0 / 16.0), w);
-    auto a7 = mulx(mulx(mc(x, -5.0 / 16.0), u), w);
-    return sum({a1, a3, a5, a7});
+    auto m3 = mc(x, -35.0 / 16.0), m5 = mc(x, 21.0 / 16.0), m7 = mc(x, -5.0 / 16.0);
+    auto r = mulx_n({u, m3, m7}, {u, u, u});          // w, a3, (-5/16 x) u
+    auto q = mulx_n({m5, r[2]}, {r[0], r[0]});        // a5, a7
+    return sum({a1, r[1], q[0], q[1]});
   }
 
   // ---- the same sequences over several independent operands ("lanes"):
@@ -351,9 +352,9 @@ std::vector<CtPtr> stat_zscore(Context& cx, const EvalKeys& evk, const std::vect
   auto mv = c.moments(X, n, B, B);
   auto mu = c.mc(mv.first, B);
   auto b = c.inv_sqrt(mv.second, B * B, cfg).first;
-  std::vector<CtPtr> out;
-  for (auto& x : X) out.push_back(c.mulx(c.subx(x, mu), b));
-  return out;
+  std::vector<CtPtr> dx;
+  for (auto& x : X) dx.push_back(c.subx(x, mu));
+  return c.mulx_n(dx, std::vector<CtPtr>(dx.size(), b));
 }
 
 CtPtr stat_kurtosis(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& X, size_t n,
@@ -365,13 +366,10 @@ CtPtr stat_kurtosis(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& 
   auto mv = c.moments(X, n, B, B);
   auto var = mv.second;
   auto mu = c.mc(mv.first, B);
-  std::vector<CtPtr> x4;
-  for (auto& x : X) {
-    auto x1 = c.subx(x, mu);
-    auto x2 = c.sq(x1);
-    x4.push_back(c.sq(x2));
-  }
-  auto num = c.mask_mean(x4, n);
+  std::vector<CtPtr> x1;
+  for (auto& x : X) x1.push_back(c.subx(x, mu));
+  auto x2 = c.mulx_n(x1, x1);
+  auto num = c.mask_mean(c.mulx_n(x2, x2), n);
   auto i = c.inv_sqrt(var, B * B, cfg).first;
   auto i2 = c.sq(i);
   // (num i^2) i^2 keeps every partial product near the result's size
@@ -388,13 +386,10 @@ CtPtr stat_skewness(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& 
   auto mv = c.moments(X, n, B, B);
   auto var = mv.second;
   auto mu = c.mc(mv.first, B);
-  std::vector<CtPtr> x3;
-  for (auto& x : X) {
-    auto x1 = c.subx(x, mu);
-    auto x2 = c.sq(x1);
-    x3.push_back(c.mulx(x2, x1));
-  }
-  auto num = c.mask_mean(x3, n);
+  std::vector<CtPtr> x1;
+  for (auto& x : X) x1.push_back(c.subx(x, mu));
+  auto x2 = c.mulx_n(x1, x1);
+  auto num = c.mask_mean(c.mulx_n(x2, x1), n);
   auto i = c.inv_sqrt(var, B * B, cfg).first;
   auto i2 = c.sq(i);
   return c.mulx(c.mulx(num, i), i2);
