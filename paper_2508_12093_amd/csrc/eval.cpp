@@ -55,9 +55,11 @@ void* Pool::alloc_retry(size_t bytes) {
   if (p) return p;
   if (capturing_)   // no synchronisation is possible while a recording is open
     PPST_THROW(ST_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
-  if (std::getenv("PPST_POOL_LOG"))
+  if (std::getenv("PPST_POOL_LOG")) {
+    std::lock_guard<std::mutex> g(mu_);
     std::fprintf(stderr, "[ppstat] allocation of %zu bytes failed; freeing %zu cached bytes\n",
                  bytes, cached_);
+  }
   trim();
   p = raw_alloc(bytes);
   if (!p && registry_) {
