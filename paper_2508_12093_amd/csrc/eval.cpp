@@ -1220,7 +1220,7 @@ std::vector<CtPtr> rotsum_step(Context& cx, const EvalKeys& evk,
   std::vector<CtPtr> outs(n);
   const int chunk = (int)std::min<size_t>(n, kPtrBatch);
   Buf ext = dev_buf(cx.pool, sext * chunk);
-  Buf x = dev_buf(cx.pool, per);
+  Buf x = dev_buf(cx.pool, per * chunk);
   Buf u = dev_buf(cx.pool, su * chunk);
   for (size_t b0 = 0; b0 < n; b0 += chunk) {
     const int nb = (int)std::min<size_t>(chunk, n - b0);
@@ -1228,20 +1228,36 @@ std::vector<CtPtr> rotsum_step(Context& cx, const EvalKeys& evk,
     std::vector<u64*> po(nb);
     for (int i = 0; i < nb; ++i) {
       const Ciphertext& c = *cts[b0 + i];
-      NttLaunch L{};
-      L.src = c.poly(1);
-      L.dst = x.p;
-      L.nlimbs = nl;
-      L.nq = nl;
-      L.pofs = P.L + 1;
-      ntt(sh, L, true, cx.stream);
-      k_modup(sh, x.p, ext.p + sext * i, level, 1, per, sext, cx.stream);
       d[i] = c.poly(1);
       add[i] = c.poly(0);
       acc[i] = c.buf.p;
       outs[b0 + i] = new_ct(cx, level, c.scale);
       po[i] = outs[b0 + i]->buf.p;
     }
+    // the c1 polynomials side by side (one copy each unless there is one),
+    // then one inverse NTT and one ModUp launch over the group
+    if (nb == 1) {
+      NttLaunch L{};
+      L.src = d[0];
+      L.dst = x.p;
+      L.nlimbs = nl;
+      L.nq = nl;
+      L.pofs = P.L + 1;
+      ntt(sh, L, true, cx.stream);
+    } else {
+      for (int i = 0; i < nb; ++i)
+        HIP_CHECK(hipMemcpyAsync(x.p + per * i, d[i], per * 8, hipMemcpyDeviceToDevice, cx.stream));
+      NttLaunch L{};
+      L.src = x.p;
+      L.dst = x.p;
+      L.nlimbs = nl;
+      L.nbatch = nb;
+      L.batch_stride = per;
+      L.nq = nl;
+      L.pofs = P.L + 1;
+      ntt(sh, L, true, cx.stream);
+    }
+    k_modup(sh, x.p, ext.p, level, nb, per, sext, cx.stream);
     ntt_ext_digits(cx, ext.p, level, nb);   // the digits' own limbs are skipped
     // c0's permutations enter u0 as P sum_r c0(X^g_r) (exact through ModDown);
     // the ModDown's last pass adds the input itself
