@@ -13,7 +13,7 @@ every operation is exact integer arithmetic on the same inputs and the sequence
 * FP64 constants are formed exactly as written (e.g. ``1.0 / (B * n)``).
 
 Circuits (paper references):
-  mean_B      Mean(x, B) = sum x_i / (B n)                           Sec. 5.1
+  mean_B      Mean(x, B) = sum x_i / (B n) (ciphertexts added, then scaled) Sec. 5.1
   variance_B  Variance(x, B) = sum (x_i / (B sqrt n))^2 - Mean(x,B)^2  Sec. 5.1, Eq. 2
   inv_sqrt    Chebyshev initial value (Alg. 3, Eq. 3) + Newton (Alg. 2, n = 2)
   invsqrt     CryptoInvSqrt of x / B slot by slot (Sec. 6.2, Exp. 1)
@@ -196,24 +196,28 @@ class Circuits:
         return acc
 
     def mask_mean(self, zs, n):
-        """RotSum(sum_c Z_c * mask_c) with mask_c = 1/n on rows < n, else 0."""
+        """RotSum(sum_c Z_c * mask_c) with mask_c = 1/n on rows < n, else 0:
+        the full ciphertexts are added first and scaled by 1/n once; a ragged
+        last one is multiplied by its 1/n row mask."""
         S = self.ev.slots
-        terms = []
+        full, terms = [], []
         for c, z in enumerate(zs):
             rows = min(S, n - c * S)
             if rows == S:
-                terms.append(self.ev.mul_const(z, 1.0 / float(n)))
+                full.append(z)
             else:
                 vec = np.zeros(S)
                 vec[:rows] = 1.0 / float(n)
                 terms.append(self.ev.mul_vec(z, vec))
+        if full:
+            terms.insert(0, self.ev.mul_const(self.sumx(full), 1.0 / float(n)))
         return self.ev.rotsum(self.sumx(terms))
 
     # Sec. 5.1 -------------------------------------------------------------
     def mean_B(self, X, n, B):
         """Mean(x, B) = sum_i x_i / (B n)."""
         c = 1.0 / (B * float(n))
-        return self.ev.rotsum(self.sumx([self.ev.mul_const(x, c) for x in X]))
+        return self.ev.rotsum(self.ev.mul_const(self.sumx(X), c))
 
     def variance_B(self, X, n, B, mean_term):
         """Variance(x, B) = sum (x_i / (B sqrt n))^2 - mean_term^2  (Eq. 2)."""
@@ -285,7 +289,7 @@ class Circuits:
         need the mean, so the mean's sum is brought to its level and the two
         are summed together; Var = E2 - m^2 with m = Mean(x, B_var)."""
         ev = self.ev
-        s1 = self.sumx([ev.mul_const(x, 1.0 / (B_mean * float(n))) for x in X])
+        s1 = ev.mul_const(self.sumx(X), 1.0 / (B_mean * float(n)))
         c = 1.0 / (B_var * math.sqrt(float(n)))
         xs = [ev.mul_const(x, c) for x in X]
         s2 = self.sumx([ev.mul(x, x) for x in xs])
@@ -352,8 +356,8 @@ class Circuits:
         five slot sums depends on another, so they are formed first, brought
         to one level and summed together."""
         ev = self.ev
-        sx = self.sumx([ev.mul_const(x, 1.0 / (Bx * float(n))) for x in X])
-        sy = self.sumx([ev.mul_const(y, 1.0 / (By * float(n))) for y in Y])
+        sx = ev.mul_const(self.sumx(X), 1.0 / (Bx * float(n)))
+        sy = ev.mul_const(self.sumx(Y), 1.0 / (By * float(n)))
         xs = [ev.mul_const(x, 1.0 / (Bx * math.sqrt(float(n)))) for x in X]
         ys = [ev.mul_const(y, 1.0 / (By * math.sqrt(float(n)))) for y in Y]
         sxx = self.sumx([ev.mul(a, a) for a in xs])

@@ -83,13 +83,15 @@ struct Circ {
   }
   CtPtr rs(const CtPtr& a) { return rotsum(cx, evk, *a); }
 
+  // RotSum(sum_c Z_c mask_c), mask 1/n on rows < n: the full ciphertexts are
+  // added first and scaled by 1/n once; a ragged last one takes its row mask
   CtPtr mask_mean(const std::vector<CtPtr>& zs, size_t n) {
     const size_t S = (size_t)cx.P().slots();
-    std::vector<CtPtr> terms;
+    std::vector<CtPtr> full, terms;
     for (size_t c = 0; c < zs.size(); ++c) {
       size_t rows = std::min(S, n - c * S);
       if (rows == S) {
-        terms.push_back(mc(zs[c], 1.0 / (double)n));
+        full.push_back(zs[c]);
       } else {
         std::vector<double> v(S, 0.0);
         for (size_t j = 0; j < rows; ++j) v[j] = 1.0 / (double)n;
@@ -97,14 +99,13 @@ struct Circ {
         terms.push_back(mul_plain(cx, *zs[c], *pt));
       }
     }
+    if (!full.empty()) terms.insert(terms.begin(), mc(sum(full), 1.0 / (double)n));
     return rs(sum(terms));
   }
 
+  // Mean(x, B): the column's ciphertexts added, scaled by 1/(B n) once, summed
   CtPtr mean_B(const std::vector<CtPtr>& X, size_t n, double B) {
-    const double c = 1.0 / (B * (double)n);
-    std::vector<CtPtr> t;
-    for (auto& x : X) t.push_back(mc(x, c));
-    return rs(sum(t));
+    return rs(mc(sum(X), 1.0 / (B * (double)n)));
   }
 
   CtPtr variance_B(const std::vector<CtPtr>& X, size_t n, double B, const CtPtr& mean_term) {
@@ -125,9 +126,8 @@ struct Circ {
   // m = Mean(x, B_var)
   std::pair<CtPtr, CtPtr> moments(const std::vector<CtPtr>& X, size_t n, double B_mean,
                                   double B_var) {
-    std::vector<CtPtr> t, xs;
-    for (auto& x : X) t.push_back(mc(x, 1.0 / (B_mean * (double)n)));
-    auto s1 = sum(t);
+    std::vector<CtPtr> xs;
+    auto s1 = mc(sum(X), 1.0 / (B_mean * (double)n));
     const double c = 1.0 / (B_var * std::sqrt((double)n));
     for (auto& x : X) xs.push_back(mc(x, c));
     auto s2 = sum(mulx_n(xs, xs));
@@ -426,16 +426,10 @@ CtPtr stat_pearson(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& X
   // five independent slot sums, summed together at one level (one batched
   // RotSum); Var_B = E2 - Mean^2, Cov_B = Exy - Mean(x) Mean(y) = Cov/(Bx By)
   const double nd = (double)n;
-  std::vector<CtPtr> px, py, xs, ys;
-  for (auto& x : X) {
-    px.push_back(c.mc(x, 1.0 / (Bx * nd)));
-    xs.push_back(c.mc(x, 1.0 / (Bx * std::sqrt(nd))));
-  }
-  for (auto& y : Y) {
-    py.push_back(c.mc(y, 1.0 / (By * nd)));
-    ys.push_back(c.mc(y, 1.0 / (By * std::sqrt(nd))));
-  }
-  auto sx = c.sum(px), sy = c.sum(py);
+  std::vector<CtPtr> xs, ys;
+  for (auto& x : X) xs.push_back(c.mc(x, 1.0 / (Bx * std::sqrt(nd))));
+  for (auto& y : Y) ys.push_back(c.mc(y, 1.0 / (By * std::sqrt(nd))));
+  auto sx = c.mc(c.sum(X), 1.0 / (Bx * nd)), sy = c.mc(c.sum(Y), 1.0 / (By * nd));
   const size_t m = X.size();
   std::vector<CtPtr> lhs, rhs;
   for (size_t i = 0; i < m; ++i) { lhs.push_back(xs[i]); rhs.push_back(xs[i]); }
