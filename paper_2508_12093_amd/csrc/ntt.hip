@@ -1013,19 +1013,24 @@ void ntt_autotune(Shared& sh, hipStream_t st, u64* scratch, int max_limbs) {
         const Variant* tab = P.logN == 16 ? (pass == 0 ? kCol16 : kRow16) : kFull12;
         const int nv = P.logN == 16 ? (pass == 0 ? kNCol16 : kNRow16) : kNFull12;
         a.logR = P.logN == 16 ? 8 : 0;
-        float best = 1e30f;
+        // three rounds over all variants, each variant's best round counts:
+        // a transient slowdown during one variant's timing cannot decide
+        std::vector<float> t(nv, 1e30f);
+        for (int v = 0; v < nv; ++v) (inv ? tab[v].inv : tab[v].fwd)(a, nlc, nb, st);   // warm
+        for (int round = 0; round < 3; ++round)
+          for (int v = 0; v < nv; ++v) {
+            PassFn f = inv ? tab[v].inv : tab[v].fwd;
+            HIP_CHECK(hipEventRecord(e0, st));
+            for (int r = 0; r < 5; ++r) f(a, nlc, nb, st);
+            HIP_CHECK(hipEventRecord(e1, st));
+            HIP_CHECK(hipEventSynchronize(e1));
+            float ms = 0;
+            HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+            t[v] = std::min(t[v], ms);
+          }
         int best_i = 0;
-        for (int v = 0; v < nv; ++v) {
-          PassFn f = inv ? tab[v].inv : tab[v].fwd;
-          f(a, nlc, nb, st);   // warm
-          HIP_CHECK(hipEventRecord(e0, st));
-          for (int r = 0; r < 5; ++r) f(a, nlc, nb, st);
-          HIP_CHECK(hipEventRecord(e1, st));
-          HIP_CHECK(hipEventSynchronize(e1));
-          float ms = 0;
-          HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
-          if (ms < best) { best = ms; best_i = v; }
-        }
+        for (int v = 1; v < nv; ++v)
+          if (t[v] < t[best_i]) best_i = v;
         sh.ntt_plan.v[inv][P.logN == 16 ? pass : 1][b] = best_i;
       }
     }
