@@ -379,7 +379,9 @@ typedef struct {
 } ppst_query_stats;
 int ppst_server_create(ppst_context* ctx, const ppst_eval_keys* evk, size_t hbm_budget,
                        int32_t slots, ppst_server** out);
-/* the server keeps its own reference to the ciphertexts (they are copied) */
+/* the server keeps its own copy of the ciphertexts; the call waits until the
+ * device is idle first, so ciphertexts still being produced on any stream
+ * (e.g. an asynchronous encryption) are complete when they are copied */
 int ppst_server_register_column(ppst_server* srv, const ppst_ciphertext* const* cts, size_t nct,
                                 size_t nrows, uint64_t* col_id);
 int ppst_server_submit(ppst_server* srv, const ppst_query* q, uint64_t* ticket);

@@ -39,6 +39,10 @@ u64 Server::register_column(const std::vector<const Ciphertext*>& cts, size_t nr
   if (nrows == 0 || need != cts.size()) PPST_THROW(ST_EINVAL, "row count does not match the column");
   Column col;
   col.nrows = nrows;
+  // the ciphertexts may still be in flight on the stream of whichever context
+  // produced them (an encryption is asynchronous): let every stream drain
+  // before copying, registration is not on the query path
+  HIP_CHECK(hipDeviceSynchronize());
   for (auto* c : cts) col.cts.push_back(copy_ct(*base_, *c));
   HIP_CHECK(hipStreamSynchronize(base_->stream));
   std::lock_guard<std::mutex> g(mu_);

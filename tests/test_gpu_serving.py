@@ -158,3 +158,25 @@ def test_poll_does_not_block(env):
     assert rc == 0
     assert all(ffi.ppst_server_poll(srv, t) for t in ts[:-1])   # served before it, in order
     assert all(ffi.ppst_server_wait(srv, t)[0] == 0 for t in ts[:-1])
+
+
+def test_register_right_after_encryption(env):
+    """Columns registered while their encryptions may still be running on the
+    caller's stream are copied complete: every mean matches FP64."""
+    ctx, sk, evk, cols = env
+    slots = ctx.info.slots
+    pk = ffi.ppst_keygen(ctx, 5)[1]
+    srv = ffi.ppst_server_create(ctx, evk, 8 << 30, 4)
+    cfg = ffi.ppst_invsqrt_cfg_default()
+    fresh = []
+    for seed in range(4):
+        n = 3 * slots - 100
+        y = synth.lognormal_bernoulli_pair(40 + seed, n)[1] / 4.0
+        cy = [ffi.ppst_encrypt(ctx, pk, ffi.ppst_encode(ctx, v, 24), 900 + 10 * seed + i)
+              for i, v in enumerate(synth.split_column(y, slots))]
+        fresh.append((ffi.ppst_server_register_column(srv, cy, n), n, y))   # no sync before
+    ts = [ffi.ppst_server_submit(srv, ffi.Q_MEAN, cid, 0, 1.0, 1.0, cfg) for cid, _, _ in fresh]
+    for t, (cid, n, y) in zip(ts, fresh):
+        rc, ct, st = ffi.ppst_server_wait(srv, t)
+        got = ffi.ppst_decode(ctx, ffi.ppst_decrypt(ctx, sk, ct))[0]
+        assert rc == 0 and abs(got - y.mean()) < 1e-3 * max(1.0, abs(y.mean()))
