@@ -377,6 +377,8 @@ typedef struct {
   double t_submit, t_admit, t_done;   /* seconds, monotonic clock */
   uint64_t bytes_reserved;
 } ppst_query_stats;
+/* waits until the device is idle (the keys may still be in generation on the
+ * caller's stream), then starts `slots` workers with streams of their own */
 int ppst_server_create(ppst_context* ctx, const ppst_eval_keys* evk, size_t hbm_budget,
                        int32_t slots, ppst_server** out);
 /* the server keeps its own copy of the ciphertexts; the call waits until the

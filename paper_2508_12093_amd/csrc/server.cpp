@@ -15,6 +15,9 @@ double now_seconds() {
 Server::Server(Context& base, std::shared_ptr<const EvalKeys> evk, size_t budget, int slots)
     : sh_(base.sh), evk_(std::move(evk)), budget_(budget) {
   if (slots < 1 || slots > 16) PPST_THROW(ST_EINVAL, "server slots must be in 1..16");
+  // the evaluation keys may still be being generated on the caller's stream;
+  // the workers read them from their own streams
+  HIP_CHECK(hipDeviceSynchronize());
   base_ = make_context(sh_, nullptr);
   for (int i = 0; i < slots; ++i) workers_cx_.push_back(make_context(sh_, nullptr));
   for (int i = 0; i < slots; ++i) threads_.emplace_back([this, i] { worker(i); });
