@@ -253,6 +253,15 @@ int ppst_level_align(ppst_context* ctx, const ppst_ciphertext* a, int32_t level,
  * ppst_mul_const.  ELEVEL when a term is not above `level`. */
 int ppst_lincomb(ppst_context* ctx, const ppst_ciphertext* const* cts, const double* cs, size_t n,
                  int32_t level, ppst_ciphertext** out);
+/* ppst_mul_const(cts[i], c) for i < n, all ciphertexts at one level and of
+ * one degree: the rescales of up to 16 ciphertexts run as one launch
+ * sequence (the dropped limbs gathered, one inverse NTT, one conversion, one
+ * forward NTT whose last pass multiplies by c and divides by q_l).  Bit for
+ * bit the same as n calls of ppst_mul_const.  outs: n handles written on
+ * success.  PPST_ESCALE when levels or degrees differ, PPST_ELEVEL at level
+ * 0, PPST_EDOMAIN when c does not fit the scale. */
+int ppst_mul_const_batch(ppst_context* ctx, const ppst_ciphertext* const* cts, size_t n, double c,
+                         ppst_ciphertext** outs);
 /* n independent products a[i] * b[i] (same level): each stage of tensor,
  * relinearisation and rescale runs once per group of 16 products (the key
  * is read once per 8 products inside the inner product) */
@@ -263,7 +272,8 @@ int ppst_mul_batch(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciph
 /* Recording of evaluation work into a HIP graph (stream capture on the
  * context's stream), for callers that replay a fixed sequence many times.
  * Between ppst_graph_begin and ppst_graph_end the evaluation calls (add, sub,
- * add_const, mul_const, mul_int, mul_plain, mul, tensor, relin, rescale,
+ * add_const, mul_const, mul_const_batch, mul_int, mul_plain, mul, tensor,
+ * relin, rescale,
  * rotate, rotate_batch, rotate_hoisted(_batch), rotsum, level_align,
  * mul_batch) are
  * recorded, not run: their output handles are valid at once, and each

@@ -679,6 +679,20 @@ int ppst_rotsum(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciphert
     *out = wrap(rotsum(*ctx->cx, evk->e, *a->c));
   });
 }
+int ppst_mul_const_batch(ppst_context* ctx, const ppst_ciphertext* const* cts, size_t n, double c,
+                         ppst_ciphertext** outs) {
+  return guard([&] {
+    NEED(ctx); NEED(cts); NEED(outs);
+    std::vector<const Ciphertext*> v;
+    for (size_t i = 0; i < n; ++i) {
+      NEED(cts[i]);
+      v.push_back(cts[i]->c.get());
+    }
+    auto r = mul_const_n(*ctx->cx, v, c);
+    for (size_t i = 0; i < n; ++i) outs[i] = wrap(r[i]);
+  });
+}
+
 int ppst_mul_batch(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciphertext* const* a,
                    const ppst_ciphertext* const* b, size_t n, ppst_ciphertext** outs) {
   return guard([&] {

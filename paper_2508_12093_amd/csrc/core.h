@@ -106,6 +106,10 @@ void dg_thresholds(u64 thr[kDgMax]);        // cumulative thresholds, x = 0..18
 // -------------------------------------------------------------------------
 // encoding (host, extended precision)
 // -------------------------------------------------------------------------
+// encode_coeffs = encode_embed (the scale-free values p_k, N of them) then
+// encode_round (coefficient k = round_half_away(scale p_k))
+void encode_embed(const Params& P, const double* m, int n_used, std::vector<long double>& p);
+void encode_round(const std::vector<long double>& p, double scale, int64_t* out);
 void encode_coeffs(const Params& P, const double* m, int n_used, double scale, int64_t* out);
 void decode_coeffs(const Params& P, const long double* coeffs, double scale, double* out, int n);
 

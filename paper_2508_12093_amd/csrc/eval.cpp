@@ -598,13 +598,18 @@ void ks_moddown_rescale(Context& cx, Buf& u, const u64* D, size_t sd, int level,
   ntt_fwd_mdr_final(sh, corr.p, level, nbatch, tail, cx.stream);
 }
 
-// Rescale npoly polynomials at `level` (polynomial c at a + c pstride) into
-// out ([npoly][level][N]).  With k (host arrays of level+1 constant residues
-// and Shoup companions) the input is first multiplied by that constant; the
-// result is bit for bit rescale(k a).  The dropped limb is transformed out of
-// place, so the input is never copied or modified.
-void rescale_raw(Context& cx, const u64* a, size_t pstride, int level, int npoly, u64* out,
-                 const u64* k = nullptr, const u64* kp = nullptr) {
+// ciphertexts per batched launch group
+constexpr size_t kMulChunk = 16;
+
+// Rescale npoly polynomials at `level`: polynomial c at a[c] (limbs 0..level)
+// into out[c] (limbs 0..level-1).  With k (host arrays of level+1 constant
+// residues and Shoup companions) the input is first multiplied by that
+// constant; the result is bit for bit rescale(k a).  The dropped limbs are
+// read strided from a[0] when pstride is nonzero (a[c] = a[0] + c pstride),
+// else gathered; they are transformed out of place, so the input is never
+// modified.
+void rescale_ptrs(Context& cx, const u64* const* a, u64* const* out, int level, int npoly,
+                  size_t pstride, const u64* k, const u64* kp) {
   const Params& P = cx.P();
   const Shared& sh = *cx.sh;
   const int N = P.N;
@@ -612,11 +617,19 @@ void rescale_raw(Context& cx, const u64* a, size_t pstride, int level, int npoly
   Buf tmp = dev_buf(cx.pool, (size_t)npoly * level * N);
   {
     NttLaunch L{};
-    L.src = a + (size_t)level * N;
+    if (pstride) {
+      L.src = a[0] + (size_t)level * N;
+      L.batch_stride = pstride;
+    } else {
+      std::vector<const u64*> rows(npoly);
+      for (int c = 0; c < npoly; ++c) rows[c] = a[c] + (size_t)level * N;
+      k_gather_rows(sh, rows.data(), top.p, npoly, cx.stream);
+      L.src = top.p;
+      L.batch_stride = N;
+    }
     L.dst = top.p;
     L.nlimbs = 1;
     L.nbatch = npoly;
-    L.batch_stride = pstride;
     L.dst_stride = N;
     L.nq = 0;
     L.pofs = level;     // every row is on q_level
@@ -624,8 +637,22 @@ void rescale_raw(Context& cx, const u64* a, size_t pstride, int level, int npoly
   }
   const u64 kl[2] = {k ? k[level] : 0, k ? kp[level] : 0};
   k_rescale_conv(sh, top.p, tmp.p, level, npoly, N, cx.stream, k ? kl : nullptr);
-  RsTail tail{a, pstride, out, (size_t)level * N, rescale_table(sh, level), k, kp};
+  RsTail tail{a, out, rescale_table(sh, level), k, kp};
   ntt_fwd_rescale_final(sh, tmp.p, level, npoly, tail, cx.stream);
+}
+
+// Rescale npoly polynomials at `level` (polynomial c at a + c pstride) into
+// out ([npoly][level][N]); k, kp as for rescale_ptrs.
+void rescale_raw(Context& cx, const u64* a, size_t pstride, int level, int npoly, u64* out,
+                 const u64* k = nullptr, const u64* kp = nullptr) {
+  const size_t N = (size_t)cx.P().N;
+  std::vector<const u64*> ap(npoly);
+  std::vector<u64*> op(npoly);
+  for (int c = 0; c < npoly; ++c) {
+    ap[c] = a + (size_t)c * pstride;
+    op[c] = out + (size_t)c * level * N;
+  }
+  rescale_ptrs(cx, ap.data(), op.data(), level, npoly, pstride, k, kp);
 }
 
 void scalar_residues(const Params& P, int64_t k, int nl, std::vector<u64>& v, std::vector<u64>& vp) {
@@ -759,6 +786,15 @@ PtPtr encode(Context& cx, const double* v, size_t n, int level) {
   if (n > (size_t)P.slots()) PPST_THROW(ST_EINVAL, "more values than slots");
   std::vector<int64_t> c(P.N);
   encode_coeffs(P, v, (int)n, P.scale[level], c.data());
+  return plaintext_from_coeffs(cx, c.data(), level, P.scale[level]);
+}
+
+PtPtr encode_embedded(Context& cx, const std::vector<long double>& p, int level) {
+  const Params& P = cx.P();
+  if (level < 0 || level > P.L) PPST_THROW(ST_ELEVEL, "level out of range");
+  if (p.size() != (size_t)P.N) PPST_THROW(ST_EINVAL, "embedding of the wrong length");
+  std::vector<int64_t> c(P.N);
+  encode_round(p, P.scale[level], c.data());
   return plaintext_from_coeffs(cx, c.data(), level, P.scale[level]);
 }
 
@@ -934,6 +970,74 @@ CtPtr mul_const(Context& cx, const Ciphertext& a, double c) {
   rescale_raw(cx, a.buf.p, (size_t)(a.level + 1) * a.N, a.level, a.npoly, out->buf.p, v.data(),
               vp.data());
   return out;
+}
+
+namespace {
+// Ciphertexts of one level and degree, each multiplied by the constant with
+// residues v, vp and rescaled from rlevel (limbs above rlevel are not read):
+// the group-wise form of rescale_raw
+std::vector<CtPtr> rescale_group(Context& cx, const std::vector<const Ciphertext*>& a, int rlevel,
+                                 const std::vector<u64>& v, const std::vector<u64>& vp) {
+  const Params& P = cx.P();
+  std::vector<CtPtr> outs;
+  const size_t per = (size_t)(a[0]->level + 1) * P.N, per_out = (size_t)rlevel * P.N;
+  for (size_t i0 = 0; i0 < a.size(); i0 += kMulChunk) {
+    const size_t n = std::min(kMulChunk, a.size() - i0);
+    std::vector<const u64*> ap;
+    std::vector<u64*> op;
+    for (size_t i = 0; i < n; ++i) {
+      const Ciphertext& x = *a[i0 + i];
+      auto o = new_ct(cx, rlevel - 1, P.scale[rlevel - 1], x.npoly);
+      for (int p = 0; p < x.npoly; ++p) {
+        ap.push_back(x.buf.p + p * per);
+        op.push_back(o->buf.p + p * per_out);
+      }
+      outs.push_back(o);
+    }
+    rescale_ptrs(cx, ap.data(), op.data(), rlevel, (int)ap.size(), 0, v.data(), vp.data());
+  }
+  return outs;
+}
+
+// Level alignment from `from` to `level` multiplies by
+// K = round(Delta_level q_{level+1} / Delta_from) and rescales by q_{level+1}:
+// K's residues on q_0..q_{level+1}
+void align_residues(const Params& P, int from, int level, std::vector<u64>& v,
+                    std::vector<u64>& vp) {
+  const int64_t K = llround((P.scale[level] * (double)P.q[level + 1]) / P.scale[from]);
+  scalar_residues(P, K, level + 2, v, vp);
+}
+
+void check_group(const std::vector<const Ciphertext*>& a) {
+  for (const Ciphertext* x : a)
+    if (x->level != a[0]->level || x->npoly != a[0]->npoly)
+      PPST_THROW(ST_ESCALE, "ciphertexts of different levels or degrees");
+}
+}  // namespace
+
+std::vector<CtPtr> mul_const_n(Context& cx, const std::vector<const Ciphertext*>& a, double c) {
+  if (a.empty()) return {};
+  check_group(a);
+  const int level = a[0]->level;
+  if (level < 1) PPST_THROW(ST_ELEVEL, "no level left for a constant product");
+  std::vector<u64> v, vp;
+  scalar_residues(cx.P(), const_int(cx.P(), c, level), level + 1, v, vp);
+  return rescale_group(cx, a, level, v, vp);
+}
+
+std::vector<CtPtr> level_align_n(Context& cx, const std::vector<const Ciphertext*>& a, int level) {
+  if (a.empty()) return {};
+  check_group(a);
+  const int from = a[0]->level;
+  std::vector<CtPtr> outs;
+  if (level == from) {
+    for (const Ciphertext* x : a) outs.push_back(copy_ct(cx, *x));
+    return outs;
+  }
+  if (level > from || level < 0) PPST_THROW(ST_ELEVEL, "cannot raise a ciphertext's level");
+  std::vector<u64> v, vp;
+  align_residues(cx.P(), from, level, v, vp);
+  return rescale_group(cx, a, level + 1, v, vp);
 }
 
 CtPtr lincomb(Context& cx, const std::vector<const Ciphertext*>& cts,
@@ -1300,10 +1404,8 @@ CtPtr level_align(Context& cx, const Ciphertext& a, int level) {
   if (level == a.level) return copy_ct(cx, a);
   if (level > a.level || level < 0) PPST_THROW(ST_ELEVEL, "cannot raise a ciphertext's level");
   const Params& P = cx.P();
-  const int nl = level + 2;           // keep q_0 .. q_{level+1}
-  const int64_t K = llround((P.scale[level] * (double)P.q[level + 1]) / P.scale[a.level]);
   std::vector<u64> v, vp;
-  scalar_residues(P, K, nl, v, vp);
+  align_residues(P, a.level, level, v, vp);
   // limbs q_0..q_{level+1} of a, multiplied by K and rescaled by q_{level+1}
   auto out = new_ct(cx, level, P.scale[level], a.npoly);
   rescale_raw(cx, a.buf.p, (size_t)(a.level + 1) * P.N, level + 1, a.npoly, out->buf.p, v.data(),
@@ -1311,7 +1413,6 @@ CtPtr level_align(Context& cx, const Ciphertext& a, int level) {
   return out;
 }
 
-constexpr size_t kMulChunk = 16;
 
 std::vector<CtPtr> mul_batch(Context& cx, const EvalKeys& evk,
                              const std::vector<const Ciphertext*>& a,

@@ -27,6 +27,8 @@ std::shared_ptr<KsKey> keygen_galois(Context& cx, const SecretKey& sk, u64 seed,
 
 // ----------------------------------------------------------- plaintexts
 PtPtr encode(Context& cx, const double* v, size_t n, int level);
+// encode at `level` from encode_embed's values: the same plaintext as encode
+PtPtr encode_embedded(Context& cx, const std::vector<long double>& p, int level);
 PtPtr plaintext_from_coeffs(Context& cx, const int64_t* coeffs, int level, double scale);
 void decode(Context& cx, const Plaintext& pt, double* out, size_t n);
 
@@ -43,6 +45,10 @@ int64_t const_int(const Params& P, double c, int level);
 CtPtr add_const(Context& cx, const Ciphertext& a, double c);
 CtPtr mul_int(Context& cx, const Ciphertext& a, int64_t k);
 CtPtr mul_const(Context& cx, const Ciphertext& a, double c);
+// mul_const of each ciphertext, all at one level and of one degree; the
+// rescales of up to 16 ciphertexts share each launch.  Bit for bit the same
+// as mul_const of each.
+std::vector<CtPtr> mul_const_n(Context& cx, const std::vector<const Ciphertext*>& a, double c);
 CtPtr mul_plain(Context& cx, const Ciphertext& a, const Plaintext& pt);
 CtPtr tensor(Context& cx, const Ciphertext& a, const Ciphertext& b);
 CtPtr relin(Context& cx, const EvalKeys& evk, const Ciphertext& d);
@@ -71,6 +77,10 @@ std::vector<CtPtr> rotsum_batch(Context& cx, const EvalKeys& evk, const std::vec
 // remain, then radix 2; the Galois keys needed are those of k s, 0 < k < radix
 std::vector<std::pair<long, int>> rotsum_plan(const Params& P);
 CtPtr level_align(Context& cx, const Ciphertext& a, int level);
+// level_align of each ciphertext, all at one level and of one degree; the
+// rescales of up to 16 ciphertexts share each launch.  Bit for bit the same
+// as level_align of each.
+std::vector<CtPtr> level_align_n(Context& cx, const std::vector<const Ciphertext*>& a, int level);
 // sum_k cs[k] cts[k] at `level` with one rescale: each term (level > level)
 // cut to q_0..q_{level+1}, multiplied by round(c Delta_{level+1}
 // (Delta_{level+1} / Delta_term)), the products added, then rescaled by

@@ -1,6 +1,9 @@
 // host_math.cpp -- parameter generation, sampling specification and the
 // canonical-embedding encoder of the ppstat library (host side).
+#include <algorithm>
 #include <cmath>
+#include <functional>
+#include <thread>
 
 #include "core.h"
 #include "tables.h"
@@ -177,26 +180,89 @@ namespace {
 typedef long double ld;
 const ld kPi = 3.141592653589793238462643383279502884L;
 
-// in-place decimation-in-frequency FFT of length n (power of two);
-// output X_k = sum_j x_j exp(sign 2 pi i j k / n) lands at position brv(k)
-void dif_fft(std::vector<ld>& re, std::vector<ld>& im, int sign) {
-  const size_t n = re.size();
-  for (size_t len = n; len >= 2; len >>= 1) {
-    const size_t h = len / 2;
-    for (size_t j = 0; j < h; ++j) {
-      ld ang = (ld)sign * 2.0L * kPi * (ld)j / (ld)len;
-      ld c = cosl(ang), s = sinl(ang);
-      for (size_t i = 0; i < n; i += len) {
-        ld ur = re[i + j], ui = im[i + j];
-        ld vr = re[i + j + h], vi = im[i + j + h];
-        re[i + j] = ur + vr;
-        im[i + j] = ui + vi;
-        ld dr = ur - vr, di = ui - vi;
-        re[i + j + h] = dr * c - di * s;
-        im[i + j + h] = dr * s + di * c;
-      }
+// cos and sin of sign 2 pi J / n for J < n/2, computed once per (n, sign)
+// and shared by every later call (threads included).  Stage len of the FFT
+// uses the angle sign 2 pi j / len = sign 2 pi (j n/len) / n: the two
+// expressions scale the same rounded factors by a power of two, so the
+// table entry is bit for bit the value the stage would compute itself.
+struct Twiddles {
+  std::vector<ld> c, s;
+};
+
+const Twiddles& twiddles(size_t n, int sign) {
+  static std::mutex mu;
+  static std::map<std::pair<size_t, int>, std::unique_ptr<Twiddles>> cache;
+  std::lock_guard<std::mutex> g(mu);
+  auto& t = cache[{n, sign}];
+  if (!t) {
+    t.reset(new Twiddles);
+    t->c.resize(n / 2);
+    t->s.resize(n / 2);
+    for (size_t j = 0; j < n / 2; ++j) {
+      ld ang = (ld)sign * 2.0L * kPi * (ld)j / (ld)n;
+      t->c[j] = cosl(ang);
+      t->s[j] = sinl(ang);
     }
   }
+  return *t;
+}
+
+// Butterflies of the stage of block length len over j in [j0, j1) and the
+// blocks starting at i in [i0, i1)
+void dif_stage(ld* re, ld* im, size_t len, size_t step, const Twiddles& tw, size_t j0, size_t j1,
+               size_t i0, size_t i1) {
+  const size_t h = len / 2;
+  for (size_t j = j0; j < j1; ++j) {
+    const ld c = tw.c[j * step], s = tw.s[j * step];
+    for (size_t i = i0; i < i1; i += len) {
+      ld ur = re[i + j], ui = im[i + j];
+      ld vr = re[i + j + h], vi = im[i + j + h];
+      re[i + j] = ur + vr;
+      im[i + j] = ui + vi;
+      ld dr = ur - vr, di = ui - vi;
+      re[i + j + h] = dr * c - di * s;
+      im[i + j + h] = dr * s + di * c;
+    }
+  }
+}
+
+// in-place decimation-in-frequency FFT of length n (power of two);
+// output X_k = sum_j x_j exp(sign 2 pi i j k / n) lands at position brv(k).
+// Long transforms run on T threads: the first log2 T stages split each
+// block's butterflies by j, after which the n/T-point blocks are independent
+// transforms, one per thread.  Every butterfly is computed as in the serial
+// loop, so the result does not depend on T.
+void dif_fft(std::vector<ld>& re, std::vector<ld>& im, int sign) {
+  const size_t n = re.size();
+  const Twiddles& tw = twiddles(n, sign);
+  size_t T = 1;
+  if (n >= ((size_t)1 << 14)) {
+    const size_t hw = std::max<unsigned>(1u, std::thread::hardware_concurrency());
+    while (T * 2 <= std::min<size_t>(hw, 8)) T *= 2;
+  }
+  size_t len = n, step = 1;
+  auto run = [&](const std::function<void(size_t)>& f) {
+    std::vector<std::thread> th;
+    for (size_t t = 1; t < T; ++t) th.emplace_back(f, t);
+    f(0);
+    for (auto& x : th) x.join();
+  };
+  for (; T > 1 && len > n / T; len >>= 1, step <<= 1) {
+    const size_t h = len / 2, l = len, st = step;
+    run([&, h, l, st](size_t t) {
+      dif_stage(re.data(), im.data(), l, st, tw, t * h / T, (t + 1) * h / T, 0, n);
+    });
+  }
+  if (T > 1) {
+    const size_t len0 = len, step0 = step, blk = n / T;
+    run([&, len0, step0, blk](size_t t) {
+      for (size_t l = len0, st = step0; l >= 2; l >>= 1, st <<= 1)
+        dif_stage(re.data(), im.data(), l, st, tw, 0, l / 2, t * blk, (t + 1) * blk);
+    });
+    return;
+  }
+  for (; len >= 2; len >>= 1, step <<= 1)
+    dif_stage(re.data(), im.data(), len, step, tw, 0, len / 2, 0, n);
 }
 
 size_t bitrev(size_t x, int bits) {
@@ -210,7 +276,7 @@ size_t bitrev(size_t x, int bits) {
 // Canonical embedding inverse: slot j is the evaluation at zeta^(5^j),
 // zeta = exp(i pi / N); p_k = (2/N) Re sum_j m_j zeta^(-5^j k);
 // coefficient k = round_half_away(scale * p_k).
-void encode_coeffs(const Params& P, const double* m, int n_used, double scale, int64_t* out) {
+void encode_embed(const Params& P, const double* m, int n_used, std::vector<long double>& p) {
   const int N = P.N, n = N / 2;
   if (n_used < 0 || n_used > n) PPST_THROW(ST_EINVAL, "more values than slots");
   const size_t M2 = 2 * (size_t)N;
@@ -222,10 +288,18 @@ void encode_coeffs(const Params& P, const double* m, int n_used, double scale, i
   }
   dif_fft(re, im, -1);
   const int bits = P.logN + 1;
-  for (int k = 0; k < N; ++k) {
-    ld v = (2.0L / (ld)N) * re[bitrev((size_t)k, bits)];
-    out[k] = llroundl((ld)scale * v);
-  }
+  p.resize(N);
+  for (int k = 0; k < N; ++k) p[k] = (2.0L / (ld)N) * re[bitrev((size_t)k, bits)];
+}
+
+void encode_round(const std::vector<long double>& p, double scale, int64_t* out) {
+  for (size_t k = 0; k < p.size(); ++k) out[k] = llroundl((ld)scale * p[k]);
+}
+
+void encode_coeffs(const Params& P, const double* m, int n_used, double scale, int64_t* out) {
+  std::vector<ld> p;
+  encode_embed(P, m, n_used, p);
+  encode_round(p, scale, out);
 }
 
 // m_j = Re sum_k c_k zeta^(5^j k) / scale

@@ -78,13 +78,12 @@ void ntt_fwd_md_final(const Shared& sh, u64* conv, int level, int nbatch, const 
 // Forward NTT of a rescale's correction corr [npoly][l][N] (coefficient form,
 // primes q_0..q_{l-1}) whose last pass stores, for limb i of polynomial c,
 //   out_c,i = ((k_i a_c,i or a_c,i) - corr_c,i) q_l^-1 mod q_i
-// (a_c at a + c sa, out_c at out + c so; k, kp: host arrays of l constant
-// residues and their Shoup companions, or null; rc: the rescale table of l).
+// (a, out: host arrays of npoly device pointers to limb 0 of each input and
+// output polynomial; k, kp: host arrays of l constant residues and their
+// Shoup companions, or null; rc: the rescale table of l).
 struct RsTail {
-  const u64* a;
-  size_t sa;
-  u64* out;
-  size_t so;
+  const u64* const* a;
+  u64* const* out;
   const u64* rc;
   const u64* k;
   const u64* kp;
@@ -178,6 +177,9 @@ void k_mdr_corr(const Shared& sh, const u64* u, u64* corr, int level, int nbatch
 // companion) is given.
 void k_rescale_conv(const Shared& sh, const u64* top, u64* tmp, int level, int npoly,
                     size_t top_stride, hipStream_t st, const u64* kl = nullptr);
+
+// rows[i] (host array of nrows device pointers, N words each) -> dst + i N
+void k_gather_rows(const Shared& sh, const u64* const* rows, u64* dst, int nrows, hipStream_t st);
 
 // ------------------------------------------------------- sampling etc.
 // signed 64-bit integers -> residues on limbs t of a map

@@ -586,6 +586,13 @@ __global__ void k_fma3_kernel(const u64* x, const u64* y, const u64* z, const u6
   out[r] = v;
 }
 
+__global__ void k_gather_rows_kernel(PtrsIn rows, u64* dst, int logN) {
+  const size_t N = (size_t)1 << logN;
+  const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  dst[(size_t)blockIdx.y * N + k] = rows.p[blockIdx.y][k];
+}
+
 const Mod* M(const Shared& sh) { return (const Mod*)sh.tab.mods.p; }
 
 ScalarArr scalars(const Shared& sh, const u64* k, const u64* kp, int nl) {
@@ -604,6 +611,19 @@ void k_add(const Shared& sh, const u64* a, const u64* b, u64* out, int npoly, in
   hipLaunchKernelGGL(k_add_kernel, grid_for(n), dim3(kBlock), 0, st, a, b, out, M(sh), sh.P.logN,
                      nl, npoly, sa, sb, so, (int)sub);
   LAUNCH_CHECK();
+}
+
+void k_gather_rows(const Shared& sh, const u64* const* rows, u64* dst, int nrows, hipStream_t st) {
+  for (int r0 = 0; r0 < nrows; r0 += kPtrBatch) {
+    const int nr = std::min(kPtrBatch, nrows - r0);
+    PtrsIn p{};
+    for (int i = 0; i < nr; ++i) p.p[i] = rows[r0 + i];
+    dim3 g = grid_for((size_t)sh.P.N);
+    g.y = nr;
+    hipLaunchKernelGGL(k_gather_rows_kernel, g, dim3(kBlock), 0, st, p,
+                       dst + (size_t)r0 * sh.P.N, sh.P.logN);
+    LAUNCH_CHECK();
+  }
 }
 
 void k_lincomb(const Shared& sh, const u64* const* src, const size_t* ps, const u64* k,

@@ -581,10 +581,8 @@ void run_row_md(const NttArgs& base, const MdEpi& e, int nlimbs, int nbatch, hip
 // optional constant multiplier (Mul(P) by a constant, level alignment) —
 // the operations of the separate scalar-product and final kernels.
 struct RsEpi {
-  const u64* a;      // polynomial c at a + c sa (limbs 0..l)
-  size_t sa;
-  u64* out;          // polynomial c at out + c so (limbs 0..l-1)
-  size_t so;
+  PtrsIn a;          // polynomial c of the launch (limbs 0..l)
+  OutPtrs out;       // polynomial c of the launch (limbs 0..l-1)
   const u64* rc;     // rescale table of level l
   int mulk;
   u64 k[kMaxPrimes], kp[kMaxPrimes];
@@ -619,8 +617,8 @@ k_ntt_row_rs(NttArgs a, RsEpi e) {
   const ulonglong2* tw = (const ulonglong2*)(a.tw + (size_t)t * N * 2);
   const u64* ni = a.ninv + 2 * t;
   RsStore<(1 << LOGE)> store;
-  store.a = e.a + (size_t)c * e.sa + (size_t)t * N;
-  store.out = e.out + (size_t)c * e.so + (size_t)t * N;
+  store.a = e.a.p[c] + (size_t)t * N;
+  store.out = e.out.p[c] + (size_t)t * N;
   store.q = q;
   store.qlinv = e.rc[3 * t];
   store.qlinvs = e.rc[3 * t + 1];
@@ -962,17 +960,23 @@ void ntt_fwd_rescale_final(const Shared& sh, u64* corr, int level, int npoly, co
     PPST_THROW(ST_EINVAL, "NTT supports log2 N in {12, 16}");
   }
   RsEpi e{};
-  e.a = tail.a;
-  e.sa = tail.sa;
-  e.out = tail.out;
-  e.so = tail.so;
   e.rc = tail.rc;
   e.mulk = tail.k != nullptr;
   for (int i = 0; i < level && tail.k; ++i) {
     e.k[i] = tail.k[i];
     e.kp[i] = tail.kp[i];
   }
-  rs_variant(P.logN, plan.v[0][1][b])(a, e, level, npoly, st);
+  const RsFn f = rs_variant(P.logN, plan.v[0][1][b]);
+  for (int c0 = 0; c0 < npoly; c0 += kPtrBatch) {
+    const int nc = std::min(kPtrBatch, npoly - c0);
+    for (int i = 0; i < nc; ++i) {
+      if (!tail.a[c0 + i] || !tail.out[c0 + i]) PPST_THROW(ST_EINVAL, "missing rescale operand");
+      e.a.p[i] = tail.a[c0 + i];
+      e.out.p[i] = tail.out[c0 + i];
+    }
+    a.src = a.dst = corr + (size_t)c0 * level * N;
+    f(a, e, level, nc, st);
+  }
   HIP_CHECK(hipGetLastError());
 }
 

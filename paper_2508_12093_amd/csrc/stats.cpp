@@ -19,6 +19,12 @@
 //     a constant when a ciphertext is full and a plaintext vector otherwise.
 #include "stats.h"
 
+#include <future>
+#include <map>
+#include <tuple>
+
+#include <map>
+#include <tuple>
 #include <cmath>
 
 namespace ppst {
@@ -28,8 +34,50 @@ namespace {
 struct Circ {
   Context& cx;
   const EvalKeys& evk;
+  // embedding of a ragged column's row mask, computed on a host thread while
+  // the device runs the circuit up to mask_mean (see prefetch_mask)
+  size_t mask_rows = 0, mask_n = 0;
+  std::shared_future<std::vector<long double>> mask_embed;
 
   CtPtr at(const CtPtr& a, int level) { return a->level == level ? a : level_align(cx, *a, level); }
+  // at(xs[i], to[i]) for every i: alignments that share a source level, a
+  // target level and a degree run as one batch, and a ciphertext listed
+  // twice is aligned once
+  std::vector<CtPtr> at_each(const std::vector<CtPtr>& xs, const std::vector<int>& to) {
+    std::vector<CtPtr> out(xs.size());
+    std::map<std::tuple<int, int, int>, std::vector<size_t>> groups;
+    for (size_t i = 0; i < xs.size(); ++i) {
+      if (xs[i]->level == to[i])
+        out[i] = xs[i];
+      else
+        groups[{xs[i]->level, to[i], xs[i]->npoly}].push_back(i);
+    }
+    for (auto& g : groups) {
+      std::vector<const Ciphertext*> src;
+      std::map<const Ciphertext*, size_t> slot;
+      for (size_t i : g.second)
+        if (slot.emplace(xs[i].get(), src.size()).second) src.push_back(xs[i].get());
+      const int level = std::get<1>(g.first);
+      std::vector<CtPtr> r;
+      if (src.size() == 1)
+        r.push_back(level_align(cx, *src[0], level));
+      else
+        r = level_align_n(cx, src, level);
+      for (size_t i : g.second) out[i] = r[slot[xs[i].get()]];
+    }
+    return out;
+  }
+  // x - mu for every x, at the lowest of their levels
+  std::vector<CtPtr> sub_each(const std::vector<CtPtr>& X, const CtPtr& mu) {
+    std::vector<CtPtr> ops(X);
+    ops.push_back(mu);
+    int m = mu->level;
+    for (auto& x : X) m = std::min(m, x->level);
+    auto al = at_each(ops, std::vector<int>(ops.size(), m));
+    std::vector<CtPtr> out;
+    for (size_t i = 0; i < X.size(); ++i) out.push_back(sub(cx, *al[i], *al.back()));
+    return out;
+  }
   CtPtr addx(const CtPtr& a, const CtPtr& b) {
     int m = std::min(a->level, b->level);
     return add(cx, *at(a, m), *at(b, m));
@@ -76,6 +124,17 @@ struct Circ {
     return lincomb(cx, ts, cs, low - 1);
   }
   CtPtr mc(const CtPtr& a, double c) { return mul_const(cx, *a, c); }
+  // mc(x, c) of every x (one level): the rescales run batched
+  std::vector<CtPtr> mc_n(const std::vector<CtPtr>& xs, double c) {
+    if (xs.size() < 2) {
+      std::vector<CtPtr> out;
+      for (auto& x : xs) out.push_back(mc(x, c));
+      return out;
+    }
+    std::vector<const Ciphertext*> p;
+    for (auto& x : xs) p.push_back(x.get());
+    return mul_const_n(cx, p, c);
+  }
   CtPtr sum(const std::vector<CtPtr>& xs) {
     CtPtr acc = xs[0];
     for (size_t i = 1; i < xs.size(); ++i) acc = addx(acc, xs[i]);
@@ -85,6 +144,23 @@ struct Circ {
 
   // RotSum(sum_c Z_c mask_c), mask 1/n on rows < n: the full ciphertexts are
   // added first and scaled by 1/n once; a ragged last one takes its row mask
+  // Start encoding the row mask of an n-row column on a host thread (the
+  // mask's values do not depend on the level; only the final rounding does)
+  void prefetch_mask(size_t n) {
+    const size_t S = (size_t)cx.P().slots(), rows = n % S;
+    if (rows == 0) return;
+    const Params* P = &cx.P();
+    mask_rows = rows;
+    mask_n = n;
+    mask_embed = std::async(std::launch::async, [P, rows, n, S] {
+                   std::vector<double> v(S, 0.0);
+                   for (size_t j = 0; j < rows; ++j) v[j] = 1.0 / (double)n;
+                   std::vector<long double> p;
+                   encode_embed(*P, v.data(), (int)S, p);
+                   return p;
+                 }).share();
+  }
+
   CtPtr mask_mean(const std::vector<CtPtr>& zs, size_t n) {
     const size_t S = (size_t)cx.P().slots();
     std::vector<CtPtr> full, terms;
@@ -93,9 +169,14 @@ struct Circ {
       if (rows == S) {
         full.push_back(zs[c]);
       } else {
-        std::vector<double> v(S, 0.0);
-        for (size_t j = 0; j < rows; ++j) v[j] = 1.0 / (double)n;
-        auto pt = encode(cx, v.data(), S, zs[c]->level);
+        PtPtr pt;
+        if (mask_embed.valid() && mask_rows == rows && mask_n == n) {
+          pt = encode_embedded(cx, mask_embed.get(), zs[c]->level);
+        } else {
+          std::vector<double> v(S, 0.0);
+          for (size_t j = 0; j < rows; ++j) v[j] = 1.0 / (double)n;
+          pt = encode(cx, v.data(), S, zs[c]->level);
+        }
         terms.push_back(mul_plain(cx, *zs[c], *pt));
       }
     }
@@ -109,13 +190,8 @@ struct Circ {
   }
 
   CtPtr variance_B(const std::vector<CtPtr>& X, size_t n, double B, const CtPtr& mean_term) {
-    const double c = 1.0 / (B * std::sqrt((double)n));
-    std::vector<CtPtr> sqs;
-    for (auto& x : X) {
-      auto xs = mc(x, c);
-      sqs.push_back(sq(xs));
-    }
-    auto e2 = rs(sum(sqs));
+    auto xs = mc_n(X, 1.0 / (B * std::sqrt((double)n)));
+    auto e2 = rs(sum(mulx_n(xs, xs)));
     auto m2 = sq(mean_term);
     return subx(e2, m2);
   }
@@ -126,10 +202,8 @@ struct Circ {
   // m = Mean(x, B_var)
   std::pair<CtPtr, CtPtr> moments(const std::vector<CtPtr>& X, size_t n, double B_mean,
                                   double B_var) {
-    std::vector<CtPtr> xs;
     auto s1 = mc(sum(X), 1.0 / (B_mean * (double)n));
-    const double c = 1.0 / (B_var * std::sqrt((double)n));
-    for (auto& x : X) xs.push_back(mc(x, c));
+    auto xs = mc_n(X, 1.0 / (B_var * std::sqrt((double)n)));
     auto s2 = sum(mulx_n(xs, xs));
     auto r = rs_n({at(s1, s2->level), s2});
     CtPtr m = (B_var == B_mean) ? r[0] : mc(r[0], B_mean / B_var);
@@ -172,14 +246,11 @@ struct Circ {
   // every lane performs exactly the operations of the one-operand helpers
   // above, and the products and RotSums of equal level run as one batch.
   std::vector<CtPtr> mulx_n(const std::vector<CtPtr>& a, const std::vector<CtPtr>& b) {
-    std::vector<CtPtr> A, B;
+    std::vector<int> m(a.size());
+    for (size_t i = 0; i < a.size(); ++i) m[i] = std::min(a[i]->level, b[i]->level);
+    const std::vector<CtPtr> A = at_each(a, m), B = at_each(b, m);
     bool same = true;
-    for (size_t i = 0; i < a.size(); ++i) {
-      int m = std::min(a[i]->level, b[i]->level);
-      A.push_back(at(a[i], m));
-      B.push_back(at(b[i], m));
-      same = same && A[i]->level == A[0]->level;
-    }
+    for (size_t i = 0; i < a.size(); ++i) same = same && A[i]->level == A[0]->level;
     if (!same || A.size() < 2) {
       std::vector<CtPtr> out;
       for (size_t i = 0; i < A.size(); ++i) out.push_back(mul(cx, evk, *A[i], *B[i]));
@@ -335,8 +406,7 @@ std::vector<CtPtr> stat_invsqrt(Context& cx, const EvalKeys& evk, const std::vec
   check_cfg(cfg);
   Circ c{cx, evk};
   c.check_depth(X, 1 + invsqrt_depth(cfg));
-  std::vector<CtPtr> vs;
-  for (auto& x : X) vs.push_back(c.mc(x, 1.0 / B));
+  auto vs = c.mc_n(X, 1.0 / B);
   auto r = c.inv_sqrt_n(vs, std::vector<double>(X.size(), B), cfg);
   std::vector<CtPtr> out;
   for (auto& p : r) out.push_back(p.first);
@@ -352,8 +422,7 @@ std::vector<CtPtr> stat_zscore(Context& cx, const EvalKeys& evk, const std::vect
   auto mv = c.moments(X, n, B, B);
   auto mu = c.mc(mv.first, B);
   auto b = c.inv_sqrt(mv.second, B * B, cfg).first;
-  std::vector<CtPtr> dx;
-  for (auto& x : X) dx.push_back(c.subx(x, mu));
+  auto dx = c.sub_each(X, mu);
   return c.mulx_n(dx, std::vector<CtPtr>(dx.size(), b));
 }
 
@@ -363,11 +432,11 @@ CtPtr stat_kurtosis(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& 
   check_cfg(cfg);
   Circ c{cx, evk};
   c.check_depth(X, 6 + invsqrt_depth(cfg));
+  c.prefetch_mask(n);
   auto mv = c.moments(X, n, B, B);
   auto var = mv.second;
   auto mu = c.mc(mv.first, B);
-  std::vector<CtPtr> x1;
-  for (auto& x : X) x1.push_back(c.subx(x, mu));
+  auto x1 = c.sub_each(X, mu);
   auto x2 = c.mulx_n(x1, x1);
   auto num = c.mask_mean(c.mulx_n(x2, x2), n);
   auto i = c.inv_sqrt(var, B * B, cfg).first;
@@ -383,11 +452,11 @@ CtPtr stat_skewness(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& 
   check_cfg(cfg);
   Circ c{cx, evk};
   c.check_depth(X, 5 + invsqrt_depth(cfg));
+  c.prefetch_mask(n);
   auto mv = c.moments(X, n, B, B);
   auto var = mv.second;
   auto mu = c.mc(mv.first, B);
-  std::vector<CtPtr> x1;
-  for (auto& x : X) x1.push_back(c.subx(x, mu));
+  auto x1 = c.sub_each(X, mu);
   auto x2 = c.mulx_n(x1, x1);
   auto num = c.mask_mean(c.mulx_n(x2, x1), n);
   auto i = c.inv_sqrt(var, B * B, cfg).first;
@@ -426,9 +495,8 @@ CtPtr stat_pearson(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& X
   // five independent slot sums, summed together at one level (one batched
   // RotSum); Var_B = E2 - Mean^2, Cov_B = Exy - Mean(x) Mean(y) = Cov/(Bx By)
   const double nd = (double)n;
-  std::vector<CtPtr> xs, ys;
-  for (auto& x : X) xs.push_back(c.mc(x, 1.0 / (Bx * std::sqrt(nd))));
-  for (auto& y : Y) ys.push_back(c.mc(y, 1.0 / (By * std::sqrt(nd))));
+  auto xs = c.mc_n(X, 1.0 / (Bx * std::sqrt(nd)));
+  auto ys = c.mc_n(Y, 1.0 / (By * std::sqrt(nd)));
   auto sx = c.mc(c.sum(X), 1.0 / (Bx * nd)), sy = c.mc(c.sum(Y), 1.0 / (By * nd));
   const size_t m = X.size();
   std::vector<CtPtr> lhs, rhs;

@@ -127,6 +127,7 @@ _SIGS = {
     "ppst_level_align": (ctypes.c_int, [_vp, _vp, _i32, _pp]),
     "ppst_lincomb": (ctypes.c_int, [_vp, _pp, _vp, _sz, _i32, _pp]),
     "ppst_mul_batch": (ctypes.c_int, [_vp, _vp, _pp, _pp, _sz, _pp]),
+    "ppst_mul_const_batch": (ctypes.c_int, [_vp, _pp, _sz, _dbl, _pp]),
     "ppst_rotate_hoisted_batch": (ctypes.c_int, [_vp, _vp, _pp, _sz, _vp, _sz, _pp]),
     "ppst_rotate_batch": (ctypes.c_int, [_vp, _vp, _pp, _sz, ctypes.c_int32, _pp]),
     "ppst_graph_begin": (ctypes.c_int, [_vp]),
@@ -519,6 +520,12 @@ def ppst_mul_batch(ctx, evk, a, b):
     outs = (ctypes.c_void_p * len(a))()
     _chk(lib().ppst_mul_batch(ctx, evk, _ptrs(a), _ptrs(b), len(a), outs))
     return [Ciphertext(outs[i], ctx) for i in range(len(a))]
+
+
+def ppst_mul_const_batch(ctx, cts, c):
+    outs = (ctypes.c_void_p * max(1, len(cts)))()
+    _chk(lib().ppst_mul_const_batch(ctx, _ptrs(cts), len(cts), c, outs))
+    return [Ciphertext(outs[i], ctx) for i in range(len(cts))]
 
 
 def ppst_rotate_batch(ctx, evk, cts, r):

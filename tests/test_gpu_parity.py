@@ -214,6 +214,30 @@ def test_mul_batch_equals_single(pair):
         assert np.array_equal(ffi.ppst_ct_export(p.ctx, o), ffi.ppst_ct_export(p.ctx, single))
 
 
+def test_mul_const_batch_matches_oracle(pair):
+    """Constant products of 18 ciphertexts (two launch groups, the second
+    ragged) equal the oracle's mul_const bit for bit, at the top level and one
+    below; mixed levels are refused and an empty list gives no outputs."""
+    p = pair
+    cts, octs = [], []
+    for i in range(18):
+        c, o = p.encrypt(synth.uniform_column(120 + i, p.P.slots, -1, 1), 120 + i)
+        cts.append(c)
+        octs.append(o)
+    for k in (0.7071, -3.25):
+        for o, oc in zip(ffi.ppst_mul_const_batch(p.ctx, cts, k), octs):
+            p.same(o, p.O.mul_const(oc, k))
+    if p.P.L >= 2:
+        low = [ffi.ppst_rescale(p.ctx, c) for c in cts[:3]]
+        olow = [p.O.rescale(o) for o in octs[:3]]
+        for o, oc in zip(ffi.ppst_mul_const_batch(p.ctx, low, 0.5), olow):
+            p.same(o, p.O.mul_const(oc, 0.5))
+        with pytest.raises(ffi.PpstError) as e:
+            ffi.ppst_mul_const_batch(p.ctx, [cts[0], low[0]], 0.5)
+        assert e.value.name == "ESCALE"
+    assert ffi.ppst_mul_const_batch(p.ctx, [], 0.5) == []
+
+
 def test_rotate_batch_equals_single(pair):
     """Several ciphertexts rotated by one step in one key switch equal the
     oracle's rotations bit for bit (and the identity step copies)."""
@@ -314,4 +338,8 @@ def test_c2_hmult_and_rotation_bit_exact(c2pair):
         ffi.ppst_ntt_set_plan(p.ctx, col, row)
         p.same(ffi.ppst_mul(p.ctx, p.evk, cx, cy), om)
         p.same(ffi.ppst_rotate(p.ctx, p.evk, cy, 1), orot)
+        if (col, row) == (2, 4):
+            # batched constant products: the rescale's last pass under a fixed plan
+            for o, oc in zip(ffi.ppst_mul_const_batch(p.ctx, [cx, cy], 0.375), [ox, oy]):
+                p.same(o, p.O.mul_const(oc, 0.375))
     ffi.ppst_ntt_autotune(p.ctx)

@@ -94,6 +94,20 @@ def test_t2_multi_ciphertext_column(t2):
     z = ffi.ppst_stat_zscore(p.ctx, p.evk, cys, n, 20.0, p.cfg)
     zz = np.concatenate([p.decrypt(c) for c in z])[:n]
     assert S.mre(zz, S.zscore(y)) < TOL
+    # the per-ciphertext constant products and level alignments run batched
+    # on the device; every output equals the oracle's one-by-one sequence
+    for a, b in zip(z, p.cc.zscore(oys, n, 20.0, p.ocfg)):
+        p.same(a, b)
+    mu = p.cc.mean_B(oys, n, 20.0)
+    p.same(ffi.ppst_stat_variance(p.ctx, p.evk, cys, n, 20.0),
+           p.cc.variance_B(oys, n, 20.0, mu))
+    p.same(ffi.ppst_stat_skewness(p.ctx, p.evk, cys, n, 20.0, p.cfg),
+           p.cc.skewness(oys, n, 20.0, p.ocfg))
+    p.same(ffi.ppst_stat_kurtosis(p.ctx, p.evk, cys, n, 20.0, p.cfg, excess=True),
+           p.cc.kurtosis(oys, n, 20.0, p.ocfg, excess=True))
+    for a, b in zip(ffi.ppst_stat_invsqrt(p.ctx, p.evk, cys, 20.0, p.cfg),
+                    p.cc.invsqrt(oys, 20.0, p.ocfg)):
+        p.same(a, b)
 
 
 def test_t2_closed_forms(t2):
