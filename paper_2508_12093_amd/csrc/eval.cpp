@@ -915,6 +915,18 @@ CtPtr add(Context& cx, const Ciphertext& a, const Ciphertext& b) {
   return out;
 }
 
+CtPtr add_n(Context& cx, const std::vector<const Ciphertext*>& a) {
+  if (a.empty()) PPST_THROW(ST_EINVAL, "empty sum");
+  std::vector<const u64*> src;
+  for (const Ciphertext* x : a) {
+    require_same(*a[0], *x);
+    src.push_back(x->buf.p);
+  }
+  auto out = new_ct(cx, a[0]->level, a[0]->scale);
+  k_sum(*cx.sh, src.data(), (int)src.size(), out->buf.p, 2, a[0]->level + 1, cx.stream);
+  return out;
+}
+
 CtPtr sub(Context& cx, const Ciphertext& a, const Ciphertext& b) {
   require_same(a, b);
   auto out = new_ct(cx, a.level, a.scale);

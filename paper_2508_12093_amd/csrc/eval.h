@@ -40,6 +40,8 @@ PtPtr decrypt(Context& cx, const SecretKey& sk, const Ciphertext& ct);
 
 // ------------------------------------------------------------ operations
 CtPtr add(Context& cx, const Ciphertext& a, const Ciphertext& b);
+// the sum of ciphertexts of one level and scale in one launch per 64 terms
+CtPtr add_n(Context& cx, const std::vector<const Ciphertext*>& a);
 CtPtr sub(Context& cx, const Ciphertext& a, const Ciphertext& b);
 int64_t const_int(const Params& P, double c, int level);
 CtPtr add_const(Context& cx, const Ciphertext& a, double c);

@@ -178,6 +178,10 @@ void k_mdr_corr(const Shared& sh, const u64* u, u64* corr, int level, int nbatch
 void k_rescale_conv(const Shared& sh, const u64* top, u64* tmp, int level, int npoly,
                     size_t top_stride, hipStream_t st, const u64* kl = nullptr);
 
+// out = sum of nterm arrays [npoly][nl][N] (src: host array of device
+// pointers), limb t reduced mod q_t
+void k_sum(const Shared& sh, const u64* const* src, int nterm, u64* out, int npoly, int nl,
+           hipStream_t st);
 // rows[i] (host array of nrows device pointers, N words each) -> dst + i N
 void k_gather_rows(const Shared& sh, const u64* const* rows, u64* dst, int nrows, hipStream_t st);
 

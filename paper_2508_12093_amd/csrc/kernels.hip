@@ -586,6 +586,16 @@ __global__ void k_fma3_kernel(const u64* x, const u64* y, const u64* z, const u6
   out[r] = v;
 }
 
+__global__ void k_sum_kernel(PtrsIn src, int nterm, u64* out, int acc, const Mod* mods, int logN,
+                             int nl, size_t W) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= W) return;
+  const u64 q = mods[(i >> logN) % nl].q;
+  u64 s = acc ? out[i] : 0;
+  for (int k = 0; k < nterm; ++k) s = addm(s, src.p[k][i], q);
+  out[i] = s;
+}
+
 __global__ void k_gather_rows_kernel(PtrsIn rows, u64* dst, int logN) {
   const size_t N = (size_t)1 << logN;
   const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -611,6 +621,20 @@ void k_add(const Shared& sh, const u64* a, const u64* b, u64* out, int npoly, in
   hipLaunchKernelGGL(k_add_kernel, grid_for(n), dim3(kBlock), 0, st, a, b, out, M(sh), sh.P.logN,
                      nl, npoly, sa, sb, so, (int)sub);
   LAUNCH_CHECK();
+}
+
+void k_sum(const Shared& sh, const u64* const* src, int nterm, u64* out, int npoly, int nl,
+           hipStream_t st) {
+  if (nterm < 1) PPST_THROW(ST_EINVAL, "empty sum");
+  const size_t W = (size_t)npoly * nl * sh.P.N;
+  for (int k0 = 0; k0 < nterm; k0 += kPtrBatch) {
+    const int nk = std::min(kPtrBatch, nterm - k0);
+    PtrsIn p{};
+    for (int i = 0; i < nk; ++i) p.p[i] = src[k0 + i];
+    hipLaunchKernelGGL(k_sum_kernel, grid_for(W), dim3(kBlock), 0, st, p, nk, out, (int)(k0 > 0),
+                       M(sh), sh.P.logN, nl, W);
+    LAUNCH_CHECK();
+  }
 }
 
 void k_gather_rows(const Shared& sh, const u64* const* rows, u64* dst, int nrows, hipStream_t st) {

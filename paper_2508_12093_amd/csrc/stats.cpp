@@ -136,6 +136,13 @@ struct Circ {
     return mul_const_n(cx, p, c);
   }
   CtPtr sum(const std::vector<CtPtr>& xs) {
+    bool same = xs.size() > 2;
+    for (auto& x : xs) same = same && x->level == xs[0]->level && x->scale == xs[0]->scale;
+    if (same) {
+      std::vector<const Ciphertext*> p;
+      for (auto& x : xs) p.push_back(x.get());
+      return add_n(cx, p);
+    }
     CtPtr acc = xs[0];
     for (size_t i = 1; i < xs.size(); ++i) acc = addx(acc, xs[i]);
     return acc;
