@@ -241,6 +241,13 @@ int ppst_rotate_hoisted_batch(ppst_context* ctx, const ppst_eval_keys* evk,
  * ModDown of the summed inner products (keys: ppst_evk_add_rotsum). */
 int ppst_rotsum(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciphertext* a,
                 ppst_ciphertext** out);
+/* ppst_rotsum of n ciphertexts of one level: each step's ModUp, inner
+ * product (a thread serves up to 5 ciphertexts per key read) and ModDown
+ * run once for the whole group.  Bit for bit the same as n calls of
+ * ppst_rotsum.  outs: n handles written on success; PPST_ESCALE for mixed
+ * levels. */
+int ppst_rotsum_batch(ppst_context* ctx, const ppst_eval_keys* evk,
+                      const ppst_ciphertext* const* cts, size_t n, ppst_ciphertext** outs);
 /* bring a ciphertext down to `level`: keep q_0..q_{level+1}, multiply by
  * round(Delta_level q_{level+1} / Delta_l), rescale by q_{level+1} */
 int ppst_level_align(ppst_context* ctx, const ppst_ciphertext* a, int32_t level,
@@ -273,10 +280,8 @@ int ppst_mul_batch(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciph
  * context's stream), for callers that replay a fixed sequence many times.
  * Between ppst_graph_begin and ppst_graph_end the evaluation calls (add, sub,
  * add_const, mul_const, mul_const_batch, mul_int, mul_plain, mul, tensor,
- * relin, rescale,
- * rotate, rotate_batch, rotate_hoisted(_batch), rotsum, level_align,
- * mul_batch) are
- * recorded, not run: their output handles are valid at once, and each
+ * relin, rescale, rotate, rotate_batch, rotate_hoisted(_batch), rotsum,
+ * rotsum_batch, level_align, mul_batch) are recorded, not run: their output handles are valid at once, and each
  * ppst_graph_launch writes them again.  Calls that wait for the device or
  * move data to or from the host (keygen, encode, encrypt, decrypt, exports,
  * imports, statistics, ppst_sync, context create/fork/destroy) fail with

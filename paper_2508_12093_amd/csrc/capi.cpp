@@ -679,6 +679,19 @@ int ppst_rotsum(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciphert
     *out = wrap(rotsum(*ctx->cx, evk->e, *a->c));
   });
 }
+int ppst_rotsum_batch(ppst_context* ctx, const ppst_eval_keys* evk,
+                      const ppst_ciphertext* const* cts, size_t n, ppst_ciphertext** outs) {
+  return guard([&] {
+    NEED(ctx); NEED(evk); NEED(cts); NEED(outs);
+    std::vector<CtPtr> v;
+    for (size_t i = 0; i < n; ++i) {
+      NEED(cts[i]);
+      v.push_back(cts[i]->c);
+    }
+    auto r = rotsum_batch(*ctx->cx, evk->e, v);
+    for (size_t i = 0; i < n; ++i) outs[i] = wrap(r[i]);
+  });
+}
 int ppst_mul_const_batch(ppst_context* ctx, const ppst_ciphertext* const* cts, size_t n, double c,
                          ppst_ciphertext** outs) {
   return guard([&] {

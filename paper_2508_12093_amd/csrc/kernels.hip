@@ -796,7 +796,11 @@ void k_ks_inner_multi(const Shared& sh, const u64* const* d, const u64* ext,
   a.nkeys = nkeys;
   // items per thread: the keys are read once per group of items
   dim3 gr = grid_for((size_t)a.ne * P.N);
-  if (nbatch >= 3) {
+  if (nbatch == 5) {
+    hipLaunchKernelGGL(k_ks_inner_multi_kernel<5>, gr, dim3(kBlock), 0, st, a);
+  } else if (nbatch == 4) {
+    hipLaunchKernelGGL(k_ks_inner_multi_kernel<4>, gr, dim3(kBlock), 0, st, a);
+  } else if (nbatch >= 3) {
     gr.y = (nbatch + 2) / 3;
     hipLaunchKernelGGL(k_ks_inner_multi_kernel<3>, gr, dim3(kBlock), 0, st, a);
   } else if (nbatch == 2) {

@@ -128,6 +128,7 @@ _SIGS = {
     "ppst_lincomb": (ctypes.c_int, [_vp, _pp, _vp, _sz, _i32, _pp]),
     "ppst_mul_batch": (ctypes.c_int, [_vp, _vp, _pp, _pp, _sz, _pp]),
     "ppst_mul_const_batch": (ctypes.c_int, [_vp, _pp, _sz, _dbl, _pp]),
+    "ppst_rotsum_batch": (ctypes.c_int, [_vp, _vp, _pp, _sz, _pp]),
     "ppst_rotate_hoisted_batch": (ctypes.c_int, [_vp, _vp, _pp, _sz, _vp, _sz, _pp]),
     "ppst_rotate_batch": (ctypes.c_int, [_vp, _vp, _pp, _sz, ctypes.c_int32, _pp]),
     "ppst_graph_begin": (ctypes.c_int, [_vp]),
@@ -525,6 +526,12 @@ def ppst_mul_batch(ctx, evk, a, b):
 def ppst_mul_const_batch(ctx, cts, c):
     outs = (ctypes.c_void_p * max(1, len(cts)))()
     _chk(lib().ppst_mul_const_batch(ctx, _ptrs(cts), len(cts), c, outs))
+    return [Ciphertext(outs[i], ctx) for i in range(len(cts))]
+
+
+def ppst_rotsum_batch(ctx, evk, cts):
+    outs = (ctypes.c_void_p * max(1, len(cts)))()
+    _chk(lib().ppst_rotsum_batch(ctx, evk, _ptrs(cts), len(cts), outs))
     return [Ciphertext(outs[i], ctx) for i in range(len(cts))]
 
 

@@ -204,6 +204,24 @@ def test_rotsum(pair):
     assert abs(p.decrypt(s)[0] - m.sum()) < 1e-3
 
 
+def test_rotsum_batch_matches_oracle(pair):
+    """Rotate-and-sum of 1 to 6 ciphertexts at once (every lane count the
+    multi-key inner product groups differently) equals the oracle's RotSum
+    of each, bit for bit."""
+    p = pair
+    p.add_rotsum_keys()
+    cts, octs = [], []
+    for i in range(6):
+        m = synth.uniform_column(140 + i, p.P.slots, 0, 1) / p.P.slots
+        c, o = p.encrypt(m, 140 + i)
+        cts.append(c)
+        octs.append(p.O.rotsum(o, p.ogk))
+    for n in range(1, 7):
+        for o, oc in zip(ffi.ppst_rotsum_batch(p.ctx, p.evk, cts[:n]), octs[:n]):
+            p.same(o, oc)
+    assert ffi.ppst_rotsum_batch(p.ctx, p.evk, []) == []
+
+
 def test_mul_batch_equals_single(pair):
     p = pair
     cts = [p.encrypt(synth.uniform_column(70 + i, p.P.slots, -1, 1), 70 + i)[0] for i in range(5)]
