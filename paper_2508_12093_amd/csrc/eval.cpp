@@ -1274,15 +1274,15 @@ std::vector<CtPtr> rotate_batch(Context& cx, const EvalKeys& evk,
   const KsKey& key = galois_key(evk, g);
   const int N = P.N, nl = level + 1;
   const size_t per = (size_t)nl * N;
-  // the c1 polynomials side by side (one copy each unless there is one),
-  // then one key switch
+  // the c1 polynomials side by side (one gather launch unless there is
+  // one), then one key switch
   Buf d;
   const u64* dp = cts[0]->poly(1);
   if (n > 1) {
     d = dev_buf(cx.pool, per * n);
-    for (size_t i = 0; i < n; ++i)
-      HIP_CHECK(hipMemcpyAsync(d.p + per * i, cts[i]->poly(1), per * 8, hipMemcpyDeviceToDevice,
-                               cx.stream));
+    std::vector<const u64*> c1(n);
+    for (size_t i = 0; i < n; ++i) c1[i] = cts[i]->poly(1);
+    k_gather_rows(*cx.sh, c1.data(), d.p, (int)n, cx.stream, per);
     dp = d.p;
   }
   Buf u = ks_accumulate(cx, key, dp, per, level, (int)n, (uint32_t)g);
@@ -1350,8 +1350,8 @@ std::vector<CtPtr> rotsum_step(Context& cx, const EvalKeys& evk,
       outs[b0 + i] = new_ct(cx, level, c.scale);
       po[i] = outs[b0 + i]->buf.p;
     }
-    // the c1 polynomials side by side (one copy each unless there is one),
-    // then one inverse NTT and one ModUp launch over the group
+    // the c1 polynomials side by side (one gather launch unless there is
+    // one), then one inverse NTT and one ModUp launch over the group
     if (nb == 1) {
       NttLaunch L{};
       L.src = d[0];
@@ -1361,8 +1361,7 @@ std::vector<CtPtr> rotsum_step(Context& cx, const EvalKeys& evk,
       L.pofs = P.L + 1;
       ntt(sh, L, true, cx.stream);
     } else {
-      for (int i = 0; i < nb; ++i)
-        HIP_CHECK(hipMemcpyAsync(x.p + per * i, d[i], per * 8, hipMemcpyDeviceToDevice, cx.stream));
+      k_gather_rows(sh, d.data(), x.p, nb, cx.stream, per);
       NttLaunch L{};
       L.src = x.p;
       L.dst = x.p;

@@ -596,11 +596,10 @@ __global__ void k_sum_kernel(PtrsIn src, int nterm, u64* out, int acc, const Mod
   out[i] = s;
 }
 
-__global__ void k_gather_rows_kernel(PtrsIn rows, u64* dst, int logN) {
-  const size_t N = (size_t)1 << logN;
+__global__ void k_gather_rows_kernel(PtrsIn rows, u64* dst, size_t W) {
   const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= N) return;
-  dst[(size_t)blockIdx.y * N + k] = rows.p[blockIdx.y][k];
+  if (k >= W) return;
+  dst[(size_t)blockIdx.y * W + k] = rows.p[blockIdx.y][k];
 }
 
 const Mod* M(const Shared& sh) { return (const Mod*)sh.tab.mods.p; }
@@ -637,15 +636,19 @@ void k_sum(const Shared& sh, const u64* const* src, int nterm, u64* out, int npo
   }
 }
 
-void k_gather_rows(const Shared& sh, const u64* const* rows, u64* dst, int nrows, hipStream_t st) {
+void k_gather_rows(const Shared& sh, const u64* const* rows, u64* dst, int nrows, hipStream_t st,
+                   size_t row_words) {
+  const size_t W = row_words ? row_words : (size_t)sh.P.N;
   for (int r0 = 0; r0 < nrows; r0 += kPtrBatch) {
     const int nr = std::min(kPtrBatch, nrows - r0);
     PtrsIn p{};
-    for (int i = 0; i < nr; ++i) p.p[i] = rows[r0 + i];
-    dim3 g = grid_for((size_t)sh.P.N);
+    for (int i = 0; i < nr; ++i) {
+      if (!rows[r0 + i]) PPST_THROW(ST_EINVAL, "missing row");
+      p.p[i] = rows[r0 + i];
+    }
+    dim3 g = grid_for(W);
     g.y = nr;
-    hipLaunchKernelGGL(k_gather_rows_kernel, g, dim3(kBlock), 0, st, p,
-                       dst + (size_t)r0 * sh.P.N, sh.P.logN);
+    hipLaunchKernelGGL(k_gather_rows_kernel, g, dim3(kBlock), 0, st, p, dst + (size_t)r0 * W, W);
     LAUNCH_CHECK();
   }
 }
