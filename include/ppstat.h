@@ -410,6 +410,15 @@ int ppst_server_poll(ppst_server* srv, uint64_t ticket, int32_t* done);
  * (ZNorm: the first output ciphertext).  Returns the query's own status. */
 int ppst_server_wait(ppst_server* srv, uint64_t ticket, ppst_ciphertext** out,
                      ppst_query_stats* stats);
+/* number of result ciphertexts of a submitted query: for ZNorm the column's
+ * ciphertext count (one z-score ciphertext per input ciphertext), else 1.
+ * EINVAL for an unknown or collected ticket. */
+int ppst_server_output_count(ppst_server* srv, uint64_t ticket, size_t* n);
+/* like ppst_server_wait, but every result ciphertext: outs (cap entries)
+ * receives *n_out handles on success.  EINVAL, without collecting the query,
+ * when cap is below ppst_server_output_count. */
+int ppst_server_wait_all(ppst_server* srv, uint64_t ticket, ppst_ciphertext** outs, size_t cap,
+                         size_t* n_out, ppst_query_stats* stats);
 int ppst_server_destroy(ppst_server* srv);
 
 #ifdef __cplusplus

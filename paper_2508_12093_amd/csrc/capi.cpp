@@ -919,22 +919,56 @@ int ppst_server_poll(ppst_server* srv, uint64_t ticket, int32_t* done) {
     *done = srv->s->poll(ticket) ? 1 : 0;
   });
 }
+namespace {
+void copy_stats(const QueryState& st, ppst_query_stats* stats) {
+  if (!stats) return;
+  stats->t_submit = st.t_submit;
+  stats->t_admit = st.t_admit;
+  stats->t_done = st.t_done;
+  stats->bytes_reserved = st.bytes;
+}
+}  // namespace
+
 int ppst_server_wait(ppst_server* srv, uint64_t ticket, ppst_ciphertext** out,
                      ppst_query_stats* stats) {
   int status = PPST_OK;
   int rc = guard([&] {
     NEED(srv);
-    CtPtr res;
+    std::vector<CtPtr> res;
     QueryState st;
     status = srv->s->wait(ticket, &res, &st);
-    if (stats) {
-      stats->t_submit = st.t_submit;
-      stats->t_admit = st.t_admit;
-      stats->t_done = st.t_done;
-      stats->bytes_reserved = st.bytes;
-    }
+    copy_stats(st, stats);
     if (status != ST_OK) g_err = st.error;
-    if (out) *out = (status == ST_OK && res) ? wrap(res) : nullptr;
+    if (out) *out = (status == ST_OK && !res.empty()) ? wrap(res[0]) : nullptr;
+  });
+  return rc != PPST_OK ? rc : status;
+}
+int ppst_server_output_count(ppst_server* srv, uint64_t ticket, size_t* n) {
+  return guard([&] {
+    NEED(srv); NEED(n);
+    *n = srv->s->output_count(ticket);
+  });
+}
+int ppst_server_wait_all(ppst_server* srv, uint64_t ticket, ppst_ciphertext** outs, size_t cap,
+                         size_t* n_out, ppst_query_stats* stats) {
+  int status = PPST_OK;
+  int rc = guard([&] {
+    NEED(srv); NEED(outs); NEED(n_out);
+    const size_t need = srv->s->output_count(ticket);
+    if (cap < need)
+      PPST_THROW(ST_EINVAL, "output array holds " + std::to_string(cap) + " handles, the query has " +
+                              std::to_string(need));
+    std::vector<CtPtr> res;
+    QueryState st;
+    status = srv->s->wait(ticket, &res, &st);
+    copy_stats(st, stats);
+    *n_out = 0;
+    if (status != ST_OK) {
+      g_err = st.error;
+      return;
+    }
+    for (size_t i = 0; i < res.size(); ++i) outs[i] = wrap(res[i]);
+    *n_out = res.size();
   });
   return rc != PPST_OK ? rc : status;
 }

@@ -90,21 +90,21 @@ u64 Server::submit(const Query& q) {
   return st->ticket;
 }
 
-CtPtr Server::run(Context& cx, const QueryState& st) {
+std::vector<CtPtr> Server::run(Context& cx, const QueryState& st) {
   const Query& q = st.q;
   const Column& X = st.X;
   switch (q.kind) {
-    case 0: return stat_mean(cx, *evk_, X.cts, X.nrows, q.B);
-    case 1: return stat_variance(cx, *evk_, X.cts, X.nrows, q.B);
-    case 2: return stat_zscore(cx, *evk_, X.cts, X.nrows, q.B, q.cfg)[0];
-    case 3: return stat_cv(cx, *evk_, X.cts, X.nrows, q.B, q.B2, q.cfg, q.sign_k);
+    case 0: return {stat_mean(cx, *evk_, X.cts, X.nrows, q.B)};
+    case 1: return {stat_variance(cx, *evk_, X.cts, X.nrows, q.B)};
+    case 2: return stat_zscore(cx, *evk_, X.cts, X.nrows, q.B, q.cfg);
+    case 3: return {stat_cv(cx, *evk_, X.cts, X.nrows, q.B, q.B2, q.cfg, q.sign_k)};
     case 4: {
       const Column& Y = st.Y;
       if (Y.nrows != X.nrows) PPST_THROW(ST_EINVAL, "columns differ in row count");
-      return stat_pearson(cx, *evk_, X.cts, Y.cts, X.nrows, q.B, q.B2, q.cfg);
+      return {stat_pearson(cx, *evk_, X.cts, Y.cts, X.nrows, q.B, q.B2, q.cfg)};
     }
-    case 5: return stat_skewness(cx, *evk_, X.cts, X.nrows, q.B, q.cfg);
-    case 6: return stat_kurtosis(cx, *evk_, X.cts, X.nrows, q.B, q.cfg, false);
+    case 5: return {stat_skewness(cx, *evk_, X.cts, X.nrows, q.B, q.cfg)};
+    case 6: return {stat_kurtosis(cx, *evk_, X.cts, X.nrows, q.B, q.cfg, false)};
   }
   PPST_THROW(ST_EINVAL, "unknown query kind");
 }
@@ -129,19 +129,19 @@ void Server::worker(int idx) {
       st->t_admit = now_seconds();
     }
     try {
-      st->result = run(cx, *st);
+      st->results = run(cx, *st);
       HIP_CHECK(hipStreamSynchronize(cx.stream));
       st->status = ST_OK;
     } catch (const Error& e) {
       (void)hipStreamSynchronize(cx.stream);
       st->status = e.code;
       st->error = e.what();
-      st->result.reset();
+      st->results.clear();
     } catch (const std::exception& e) {
       (void)hipStreamSynchronize(cx.stream);
       st->status = ST_EINVAL;
       st->error = e.what();
-      st->result.reset();
+      st->results.clear();
     }
     {
       std::lock_guard<std::mutex> g(mu_);
@@ -161,7 +161,17 @@ bool Server::poll(u64 ticket) {
   return it->second->done;
 }
 
-int Server::wait(u64 ticket, CtPtr* out, QueryState* stats) {
+size_t Server::output_count(u64 ticket) {
+  std::lock_guard<std::mutex> g(mu_);
+  auto it = states_.find(ticket);
+  if (it == states_.end()) PPST_THROW(ST_EINVAL, "unknown ticket");
+  const Query& q = it->second->q;
+  if (q.kind != 2) return 1;
+  auto c = columns_.find(q.col_x);
+  return c == columns_.end() ? 1 : c->second.cts.size();
+}
+
+int Server::wait(u64 ticket, std::vector<CtPtr>* out, QueryState* stats) {
   std::unique_lock<std::mutex> g(mu_);
   auto it = states_.find(ticket);
   if (it == states_.end()) PPST_THROW(ST_EINVAL, "unknown ticket");
@@ -176,7 +186,7 @@ int Server::wait(u64 ticket, CtPtr* out, QueryState* stats) {
     stats->status = st->status;
     stats->error = st->error;
   }
-  if (out) *out = st->result;
+  if (out) *out = st->results;
   return st->status;
 }
 

@@ -29,7 +29,7 @@ struct QueryState {
   size_t bytes = 0;
   int status = 0;
   std::string error;
-  CtPtr result;
+  std::vector<CtPtr> results;  // ZNorm: one per column ciphertext; else one
   double t_submit = 0, t_admit = 0, t_done = 0;
   bool done = false;
 };
@@ -40,15 +40,18 @@ class Server {
   ~Server();
   u64 register_column(const std::vector<const Ciphertext*>& cts, size_t nrows);
   u64 submit(const Query& q);
-  // blocks; returns the query's status and moves the result out
-  int wait(u64 ticket, CtPtr* out, QueryState* stats);
+  // blocks; returns the query's status and moves the results out
+  int wait(u64 ticket, std::vector<CtPtr>* out, QueryState* stats);
+  // number of result ciphertexts the query produces (ZNorm: its column's
+  // ciphertext count; otherwise 1)
+  size_t output_count(u64 ticket);
   // whether the query has finished (its result stays until wait() collects it)
   bool poll(u64 ticket);
   size_t estimate_bytes(const Query& q) const;
 
  private:
   void worker(int idx);
-  CtPtr run(Context& cx, const QueryState& st);
+  std::vector<CtPtr> run(Context& cx, const QueryState& st);
 
   std::shared_ptr<Shared> sh_;
   std::unique_ptr<Context> base_;

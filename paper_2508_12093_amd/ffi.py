@@ -154,6 +154,9 @@ _SIGS = {
     "ppst_server_submit": (ctypes.c_int, [_vp, ctypes.POINTER(Query), ctypes.POINTER(_u64)]),
     "ppst_server_wait": (ctypes.c_int, [_vp, _u64, _pp, ctypes.POINTER(QueryStats)]),
     "ppst_server_poll": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32)]),
+    "ppst_server_output_count": (ctypes.c_int, [_vp, _u64, ctypes.POINTER(ctypes.c_size_t)]),
+    "ppst_server_wait_all": (ctypes.c_int, [_vp, _u64, _pp, _sz, ctypes.POINTER(ctypes.c_size_t),
+                                            ctypes.POINTER(QueryStats)]),
     "ppst_server_destroy": (ctypes.c_int, [_vp]),
 }
 
@@ -689,6 +692,23 @@ def ppst_server_poll(srv, ticket) -> bool:
     done = ctypes.c_int32(0)
     _chk(lib().ppst_server_poll(srv, ticket, ctypes.byref(done)))
     return bool(done.value)
+
+
+def ppst_server_output_count(srv: Server, ticket: int) -> int:
+    n = ctypes.c_size_t()
+    _chk(lib().ppst_server_output_count(srv, ticket, ctypes.byref(n)))
+    return n.value
+
+
+def ppst_server_wait_all(srv: Server, ticket: int, cap: int | None = None):
+    """Returns (status, list of ciphertexts, stats); cap defaults to the
+    query's output count."""
+    cap = ppst_server_output_count(srv, ticket) if cap is None else cap
+    outs = (ctypes.c_void_p * max(1, cap))()
+    n = ctypes.c_size_t()
+    st = QueryStats()
+    rc = lib().ppst_server_wait_all(srv, ticket, outs, cap, ctypes.byref(n), ctypes.byref(st))
+    return rc, [Ciphertext(outs[i], srv.owner) for i in range(n.value)], st
 
 
 def ppst_server_wait(srv: Server, ticket: int):

@@ -180,3 +180,29 @@ def test_register_right_after_encryption(env):
         rc, ct, st = ffi.ppst_server_wait(srv, t)
         got = ffi.ppst_decode(ctx, ffi.ppst_decrypt(ctx, sk, ct))[0]
         assert rc == 0 and abs(got - y.mean()) < 1e-3 * max(1.0, abs(y.mean()))
+
+
+def test_zscore_query_returns_every_ciphertext(env):
+    """A served ZNorm over a 3-ciphertext column hands back all three z-score
+    ciphertexts (wait_all), each equal to the direct call's; a too-small
+    output array is refused without collecting the query."""
+    ctx, sk, evk, cols = env
+    cfg = ffi.ppst_invsqrt_cfg_default()
+    n, x, y, cx, cy = cols["c"]
+    srv = ffi.ppst_server_create(ctx, evk, 8 << 30, 2)
+    cid = ffi.ppst_server_register_column(srv, cy, n)
+    t = ffi.ppst_server_submit(srv, ffi.Q_ZSCORE, cid, 0, 2.0, 2.0, cfg)
+    assert ffi.ppst_server_output_count(srv, t) == len(cy) == 3
+    rc, outs, st = ffi.ppst_server_wait_all(srv, t, cap=2)
+    assert rc == -1 and outs == []
+    rc, outs, st = ffi.ppst_server_wait_all(srv, t)
+    assert rc == 0 and len(outs) == 3
+    alone = ffi.ppst_stat_zscore(ctx, evk, cy, n, 2.0, cfg)
+    for a, b in zip(outs, alone):
+        assert np.array_equal(ffi.ppst_ct_export(ctx, a), ffi.ppst_ct_export(ctx, b))
+    z = np.concatenate([ffi.ppst_decode(ctx, ffi.ppst_decrypt(ctx, sk, c)) for c in outs])[:n]
+    assert S.mre(z, S.zscore(y)) < 1e-3
+    t = ffi.ppst_server_submit(srv, ffi.Q_MEAN, cid, 0, 1.0, 1.0, cfg)
+    assert ffi.ppst_server_output_count(srv, t) == 1
+    rc, outs, st = ffi.ppst_server_wait_all(srv, t)
+    assert rc == 0 and len(outs) == 1
