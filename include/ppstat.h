@@ -361,7 +361,8 @@ int ppst_stat_pearson(ppst_context* ctx, const ppst_eval_keys* evk,
 int ppst_ntt_forward(ppst_context* ctx, uint64_t* dev, int32_t nlimbs, int32_t first_prime);
 int ppst_ntt_inverse(ppst_context* ctx, uint64_t* dev, int32_t nlimbs, int32_t first_prime);
 /* Re-run the NTT autotuner (it also runs at context creation unless the
- * environment sets PPST_NTT_AUTOTUNE=0 or forces PPST_NTT_PLAN="col,row"):
+ * environment sets PPST_NTT_AUTOTUNE=0 or forces PPST_NTT_PLAN="col,row" or a
+ * whole plan):
  * every register-radix / workgroup-shape variant of the column and row passes
  * is timed per limb-count bucket and the fastest is kept for this parameter
  * set.  ppst_ntt_plan writes the choice as text. */
@@ -370,6 +371,11 @@ int ppst_ntt_plan(const ppst_context* ctx, char* buf, size_t cap);
 /* force one variant for every bucket and direction (col ignored at N = 2^12);
  * returns PPST_EINVAL for an index outside the variant tables */
 int ppst_ntt_set_plan(ppst_context* ctx, int32_t col, int32_t row);
+/* install a plan in the text form ppst_ntt_plan writes (e.g. one saved from
+ * an earlier autotuning); the environment variable PPST_NTT_PLAN may hold the
+ * same text.  PPST_EINVAL for an unknown variant name or a missing bucket
+ * (the plan is then unchanged). */
+int ppst_ntt_load_plan(ppst_context* ctx, const char* plan);
 /* hipStream_t of the context */
 int ppst_context_stream(const ppst_context* ctx, void** stream);
 

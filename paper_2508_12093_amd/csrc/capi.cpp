@@ -859,6 +859,12 @@ int ppst_ntt_autotune(ppst_context* ctx) {
     autotune_ntt(*ctx->cx->sh);
   });
 }
+int ppst_ntt_load_plan(ppst_context* ctx, const char* plan) {
+  return guard([&] {
+    NEED(ctx); NEED(plan);
+    ntt_load_plan(*ctx->cx->sh, plan);
+  });
+}
 int ppst_ntt_set_plan(ppst_context* ctx, int32_t col, int32_t row) {
   return guard([&] {
     NEED(ctx);

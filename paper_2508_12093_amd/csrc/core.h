@@ -302,5 +302,7 @@ struct Context {
 void ntt_autotune(Shared& sh, hipStream_t st, u64* scratch, int max_limbs);
 std::string ntt_plan_string(const Shared& sh);
 void ntt_set_plan(Shared& sh, int col, int row);
+// the plan ntt_plan_string wrote (EINVAL for unknown names or a missing bucket)
+void ntt_load_plan(Shared& sh, const std::string& text);
 
 }  // namespace ppst

@@ -388,11 +388,15 @@ std::shared_ptr<Shared> make_shared_state(const ParamSpec& spec, const Hooks* ho
   dg_thresholds(sh->dg_thr);
   build_tables(*sh);
   HIP_CHECK(hipDeviceSynchronize());
-  const char* force = std::getenv("PPST_NTT_PLAN");       // "col,row" variant indices
+  // "col,row" variant indices, or a whole plan as ntt_plan_string writes it
+  const char* force = std::getenv("PPST_NTT_PLAN");
   const char* tune = std::getenv("PPST_NTT_AUTOTUNE");
-  if (force) {
+  if (force && std::strchr(force, '[')) {
+    ntt_load_plan(*sh, force);
+  } else if (force) {
     int c = 0, r = 0;
-    if (std::sscanf(force, "%d,%d", &c, &r) != 2) PPST_THROW(ST_EINVAL, "PPST_NTT_PLAN is col,row");
+    if (std::sscanf(force, "%d,%d", &c, &r) != 2)
+      PPST_THROW(ST_EINVAL, "PPST_NTT_PLAN is col,row or a plan as ppst_ntt_plan writes it");
     ntt_set_plan(*sh, c, r);
   } else if (!(tune && tune[0] == '0')) {
     autotune_ntt(*sh);

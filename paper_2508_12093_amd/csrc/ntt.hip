@@ -1063,6 +1063,56 @@ std::string ntt_plan_string(const Shared& sh) {
   return s;
 }
 
+// Inverse of ntt_plan_string: entries "fwd|inv[bK] <col name> <row name>;"
+// (N = 2^12: "<name>" alone); every bucket and direction must appear once.
+void ntt_load_plan(Shared& sh, const std::string& text) {
+  const Params& P = sh.P;
+  NttPlan plan = sh.ntt_plan;
+  bool seen[2][5] = {};
+  auto find = [](const Variant* tab, int n, const std::string& name) {
+    for (int i = 0; i < n; ++i)
+      if (name == tab[i].name) return i;
+    PPST_THROW(ST_EINVAL, "unknown NTT variant '" + name + "'");
+  };
+  size_t pos = 0;
+  while (pos < text.size()) {
+    size_t end = text.find(';', pos);
+    if (end == std::string::npos) end = text.size();
+    std::string item = text.substr(pos, end - pos);
+    pos = end + 1;
+    std::vector<std::string> tok;
+    size_t i = 0;
+    while (i < item.size()) {
+      while (i < item.size() && item[i] == ' ') ++i;
+      size_t j = i;
+      while (j < item.size() && item[j] != ' ') ++j;
+      if (j > i) tok.push_back(item.substr(i, j - i));
+      i = j;
+    }
+    if (tok.empty()) continue;
+    int inv = -1, b = -1;
+    if (tok[0].size() == 7 && tok[0].compare(3, 2, "[b") == 0 && tok[0][6] == ']' &&
+        tok[0][5] >= '0' && tok[0][5] <= '4') {
+      if (tok[0].compare(0, 3, "fwd") == 0) inv = 0;
+      if (tok[0].compare(0, 3, "inv") == 0) inv = 1;
+      b = tok[0][5] - '0';
+    }
+    const size_t want = P.logN == 16 ? 3 : 2;
+    if (inv < 0 || tok.size() != want) PPST_THROW(ST_EINVAL, "malformed NTT plan entry '" + item + "'");
+    if (P.logN == 16) {
+      plan.v[inv][0][b] = find(kCol16, kNCol16, tok[1]);
+      plan.v[inv][1][b] = find(kRow16, kNRow16, tok[2]);
+    } else {
+      plan.v[inv][1][b] = find(kFull12, kNFull12, tok[1]);
+    }
+    seen[inv][b] = true;
+  }
+  for (int inv = 0; inv < 2; ++inv)
+    for (int b = 0; b < 5; ++b)
+      if (!seen[inv][b]) PPST_THROW(ST_EINVAL, "NTT plan misses a bucket");
+  sh.ntt_plan = plan;
+}
+
 void ntt_set_plan(Shared& sh, int col, int row) {
   const Params& P = sh.P;
   const int ncol = P.logN == 16 ? kNCol16 : 1, nrow = P.logN == 16 ? kNRow16 : kNFull12;

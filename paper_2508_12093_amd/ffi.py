@@ -146,6 +146,7 @@ _SIGS = {
     "ppst_stat_pearson": (ctypes.c_int, [_vp, _vp, _pp, _pp, _sz, _sz, _dbl, _dbl, _cfgp, _pp]),
     "ppst_ntt_autotune": (ctypes.c_int, [_vp]),
     "ppst_ntt_plan": (ctypes.c_int, [_vp, ctypes.c_char_p, _sz]),
+    "ppst_ntt_load_plan": (ctypes.c_int, [_vp, ctypes.c_char_p]),
     "ppst_ntt_set_plan": (ctypes.c_int, [_vp, _i32, _i32]),
     "ppst_ntt_forward": (ctypes.c_int, [_vp, _vp, _i32, _i32]),
     "ppst_ntt_inverse": (ctypes.c_int, [_vp, _vp, _i32, _i32]),
@@ -654,6 +655,10 @@ def ppst_ntt_plan(ctx: Context) -> str:
 
 def ppst_ntt_set_plan(ctx: Context, col: int, row: int):
     _chk(lib().ppst_ntt_set_plan(ctx, col, row))
+
+
+def ppst_ntt_load_plan(ctx: Context, plan: str):
+    _chk(lib().ppst_ntt_load_plan(ctx, plan.encode()))
 
 
 def ppst_ntt_forward(ctx: Context, dev_ptr: int, nlimbs: int, first_prime: int):

@@ -361,3 +361,21 @@ def test_c2_hmult_and_rotation_bit_exact(c2pair):
             for o, oc in zip(ffi.ppst_mul_const_batch(p.ctx, [cx, cy], 0.375), [ox, oy]):
                 p.same(o, p.O.mul_const(oc, 0.375))
     ffi.ppst_ntt_autotune(p.ctx)
+
+
+@pytest.mark.parametrize("name", ["t1", "c2"])
+def test_ntt_plan_round_trip(name):
+    """A plan written by ppst_ntt_plan loads back unchanged (so an autotuning
+    can be saved and reused); malformed text is refused and leaves the
+    plan as it was."""
+    _torch()
+    ctx = ffi.ppst_context_create(name)
+    tuned = ffi.ppst_ntt_plan(ctx)
+    ffi.ppst_ntt_set_plan(ctx, 0, 1)
+    ffi.ppst_ntt_load_plan(ctx, tuned)
+    assert ffi.ppst_ntt_plan(ctx) == tuned
+    for bad in ["fwd[b0] nonsense", tuned.split(";", 1)[1], "fwd[b9] x y;"]:
+        with pytest.raises(ffi.PpstError) as e:
+            ffi.ppst_ntt_load_plan(ctx, bad)
+        assert e.value.name == "EINVAL"
+        assert ffi.ppst_ntt_plan(ctx) == tuned
