@@ -110,6 +110,29 @@ def test_t2_multi_ciphertext_column(t2):
         p.same(a, b)
 
 
+def test_t2_column_longer_than_one_launch_group(t2):
+    """A column of 66 ciphertexts (the last one ragged): the n-ary sum runs
+    two launches (64 terms, then the rest accumulated), the constant products
+    five rescale groups and the squares five product groups; mean and
+    variance equal the oracle's left-to-right sequence bit for bit."""
+    p = t2
+    S_ = p.P.slots
+    n = 65 * S_ + 100
+    y = synth.lognormal_bernoulli_pair(17, n)[1] / 4.0
+    cys, oys = [], []
+    for i, v in enumerate(synth.split_column(y, S_)):
+        c, o = p.encrypt(v, 5000 + i)
+        cys.append(c)
+        oys.append(o)
+    assert len(cys) == 66
+    print("[stats] 66-ciphertext mean/variance", flush=True)
+    mean = ffi.ppst_stat_mean(p.ctx, p.evk, cys, n, 2.0)
+    omu = p.cc.mean_B(oys, n, 2.0)
+    p.same(mean, omu)
+    p.same(ffi.ppst_stat_variance(p.ctx, p.evk, cys, n, 2.0), p.cc.variance_B(oys, n, 2.0, omu))
+    assert rel(p.decrypt(mean)[0], y.mean() / 2.0) < TOL
+
+
 def test_t2_closed_forms(t2):
     """PCC(x, a x + b) = sign(a); z-score has mean 0, variance 1; a symmetric
     sample has skewness 0 (absolute error 1e-3)."""
