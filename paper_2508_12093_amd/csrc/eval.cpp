@@ -1205,25 +1205,39 @@ std::vector<CtPtr> rotate_hoisted_batch(Context& cx, const EvalKeys& evk,
   }
   std::vector<CtPtr> outs(n * m);
   // ModUp of every c1, with each digit's own limbs copied in beside the
-  // extension so that the inner product reads one buffer
+  // extension so that the inner product reads one buffer; groups of
+  // kMulChunk ciphertexts share each launch
   Buf ext = dev_buf(cx.pool, sext * n);
   {
-    Buf x = dev_buf(cx.pool, per);
-    for (size_t i = 0; i < n; ++i) {
+    const size_t grp = std::min(n, kMulChunk);
+    Buf x = dev_buf(cx.pool, per * grp);
+    for (size_t i0 = 0; i0 < n; i0 += grp) {
+      const int nb = (int)std::min(grp, n - i0);
+      u64* e0 = ext.p + sext * i0;
+      std::vector<const u64*> c1(nb);
+      for (int i = 0; i < nb; ++i) c1[i] = cts[i0 + i]->poly(1);
+      for (int j = 0; j < beta; ++j) {
+        const int lo = P.digit_lo(j), hi = P.digit_hi(j, level);
+        std::vector<const u64*> own(nb);
+        for (int i = 0; i < nb; ++i) own[i] = c1[i] + (size_t)lo * N;
+        k_gather_rows(sh, own.data(), e0 + ((size_t)j * ne + lo) * N, nb, cx.stream,
+                      (size_t)(hi - lo) * N, sext);
+      }
       NttLaunch L{};
-      L.src = cts[i]->poly(1);
+      if (nb == 1) {
+        L.src = c1[0];
+      } else {
+        k_gather_rows(sh, c1.data(), x.p, nb, cx.stream, per);
+        L.src = x.p;
+      }
       L.dst = x.p;
       L.nlimbs = nl;
+      L.nbatch = nb;
+      L.batch_stride = per;
       L.nq = nl;
       L.pofs = P.L + 1;
       ntt(sh, L, true, cx.stream);
-      u64* ei = ext.p + sext * i;
-      k_modup(sh, x.p, ei, level, 1, per, sext, cx.stream);
-      for (int j = 0; j < beta; ++j) {
-        const int lo = P.digit_lo(j), hi = P.digit_hi(j, level);
-        HIP_CHECK(hipMemcpyAsync(ei + ((size_t)j * ne + lo) * N, cts[i]->poly(1) + (size_t)lo * N,
-                                 (size_t)(hi - lo) * N * 8, hipMemcpyDeviceToDevice, cx.stream));
-      }
+      k_modup(sh, x.p, e0, level, nb, per, sext, cx.stream);
     }
     ntt_ext_digits(cx, ext.p, level, (int)n);   // the copied own limbs are skipped
   }

@@ -183,9 +183,9 @@ void k_rescale_conv(const Shared& sh, const u64* top, u64* tmp, int level, int n
 void k_sum(const Shared& sh, const u64* const* src, int nterm, u64* out, int npoly, int nl,
            hipStream_t st);
 // rows[i] (host array of nrows device pointers, row_words words each; 0
-// means N) -> dst + i row_words
+// means N) -> dst + i dst_stride (0 means row_words)
 void k_gather_rows(const Shared& sh, const u64* const* rows, u64* dst, int nrows, hipStream_t st,
-                   size_t row_words = 0);
+                   size_t row_words = 0, size_t dst_stride = 0);
 
 // ------------------------------------------------------- sampling etc.
 // signed 64-bit integers -> residues on limbs t of a map

@@ -596,10 +596,10 @@ __global__ void k_sum_kernel(PtrsIn src, int nterm, u64* out, int acc, const Mod
   out[i] = s;
 }
 
-__global__ void k_gather_rows_kernel(PtrsIn rows, u64* dst, size_t W) {
+__global__ void k_gather_rows_kernel(PtrsIn rows, u64* dst, size_t W, size_t ds) {
   const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= W) return;
-  dst[(size_t)blockIdx.y * W + k] = rows.p[blockIdx.y][k];
+  dst[(size_t)blockIdx.y * ds + k] = rows.p[blockIdx.y][k];
 }
 
 const Mod* M(const Shared& sh) { return (const Mod*)sh.tab.mods.p; }
@@ -637,8 +637,10 @@ void k_sum(const Shared& sh, const u64* const* src, int nterm, u64* out, int npo
 }
 
 void k_gather_rows(const Shared& sh, const u64* const* rows, u64* dst, int nrows, hipStream_t st,
-                   size_t row_words) {
+                   size_t row_words, size_t dst_stride) {
   const size_t W = row_words ? row_words : (size_t)sh.P.N;
+  const size_t ds = dst_stride ? dst_stride : W;
+  if (ds < W) PPST_THROW(ST_EINVAL, "gathered rows would overlap");
   for (int r0 = 0; r0 < nrows; r0 += kPtrBatch) {
     const int nr = std::min(kPtrBatch, nrows - r0);
     PtrsIn p{};
@@ -648,7 +650,8 @@ void k_gather_rows(const Shared& sh, const u64* const* rows, u64* dst, int nrows
     }
     dim3 g = grid_for(W);
     g.y = nr;
-    hipLaunchKernelGGL(k_gather_rows_kernel, g, dim3(kBlock), 0, st, p, dst + (size_t)r0 * W, W);
+    hipLaunchKernelGGL(k_gather_rows_kernel, g, dim3(kBlock), 0, st, p, dst + (size_t)r0 * ds, W,
+                       ds);
     LAUNCH_CHECK();
   }
 }
