@@ -55,6 +55,8 @@ def parse():
                     help="skip the 1M-row statistics replay of Sec. 6.3")
     ap.add_argument("--serving-queries", type=int, default=200,
                     help="queries per load point of the serving loop (0: skip)")
+    ap.add_argument("--serving-slots", type=int, default=8,
+                    help="queries in flight at once (worker streams)")
     ap.add_argument("--serving-loads", type=str, default="0.6",
                     help="offered loads as fractions of the measured saturation rate")
     return ap.parse_args()
@@ -273,7 +275,8 @@ def main():
     serving = None
     if args.serving_queries > 0:
         loads = [float(v) for v in args.serving_loads.split(",") if v]
-        serving = serving_bench(ctx, pk, sk, evk, args.serving_queries, loads)
+        serving = serving_bench(ctx, pk, sk, evk, args.serving_queries, loads,
+                                nslots=args.serving_slots)
     rf = measure_ntt(ctx, stream, reps=10 if args.quick else 50)
 
     out = {
@@ -391,7 +394,7 @@ def exp2_replay(ctx, pk, sk, evk, sync, n: int = 1_000_000):
 SERVING_ROWS = [1 << 10, 1 << 12, 1 << 14, 1 << 16, 1 << 18, 1 << 20]
 
 
-def serving_bench(ctx, pk, sk, evk, nq: int, loads, seed: int = 4):
+def serving_bench(ctx, pk, sk, evk, nq: int, loads, seed: int = 4, nslots: int = 8):
     """Continuous-batching server over resident columns of 2^10..2^20 rows
     (1..32 ciphertexts): x ~ Bernoulli(0.3), y = (lognormal(0, 1) + s x) / 4
     with corr ~ 0.5.  Query kinds uniform over mean, variance, z-score, CV and
@@ -412,7 +415,7 @@ def serving_bench(ctx, pk, sk, evk, nq: int, loads, seed: int = 4):
 
     info = ctx.info
     slots, L = info.slots, info.L
-    srv = ffi.ppst_server_create(ctx, evk, 96 << 30, 8)
+    srv = ffi.ppst_server_create(ctx, evk, 96 << 30, nslots)
     cols = {}
     for i, n in enumerate(SERVING_ROWS):
         x, y = synth.lognormal_bernoulli_pair(seed + i, n)
@@ -498,7 +501,7 @@ def serving_bench(ctx, pk, sk, evk, nq: int, loads, seed: int = 4):
     del srv
     log("serving: server closed in %.1f s" % (time.perf_counter() - t))
     return {"saturation_qps": round(sat_rate, 2), "queries_per_point": nq,
-            "rows": SERVING_ROWS, "kinds": "mean,variance,zscore,cv,pearson", "slots": 8,
+            "rows": SERVING_ROWS, "kinds": "mean,variance,zscore,cv,pearson", "slots": nslots,
             "loads": points, "failed": nfail, "spot_max_err": float(max(errs)) if errs else None}
 
 
