@@ -235,10 +235,10 @@ int ppst_rotate_hoisted_batch(ppst_context* ctx, const ppst_eval_keys* evk,
                               const ppst_ciphertext* const* cts, size_t n, const int32_t* rs,
                               size_t m, ppst_ciphertext** outs);
 /* rotate-and-sum: every slot ends up holding the sum of all N/2 slots (the
- * sums of Eq. 2, Sec. 5.1).  Steps of two bits, ct += rot(ct, s) + rot(ct, 2s)
- * + rot(ct, 3s) for s = 1, 4, 16, ..., then ct += rot(ct, s) for a last odd
- * bit; each step's key switches share one ModUp of c1 and one rounding
- * ModDown of the summed inner products (keys: ppst_evk_add_rotsum). */
+ * sums of Eq. 2, Sec. 5.1).  Steps of three bits, ct += rot(ct, s) + ... +
+ * rot(ct, 7s) for s = 1, 8, 64, ..., then one step of two bits or one bit
+ * for what remains; each step's key switches share one ModUp of c1 and one
+ * rounding ModDown of the summed inner products (keys: ppst_evk_add_rotsum). */
 int ppst_rotsum(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciphertext* a,
                 ppst_ciphertext** out);
 /* ppst_rotsum of n ciphertexts of one level: each step's ModUp, inner

@@ -254,13 +254,15 @@ class Oracle:
                 for r in steps}
 
     def rotsum_plan(self):
-        """Steps (s, radix) of RotSum over the N/2 slots: radix 4 while two or
-        more bits of the slot index remain, then radix 2."""
+        """Steps (s, radix) of RotSum over the N/2 slots: radix 8 while three
+        or more bits of the slot index remain, then one step of radix 4 or 2
+        for the bits left."""
+        bits = self.P.slots.bit_length() - 1
         plan, b = [], 0
-        while (1 << b) < self.P.slots:
-            rad = 4 if (1 << (b + 2)) <= self.P.slots else 2
-            plan.append((1 << b, rad))
-            b += 2 if rad == 4 else 1
+        while b < bits:
+            take = min(3, bits - b)
+            plan.append((1 << b, 1 << take))
+            b += take
         return plan
 
     def rotsum_steps(self):

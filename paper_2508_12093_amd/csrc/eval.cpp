@@ -1318,11 +1318,12 @@ std::vector<CtPtr> rotate_batch(Context& cx, const EvalKeys& evk,
 
 std::vector<std::pair<long, int>> rotsum_plan(const Params& P) {
   std::vector<std::pair<long, int>> plan;
-  int b = 0;
-  while ((1L << b) < P.slots()) {
-    const int rad = (1L << (b + 2)) <= P.slots() ? 4 : 2;
-    plan.emplace_back(1L << b, rad);
-    b += rad == 4 ? 2 : 1;
+  int bits = 0;
+  while ((1L << bits) < P.slots()) ++bits;
+  for (int b = 0; b < bits;) {
+    const int take = std::min(3, bits - b);
+    plan.emplace_back(1L << b, 1 << take);
+    b += take;
   }
   return plan;
 }

@@ -75,8 +75,9 @@ std::vector<CtPtr> rotate_batch(Context& cx, const EvalKeys& evk,
 CtPtr rotsum(Context& cx, const EvalKeys& evk, const Ciphertext& a);
 // rotsum() of several ciphertexts of one level, each step batched
 std::vector<CtPtr> rotsum_batch(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& cts);
-// (s, radix) per step: radix 4 while two or more bits of the slot index
-// remain, then radix 2; the Galois keys needed are those of k s, 0 < k < radix
+// (s, radix) per step: radix 8 while three or more bits of the slot index
+// remain, then radix 4 or 2 for the rest; the Galois keys needed are those of
+// k s, 0 < k < radix
 std::vector<std::pair<long, int>> rotsum_plan(const Params& P);
 CtPtr level_align(Context& cx, const Ciphertext& a, int level);
 // level_align of each ciphertext, all at one level and of one degree; the

@@ -316,7 +316,7 @@ def test_error_statuses(pair):
         ffi.ppst_mul(p.ctx, p.evk, low, low)
     assert e.value.name == "ELEVEL"
     with pytest.raises(ffi.PpstError) as e:
-        ffi.ppst_rotate(p.ctx, p.evk, ct, 7)
+        ffi.ppst_rotate(p.ctx, p.evk, ct, 9)      # neither a fixture step nor a RotSum step
     assert e.value.name == "ENOKEY"
     with pytest.raises(ffi.PpstError) as e:
         ffi.ppst_level_align(p.ctx, low, 1)

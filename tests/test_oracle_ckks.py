@@ -140,8 +140,9 @@ def test_rotations(env):
     assert np.max(np.abs(O.decrypt(h[1], sk) - np.roll(m, -5))) < tol
     s = O.rotsum(ct, gk)
     assert np.max(np.abs(O.decrypt(s, sk) - m.sum())) < m.sum() * 1e-4
+    assert 9 not in O.rotsum_steps() + [3, 5]
     with pytest.raises(KeyError):
-        O.rotate(ct, 7, gk)
+        O.rotate(ct, 9, gk)
 
 
 def test_rotsum_plan_covers_every_slot_once(env):
@@ -178,3 +179,6 @@ def test_rotsum_step_sums_rotations(env):
     assert np.max(np.abs(O.decrypt(got, sk) - O.decrypt(sep, sk))) < 4 * tol
     two = O.rotsum_step(ct, 2, 2, gk)
     assert np.max(np.abs(O.decrypt(two, sk) - (m + np.roll(m, -2)))) < 2 * tol
+    eight = O.rotsum_step(ct, 1, 8, gk)       # seven keys in one extended sum
+    want8 = sum(np.roll(m, -k) for k in range(8))
+    assert np.max(np.abs(O.decrypt(eight, sk) - want8)) < 8 * tol
