@@ -141,8 +141,9 @@ int ppst_evk_add_relin(ppst_context* ctx, const ppst_secret_key* sk, uint64_t se
 /* Galois keys for rotations by steps[i] slots (s(X^g) -> s, g = 5^r mod 2N) */
 int ppst_evk_add_galois(ppst_context* ctx, const ppst_secret_key* sk, const int32_t* steps,
                         size_t n, uint64_t seed, ppst_eval_keys* evk);
-/* Galois keys that rotate-and-sum needs: steps k 4^i (k = 1, 2, 3) while
- * 4^(i+1) <= N/2, then k = 1 for a last odd power of two (22 keys at N = 2^16) */
+/* Galois keys that rotate-and-sum needs: steps k 8^i (k = 1..7) while
+ * 8^(i+1) <= N/2, then k 8^i for k below the remaining 4 or 2 (35 keys at
+ * N = 2^16, 24 at N = 2^12) */
 int ppst_evk_add_rotsum(ppst_context* ctx, const ppst_secret_key* sk, uint64_t seed,
                         ppst_eval_keys* evk);
 /* copy a key to the host: galois = 0 selects the relinearisation key.
