@@ -363,6 +363,23 @@ def test_c2_hmult_and_rotation_bit_exact(c2pair):
     ffi.ppst_ntt_autotune(p.ctx)
 
 
+def test_c2_rotsum_bit_exact(c2pair):
+    """Rotate-and-sum at N = 2^16, level 24 (five hoisted radix-8 steps, seven
+    Galois keys each) equals the oracle's in every residue, alone and as five
+    lanes of one batch (the five-lane multi-key inner product)."""
+    p = c2pair
+    print("\n[parity] c2 RotSum: 35 Galois keys on both sides, oracle RotSum", flush=True)
+    p.add_rotsum_keys()
+    m = synth.uniform_column(11, p.P.slots, 0, 1) / p.P.slots
+    ct, oct_ = p.encrypt(m, 61)
+    ors = p.O.rotsum(oct_, p.ogk)
+    s = ffi.ppst_rotsum(p.ctx, p.evk, ct)
+    p.same(s, ors)
+    for o in ffi.ppst_rotsum_batch(p.ctx, p.evk, [ct] * 5):
+        p.same(o, ors)
+    assert abs(p.decrypt(s)[0] - m.sum()) < 1e-3
+
+
 @pytest.mark.parametrize("name", ["t1", "c2"])
 def test_ntt_plan_round_trip(name):
     """A plan written by ppst_ntt_plan loads back unchanged (so an autotuning
