@@ -154,6 +154,10 @@ class Pool {
   size_t in_use() const { return in_use_; }
   size_t cached() const { return cached_; }
   void trim();
+  // The owning context is going away (its stream drained, about to be
+  // destroyed): blocks still held by callers may outlive it, so from now on
+  // the pool never touches that stream again.
+  void detach();
   // Graph recording: every block handed out between begin_capture and
   // end_capture is pinned for the graph (end_capture returns them); a pinned
   // block released by its owner is not reused until unpin(), so the memory a
@@ -180,6 +184,7 @@ class Pool {
   void* hand_out(void* p, size_t bytes);   // bookkeeping of a block leaving the pool (mu_ held)
 
   hipStream_t stream_;
+  bool detached_ = false;
   Hooks hooks_;
   std::shared_ptr<PoolRegistry> registry_;
   std::mutex mu_;

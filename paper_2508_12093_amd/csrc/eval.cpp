@@ -183,10 +183,21 @@ void PoolRegistry::trim_others(const Pool* except) {
 
 // Returns every cached block of its own and every slab none of whose blocks
 // is in use; blocks of slabs still in use stay cached.
+void Pool::detach() {
+  std::lock_guard<std::mutex> g(mu_);
+  detached_ = true;
+  stream_ = nullptr;
+}
+
 void Pool::trim() {
   std::lock_guard<std::mutex> g(mu_);
   if (capturing_) return;   // a recording stream cannot be synchronised
-  if (!free_.empty()) (void)hipStreamSynchronize(stream_);
+  // cached blocks may still be read by work in flight: on the pool's stream,
+  // or, once detached, on whichever stream last used a caller's block
+  if (!free_.empty()) {
+    if (detached_) (void)hipDeviceSynchronize();
+    else (void)hipStreamSynchronize(stream_);
+  }
   for (auto it = free_.begin(); it != free_.end();) {
     auto s = slab_of_.find(it->second);
     if (s == slab_of_.end()) {
@@ -421,6 +432,8 @@ std::unique_ptr<Context> make_context(std::shared_ptr<Shared> sh, hipStream_t st
 void destroy_context(Context* cx) {
   if (!cx) return;
   (void)hipStreamSynchronize(cx->stream);
+  // ciphertexts the caller still holds keep the pool alive past the stream
+  if (cx->pool) cx->pool->detach();
   cx->pool.reset();
   if (cx->own_stream) (void)hipStreamDestroy(cx->stream);
 }
