@@ -206,3 +206,22 @@ def test_zscore_query_returns_every_ciphertext(env):
     assert ffi.ppst_server_output_count(srv, t) == 1
     rc, outs, st = ffi.ppst_server_wait_all(srv, t)
     assert rc == 0 and len(outs) == 1
+
+
+def test_results_outlive_the_server(env):
+    """Result ciphertexts stay usable after the server that produced them is
+    destroyed, and releasing them afterwards (the last use of the worker's
+    memory pool, whose stream is gone) leaves the device working."""
+    ctx, sk, evk, cols = env
+    cfg = ffi.ppst_invsqrt_cfg_default()
+    n, x, y, cx, cy = cols["c"]
+    srv = ffi.ppst_server_create(ctx, evk, 8 << 30, 2)
+    cid = ffi.ppst_server_register_column(srv, cy, n)
+    ts = [ffi.ppst_server_submit(srv, ffi.Q_MEAN, cid, 0, 1.0, 1.0, cfg) for _ in range(3)]
+    outs = [ffi.ppst_server_wait(srv, t)[1] for t in ts]
+    del srv
+    for ct in outs:
+        assert abs(ffi.ppst_decode(ctx, ffi.ppst_decrypt(ctx, sk, ct))[0] - y.mean()) < 1e-3
+    del outs, ct
+    again = ffi.ppst_stat_mean(ctx, evk, cy, n, 1.0)
+    assert abs(ffi.ppst_decode(ctx, ffi.ppst_decrypt(ctx, sk, again))[0] - y.mean()) < 1e-3
