@@ -111,6 +111,8 @@ int ppst_context_create(const ppst_params* params, const ppst_device_hooks* hook
  * may be used on another after ppst_sync of the first, and must not be
  * destroyed while another context's queued work still reads it. */
 int ppst_context_fork(const ppst_context* base, void* stream, ppst_context** out);
+/* waits for the context's stream; ciphertexts and plaintexts it produced stay
+ * valid (their memory is released when the last of them is destroyed) */
 int ppst_context_destroy(ppst_context* ctx);
 /* waits for all work enqueued on the context's stream */
 int ppst_sync(ppst_context* ctx);
@@ -426,6 +428,9 @@ int ppst_server_output_count(ppst_server* srv, uint64_t ticket, size_t* n);
  * when cap is below ppst_server_output_count. */
 int ppst_server_wait_all(ppst_server* srv, uint64_t ticket, ppst_ciphertext** outs, size_t cap,
                          size_t* n_out, ppst_query_stats* stats);
+/* lets the queries being run finish, drops those still waiting for
+ * admission, and releases the server's streams; result ciphertexts already
+ * collected stay valid */
 int ppst_server_destroy(ppst_server* srv);
 
 #ifdef __cplusplus
