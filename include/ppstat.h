@@ -91,6 +91,11 @@ int ppst_dg_thresholds(uint64_t* out, size_t cap);
  * (level, Delta_level), host only (N outputs) */
 int ppst_encode_coeffs(const ppst_params* params, const double* values, size_t n, int32_t level,
                        int64_t* out, size_t cap);
+/* the rotation steps whose Galois keys ppst_rotsum needs (the keys
+ * ppst_evk_add_rotsum makes), host only: *n receives their number; with
+ * out == NULL and cap == 0 only the count is returned, otherwise cap must be
+ * at least that count (EINVAL) */
+int ppst_rotsum_steps(const ppst_params* params, int32_t* out, size_t cap, size_t* n);
 /* SplitMix64 stream state for (seed, purpose, limb), host only */
 uint64_t ppst_stream_key(uint64_t seed, uint64_t purpose, uint64_t limb);
 

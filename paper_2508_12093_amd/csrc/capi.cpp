@@ -161,6 +161,24 @@ int ppst_encode_coeffs(const ppst_params* params, const double* values, size_t n
   });
 }
 
+int ppst_rotsum_steps(const ppst_params* params, int32_t* out, size_t cap, size_t* n) {
+  return guard([&] {
+    NEED(params);
+    NEED(n);
+    ParamSpec sp{params->logN, params->L, params->K, params->dnum, params->q0_bits,
+                 params->p_bits, params->scale};
+    Params P = make_params(sp);
+    std::vector<int32_t> steps;
+    for (const auto& st : rotsum_plan(P))
+      for (int k = 1; k < st.second; ++k) steps.push_back((int32_t)(k * st.first));
+    *n = steps.size();
+    if (out == nullptr && cap == 0) return;
+    NEED(out);
+    if (cap < steps.size()) PPST_THROW(ST_EINVAL, "buffer too small");
+    for (size_t i = 0; i < steps.size(); ++i) out[i] = steps[i];
+  });
+}
+
 uint64_t ppst_stream_key(uint64_t seed, uint64_t purpose, uint64_t limb) {
   return stream_key(seed, purpose, limb);
 }

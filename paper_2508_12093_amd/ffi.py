@@ -75,6 +75,7 @@ _SIGS = {
     "ppst_params_preset": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(Params)]),
     "ppst_params_derive": (ctypes.c_int, [ctypes.POINTER(Params), _vp, _vp, _vp, _sz]),
     "ppst_dg_thresholds": (ctypes.c_int, [_vp, _sz]),
+    "ppst_rotsum_steps": (ctypes.c_int, [_vp, _vp, _sz, ctypes.POINTER(ctypes.c_size_t)]),
     "ppst_encode_coeffs": (ctypes.c_int, [ctypes.POINTER(Params), _vp, _sz, _i32, _vp, _sz]),
     "ppst_stream_key": (_u64, [_u64, _u64, _u64]),
     "ppst_context_create": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.POINTER(DeviceHooks), _vp, _pp]),
@@ -304,6 +305,15 @@ def ppst_dg_thresholds():
     out = np.zeros(19, dtype=np.uint64)
     _chk(lib().ppst_dg_thresholds(_p(out), 19))
     return out
+
+
+def ppst_rotsum_steps(params) -> list:
+    """Rotation steps whose Galois keys ppst_rotsum needs (host only)."""
+    n = ctypes.c_size_t()
+    _chk(lib().ppst_rotsum_steps(ctypes.byref(params), None, 0, ctypes.byref(n)))
+    out = np.zeros(max(1, n.value), dtype=np.int32)
+    _chk(lib().ppst_rotsum_steps(ctypes.byref(params), _p(out), n.value, ctypes.byref(n)))
+    return [int(v) for v in out[:n.value]]
 
 
 def ppst_encode_coeffs(params: Params, values, level: int):

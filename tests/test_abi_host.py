@@ -62,3 +62,15 @@ def test_encoder_matches_oracle(name, n):
             a = ffi.ppst_encode_coeffs(p, vals, level)
             b = O.encode_coeffs(vals, P.scale[level])
             assert np.array_equal(a, b), int(np.sum(a != b))
+
+
+@pytest.mark.parametrize("name", ["c1", "t1", "t2", "c2"])
+def test_rotsum_steps_match_oracle(name):
+    """The library's RotSum key steps (host only) are the oracle's plan: radix-8
+    steps, then one of radix 4 or 2; each step's keys cover k s, 0 < k < radix."""
+    p = ffi.ppst_params_preset(name)
+    O = ref.Oracle(ref.Params.preset(name))
+    got = ffi.ppst_rotsum_steps(p)
+    assert got == O.rotsum_steps()
+    assert len(got) == len(set(got)) and all(0 < r < O.P.slots for r in got)
+    assert O.rotsum_plan()[0] == (1, 8)
