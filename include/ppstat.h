@@ -249,6 +249,14 @@ int ppst_rotate_hoisted_batch(ppst_context* ctx, const ppst_eval_keys* evk,
  * rounding ModDown of the summed inner products (keys: ppst_evk_add_rotsum). */
 int ppst_rotsum(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciphertext* a,
                 ppst_ciphertext** out);
+/* rotate-and-sum by its plain definition (the slot sums of Eq. 2, with
+ * Sec. 3.1's Rot): for k = 0 .. log2(N/2) - 1, ct <- ct + Rot(ct, 2^k), each
+ * Rot an ordinary (unhoisted) rotation.  Fifteen key switches at N = 2^16
+ * instead of ppst_rotsum's five hoisted steps; the same sum up to the
+ * key-switching rounding.  Galois keys for the steps 2^k (ppst_evk_add_rotsum
+ * makes them, or ppst_evk_add_galois); ENOKEY when one is missing. */
+int ppst_rotsum_serial(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciphertext* a,
+                       ppst_ciphertext** out);
 /* ppst_rotsum of n ciphertexts of one level: each step's ModUp, inner
  * product (a thread serves up to 5 ciphertexts per key read) and ModDown
  * run once for the whole group.  Bit for bit the same as n calls of
@@ -288,7 +296,7 @@ int ppst_mul_batch(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciph
  * context's stream), for callers that replay a fixed sequence many times.
  * Between ppst_graph_begin and ppst_graph_end the evaluation calls (add, sub,
  * add_const, mul_const, mul_const_batch, mul_int, mul_plain, mul, tensor,
- * relin, rescale, rotate, rotate_batch, rotate_hoisted(_batch), rotsum,
+ * relin, rescale, rotate, rotate_batch, rotate_hoisted(_batch), rotsum, rotsum_serial,
  * rotsum_batch, level_align, mul_batch) are recorded, not run: their output handles are valid at once, and each
  * ppst_graph_launch writes them again.  Calls that wait for the device or
  * move data to or from the host (keygen, encode, encrypt, decrypt, exports,

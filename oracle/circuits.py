@@ -104,7 +104,11 @@ class EncEval:
         return self.O.mul_plain(a, pt)
 
     def rotsum(self, a):
-        return self.O.rotsum(a, self.gkeys)
+        # The circuits' slot sums use the hoisted radix-8 rotate-and-sum (five
+        # steps at N = 2^16), the form the library runs; tests pin it to the
+        # plain definition ``Oracle.rotsum`` (serial ct + Rot(ct, 2^k)) by
+        # decryption within the key-switching noise.
+        return self.O.rotsum_hoisted8(a, self.gkeys)
 
 
 class PlainEval:

@@ -618,11 +618,11 @@ void orc_decrypt(const orc_params* P, const u64* s_ntt, const u64* ct, int level
  * When `g` != 0 the extended digits are permuted by X -> X^g after ModUp
  * (the hoisted-rotation form); g = 0 means no permutation.
  */
-/* ModUp of d, optional automorphism, inner product with the key: the two
- * accumulators over q_0..q_l, p_0..p_{K-1} (NTT form, [ne][N] each) */
-static void ks_accumulate(const orc_params* P, int level, const u64* d, const u64* key,
-                          u64 g, u64* acc0, u64* acc1) {
-    int N = P->N, L = P->L, K = P->K, np = L + 1 + K;
+/* ModUp of every digit of d: ext [beta][ne][N] in NTT form over
+ * q_0..q_l, p_0..p_{K-1}; digit j's own limbs are d's, the others the fast
+ * base conversion of iNTT(d|D_j) (no correction), then NTT. */
+static void ks_modup(const orc_params* P, int level, const u64* d, u64* ext_all) {
+    int N = P->N, L = P->L, K = P->K;
     int nl = level + 1;
     int ne = nl + K;                       /* extended limbs: q_0..q_l, p_0..p_{K-1} */
     int32_t ext_pidx[ORC_MAXP];
@@ -636,16 +636,11 @@ static void ks_accumulate(const orc_params* P, int level, const u64* d, const u6
     seq_pidx(qidx, nl);
     orc_intt(P, xc, nl, qidx);
 
-    memset(acc0, 0, sizeof(u64) * (size_t)ne * N);
-    memset(acc1, 0, sizeof(u64) * (size_t)ne * N);
-    u64* ext = (u64*)malloc(sizeof(u64) * (size_t)ne * N);
-    u64* tmp = (u64*)malloc(sizeof(u64) * (size_t)ne * N);
-
     for (int j = 0; j < beta; j++) {
         int lo = j * P->alpha;
         int hi = lo + P->alpha;
         if (hi > nl) hi = nl;
-        /* ModUp_j */
+        u64* ext = ext_all + (size_t)j * ne * N;
         #pragma omp parallel for schedule(dynamic)
         for (int t = 0; t < ne; t++) {
             u64* y = ext + (size_t)t * N;
@@ -672,14 +667,36 @@ static void ks_accumulate(const orc_params* P, int level, const u64* d, const u6
             }
             orc_ntt_limb(P, ext_pidx[t], y);
         }
-        const u64* src = ext;
+    }
+    free(xc);
+}
+
+/* Optional automorphism X -> X^g of the extended digits (g = 0: none), then
+ * the inner product with the key: the two accumulators over q_0..q_l,
+ * p_0..p_{K-1} (NTT form, [ne][N] each). */
+static void ks_inner(const orc_params* P, int level, const u64* ext_all, const u64* key,
+                     u64 g, u64* acc0, u64* acc1) {
+    int N = P->N, L = P->L, K = P->K, np = L + 1 + K;
+    int nl = level + 1;
+    int ne = nl + K;
+    int32_t ext_pidx[ORC_MAXP];
+    for (int t = 0; t < nl; t++) ext_pidx[t] = t;
+    for (int k = 0; k < K; k++) ext_pidx[nl + k] = L + 1 + k;
+    int beta = (nl + P->alpha - 1) / P->alpha;
+
+    memset(acc0, 0, sizeof(u64) * (size_t)ne * N);
+    memset(acc1, 0, sizeof(u64) * (size_t)ne * N);
+    u64* tmp = (u64*)malloc(sizeof(u64) * (size_t)ne * N);
+    for (int j = 0; j < beta; j++) {
+        const u64* src = ext_all + (size_t)j * ne * N;
         if (g) {
-            orc_automorph_ntt(P, ext, tmp, ne, ext_pidx, g);
+            orc_automorph_ntt(P, src, tmp, ne, ext_pidx, g);
             src = tmp;
         }
         /* inner product with digit j of the key */
         const u64* kb = key + (size_t)(2 * j) * np * N;
         const u64* ka = key + (size_t)(2 * j + 1) * np * N;
+        #pragma omp parallel for schedule(static)
         for (int t = 0; t < ne; t++) {
             int p = ext_pidx[t];
             u64 q = P->q[p];
@@ -691,7 +708,22 @@ static void ks_accumulate(const orc_params* P, int level, const u64* d, const u6
             }
         }
     }
-    free(xc); free(ext); free(tmp);
+    free(tmp);
+}
+
+static u64* modup_alloc(const orc_params* P, int level) {
+    int nl = level + 1, ne = nl + P->K;
+    int beta = (nl + P->alpha - 1) / P->alpha;
+    return (u64*)malloc(sizeof(u64) * (size_t)beta * ne * P->N);
+}
+
+/* ModUp of d, optional automorphism, inner product with the key */
+static void ks_accumulate(const orc_params* P, int level, const u64* d, const u64* key,
+                          u64 g, u64* acc0, u64* acc1) {
+    u64* ext = modup_alloc(P, level);
+    ks_modup(P, level, d, ext);
+    ks_inner(P, level, ext, key, g, acc0, acc1);
+    free(ext);
 }
 
 /* ModDown of both accumulators, rounding: out = (u + h - Conv(u + h)) / P
@@ -829,6 +861,7 @@ void orc_mul_poly(const orc_params* P, const u64* a, const u64* pt, int level, i
 void orc_tensor(const orc_params* P, const u64* a, const u64* b, int level, u64* d) {
     int N = P->N, nl = level + 1;
     size_t L1 = (size_t)nl * N;
+    #pragma omp parallel for schedule(static)
     for (int i = 0; i < nl; i++) {
         u64 q = P->q[i];
         for (int k = 0; k < N; k++) {
@@ -906,8 +939,11 @@ void orc_rotsum_step(const orc_params* P, int level, const u64* ct, const u64* c
     u64* acc1 = (u64*)calloc(sz, sizeof(u64));
     u64* t0 = (u64*)malloc(sizeof(u64) * sz);
     u64* t1 = (u64*)malloc(sizeof(u64) * sz);
+    u64* ext = modup_alloc(P, level);     /* one ModUp of c1 serves every rotation */
+    ks_modup(P, level, ct + (size_t)nl * N, ext);
     for (int r = 0; r < nk; r++) {
-        ks_accumulate(P, level, ct + (size_t)nl * N, keys[r], gs[r], t0, t1);
+        ks_inner(P, level, ext, keys[r], gs[r], t0, t1);
+        #pragma omp parallel for schedule(static)
         for (int t = 0; t < ne; t++) {
             u64 q = P->q[t < nl ? t : L + 1 + (t - nl)];
             for (int k = 0; k < N; k++) {
@@ -941,7 +977,7 @@ void orc_rotsum_step(const orc_params* P, int level, const u64* ct, const u64* c
             }
         }
     }
-    free(acc0); free(acc1); free(t0); free(t1); free(u0); free(u1);
+    free(ext); free(acc0); free(acc1); free(t0); free(t1); free(u0); free(u1);
 }
 
 /* ------------------------------------------------------------------ */

@@ -14,7 +14,10 @@ switching, in the plainest form:
 * ``Oracle.mul_const/mul_plain`` Mul(P), then rescale       (Sec. 3.1)
 * ``Oracle.mul``               Mul(C) = tensor + relinearise + rescale (Sec. 3.1)
 * ``Oracle.rotate``            Rot, cyclic slot rotation   (Sec. 3.1)
-* ``Oracle.rotsum``            the slot sums inside Mean/Variance (Eq. 2, Sec. 5.1)
+* ``Oracle.rotsum``            the slot sums inside Mean/Variance (Eq. 2, Sec. 5.1):
+                               log2(N/2) serial steps ct <- ct + Rot(ct, 2^k)
+* ``Oracle.rotsum_hoisted8``   the same sum in hoisted radix-8 steps (the
+                               form the statistics circuits use)
 * ``Oracle.level_align``       bringing two operands to a common level
 
 Every ciphertext at level l carries the canonical scale Delta_l, with
@@ -253,10 +256,10 @@ class Oracle:
         return {galois_element(r, self.P.N): self.galois_key(sk, seed, galois_element(r, self.P.N))
                 for r in steps}
 
-    def rotsum_plan(self):
-        """Steps (s, radix) of RotSum over the N/2 slots: radix 8 while three
-        or more bits of the slot index remain, then one step of radix 4 or 2
-        for the bits left."""
+    def rotsum_hoisted8_plan(self):
+        """Steps (s, radix) of the hoisted radix-8 rotate-and-sum over the N/2
+        slots: radix 8 while three or more bits of the slot index remain,
+        then one step of radix 4 or 2 for the bits left."""
         bits = self.P.slots.bit_length() - 1
         plan, b = [], 0
         while b < bits:
@@ -265,9 +268,15 @@ class Oracle:
             b += take
         return plan
 
-    def rotsum_steps(self):
-        """Rotation steps whose Galois keys RotSum needs: k s, 0 < k < radix."""
-        return [k * s for s, rad in self.rotsum_plan() for k in range(1, rad)]
+    def rotsum_hoisted8_steps(self):
+        """Rotation steps whose Galois keys the hoisted radix-8 rotate-and-sum
+        needs: k s, 0 < k < radix.  They include every power of two below
+        N/2, so the same keys serve the plain ``rotsum``."""
+        return [k * s for s, rad in self.rotsum_hoisted8_plan() for k in range(1, rad)]
+
+    def rotsum_serial_steps(self):
+        """Rotation steps of the plain ``rotsum``: 2^k for 2^k < N/2."""
+        return [1 << k for k in range(self.P.slots.bit_length() - 1)]
 
     # ------------------------------------------------------------- encoding
     def encode_coeffs(self, m, scale: float) -> np.ndarray:
@@ -520,10 +529,23 @@ class Oracle:
             outs.append(Ciphertext(out, a.level, a.scale))
         return outs
 
+    def rotsum(self, a: Ciphertext, gkeys: dict) -> Ciphertext:
+        """Rotate-and-sum by its definition: for k = 0 .. log2(N/2) - 1,
+        ct <- ct + Rot(ct, 2^k), with Rot the plain rotation above.  After
+        the k-th step slot j holds the sum of slots j .. j + 2^(k+1) - 1, so
+        at the end every slot holds the sum of all N/2 slots (the slot sums
+        of Mean and Variance, Eq. 2 and Sec. 5.1; Rot is Sec. 3.1's)."""
+        ct = a
+        for r in self.rotsum_serial_steps():
+            ct = self.add(ct, self.rotate(ct, r, gkeys))
+        return ct
+
     def rotsum_step(self, a: Ciphertext, s: int, radix: int, gkeys: dict) -> Ciphertext:
         """ct + sum_{0<k<radix} rot(ct, k s), the key switches hoisted: one
         ModUp of c1, the permuted inner products added in the extended basis,
-        one ModDown (``orc_rotsum_step``)."""
+        one ModDown (``orc_rotsum_step``).  It differs from the sum of plain
+        rotations only in how the ModDown rounds (a distinct, equally valid
+        key switch); the tests pin it to ``rotsum`` by decryption."""
         P = self.P
         gs = np.array([galois_element(k * s, P.N) for k in range(1, radix)], dtype=np.uint64)
         keys = [np.ascontiguousarray(gkeys[int(g)]) for g in gs]
@@ -533,11 +555,13 @@ class Oracle:
                                len(keys), _p(out))
         return Ciphertext(out, a.level, a.scale)
 
-    def rotsum(self, a: Ciphertext, gkeys: dict) -> Ciphertext:
-        """Rotate-and-sum: every slot ends up holding the sum of all slots.
-        Steps of ``rotsum_plan``: ct <- ct + sum_{0<k<radix} rot(ct, k s)."""
+    def rotsum_hoisted8(self, a: Ciphertext, gkeys: dict) -> Ciphertext:
+        """Rotate-and-sum in the steps of ``rotsum_hoisted8_plan``:
+        ct <- ct + sum_{0<k<radix} rot(ct, k s), each step hoisted
+        (``rotsum_step``).  Five steps instead of fifteen at N = 2^16; the
+        same sum as ``rotsum`` up to the key-switching noise."""
         ct = a
-        for s, rad in self.rotsum_plan():
+        for s, rad in self.rotsum_hoisted8_plan():
             ct = self.rotsum_step(ct, s, rad, gkeys)
         return ct
 

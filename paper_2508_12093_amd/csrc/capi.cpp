@@ -697,6 +697,13 @@ int ppst_rotsum(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciphert
     *out = wrap(rotsum(*ctx->cx, evk->e, *a->c));
   });
 }
+int ppst_rotsum_serial(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciphertext* a,
+                       ppst_ciphertext** out) {
+  return guard([&] {
+    NEED(ctx); NEED(evk); NEED(a); NEED(out);
+    *out = wrap(rotsum_serial(*ctx->cx, evk->e, *a->c));
+  });
+}
 int ppst_rotsum_batch(ppst_context* ctx, const ppst_eval_keys* evk,
                       const ppst_ciphertext* const* cts, size_t n, ppst_ciphertext** outs) {
   return guard([&] {

@@ -1443,6 +1443,28 @@ CtPtr rotsum(Context& cx, const EvalKeys& evk, const Ciphertext& a) {
   return cur ? cur : copy_ct(cx, a);
 }
 
+CtPtr rotsum_serial(Context& cx, const EvalKeys& evk, const Ciphertext& a) {
+  if (a.npoly != 2) PPST_THROW(ST_EINVAL, "rotate-and-sum expects a degree-1 ciphertext");
+  const Params& P = cx.P();
+  CtPtr cur;
+  const Ciphertext* in = &a;
+  for (long s = 1; s < (long)P.slots(); s <<= 1) {
+    const u64 g = galois_elt(P, s);
+    const KsKey& key = galois_key(evk, g);
+    // in + Rot(in, s): the key switch of c1(X^g), whose ModDown's last pass
+    // adds c0(X^g) and the step's input
+    auto out = new_ct(cx, in->level, in->scale);
+    Buf u = ks_accumulate(cx, key, in->poly(1), 0, in->level, 1, (uint32_t)g);
+    const u64* add0 = in->poly(0);
+    const u64* acc = in->buf.p;
+    u64* op = out->buf.p;
+    ks_moddown_ptr(cx, u, in->level, 1, &add0, nullptr, &acc, &op, (uint32_t)g);
+    cur = out;
+    in = cur.get();
+  }
+  return cur ? cur : copy_ct(cx, a);
+}
+
 CtPtr level_align(Context& cx, const Ciphertext& a, int level) {
   if (level == a.level) return copy_ct(cx, a);
   if (level > a.level || level < 0) PPST_THROW(ST_ELEVEL, "cannot raise a ciphertext's level");

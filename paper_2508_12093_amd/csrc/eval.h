@@ -73,6 +73,10 @@ std::vector<CtPtr> rotate_batch(Context& cx, const EvalKeys& evk,
 // step's key switches hoisted (one ModUp of c1, the permuted inner products
 // added in the extended basis, one ModDown).
 CtPtr rotsum(Context& cx, const EvalKeys& evk, const Ciphertext& a);
+// Rotate-and-sum by its definition: log2(N/2) steps ct <- ct + Rot(ct, 2^k),
+// each a plain rotation (key switch of c1(X^g), ModDown adding c0(X^g))
+// whose last pass also adds the step's input
+CtPtr rotsum_serial(Context& cx, const EvalKeys& evk, const Ciphertext& a);
 // rotsum() of several ciphertexts of one level, each step batched
 std::vector<CtPtr> rotsum_batch(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& cts);
 // (s, radix) per step: radix 8 while three or more bits of the slot index

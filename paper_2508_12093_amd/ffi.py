@@ -125,6 +125,7 @@ _SIGS = {
     "ppst_rotate": (ctypes.c_int, [_vp, _vp, _vp, _i32, _pp]),
     "ppst_rotate_hoisted": (ctypes.c_int, [_vp, _vp, _vp, _vp, _sz, _pp]),
     "ppst_rotsum": (ctypes.c_int, [_vp, _vp, _vp, _pp]),
+    "ppst_rotsum_serial": (ctypes.c_int, [_vp, _vp, _vp, _pp]),
     "ppst_level_align": (ctypes.c_int, [_vp, _vp, _i32, _pp]),
     "ppst_lincomb": (ctypes.c_int, [_vp, _pp, _vp, _sz, _i32, _pp]),
     "ppst_mul_batch": (ctypes.c_int, [_vp, _vp, _pp, _pp, _sz, _pp]),
@@ -507,6 +508,7 @@ ppst_relin = _unary("ppst_relin")
 ppst_rescale = _unary("ppst_rescale")
 ppst_rotate = _unary("ppst_rotate")
 ppst_rotsum = _unary("ppst_rotsum")
+ppst_rotsum_serial = _unary("ppst_rotsum_serial")
 ppst_level_align = _unary("ppst_level_align")
 
 

@@ -25,8 +25,11 @@ class Pair:
         self.galois_seed = galois_seed
 
     def add_rotsum_keys(self):
+        if getattr(self, "_rotsum_keys", False):
+            return
+        self._rotsum_keys = True
         ffi.ppst_evk_add_rotsum(self.ctx, self.sk, self.galois_seed, self.evk)
-        need = [r for r in self.O.rotsum_steps() if ref.galois_element(r, self.P.N) not in self.ogk]
+        need = [r for r in self.O.rotsum_hoisted8_steps() if ref.galois_element(r, self.P.N) not in self.ogk]
         self.ogk.update(self.O.rotation_keys(self.osk, self.galois_seed, need))
 
     def encrypt(self, values, seed, level=None):

@@ -71,6 +71,6 @@ def test_rotsum_steps_match_oracle(name):
     p = ffi.ppst_params_preset(name)
     O = ref.Oracle(ref.Params.preset(name))
     got = ffi.ppst_rotsum_steps(p)
-    assert got == O.rotsum_steps()
+    assert got == O.rotsum_hoisted8_steps()
     assert len(got) == len(set(got)) and all(0 < r < O.P.slots for r in got)
-    assert O.rotsum_plan()[0] == (1, 8)
+    assert O.rotsum_hoisted8_plan()[0] == (1, 8)

@@ -200,8 +200,14 @@ def test_rotsum(pair):
     m = synth.uniform_column(11, p.P.slots, 0, 1) / p.P.slots
     ct, oct_ = p.encrypt(m, 61)
     s = ffi.ppst_rotsum(p.ctx, p.evk, ct)
-    p.same(s, p.O.rotsum(oct_, p.ogk))
+    p.same(s, p.O.rotsum_hoisted8(oct_, p.ogk))
     assert abs(p.decrypt(s)[0] - m.sum()) < 1e-3
+    # the plain definition: serial ct + Rot(ct, 2^k)
+    s2 = ffi.ppst_rotsum_serial(p.ctx, p.evk, ct)
+    p.same(s2, p.O.rotsum(oct_, p.ogk))
+    assert abs(p.decrypt(s2)[0] - m.sum()) < 1e-3
+    low, olow = ffi.ppst_level_align(p.ctx, ct, 0), p.O.level_align(oct_, 0)
+    p.same(ffi.ppst_rotsum_serial(p.ctx, p.evk, low), p.O.rotsum(olow, p.ogk))
 
 
 def test_rotsum_batch_matches_oracle(pair):
@@ -215,7 +221,7 @@ def test_rotsum_batch_matches_oracle(pair):
         m = synth.uniform_column(140 + i, p.P.slots, 0, 1) / p.P.slots
         c, o = p.encrypt(m, 140 + i)
         cts.append(c)
-        octs.append(p.O.rotsum(o, p.ogk))
+        octs.append(p.O.rotsum_hoisted8(o, p.ogk))
     for n in range(1, 7):
         for o, oc in zip(ffi.ppst_rotsum_batch(p.ctx, p.evk, cts[:n]), octs[:n]):
             p.same(o, oc)
@@ -372,12 +378,130 @@ def test_c2_rotsum_bit_exact(c2pair):
     p.add_rotsum_keys()
     m = synth.uniform_column(11, p.P.slots, 0, 1) / p.P.slots
     ct, oct_ = p.encrypt(m, 61)
-    ors = p.O.rotsum(oct_, p.ogk)
+    ors = p.O.rotsum_hoisted8(oct_, p.ogk)
     s = ffi.ppst_rotsum(p.ctx, p.evk, ct)
     p.same(s, ors)
     for o in ffi.ppst_rotsum_batch(p.ctx, p.evk, [ct] * 5):
         p.same(o, ors)
     assert abs(p.decrypt(s)[0] - m.sum()) < 1e-3
+
+
+def test_c2_rotsum_serial_bit_exact(c2pair):
+    """The plain rotate-and-sum at N = 2^16, level 24: fifteen serial steps
+    ct + Rot(ct, 2^k) equal the oracle's definition in every residue, and the
+    five-step hoisted form decrypts to the same sum."""
+    p = c2pair
+    print("\n[parity] c2 serial RotSum (15 rotations on both sides)", flush=True)
+    p.add_rotsum_keys()
+    m = synth.uniform_column(12, p.P.slots, 0, 1) / p.P.slots
+    ct, oct_ = p.encrypt(m, 62)
+    s = ffi.ppst_rotsum_serial(p.ctx, p.evk, ct)
+    p.same(s, p.O.rotsum(oct_, p.ogk))
+    fused = ffi.ppst_rotsum(p.ctx, p.evk, ct)
+    a, b = p.decrypt(s), p.decrypt(fused)
+    assert np.max(np.abs(a - m.sum())) < 1e-6 and np.max(np.abs(b - m.sum())) < 1e-6
+
+
+def test_c2_primitives_bit_exact(c2pair):
+    """N = 2^16, L = 24: standalone tensor, relinearisation and rescale, the
+    plaintext product, level alignment to 23, 12 and 0, and a weighted sum
+    over terms at three levels equal the oracle bit for bit."""
+    p = c2pair
+    print("\n[parity] c2 primitives", flush=True)
+    a = synth.uniform_column(21, p.P.slots, -1, 1)
+    b = synth.uniform_column(22, p.P.slots, -1, 1)
+    ca, oa = p.encrypt(a, 121)
+    cb, ob = p.encrypt(b, 122)
+    L = p.P.L
+    d = ffi.ppst_tensor(p.ctx, ca, cb)
+    od = p.O.tensor(oa, ob)
+    assert np.array_equal(ffi.ppst_ct_export(p.ctx, d), od)
+    r = ffi.ppst_relin(p.ctx, p.evk, d)
+    orl = p.O.relin(od, L, p.orlk, oa.scale * ob.scale)
+    p.same(r, orl)
+    p.same(ffi.ppst_rescale(p.ctx, r), p.O.rescale(orl))
+    p.same(ffi.ppst_rescale(p.ctx, ca), p.O.rescale(oa))
+    pt = ffi.ppst_encode(p.ctx, b, L)
+    p.same(ffi.ppst_mul_plain(p.ctx, ca, pt), p.O.mul_plain(oa, p.O.encode(b, L)))
+    lows, olows = {}, {}
+    for lvl in (23, 12, 0):
+        lows[lvl] = ffi.ppst_level_align(p.ctx, ca, lvl)
+        olows[lvl] = p.O.level_align(oa, lvl)
+        p.same(lows[lvl], olows[lvl])
+    pt12 = ffi.ppst_encode(p.ctx, b, 12)
+    p.same(ffi.ppst_mul_plain(p.ctx, lows[12], pt12),
+           p.O.mul_plain(olows[12], p.O.encode(b, 12)))
+    b23, ob23 = ffi.ppst_level_align(p.ctx, cb, 23), p.O.level_align(ob, 23)
+    terms = [ca, lows[23], cb, b23, lows[12]]
+    oterms = [oa, olows[23], ob, ob23, olows[12]]
+    cs = [0.5, -1.25, 0.125, 3.0, -0.0625]
+    got = ffi.ppst_lincomb(p.ctx, terms, cs, 11)
+    p.same(got, p.O.lincomb(oterms, cs, 11))
+    want = 0.5 * a - 1.25 * a + 0.125 * b + 3.0 * b - 0.0625 * a
+    assert np.max(np.abs(p.decrypt(got) - want)) < 1e-4
+
+
+def test_c2_hoisted_rotation_bit_exact(c2pair):
+    """Hoisted rotations by 1, 3 and 16 at N = 2^16 (one ModUp, the
+    automorphism on the extended digits) equal the oracle's hoisted form."""
+    p = c2pair
+    p.add_rotsum_keys()                      # 3 and 16 are RotSum steps
+    m = synth.uniform_column(23, p.P.slots, -1, 1)
+    ct, oct_ = p.encrypt(m, 123)
+    steps = [1, 3, 16]
+    for h, oh in zip(ffi.ppst_rotate_hoisted(p.ctx, p.evk, ct, steps),
+                     p.O.rotate_hoisted(oct_, steps, p.ogk)):
+        p.same(h, oh)
+
+
+def test_c2_batch_items_match_oracle(c2pair):
+    """One item of a batched product and one of a batched hoisted rotation at
+    N = 2^16 against the oracle itself (not against the library's own
+    one-ciphertext forms)."""
+    p = c2pair
+    p.add_rotsum_keys()
+    cts, octs = [], []
+    for i in range(3):
+        c, o = p.encrypt(synth.uniform_column(130 + i, p.P.slots, -1, 1), 130 + i)
+        cts.append(c)
+        octs.append(o)
+    outs = ffi.ppst_mul_batch(p.ctx, p.evk, cts, cts[1:] + cts[:1])
+    p.same(outs[1], p.O.mul(octs[1], octs[2], p.orlk))
+    rows = ffi.ppst_rotate_hoisted_batch(p.ctx, p.evk, cts, [2, 5])
+    p.same(rows[2][1], p.O.rotate_hoisted(octs[2], [5], p.ogk)[0])
+
+
+def test_c2_pearson_matches_oracle_digest(c2pair):
+    """The headline latency workload: Pearson on the config-2 columns
+    (x ~ Bernoulli(0.2), y lognormal with corr 0.79; Bx = 1, By = 20,
+    degree-7 Chebyshev on [1e-3, 1] + 3 Newton steps) at N = 2^16, L = 24.
+    The result ciphertext equals the oracle's residue for residue: the
+    oracle's output (about 90 s of host time) is stored as a SHA-256 digest
+    by tests/golden/make_c2_pearson.py, which calls only the oracle."""
+    import hashlib
+    import json
+    from oracle import cheb, stats64 as S
+    p = c2pair
+    with open(os.path.join(os.path.dirname(__file__), "golden", "c2_pearson.json")) as f:
+        g = json.load(f)
+    spec = g["spec"]
+    assert (p.name, 11, 12, 13) == (spec["preset"], spec["key_seed"], spec["relin_seed"],
+                                    spec["galois_seed"])
+    p.add_rotsum_keys()
+    x, y = synth.binary_cost_pair(spec["data_seed"])
+    cx = ffi.ppst_encrypt(p.ctx, p.pk, ffi.ppst_encode(p.ctx, x, p.P.L), spec["enc_seed_x"])
+    cy = ffi.ppst_encrypt(p.ctx, p.pk, ffi.ppst_encode(p.ctx, y, p.P.L), spec["enc_seed_y"])
+    base = cheb.invsqrt_coeffs(spec["a"], spec["b"], spec["degree"], 1.0)
+    cfg = ffi.ppst_invsqrt_cfg_default(coeffs=base)
+    print("\n[parity] c2 Pearson vs the oracle's digest", flush=True)
+    out = ffi.ppst_stat_pearson(p.ctx, p.evk, [cx], [cy], len(x), spec["Bx"], spec["By"], cfg)
+    words = ffi.ppst_ct_export(p.ctx, out)
+    assert out.level == g["level"] and float(out.scale).hex() == g["scale_hex"]
+    assert list(words.shape) == g["shape"]
+    assert hashlib.sha256(np.ascontiguousarray(words, dtype="<u8").tobytes()).hexdigest() == g["sha256"]
+    got = p.decrypt(out)[0]
+    assert abs(got - g["decrypted"]) < 1e-9
+    assert abs(got - S.pearson(x, y)) / abs(S.pearson(x, y)) < 1e-3
 
 
 @pytest.mark.parametrize("name", ["t1", "c2"])

@@ -14,7 +14,7 @@ def env(request):
     O = ref.Oracle(P)
     sk, pk = O.keygen(1)
     rlk = O.relin_key(sk, 2)
-    gk = O.rotation_keys(sk, 3, O.rotsum_steps() + [3, 5])
+    gk = O.rotation_keys(sk, 3, O.rotsum_hoisted8_steps() + [3, 5])
     return P, O, sk, pk, rlk, gk
 
 
@@ -140,7 +140,7 @@ def test_rotations(env):
     assert np.max(np.abs(O.decrypt(h[1], sk) - np.roll(m, -5))) < tol
     s = O.rotsum(ct, gk)
     assert np.max(np.abs(O.decrypt(s, sk) - m.sum())) < m.sum() * 1e-4
-    assert 9 not in O.rotsum_steps() + [3, 5]
+    assert 9 not in O.rotsum_hoisted8_steps() + [3, 5]
     with pytest.raises(KeyError):
         O.rotate(ct, 9, gk)
 
@@ -152,13 +152,13 @@ def test_rotsum_plan_covers_every_slot_once(env):
     P, O = env[0], env[1]
     poly = np.zeros(P.slots, dtype=np.int64)
     poly[0] = 1
-    for s, rad in O.rotsum_plan():
+    for s, rad in O.rotsum_hoisted8_plan():
         nxt = np.zeros_like(poly)
         for k in range(rad):
             nxt += np.roll(poly, k * s)
         poly = nxt
     assert np.array_equal(poly, np.ones(P.slots, dtype=np.int64))
-    assert sorted(set(O.rotsum_steps())) == sorted(O.rotsum_steps())
+    assert sorted(set(O.rotsum_hoisted8_steps())) == sorted(O.rotsum_hoisted8_steps())
 
 
 def test_rotsum_step_sums_rotations(env):
@@ -182,3 +182,40 @@ def test_rotsum_step_sums_rotations(env):
     eight = O.rotsum_step(ct, 1, 8, gk)       # seven keys in one extended sum
     want8 = sum(np.roll(m, -k) for k in range(8))
     assert np.max(np.abs(O.decrypt(eight, sk) - want8)) < 8 * tol
+
+
+def test_rotsum_serial_definition_and_hoisted8_pin(env):
+    """The plain rotate-and-sum (log2(N/2) steps ct <- ct + Rot(ct, 2^k);
+    the slot sums of Eq. 2) leaves the sum of all slots in every slot, and
+    the hoisted radix-8 form the circuits use decrypts to the same integer
+    polynomial up to the key-switching rounding.
+
+    Bound: a rounding ModDown of u returns round(u/P) - v with 0 <= v < K
+    (fast conversion without correction), so one key switch adds at most
+    B = (K + 1/2)(1 + ||s||_1) + 1 to a decrypted coefficient (the key's
+    own error times ModUp(d)/P is below 1 at these parameters).  Each
+    serial step doubles what came before, so its total is below slots * B;
+    the radix-8 form adds one ModDown per step and stays below that too.
+    The two decryptions therefore differ by at most 2 slots B, while one
+    dropped rotation term would move a coefficient by about Delta/2."""
+    P, O, sk, pk, rlk, gk = env
+    m = np.random.default_rng(7).uniform(0, 1, P.slots)
+    ct = enc(O, pk, m, 40)
+    serial = O.rotsum(ct, gk)
+    fused = O.rotsum_hoisted8(ct, gk)
+    assert len(O.rotsum_serial_steps()) == P.slots.bit_length() - 1
+    assert set(O.rotsum_serial_steps()) <= set(O.rotsum_hoisted8_steps())
+    cs = O.decrypt_coeffs(serial, sk)
+    cf = O.decrypt_coeffs(fused, sk)
+    s1 = int(np.abs(sk.s_coef.astype(np.int64)).sum())
+    B = (P.K + 0.5) * (1 + s1) + 1
+    diff = np.abs(cs - cf)
+    assert diff.max() <= 2 * P.slots * B
+    assert diff.max() < P.scale[P.L] / 64
+    total = m.sum()
+    for c in (serial, fused):
+        got = O.decrypt(c, sk)
+        assert np.max(np.abs(got - total)) < 2 * P.slots * B / P.scale[P.L] + 1e-9 * total
+    # the first serial step alone: ct + Rot(ct, 1) holds m_j + m_{j+1}
+    one = O.add(ct, O.rotate(ct, 1, gk))
+    assert np.max(np.abs(O.decrypt(one, sk) - (m + np.roll(m, -1)))) < 64 * fresh_std(P)

@@ -136,7 +136,7 @@ def t2():
     O = ref.Oracle(P)
     sk, pk = O.keygen(101)
     rlk = O.relin_key(sk, 102)
-    gk = O.rotation_keys(sk, 103, O.rotsum_steps())
+    gk = O.rotation_keys(sk, 103, O.rotsum_hoisted8_steps())
     return P, O, sk, pk, C.Circuits(C.EncEval(O, rlk, gk))
 
 
@@ -198,7 +198,7 @@ def test_config1_mean_variance():
     O = ref.Oracle(P)
     sk, pk = O.keygen(1)
     rlk = O.relin_key(sk, 101)
-    gk = O.rotation_keys(sk, 102, O.rotsum_steps())
+    gk = O.rotation_keys(sk, 102, O.rotsum_hoisted8_steps())
     x = synth.uniform_column(1, P.slots)
     ct = O.encrypt(O.encode(x), pk, 201)
     cc = C.Circuits(C.EncEval(O, rlk, gk))
