@@ -399,7 +399,13 @@ def test_c2_rotsum_serial_bit_exact(c2pair):
     p.same(s, p.O.rotsum(oct_, p.ogk))
     fused = ffi.ppst_rotsum(p.ctx, p.evk, ct)
     a, b = p.decrypt(s), p.decrypt(fused)
-    assert np.max(np.abs(a - m.sum())) < 1e-6 and np.max(np.abs(b - m.sum())) < 1e-6
+    # every slot sums the encryption noise of all N/2 slots: fresh noise has
+    # std N sigma sqrt(2/3) / Delta = 1.6e-7 per slot, so the sum's std is
+    # sqrt(32768) x 1.6e-7 = 2.9e-5; 3e-4 is about ten of them
+    ea, eb, ab = (float(np.max(np.abs(a - m.sum()))), float(np.max(np.abs(b - m.sum()))),
+                  float(np.max(np.abs(a - b))))
+    print("serial %.2e, hoisted %.2e, between %.2e" % (ea, eb, ab), flush=True)
+    assert ea < 3e-4 and eb < 3e-4 and ab < 3e-4
 
 
 def test_c2_primitives_bit_exact(c2pair):
