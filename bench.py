@@ -27,14 +27,21 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# ALU ceiling of the NTT: 256 CUs x 64 lanes x 2.4 GHz = 39.32 T VALU lane-slots/s;
-# 32-bit multiplies issue at half that rate (19.66 T/s); one Shoup modular
-# multiplication (the twiddle product of a butterfly) needs 10 of them.
-BFLY_PEAK_G = 256 * 64 * 2.4e9 / 2 / 10 / 1e9
-# HBM bytes per launch pair from FETCH_SIZE + WRITE_SIZE counters (rocprofv3
-# --pmc, one counter per run), scaled by the same counters on a plain copy of
-# known size; null when the kernels change after the counters were taken.
-NTT_TRAFFIC_BYTES = 79906202   # profiles/ntt_fwd_c2_25limbs_traffic.md
+# VALU ceiling: 256 CUs x 64 lanes x 2.4 GHz = 39.32 T lane-operations/s
+# (FP64 fused multiply-add issues at that full rate: 78.6 TFLOP/s).
+VALU_PEAK = 256 * 64 * 2.4e9
+# One forward butterfly on the FP64 path (every 40-bit prime of the chain):
+# 6 operations for the exact product y w - k q (mul, fma, mul, rint, fma,
+# add), 3 for the two outputs (a + q, a + q + r, a + q - r) and 4 for the lazy
+# reduction of x into [0, 2q) (subtract, compare, two 32-bit selects).
+OPS_PER_BFLY = 13
+BFLY_PEAK_G = VALU_PEAK / OPS_PER_BFLY / 1e9
+# HBM bytes per 25-limb forward NTT from FETCH_SIZE + WRITE_SIZE counters
+# (rocprofv3 --pmc, one counter per run), scaled by the same counters on a
+# plain copy of known size.  The figure belongs to the NTT source it was taken
+# with (its SHA-256 below); for any other source the traffic is reported as
+# null.
+NTT_TRAFFIC = {"bytes": 79906202, "source_sha256": "see profiles"}
 
 
 def parse():
@@ -44,7 +51,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--pearson-runs", type=int, default=30)
-    ap.add_argument("--cpu-sample", type=int, default=60, help="oracle HMults timed on the host")
+    ap.add_argument("--cpu-runs", type=int, default=5,
+                    help="repetitions per operation of the oracle timed on the host")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="short run for profiling")
     ap.add_argument("--kernels-only", action="store_true",
@@ -278,6 +286,7 @@ def main():
         serving = serving_bench(ctx, pk, sk, evk, args.serving_queries, loads,
                                 nslots=args.serving_slots)
     rf = measure_ntt(ctx, stream, reps=10 if args.quick else 50)
+    peaks = measure_peaks(stream)
 
     out = {
         "metric": "HMult+relin/sec and rotations/sec at N=2^16; p50/p99 encrypted-Pearson latency",
@@ -314,13 +323,14 @@ def main():
         "exp1_invsqrt_p50_ms": round(e1_p50, 3),
         "exp1_invsqrt_mre": e1_mre,
         "roofline": rf,
+        "peaks": peaks,
     }
     if exp2 is not None:
         out["exp2"] = exp2
     if serving is not None:
         out["serving"] = serving
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_runs)
     print(json.dumps(out), flush=True)
 
 
@@ -511,10 +521,22 @@ def serving_bench(ctx, pk, sk, evk, nq: int, loads, seed: int = 4, nslots: int =
 NTT_COL_VARIANT, NTT_ROW_VARIANT = 5, 6      # col:E3,SB16,D / row:E3,SB4,D
 
 
+def _ntt_source_sha():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2508_12093_amd", "csrc", "ntt.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
 def measure_ntt(ctx, stream, reps: int):
     """Forward NTT (column pass + row pass) of one 25-limb polynomial at
     N = 2^16, timed with HIP events on the library's stream.  Leaves the
-    context on the fixed plan."""
+    context on the fixed plan.
+
+    Algorithmic work per launch pair: 25 (N/2) log2 N butterflies and
+    25 MiB of HBM traffic (one read and one write of each 512 KiB limb).
+    Floors: 13 FP64 VALU operations per butterfly at 39.3 T/s, and 25 MiB at
+    8 TB/s; the larger floor names the bound."""
     import numpy as np
     import torch
 
@@ -544,22 +566,82 @@ def measure_ntt(ctx, stream, reps: int):
     torch.cuda.synchronize()
     sec = e0.elapsed_time(e1) * 1e-3 / (2 * reps)           # per 25-limb forward NTT
     butterflies = limbs * (N // 2) * info.logN               # N/2 log2 N per limb
-    alg_bytes = 2 * 2 * limbs * N * 8                        # each pass reads and writes every limb
+    alg_bytes = 2 * limbs * N * 8                            # read + write each limb once
     g_bfly = butterflies / sec / 1e9
-    log("forward NTT (25 limbs, 2 passes): %.1f us, %.1f G butterflies/s, %.0f GB/s algorithmic" % (
-        sec * 1e6, g_bfly, alg_bytes / sec / 1e9))
+    alu_floor = butterflies / (BFLY_PEAK_G * 1e9)
+    hbm_floor = alg_bytes / (HBM_PEAK_GBS * 1e9)
+    stale = NTT_TRAFFIC["source_sha256"] != _ntt_source_sha()
+    log("forward NTT (25 limbs, 2 passes): %.2f us, %.1f G butterflies/s (%.3f of %.0f), "
+        "%.0f GB/s of algorithmic bytes (%.3f of HBM)" % (
+            sec * 1e6, g_bfly, g_bfly / BFLY_PEAK_G, BFLY_PEAK_G, alg_bytes / sec / 1e9,
+            alg_bytes / sec / 1e9 / HBM_PEAK_GBS))
     return {
         "kernel": "forward NTT of 25 limbs at N=2^16 (column pass + row pass; %s)" % plan.strip(),
-        "bound": "alu",
+        "bound": "alu" if alu_floor >= hbm_floor else "hbm",
         "achieved": round(g_bfly, 1),
         "peak": round(BFLY_PEAK_G, 1),
         "unit": "G butterflies/s",
         "frac": round(g_bfly / BFLY_PEAK_G, 4),
-        "traffic": NTT_TRAFFIC_BYTES,
-        "us_per_launch_pair": round(sec * 1e6, 2),
+        "traffic": None if stale else NTT_TRAFFIC["bytes"],
+        "us_per_launch_pair": round(sec * 1e6, 3),
+        "butterflies_per_launch_pair": butterflies,
+        "alg_bytes_per_launch_pair": alg_bytes,
+        "alu_floor_us": round(alu_floor * 1e6, 3),
+        "hbm_floor_us": round(hbm_floor * 1e6, 3),
         "hbm_algorithmic_GBs": round(alg_bytes / sec / 1e9, 1),
         "hbm_frac": round(alg_bytes / sec / 1e9 / HBM_PEAK_GBS, 4),
     }
+
+
+def measure_peaks(stream):
+    """Measured ceilings beside the published ones (libppstat_probe.so):
+    a 1 GiB device copy, and eight independent chains per work-item of FP64
+    fused multiply-adds and of v_mad_u64_u32, over 2^19 work-items (eight
+    waves per SIMD).  HIP events on `stream`."""
+    import torch
+
+    from paper_2508_12093_amd import ffi
+
+    pl = ffi.probe_lib()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 8, dtype=torch.int64, device="cuda")
+    dst = torch.empty_like(src)
+    threads, iters = 1 << 19, 2048
+    outd = torch.empty(threads, dtype=torch.float64, device="cuda")
+    outi = torch.empty(threads, dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+
+    def timed(launch, reps):
+        launch()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            launch()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / reps
+
+    def chk(rc):
+        if rc != 0:
+            raise RuntimeError("probe launch failed (%d)" % rc)
+
+    t_copy = timed(lambda: chk(pl.ppst_probe_copy(ctypes.c_void_p(src.data_ptr()),
+                                                  ctypes.c_void_p(dst.data_ptr()), nbytes, sp)), 10)
+    t_fma = timed(lambda: chk(pl.ppst_probe_fma_f64(ctypes.c_void_p(outd.data_ptr()), threads,
+                                                    iters, sp)), 5)
+    t_mad = timed(lambda: chk(pl.ppst_probe_mad_u64_u32(ctypes.c_void_p(outi.data_ptr()), threads,
+                                                        iters, sp)), 5)
+    ops = 8 * threads * iters
+    out = {"copy_GBs": round(2 * nbytes / t_copy / 1e9, 1),
+           "fp64_fma_T_per_s": round(ops / t_fma / 1e12, 3),
+           "mad_u64_u32_T_per_s": round(ops / t_mad / 1e12, 3),
+           "valu_peak_T_per_s": round(VALU_PEAK / 1e12, 3),
+           "hbm_peak_GBs": HBM_PEAK_GBS}
+    log("peaks: copy %.0f GB/s, FP64 FMA %.2f T/s, v_mad_u64_u32 %.2f T/s (VALU slots %.2f T/s)" % (
+        out["copy_GBs"], out["fp64_fma_T_per_s"], out["mad_u64_u32_T_per_s"], VALU_PEAK / 1e12))
+    del src, dst, outd, outi
+    return out
 
 
 def kernels_only(args):
@@ -582,27 +664,61 @@ def kernels_only(args):
     print(json.dumps({"roofline": rf, "copy_bytes_each_way": n * 8}), flush=True)
 
 
-def cpu_baseline(count: int):
-    """The CPU reference (plain C oracle) timed on the host: `count` HMults at
-    N = 2^16, level 24."""
-    import numpy as np
+def _cpu_model():
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, ValueError):
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(runs: int):
+    """The CPU reference (the plain C oracle, built on this host at -O2
+    -march=native) timed on the host at N = 2^16, level 24: medians of `runs`
+    repetitions of a 25-limb NTT, an HMult+relin+rescale and a rotation, at
+    one OpenMP thread and at every core of the process's CPU share, each in a
+    child process (oracle/timing.py)."""
+    import subprocess
+    import tempfile
 
     from oracle import ref
-    from paper_2508_12093_amd import synth
 
-    P = ref.Params.preset("c2")
-    O = ref.Oracle(P)
-    sk, pk = O.keygen(1)
-    rlk = O.relin_key(sk, 2)
-    a = O.encrypt(O.encode(synth.uniform_column(1, P.slots, -1, 1)), pk, 3)
-    b = O.encrypt(O.encode(synth.uniform_column(2, P.slots, -1, 1)), pk, 4)
-    t = time.perf_counter()
-    for _ in range(count):
-        O.mul(a, b, rlk)
-    dt = time.perf_counter() - t
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": round(count / dt, 4), "unit": "HMult+relin/s", "cores": cores, "kind": "oracle",
-            "sample": "%d HMult+relin+rescale at N=2^16, level 24 (%.1f s)" % (count, dt)}
+    tmp = tempfile.mkdtemp(prefix="ppst_oracle_")
+    so = ref.build_native(os.path.join(tmp, "libckks_ref_native.so"))
+    share = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    cores = int(os.environ.get("OMP_NUM_THREADS", share))
+    legs = {}
+    for threads in sorted({1, cores}):
+        env = dict(os.environ, OMP_NUM_THREADS=str(threads), PPST_ORACLE_SO=so)
+        r = subprocess.run([sys.executable, os.path.join(ROOT, "oracle", "timing.py"), "--runs", str(runs)],
+                           env=env, capture_output=True, text=True, timeout=600)
+        if r.returncode != 0:
+            raise RuntimeError("oracle timing failed:\n" + r.stderr[-2000:])
+        legs[threads] = json.loads(r.stdout.strip().splitlines()[-1])
+        log("oracle at %d thread(s): NTT(25 limbs) %.1f ms, HMult %.0f ms, rotation %.0f ms" % (
+            threads, legs[threads]["ntt25_ms"], legs[threads]["hmult_ms"], legs[threads]["rotation_ms"]))
+    top, one = legs[cores], legs[1]
+    return {"value": top["hmult_per_s"], "unit": "HMult+relin/s", "cores": cores, "kind": "oracle",
+            "sample": "median of %d runs each of a 25-limb NTT, an HMult+relin+rescale and a rotation "
+                      "at N=2^16, level 24 (%.1f s timed at %d threads, %.1f s at 1)" % (
+                          runs, top["timed_s"], cores, one["timed_s"]),
+            "cpu_model": _cpu_model(), "build": "gcc -O2 -march=native -fopenmp",
+            "per_op_ms": {"ntt25": top["ntt25_ms"], "hmult": top["hmult_ms"], "rotation": top["rotation_ms"]},
+            "rotations_per_s": top["rotations_per_s"],
+            "single_thread": {"hmult_per_s": one["hmult_per_s"], "rotations_per_s": one["rotations_per_s"],
+                              "per_op_ms": {"ntt25": one["ntt25_ms"], "hmult": one["hmult_ms"],
+                                            "rotation": one["rotation_ms"]}}}
 
 
 if __name__ == "__main__":

@@ -96,6 +96,14 @@ int ppst_encode_coeffs(const ppst_params* params, const double* values, size_t n
  * out == NULL and cap == 0 only the count is returned, otherwise cap must be
  * at least that count (EINVAL) */
 int ppst_rotsum_steps(const ppst_params* params, int32_t* out, size_t cap, size_t* n);
+/* Host only: the Chebyshev coefficients c_0..c_degree (first kind, in
+ * t = (2v - a - b) / (b - a)) of 1/sqrt(B' v) on [a, b], interpolated at the
+ * first-kind nodes cos(pi (j + 1/2) / (degree + 1)): the initial value of
+ * CryptoInvSqrt (Sec. 4.1 Alg. 3, Sec. 4.2 Eq. 1 and Eq. 3 with a = 0, b = 2)
+ * that the statistics use when their configuration brings no coefficients.
+ * EDOMAIN unless 0 <= a < b, B' > 0 and 1 <= degree <= 511; EINVAL when cap <
+ * degree + 1. */
+int ppst_chebyshev_invsqrt(double a, double b, int32_t degree, double Bp, double* out, size_t cap);
 /* SplitMix64 stream state for (seed, purpose, limb), host only */
 uint64_t ppst_stream_key(uint64_t seed, uint64_t purpose, uint64_t limb);
 
@@ -157,7 +165,20 @@ int ppst_evk_add_rotsum(ppst_context* ctx, const ppst_secret_key* sk, uint64_t s
  * Layout [dnum][2][nprimes][N] (b, a per digit, NTT form). */
 int ppst_evk_export(ppst_context* ctx, const ppst_eval_keys* evk, uint64_t galois, uint64_t* host,
                     size_t cap_words);
+/* The server side of the paper's roles (Sec. 4: the client sends the
+ * evaluation keys with its ciphertexts): a key in ppst_evk_export's layout,
+ * `words` = dnum * 2 * nprimes * N, added to `evk` as the relinearisation key
+ * (galois = 0) or the Galois key of element `galois` (odd, 1 < g < 2N),
+ * replacing one already there.  The words are copied (the host buffer is not
+ * kept); every residue must be below its prime (EINVAL otherwise, nothing
+ * changed).  Synchronises. */
+int ppst_evk_import(ppst_context* ctx, ppst_eval_keys* evk, uint64_t galois, const uint64_t* host,
+                    size_t words);
+/* [2][L+1][N] (b, a over q_0..q_L, NTT form) */
 int ppst_pk_export(ppst_context* ctx, const ppst_public_key* pk, uint64_t* host, size_t cap_words);
+/* a public key from ppst_pk_export's words (`words` = 2 (L+1) N, each below
+ * its prime, else EINVAL); the caller owns *out.  Synchronises. */
+int ppst_pk_import(ppst_context* ctx, const uint64_t* host, size_t words, ppst_public_key** out);
 /* s in NTT form over every prime, [nprimes][N] */
 int ppst_sk_export(ppst_context* ctx, const ppst_secret_key* sk, uint64_t* host, size_t cap_words);
 
@@ -171,8 +192,16 @@ int ppst_plaintext_from_coeffs(ppst_context* ctx, const int64_t* coeffs, int32_t
                                double scale, ppst_plaintext** out);
 /* integer coefficients of an encoded plaintext (N values) */
 int ppst_plaintext_coeffs(const ppst_plaintext* pt, int64_t* out, size_t cap);
+/* [level+1][N] residues, NTT form */
 int ppst_plaintext_export(ppst_context* ctx, const ppst_plaintext* pt, uint64_t* host,
                           size_t cap_words);
+/* a plaintext from ppst_plaintext_export's words at (level, scale): usable
+ * wherever an encoded one is (ppst_mul_plain, ppst_decode); it carries no
+ * integer coefficients (ppst_plaintext_coeffs gives EINVAL).  Residues must be
+ * below their primes and scale positive (EINVAL), level in 0..L (ELEVEL).
+ * Synchronises; the caller owns *out. */
+int ppst_plaintext_import(ppst_context* ctx, const uint64_t* host, int32_t level, double scale,
+                          ppst_plaintext** out);
 /* decode slots (the centred lift uses q_0, or q_0 q_1 above level 0) */
 int ppst_decode(ppst_context* ctx, const ppst_plaintext* pt, double* out, size_t n);
 int ppst_plaintext_destroy(ppst_plaintext* pt);

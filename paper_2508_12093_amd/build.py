@@ -1,7 +1,9 @@
 """Build libppstat.so (HIP for gfx950) in-tree.
 
-Every source under csrc/ is compiled by hipcc for --offload-arch=gfx950 and
-linked into paper_2508_12093_amd/libppstat.so.  Objects go to _build/.
+Every library source under csrc/ is compiled by hipcc for
+--offload-arch=gfx950 and linked into paper_2508_12093_amd/libppstat.so; the
+peak-rate microbenchmarks (csrc/probe.hip) go into libppstat_probe.so.
+Objects go to _build/.
 """
 from __future__ import annotations
 
@@ -19,6 +21,10 @@ BUILD = os.path.join(ROOT, "_build")
 SOURCES = ["host_math.cpp", "eval.cpp", "stats.cpp", "server.cpp", "capi.cpp",
            "ntt.hip", "kernels.hip"]
 
+# peak-rate microbenchmarks for the roofline figures: a library of their own
+PROBE_SOURCE = "probe.hip"
+PROBE_OUT = os.path.join(HERE, "libppstat_probe.so")
+
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -34,19 +40,25 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
-    jobs = min(len(SOURCES), int(os.environ.get("MAX_JOBS", "8")))
-    with ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = OUT + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
+def _link(objs, out, extra=()):
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + list(objs) + list(extra)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s%s" % (r.stdout, r.stderr))
-    os.replace(tmp, OUT)
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    srcs = SOURCES + [PROBE_SOURCE]
+    jobs = min(len(srcs), int(os.environ.get("MAX_JOBS", "8")))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(_compile, srcs))
+    _link(objs[:-1], OUT, ["-lpthread"])
+    _link(objs[-1:], PROBE_OUT)
     if verbose:
-        print("built", OUT)
+        print("built", OUT, "and", PROBE_OUT)
     return OUT
 
 

@@ -1,62 +1,16 @@
 // capi.cpp -- the extern "C" boundary declared in include/ppstat.h.
-#include "../../include/ppstat.h"
-
-#include <new>
-
-#include "server.h"
+#include "capi.h"
 
 using namespace ppst;
 
-struct ppst_context {
-  std::unique_ptr<Context> cx;
-};
-struct ppst_secret_key {
-  std::unique_ptr<SecretKey> k;
-};
-struct ppst_public_key {
-  std::unique_ptr<PublicKey> k;
-};
-struct ppst_eval_keys {
-  EvalKeys e;
-};
-struct ppst_plaintext {
-  PtPtr p;
-};
-struct ppst_ciphertext {
-  CtPtr c;
-};
-struct ppst_server {
-  std::unique_ptr<Server> s;
-};
-struct ppst_graph {
-  std::unique_ptr<Graph> g;
-};
+namespace ppst {
+std::string& last_error() {
+  thread_local std::string msg;
+  return msg;
+}
+}  // namespace ppst
 
 namespace {
-
-thread_local std::string g_err;
-
-template <class F>
-int guard(F&& f) {
-  try {
-    f();
-    return PPST_OK;
-  } catch (const Error& e) {
-    g_err = e.what();
-    return e.code;
-  } catch (const std::bad_alloc&) {
-    g_err = "host allocation failed";
-    return PPST_ENOMEM;
-  } catch (const std::exception& e) {
-    g_err = e.what();
-    return PPST_EINVAL;
-  }
-}
-
-#define NEED(p)                                                   \
-  do {                                                            \
-    if (!(p)) PPST_THROW(ST_EINVAL, "null argument: " #p);          \
-  } while (0)
 
 ppst_ciphertext* wrap(CtPtr c) { return new ppst_ciphertext{std::move(c)}; }
 
@@ -101,7 +55,7 @@ void copy_out(Context& cx, const u64* dev, size_t words, uint64_t* host, size_t 
 
 extern "C" {
 
-const char* ppst_last_error(void) { return g_err.c_str(); }
+const char* ppst_last_error(void) { return last_error().c_str(); }
 
 int ppst_params_preset(const char* name, ppst_params* out) {
   return guard([&] {
@@ -143,6 +97,17 @@ int ppst_dg_thresholds(uint64_t* out, size_t cap) {
     u64 t[kDgMax];
     dg_thresholds(t);
     for (int i = 0; i < kDgMax; ++i) out[i] = t[i];
+  });
+}
+
+int ppst_chebyshev_invsqrt(double a, double b, int32_t degree, double Bp, double* out, size_t cap) {
+  return guard([&] {
+    NEED(out);
+    if (!(a >= 0.0 && b > a && Bp > 0.0)) PPST_THROW(ST_EDOMAIN, "need 0 <= a < b and B' > 0");
+    if (degree < 1 || degree > 511) PPST_THROW(ST_EDOMAIN, "degree must be in 1..511");
+    if (cap < (size_t)degree + 1) PPST_THROW(ST_EINVAL, "buffer too small");
+    const std::vector<double> c = chebyshev_invsqrt(a, b, degree, Bp);
+    std::copy(c.begin(), c.end(), out);
   });
 }
 
@@ -392,6 +357,56 @@ int ppst_evk_export(ppst_context* ctx, const ppst_eval_keys* evk, uint64_t galoi
   });
 }
 
+int ppst_evk_import(ppst_context* ctx, ppst_eval_keys* evk, uint64_t galois, const uint64_t* host,
+                    size_t words) {
+  return guard([&] {
+    NEED(ctx);
+    NOT_RECORDING(ctx);
+    NEED(evk);
+    NEED(host);
+    Context& cx = *ctx->cx;
+    const Params& P = cx.P();
+    const size_t np = (size_t)P.nprimes, N = (size_t)P.N, want = (size_t)P.dnum * 2 * np * N;
+    if (words != want)
+      PPST_THROW(ST_EINVAL, "a key switching key has " + std::to_string(want) + " words");
+    if (galois != 0 && (galois >= 2 * N || !(galois & 1) || galois == 1))
+      PPST_THROW(ST_EINVAL, "not a rotation's Galois element (odd, 1 < g < 2N)");
+    for (size_t r = 0; r < (size_t)P.dnum * 2; ++r)
+      for (size_t t = 0; t < np; ++t) {
+        const uint64_t* row = host + (r * np + t) * N;
+        for (size_t k = 0; k < N; ++k)
+          if (row[k] >= P.q[t]) PPST_THROW(ST_EINVAL, "residue not reduced modulo its prime");
+      }
+    auto key = std::make_shared<KsKey>();
+    key->k = Buf(cx.sh->const_pool, want * 8);
+    HIP_CHECK(hipMemcpyAsync(key->k.p, host, want * 8, hipMemcpyHostToDevice, cx.stream));
+    HIP_CHECK(hipStreamSynchronize(cx.stream));
+    if (galois == 0) evk->e.relin = key;
+    else evk->e.galois[galois] = key;
+  });
+}
+
+int ppst_pk_import(ppst_context* ctx, const uint64_t* host, size_t words, ppst_public_key** out) {
+  return guard([&] {
+    NEED(ctx);
+    NOT_RECORDING(ctx);
+    NEED(host);
+    NEED(out);
+    Context& cx = *ctx->cx;
+    const Params& P = cx.P();
+    const size_t N = (size_t)P.N, nl = (size_t)P.L + 1, want = 2 * nl * N;
+    if (words != want) PPST_THROW(ST_EINVAL, "a public key has " + std::to_string(want) + " words");
+    for (size_t r = 0; r < 2 * nl; ++r)
+      for (size_t k = 0; k < N; ++k)
+        if (host[r * N + k] >= P.q[r % nl]) PPST_THROW(ST_EINVAL, "residue not reduced modulo its prime");
+    auto pk = std::make_unique<PublicKey>();
+    pk->pk = Buf(cx.sh->const_pool, want * 8);
+    HIP_CHECK(hipMemcpyAsync(pk->pk.p, host, want * 8, hipMemcpyHostToDevice, cx.stream));
+    HIP_CHECK(hipStreamSynchronize(cx.stream));
+    *out = new ppst_public_key{std::move(pk)};
+  });
+}
+
 int ppst_pk_export(ppst_context* ctx, const ppst_public_key* pk, uint64_t* host, size_t cap_words) {
   return guard([&] {
     NEED(ctx);
@@ -452,6 +467,31 @@ int ppst_plaintext_export(ppst_context* ctx, const ppst_plaintext* pt, uint64_t*
     NOT_RECORDING(ctx);
     NEED(pt);
     copy_out(*ctx->cx, pt->p->buf.p, (size_t)(pt->p->level + 1) * ctx->cx->P().N, host, cap_words);
+  });
+}
+
+int ppst_plaintext_import(ppst_context* ctx, const uint64_t* host, int32_t level, double scale,
+                          ppst_plaintext** out) {
+  return guard([&] {
+    NEED(ctx);
+    NOT_RECORDING(ctx);
+    NEED(host);
+    NEED(out);
+    Context& cx = *ctx->cx;
+    const Params& P = cx.P();
+    if (level < 0 || level > P.L) PPST_THROW(ST_ELEVEL, "level out of range");
+    if (!(scale > 0.0)) PPST_THROW(ST_EINVAL, "a plaintext needs a positive scale");
+    const size_t N = (size_t)P.N, words = (size_t)(level + 1) * N;
+    for (int i = 0; i <= level; ++i)
+      for (size_t k = 0; k < N; ++k)
+        if (host[(size_t)i * N + k] >= P.q[i]) PPST_THROW(ST_EINVAL, "residue not reduced modulo its prime");
+    auto pt = std::make_shared<Plaintext>();
+    pt->level = level;
+    pt->scale = scale;
+    pt->buf = Buf(cx.pool, words * 8);
+    HIP_CHECK(hipMemcpyAsync(pt->buf.p, host, words * 8, hipMemcpyHostToDevice, cx.stream));
+    HIP_CHECK(hipStreamSynchronize(cx.stream));
+    *out = new ppst_plaintext{pt};
   });
 }
 
@@ -969,7 +1009,7 @@ int ppst_server_wait(ppst_server* srv, uint64_t ticket, ppst_ciphertext** out,
     QueryState st;
     status = srv->s->wait(ticket, &res, &st);
     copy_stats(st, stats);
-    if (status != ST_OK) g_err = st.error;
+    if (status != ST_OK) last_error() = st.error;
     if (out) *out = (status == ST_OK && !res.empty()) ? wrap(res[0]) : nullptr;
   });
   return rc != PPST_OK ? rc : status;
@@ -995,7 +1035,7 @@ int ppst_server_wait_all(ppst_server* srv, uint64_t ticket, ppst_ciphertext** ou
     copy_stats(st, stats);
     *n_out = 0;
     if (status != ST_OK) {
-      g_err = st.error;
+      last_error() = st.error;
       return;
     }
     for (size_t i = 0; i < res.size(); ++i) outs[i] = wrap(res[i]);

@@ -1,0 +1,64 @@
+// capi.h -- what the files of the C boundary share: the handle types behind
+// include/ppstat.h's opaque structs and the exception-to-status guard.
+#pragma once
+
+#include "../../include/ppstat.h"
+
+#include <new>
+
+#include "server.h"
+
+struct ppst_context {
+  std::unique_ptr<ppst::Context> cx;
+};
+struct ppst_secret_key {
+  std::unique_ptr<ppst::SecretKey> k;
+};
+struct ppst_public_key {
+  std::unique_ptr<ppst::PublicKey> k;
+};
+struct ppst_eval_keys {
+  ppst::EvalKeys e;
+};
+struct ppst_plaintext {
+  ppst::PtPtr p;
+};
+struct ppst_ciphertext {
+  ppst::CtPtr c;
+};
+struct ppst_server {
+  std::unique_ptr<ppst::Server> s;
+};
+struct ppst_graph {
+  std::unique_ptr<ppst::Graph> g;
+};
+
+namespace ppst {
+
+// the calling thread's last failure message (ppst_last_error)
+std::string& last_error();
+
+// runs f, turning a thrown Error into its status code and message
+template <class F>
+int guard(F&& f) {
+  try {
+    f();
+    return PPST_OK;
+  } catch (const Error& e) {
+    last_error() = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    last_error() = "host allocation failed";
+    return PPST_ENOMEM;
+  } catch (const std::exception& e) {
+    last_error() = e.what();
+    return PPST_EINVAL;
+  }
+}
+
+#define NEED(p)                                                   \
+  do {                                                            \
+    if (!(p)) PPST_THROW(ST_EINVAL, "null argument: " #p);          \
+  } while (0)
+
+}  // namespace ppst

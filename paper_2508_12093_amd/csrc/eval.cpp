@@ -507,19 +507,18 @@ void ntt_ext_digits(Context& cx, u64* ext, int level, int nbatch) {
 // With prep_d (products), limb q_l of u also receives (P mod q_l) times the
 // tensor's d0, d1 (prep_d: [nbatch][3][nl][N] at stride sd), the first step
 // of the fused ModDown + rescale.
-Buf ks_accumulate(Context& cx, const KsKey& key, const u64* d, size_t sd, int level, int nbatch,
-                  uint32_t g = 0, const u64* prep_d = nullptr) {
+// The scratch is caller memory: x ([nbatch][l+1][N], free again once this
+// returns), ext ([nbatch][beta][ne][N]) and the result u.
+void ks_accumulate_into(Context& cx, const KsKey& key, const u64* d, size_t sd, int level,
+                        int nbatch, uint32_t g, const u64* prep_d, u64* x, u64* ext, u64* u) {
   const Params& P = cx.P();
   const Shared& sh = *cx.sh;
   const int N = P.N, nl = level + 1, K = P.K, ne = nl + K, beta = P.beta(level);
   const size_t sx = (size_t)nl * N, sext = (size_t)beta * ne * N, su = 2 * (size_t)ne * N;
-  Buf x = dev_buf(cx.pool, sx * nbatch);
-  Buf ext = dev_buf(cx.pool, sext * nbatch);
-  Buf u = dev_buf(cx.pool, su * nbatch);
   {
     NttLaunch L{};
     L.src = d;
-    L.dst = x.p;
+    L.dst = x;
     L.nlimbs = nl;
     L.nbatch = nbatch;
     L.batch_stride = sd;
@@ -529,11 +528,20 @@ Buf ks_accumulate(Context& cx, const KsKey& key, const u64* d, size_t sd, int le
     L.galois = g;
     ntt(sh, L, true, cx.stream);
   }
-  k_modup(sh, x.p, ext.p, level, nbatch, sx, sext, cx.stream);
-  x.release();
-  ntt_ext_digits(cx, ext.p, level, nbatch);
-  k_ks_inner(sh, d, ext.p, key.k.p, u.p, level, nbatch, sd, sext, su, g, 0, cx.stream, prep_d,
-             sd);
+  k_modup(sh, x, ext, level, nbatch, sx, sext, cx.stream);
+  ntt_ext_digits(cx, ext, level, nbatch);
+  k_ks_inner(sh, d, ext, key.k.p, u, level, nbatch, sd, sext, su, g, 0, cx.stream, prep_d, sd);
+}
+
+Buf ks_accumulate(Context& cx, const KsKey& key, const u64* d, size_t sd, int level, int nbatch,
+                  uint32_t g = 0, const u64* prep_d = nullptr) {
+  const Params& P = cx.P();
+  const int N = P.N, nl = level + 1, ne = nl + P.K, beta = P.beta(level);
+  const size_t sx = (size_t)nl * N, sext = (size_t)beta * ne * N, su = 2 * (size_t)ne * N;
+  Buf x = dev_buf(cx.pool, sx * nbatch);
+  Buf ext = dev_buf(cx.pool, sext * nbatch);
+  Buf u = dev_buf(cx.pool, su * nbatch);
+  ks_accumulate_into(cx, key, d, sd, level, nbatch, g, prep_d, x.p, ext.p, u.p);
   return u;
 }
 
@@ -590,16 +598,17 @@ void keyswitch(Context& cx, const KsKey& key, const u64* d, size_t sd, int level
 // with relinearisation followed by rescale (kern.h, k_mdr_*).  D is the
 // tensor [3][nl][N] per item (stride sd); out: one device pointer per item,
 // each [2][l][N].
-void ks_moddown_rescale(Context& cx, Buf& u, const u64* D, size_t sd, int level,
-                        u64* const* out, int nbatch) {
+// corr: caller scratch of [nbatch][2][l][N] words
+void ks_moddown_rescale_into(Context& cx, u64* u, const u64* D, size_t sd, int level,
+                             u64* const* out, int nbatch, u64* corr) {
   const Params& P = cx.P();
   const Shared& sh = *cx.sh;
   const int N = P.N, nl = level + 1, K = P.K, ne = nl + K;
   const size_t su = 2 * (size_t)ne * N, sc = 2 * (size_t)level * N;
   {
     NttLaunch L{};                    // limbs q_l, p_0..p_{K-1} of both polynomials
-    L.src = u.p;
-    L.dst = u.p;
+    L.src = u;
+    L.dst = u;
     L.nlimbs = K + 1;
     L.nbatch = 2 * nbatch;
     L.batch_stride = (size_t)ne * N;
@@ -609,10 +618,15 @@ void ks_moddown_rescale(Context& cx, Buf& u, const u64* D, size_t sd, int level,
     L.skip_hi = level;
     ntt(sh, L, true, cx.stream);
   }
-  Buf corr = dev_buf(cx.pool, sc * nbatch);
-  k_mdr_corr(sh, u.p, corr.p, level, nbatch, su, sc, cx.stream);
-  MdrTail tail{u.p, D, su, sd, rescale_table(sh, level), out};
-  ntt_fwd_mdr_final(sh, corr.p, level, nbatch, tail, cx.stream);
+  k_mdr_corr(sh, u, corr, level, nbatch, su, sc, cx.stream);
+  MdrTail tail{u, D, su, sd, rescale_table(sh, level), out};
+  ntt_fwd_mdr_final(sh, corr, level, nbatch, tail, cx.stream);
+}
+
+void ks_moddown_rescale(Context& cx, Buf& u, const u64* D, size_t sd, int level,
+                        u64* const* out, int nbatch) {
+  Buf corr = dev_buf(cx.pool, 2 * (size_t)level * cx.P().N * nbatch);
+  ks_moddown_rescale_into(cx, u.p, D, sd, level, out, nbatch, corr.p);
 }
 
 // ciphertexts per batched launch group

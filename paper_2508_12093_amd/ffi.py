@@ -78,6 +78,7 @@ _SIGS = {
     "ppst_rotsum_steps": (ctypes.c_int, [_vp, _vp, _sz, ctypes.POINTER(ctypes.c_size_t)]),
     "ppst_encode_coeffs": (ctypes.c_int, [ctypes.POINTER(Params), _vp, _sz, _i32, _vp, _sz]),
     "ppst_stream_key": (_u64, [_u64, _u64, _u64]),
+    "ppst_chebyshev_invsqrt": (ctypes.c_int, [_dbl, _dbl, _i32, _dbl, _vp, _sz]),
     "ppst_context_create": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.POINTER(DeviceHooks), _vp, _pp]),
     "ppst_context_fork": (ctypes.c_int, [_vp, _vp, _pp]),
     "ppst_context_destroy": (ctypes.c_int, [_vp]),
@@ -96,12 +97,15 @@ _SIGS = {
     "ppst_evk_add_galois": (ctypes.c_int, [_vp, _vp, _vp, _sz, _u64, _vp]),
     "ppst_evk_add_rotsum": (ctypes.c_int, [_vp, _vp, _u64, _vp]),
     "ppst_evk_export": (ctypes.c_int, [_vp, _vp, _u64, _vp, _sz]),
+    "ppst_evk_import": (ctypes.c_int, [_vp, _vp, _u64, _vp, _sz]),
     "ppst_pk_export": (ctypes.c_int, [_vp, _vp, _vp, _sz]),
+    "ppst_pk_import": (ctypes.c_int, [_vp, _vp, _sz, _pp]),
     "ppst_sk_export": (ctypes.c_int, [_vp, _vp, _vp, _sz]),
     "ppst_encode": (ctypes.c_int, [_vp, _vp, _sz, _i32, _pp]),
     "ppst_plaintext_from_coeffs": (ctypes.c_int, [_vp, _vp, _i32, _dbl, _pp]),
     "ppst_plaintext_coeffs": (ctypes.c_int, [_vp, _vp, _sz]),
     "ppst_plaintext_export": (ctypes.c_int, [_vp, _vp, _vp, _sz]),
+    "ppst_plaintext_import": (ctypes.c_int, [_vp, _vp, _i32, _dbl, _pp]),
     "ppst_decode": (ctypes.c_int, [_vp, _vp, _vp, _sz]),
     "ppst_plaintext_destroy": (ctypes.c_int, [_vp]),
     "ppst_encrypt": (ctypes.c_int, [_vp, _vp, _vp, _u64, _pp]),
@@ -181,9 +185,32 @@ def lib():
     return _lib
 
 
-def header_symbols():
-    """Names of the functions include/ppstat.h declares."""
-    text = open(HEADER).read()
+PROBE_PATH = os.path.join(_HERE, "libppstat_probe.so")
+PROBE_HEADER = os.path.join(os.path.dirname(_HERE), "include", "ppstat_probe.h")
+_probe = None
+
+
+def probe_lib():
+    """Load libppstat_probe.so, the peak-rate microbenchmarks
+    (include/ppstat_probe.h); raises if it has not been built."""
+    global _probe
+    if _probe is None:
+        if not os.path.exists(PROBE_PATH):
+            raise RuntimeError("libppstat_probe.so is not built (run __graft_entry__.build())")
+        L = ctypes.CDLL(PROBE_PATH)
+        for name, args in {"ppst_probe_copy": [_vp, _vp, _sz, _vp],
+                           "ppst_probe_fma_f64": [_vp, _sz, ctypes.c_int, _vp],
+                           "ppst_probe_mad_u64_u32": [_vp, _sz, ctypes.c_int, _vp]}.items():
+            f = getattr(L, name)
+            f.restype = ctypes.c_int
+            f.argtypes = args
+        _probe = L
+    return _probe
+
+
+def header_symbols(header: str = HEADER):
+    """Names of the functions a header (by default include/ppstat.h) declares."""
+    text = open(header).read()
     return sorted(set(re.findall(r"\b(ppst_[a-z0-9_]+)\s*\(", text)))
 
 
@@ -324,6 +351,12 @@ def ppst_encode_coeffs(params: Params, values, level: int):
     return out
 
 
+def ppst_chebyshev_invsqrt(a: float, b: float, degree: int, Bp: float):
+    out = np.zeros(degree + 1, dtype=np.float64)
+    _chk(lib().ppst_chebyshev_invsqrt(a, b, degree, Bp, _p(out), out.size))
+    return out
+
+
 def ppst_stream_key(seed: int, purpose: int, limb: int) -> int:
     return int(lib().ppst_stream_key(seed, purpose, limb))
 
@@ -338,14 +371,50 @@ def _torch_stream():
     return None
 
 
-def ppst_context_create(params, stream=None, use_torch_stream=True) -> Context:
-    """Create a context; by default it runs on torch's current stream."""
+# ctypes callbacks handed to the library stay alive for the whole process:
+# its pools may return memory through them until their last context is gone
+_HOOK_REFS = []
+
+
+def torch_device_hooks() -> DeviceHooks:
+    """ppst_device_hooks backed by torch's caching allocator: every device
+    block the library takes (ciphertexts, keys, tables, scratch) comes from
+    torch.cuda.caching_allocator_alloc on the stream the library names, and
+    goes back through caching_allocator_delete.  A failed allocation returns
+    NULL, on which the library releases its own cached blocks and retries
+    before reporting ENOMEM.  Contexts made with these hooks should be
+    destroyed before the interpreter shuts down."""
+    import torch
+    dev = torch.cuda.current_device()
+
+    def alloc(nbytes, stream, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device=dev, stream=int(stream or 0))
+        except Exception:
+            return None
+
+    def free(ptr, nbytes, stream, user):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    h = DeviceHooks(HooksAlloc(alloc), HooksFree(free), None)
+    _HOOK_REFS.append(h)
+    return h
+
+
+def ppst_context_create(params, stream=None, use_torch_stream=True, alloc: str = "library") -> Context:
+    """Create a context; by default it runs on torch's current stream.
+    alloc="torch" takes every device block from torch's caching allocator
+    (torch_device_hooks); "library" lets the library's own pool call
+    hipMalloc."""
     if isinstance(params, str):
         params = ppst_params_preset(params)
     if stream is None and use_torch_stream:
         stream = _torch_stream()
+    if alloc not in ("library", "torch"):
+        raise ValueError("alloc must be 'library' or 'torch'")
+    hooks = ctypes.byref(torch_device_hooks()) if alloc == "torch" else None
     out = _out()
-    _chk(lib().ppst_context_create(ctypes.byref(params), None, stream, ctypes.byref(out)))
+    _chk(lib().ppst_context_create(ctypes.byref(params), hooks, stream, ctypes.byref(out)))
     return Context(out.value)
 
 
@@ -403,6 +472,18 @@ def ppst_evk_export(ctx: Context, evk: EvalKeys, galois: int):
     return out
 
 
+def ppst_evk_import(ctx: Context, evk: EvalKeys, galois: int, words: np.ndarray):
+    w = np.ascontiguousarray(words, dtype=np.uint64)
+    _chk(lib().ppst_evk_import(ctx, evk, galois, _p(w), w.size))
+
+
+def ppst_pk_import(ctx: Context, words: np.ndarray) -> PublicKey:
+    w = np.ascontiguousarray(words, dtype=np.uint64)
+    out = _out()
+    _chk(lib().ppst_pk_import(ctx, _p(w), w.size, ctypes.byref(out)))
+    return PublicKey(out.value, ctx)
+
+
 def ppst_pk_export(ctx: Context, pk: PublicKey):
     i = ctx.info
     out = np.zeros((2, i.L + 1, i.N), dtype=np.uint64)
@@ -441,6 +522,15 @@ def ppst_plaintext_export(ctx: Context, pt: Plaintext, level: int):
     out = np.zeros((level + 1, ctx.info.N), dtype=np.uint64)
     _chk(lib().ppst_plaintext_export(ctx, pt, _p(out), out.size))
     return out
+
+
+def ppst_plaintext_import(ctx: Context, words: np.ndarray, level: int, scale: float) -> Plaintext:
+    w = np.ascontiguousarray(words, dtype=np.uint64)
+    if w.size != (level + 1) * ctx.info.N:
+        raise PpstError(-1, "expected [level+1][N] words")
+    out = _out()
+    _chk(lib().ppst_plaintext_import(ctx, _p(w), level, scale, ctypes.byref(out)))
+    return Plaintext(out.value, ctx)
 
 
 def ppst_decode(ctx: Context, pt: Plaintext, n: int | None = None):

@@ -21,6 +21,18 @@ def test_library_exports_every_declared_symbol():
         assert n in ffi._SIGS, "binding misses " + n
 
 
+def test_probe_library_exports_every_declared_symbol():
+    L = ffi.probe_lib()
+    names = ffi.header_symbols(ffi.PROBE_HEADER)
+    assert names == ["ppst_probe_copy", "ppst_probe_fma_f64", "ppst_probe_mad_u64_u32"]
+    for n in names:
+        assert hasattr(L, n), n
+    # argument checks happen before any launch, so they run without a GPU
+    assert L.ppst_probe_copy(None, None, 16, None) == -1
+    assert L.ppst_probe_fma_f64(None, 256, 1, None) == -1
+    assert L.ppst_probe_mad_u64_u32(ctypes.c_void_p(8), 100, 1, None) == -1
+
+
 def test_status_of_bad_preset():
     with pytest.raises(ffi.PpstError) as e:
         ffi.ppst_params_preset("nope")
@@ -74,3 +86,34 @@ def test_rotsum_steps_match_oracle(name):
     assert got == O.rotsum_hoisted8_steps()
     assert len(got) == len(set(got)) and all(0 < r < O.P.slots for r in got)
     assert O.rotsum_hoisted8_plan()[0] == (1, 8)
+
+
+@pytest.mark.parametrize("a,b,degree,Bp", [(1e-3, 1.0, 7, 1.0), (1e-3, 1.0, 7, 400.0),
+                                           (1e-3, 1.0, 63, 1.0), (1e-3, 1.0, 511, 4.0),
+                                           (0.0, 2.0, 31, 100.0)])
+def test_chebyshev_generator_matches_oracle(a, b, degree, Bp):
+    """The library's Chebyshev initial value of CryptoInvSqrt (host code the
+    statistics use when no table is passed) equals the oracle's interpolation
+    within the rounding of an (d + 1)-term sum: |dc_k| <= (d + 1) 2^-52 times
+    the sum of |f| over the nodes (2/(d+1) weights)."""
+    from oracle import cheb
+    got = ffi.ppst_chebyshev_invsqrt(a, b, degree, Bp)
+    if a > 0:
+        want = cheb.invsqrt_coeffs(a, b, degree, Bp)
+    else:                                  # Eq. 3: 1/(sqrt(B) sqrt(x + 1)) on [-1, 1]
+        want = cheb.paper_invsqrt_coeffs(degree, Bp)
+    n = degree + 1
+    t = np.cos(np.pi * (np.arange(n) + 0.5) / n)
+    fsum = np.sum(1.0 / np.sqrt(Bp * (a + (b - a) * (t + 1.0) / 2.0))) * 2.0 / n
+    assert np.max(np.abs(got - want)) <= n * 2.0 ** -52 * fsum
+    # the two sums differ in order only: a few units in the last place of the
+    # largest coefficient (measured: at most 15 at degree 7)
+    assert np.max(np.abs(got - want)) <= 64 * np.spacing(np.max(np.abs(want))) * n
+
+
+def test_chebyshev_generator_domain():
+    for args in [(0.5, 0.5, 7, 1.0), (-1.0, 1.0, 7, 1.0), (1e-3, 1.0, 0, 1.0), (1e-3, 1.0, 512, 1.0),
+                 (1e-3, 1.0, 7, 0.0)]:
+        with pytest.raises(ffi.PpstError) as e:
+            ffi.ppst_chebyshev_invsqrt(*args)
+        assert e.value.name == "EDOMAIN"

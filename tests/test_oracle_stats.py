@@ -97,6 +97,42 @@ def _levels_and_values(n=32768):
     }
 
 
+def _sqrt1px_aliased(degree):
+    """Coefficients of the degree-d interpolant of sqrt(1 + x) at the d + 1
+    first-kind Chebyshev nodes, from the closed-form series
+    sqrt(1 + x) = (2 sqrt 2 / pi) (1 + 2 sum_k (-1)^(k+1) T_k(x) / (4k^2 - 1))
+    (the cosine series of sqrt 2 cos(theta / 2), x = cos theta) and the
+    aliasing of T_(2m n +- k) onto (-1)^m T_k at those n = d + 1 nodes."""
+    n = degree + 1
+    amp = 2.0 * np.sqrt(2.0) / np.pi
+
+    def a(k):
+        k = np.asarray(k, dtype=np.float64)
+        return np.where(k == 0, amp, amp * 2.0 * (-1.0) ** (k + 1) / (4.0 * k * k - 1.0))
+
+    m = np.arange(1, 400001, dtype=np.float64)
+    sign = (-1.0) ** m
+    c = np.empty(n)
+    c[0] = a(0) + np.sum(sign * a(2 * m * n))
+    for k in range(1, n):
+        c[k] = a(k) + np.sum(sign * (a(2 * m * n - k) + a(2 * m * n + k)))
+    return c
+
+
+@pytest.mark.parametrize("degree,B", [(7, 1.0), (7, 20.0), (31, 100.0)])
+def test_paper_sqrt_coefficients_closed_form(degree, B):
+    """Eq. 4 (CryptoSqrt's initial polynomial sqrt(B) sqrt(x + 1) on
+    [-1, 1]): the oracle's interpolated coefficients equal the closed-form
+    Chebyshev series with its aliasing summed, and the polynomial matches
+    the function at the nodes."""
+    got = cheb.paper_sqrt_coeffs(degree, B)
+    want = np.sqrt(B) * _sqrt1px_aliased(degree)
+    assert np.max(np.abs(got - want)) < 1e-12 * np.sqrt(B)
+    nodes = np.cos(np.pi * (np.arange(degree + 1) + 0.5) / (degree + 1))
+    assert np.allclose(np.polynomial.chebyshev.chebval(nodes, got), np.sqrt(B * (nodes + 1.0)),
+                       rtol=0, atol=1e-13 * np.sqrt(B))
+
+
 def test_plain_circuits_match_fp64_and_depths():
     x, y, r = _levels_and_values()
     assert S.mre(r["zscore"].v, S.zscore(y)) < 1e-6
