@@ -243,6 +243,26 @@ int ppst_mul_plain(ppst_context* ctx, const ppst_ciphertext* a, const ppst_plain
 /* Mul(C): tensor, relinearise (hybrid key switching), rescale: level l -> l-1 */
 int ppst_mul(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciphertext* a,
              const ppst_ciphertext* b, ppst_ciphertext** out);
+/* ppst_mul into caller memory, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): no hipMalloc, hipFree or pool allocation happens in it.
+ *   a, b   device addresses of two ciphertexts at `level` (1..L), each
+ *          [2][level+1][N] words in the layout above, scale Delta_level (the
+ *          layout ppst_ct_device_ptr exposes); borrowed, read on the stream.
+ *   out    device address of [2][level][N] words receiving the product at
+ *          scale Delta_{level-1}, bit for bit ppst_mul's; must not overlap
+ *          a or b (EINVAL).
+ * The key-switching intermediates live in one library-wide device array of
+ * 144 MiB per GPU, held from the first context on that GPU until the process
+ * ends; a product whose intermediates exceed it is refused with EINVAL (at
+ * N = 2^16, K = 7, dnum = 3 every level up to 24 fits).  All calls on one GPU
+ * share that array: calls that overlap in time (other contexts' streams,
+ * other threads) race, and the caller must order them.  Nothing in the array
+ * needs clearing between calls.  Asynchronous on the context's stream;
+ * ELEVEL outside 1..L, ENOKEY without a relinearisation key, EDEVICE when
+ * the runtime could not resolve the array. */
+int ppst_mul_noalloc(ppst_context* ctx, const ppst_eval_keys* evk, const uint64_t* a,
+                     const uint64_t* b, int32_t level, uint64_t* out);
 /* the three steps of ppst_mul separately (tensor output has npoly = 3) */
 int ppst_tensor(ppst_context* ctx, const ppst_ciphertext* a, const ppst_ciphertext* b,
                 ppst_ciphertext** out);

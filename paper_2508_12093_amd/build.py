@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libppstat.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["host_math.cpp", "eval.cpp", "stats.cpp", "server.cpp", "capi.cpp",
+SOURCES = ["host_math.cpp", "eval.cpp", "stats.cpp", "server.cpp", "capi.cpp", "noalloc.cpp",
            "ntt.hip", "kernels.hip"]
 
 # peak-rate microbenchmarks for the roofline figures: a library of their own

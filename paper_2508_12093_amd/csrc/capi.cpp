@@ -165,6 +165,12 @@ int ppst_context_create(const ppst_params* params, const ppst_device_hooks* hook
     }
     auto sh = make_shared_state(s, hooks ? &h : nullptr);
     *out = new ppst_context{make_context(sh, (hipStream_t)stream)};
+    // resolve this device's ppst_mul_noalloc scratch now; a failure is kept
+    // and reported by that entry point, the context itself is usable
+    try {
+      noalloc_scratch();
+    } catch (const Error&) {
+    }
   });
 }
 

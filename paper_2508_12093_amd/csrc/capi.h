@@ -61,4 +61,10 @@ int guard(F&& f) {
     if (!(p)) PPST_THROW(ST_EINVAL, "null argument: " #p);          \
   } while (0)
 
+// Device-side scratch of ppst_mul_noalloc: sets up the current device's
+// array (once per device; context creation calls it) and returns its
+// address, or throws when the runtime could not resolve it.
+u64* noalloc_scratch();
+size_t noalloc_scratch_bytes();
+
 }  // namespace ppst

@@ -1156,6 +1156,26 @@ CtPtr mul(Context& cx, const EvalKeys& evk, const Ciphertext& a, const Ciphertex
   return out;
 }
 
+size_t mul_scratch_words(const Params& P, int level) {
+  const size_t nl = (size_t)level + 1, ne = nl + P.K, beta = (size_t)P.beta(level);
+  return (3 * nl + beta * ne + 2 * ne + std::max(nl, 2 * (size_t)level)) * (size_t)P.N;
+}
+
+void mul_into(Context& cx, const EvalKeys& evk, const u64* a, const u64* b, int level, u64* out,
+              u64* scratch) {
+  const Params& P = cx.P();
+  if (level < 1 || level > P.L) PPST_THROW(ST_ELEVEL, "no level left for a product");
+  const KsKey& key = relin_key(evk);
+  const size_t N = (size_t)P.N, nl = (size_t)level + 1, ne = nl + P.K;
+  u64* D = scratch;                                   // tensor [3][l+1][N]
+  u64* ext = D + 3 * nl * N;                          // extended digits [beta][ne][N]
+  u64* u = ext + (size_t)P.beta(level) * ne * N;      // accumulators [2][ne][N]
+  u64* xc = u + 2 * ne * N;                           // d2's coefficients, later the correction
+  k_tensor(*cx.sh, &a, &b, D, (int)nl, 1, 0, cx.stream);
+  ks_accumulate_into(cx, key, D + 2 * nl * N, 0, level, 1, 0, D, xc, ext, u);
+  ks_moddown_rescale_into(cx, u, D, 0, level, &out, 1, xc);
+}
+
 CtPtr rotate(Context& cx, const EvalKeys& evk, const Ciphertext& a, long r) {
   if (a.npoly != 2) PPST_THROW(ST_EINVAL, "rotation expects a degree-1 ciphertext");
   const Params& P = cx.P();

@@ -56,6 +56,14 @@ CtPtr tensor(Context& cx, const Ciphertext& a, const Ciphertext& b);
 CtPtr relin(Context& cx, const EvalKeys& evk, const Ciphertext& d);
 CtPtr rescale(Context& cx, const Ciphertext& a);
 CtPtr mul(Context& cx, const EvalKeys& evk, const Ciphertext& a, const Ciphertext& b);
+// mul() of raw device ciphertexts a, b ([2][l+1][N] at scale Delta_l) into
+// out ([2][l][N]) with no allocation: every intermediate lives in `scratch`
+// (mul_scratch_words(P, l) words: the tensor, the extended digits, the
+// accumulators, and d2's coefficient copy whose space the ModDown
+// correction takes over).  Bit for bit mul()'s result.
+size_t mul_scratch_words(const Params& P, int level);
+void mul_into(Context& cx, const EvalKeys& evk, const u64* a, const u64* b, int level, u64* out,
+              u64* scratch);
 CtPtr rotate(Context& cx, const EvalKeys& evk, const Ciphertext& a, long r);
 std::vector<CtPtr> rotate_hoisted(Context& cx, const EvalKeys& evk, const Ciphertext& a,
                                   const std::vector<long>& rs);

@@ -123,6 +123,7 @@ _SIGS = {
     "ppst_mul_int": (ctypes.c_int, [_vp, _vp, _i64, _pp]),
     "ppst_mul_plain": (ctypes.c_int, [_vp, _vp, _vp, _pp]),
     "ppst_mul": (ctypes.c_int, [_vp, _vp, _vp, _vp, _pp]),
+    "ppst_mul_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _vp]),
     "ppst_tensor": (ctypes.c_int, [_vp, _vp, _vp, _pp]),
     "ppst_relin": (ctypes.c_int, [_vp, _vp, _vp, _pp]),
     "ppst_rescale": (ctypes.c_int, [_vp, _vp, _pp]),
@@ -569,6 +570,12 @@ def ppst_ct_import(ctx: Context, data: np.ndarray, level: int, scale: float) -> 
     out = _out()
     _chk(lib().ppst_ct_import(ctx, _p(d), level, scale, d.shape[0], ctypes.byref(out)))
     return Ciphertext(out.value, ctx)
+
+
+def ppst_mul_noalloc(ctx: Context, evk, a_ptr: int, b_ptr: int, level: int, out_ptr: int):
+    """Device addresses in, device address out (see the header)."""
+    _chk(lib().ppst_mul_noalloc(ctx, evk, ctypes.c_void_p(a_ptr), ctypes.c_void_p(b_ptr), level,
+                                ctypes.c_void_p(out_ptr)))
 
 
 def ppst_ct_device_ptr(ct: Ciphertext) -> int:
