@@ -41,7 +41,17 @@ BFLY_PEAK_G = VALU_PEAK / OPS_PER_BFLY / 1e9
 # plain copy of known size.  The figure belongs to the NTT source it was taken
 # with (its SHA-256 below); for any other source the traffic is reported as
 # null.
-NTT_TRAFFIC = {"bytes": 79906202, "source_sha256": "see profiles"}
+NTT_TRAFFIC = {"bytes": 79871872,
+               "source_sha256": "125cdbd2da275fad871489166c72fc30d2ce2ca4abaf98ed85b3e415ab02d652"}
+# Algorithmic HBM bytes of the other key-switching kernels of one plain
+# product at level 24 (N = 2^16, K = 7, dnum = 3; a limb is 512 KiB): the key
+# inner product reads 3 digit limbs and 6 key limbs per extended limb (32)
+# and writes 2 (352 limbs); ModUp reads d2's 25 limbs and writes the 71
+# extension limbs; the ModDown correction reads 2 x 8 limbs and writes
+# 2 x 24; the tensor reads 4 x 25 and writes 3 x 25.
+LIMB = 1 << 19
+KS_KERNELS = {"k_ks_inner_kernel<1>": ("hbm", 352 * LIMB), "k_modup_kernel<9>": ("alu", 96 * LIMB),
+              "k_mdr_corr_kernel<8>": ("alu", 64 * LIMB), "k_tensor_kernel": ("hbm", 175 * LIMB)}
 
 
 def parse():
@@ -323,6 +333,7 @@ def main():
         "exp1_invsqrt_p50_ms": round(e1_p50, 3),
         "exp1_invsqrt_mre": e1_mre,
         "roofline": rf,
+        "roofline_kernels": profiled_kernels(),
         "peaks": peaks,
     }
     if exp2 is not None:
@@ -591,6 +602,33 @@ def measure_ntt(ctx, stream, reps: int):
         "hbm_algorithmic_GBs": round(alg_bytes / sec / 1e9, 1),
         "hbm_frac": round(alg_bytes / sec / 1e9 / HBM_PEAK_GBS, 4),
     }
+
+
+def profiled_kernels():
+    """Roofline entries of the plain product's other large kernels, from the
+    committed rocprofv3 counter summary (profiles/hmult_c2_plain_valu_traffic.md):
+    average duration, VALU busy fraction and counted HBM bytes per launch,
+    against the algorithmic bytes above (8 TB/s)."""
+    path = os.path.join(ROOT, "profiles", "hmult_c2_plain_valu_traffic.md")
+    out = []
+    try:
+        rows = [l for l in open(path).read().splitlines() if l.startswith("| `")]
+    except OSError:
+        return out
+    for l in rows:
+        cells = [c.strip() for c in l.strip("|").split("|")]
+        name = cells[0].strip("`")
+        if name not in KS_KERNELS:
+            continue
+        bound, alg = KS_KERNELS[name]
+        us = float(cells[3])
+        fetch, write = (float(v) for v in cells[9].split("+"))
+        out.append({"kernel": name, "bound": bound, "us": us, "alg_bytes": alg,
+                    "achieved_GBs": round(alg / (us * 1e-6) / 1e9, 1),
+                    "hbm_frac": round(alg / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                    "valu_busy": float(cells[8]), "traffic": int((fetch + write) * 1e6),
+                    "source": "profiles/hmult_c2_plain_valu_traffic.md"})
+    return out
 
 
 def measure_peaks(stream):

@@ -253,11 +253,11 @@ void build_tables(Shared& sh) {
   sh.tab.mods = upload(pool, mods);
 
   // Twiddle pairs: (w, floor(w 2^64 / q)) for the 64-bit integer path;
-  // (double w, double w/q) bit patterns for primes below 2^50, which the NTT
-  // runs in FP64 (ntt.hip).
+  // (double w, double w/q) bit patterns for primes below kFpPrimeBound, which
+  // the NTT runs in FP64 (ntt.hip).
   std::vector<u64> fwd((size_t)np * N * 2), inv((size_t)np * N * 2), ninv(2 * np);
   auto pair = [](u64 w, u64 q, u64* out) {
-    if (q < (1ULL << 50)) {
+    if (q < kFpPrimeBound) {
       double d = (double)w, s = (double)w / (double)q;
       std::memcpy(out, &d, 8);
       std::memcpy(out + 1, &s, 8);

@@ -61,11 +61,21 @@ __device__ __forceinline__ BlockPos block_pos(int blocks_per_limb, int nbatch) {
 //
 // IntArith: 64-bit residues, Shoup twiddle products (w, w' = floor(w 2^64/q))
 //   with Harvey's lazy ranges [0, 4q) forward and [0, 2q) inverse.
-// FpArith (q < 2^50): residues held as exact integers in FP64.  The twiddle
-//   product y w mod q is  h = fl(y w),  l = fma(y, w, -h)  (so h + l = y w
-//   exactly),  k = rint(y * (w/q)),  r = fma(-k, q, h) + l  = y w - k q exactly,
-//   with |r| < q because k is the nearest integer to y w / q up to a rounding
-//   error far below 1/2.  Table entries are (w, w/q) as doubles.
+// FpArith (q < 2^44): residues held as exact integers in FP64, signed and
+//   unreduced.  The twiddle product y w mod q is  h = fl(y w),
+//   l = fma(y, w, -h)  (so h + l = y w exactly),  k = rint(y * (w/q)),
+//   r = fma(-k, q, h) + l  = y w - k q exactly (every intermediate is an
+//   integer below 2^53), and |r| <= 0.55 q because k is the nearest integer
+//   to y w / q up to an error of at most 2 |y| 2^-53 < 0.05 for |y| < 2^47.4.
+//   A forward butterfly is then x + r, x - r with no reduction: over the 16
+//   stages of a transform |x| grows from q to at most q + 16 (0.55 q) < 10 q,
+//   below 2^47.4 for q < 2^44.  An inverse butterfly's sum x + y at most
+//   doubles per stage, so every register pass (at most 4 stages) starts by
+//   centring its values, v - q rint(v / q) (|v| <= q/2 + 1 after it), and
+//   its sums and differences stay below 2^4 (q/2 + 1) < 9 q.  Values cross
+//   from one pass to the next as the doubles' bits (no conversion), and the
+//   last pass rounds into [0, q).
+//   Table entries are (w, w/q) as doubles.
 // Both produce the same canonical residues at the end of a transform.
 // ----------------------------------------------------------------------
 struct IntArith {
@@ -73,9 +83,12 @@ struct IntArith {
   u64 q, q2;
   __device__ __forceinline__ explicit IntArith(u64 q_) : q(q_), q2(2 * q_) {}
   __device__ __forceinline__ T in(u64 v) const { return v; }
+  // a value written by the previous pass of the same transform, and back
+  __device__ __forceinline__ T in_mid(u64 v) const { return v; }
+  __device__ __forceinline__ u64 mid(T v) const { return v; }
+  __device__ __forceinline__ void centre(T&) const {}
   __device__ __forceinline__ u64 out_fwd(T v) const { v = v >= q2 ? v - q2 : v; return csub(v, q); }
   __device__ __forceinline__ u64 out_inv(T v, u64 ni, u64 nip) const { return mul_shoup(v, ni, nip, q); }
-  __device__ __forceinline__ T keep(T v) const { return v; }       // value carried between passes
   // forward CT on [0, 4q)
   __device__ __forceinline__ void ct(T& x, T& y, ulonglong2 w) const {
     u64 a = x >= q2 ? x - q2 : x;
@@ -95,9 +108,10 @@ struct IntArith {
 
 struct FpArith {
   typedef double T;
-  double q, q2;
-  __device__ __forceinline__ explicit FpArith(u64 q_) : q((double)q_), q2(2.0 * (double)q_) {}
-  // y w - k q with k = rint(y w / q): exact, in (-q, q)
+  double q, qinv;
+  __device__ __forceinline__ explicit FpArith(u64 q_)
+      : q((double)q_), qinv(1.0 / (double)q_) {}
+  // y w - k q with k = rint(y w / q): exact, |.| <= 0.55 q
   __device__ __forceinline__ double mulmod(double y, double w, double ws) const {
     double h = y * w;
     double l = __fma_rn(y, w, -h);
@@ -106,36 +120,35 @@ struct FpArith {
     return r + l;
   }
   __device__ __forceinline__ T in(u64 v) const { return (double)v; }
+  __device__ __forceinline__ T in_mid(u64 v) const { return __longlong_as_double((long long)v); }
+  __device__ __forceinline__ u64 mid(T v) const { return (u64)__double_as_longlong(v); }
+  // v - q rint(v / q): exact (an integer of magnitude below q), |.| <= q/2 + 1
+  __device__ __forceinline__ void centre(T& v) const { v = __fma_rn(-rint(v * qinv), q, v); }
+  // the canonical residue of v
   __device__ __forceinline__ u64 out_fwd(T v) const {
-    v = v >= q2 ? v - q2 : v;
-    v = v >= q ? v - q : v;
-    return (u64)v;
+    double r = __fma_rn(-rint(v * qinv), q, v);
+    r = r < 0.0 ? r + q : r;
+    return (u64)r;
   }
   __device__ __forceinline__ u64 out_inv(T v, u64 ni, u64 nis) const {
     double r = mulmod(v, __longlong_as_double((long long)ni), __longlong_as_double((long long)nis));
     r = r < 0.0 ? r + q : r;
     return (u64)r;
   }
-  // forward CT: x, y in [0, 4q) -> (0, 4q)
+  // forward CT: x + r, x - r
   __device__ __forceinline__ void ct(T& x, T& y, ulonglong2 w) const {
-    double a = x >= q2 ? x - q2 : x;
     double r = mulmod(y, __longlong_as_double((long long)w.x), __longlong_as_double((long long)w.y));
-    double aq = a + q;
-    x = aq + r;
-    y = aq - r;
+    y = x - r;
+    x = x + r;
   }
-  // inverse GS: x, y in [0, 2q) -> [0, 2q), (0, 2q)
+  // inverse GS: x + y, (x - y) w
   __device__ __forceinline__ void gs(T& x, T& y, ulonglong2 w) const {
     double s = x + y;
-    s = s >= q2 ? s - q2 : s;
-    double r = mulmod(x - y, __longlong_as_double((long long)w.x), __longlong_as_double((long long)w.y));
-    y = r + q;
+    y = mulmod(x - y, __longlong_as_double((long long)w.x), __longlong_as_double((long long)w.y));
     x = s;
   }
 };
 
-// primes below this bound take the FP64 path (values stay below 2^53)
-constexpr u64 kFpPrimeBound = 1ULL << 50;
 
 // One pass of LOGM stages over SB independent sub-problems of M = 2^LOGM
 // points.  ROWS: sub-problem r = row (contiguous), twiddle base R + r;
@@ -150,7 +163,8 @@ constexpr u64 kFpPrimeBound = 1ULL << 50;
 template <class A, int LOGM, int LOGE, int SB, bool ROWS, bool INV>
 __device__ __forceinline__ void ntt_body(const A ar, typename A::T* lds, const u64* src, u64* dst,
                                          const ulonglong2* tw, const u64* ninv2, int N, int logR,
-                                         int first, bool last, uint32_t galois, int logN) {
+                                         int first, bool firstp, bool last, uint32_t galois,
+                                         int logN) {
   typedef typename A::T T;
   constexpr int M = 1 << LOGM;
   constexpr int E = 1 << LOGE;
@@ -174,13 +188,14 @@ __device__ __forceinline__ void ntt_body(const A ar, typename A::T* lds, const u
 #pragma unroll 4
     for (int idx = tid; idx < SB * M; idx += NT) {
       int sp = idx / M, e = idx - sp * M;
-      lds[sp * PAD + e] = ar.in(g[idx]);
+      lds[sp * PAD + e] = firstp ? ar.in(g[idx]) : ar.in_mid(g[idx]);
     }
   } else {
 #pragma unroll 4
     for (int idx = tid; idx < SB * M; idx += NT) {
       int e = idx / SB, sp = idx - e * SB;
-      lds[sp * PAD + e] = ar.in(src[(size_t)e * C + first + sp]);
+      const u64 v = src[(size_t)e * C + first + sp];
+      lds[sp * PAD + e] = firstp ? ar.in(v) : ar.in_mid(v);
     }
   }
   __syncthreads();
@@ -207,6 +222,11 @@ __device__ __forceinline__ void ntt_body(const A ar, typename A::T* lds, const u
       e0[g] = hi * (M >> s0) + lo;
 #pragma unroll
       for (int k = 0; k < GS; ++k) x[g * GS + k] = my[e0[g] + k * si];
+    }
+    // inverse sums grow: every register pass starts from centred values
+    if (INV) {
+#pragma unroll
+      for (int i = 0; i < E; ++i) ar.centre(x[i]);
     }
 #pragma unroll
     for (int uu = 0; uu < ls; ++uu) {
@@ -241,14 +261,14 @@ __device__ __forceinline__ void ntt_body(const A ar, typename A::T* lds, const u
     for (int idx = tid; idx < SB * M; idx += NT) {
       int s2 = idx / M, e = idx - s2 * M;
       T v = lds[s2 * PAD + e];
-      g[idx] = last ? (INV ? ar.out_inv(v, ni, nip) : ar.out_fwd(v)) : (u64)v;
+      g[idx] = last ? (INV ? ar.out_inv(v, ni, nip) : ar.out_fwd(v)) : ar.mid(v);
     }
   } else {
 #pragma unroll 4
     for (int idx = tid; idx < SB * M; idx += NT) {
       int e = idx / SB, s2 = idx - e * SB;
       T v = lds[s2 * PAD + e];
-      dst[(size_t)e * C + first + s2] = last ? (INV ? ar.out_inv(v, ni, nip) : ar.out_fwd(v)) : (u64)v;
+      dst[(size_t)e * C + first + s2] = last ? (INV ? ar.out_inv(v, ni, nip) : ar.out_fwd(v)) : ar.mid(v);
     }
   }
 }
@@ -272,7 +292,7 @@ template <class A, int LOGM, int LOGE, int SB, bool ROWS, bool INV, class Store 
 __device__ __forceinline__ void ntt_body_dio(const A ar, typename A::T* lds, const u64* src,
                                              Store& store, const ulonglong2* tw,
                                              const u64* ninv2, int N, int logR, int first,
-                                             bool last, uint32_t galois, int logN) {
+                                             bool firstp, bool last, uint32_t galois, int logN) {
   typedef typename A::T T;
   constexpr int M = 1 << LOGM;
   constexpr int E = 1 << LOGE;
@@ -314,7 +334,7 @@ __device__ __forceinline__ void ntt_body_dio(const A ar, typename A::T* lds, con
           const int e = e0[g] + k * si;
           size_t at = ROWS ? rowbase + e : (size_t)e * C + col;
           if (ROWS && INV && galois != 0) at = galois_src((uint32_t)at, galois, logN);
-          x[g * GS + k] = ar.in(src[at]);
+          x[g * GS + k] = firstp ? ar.in(src[at]) : ar.in_mid(src[at]);
         }
     } else {
 #pragma unroll
@@ -330,6 +350,11 @@ __device__ __forceinline__ void ntt_body_dio(const A ar, typename A::T* lds, con
           const int e = e0[g] + k * si;
           store.prefetch(g * GS + k, ROWS ? rowbase + e : (size_t)e * C + col);
         }
+    }
+    // inverse sums grow: every register pass starts from centred values
+    if (INV) {
+#pragma unroll
+      for (int i = 0; i < E; ++i) ar.centre(x[i]);
     }
 #pragma unroll
     for (int uu = 0; uu < ls; ++uu) {
@@ -357,7 +382,7 @@ __device__ __forceinline__ void ntt_body_dio(const A ar, typename A::T* lds, con
           const int e = e0[g] + k * si;
           const size_t at = ROWS ? rowbase + e : (size_t)e * C + col;
           const T v = x[g * GS + k];
-          store.put(g * GS + k, at, last ? (INV ? ar.out_inv(v, ni, nip) : ar.out_fwd(v)) : (u64)v);
+          store.put(g * GS + k, at, last ? (INV ? ar.out_inv(v, ni, nip) : ar.out_fwd(v)) : ar.mid(v));
         }
     } else {
 #pragma unroll
@@ -392,23 +417,24 @@ k_ntt_pass(NttArgs a) {
   const ulonglong2* tw = (const ulonglong2*)(a.tw + (size_t)prime * N * 2);
   const u64* ni = a.ninv + 2 * prime;
   const bool last = INV ? (!ROWS || a.logR == 0) : ROWS;
+  const bool firstp = INV ? ROWS : (!ROWS || a.logR == 0);   // reads the transform's input
   const int first = grp * SB;        // first sub-problem of this workgroup
   if (DIO) {
     PlainStore store{dst};
     if (q < kFpPrimeBound)
       ntt_body_dio<FpArith, LOGM, LOGE, SB, ROWS, INV>(FpArith(q), (double*)lds, src, store, tw,
-                                                        ni, N, a.logR, first, last, a.galois,
+                                                        ni, N, a.logR, first, firstp, last, a.galois,
                                                         a.logN);
     else
       ntt_body_dio<IntArith, LOGM, LOGE, SB, ROWS, INV>(IntArith(q), lds, src, store, tw, ni, N,
-                                                         a.logR, first, last, a.galois, a.logN);
+                                                         a.logR, first, firstp, last, a.galois, a.logN);
   } else {
     if (q < kFpPrimeBound)
       ntt_body<FpArith, LOGM, LOGE, SB, ROWS, INV>(FpArith(q), (double*)lds, src, dst, tw, ni, N,
-                                                    a.logR, first, last, a.galois, a.logN);
+                                                    a.logR, first, firstp, last, a.galois, a.logN);
     else
       ntt_body<IntArith, LOGM, LOGE, SB, ROWS, INV>(IntArith(q), lds, src, dst, tw, ni, N,
-                                                     a.logR, first, last, a.galois, a.logN);
+                                                     a.logR, first, firstp, last, a.galois, a.logN);
   }
 }
 
@@ -473,10 +499,10 @@ k_ntt_row_mdr(NttArgs a, MdrEpi e) {
   const int first = grp * SB;
   if (q < kFpPrimeBound)
     ntt_body_dio<FpArith, LOGM, LOGE, SB, true, false>(FpArith(q), (double*)lds, src, store, tw,
-                                                        ni, N, a.logR, first, true, 0u, a.logN);
+                                                        ni, N, a.logR, first, a.logR == 0, true, 0u, a.logN);
   else
     ntt_body_dio<IntArith, LOGM, LOGE, SB, true, false>(IntArith(q), lds, src, store, tw, ni, N,
-                                                         a.logR, first, true, 0u, a.logN);
+                                                         a.logR, first, a.logR == 0, true, 0u, a.logN);
 }
 
 template <int LOGM, int LOGE, int SB>
@@ -558,10 +584,10 @@ k_ntt_row_md(NttArgs a, MdEpi e) {
   const int first = grp * SB;
   if (q < kFpPrimeBound)
     ntt_body_dio<FpArith, LOGM, LOGE, SB, true, false>(FpArith(q), (double*)lds, src, store, tw,
-                                                        ni, N, a.logR, first, true, 0u, a.logN);
+                                                        ni, N, a.logR, first, a.logR == 0, true, 0u, a.logN);
   else
     ntt_body_dio<IntArith, LOGM, LOGE, SB, true, false>(IntArith(q), lds, src, store, tw, ni, N,
-                                                         a.logR, first, true, 0u, a.logN);
+                                                         a.logR, first, a.logR == 0, true, 0u, a.logN);
 }
 
 template <int LOGM, int LOGE, int SB>
@@ -628,10 +654,10 @@ k_ntt_row_rs(NttArgs a, RsEpi e) {
   const int first = grp * SB;
   if (q < kFpPrimeBound)
     ntt_body_dio<FpArith, LOGM, LOGE, SB, true, false>(FpArith(q), (double*)lds, src, store, tw,
-                                                        ni, N, a.logR, first, true, 0u, a.logN);
+                                                        ni, N, a.logR, first, a.logR == 0, true, 0u, a.logN);
   else
     ntt_body_dio<IntArith, LOGM, LOGE, SB, true, false>(IntArith(q), lds, src, store, tw, ni, N,
-                                                         a.logR, first, true, 0u, a.logN);
+                                                         a.logR, first, a.logR == 0, true, 0u, a.logN);
 }
 
 template <int LOGM, int LOGE, int SB>

@@ -6,6 +6,9 @@
 namespace ppst {
 
 constexpr int kMaxAlpha = 16;     // limbs per key-switching digit
+// primes below this bound run their NTT in FP64 (ntt.hip, FpArith), whose
+// twiddle entries are then (double w, double w/q)
+constexpr u64 kFpPrimeBound = 1ULL << 44;
 constexpr int kMaxSpecial = 8;    // special primes
 
 // ModDown table layout (one table serves every level); the rows of the first
