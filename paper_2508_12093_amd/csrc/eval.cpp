@@ -631,6 +631,11 @@ void ks_moddown_rescale(Context& cx, Buf& u, const u64* D, size_t sd, int level,
 
 // ciphertexts per batched launch group
 constexpr size_t kMulChunk = 16;
+// products per group of ppst_mul_batch: as many as one launch's pointer
+// arrays take, so that a batch of up to 64 reads the relinearisation key once
+// (key-switching scratch: about 154 MiB per product at level 24, under 10 GiB
+// for a full group)
+constexpr size_t kMulBatchGroup = kPtrBatch;
 
 // Rescale npoly polynomials at `level`: polynomial c at a[c] (limbs 0..level)
 // into out[c] (limbs 0..level-1).  With k (host arrays of level+1 constant
@@ -1536,11 +1541,10 @@ std::vector<CtPtr> mul_batch(Context& cx, const EvalKeys& evk,
   }
   std::vector<CtPtr> outs;
   for (size_t i = 0; i < n; ++i) outs.push_back(new_ct(cx, level - 1, P.scale[level - 1]));
-  // groups of kMulChunk products: the inner product already reads the key
-  // once per 8 items, and the key-switching scratch (about 130 MiB per
-  // product at level 24) stays bounded for long batches
-  for (size_t b0 = 0; b0 < n; b0 += kMulChunk) {
-    const int nb = (int)std::min<size_t>(kMulChunk, n - b0);
+  // groups of kMulBatchGroup products: one launch per stage and one read of
+  // the key per group
+  for (size_t b0 = 0; b0 < n; b0 += kMulBatchGroup) {
+    const int nb = (int)std::min<size_t>(kMulBatchGroup, n - b0);
     Buf D = dev_buf(cx.pool, 3 * per * nb);
     k_tensor(*cx.sh, pa.data() + b0, pb.data() + b0, D.p, nl, nb, 3 * per, cx.stream);
     Buf u = ks_accumulate(cx, key, D.p + 2 * per, 3 * per, level, nb, 0, D.p);

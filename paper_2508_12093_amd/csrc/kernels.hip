@@ -208,6 +208,8 @@ struct InnerArgs {
   u64 pmod, pmods;    // P mod q_l and its Shoup companion
 };
 
+constexpr int kMaxDigits = 8;
+
 // ITEMS batch items per thread: one key load serves all of them
 template <int ITEMS>
 __global__ void __launch_bounds__(kBlock) k_ks_inner_kernel(InnerArgs a) {
@@ -261,6 +263,70 @@ __global__ void __launch_bounds__(kBlock) k_ks_inner_kernel(InnerArgs a) {
       }
       u[(size_t)t * N + k] = v0;
       u[((size_t)a.ne + t) * N + k] = v1;
+    }
+  }
+}
+
+// Long batches: one thread per (extended limb, coefficient) for the whole
+// batch.  The key's 2 beta values there are read once into registers, then
+// the batch is taken ITEMS items at a time (the items' loads of one digit
+// issued together), so the key crosses HBM once per launch whatever the batch
+// size.  (The register copy of the key costs occupancy, which the short
+// batches above, bound by HBM, cannot spare.)
+template <int ITEMS>
+__global__ void __launch_bounds__(kBlock) k_ks_inner_loop_kernel(InnerArgs a) {
+  const size_t N = (size_t)1 << a.logN;
+  size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= (size_t)a.ne * N) return;
+  const int t = (int)(r >> a.logN);
+  const size_t k = r & (N - 1);
+  const int p = t < a.nl ? t : a.pofs + (t - a.nl);
+  // digit holding limb t; with d == null the digits' own limbs are read from ext too
+  const int own = (a.d != nullptr && t < a.nl) ? t / a.alpha : -1;
+  const size_t kd = galois_src((uint32_t)k, a.gd, a.logN);
+  const size_t kx = galois_src((uint32_t)k, a.gext, a.logN);
+  Split30 kb[kMaxDigits], ka[kMaxDigits];
+#pragma unroll
+  for (int j = 0; j < kMaxDigits; ++j) {
+    if (j < a.beta) {
+      kb[j] = Split30(a.key[((size_t)(2 * j) * a.nprimes + p) * N + k]);
+      ka[j] = Split30(a.key[((size_t)(2 * j + 1) * a.nprimes + p) * N + k]);
+    }
+  }
+  const Mod m = a.mods[p];
+  const bool prep = a.pd != nullptr && t == a.nl - 1;
+  for (int b0 = 0; b0 < a.nbatch; b0 += ITEMS) {
+    const int nb = min(ITEMS, a.nbatch - b0);
+    Acc30 s0[ITEMS], s1[ITEMS];
+#pragma unroll
+    for (int j = 0; j < kMaxDigits; ++j) {
+      if (j < a.beta) {
+        const u64* src = (j == own) ? a.d + (size_t)t * N + kd : a.ext + ((size_t)j * a.ne + t) * N + kx;
+        const size_t stride = (j == own) ? a.sd : a.sext;
+        u64 ev[ITEMS];
+#pragma unroll
+        for (int q = 0; q < ITEMS; ++q) ev[q] = src[(size_t)(b0 + min(q, nb - 1)) * stride];
+#pragma unroll
+        for (int q = 0; q < ITEMS; ++q) {
+          const Split30 e(ev[q]);
+          s0[q].mac(e, kb[j]);
+          s1[q].mac(e, ka[j]);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < ITEMS; ++q) {
+      if (q < nb) {
+        u64* u = a.u + (size_t)(b0 + q) * a.su;
+        u64 v0 = s0[q].reduce(m), v1 = s1[q].reduce(m);
+        if (prep) {
+          const u64* d = a.pd + (size_t)(b0 + q) * a.spd + (size_t)t * N + k;
+          v0 = addm(v0, mul_shoup(d[0], a.pmod, a.pmods, m.q), m.q);
+          v1 = addm(v1, mul_shoup(d[(size_t)a.nl * N], a.pmod, a.pmods, m.q), m.q);
+        }
+        u[(size_t)t * N + k] = v0;
+        u[((size_t)a.ne + t) * N + k] = v1;
+      }
     }
   }
 }
@@ -847,9 +913,11 @@ void k_ks_inner(const Shared& sh, const u64* d, const u64* ext, const u64* key, 
   a.pofs = P.L + 1;
   a.nprimes = P.nprimes;
   a.nbatch = nbatch;
+  if (a.beta > kMaxDigits) PPST_THROW(ST_EINVAL, "more than 8 key-switching digits");
   dim3 g = grid_for((size_t)a.ne * P.N);
-  if (nbatch >= 8) {
-    g.y = (nbatch + 7) / 8;
+  if (nbatch > 8) {
+    hipLaunchKernelGGL(k_ks_inner_loop_kernel<4>, g, dim3(kBlock), 0, st, a);
+  } else if (nbatch == 8) {
     hipLaunchKernelGGL(k_ks_inner_kernel<8>, g, dim3(kBlock), 0, st, a);
   } else if (nbatch >= 4) {
     g.y = (nbatch + 3) / 4;

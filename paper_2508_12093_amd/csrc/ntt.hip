@@ -394,17 +394,24 @@ __device__ __forceinline__ void ntt_body_dio(const A ar, typename A::T* lds, con
   }
 }
 
+// Workgroup -> (limb, group, batch item) of tile `b` (see block_pos)
+__device__ __forceinline__ BlockPos tile_pos(unsigned b, int blocks_per_limb, int nbatch) {
+  const unsigned tile = b / (unsigned)nbatch;
+  BlockPos p;
+  p.item = (int)(b - tile * (unsigned)nbatch);
+  p.limb = (int)(tile / (unsigned)blocks_per_limb);
+  p.grp = (int)(tile - (unsigned)p.limb * (unsigned)blocks_per_limb);
+  return p;
+}
+
+// One tile of a pass: SB sub-problems of one limb of one batch item.
 template <int LOGM, int LOGE, int SB, bool ROWS, bool INV, bool DIO>
-__global__ void __launch_bounds__(SB * (1 << (LOGM - LOGE)))
-k_ntt_pass(NttArgs a) {
-  constexpr int M = 1 << LOGM;
-  __shared__ u64 lds[SB * (M + 1)];
+__device__ __forceinline__ void ntt_tile(const NttArgs& a, u64* lds, const BlockPos bp) {
   const int N = a.N;
-  const BlockPos bp = block_pos(a.blocks_per_limb, a.nbatch);
   const int limb_u = bp.limb;
   const int grp = bp.grp;
   int skip_lo = a.skip_lo, skip_hi = a.skip_hi;
-  if (a.dalpha > 0) {            // block-uniform: the whole workgroup leaves together
+  if (a.dalpha > 0) {            // tile-uniform: the whole workgroup skips together
     skip_lo = (bp.item % a.dcount) * a.dalpha;
     skip_hi = min(skip_lo + a.dalpha, a.nq);
     if (limb_u >= a.dtotal - (skip_hi - skip_lo)) return;
@@ -435,6 +442,26 @@ k_ntt_pass(NttArgs a) {
     else
       ntt_body<IntArith, LOGM, LOGE, SB, ROWS, INV>(IntArith(q), lds, src, dst, tw, ni, N,
                                                      a.logR, first, firstp, last, a.galois, a.logN);
+  }
+}
+
+template <int LOGM, int LOGE, int SB, bool ROWS, bool INV, bool DIO>
+__global__ void __launch_bounds__(SB * (1 << (LOGM - LOGE)))
+k_ntt_pass(NttArgs a) {
+  __shared__ u64 lds[SB * ((1 << LOGM) + 1)];
+  ntt_tile<LOGM, LOGE, SB, ROWS, INV, DIO>(a, lds, block_pos(a.blocks_per_limb, a.nbatch));
+}
+
+// Persistent form: a grid sized to what the device holds at once walks the
+// tiles (grid-stride), so a launch of thousands of tiles dispatches each
+// workgroup once; the barrier after each tile lets the next one reuse LDS.
+template <int LOGM, int LOGE, int SB, bool ROWS, bool INV, bool DIO>
+__global__ void __launch_bounds__(SB * (1 << (LOGM - LOGE)))
+k_ntt_pass_persistent(NttArgs a, unsigned ntiles) {
+  __shared__ u64 lds[SB * ((1 << LOGM) + 1)];
+  for (unsigned b = blockIdx.x; b < ntiles; b += gridDim.x) {
+    ntt_tile<LOGM, LOGE, SB, ROWS, INV, DIO>(a, lds, tile_pos(b, a.blocks_per_limb, a.nbatch));
+    __syncthreads();
   }
 }
 
@@ -683,6 +710,34 @@ void run_pass(const NttArgs& base, int nlimbs, int nbatch, hipStream_t st) {
   hipLaunchKernelGGL((k_ntt_pass<LOGM, LOGE, SB, ROWS, INV, DIO>), grid, block, 0, st, a);
 }
 
+// workgroups of a kernel the device holds at once (occupancy x CUs), asked
+// of the runtime once per kernel
+template <class K>
+unsigned resident_blocks(K kernel, int block) {
+  static unsigned cached = 0;
+  if (!cached) {
+    int per_cu = 0, cus = 0, dev = 0;
+    HIP_CHECK(hipGetDevice(&dev));
+    HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0));
+    cached = (unsigned)std::max(1, per_cu) * (unsigned)std::max(1, cus);
+  }
+  return cached;
+}
+
+template <int LOGM, int LOGE, int SB, bool ROWS, bool INV, bool DIO>
+void run_pass_persistent(const NttArgs& base, int nlimbs, int nbatch, hipStream_t st) {
+  NttArgs a = base;
+  const int nsub = ROWS ? (1 << a.logR) : (a.N >> a.logR);
+  a.blocks_per_limb = nsub / SB;
+  a.nbatch = nbatch;
+  const unsigned ntiles = (unsigned)a.blocks_per_limb * nlimbs * nbatch;
+  const int block = SB * (1 << (LOGM - LOGE));
+  auto kern = k_ntt_pass_persistent<LOGM, LOGE, SB, ROWS, INV, DIO>;
+  const unsigned grid = std::min(ntiles, resident_blocks(kern, block));
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, st, a, ntiles);
+}
+
 // Variant tables.  N = 2^16 runs a column pass and a row pass of 2^8 points;
 // N = 2^12 a single row pass of 2^12 points.  A variant fixes the register
 // radix (E = 2^LOGE elements per thread) and the sub-problems per workgroup.
@@ -698,13 +753,19 @@ struct Variant {
                          run_pass<8, LE, SB, true, false, D>, run_pass<8, LE, SB, true, true, D>}
 #define V12(LE, D) {D ? "full:E" #LE ",D" : "full:E" #LE, run_pass<12, LE, 1, true, false, D>, \
                     run_pass<12, LE, 1, true, true, D>}
+// "P": the persistent launch of a direct variant (run_pass_persistent)
+#define V16CP(LE, SB) {"col:E" #LE ",SB" #SB ",D,P", run_pass_persistent<8, LE, SB, false, false, true>, \
+                       run_pass_persistent<8, LE, SB, false, true, true>}
+#define V16RP(LE, SB) {"row:E" #LE ",SB" #SB ",D,P", run_pass_persistent<8, LE, SB, true, false, true>, \
+                       run_pass_persistent<8, LE, SB, true, true, true>}
 const Variant kCol16[] = {V16C(4, 16, false), V16C(3, 16, false), V16C(2, 16, false),
                           V16C(3, 8, false),  V16C(2, 8, false),  V16C(3, 16, true),
-                          V16C(2, 16, true),  V16C(2, 8, true),   V16C(4, 16, true)};
+                          V16C(2, 16, true),  V16C(2, 8, true),   V16C(4, 16, true),
+                          V16CP(3, 16),       V16CP(2, 16)};
 const Variant kRow16[] = {V16R(4, 16, false), V16R(4, 4, false), V16R(3, 8, false),
                           V16R(2, 4, false),  V16R(3, 4, false), V16R(2, 8, false),
                           V16R(3, 4, true),   V16R(2, 4, true),  V16R(3, 8, true),
-                          V16R(4, 4, true)};
+                          V16R(4, 4, true),   V16RP(3, 4),       V16RP(2, 4)};
 const Variant kFull12[] = {V12(4, false), V12(3, false), V12(2, false), V12(4, true), V12(3, true)};
 constexpr int kNCol16 = sizeof(kCol16) / sizeof(kCol16[0]);
 constexpr int kNRow16 = sizeof(kRow16) / sizeof(kRow16[0]);
@@ -808,7 +869,7 @@ static MdrFn mdr_variant(int logN, int row_index) {
   switch (row_index) {
     case 1: case 9: return run_row_mdr<8, 4, 4>;
     case 2: case 8: return run_row_mdr<8, 3, 8>;
-    case 3: case 7: return run_row_mdr<8, 2, 4>;
+    case 3: case 7: case 11: return run_row_mdr<8, 2, 4>;
     default: return run_row_mdr<8, 3, 4>;
   }
 }
@@ -876,7 +937,7 @@ static MdFn md_variant(int logN, int row_index) {
   switch (row_index) {
     case 1: case 9: return run_row_md<8, 4, 4>;
     case 2: case 8: return run_row_md<8, 3, 8>;
-    case 3: case 7: return run_row_md<8, 2, 4>;
+    case 3: case 7: case 11: return run_row_md<8, 2, 4>;
     default: return run_row_md<8, 3, 4>;
   }
 }
@@ -948,7 +1009,7 @@ static RsFn rs_variant(int logN, int row_index) {
   switch (row_index) {
     case 1: case 9: return run_row_rs<8, 4, 4>;
     case 2: case 8: return run_row_rs<8, 3, 8>;
-    case 3: case 7: return run_row_rs<8, 2, 4>;
+    case 3: case 7: case 11: return run_row_rs<8, 2, 4>;
     default: return run_row_rs<8, 3, 4>;
   }
 }
