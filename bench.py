@@ -75,7 +75,7 @@ def parse():
                     help="queries per load point of the serving loop (0: skip)")
     ap.add_argument("--serving-slots", type=int, default=8,
                     help="queries in flight at once (worker streams)")
-    ap.add_argument("--serving-loads", type=str, default="0.6",
+    ap.add_argument("--serving-loads", type=str, default="0.5,0.9",
                     help="offered loads as fractions of the measured saturation rate")
     return ap.parse_args()
 
@@ -436,8 +436,7 @@ def serving_bench(ctx, pk, sk, evk, nq: int, loads, seed: int = 4, nslots: int =
 
     info = ctx.info
     slots, L = info.slots, info.L
-    srv = ffi.ppst_server_create(ctx, evk, 96 << 30, nslots)
-    cols = {}
+    data = {}
     for i, n in enumerate(SERVING_ROWS):
         x, y = synth.lognormal_bernoulli_pair(seed + i, n)
         y = y / 4.0
@@ -445,9 +444,17 @@ def serving_bench(ctx, pk, sk, evk, nq: int, loads, seed: int = 4, nslots: int =
               for k, v in enumerate(synth.split_column(x, slots))]
         cy = [ffi.ppst_encrypt(ctx, pk, ffi.ppst_encode(ctx, v, L), 10000 * (i + 1) + 5000 + k)
               for k, v in enumerate(synth.split_column(y, slots))]
-        cols[n] = (ffi.ppst_server_register_column(srv, cx, n), ffi.ppst_server_register_column(srv, cy, n), x, y)
-        del cx, cy
+        data[n] = (cx, cy, x, y)
     ffi.ppst_sync(ctx)
+
+    def open_server(merge):
+        # admission by the device's free memory (budget 0)
+        s = ffi.ppst_server_create(ctx, evk, 0, nslots, merge=merge)
+        c = {n: (ffi.ppst_server_register_column(s, cx, n), ffi.ppst_server_register_column(s, cy, n), x, y)
+             for n, (cx, cy, x, y) in data.items()}
+        return s, c
+
+    srv, cols = open_server(True)
     cfg = ffi.ppst_invsqrt_cfg_default()
     # (kind, column, bounds): Var/B^2 inside [1e-3, 1] and mean/B_mean inside [0.6, 1.1]
     kinds = [(ffi.Q_MEAN, "y", 1.0, 1.0), (ffi.Q_VARIANCE, "y", 2.0, 2.0), (ffi.Q_ZSCORE, "y", 2.0, 2.0),
@@ -518,10 +525,22 @@ def serving_bench(ctx, pk, sk, evk, nq: int, loads, seed: int = 4, nslots: int =
                        "failed": nf})
         log("serving: offered %.1f q/s -> p50 %.1f ms, p99 %.1f ms" % (
             rate, points[-1]["p50_ms"], points[-1]["p99_ms"]))
+    info = ffi.ppst_server_info(srv)
     t = time.perf_counter()
     del srv
-    log("serving: server closed in %.1f s" % (time.perf_counter() - t))
-    return {"saturation_qps": round(sat_rate, 2), "queries_per_point": nq,
+    log("serving: server closed in %.1f s; merged rotate-and-sums %s" % (time.perf_counter() - t, info))
+    # the same saturation run without merging the queries' rotate-and-sums
+    srv, cols = open_server(False)
+    run([(k, n) for k in kinds for n in SERVING_ROWS], None)
+    _, _, wall0, nf0 = run(sat_q, None)
+    nfail += nf0
+    sat0 = len(sat_q) / wall0
+    log("serving: saturation without merging %.1f queries/s" % sat0)
+    del srv
+    return {"saturation_qps": round(sat_rate, 2), "saturation_qps_no_merge": round(sat0, 2),
+            "queries_per_point": nq, "budget_bytes": info["budget"],
+            "merged_rotsum_launches": info["merged_launches"], "merged_rotsum_lanes": info["merged_lanes"],
+            "multi_query_rotsum_launches": info["multi_query_launches"],
             "rows": SERVING_ROWS, "kinds": "mean,variance,zscore,cv,pearson", "slots": nslots,
             "loads": points, "failed": nfail, "spot_max_err": float(max(errs)) if errs else None}
 

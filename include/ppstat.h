@@ -461,12 +461,26 @@ typedef struct {
 } ppst_query;
 typedef struct {
   double t_submit, t_admit, t_done;   /* seconds, monotonic clock */
-  uint64_t bytes_reserved;
+  uint64_t bytes_reserved;            /* the admission estimate */
+  uint64_t bytes_peak;                /* device bytes its worker's pool held at most */
 } ppst_query_stats;
-/* waits until the device is idle (the keys may still be in generation on the
- * caller's stream), then starts `slots` workers with streams of their own */
+enum { PPST_SERVER_NO_MERGE = 1 };
+/* Waits until the device is idle (the keys may still be in generation on the
+ * caller's stream), then starts `slots` workers (1..16) with streams of their
+ * own.  Queries are admitted while the sum of their estimated peak device
+ * memory stays within hbm_budget; hbm_budget = 0 takes the device's free
+ * memory at creation less 2 GiB.  Unless flags has PPST_SERVER_NO_MERGE, the
+ * rotate-and-sums of queries running at once are merged into shared launches
+ * (the lanes of every worker that reaches one at the same level within
+ * 0.5 ms, up to 10 lanes, one key read per step for up to five of them);
+ * each result is bit for bit the one the query gets alone. */
 int ppst_server_create(ppst_context* ctx, const ppst_eval_keys* evk, size_t hbm_budget,
-                       int32_t slots, ppst_server** out);
+                       int32_t slots, uint32_t flags, ppst_server** out);
+/* the admission budget in force, and the merged rotate-and-sum launches run,
+ * the lanes they served and how many carried more than one query's lanes
+ * (any pointer may be NULL) */
+int ppst_server_info(ppst_server* srv, uint64_t* budget, uint64_t* merged_launches,
+                     uint64_t* merged_lanes, uint64_t* multi_query_launches);
 /* the server keeps its own copy of the ciphertexts; the call waits until the
  * device is idle first, so ciphertexts still being produced on any stream
  * (e.g. an asynchronous encryption) are complete when they are copied */

@@ -955,12 +955,26 @@ int ppst_ntt_plan(const ppst_context* ctx, char* buf, size_t cap) {
 
 // -------------------------------------------------------------- serving
 int ppst_server_create(ppst_context* ctx, const ppst_eval_keys* evk, size_t hbm_budget,
-                       int32_t slots, ppst_server** out) {
+                       int32_t slots, uint32_t flags, ppst_server** out) {
   return guard([&] {
     NEED(ctx); NEED(evk); NEED(out);
     NOT_RECORDING(ctx);
+    if (flags & ~(uint32_t)PPST_SERVER_NO_MERGE) PPST_THROW(ST_EINVAL, "unknown server flags");
     auto keys = std::make_shared<const EvalKeys>(evk->e);
-    *out = new ppst_server{std::make_unique<Server>(*ctx->cx, keys, hbm_budget, slots)};
+    *out = new ppst_server{std::make_unique<Server>(*ctx->cx, keys, hbm_budget, slots,
+                                                    !(flags & PPST_SERVER_NO_MERGE))};
+  });
+}
+int ppst_server_info(ppst_server* srv, uint64_t* budget, uint64_t* merged_launches,
+                     uint64_t* merged_lanes, uint64_t* multi_query_launches) {
+  return guard([&] {
+    NEED(srv);
+    u64 l = 0, n = 0, m = 0;
+    srv->s->merge_counters(&l, &n, &m);
+    if (budget) *budget = srv->s->budget();
+    if (merged_launches) *merged_launches = l;
+    if (merged_lanes) *merged_lanes = n;
+    if (multi_query_launches) *multi_query_launches = m;
   });
 }
 int ppst_server_register_column(ppst_server* srv, const ppst_ciphertext* const* cts, size_t nct,
@@ -1003,6 +1017,7 @@ void copy_stats(const QueryState& st, ppst_query_stats* stats) {
   stats->t_admit = st.t_admit;
   stats->t_done = st.t_done;
   stats->bytes_reserved = st.bytes;
+  stats->bytes_peak = st.peak;
 }
 }  // namespace
 

@@ -153,6 +153,10 @@ class Pool {
   void put(void* p, size_t bytes);
   size_t in_use() const { return in_use_; }
   size_t cached() const { return cached_; }
+  // the largest in_use() since the last reset_peak() (the serving loop checks
+  // its per-query estimates against it)
+  size_t peak() const { return peak_; }
+  void reset_peak();
   void trim();
   // The owning context is going away (its stream drained, about to be
   // destroyed): blocks still held by callers may outlive it, so from now on
@@ -193,7 +197,7 @@ class Pool {
   std::map<void*, int> slab_of_;   // carved block -> slab index
   std::vector<Slab> slabs_;
   int cur_ = -1;                   // slab being carved
-  size_t in_use_ = 0, cached_ = 0, nalloc_ = 0;
+  size_t in_use_ = 0, cached_ = 0, nalloc_ = 0, peak_ = 0;
   bool capturing_ = false;
   std::vector<void*> captured_;
   std::map<void*, bool> pinned_;   // block -> released by its owner
@@ -290,12 +294,24 @@ struct EvalKeys {
   std::map<u64, std::shared_ptr<KsKey>> galois;   // keyed by Galois element
 };
 
+struct Context;
+// Where a statistics circuit's rotate-and-sums go: with none set, straight to
+// rotsum_batch on the context's stream; a server installs one that merges the
+// lanes of concurrent queries into shared launches (results bit for bit the
+// same: the batched form equals the one-lane form).
+struct RotSumRouter {
+  virtual ~RotSumRouter() = default;
+  virtual std::vector<std::shared_ptr<Ciphertext>> rotsum(
+      Context& cx, const EvalKeys& evk, const std::vector<std::shared_ptr<Ciphertext>>& lanes) = 0;
+};
+
 struct Context {
   std::shared_ptr<Shared> sh;
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::shared_ptr<Pool> pool;    // temporaries and results on this stream
   bool recording = false;        // a graph recording is open on the stream
+  RotSumRouter* router = nullptr;
   const Params& P() const { return sh->P; }
 };
 

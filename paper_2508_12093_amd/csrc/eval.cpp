@@ -70,8 +70,14 @@ void* Pool::alloc_retry(size_t bytes) {
   return p;
 }
 
+void Pool::reset_peak() {
+  std::lock_guard<std::mutex> g(mu_);
+  peak_ = in_use_;
+}
+
 void* Pool::hand_out(void* p, size_t bytes) {
   in_use_ += bytes;
+  if (in_use_ > peak_) peak_ = in_use_;
   sizes_[p] = bytes;
   auto s = slab_of_.find(p);
   if (s != slab_of_.end()) ++slabs_[s->second].inuse;
@@ -1386,8 +1392,11 @@ namespace {
 // sum_{0<k<radix} rot(ct_i, k s), with one ModUp of each c1, the radix - 1
 // permuted inner products (and P times c0's permutations) added in the
 // extended basis, and one ModDown whose last pass adds the item itself.
+// into: when given, the outputs are these ciphertexts (allocated by the
+// caller, same level and scale as the inputs) instead of new ones
 std::vector<CtPtr> rotsum_step(Context& cx, const EvalKeys& evk,
-                               const std::vector<const Ciphertext*>& cts, long s, int radix) {
+                               const std::vector<const Ciphertext*>& cts, long s, int radix,
+                               const std::vector<CtPtr>* into = nullptr) {
   const Params& P = cx.P();
   const Shared& sh = *cx.sh;
   const size_t n = cts.size();
@@ -1418,7 +1427,7 @@ std::vector<CtPtr> rotsum_step(Context& cx, const EvalKeys& evk,
       d[i] = c.poly(1);
       add[i] = c.poly(0);
       acc[i] = c.buf.p;
-      outs[b0 + i] = new_ct(cx, level, c.scale);
+      outs[b0 + i] = into ? (*into)[b0 + i] : new_ct(cx, level, c.scale);
       po[i] = outs[b0 + i]->buf.p;
     }
     // the c1 polynomials side by side (one gather launch unless there is
@@ -1457,16 +1466,41 @@ std::vector<CtPtr> rotsum_step(Context& cx, const EvalKeys& evk,
 }  // namespace
 
 std::vector<CtPtr> rotsum_batch(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& cts) {
+  return rotsum_batch_into(cx, evk, cts, {});
+}
+
+std::vector<CtPtr> rotsum_batch_into(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& cts,
+                                     const std::vector<CtPtr>& outs) {
   std::vector<CtPtr> cur = cts;
   if (cur.empty()) return cur;
   for (const CtPtr& c : cur) {
     if (c->npoly != 2) PPST_THROW(ST_EINVAL, "rotate-and-sum expects degree-1 ciphertexts");
     if (c->level != cur[0]->level) PPST_THROW(ST_ESCALE, "batch members at different levels");
   }
-  for (const auto& st : rotsum_plan(cx.P())) {
+  if (!outs.empty()) {
+    if (outs.size() != cts.size()) PPST_THROW(ST_EINVAL, "rotate-and-sum outputs differ in number");
+    for (size_t i = 0; i < outs.size(); ++i)
+      if (outs[i]->level != cts[i]->level || outs[i]->npoly != 2 || outs[i]->N != cts[i]->N)
+        PPST_THROW(ST_EINVAL, "rotate-and-sum output of the wrong shape");
+  }
+  const auto plan = rotsum_plan(cx.P());
+  if (plan.empty()) {                      // one slot: the sum is the input
+    if (outs.empty()) {
+      std::vector<CtPtr> r;
+      for (const CtPtr& c : cts) r.push_back(copy_ct(cx, *c));
+      return r;
+    }
+    for (size_t i = 0; i < outs.size(); ++i)
+      HIP_CHECK(hipMemcpyAsync(outs[i]->buf.p, cts[i]->buf.p, cts[i]->buf.bytes,
+                               hipMemcpyDeviceToDevice, cx.stream));
+    return outs;
+  }
+  for (size_t k = 0; k < plan.size(); ++k) {
     std::vector<const Ciphertext*> v;
     for (const CtPtr& c : cur) v.push_back(c.get());
-    cur = rotsum_step(cx, evk, v, st.first, st.second);
+    const bool last = k + 1 == plan.size();
+    cur = rotsum_step(cx, evk, v, plan[k].first, plan[k].second,
+                      last && !outs.empty() ? &outs : nullptr);
   }
   return cur;
 }

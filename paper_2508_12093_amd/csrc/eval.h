@@ -87,6 +87,11 @@ CtPtr rotsum(Context& cx, const EvalKeys& evk, const Ciphertext& a);
 CtPtr rotsum_serial(Context& cx, const EvalKeys& evk, const Ciphertext& a);
 // rotsum() of several ciphertexts of one level, each step batched
 std::vector<CtPtr> rotsum_batch(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& cts);
+// rotsum_batch whose results are written into `outs` (caller-allocated, one
+// per input, of its level and scale; empty: new ones), for a caller whose
+// lanes come from other streams and must land in memory they own
+std::vector<CtPtr> rotsum_batch_into(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& cts,
+                                     const std::vector<CtPtr>& outs);
 // (s, radix) per step: radix 8 while three or more bits of the slot index
 // remain, then radix 4 or 2 for the rest; the Galois keys needed are those of
 // k s, 0 < k < radix

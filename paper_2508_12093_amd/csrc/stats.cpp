@@ -147,7 +147,10 @@ struct Circ {
     for (size_t i = 1; i < xs.size(); ++i) acc = addx(acc, xs[i]);
     return acc;
   }
-  CtPtr rs(const CtPtr& a) { return rotsum(cx, evk, *a); }
+  CtPtr rs(const CtPtr& a) {
+    if (cx.router) return cx.router->rotsum(cx, evk, {a})[0];
+    return rotsum(cx, evk, *a);
+  }
 
   // RotSum(sum_c Z_c mask_c), mask 1/n on rows < n: the full ciphertexts are
   // added first and scaled by 1/n once; a ragged last one takes its row mask
@@ -273,7 +276,8 @@ struct Circ {
   std::vector<CtPtr> rs_n(const std::vector<CtPtr>& xs) {
     bool same = true;
     for (auto& x : xs) same = same && x->level == xs[0]->level;
-    if (same && xs.size() > 1) return rotsum_batch(cx, evk, xs);
+    if (same && xs.size() > 1)
+      return cx.router ? cx.router->rotsum(cx, evk, xs) : rotsum_batch(cx, evk, xs);
     std::vector<CtPtr> out;
     for (auto& x : xs) out.push_back(rs(x));
     return out;

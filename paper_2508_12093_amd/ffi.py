@@ -54,7 +54,8 @@ class Query(ctypes.Structure):
 
 class QueryStats(ctypes.Structure):
     _fields_ = [("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
-                ("t_done", ctypes.c_double), ("bytes_reserved", ctypes.c_uint64)]
+                ("t_done", ctypes.c_double), ("bytes_reserved", ctypes.c_uint64),
+                ("bytes_peak", ctypes.c_uint64)]
 
 
 HooksAlloc = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
@@ -157,7 +158,8 @@ _SIGS = {
     "ppst_ntt_set_plan": (ctypes.c_int, [_vp, _i32, _i32]),
     "ppst_ntt_forward": (ctypes.c_int, [_vp, _vp, _i32, _i32]),
     "ppst_ntt_inverse": (ctypes.c_int, [_vp, _vp, _i32, _i32]),
-    "ppst_server_create": (ctypes.c_int, [_vp, _vp, _sz, _i32, _pp]),
+    "ppst_server_create": (ctypes.c_int, [_vp, _vp, _sz, _i32, ctypes.c_uint32, _pp]),
+    "ppst_server_info": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "ppst_server_register_column": (ctypes.c_int, [_vp, _pp, _sz, _sz, ctypes.POINTER(_u64)]),
     "ppst_server_submit": (ctypes.c_int, [_vp, ctypes.POINTER(Query), ctypes.POINTER(_u64)]),
     "ppst_server_wait": (ctypes.c_int, [_vp, _u64, _pp, ctypes.POINTER(QueryStats)]),
@@ -778,12 +780,24 @@ def ppst_ntt_inverse(ctx: Context, dev_ptr: int, nlimbs: int, first_prime: int):
     _chk(lib().ppst_ntt_inverse(ctx, ctypes.c_void_p(dev_ptr), nlimbs, first_prime))
 
 
-def ppst_server_create(ctx, evk, hbm_budget: int, slots: int) -> Server:
+SERVER_NO_MERGE = 1
+
+
+def ppst_server_create(ctx, evk, hbm_budget: int, slots: int, merge: bool = True) -> Server:
+    """hbm_budget 0: the device's free memory at creation less 2 GiB."""
     out = _out()
-    _chk(lib().ppst_server_create(ctx, evk, hbm_budget, slots, ctypes.byref(out)))
+    _chk(lib().ppst_server_create(ctx, evk, hbm_budget, slots, 0 if merge else SERVER_NO_MERGE,
+                                  ctypes.byref(out)))
     s = Server(out.value, ctx)
     s.evk = evk
     return s
+
+
+def ppst_server_info(srv: Server) -> dict:
+    v = [ctypes.c_uint64() for _ in range(4)]
+    _chk(lib().ppst_server_info(srv, *[ctypes.byref(x) for x in v]))
+    return {"budget": v[0].value, "merged_launches": v[1].value, "merged_lanes": v[2].value,
+            "multi_query_launches": v[3].value}
 
 
 def ppst_server_register_column(srv: Server, cts, nrows: int) -> int:

@@ -91,6 +91,9 @@ def test_mixed_stream_equals_alone(env):
                 overlap += 1
                 break
     assert overlap > 0, "no two queries were in flight together"
+    info = ffi.ppst_server_info(srv)
+    print("[serving] merged rotate-and-sums:", info, flush=True)
+    assert info["merged_lanes"] >= info["merged_launches"] > 0
     # decrypted values are the statistics
     n, x, y, cx, cy = cols["c"]
     rc, ct, _ = results[[k for k, p in enumerate(plan) if p[0] == ffi.Q_PEARSON and p[1] == "c"][0]]
@@ -123,6 +126,27 @@ def test_admission_by_memory(env):
         assert b[2].t_admit >= a[2].t_done
     ref = ffi.ppst_ct_export(ctx, res[0][1])
     assert all(np.array_equal(ffi.ppst_ct_export(ctx, r[1]), ref) for r in res)
+
+
+def test_estimates_cover_peaks(env):
+    """Each query's admission estimate covers the device memory its worker
+    actually held (queries run one at a time, no merging)."""
+    ctx, sk, evk, cols = env
+    cfg = ffi.ppst_invsqrt_cfg_default()
+    srv = ffi.ppst_server_create(ctx, evk, 8 << 30, 1, merge=False)
+    n, x, y, cx, cy = cols["c"]
+    cid, yid = ffi.ppst_server_register_column(srv, cx, n), ffi.ppst_server_register_column(srv, cy, n)
+    for kind, col, B, B2 in [(ffi.Q_MEAN, cid, 1.0, 1.0), (ffi.Q_VARIANCE, cid, 2.0, 2.0),
+                             (ffi.Q_ZSCORE, yid, 2.0, 2.0), (ffi.Q_CV, yid, 1.0, 2.0),
+                             (ffi.Q_PEARSON, cid, 1.0, 2.0), (ffi.Q_KURTOSIS, yid, 2.0, 2.0)]:
+        rc, ct, st = ffi.ppst_server_wait(srv, ffi.ppst_server_submit(srv, kind, col, yid, B, B2, cfg))
+        assert rc == 0
+        print("[serving] kind %d: estimate %d, peak %d bytes" % (kind, st.bytes_reserved, st.bytes_peak),
+              flush=True)
+        assert 0 < st.bytes_peak <= st.bytes_reserved, (kind, st.bytes_peak, st.bytes_reserved)
+    assert ffi.ppst_server_info(srv)["merged_launches"] == 0
+    free = ffi.ppst_server_create(ctx, evk, 0, 1)         # admission by the device's free memory
+    assert ffi.ppst_server_info(free)["budget"] > (1 << 30)
 
 
 def test_bad_queries(env):
@@ -225,3 +249,41 @@ def test_results_outlive_the_server(env):
     del outs, ct
     again = ffi.ppst_stat_mean(ctx, evk, cy, n, 1.0)
     assert abs(ffi.ppst_decode(ctx, ffi.ppst_decrypt(ctx, sk, again))[0] - y.mean()) < 1e-3
+
+
+def test_c2_mixed_stream_equals_alone():
+    """N = 2^16, L = 24, config-2 columns (x ~ Bernoulli(0.2), lognormal y):
+    mean, variance, z-score, CV and Pearson twice each on 8 workers, their
+    rotate-and-sums merged across queries, give the same result ciphertexts
+    as the same calls made one at a time."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    print("\n[serving] preset c2", flush=True)
+    ctx = ffi.ppst_context_create("c2")
+    sk, pk = ffi.ppst_keygen(ctx, 15)
+    evk = ffi.ppst_evk_create(ctx)
+    ffi.ppst_evk_add_relin(ctx, sk, 16, evk)
+    ffi.ppst_evk_add_rotsum(ctx, sk, 17, evk)
+    x, y = synth.binary_cost_pair(3)
+    n, L = len(x), ctx.info.L
+    cx = [ffi.ppst_encrypt(ctx, pk, ffi.ppst_encode(ctx, x, L), 301)]
+    cy = [ffi.ppst_encrypt(ctx, pk, ffi.ppst_encode(ctx, y, L), 302)]
+    cfg = ffi.ppst_invsqrt_cfg_default()
+    srv = ffi.ppst_server_create(ctx, evk, 0, 8)
+    xid, yid = ffi.ppst_server_register_column(srv, cx, n), ffi.ppst_server_register_column(srv, cy, n)
+    # y: mean ~18, variance ~300 -> Var/B^2 in [1e-3, 1] with B = 20, mean/B_mean in [0.6, 1.1] with 25
+    plan = [(ffi.Q_MEAN, 20.0, 20.0), (ffi.Q_VARIANCE, 20.0, 20.0), (ffi.Q_ZSCORE, 20.0, 20.0),
+            (ffi.Q_CV, 25.0, 20.0), (ffi.Q_PEARSON, 1.0, 20.0)] * 2
+    tickets = [ffi.ppst_server_submit(srv, k, xid if k == ffi.Q_PEARSON else yid, yid, B, B2, cfg)
+               for k, B, B2 in plan]
+    res = [ffi.ppst_server_wait(srv, t) for t in tickets]
+    info = ffi.ppst_server_info(srv)
+    print("[serving] c2 merged rotate-and-sums:", info, flush=True)
+    for (k, B, B2), (rc, ct, st) in zip(plan, res):
+        assert rc == 0, (k, ffi.lib().ppst_last_error())
+        alone = direct(ctx, evk, k, cx if k == ffi.Q_PEARSON else cy, cy, n, B, B2, cfg)
+        assert np.array_equal(ffi.ppst_ct_export(ctx, ct), ffi.ppst_ct_export(ctx, alone)), k
+    assert info["multi_query_launches"] > 0, info
+    got = ffi.ppst_decode(ctx, ffi.ppst_decrypt(ctx, sk, res[4][1]))[0]
+    assert abs(got - S.pearson(x, y)) / abs(S.pearson(x, y)) < 1e-3
