@@ -81,3 +81,16 @@ def exp1_mre(degree: int = 31, iters: int = 6, B: float = 100.0) -> float:
     y = exp1_model(v, degree, iters, B)
     ref = 1.0 / np.sqrt(v)
     return float(np.mean(np.abs(y - ref) / np.abs(ref)))
+
+
+def evalmod_cos_coeffs(K: int, r: int, degree: int) -> np.ndarray:
+    """Coefficients c_0..c_d (first kind) of cos(2 pi (K u - 1/4) / 2^r) on
+    u in [-1, 1], interpolated at the first-kind nodes: EvalMod's polynomial
+    (bootstrapping, Sec. 3.2; Sec. 3.4 names Chebyshev approximation
+    of the sine in the modular reduction).  r double angles y <- 2 y^2 - 1
+    turn it into cos(2 pi K u - pi/2) = sin(2 pi x) at x = K u, which is
+    2 pi (x - I) + O((x - I)^3) near every integer I."""
+    def f(u):
+        return np.cos(2.0 * np.pi * (K * u - 0.25) / float(2 ** r))
+
+    return C.chebinterpolate(f, degree)

@@ -232,15 +232,12 @@ class Circuits:
         return self.subx(e2, m2)
 
     # Alg. 3 + Alg. 2 -------------------------------------------------------
-    def inv_sqrt(self, v, Bp, cfg: InvSqrtCfg):
-        """y ~ 1/sqrt(Bp v); returns (y, w2) with w2 = (Bp/2) v."""
+    def cheb_series(self, t, coeffs, d):
+        """sum_{k<=d} c_k T_k(t): T_1 = t, T_2m = 2 T_m^2 - 1,
+        T_2m+1 = 2 T_m T_m+1 - T_1 (each the product of two lower terms, so
+        T_k sits ceil(log2 k) levels below t), then c_1..c_d combined at one
+        level below the lowest T_k with one rescale, and c_0 added."""
         ev = self.ev
-        a, b, d = cfg.a, cfg.b, cfg.degree
-        coeffs = cfg.coeffs_for(Bp)
-        # the affine map onto [-1, 1]; a pure shift (b - a = 2, Eq. 1's
-        # x - 1 on [0, 2]) needs no product and no level
-        g = 2.0 / (b - a)
-        t = ev.add_const(v if g == 1.0 else ev.mul_const(v, g), -(a + b) / (b - a))
         T = {1: t}
         for k in range(2, d + 1):
             if k % 2 == 0:
@@ -251,7 +248,18 @@ class Circuits:
                 T[k] = self.subx(ev.mul_int(self.mulx(T[m], T[m + 1]), 2), T[1])
         y = ev.lincomb([T[k] for k in range(1, d + 1)], [float(coeffs[k]) for k in range(1, d + 1)],
                        min(ev.level(T[k]) for k in range(1, d + 1)) - 1)
-        y = ev.add_const(y, float(coeffs[0]))
+        return ev.add_const(y, float(coeffs[0]))
+
+    def inv_sqrt(self, v, Bp, cfg: InvSqrtCfg):
+        """y ~ 1/sqrt(Bp v); returns (y, w2) with w2 = (Bp/2) v."""
+        ev = self.ev
+        a, b, d = cfg.a, cfg.b, cfg.degree
+        coeffs = cfg.coeffs_for(Bp)
+        # the affine map onto [-1, 1]; a pure shift (b - a = 2, Eq. 1's
+        # x - 1 on [0, 2]) needs no product and no level
+        g = 2.0 / (b - a)
+        t = ev.add_const(v if g == 1.0 else ev.mul_const(v, g), -(a + b) / (b - a))
+        y = self.cheb_series(t, coeffs, d)
         w2 = ev.mul_const(v, Bp / 2.0)
         for _ in range(cfg.iters):
             y2 = ev.mul(y, y)

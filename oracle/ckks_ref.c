@@ -29,17 +29,9 @@
 #include <string.h>
 #include <math.h>
 
-typedef uint64_t u64;
+#include "ckks_ref.h"
+
 typedef unsigned __int128 u128;
-
-#define ORC_MAXP 64
-
-typedef struct {
-    int32_t logN, N, L, K, dnum, alpha;
-    u64 q[ORC_MAXP];      /* combined prime list */
-    u64 psi[ORC_MAXP];    /* primitive 2N-th root of unity per prime */
-    double scale[ORC_MAXP]; /* canonical scale Delta_l, l = 0..L */
-} orc_params;
 
 /* ------------------------------------------------------------------ */
 /* modular arithmetic on residues in [0,q)                             */
@@ -160,6 +152,82 @@ int orc_params_make(int logN, int L, int K, int dnum, int q0_bits, double delta,
         double sq = out->scale[l] * out->scale[l];
         double target = sq / delta;
         u64 p = nearest_prime(target, twoN, used, nused);
+        out->q[l] = p;
+        used[nused++] = p;
+        out->scale[l - 1] = sq / (double)p;
+    }
+    for (int k = 0; k < K; k++) {
+        u64 p = largest_prime_below(p_bits, twoN, used, nused);
+        out->q[L + 1 + k] = p;
+        used[nused++] = p;
+    }
+    for (int i = 0; i < L + 1 + K; i++) {
+        if (out->q[i] == 0) return -2;
+        out->psi[i] = find_psi(out->q[i], out->N);
+    }
+    return 0;
+}
+
+/*
+ * Bootstrappable chain (a reading: the paper's set has a depth of 27 of which
+ * 11 levels are usable between bootstraps, Sec. 6.1, and leaves the rest to
+ * the cited bootstrapping).  From the top level L down: C levels for
+ * CoeffToSlot, E for EvalMod, S for SlotToCoeff, then Lc = L - C - E - S
+ * levels of computation, then q_0.  Primes, in the order they are chosen:
+ *   q_0                 largest prime < 2^q0_bits, = 1 mod 2N;
+ *   q_L..q_{L-C+1}      the largest unused primes < 2^p_bits (CoeffToSlot);
+ *   q_l, l = L-C..Lc+S+1  the unused prime nearest Delta_l^2 / Delta_b, with
+ *                       Delta_{L-C} = Delta_b and Delta_{l-1} = Delta_l^2 / q_l;
+ *   q_{Lc+S}..q_{Lc+1}  the largest unused primes < 2^p_bits (SlotToCoeff);
+ *   q_l, l = Lc..1      the unused prime nearest Delta_l^2 / Delta, with
+ *                       Delta_Lc = Delta and Delta_{l-1} = Delta_l^2 / q_l;
+ *   p_0..p_{K-1}        the K largest unused primes < 2^p_bits.
+ * Scales of the levels the linear transforms end on (no product of two
+ * ciphertexts is rescaled there): Delta_l = Delta_b for l >= L - C, and
+ * Delta_{Lc+i} = Delta * 2^floor(i e / S) for 0 < i < S, with e the
+ * difference of the binary exponents of Delta_b and Delta.
+ */
+int orc_params_make_boot(int logN, int Lc, int C, int E, int S, int K, int dnum, int q0_bits,
+                         double delta, double delta_b, int p_bits, orc_params* out) {
+    int L = Lc + C + E + S;
+    if (logN < 2 || logN > 17 || Lc < 1 || C < 1 || E < 1 || S < 1 || K < 1 ||
+        L + 1 + K > ORC_MAXP || dnum < 1)
+        return -1;
+    memset(out, 0, sizeof(*out));
+    out->logN = logN;
+    out->N = 1 << logN;
+    out->L = L;
+    out->K = K;
+    out->dnum = dnum;
+    out->alpha = (L + 1 + dnum - 1) / dnum;
+    u64 twoN = 2 * (u64)out->N;
+    u64 used[ORC_MAXP];
+    int nused = 0;
+    out->q[0] = largest_prime_below(q0_bits, twoN, used, nused);
+    used[nused++] = out->q[0];
+    for (int l = L; l > L - C; l--) {
+        out->q[l] = largest_prime_below(p_bits, twoN, used, nused);
+        used[nused++] = out->q[l];
+        out->scale[l] = delta_b;
+    }
+    out->scale[L - C] = delta_b;
+    for (int l = L - C; l > Lc + S; l--) {
+        double sq = out->scale[l] * out->scale[l];
+        u64 p = nearest_prime(sq / delta_b, twoN, used, nused);
+        out->q[l] = p;
+        used[nused++] = p;
+        out->scale[l - 1] = sq / (double)p;
+    }
+    for (int l = Lc + S; l > Lc; l--) {
+        out->q[l] = largest_prime_below(p_bits, twoN, used, nused);
+        used[nused++] = out->q[l];
+    }
+    int e = ilogb(delta_b) - ilogb(delta);
+    for (int i = 1; i < S; i++) out->scale[Lc + i] = ldexp(delta, (i * e) / S);
+    out->scale[Lc] = delta;
+    for (int l = Lc; l >= 1; l--) {
+        double sq = out->scale[l] * out->scale[l];
+        u64 p = nearest_prime(sq / delta, twoN, used, nused);
         out->q[l] = p;
         used[nused++] = p;
         out->scale[l - 1] = sq / (double)p;
@@ -390,7 +458,49 @@ int orc_encode_coeffs(const orc_params* P, const double* m, int n_used, double s
     return 0;
 }
 
+/* The same for complex slot values m_j = mre_j + i mim_j:
+ *   p_k = (2/N) Re sum_j m_j xi_j^(-k)  (the inverse of the canonical
+ * embedding of a real polynomial), pt_k = round_half_away(scale * p_k). */
+int orc_encode_coeffs_complex(const orc_params* P, const double* mre, const double* mim, int n_used,
+                              double scale, int64_t* out) {
+    int N = P->N, n = N / 2;
+    if (n_used < 0 || n_used > n) return -1;
+    long double* re = (long double*)calloc(2 * (size_t)N, sizeof(long double));
+    long double* im = (long double*)calloc(2 * (size_t)N, sizeof(long double));
+    int* e = (int*)malloc(sizeof(int) * n);
+    slot_exponents(N, e);
+    for (int j = 0; j < n_used; j++) {
+        re[e[j]] = (long double)mre[j];
+        im[e[j]] = (long double)mim[j];
+    }
+    fft_ld(re, im, 2 * N, -1);
+    for (int k = 0; k < N; k++) {
+        long double v = (2.0L / (long double)N) * re[k];
+        out[k] = llroundl((long double)scale * v);
+    }
+    free(re); free(im); free(e);
+    return 0;
+}
+
 /* m_j = Re sum_k c_k xi_j^k / scale, from centred integer coefficients */
+/* complex slots m_j = sum_k c_k xi_j^k / scale (real and imaginary parts) */
+int orc_decode_coeffs_complex(const orc_params* P, const int64_t* c, double scale, double* ore,
+                              double* oim) {
+    int N = P->N, n = N / 2;
+    long double* re = (long double*)calloc(2 * (size_t)N, sizeof(long double));
+    long double* im = (long double*)calloc(2 * (size_t)N, sizeof(long double));
+    int* e = (int*)malloc(sizeof(int) * n);
+    slot_exponents(N, e);
+    for (int k = 0; k < N; k++) re[k] = (long double)c[k];
+    fft_ld(re, im, 2 * N, +1);
+    for (int j = 0; j < n; j++) {
+        ore[j] = (double)(re[e[j]] / (long double)scale);
+        oim[j] = (double)(im[e[j]] / (long double)scale);
+    }
+    free(re); free(im); free(e);
+    return 0;
+}
+
 int orc_decode_coeffs(const orc_params* P, const int64_t* c, double scale, double* out) {
     int N = P->N, n = N / 2;
     long double* re = (long double*)calloc(2 * (size_t)N, sizeof(long double));
@@ -427,6 +537,39 @@ void orc_keygen_secret(const orc_params* P, u64 seed, int8_t* s_coef, u64* s_ntt
     orc_from_signed(P, c, np, pidx, s_ntt);
     orc_ntt(P, s_ntt, np, pidx);
     free(c);
+}
+
+/* Sparse ternary secret with exactly h nonzero coefficients (the sparse
+ * secrets of CKKS bootstrapping).  From the secret-key stream's words
+ * w_0, w_1, ...: positions are the first h entries of a Fisher-Yates shuffle
+ * of 0..N-1 in which step i swaps entries i and i + (w_i mod (N - i)); the
+ * coefficient at the i-th position is -1 when the top bit of w_{h+i} is set,
+ * else +1. */
+int orc_keygen_secret_sparse(const orc_params* P, u64 seed, int h, int8_t* s_coef, u64* s_ntt) {
+    int N = P->N, np = P->L + 1 + P->K;
+    if (h < 1 || h > N) return -1;
+    u64 st = stream_key(seed, purpose(PUR_SK, 0, 0), 0);
+    int32_t* perm = (int32_t*)malloc(sizeof(int32_t) * N);
+    for (int k = 0; k < N; k++) perm[k] = k;
+    for (int i = 0; i < h; i++) {
+        u64 w = sm_next(&st);
+        int j = i + (int)(w % (u64)(N - i));
+        int32_t t = perm[i]; perm[i] = perm[j]; perm[j] = t;
+    }
+    memset(s_coef, 0, (size_t)N);
+    for (int i = 0; i < h; i++) {
+        u64 w = sm_next(&st);
+        s_coef[perm[i]] = (w >> 63) ? -1 : 1;
+    }
+    int64_t* c = (int64_t*)malloc(sizeof(int64_t) * N);
+    for (int k = 0; k < N; k++) c[k] = s_coef[k];
+    int32_t pidx[ORC_MAXP];
+    seq_pidx(pidx, np);
+    orc_from_signed(P, c, np, pidx, s_ntt);
+    orc_ntt(P, s_ntt, np, pidx);
+    free(c);
+    free(perm);
+    return 0;
 }
 
 /* pk = (b, a) over Q_L: a uniform (drawn directly in NTT form), b = -a s + e */

@@ -34,6 +34,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ckks_ref.c")
+_SRCS = [_SRC, os.path.join(_HERE, "boot_ref.c")]
+_HDR = os.path.join(_HERE, "ckks_ref.h")
 _SO = os.path.join(_HERE, "libckks_ref.so")
 
 MAXP = 64
@@ -45,12 +47,13 @@ PUR_ENC_V, PUR_ENC_E0, PUR_ENC_E1, PUR_SKE_A, PUR_SKE_E = 6, 7, 8, 9, 10
 
 
 def build(force: bool = False) -> str:
-    """Compile ckks_ref.c with gcc into oracle/libckks_ref.so (portable
-    flags: the file travels to other hosts)."""
-    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+    """Compile ckks_ref.c and boot_ref.c with gcc into oracle/libckks_ref.so
+    (portable flags: the file travels to other hosts)."""
+    newest = max(os.path.getmtime(f) for f in _SRCS + [_HDR])
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < newest:
         tmp = _SO + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
-               "-o", tmp, _SRC, "-lm"]
+        cmd = ["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-I" + _HERE,
+               "-o", tmp] + _SRCS + ["-lquadmath", "-lm"]
         subprocess.check_call(cmd)
         os.replace(tmp, _SO)
     return _SO
@@ -63,7 +66,7 @@ def build_native(out: str) -> str:
     1.5x slower).  Load it by starting a process with PPST_ORACLE_SO set to
     `out`."""
     cmd = ["gcc", "-O2", "-march=native", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
-           "-o", out, _SRC, "-lm"]
+           "-I" + _HERE, "-o", out] + _SRCS + ["-lquadmath", "-lm"]
     subprocess.check_call(cmd)
     return out
 
@@ -106,6 +109,8 @@ def lib():
             "orc_sample_dg": (None, [u64, u64, ctypes.c_int, vp]),
             "orc_encode_coeffs": (ctypes.c_int, [PP, vp, ctypes.c_int, dbl, vp]),
             "orc_decode_coeffs": (ctypes.c_int, [PP, vp, dbl, vp]),
+            "orc_encode_coeffs_complex": (ctypes.c_int, [PP, vp, vp, ctypes.c_int, dbl, vp]),
+            "orc_decode_coeffs_complex": (ctypes.c_int, [PP, vp, dbl, vp, vp]),
             "orc_from_signed": (None, [PP, vp, ctypes.c_int, vp, vp]),
             "orc_keygen_secret": (None, [PP, u64, vp, vp]),
             "orc_keygen_public": (None, [PP, u64, vp, vp]),
@@ -129,6 +134,11 @@ def lib():
             "orc_round_half_away": (i64, [dbl]),
             "orc_mulmod_vec": (None, [vp, vp, vp, ctypes.c_int, u64]),
             "orc_splitmix64_next": (u64, [u64]),
+            "orc_params_make_boot": (ctypes.c_int, [ctypes.c_int] * 8 + [dbl, dbl, ctypes.c_int, PP]),
+            "orc_keygen_secret_sparse": (ctypes.c_int, [PP, u64, ctypes.c_int, vp, vp]),
+            "orc_boot_group_diags": (ctypes.c_int, [ctypes.c_int] * 5 + [vp, vp, vp]),
+            "orc_boot_group_factor": (dbl, [PP] + [ctypes.c_int] * 4),
+            "orc_boot_grid": (ctypes.c_int, [PP] + [ctypes.c_int] * 11 + [vp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -157,15 +167,30 @@ PRESETS = {
     "t1": dict(logN=12, L=6, K=3, dnum=3, q0_bits=60, delta=2.0 ** 40, p_bits=60),
     # the c2 prime chain (L=24, dnum=3, 7 special primes) at N=2^12, for circuits
     "t2": dict(logN=12, L=24, K=7, dnum=3, q0_bits=60, delta=2.0 ** 40, p_bits=60),
+    # bootstrappable chain (orc_params_make_boot): 11 computation levels at
+    # Delta = 2^40 under 3 SlotToCoeff, 10 EvalMod (Delta_b = 2^58) and 3
+    # CoeffToSlot levels (L = 27), sparse secret of weight 64, dnum = 4
+    "b2": dict(logN=16, Lc=11, boot=(3, 10, 3), K=8, dnum=4, q0_bits=60, delta=2.0 ** 40,
+               delta_b=2.0 ** 58, p_bits=60, h=64),
+    # the b2 chain at N=2^12
+    "b1": dict(logN=12, Lc=11, boot=(3, 10, 3), K=8, dnum=4, q0_bits=60, delta=2.0 ** 40,
+               delta_b=2.0 ** 58, p_bits=60, h=64),
 }
 
 
 class Params:
-    def __init__(self, logN, L, K, dnum, q0_bits, delta, p_bits):
+    def __init__(self, logN, L=None, K=1, dnum=1, q0_bits=60, delta=2.0 ** 40, p_bits=60,
+                 Lc=None, boot=None, delta_b=None, h=0):
         self.c = OrcParams()
-        rc = lib().orc_params_make(logN, L, K, dnum, q0_bits, float(delta), p_bits, ctypes.byref(self.c))
+        if boot is None:
+            rc = lib().orc_params_make(logN, L, K, dnum, q0_bits, float(delta), p_bits, ctypes.byref(self.c))
+        else:
+            C, E, S = boot
+            L = Lc + C + E + S
+            rc = lib().orc_params_make_boot(logN, Lc, C, E, S, K, dnum, q0_bits, float(delta),
+                                            float(delta_b), p_bits, ctypes.byref(self.c))
         if rc != 0:
-            raise ValueError("orc_params_make failed: %d" % rc)
+            raise ValueError("parameter derivation failed: %d" % rc)
         self.logN, self.N, self.L, self.K = logN, 1 << logN, L, K
         self.dnum, self.alpha = dnum, self.c.alpha
         self.nprimes = L + 1 + K
@@ -173,6 +198,9 @@ class Params:
         self.psi = [int(self.c.psi[i]) for i in range(self.nprimes)]
         self.scale = [float(self.c.scale[i]) for i in range(L + 1)]
         self.slots = self.N // 2
+        self.h = h                      # secret weight; 0: uniform ternary
+        self.boot = boot                # (CoeffToSlot, EvalMod, SlotToCoeff) levels
+        self.Lc = Lc if boot is not None else L
 
     @classmethod
     def preset(cls, name):
@@ -242,7 +270,11 @@ class Oracle:
         P = self.P
         s_coef = np.zeros(P.N, dtype=np.int8)
         s_ntt = np.zeros((P.nprimes, P.N), dtype=np.uint64)
-        self.L.orc_keygen_secret(P.ref, seed, _p(s_coef), _p(s_ntt))
+        if P.h:
+            if self.L.orc_keygen_secret_sparse(P.ref, seed, P.h, _p(s_coef), _p(s_ntt)) != 0:
+                raise ValueError("bad secret weight")
+        else:
+            self.L.orc_keygen_secret(P.ref, seed, _p(s_coef), _p(s_ntt))
         pk = np.zeros((2, P.L + 1, P.N), dtype=np.uint64)
         self.L.orc_keygen_public(P.ref, seed, _p(s_ntt), _p(pk))
         return SecretKey(s_coef, s_ntt), pk
