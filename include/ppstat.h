@@ -58,13 +58,26 @@ const char* ppst_last_error(void);
  * Presets: "c1" (N=2^12, 40/30/30-bit chain, Delta=2^30, one 60-bit special
  * prime); "c2" (N=2^16, Delta=2^40, 24 scale primes + 60-bit q_0, 7 special
  * primes, dnum=3: the paper's N, Delta and log2 PQ <= 1443 budget, Sec. 6.1);
- * "t1", "t2" (N=2^12 test sets with the c2 prime shapes, L=6 and L=24).
+ * "t1", "t2" (N=2^12 test sets with the c2 prime shapes, L=6 and L=24);
+ * "b2" (N=2^16) and "b1" (N=2^12), bootstrappable: L = 27 levels of which
+ * the top 16 serve bootstrapping (3 CoeffToSlot, 10 EvalMod at scale 2^58,
+ * 3 SlotToCoeff) and 11 computation (Delta = 2^40; the paper's depth 27
+ * with 11 levels between bootstraps, Sec. 6.1), a sparse secret of weight
+ * 64, 8 special primes, dnum = 4.
  * Every prime must stay below 2^60 (q0_bits, p_bits <= 60 and Delta well
  * below 2^60), K <= 8, dnum <= 8 and ceil((L+1)/dnum) <= 16; other sets are
- * rejected with PPST_EINVAL. */
+ * rejected with PPST_EINVAL.
+ * h: secret weight (0: uniform ternary).  boot_cts, boot_evalmod, boot_stc:
+ * levels of the bootstrapping stages at the top of the chain (all 0 for a
+ * chain without bootstrapping), boot_scale: EvalMod's scale.  Their primes:
+ * the largest unused primes below 2^p_bits for the two transforms (labels
+ * boot_scale on top, Delta 2^(i e / stc) between, e the difference of the
+ * binary exponents), an EvalMod chain near boot_scale. */
 typedef struct {
   int32_t logN, L, K, dnum, q0_bits, p_bits;
   double scale;
+  int32_t h, boot_cts, boot_evalmod, boot_stc;
+  double boot_scale;
 } ppst_params;
 
 int ppst_params_preset(const char* name, ppst_params* out);
@@ -355,7 +368,10 @@ int ppst_mul_batch(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciph
  * recorded output early is safe; the recorded inputs must stay alive for as
  * long as the graph is launched.  Launches are asynchronous on the
  * context's stream; ppst_graph_destroy waits for them and must come before
- * the context's destruction. */
+ * the context's destruction.  While a recording is open no other context
+ * may be created or destroyed in the process: that synchronises or frees
+ * device memory, which invalidates the capture (the calls of the
+ * recording then fail with PPST_EDEVICE). */
 typedef struct ppst_graph ppst_graph;
 int ppst_graph_begin(ppst_context* ctx);
 int ppst_graph_end(ppst_context* ctx, ppst_graph** out);
@@ -418,6 +434,76 @@ int ppst_stat_pearson(ppst_context* ctx, const ppst_eval_keys* evk,
                       const ppst_ciphertext* const* colx, const ppst_ciphertext* const* coly,
                       size_t nct, size_t nrows, double Bx, double By, const ppst_invsqrt_cfg* cfg,
                       ppst_ciphertext** out);                                          /* Sec. 5.5 */
+
+/* ---------------------------------------------------------- bootstrapping */
+/* CKKS bootstrapping (Sec. 3.2: it refreshes a ciphertext whose levels are
+ * spent; Alg. 3 refreshes the InvSqrt initial value with it; Tab. 1 gives its
+ * cost), built as in the work the paper cites, for the bootstrappable
+ * presets "b1"/"b2" (EINVAL on other parameter sets):
+ *   ModRaise     a level-0 ciphertext read over q_0..q_L (centred lift):
+ *                it decrypts to t = c + q_0 I, I small;
+ *   CoeffToSlot  the inverse decoding map in three levels, each a
+ *                baby-step giant-step sum of rotated diagonals (baby
+ *                rotations hoisted) and one rescale: slots
+ *                (t_k + i t_{k+N/2}) / (2 K q_0), K = 16, in bit-reversed order;
+ *   split        re = w + conj(w), im = -X^{N/2} (w - conj(w));
+ *   EvalMod      per lane, the degree-27 Chebyshev series of
+ *                cos(2 pi (K u - 1/4) / 16) and four double angles:
+ *                sin(2 pi K u), i.e. 2 pi c_k / q_0 near the integers;
+ *   SlotToCoeff  re + X^{N/2} im through the decoding map in three levels,
+ *                times q_0 / (2 pi Delta_0): the message at level Lc = L - 16.
+ * A refreshed [-1, 1] message carries an error of about 2^-15 (N = 2^12).
+ * The diagonals' plaintexts are encoded on the host in binary128 (each
+ * integer the correctly rounded one), then transformed on the device;
+ * ppst_boot_create takes seconds at N = 2^16 and holds about 3.3 GiB there.
+ * Every call is enqueued on the context's stream; outputs are new handles. */
+typedef struct ppst_boot ppst_boot;
+/* coeffs: EvalMod's c_0..c_27 (NULL: the library's interpolation, see
+ * ppst_evalmod_coeffs); ncoeffs must be 28 when coeffs is given */
+int ppst_boot_create(ppst_context* ctx, const double* coeffs, size_t ncoeffs, ppst_boot** out);
+int ppst_boot_destroy(ppst_boot* bt);
+/* the Galois keys bootstrapping needs: every rotation step of
+ * ppst_boot_rotations and conjugation (Galois element 2N - 1) */
+int ppst_evk_add_boot(ppst_context* ctx, const ppst_secret_key* sk, uint64_t seed,
+                      ppst_eval_keys* evk);
+/* host only: the nonzero rotation steps (mod N/2, ascending) of the
+ * transforms; *n receives their count (out == NULL with cap == 0: count only) */
+int ppst_boot_rotations(const ppst_params* params, int32_t* out, size_t cap, size_t* n);
+/* host only: group `group` (0..2, in the order applied) of CoeffToSlot
+ * (transform 0) or SlotToCoeff (1) as 9 integers: inverse, lo, hi (layers
+ * len = 2^lo..2^hi), level, constant kind, offset unit u, first offset m0,
+ * baby steps b, giant steps G */
+int ppst_boot_group_info(const ppst_params* params, int32_t transform, int32_t group, int32_t* desc);
+/* host only: the integer coefficients of that group's b G plaintexts, out
+ * [b G][N] (row j b + i: the diagonal of offset u (m0 + b j + i) rotated by
+ * -u (m0 + b j), encoded at Delta_{l-1} q_l / Delta_l times the group's
+ * constant), used[b G] (0: no such diagonal, row left zero); cap_cells >= b G */
+int ppst_boot_group_coeffs(const ppst_params* params, int32_t transform, int32_t group,
+                           int64_t* out, uint8_t* used, size_t cap_cells);
+/* host only: first-kind Chebyshev interpolation of cos(2 pi (K u - 1/4) / 2^r)
+ * on [-1, 1], c_0..c_degree (EDOMAIN for degree < 1, K < 1 or r < 0) */
+int ppst_evalmod_coeffs(int32_t K, int32_t r, int32_t degree, double* out, size_t cap);
+/* the refresh: level 0 in, level L - 16 out (ELEVEL otherwise) */
+int ppst_bootstrap(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_boot* bt,
+                   const ppst_ciphertext* a, ppst_ciphertext** out);
+/* its stages, for inspection: ModRaise (level 0 -> L); X -> X^g with the key
+ * switch back (g odd, < 2N; g = 2N - 1 conjugates every slot); a * (sign
+ * X^k), exact; CoeffToSlot (level L -> L - 3); the split into re and im;
+ * EvalMod of n lanes of one level; SlotToCoeff of (re, im) */
+int ppst_mod_raise(ppst_context* ctx, const ppst_ciphertext* a, ppst_ciphertext** out);
+int ppst_apply_galois(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_ciphertext* a,
+                      uint64_t g, ppst_ciphertext** out);
+int ppst_mul_monomial(ppst_context* ctx, const ppst_ciphertext* a, int32_t k, int32_t sign,
+                      ppst_ciphertext** out);
+int ppst_boot_coeff_to_slot(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_boot* bt,
+                            const ppst_ciphertext* a, ppst_ciphertext** out);
+int ppst_boot_split(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_boot* bt,
+                    const ppst_ciphertext* w, ppst_ciphertext** re, ppst_ciphertext** im);
+int ppst_boot_eval_mod(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_boot* bt,
+                       const ppst_ciphertext* const* lanes, size_t n, ppst_ciphertext** outs);
+int ppst_boot_slot_to_coeff(ppst_context* ctx, const ppst_eval_keys* evk, const ppst_boot* bt,
+                            const ppst_ciphertext* re, const ppst_ciphertext* im,
+                            ppst_ciphertext** out);
 
 /* ------------------------------------------------------------ raw kernels */
 /* In-place forward / inverse negacyclic NTT of `nlimbs` limbs of N words at

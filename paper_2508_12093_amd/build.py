@@ -19,7 +19,11 @@ OUT = os.path.join(HERE, "libppstat.so")
 BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["host_math.cpp", "eval.cpp", "stats.cpp", "server.cpp", "capi.cpp", "noalloc.cpp",
-           "ntt.hip", "kernels.hip"]
+           "boot.cpp", "capi_boot.cpp", "ntt.hip", "kernels.hip"]
+# host-only C++ built by g++ (binary128 arithmetic through libquadmath)
+HOST_SOURCES = ["boot_host.cpp"]
+CXX = os.environ.get("CXX_HOST", "g++")
+HOST_FLAGS = ["-O2", "-fPIC", "-std=gnu++17", "-Wall", "-pthread"]
 
 # peak-rate microbenchmarks for the roofline figures: a library of their own
 PROBE_SOURCE = "probe.hip"
@@ -40,6 +44,15 @@ def _compile(src: str) -> str:
     return obj
 
 
+def _compile_host(src: str) -> str:
+    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    cmd = [CXX] + HOST_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("%s failed on %s:\n%s%s" % (CXX, src, r.stdout, r.stderr))
+    return obj
+
+
 def _link(objs, out, extra=()):
     tmp = out + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + list(objs) + list(extra)
@@ -54,8 +67,10 @@ def build(verbose: bool = False) -> str:
     srcs = SOURCES + [PROBE_SOURCE]
     jobs = min(len(srcs), int(os.environ.get("MAX_JOBS", "8")))
     with ThreadPoolExecutor(max_workers=jobs) as ex:
+        host = [ex.submit(_compile_host, h) for h in HOST_SOURCES]
         objs = list(ex.map(_compile, srcs))
-    _link(objs[:-1], OUT, ["-lpthread"])
+        hobjs = [f.result() for f in host]
+    _link(objs[:-1] + hobjs, OUT, ["-lpthread", "-lquadmath"])
     _link(objs[-1:], PROBE_OUT)
     if verbose:
         print("built", OUT, "and", PROBE_OUT)

@@ -12,15 +12,6 @@ std::string& last_error() {
 
 namespace {
 
-ppst_ciphertext* wrap(CtPtr c) { return new ppst_ciphertext{std::move(c)}; }
-
-// calls that wait for the device or move data to or from the host cannot be
-// recorded into a graph
-#define NOT_RECORDING(ctx)                                                       \
-  do {                                                                           \
-    if ((ctx)->cx->recording)                                                    \
-      PPST_THROW(ST_EINVAL, "not allowed while a graph recording is open");      \
-  } while (0)
 
 std::vector<CtPtr> column(const ppst_ciphertext* const* col, size_t nct) {
   NEED(col);
@@ -53,6 +44,23 @@ void copy_out(Context& cx, const u64* dev, size_t words, uint64_t* host, size_t 
 
 }  // namespace
 
+ParamSpec ppst::spec_from(const ppst_params& p) {
+  ParamSpec s;
+  s.logN = p.logN;
+  s.L = p.L;
+  s.K = p.K;
+  s.dnum = p.dnum;
+  s.q0_bits = p.q0_bits;
+  s.p_bits = p.p_bits;
+  s.scale = p.scale;
+  s.h = p.h;
+  s.boot_cts = p.boot_cts;
+  s.boot_evalmod = p.boot_evalmod;
+  s.boot_stc = p.boot_stc;
+  s.boot_scale = p.boot_scale;
+  return s;
+}
+
 extern "C" {
 
 const char* ppst_last_error(void) { return last_error().c_str(); }
@@ -70,6 +78,11 @@ int ppst_params_preset(const char* name, ppst_params* out) {
     out->q0_bits = s.q0_bits;
     out->p_bits = s.p_bits;
     out->scale = s.scale;
+    out->h = s.h;
+    out->boot_cts = s.boot_cts;
+    out->boot_evalmod = s.boot_evalmod;
+    out->boot_stc = s.boot_stc;
+    out->boot_scale = s.boot_scale;
   });
 }
 
@@ -77,8 +90,7 @@ int ppst_params_derive(const ppst_params* params, uint64_t* primes, uint64_t* ro
                        double* scales, size_t cap) {
   return guard([&] {
     NEED(params);
-    ParamSpec s{params->logN, params->L, params->K, params->dnum, params->q0_bits,
-                params->p_bits, params->scale};
+    ParamSpec s = spec_from(*params);
     Params P = make_params(s);
     if (cap < (size_t)P.nprimes) PPST_THROW(ST_EINVAL, "buffer too small");
     for (int i = 0; i < P.nprimes; ++i) {
@@ -117,8 +129,7 @@ int ppst_encode_coeffs(const ppst_params* params, const double* values, size_t n
     NEED(params);
     NEED(out);
     if (n) NEED(values);
-    ParamSpec s{params->logN, params->L, params->K, params->dnum, params->q0_bits,
-                params->p_bits, params->scale};
+    ParamSpec s = spec_from(*params);
     Params P = make_params(s);
     if (level < 0 || level > P.L) PPST_THROW(ST_ELEVEL, "level out of range");
     if (cap < (size_t)P.N) PPST_THROW(ST_EINVAL, "buffer too small");
@@ -130,8 +141,7 @@ int ppst_rotsum_steps(const ppst_params* params, int32_t* out, size_t cap, size_
   return guard([&] {
     NEED(params);
     NEED(n);
-    ParamSpec sp{params->logN, params->L, params->K, params->dnum, params->q0_bits,
-                 params->p_bits, params->scale};
+    ParamSpec sp = spec_from(*params);
     Params P = make_params(sp);
     std::vector<int32_t> steps;
     for (const auto& st : rotsum_plan(P))
@@ -153,8 +163,7 @@ int ppst_context_create(const ppst_params* params, const ppst_device_hooks* hook
   return guard([&] {
     NEED(params);
     NEED(out);
-    ParamSpec s{params->logN, params->L, params->K, params->dnum, params->q0_bits,
-                params->p_bits, params->scale};
+    ParamSpec s = spec_from(*params);
     if (s.logN != 12 && s.logN != 16) PPST_THROW(ST_EDOMAIN, "log2 N must be 12 or 16");
     Hooks h;
     if (hooks) {

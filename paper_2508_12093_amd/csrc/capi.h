@@ -32,6 +32,13 @@ struct ppst_server {
 struct ppst_graph {
   std::unique_ptr<ppst::Graph> g;
 };
+namespace ppst {
+struct Bootstrapper;
+}
+struct ppst_boot {
+  std::unique_ptr<ppst::Bootstrapper> b;
+  ~ppst_boot();
+};
 
 namespace ppst {
 
@@ -60,6 +67,19 @@ int guard(F&& f) {
   do {                                                            \
     if (!(p)) PPST_THROW(ST_EINVAL, "null argument: " #p);          \
   } while (0)
+
+inline ppst_ciphertext* wrap(CtPtr c) { return new ppst_ciphertext{std::move(c)}; }
+
+// calls that wait for the device or move data to or from the host cannot be
+// recorded into a graph
+#define NOT_RECORDING(ctx)                                                       \
+  do {                                                                           \
+    if ((ctx)->cx->recording)                                                    \
+      PPST_THROW(ST_EINVAL, "not allowed while a graph recording is open");      \
+  } while (0)
+
+// the library's parameter specification of a ppst_params
+ParamSpec spec_from(const ppst_params& p);
 
 // Device-side scratch of ppst_mul_noalloc: sets up the current device's
 // array (once per device; context creation calls it) and returns its

@@ -70,15 +70,26 @@ inline u64 shoup(u64 w, u64 q) { return (u64)(((u128)w << 64) / q); }
 struct ParamSpec {
   int logN = 0, L = 0, K = 0, dnum = 0, q0_bits = 0, p_bits = 0;
   double scale = 0.0;
+  // bootstrappable chains: secret weight (0: uniform ternary), the levels of
+  // CoeffToSlot, EvalMod and SlotToCoeff at the top of the chain (counted in
+  // L; all zero for a chain without bootstrapping) and EvalMod's scale
+  int h = 0, boot_cts = 0, boot_evalmod = 0, boot_stc = 0;
+  double boot_scale = 0.0;
 };
 
 struct Params {
   ParamSpec spec;
   int logN = 0, N = 0, L = 0, K = 0, dnum = 0, alpha = 0, nprimes = 0;
+  int Lc = 0;                 // top level of computation (L without bootstrapping levels)
   std::vector<u64> q;         // combined: q_0..q_L, p_0..p_{K-1}
   std::vector<u64> psi;       // primitive 2N-th roots
   std::vector<double> scale;  // Delta_l, l = 0..L
+  // canon[l]: Delta_{l-1} = Delta_l^2 / q_l, so a product at level l rescales
+  // onto level l-1's scale; false only on the levels of the bootstrapping
+  // linear transforms, whose scales are set by their plaintexts
+  std::vector<uint8_t> canon;
   int slots() const { return N / 2; }
+  bool bootstrappable() const { return spec.boot_cts > 0; }
   int digit_lo(int j) const { return j * alpha; }
   int digit_hi(int j, int level) const {  // one past the last limb of digit j at level
     int h = (j + 1) * alpha;
@@ -102,6 +113,10 @@ inline u64 purpose_code(u64 tag, u64 keyid, u64 digit) { return (tag << 40) | (k
 u64 stream_key(u64 seed, u64 purpose, u64 limb);
 constexpr int kDgMax = 19;                  // |e| <= 19 (about 6 sigma)
 void dg_thresholds(u64 thr[kDgMax]);        // cumulative thresholds, x = 0..18
+// sparse ternary secret with exactly h nonzero coefficients, from the
+// secret-key stream (seed, P_SK, 0): positions by a partial Fisher-Yates
+// shuffle driven by its first h words, signs by the top bits of the next h
+void sparse_ternary(u64 seed, int N, int h, int32_t* out);
 
 // -------------------------------------------------------------------------
 // encoding (host, extended precision)

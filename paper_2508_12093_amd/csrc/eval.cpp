@@ -475,6 +475,14 @@ void require_same(const Ciphertext& a, const Ciphertext& b) {
   if (a.npoly != 2 || b.npoly != 2) PPST_THROW(ST_EINVAL, "expected degree-1 ciphertexts");
 }
 
+// products rescaled at `level` land on Delta_{level-1} only where the scale
+// rule holds; the levels of the bootstrapping transforms are excluded
+void require_canon(const Params& P, int level) {
+  if (level >= 1 && level <= P.L && !P.canon[level])
+    PPST_THROW(ST_ESCALE, "level " + std::to_string(level) +
+                              " is reserved for the bootstrapping linear transforms");
+}
+
 const KsKey& relin_key(const EvalKeys& evk) {
   if (!evk.relin) PPST_THROW(ST_ENOKEY, "no relinearisation key");
   return *evk.relin;
@@ -714,7 +722,15 @@ std::unique_ptr<SecretKey> keygen_secret(Context& cx, u64 seed) {
   const Shared& sh = *cx.sh;
   auto sk = std::make_unique<SecretKey>();
   Buf s32(cx.pool, (size_t)P.N * 4);
-  k_sample_ternary(sh, (int32_t*)s32.p, seed, purpose_code(P_SK, 0, 0), cx.stream);
+  std::vector<int32_t> sparse;
+  if (P.spec.h > 0) {
+    sparse.resize(P.N);
+    sparse_ternary(seed, P.N, P.spec.h, sparse.data());
+    HIP_CHECK(hipMemcpyAsync(s32.p, sparse.data(), (size_t)P.N * 4, hipMemcpyHostToDevice,
+                             cx.stream));
+  } else {
+    k_sample_ternary(sh, (int32_t*)s32.p, seed, purpose_code(P_SK, 0, 0), cx.stream);
+  }
   sk->s_ntt = dev_buf(sh.const_pool, (size_t)P.nprimes * P.N);
   k_small_to_rns(sh, (int32_t*)s32.p, sk->s_ntt.p, P.nprimes, P.nprimes, 0, cx.stream);
   NttLaunch L{};
@@ -1010,6 +1026,7 @@ CtPtr mul_int(Context& cx, const Ciphertext& a, int64_t k) {
 CtPtr rescale(Context& cx, const Ciphertext& a) {
   if (a.level < 1) PPST_THROW(ST_ELEVEL, "no level left to rescale");
   const Params& P = cx.P();
+  require_canon(P, a.level);
   auto out = new_ct(cx, a.level - 1, P.scale[a.level - 1], a.npoly);
   rescale_raw(cx, a.buf.p, (size_t)(a.level + 1) * a.N, a.level, a.npoly, out->buf.p);
   return out;
@@ -1018,6 +1035,7 @@ CtPtr rescale(Context& cx, const Ciphertext& a) {
 CtPtr mul_const(Context& cx, const Ciphertext& a, double c) {
   if (a.level < 1) PPST_THROW(ST_ELEVEL, "no level left for a constant product");
   const Params& P = cx.P();
+  require_canon(P, a.level);
   std::vector<u64> v, vp;
   scalar_residues(P, const_int(P, c, a.level), a.level + 1, v, vp);
   auto out = new_ct(cx, a.level - 1, P.scale[a.level - 1], a.npoly);
@@ -1074,6 +1092,7 @@ std::vector<CtPtr> mul_const_n(Context& cx, const std::vector<const Ciphertext*>
   check_group(a);
   const int level = a[0]->level;
   if (level < 1) PPST_THROW(ST_ELEVEL, "no level left for a constant product");
+  require_canon(cx.P(), level);
   std::vector<u64> v, vp;
   scalar_residues(cx.P(), const_int(cx.P(), c, level), level + 1, v, vp);
   return rescale_group(cx, a, level, v, vp);
@@ -1100,6 +1119,7 @@ CtPtr lincomb(Context& cx, const std::vector<const Ciphertext*>& cts,
   if (cts.empty() || cts.size() != cs.size())
     PPST_THROW(ST_EINVAL, "need matching ciphertexts and constants");
   if (level < 0) PPST_THROW(ST_ELEVEL, "combination level below 0");
+  if (level + 1 <= P.L) require_canon(P, level + 1);
   const int lv1 = level + 1, nl = lv1 + 1, N = P.N;
   const size_t nt = cts.size();
   std::vector<const u64*> src(nt);
@@ -1157,6 +1177,7 @@ CtPtr relin(Context& cx, const EvalKeys& evk, const Ciphertext& d) {
 CtPtr mul(Context& cx, const EvalKeys& evk, const Ciphertext& a, const Ciphertext& b) {
   require_same(a, b);
   if (a.level < 1) PPST_THROW(ST_ELEVEL, "no level left for a product");
+  require_canon(cx.P(), a.level);
   const KsKey& key = relin_key(evk);
   const Params& P = cx.P();
   auto d = tensor(cx, a, b);
@@ -1176,6 +1197,7 @@ void mul_into(Context& cx, const EvalKeys& evk, const u64* a, const u64* b, int 
               u64* scratch) {
   const Params& P = cx.P();
   if (level < 1 || level > P.L) PPST_THROW(ST_ELEVEL, "no level left for a product");
+  require_canon(P, level);
   const KsKey& key = relin_key(evk);
   const size_t N = (size_t)P.N, nl = (size_t)level + 1, ne = nl + P.K;
   u64* D = scratch;                                   // tensor [3][l+1][N]
@@ -1187,16 +1209,70 @@ void mul_into(Context& cx, const EvalKeys& evk, const u64* a, const u64* b, int 
   ks_moddown_rescale_into(cx, u, D, 0, level, &out, 1, xc);
 }
 
-CtPtr rotate(Context& cx, const EvalKeys& evk, const Ciphertext& a, long r) {
-  if (a.npoly != 2) PPST_THROW(ST_EINVAL, "rotation expects a degree-1 ciphertext");
+CtPtr apply_galois(Context& cx, const EvalKeys& evk, const Ciphertext& a, u64 g) {
+  if (a.npoly != 2) PPST_THROW(ST_EINVAL, "an automorphism expects a degree-1 ciphertext");
   const Params& P = cx.P();
-  u64 g = galois_elt(P, r);
+  if (g % 2 == 0 || g >= 2 * (u64)P.N) PPST_THROW(ST_EINVAL, "Galois element must be odd and below 2N");
   if (g == 1) return copy_ct(cx, a);
   const KsKey& key = galois_key(evk, g);
   auto out = new_ct(cx, a.level, a.scale);
   keyswitch(cx, key, a.poly(1), 0, a.level, a.poly(0), nullptr, 0, out->buf.p, 0, 1,
             (uint32_t)g);
   return out;
+}
+
+CtPtr rotate(Context& cx, const EvalKeys& evk, const Ciphertext& a, long r) {
+  if (a.npoly != 2) PPST_THROW(ST_EINVAL, "rotation expects a degree-1 ciphertext");
+  return apply_galois(cx, evk, a, galois_elt(cx.P(), r));
+}
+
+CtPtr rescale_as(Context& cx, const Ciphertext& a, double scale) {
+  if (a.level < 1) PPST_THROW(ST_ELEVEL, "no level left to rescale");
+  auto out = new_ct(cx, a.level - 1, scale, a.npoly);
+  rescale_raw(cx, a.buf.p, (size_t)(a.level + 1) * a.N, a.level, a.npoly, out->buf.p);
+  return out;
+}
+
+CtPtr mod_raise(Context& cx, const Ciphertext& a) {
+  if (a.npoly != 2) PPST_THROW(ST_EINVAL, "ModRaise expects a degree-1 ciphertext");
+  if (a.level != 0) PPST_THROW(ST_ELEVEL, "ModRaise takes a level-0 ciphertext");
+  const Params& P = cx.P();
+  const Shared& sh = *cx.sh;
+  const size_t N = (size_t)P.N;
+  Buf x = dev_buf(cx.pool, 2 * N);
+  {
+    NttLaunch L{};                      // limb q_0 of both polynomials to coefficients
+    L.src = a.buf.p;
+    L.dst = x.p;
+    L.nlimbs = 1;
+    L.nbatch = 2;
+    L.batch_stride = N;
+    L.dst_stride = N;
+    L.nq = 1;
+    L.pofs = P.L + 1;
+    ntt(sh, L, true, cx.stream);
+  }
+  auto out = new_ct(cx, P.L, P.scale[P.L]);
+  k_mod_raise(sh, x.p, out->buf.p, P.L + 1, 2, cx.stream);
+  ntt_ct_limbs(cx, out->buf.p, P.L + 1, 2, (size_t)(P.L + 1) * N, false);
+  return out;
+}
+
+CtPtr mul_monomial(Context& cx, const Ciphertext& a, int k, int sign) {
+  const Params& P = cx.P();
+  if (k < 0 || k >= P.N || (sign != 1 && sign != -1)) PPST_THROW(ST_EINVAL, "monomial out of range");
+  std::vector<int64_t> e(P.N, 0);
+  e[k] = sign;
+  auto pt = plaintext_from_coeffs(cx, e.data(), a.level, 1.0);
+  return mul_plain_raw(cx, a, *pt);
+}
+
+CtPtr mul_plain_raw(Context& cx, const Ciphertext& a, const Plaintext& pt) {
+  if (pt.level < a.level) PPST_THROW(ST_ESCALE, "plaintext has fewer limbs than the ciphertext");
+  auto t = new_ct(cx, a.level, a.scale, a.npoly);
+  const size_t per = (size_t)(a.level + 1) * a.N;
+  k_mul_poly(*cx.sh, a.buf.p, pt.buf.p, t->buf.p, a.npoly, a.level + 1, per, per, cx.stream);
+  return t;
 }
 
 std::vector<CtPtr> rotate_hoisted(Context& cx, const EvalKeys& evk, const Ciphertext& a,
@@ -1565,6 +1641,7 @@ std::vector<CtPtr> mul_batch(Context& cx, const EvalKeys& evk,
     if (a[i]->level != level) PPST_THROW(ST_ESCALE, "batch members at different levels");
   }
   if (level < 1) PPST_THROW(ST_ELEVEL, "no level left for a product");
+  require_canon(P, level);
   const KsKey& key = relin_key(evk);
   const int nl = level + 1, N = P.N;
   const size_t per = (size_t)nl * N;

@@ -65,6 +65,20 @@ size_t mul_scratch_words(const Params& P, int level);
 void mul_into(Context& cx, const EvalKeys& evk, const u64* a, const u64* b, int level, u64* out,
               u64* scratch);
 CtPtr rotate(Context& cx, const EvalKeys& evk, const Ciphertext& a, long r);
+// X -> X^g (g odd, below 2N) and the key switch back to s: rotate() for
+// g = 5^r; conjugation of every slot for g = 2N - 1
+CtPtr apply_galois(Context& cx, const EvalKeys& evk, const Ciphertext& a, u64 g);
+// rescale by q_l whose result carries `scale` (for products whose plaintext
+// factor was chosen to land on that scale)
+CtPtr rescale_as(Context& cx, const Ciphertext& a, double scale);
+// the product with a plaintext (limbs 0..a.level of it), no rescale
+CtPtr mul_plain_raw(Context& cx, const Ciphertext& a, const Plaintext& pt);
+// a * (sign X^k), exact (no level)
+CtPtr mul_monomial(Context& cx, const Ciphertext& a, int k, int sign);
+// ModRaise: a level-0 ciphertext read over q_0..q_L, each residue mod q_0
+// lifted to (-q_0/2, q_0/2]; it decrypts to the old plaintext plus q_0 I for
+// a small integer polynomial I
+CtPtr mod_raise(Context& cx, const Ciphertext& a);
 std::vector<CtPtr> rotate_hoisted(Context& cx, const EvalKeys& evk, const Ciphertext& a,
                                   const std::vector<long>& rs);
 // rotate_hoisted for many ciphertexts of one level: every ModUp first, then

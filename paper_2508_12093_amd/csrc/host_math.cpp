@@ -103,16 +103,52 @@ Params make_params(const ParamSpec& s) {
   std::vector<u64> used;
   P.q.assign(P.nprimes, 0);
   P.scale.assign(P.L + 1, 0.0);
+  P.canon.assign(P.L + 1, 1);
   P.q[0] = top_prime(s.q0_bits, m, used);
   used.push_back(P.q[0]);
-  // scale chain: Delta_L = Delta, Delta_{l-1} = (Delta_l * Delta_l) / q_l
-  P.scale[P.L] = s.scale;
-  for (int l = P.L; l >= 1; --l) {
-    double sq = P.scale[l] * P.scale[l];
-    u64 p = closest_prime(sq / s.scale, m, used);
-    P.q[l] = p;
-    used.push_back(p);
-    P.scale[l - 1] = sq / (double)p;
+  // a segment of levels hi..lo+1 whose scale stays near `target`:
+  // Delta_{l-1} = (Delta_l * Delta_l) / q_l with q_l the unused prime
+  // nearest Delta_l^2 / target
+  auto chain = [&](int hi, int lo, double target) {
+    for (int l = hi; l > lo; --l) {
+      double sq = P.scale[l] * P.scale[l];
+      u64 p = closest_prime(sq / target, m, used);
+      P.q[l] = p;
+      used.push_back(p);
+      P.scale[l - 1] = sq / (double)p;
+    }
+  };
+  if (s.boot_cts <= 0) {
+    P.Lc = P.L;
+    P.scale[P.L] = s.scale;
+    chain(P.L, 0, s.scale);
+  } else {
+    // Bootstrappable chain, top down: CoeffToSlot levels (the largest unused
+    // primes below 2^p_bits, scale boot_scale), EvalMod levels (a chain at
+    // boot_scale), SlotToCoeff levels (the largest unused primes, scales
+    // stepping from boot_scale down to Delta by powers of two), then the
+    // computation levels (a chain at Delta).
+    const int C = s.boot_cts, E = s.boot_evalmod, S = s.boot_stc;
+    if (E < 1 || S < 1 || !(s.boot_scale > 1.0)) PPST_THROW(ST_EINVAL, "invalid bootstrapping levels");
+    P.Lc = P.L - C - E - S;
+    if (P.Lc < 1) PPST_THROW(ST_EINVAL, "no computation level under the bootstrapping levels");
+    for (int l = P.L; l > P.L - C; --l) {
+      P.q[l] = top_prime(s.p_bits, m, used);
+      used.push_back(P.q[l]);
+      P.scale[l] = s.boot_scale;
+      P.canon[l] = 0;
+    }
+    P.scale[P.L - C] = s.boot_scale;
+    chain(P.L - C, P.Lc + S, s.boot_scale);
+    for (int l = P.Lc + S; l > P.Lc; --l) {
+      P.q[l] = top_prime(s.p_bits, m, used);
+      used.push_back(P.q[l]);
+      P.canon[l] = 0;
+    }
+    const int e = std::ilogb(s.boot_scale) - std::ilogb(s.scale);
+    for (int i = 1; i < S; ++i) P.scale[P.Lc + i] = std::ldexp(s.scale, (i * e) / S);
+    P.scale[P.Lc] = s.scale;
+    chain(P.Lc, 0, s.scale);
   }
   for (int k = 0; k < P.K; ++k) {
     u64 p = top_prime(s.p_bits, m, used);
@@ -137,6 +173,12 @@ bool preset_spec(const std::string& name, ParamSpec* out) {
     s = {12, 6, 3, 3, 60, 60, 1099511627776.0};
   } else if (name == "t2") {   // N=2^12 with the full c2 chain, L=24
     s = {12, 24, 7, 3, 60, 60, 1099511627776.0};
+  } else if (name == "b2" || name == "b1") {
+    // bootstrappable: 11 computation levels at 2^40 under 3 SlotToCoeff,
+    // 10 EvalMod (2^58) and 3 CoeffToSlot levels; sparse secret of weight 64;
+    // b1 is the same chain at N=2^12
+    s = {name == "b2" ? 16 : 12, 27, 8, 4, 60, 60, 1099511627776.0, 64, 3, 10, 3,
+         288230376151711744.0};
   } else {
     return false;
   }
@@ -157,6 +199,19 @@ static inline u64 mix_once(u64 x) { return splitmix(x); }
 
 u64 stream_key(u64 seed, u64 purpose, u64 limb) {
   return mix_once(mix_once(mix_once(seed) ^ purpose) ^ limb);
+}
+
+void sparse_ternary(u64 seed, int N, int h, int32_t* out) {
+  if (h < 1 || h > N) PPST_THROW(ST_EINVAL, "secret weight out of range");
+  u64 state = stream_key(seed, purpose_code(P_SK, 0, 0), 0);
+  std::vector<int32_t> idx(N);
+  for (int k = 0; k < N; ++k) idx[k] = k;
+  for (int i = 0; i < h; ++i) {
+    const u64 w = splitmix(state);
+    std::swap(idx[i], idx[i + (int)(w % (u64)(N - i))]);
+  }
+  std::fill(out, out + N, 0);
+  for (int i = 0; i < h; ++i) out[idx[i]] = (splitmix(state) >> 63) ? -1 : 1;
 }
 
 void dg_thresholds(u64 thr[kDgMax]) {

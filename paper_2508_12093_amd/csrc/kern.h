@@ -202,6 +202,15 @@ void k_sample_dg(const Shared& sh, int32_t* out, u64 seed, u64 purpose, hipStrea
 // out_t = e_t - a_t s_t + f_t sp_t (f_t = 0 skips the last term), on nl limbs (map)
 void k_keyform(const Shared& sh, const u64* a, const u64* s, const u64* e, const u64* sp,
                const u64* f, u64* out, int nl, int nq, int pofs, hipStream_t st);
+// ModRaise: x [npoly][N] coefficients mod q_0 -> out [npoly][nl][N], the
+// centred lift of each coefficient reduced mod q_0..q_{nl-1}
+void k_mod_raise(const Shared& sh, const u64* x, u64* out, int nl, int npoly, hipStream_t st);
+// baby-step giant-step inner sums: outs[j] = sum_{i<b} pts[j b + i] . baby[i]
+// for j < G (both polynomials of [2][nl][N] ciphertexts at polynomial strides
+// ps_in / ps_out; plaintexts [nl][N]; null plaintexts skipped, null outputs
+// not written); b <= 16, G <= 16, b G <= 64 after b is padded to a power of two
+void k_bsgs_inner(const Shared& sh, const u64* const* baby, int b, const u64* const* pts,
+                  u64* const* outs, int G, int nl, size_t ps_in, size_t ps_out, hipStream_t st);
 // out = x + y * z (+ w when w != null) on nl limbs of the ciphertext primes
 void k_fma3(const Shared& sh, const u64* x, const u64* y, const u64* z, const u64* w, u64* out,
             int nl, hipStream_t st);

@@ -642,6 +642,62 @@ __global__ void k_keyform_kernel(const u64* a, const u64* s, const u64* e, const
   out[r] = v;
 }
 
+// ModRaise: x [npoly][N] residues mod q_0 (coefficient form); out[c][t] the
+// centred lift of x_c (in (-q_0/2, q_0/2]) mod q_t, t < nl
+__global__ void k_mod_raise_kernel(const u64* __restrict__ x, u64* __restrict__ out,
+                                   const Mod* __restrict__ mods, int logN, int nl, int npoly) {
+  const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t per = (size_t)nl << logN;
+  if (r >= per * npoly) return;
+  const int c = (int)(r / per);
+  const size_t rr = r - (size_t)c * per;
+  const int t = (int)(rr >> logN);
+  const u64 v = x[((size_t)c << logN) + (rr & (((size_t)1 << logN) - 1))];
+  const u64 q0 = mods[0].q;
+  const Mod m = mods[t];
+  if (v > q0 / 2) {
+    const u64 w = reduce64(q0 - v, m);      // the lift is -(q0 - v)
+    out[r] = w ? m.q - w : 0;
+  } else {
+    out[r] = reduce64(v, m);
+  }
+}
+
+// The inner sums of a baby-step giant-step product: for every giant step j,
+// out_j = sum_i pt[j B + i] . baby_i (NTT form, both polynomials, limb t mod
+// q_t); null plaintexts are skipped, null outputs not written.  Each thread
+// holds its coefficient of the B baby steps in registers and reads each
+// plaintext once.
+constexpr int kBsgsMaxBaby = 16, kBsgsMaxCells = 64, kBsgsMaxGiant = 16;
+struct BsgsArgs {
+  const u64* baby[kBsgsMaxBaby];   // [2][nl][N] at polynomial stride ps_in
+  const u64* pt[kBsgsMaxCells];    // [nl][N]
+  u64* out[kBsgsMaxGiant];         // [2][nl][N] at polynomial stride ps_out
+  size_t ps_in, ps_out;
+  int G;
+};
+
+template <int B>
+__global__ void k_bsgs_inner_kernel(BsgsArgs a, const Mod* __restrict__ mods, int logN, int nl) {
+  const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= ((size_t)nl << logN)) return;
+  const int c = blockIdx.y;
+  const Mod m = mods[r >> logN];
+  u64 x[B];
+#pragma unroll
+  for (int i = 0; i < B; ++i) x[i] = a.baby[i][(size_t)c * a.ps_in + r];
+  for (int j = 0; j < a.G; ++j) {
+    if (!a.out[j]) continue;
+    u64 acc = 0;
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+      const u64* p = a.pt[j * B + i];
+      if (p) acc = addm(acc, mulm(x[i], p[r], m), m.q);
+    }
+    a.out[j][(size_t)c * a.ps_out + r] = acc;
+  }
+}
+
 __global__ void k_fma3_kernel(const u64* x, const u64* y, const u64* z, const u64* w, u64* out,
                               const Mod* mods, int logN, int nl) {
   size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1039,6 +1095,42 @@ void k_keyform(const Shared& sh, const u64* a, const u64* s, const u64* e, const
   }
   hipLaunchKernelGGL(k_keyform_kernel, grid_for((size_t)nl * sh.P.N), dim3(kBlock), 0, st, a, s,
                      e, sp, fa, out, M(sh), sh.P.logN, nl, nq, pofs, sp ? 1 : 0);
+  LAUNCH_CHECK();
+}
+
+void k_mod_raise(const Shared& sh, const u64* x, u64* out, int nl, int npoly, hipStream_t st) {
+  hipLaunchKernelGGL(k_mod_raise_kernel, grid_for((size_t)npoly * nl * sh.P.N), dim3(kBlock), 0, st,
+                     x, out, M(sh), sh.P.logN, nl, npoly);
+  LAUNCH_CHECK();
+}
+
+void k_bsgs_inner(const Shared& sh, const u64* const* baby, int b, const u64* const* pts,
+                  u64* const* outs, int G, int nl, size_t ps_in, size_t ps_out, hipStream_t st) {
+  if (b < 1 || G < 1 || G > kBsgsMaxGiant || b * G > kBsgsMaxCells)
+    PPST_THROW(ST_EINVAL, "baby-step grid too large");
+  BsgsArgs a{};
+  int B = 1;
+  while (B < b) B <<= 1;
+  if (B > kBsgsMaxBaby || B * G > kBsgsMaxCells) PPST_THROW(ST_EINVAL, "baby-step grid too large");
+  // baby steps b..B-1 (padding to a power of two) carry no plaintext; they
+  // read baby step 0 so that every load stays in bounds
+  for (int i = 0; i < B; ++i) a.baby[i] = baby[i < b ? i : 0];
+  for (int j = 0; j < G; ++j) {
+    a.out[j] = outs[j];
+    for (int i = 0; i < B; ++i) a.pt[j * B + i] = i < b ? pts[j * b + i] : nullptr;
+  }
+  a.ps_in = ps_in;
+  a.ps_out = ps_out;
+  a.G = G;
+  dim3 g = grid_for((size_t)nl * sh.P.N);
+  g.y = 2;
+  switch (B) {
+    case 1: hipLaunchKernelGGL(k_bsgs_inner_kernel<1>, g, dim3(kBlock), 0, st, a, M(sh), sh.P.logN, nl); break;
+    case 2: hipLaunchKernelGGL(k_bsgs_inner_kernel<2>, g, dim3(kBlock), 0, st, a, M(sh), sh.P.logN, nl); break;
+    case 4: hipLaunchKernelGGL(k_bsgs_inner_kernel<4>, g, dim3(kBlock), 0, st, a, M(sh), sh.P.logN, nl); break;
+    case 8: hipLaunchKernelGGL(k_bsgs_inner_kernel<8>, g, dim3(kBlock), 0, st, a, M(sh), sh.P.logN, nl); break;
+    default: hipLaunchKernelGGL(k_bsgs_inner_kernel<16>, g, dim3(kBlock), 0, st, a, M(sh), sh.P.logN, nl); break;
+  }
   LAUNCH_CHECK();
 }
 

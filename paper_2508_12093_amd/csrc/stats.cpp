@@ -283,22 +283,16 @@ struct Circ {
     return out;
   }
 
-  std::vector<std::pair<CtPtr, CtPtr>> inv_sqrt_n(const std::vector<CtPtr>& vs,
-                                                  const std::vector<double>& Bps,
-                                                  const InvSqrtCfg& cfg) {
-    const double a = cfg.a, b = cfg.b;
-    const int d = cfg.degree;
-    const size_t nl = vs.size();
-    std::vector<std::vector<double>> c(nl);
+  // sum_{k<=d} c[l][k] T_k(ts[l]) for every lane l: T_1 = t,
+  // T_k = 2 T_m T_{m+1} - T_1 (k = 2m + 1) or 2 T_m^2 - 1 (k = 2m); the terms
+  // with 2^w < k <= 2^(w+1) need only earlier ones and share a level, so
+  // each such wave is one batch of products over all lanes; then c_1..c_d in
+  // one weighted sum one level below the lowest T_k, and c_0 added
+  std::vector<CtPtr> cheb_series_n(const std::vector<CtPtr>& ts,
+                                   const std::vector<std::vector<double>>& c, int d) {
+    const size_t nl = ts.size();
     std::vector<std::vector<CtPtr>> T(nl, std::vector<CtPtr>(d + 1));
-    for (size_t l = 0; l < nl; ++l) {
-      c[l] = coeffs(cfg, Bps[l]);
-      if ((int)c[l].size() != d + 1) PPST_THROW(ST_EINVAL, "coefficient table does not match the degree");
-      T[l][1] = affine(vs[l], a, b);
-    }
-    // T_k = 2 T_m T_{m+1} - T_1 (k = 2m + 1) or 2 T_m^2 - 1 (k = 2m): the terms
-    // with 2^w < k <= 2^(w+1) need only earlier ones and share a level, so
-    // each such wave is one batch of products over all lanes
+    for (size_t l = 0; l < nl; ++l) T[l][1] = ts[l];
     std::vector<LevelCache> t1(nl, LevelCache{this});
     for (int w = 0; (1 << w) < d; ++w) {
       const int lo = (1 << w) + 1, hi = std::min(1 << (w + 1), d);
@@ -317,12 +311,29 @@ struct Circ {
           T[l][k] = (k % 2) ? subx(q, t1[l].get(T[l][1], q->level)) : add_const(cx, *q, -1.0);
         }
     }
-    std::vector<CtPtr> y(nl), w2(nl);
+    std::vector<CtPtr> y(nl);
     for (size_t l = 0; l < nl; ++l) {
       y[l] = add_const(cx, *weighted(T[l], c[l], d), c[l][0]);
       T[l].clear();
-      w2[l] = mc(vs[l], Bps[l] / 2.0);
     }
+    return y;
+  }
+
+  std::vector<std::pair<CtPtr, CtPtr>> inv_sqrt_n(const std::vector<CtPtr>& vs,
+                                                  const std::vector<double>& Bps,
+                                                  const InvSqrtCfg& cfg) {
+    const double a = cfg.a, b = cfg.b;
+    const int d = cfg.degree;
+    const size_t nl = vs.size();
+    std::vector<std::vector<double>> c(nl);
+    std::vector<CtPtr> ts(nl);
+    for (size_t l = 0; l < nl; ++l) {
+      c[l] = coeffs(cfg, Bps[l]);
+      if ((int)c[l].size() != d + 1) PPST_THROW(ST_EINVAL, "coefficient table does not match the degree");
+      ts[l] = affine(vs[l], a, b);
+    }
+    std::vector<CtPtr> y = cheb_series_n(ts, c, d), w2(nl);
+    for (size_t l = 0; l < nl; ++l) w2[l] = mc(vs[l], Bps[l] / 2.0);
     for (int it = 0; it < cfg.iters; ++it) {
       // y^2 and w2 y side by side, then their product
       std::vector<CtPtr> A(y), B(y);
@@ -390,6 +401,14 @@ std::vector<double> chebyshev_invsqrt(double a, double b, int degree, double Bp)
     c[k] = (k == 0 ? 1.0 : 2.0) * s / (double)n;
   }
   return c;
+}
+
+std::vector<CtPtr> cheb_series(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& ts,
+                               const std::vector<double>& c) {
+  if (ts.empty() || c.size() < 2) PPST_THROW(ST_EINVAL, "no lanes or no coefficients");
+  Circ circ{cx, evk};
+  const int d = (int)c.size() - 1;
+  return circ.cheb_series_n(ts, std::vector<std::vector<double>>(ts.size(), c), d);
 }
 
 CtPtr stat_mean(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& X, size_t n, double B) {

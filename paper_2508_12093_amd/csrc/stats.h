@@ -21,6 +21,12 @@ struct InvSqrtCfg {
 // in t = (2 v - a - b) / (b - a)
 std::vector<double> chebyshev_invsqrt(double a, double b, int degree, double Bp);
 
+// sum_k c_k T_k(t) of each lane t (all of one level): the Chebyshev ladder
+// of the InvSqrt initial value (T_2m = 2 T_m^2 - 1, T_2m+1 = 2 T_m T_m+1 - T_1,
+// one weighted sum with one rescale, c_0 added), ceil(log2 d) + 1 levels
+std::vector<CtPtr> cheb_series(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& ts,
+                               const std::vector<double>& c);
+
 CtPtr stat_mean(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& X, size_t n, double B);
 CtPtr stat_variance(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& X, size_t n,
                     double B);

@@ -34,7 +34,9 @@ class PpstError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("logN", ctypes.c_int32), ("L", ctypes.c_int32), ("K", ctypes.c_int32),
                 ("dnum", ctypes.c_int32), ("q0_bits", ctypes.c_int32), ("p_bits", ctypes.c_int32),
-                ("scale", ctypes.c_double)]
+                ("scale", ctypes.c_double), ("h", ctypes.c_int32), ("boot_cts", ctypes.c_int32),
+                ("boot_evalmod", ctypes.c_int32), ("boot_stc", ctypes.c_int32),
+                ("boot_scale", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
@@ -138,6 +140,21 @@ _SIGS = {
     "ppst_mul_const_batch": (ctypes.c_int, [_vp, _pp, _sz, _dbl, _pp]),
     "ppst_rotsum_batch": (ctypes.c_int, [_vp, _vp, _pp, _sz, _pp]),
     "ppst_rotate_hoisted_batch": (ctypes.c_int, [_vp, _vp, _pp, _sz, _vp, _sz, _pp]),
+    "ppst_boot_create": (ctypes.c_int, [_vp, _vp, _sz, _pp]),
+    "ppst_boot_destroy": (ctypes.c_int, [_vp]),
+    "ppst_evk_add_boot": (ctypes.c_int, [_vp, _vp, _u64, _vp]),
+    "ppst_boot_rotations": (ctypes.c_int, [_vp, _vp, _sz, ctypes.POINTER(ctypes.c_size_t)]),
+    "ppst_boot_group_info": (ctypes.c_int, [_vp, _i32, _i32, _vp]),
+    "ppst_boot_group_coeffs": (ctypes.c_int, [_vp, _i32, _i32, _vp, _vp, _sz]),
+    "ppst_evalmod_coeffs": (ctypes.c_int, [_i32, _i32, _i32, _vp, _sz]),
+    "ppst_bootstrap": (ctypes.c_int, [_vp, _vp, _vp, _vp, _pp]),
+    "ppst_mod_raise": (ctypes.c_int, [_vp, _vp, _pp]),
+    "ppst_apply_galois": (ctypes.c_int, [_vp, _vp, _vp, _u64, _pp]),
+    "ppst_mul_monomial": (ctypes.c_int, [_vp, _vp, _i32, _i32, _pp]),
+    "ppst_boot_coeff_to_slot": (ctypes.c_int, [_vp, _vp, _vp, _vp, _pp]),
+    "ppst_boot_split": (ctypes.c_int, [_vp, _vp, _vp, _vp, _pp, _pp]),
+    "ppst_boot_eval_mod": (ctypes.c_int, [_vp, _vp, _vp, _pp, _sz, _pp]),
+    "ppst_boot_slot_to_coeff": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _pp]),
     "ppst_rotate_batch": (ctypes.c_int, [_vp, _vp, _pp, _sz, ctypes.c_int32, _pp]),
     "ppst_graph_begin": (ctypes.c_int, [_vp]),
     "ppst_graph_end": (ctypes.c_int, [_vp, _pp]),
@@ -173,12 +190,25 @@ _SIGS = {
 _lib = None
 
 
+def _runtime_first():
+    """Load torch (when installed) before the library: torch ships its own HIP
+    runtime, and loading it first makes the process use that one runtime for
+    both (the library's libamdhip64.so.7 dependency resolves to the copy
+    already loaded); loaded the other way round, the library's device calls
+    have failed to find the GPU."""
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+
+
 def lib():
     """Load libppstat.so (raises if it has not been built)."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libppstat.so is not built (run __graft_entry__.build())")
+        _runtime_first()
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             f = getattr(L, name)
@@ -200,6 +230,7 @@ def probe_lib():
     if _probe is None:
         if not os.path.exists(PROBE_PATH):
             raise RuntimeError("libppstat_probe.so is not built (run __graft_entry__.build())")
+        _runtime_first()
         L = ctypes.CDLL(PROBE_PATH)
         for name, args in {"ppst_probe_copy": [_vp, _vp, _sz, _vp],
                            "ppst_probe_fma_f64": [_vp, _sz, ctypes.c_int, _vp],
@@ -609,6 +640,74 @@ ppst_rotate = _unary("ppst_rotate")
 ppst_rotsum = _unary("ppst_rotsum")
 ppst_rotsum_serial = _unary("ppst_rotsum_serial")
 ppst_level_align = _unary("ppst_level_align")
+ppst_mod_raise = _unary("ppst_mod_raise")
+ppst_apply_galois = _unary("ppst_apply_galois")
+ppst_mul_monomial = _unary("ppst_mul_monomial")
+ppst_bootstrap = _unary("ppst_bootstrap")
+ppst_boot_coeff_to_slot = _unary("ppst_boot_coeff_to_slot")
+ppst_boot_slot_to_coeff = _unary("ppst_boot_slot_to_coeff")
+
+
+# ---------------------------------------------------------- bootstrapping
+class Boot(_Handle):
+    _destroy = "ppst_boot_destroy"
+
+
+def ppst_boot_create(ctx, coeffs=None):
+    out = _out()
+    if coeffs is None:
+        _chk(lib().ppst_boot_create(ctx, None, 0, ctypes.byref(out)))
+    else:
+        c = np.ascontiguousarray(coeffs, dtype=np.float64)
+        _chk(lib().ppst_boot_create(ctx, _p(c), c.size, ctypes.byref(out)))
+    return Boot(out.value, ctx)
+
+
+def ppst_evk_add_boot(ctx, sk, seed, evk):
+    _chk(lib().ppst_evk_add_boot(ctx, sk, seed, evk))
+
+
+def ppst_boot_rotations(params) -> list:
+    n = ctypes.c_size_t()
+    _chk(lib().ppst_boot_rotations(ctypes.byref(params), None, 0, ctypes.byref(n)))
+    out = np.zeros(max(1, n.value), dtype=np.int32)
+    _chk(lib().ppst_boot_rotations(ctypes.byref(params), _p(out), n.value, ctypes.byref(n)))
+    return [int(v) for v in out[:n.value]]
+
+
+def ppst_boot_group_info(params, transform: int, group: int) -> dict:
+    d = np.zeros(9, dtype=np.int32)
+    _chk(lib().ppst_boot_group_info(ctypes.byref(params), transform, group, _p(d)))
+    keys = ("inverse", "lo", "hi", "level", "ckind", "u", "m0", "b", "G")
+    return {k: int(v) for k, v in zip(keys, d)}
+
+
+def ppst_boot_group_coeffs(params, transform: int, group: int):
+    """(coefficients [b G][N] int64, used [b G] uint8) of a group's plaintexts."""
+    g = ppst_boot_group_info(params, transform, group)
+    cells = g["b"] * g["G"]
+    out = np.zeros((cells, 1 << params.logN), dtype=np.int64)
+    used = np.zeros(cells, dtype=np.uint8)
+    _chk(lib().ppst_boot_group_coeffs(ctypes.byref(params), transform, group, _p(out), _p(used), cells))
+    return out, used
+
+
+def ppst_evalmod_coeffs(K: int, r: int, degree: int):
+    out = np.zeros(degree + 1, dtype=np.float64)
+    _chk(lib().ppst_evalmod_coeffs(K, r, degree, _p(out), out.size))
+    return out
+
+
+def ppst_boot_split(ctx, evk, bt, w):
+    re, im = _out(), _out()
+    _chk(lib().ppst_boot_split(ctx, evk, bt, w, ctypes.byref(re), ctypes.byref(im)))
+    return Ciphertext(re.value, ctx), Ciphertext(im.value, ctx)
+
+
+def ppst_boot_eval_mod(ctx, evk, bt, lanes):
+    outs = (ctypes.c_void_p * len(lanes))()
+    _chk(lib().ppst_boot_eval_mod(ctx, evk, bt, _ptrs(lanes), len(lanes), outs))
+    return [Ciphertext(outs[i], ctx) for i in range(len(lanes))]
 
 
 def ppst_lincomb(ctx, cts, cs, level):

@@ -117,3 +117,61 @@ def test_chebyshev_generator_domain():
         with pytest.raises(ffi.PpstError) as e:
             ffi.ppst_chebyshev_invsqrt(*args)
         assert e.value.name == "EDOMAIN"
+
+
+@pytest.mark.parametrize("name", ["b1", "b2"])
+def test_boot_parameters_match_oracle(name):
+    """The bootstrappable chains: the same primes, roots and FP64 scales as
+    the oracle's rule, the same secret weight, and the same rotation steps."""
+    from oracle import boot
+    p = ffi.ppst_params_preset(name)
+    spec = ref.PRESETS[name]
+    C, E, S = spec["boot"]
+    assert (p.logN, p.K, p.dnum, p.h) == (spec["logN"], spec["K"], spec["dnum"], spec["h"])
+    assert (p.boot_cts, p.boot_evalmod, p.boot_stc, p.boot_scale) == (C, E, S, spec["delta_b"])
+    assert p.L == spec["Lc"] + C + E + S
+    primes, roots, scales = ffi.ppst_params_derive(p)
+    P = ref.Params.preset(name)
+    assert primes == P.q and roots == P.psi and scales == P.scale
+    assert ffi.ppst_boot_rotations(p) == boot.rotation_steps(P)
+
+
+def test_boot_plaintexts_match_oracle():
+    """Every baby-step giant-step plaintext of both transforms at N = 2^12:
+    the library's binary128 encoding and the oracle's give the same integers
+    (both are the correctly rounded values), the same cells, the same plan."""
+    from oracle import boot
+    p = ffi.ppst_params_preset("b1")
+    P = ref.Params.preset("b1")
+    O = ref.Oracle(P)
+    plan = boot.make_plan(P)
+    for tr, groups in ((0, plan.cts), (1, plan.stc)):
+        for gi, g in enumerate(groups):
+            info = ffi.ppst_boot_group_info(p, tr, gi)
+            assert info == dict(inverse=g.inverse, lo=g.lo, hi=g.hi, level=g.level, ckind=g.ckind,
+                                u=g.u, m0=g.m0, b=g.b, G=g.G)
+            got, used = ffi.ppst_boot_group_coeffs(p, tr, gi)
+            want = np.zeros((g.G * g.b, P.N), dtype=np.int64)
+            wused = np.zeros(g.G * g.b, dtype=np.int8)
+            assert O.L.orc_boot_grid(P.ref, g.inverse, g.lo, g.hi, g.level, g.ckind, plan.K, P.boot[0],
+                                     g.u, g.m0, g.b, g.G, ref._p(want), ref._p(wused)) > 0
+            assert np.array_equal(used.astype(int), wused.astype(int))
+            assert np.array_equal(got, want)
+
+
+def test_evalmod_coefficients_match_oracle():
+    """The library's EvalMod interpolation and the oracle's (numpy) agree to
+    the rounding of a 28-term sum."""
+    from oracle import cheb
+    got = ffi.ppst_evalmod_coeffs(16, 4, 27)
+    want = cheb.evalmod_cos_coeffs(16, 4, 27)
+    assert np.max(np.abs(got - want)) < 28 * 2.0 ** -52 * 2
+    with pytest.raises(ffi.PpstError) as e:
+        ffi.ppst_evalmod_coeffs(16, 4, 0)
+    assert e.value.name == "EDOMAIN"
+
+
+def test_boot_on_plain_chain_is_rejected():
+    with pytest.raises(ffi.PpstError) as e:
+        ffi.ppst_boot_rotations(ffi.ppst_params_preset("c2"))
+    assert e.value.name == "EINVAL"

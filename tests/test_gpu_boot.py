@@ -1,0 +1,165 @@
+"""Bootstrapping on the GPU through the C-ABI against the oracle.
+
+At N = 2^12 ("b1", the bootstrappable chain of "b2") every stage is compared
+bit for bit with ``oracle/boot.py`` on the same keys and inputs: the sparse
+secret, ModRaise, conjugation and X^n, CoeffToSlot, the split into real and
+imaginary parts, EvalMod, SlotToCoeff and the whole refresh.  EvalMod takes
+the oracle's Chebyshev coefficients (an input; the library's own
+interpolation agrees to 1e-14, tests/test_abi_host.py).  At N = 2^16 ("b2")
+the refresh is checked by what holds at any size: it decrypts to the
+message, lands on level Lc, and computes on.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(__file__))
+from gpu_common import Pair  # noqa: E402
+
+from oracle import boot, cheb, ref  # noqa: E402
+from paper_2508_12093_amd import ffi, synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+BOOT_SEED = 21
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def bp():
+    _torch()
+    p = Pair("b1", steps=())
+    print("b1: keys, plaintexts", flush=True)
+    coeffs = cheb.evalmod_cos_coeffs(16, 4, 27)
+    ffi.ppst_evk_add_boot(p.ctx, p.sk, BOOT_SEED, p.evk)
+    p.bt = ffi.ppst_boot_create(p.ctx, coeffs)
+    p.OB = boot.Bootstrapper(p.O, p.osk, BOOT_SEED, coeffs=coeffs)
+    # the oracle's Bootstrapper makes its own relinearisation key from the
+    # same seed; the library's comes from Pair (seed 12): use that one
+    p.OB.rlk = p.orlk
+    p.OB.circ.ev.rlk = p.orlk
+    return p
+
+
+def level0(p, seed):
+    m = synth.uniform_column(seed, p.P.slots, -1, 1)
+    ct, oct_ = p.encrypt(m, 100 + seed, level=0)
+    return m, ct, oct_
+
+
+def test_sparse_secret_and_keys(bp):
+    p = bp
+    s = p.osk.s_coef
+    assert np.count_nonzero(s) == 64
+    assert np.array_equal(ffi.ppst_sk_export(p.ctx, p.sk), p.osk.s_ntt)
+    g = 2 * p.P.N - 1
+    assert np.array_equal(ffi.ppst_evk_export(p.ctx, p.evk, g), p.OB.gkeys[g])
+    r = boot.rotation_steps(p.P)[3]
+    ge = ref.galois_element(r, p.P.N)
+    assert np.array_equal(ffi.ppst_evk_export(p.ctx, p.evk, ge), p.OB.gkeys[ge])
+
+
+def test_mod_raise_conj_monomial(bp):
+    p = bp
+    _, ct, oct_ = level0(p, 1)
+    p.same(ct, oct_)
+    raised = ffi.ppst_mod_raise(p.ctx, ct)
+    oraised = p.OB.mod_raise(oct_)
+    p.same(raised, oraised)
+    cj = ffi.ppst_apply_galois(p.ctx, p.evk, raised, 2 * p.P.N - 1)
+    p.same(cj, p.OB.apply_galois(oraised, 2 * p.P.N - 1))
+    for k, sign in ((p.P.slots, 1), (p.P.slots, -1), (5, 1)):
+        p.same(ffi.ppst_mul_monomial(p.ctx, raised, k, sign), p.OB.mul_monomial(oraised, k, sign))
+
+
+def test_stages_bit_exact(bp):
+    p = bp
+    _, ct, oct_ = level0(p, 2)
+    raised = ffi.ppst_mod_raise(p.ctx, ct)
+    oraised = p.OB.mod_raise(oct_)
+    w = ffi.ppst_boot_coeff_to_slot(p.ctx, p.evk, p.bt, raised)
+    ow = p.OB.coeff_to_slot(oraised)
+    p.same(w, ow)
+    re, im = ffi.ppst_boot_split(p.ctx, p.evk, p.bt, w)
+    ore, oim = p.OB.split(ow)
+    p.same(re, ore)
+    p.same(im, oim)
+    yr, yi = ffi.ppst_boot_eval_mod(p.ctx, p.evk, p.bt, [re, im])
+    oyr, oyi = p.OB.eval_mod(ore), p.OB.eval_mod(oim)
+    p.same(yr, oyr)
+    p.same(yi, oyi)
+    out = ffi.ppst_boot_slot_to_coeff(p.ctx, p.evk, p.bt, yr, yi)
+    p.same(out, p.OB.slot_to_coeff(p.O.add(oyr, p.OB.mul_monomial(oyi, p.P.slots, 1))))
+
+
+def test_bootstrap_bit_exact_and_refreshes(bp):
+    p = bp
+    m, ct, oct_ = level0(p, 3)
+    out = ffi.ppst_bootstrap(p.ctx, p.evk, p.bt, ct)
+    oout = p.OB.bootstrap(oct_)
+    p.same(out, oout)
+    assert out.level == p.P.Lc
+    got = p.decrypt(out)
+    assert np.max(np.abs(got - m)) < 2.0 ** -13
+    # the refreshed ciphertext computes on
+    sq = ffi.ppst_mul(p.ctx, p.evk, out, out)
+    assert np.max(np.abs(p.decrypt(sq) - m * m)) < 2.0 ** -12
+
+
+def test_bootstrap_errors(bp):
+    p = bp
+    _, ct, _ = level0(p, 4)
+    raised = ffi.ppst_mod_raise(p.ctx, ct)
+    with pytest.raises(ffi.PpstError) as e:
+        ffi.ppst_bootstrap(p.ctx, p.evk, p.bt, raised)          # not level 0
+    assert e.value.name == "ELEVEL"
+    with pytest.raises(ffi.PpstError) as e:
+        ffi.ppst_mul(p.ctx, p.evk, raised, raised)              # a transform level
+    assert e.value.name == "ESCALE"
+    with pytest.raises(ffi.PpstError) as e:
+        ffi.ppst_apply_galois(p.ctx, p.evk, raised, 4)          # even element
+    assert e.value.name == "EINVAL"
+    with pytest.raises(ffi.PpstError):
+        ffi.ppst_boot_create(p.ctx, np.zeros(5))                # wrong coefficient count
+    other = ffi.ppst_context_create("c1")
+    with pytest.raises(ffi.PpstError) as e:
+        ffi.ppst_boot_create(other)
+    assert e.value.name == "EINVAL"
+    # the raised exceptions' tracebacks hold this frame: drop the handles now
+    # rather than whenever the cycle collector runs
+    del e, other, raised, ct
+
+
+def test_b2_bootstrap_refreshes():
+    """N = 2^16: the refresh of a full [-1, 1] column decrypts to it (max
+    error 2^-10, about 2^-12 measured), lands on level 11 and computes on;
+    the library's own EvalMod coefficients."""
+    _torch()
+    print("b2: keys, plaintexts", flush=True)
+    ctx = ffi.ppst_context_create("b2")
+    sk, pk = ffi.ppst_keygen(ctx, 31)
+    evk = ffi.ppst_evk_create(ctx)
+    ffi.ppst_evk_add_relin(ctx, sk, 32, evk)
+    ffi.ppst_evk_add_boot(ctx, sk, 33, evk)
+    bt = ffi.ppst_boot_create(ctx)
+    n = 1 << 15
+    m = synth.uniform_column(7, n, -1, 1)
+    ct = ffi.ppst_encrypt(ctx, pk, ffi.ppst_encode(ctx, m, 0), 34)
+    print("b2: bootstrap", flush=True)
+    out = ffi.ppst_bootstrap(ctx, evk, bt, ct)
+    assert out.level == 11
+    got = ffi.ppst_decode(ctx, ffi.ppst_decrypt(ctx, sk, out), n)
+    err = np.max(np.abs(got - m))
+    print("b2 refresh max error 2^%.2f" % np.log2(err), flush=True)
+    assert err < 2.0 ** -10
+    sq = ffi.ppst_mul(ctx, evk, out, out)
+    got2 = ffi.ppst_decode(ctx, ffi.ppst_decrypt(ctx, sk, sq), n)
+    assert np.max(np.abs(got2 - m * m)) < 2.0 ** -9

@@ -2,6 +2,8 @@
 result bit for bit, with eager work and synchronisation between replays,
 outputs released early stay valid, and host-bound calls are refused while
 recording (MI355X only)."""
+import contextlib
+import gc
 import os
 import sys
 
@@ -29,6 +31,21 @@ def _exp(p, c):
     return ffi.ppst_ct_export(p.ctx, c)
 
 
+@contextlib.contextmanager
+def no_collection():
+    """Python's cycle collector may destroy handles of other contexts (kept
+    alive by earlier tests' tracebacks) at any moment; a context's
+    destruction synchronises and frees device memory, which HIP does not
+    allow while a stream capture is open.  Collect first, hold it off while
+    recording."""
+    gc.collect()
+    gc.disable()
+    try:
+        yield
+    finally:
+        gc.enable()
+
+
 def test_graph_replays_equal_eager(t1):
     p = t1
     cts = [p.encrypt(synth.uniform_column(300 + i, p.P.slots, -1, 1), 300 + i)[0] for i in range(3)]
@@ -44,11 +61,12 @@ def test_graph_replays_equal_eager(t1):
     em, er, es, eh = work()
     want = [_exp(p, c) for c in em] + [_exp(p, er), _exp(p, es)] + [_exp(p, c) for row in eh for c in row]
 
-    ffi.ppst_graph_begin(p.ctx)
-    try:
-        gm, gr, gs, gh = work()
-    finally:
-        g = ffi.ppst_graph_end(p.ctx)
+    with no_collection():
+        ffi.ppst_graph_begin(p.ctx)
+        try:
+            gm, gr, gs, gh = work()
+        finally:
+            g = ffi.ppst_graph_end(p.ctx)
     del gr                      # released early: the graph keeps its memory
     for rep in range(4):
         print("[graph] replay", rep, flush=True)
@@ -68,6 +86,8 @@ def test_graph_replays_equal_eager(t1):
 def test_recording_refuses_host_calls(t1):
     p = t1
     ct, _ = p.encrypt(synth.uniform_column(310, 16, 0, 1), 310)
+    gc.collect()
+    gc.disable()
     ffi.ppst_graph_begin(p.ctx)
     try:
         with pytest.raises(ffi.PpstError) as e:
@@ -82,6 +102,7 @@ def test_recording_refuses_host_calls(t1):
         out = ffi.ppst_add(p.ctx, ct, ct)
     finally:
         g = ffi.ppst_graph_end(p.ctx)
+        gc.enable()
     g.launch()
     ffi.ppst_sync(p.ctx)
     assert np.array_equal(_exp(p, out), _exp(p, ffi.ppst_add(p.ctx, ct, ct)))
