@@ -67,7 +67,9 @@ def parse():
     ap.add_argument("--quick", action="store_true", help="short run for profiling")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the roofline kernel and a copy of known size")
-    ap.add_argument("--only", choices=["plain", "batched", "pearson"], default=None,
+    ap.add_argument("--boot-runs", type=int, default=5,
+                    help="timed bootstraps at N=2^16 (0: skip the bootstrapping leg)")
+    ap.add_argument("--only", choices=["plain", "batched", "pearson", "boot"], default=None,
                     help="time one form of the 64-product step alone (for kernel profiles)")
     ap.add_argument("--no-exp2", action="store_true",
                     help="skip the 1M-row statistics replay of Sec. 6.3")
@@ -133,6 +135,9 @@ def main():
         outs = [ffi.ppst_mul(ctx, evk, cts[i], cts[(i + 1) % B]) for i in range(B)]
         return outs
 
+    if args.only == "boot":
+        print(json.dumps({"only": "boot", "bootstrap": boot_bench(stream, max(1, args.boot_runs))}))
+        return
     if args.only == "pearson":
         x, y = synth.binary_cost_pair(0)
         cx = ffi.ppst_encrypt(ctx, pk, ffi.ppst_encode(ctx, x, L), 3001)
@@ -295,6 +300,7 @@ def main():
         loads = [float(v) for v in args.serving_loads.split(",") if v]
         serving = serving_bench(ctx, pk, sk, evk, args.serving_queries, loads,
                                 nslots=args.serving_slots)
+    boot = boot_bench(stream, args.boot_runs) if args.boot_runs > 0 else None
     rf = measure_ntt(ctx, stream, reps=10 if args.quick else 50)
     peaks = measure_peaks(stream)
 
@@ -340,6 +346,8 @@ def main():
         out["exp2"] = exp2
     if serving is not None:
         out["serving"] = serving
+    if boot is not None:
+        out["bootstrap"] = boot
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_runs)
     print(json.dumps(out), flush=True)
@@ -549,6 +557,57 @@ def serving_bench(ctx, pk, sk, evk, nq: int, loads, seed: int = 4, nslots: int =
 # autotuner picks for 25-limb forward transforms on MI355X in most runs), so
 # that the same kernels appear in the rocprofv3 profiles of --kernels-only.
 NTT_COL_VARIANT, NTT_ROW_VARIANT = 5, 6      # col:E3,SB16,D / row:E3,SB4,D
+
+
+def boot_bench(stream, runs: int):
+    """Bootstrapping at N=2^16 ("b2": 11 computation levels under 16
+    bootstrapping levels, sparse secret): a level-0 ciphertext of 32768
+    slots ~U[-1,1) refreshed to level 11, `runs` times after one warm-up;
+    inputs resident in HBM.  Reports ms per bootstrap, bootstraps/s, the
+    setup time (keys and the transforms' plaintexts) and the refresh error."""
+    import numpy as np
+    import torch
+
+    from paper_2508_12093_amd import ffi, synth
+
+    sptr = ctypes.c_void_p(stream.cuda_stream)
+    t = time.perf_counter()
+    bctx = ffi.ppst_context_create("b2", stream=sptr)
+    sk, pk = ffi.ppst_keygen(bctx, 5001)
+    evk = ffi.ppst_evk_create(bctx)
+    ffi.ppst_evk_add_relin(bctx, sk, 5002, evk)
+    ffi.ppst_evk_add_boot(bctx, sk, 5003, evk)
+    keys_s = time.perf_counter() - t
+    t = time.perf_counter()
+    bt = ffi.ppst_boot_create(bctx)
+    plain_s = time.perf_counter() - t
+    n = bctx.info.slots
+    m = synth.uniform_column(5004, n, -1, 1)
+    ct = ffi.ppst_encrypt(bctx, pk, ffi.ppst_encode(bctx, m, 0), 5005)
+    out = ffi.ppst_bootstrap(bctx, evk, bt, ct)
+
+    def sync():
+        ffi.ppst_sync(bctx)
+        torch.cuda.synchronize()
+
+    sync()
+    t = time.perf_counter()
+    for _ in range(runs):
+        out = ffi.ppst_bootstrap(bctx, evk, bt, ct)
+    sync()
+    ms = (time.perf_counter() - t) * 1e3 / runs
+    got = ffi.ppst_decode(bctx, ffi.ppst_decrypt(bctx, sk, out), n)
+    err = float(np.max(np.abs(got - m)))
+    log("bootstrap (N=2^16, L=27 -> 11): %.2f ms, %.1f /s, max error 2^%.2f; setup keys %.1f s, "
+        "plaintexts %.1f s" % (ms, 1e3 / ms, np.log2(err), keys_s, plain_s))
+    res = {"workload": "bootstrap of one ciphertext, N=2^16, level 0 -> 11 of L=27 (3 CoeffToSlot, "
+                       "10 EvalMod, 3 SlotToCoeff levels), h=64, 32768 slots ~U[-1,1)",
+           "ms_per_bootstrap": round(ms, 3), "bootstraps_per_s": round(1e3 / ms, 3), "runs": runs,
+           "max_abs_err": err, "err_log2": round(float(np.log2(err)), 2),
+           "setup_keys_s": round(keys_s, 2), "setup_plaintexts_s": round(plain_s, 2),
+           "paper_lattigo_ms": 43478.77}
+    del out, ct, bt, evk, sk, pk, bctx
+    return res
 
 
 def _ntt_source_sha():

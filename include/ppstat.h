@@ -63,7 +63,7 @@ const char* ppst_last_error(void);
  * the top 16 serve bootstrapping (3 CoeffToSlot, 10 EvalMod at scale 2^58,
  * 3 SlotToCoeff) and 11 computation (Delta = 2^40; the paper's depth 27
  * with 11 levels between bootstraps, Sec. 6.1), a sparse secret of weight
- * 64, 8 special primes, dnum = 4.
+ * 64, a 55-bit q_0, 8 special primes, dnum = 4.
  * Every prime must stay below 2^60 (q0_bits, p_bits <= 60 and Delta well
  * below 2^60), K <= 8, dnum <= 8 and ceil((L+1)/dnum) <= 16; other sets are
  * rejected with PPST_EINVAL.
@@ -452,7 +452,8 @@ int ppst_stat_pearson(ppst_context* ctx, const ppst_eval_keys* evk,
  *                sin(2 pi K u), i.e. 2 pi c_k / q_0 near the integers;
  *   SlotToCoeff  re + X^{N/2} im through the decoding map in three levels,
  *                times q_0 / (2 pi Delta_0): the message at level Lc = L - 16.
- * A refreshed [-1, 1] message carries an error of about 2^-15 (N = 2^12).
+ * A refreshed [-1, 1] message carries a max error of about 2^-21 at
+ * N = 2^12 and 2^-17 at N = 2^16 (q_0 of 55 bits: q_0 / Delta_0 = 2^15).
  * The diagonals' plaintexts are encoded on the host in binary128 (each
  * integer the correctly rounded one), then transformed on the device;
  * ppst_boot_create takes seconds at N = 2^16 and holds about 3.3 GiB there.

@@ -169,11 +169,14 @@ PRESETS = {
     "t2": dict(logN=12, L=24, K=7, dnum=3, q0_bits=60, delta=2.0 ** 40, p_bits=60),
     # bootstrappable chain (orc_params_make_boot): 11 computation levels at
     # Delta = 2^40 under 3 SlotToCoeff, 10 EvalMod (Delta_b = 2^58) and 3
-    # CoeffToSlot levels (L = 27), sparse secret of weight 64, dnum = 4
-    "b2": dict(logN=16, Lc=11, boot=(3, 10, 3), K=8, dnum=4, q0_bits=60, delta=2.0 ** 40,
+    # CoeffToSlot levels (L = 27), sparse secret of weight 64, dnum = 4; q_0
+    # of 55 bits, so that q_0 / Delta_0 = 2^15 (a refreshed message carries
+    # EvalMod's error times q_0 / Delta_0; the sine's cubic term grows as
+    # that ratio falls)
+    "b2": dict(logN=16, Lc=11, boot=(3, 10, 3), K=8, dnum=4, q0_bits=55, delta=2.0 ** 40,
                delta_b=2.0 ** 58, p_bits=60, h=64),
     # the b2 chain at N=2^12
-    "b1": dict(logN=12, Lc=11, boot=(3, 10, 3), K=8, dnum=4, q0_bits=60, delta=2.0 ** 40,
+    "b1": dict(logN=12, Lc=11, boot=(3, 10, 3), K=8, dnum=4, q0_bits=55, delta=2.0 ** 40,
                delta_b=2.0 ** 58, p_bits=60, h=64),
 }
 

@@ -176,8 +176,9 @@ bool preset_spec(const std::string& name, ParamSpec* out) {
   } else if (name == "b2" || name == "b1") {
     // bootstrappable: 11 computation levels at 2^40 under 3 SlotToCoeff,
     // 10 EvalMod (2^58) and 3 CoeffToSlot levels; sparse secret of weight 64;
-    // b1 is the same chain at N=2^12
-    s = {name == "b2" ? 16 : 12, 27, 8, 4, 60, 60, 1099511627776.0, 64, 3, 10, 3,
+    // q_0 of 55 bits (q_0 / Delta_0 = 2^15: a refresh multiplies EvalMod's
+    // error by that ratio); b1 is the same chain at N=2^12
+    s = {name == "b2" ? 16 : 12, 27, 8, 4, 55, 60, 1099511627776.0, 64, 3, 10, 3,
          288230376151711744.0};
   } else {
     return false;
