@@ -606,7 +606,47 @@ def boot_bench(stream, runs: int):
            "max_abs_err": err, "err_log2": round(float(np.log2(err)), 2),
            "setup_keys_s": round(keys_s, 2), "setup_plaintexts_s": round(plain_s, 2),
            "paper_lattigo_ms": 43478.77}
-    del out, ct, bt, evk, sk, pk, bctx
+    # config 5: kurtosis and PCC of 2^20-row columns (32 ciphertexts at
+    # level 11) with the paper's InvSqrt (Eq. 3's degree 31 on [0, 2], six
+    # Newton steps, B = 20; Sec. 6.3's U[0, 20] data), whose depth exceeds
+    # the 11 levels, so InvSqrt refreshes by bootstrapping
+    del out, ct
+    ffi.ppst_evk_add_rotsum(bctx, sk, 5006, evk)
+    rows = 1 << 20
+    x = synth.uniform_column(5010, rows, 0.0, 20.0)
+    y = 0.5 * (x + synth.uniform_column(5011, rows, 0.0, 20.0))
+
+    def enc(v, seed):
+        return [ffi.ppst_encrypt(bctx, pk, ffi.ppst_encode(bctx, c, 11), seed + k)
+                for k, c in enumerate(synth.split_column(v, n))]
+
+    X, Y = enc(x, 6000), enc(y, 7000)
+    # the library's own Eq. 3 coefficients (a = 0, b = 2)
+    cfg = ffi.ppst_invsqrt_cfg_default(a=0.0, b=2.0, degree=31, iters=6, boot=bt)
+    dx, dy = x - x.mean(), y - y.mean()
+    kurt_ref = float(np.mean(dx ** 4) / np.mean(dx ** 2) ** 2)
+    pcc_ref = float(np.mean(dx * dy) / np.sqrt(np.mean(dx * dx) * np.mean(dy * dy)))
+    pipe = {"workload": "kurtosis and PCC of 2^20-row columns (32 ciphertexts at level 11), "
+                        "U[0,20] data, B=20, InvSqrt degree 31 + 6 Newton steps with "
+                        "bootstrapping refreshes, N=2^16"}
+    for name, fn, ref in (
+            ("kurtosis", lambda: ffi.ppst_stat_kurtosis(bctx, evk, X, rows, 20.0, cfg), kurt_ref),
+            ("pearson", lambda: ffi.ppst_stat_pearson(bctx, evk, X, Y, rows, 20.0, 20.0, cfg),
+             pcc_ref)):
+        fn()
+        sync()
+        b0 = ffi.ppst_boot_count(bt)
+        t = time.perf_counter()
+        r = fn()
+        sync()
+        ms_s = (time.perf_counter() - t) * 1e3
+        v = float(ffi.ppst_decode(bctx, ffi.ppst_decrypt(bctx, sk, r), 1)[0])
+        pipe[name] = {"ms": round(ms_s, 2), "bootstraps": ffi.ppst_boot_count(bt) - b0,
+                      "value": v, "rel_err": abs(v / ref - 1)}
+        log("config 5 %-8s %8.2f ms, %d bootstraps, rel err %.2e" % (
+            name, ms_s, pipe[name]["bootstraps"], pipe[name]["rel_err"]))
+    res["pipeline"] = pipe
+    del X, Y, bt, evk, sk, pk, bctx
     return res
 
 

@@ -379,17 +379,27 @@ int ppst_graph_launch(ppst_graph* g);
 int ppst_graph_destroy(ppst_graph* g);
 
 /* ------------------------------------------------------------- statistics */
+typedef struct ppst_boot ppst_boot;   /* bootstrapping material, see below */
 /* CryptoInvSqrt configuration (Sec. 4, Alg. 2-3; Sec. 5.1, Eq. 3): Chebyshev
  * initial value of degree `degree` for 1/sqrt(B' v) on [a, b] (first-kind
  * interpolation), then `iters` Newton steps.  coeffs, when non-NULL, gives
  * c_0..c_degree of 1/sqrt(v) on [a, b] (B' = 1), divided by sqrt(B') per call.
- * sign_k: number of g_3 compositions of the sign in CV (Sec. 6.2). */
+ * sign_k: number of g_3 compositions of the sign in CV (Sec. 6.2).
+ * boot, when non-NULL (a bootstrappable context's ppst_boot, its keys in the
+ * call's evk), lets InvSqrt refresh levels by bootstrapping (Alg. 3 bootstraps
+ * the initial value; each refresh brings a ciphertext to level 0 and
+ * bootstraps it): the argument when it lacks the levels of the initial
+ * value's polynomial, the initial value itself, w = (B'/2) v or y before a
+ * Newton step that lacks its two levels, and the result when the statistic
+ * needs more levels after it than remain.  The statistics then need only
+ * their own levels around InvSqrt; CV refuses it (EINVAL). */
 typedef struct {
   double a, b;
   int32_t degree, iters, sign_k;
   const double* coeffs;
+  const ppst_boot* boot;
 } ppst_invsqrt_cfg;
-/* a, b = 1e-3, 1; degree 7; 3 iterations; sign_k 2; coeffs NULL */
+/* a, b = 1e-3, 1; degree 7; 3 iterations; sign_k 2; coeffs NULL; boot NULL */
 int ppst_invsqrt_cfg_default(ppst_invsqrt_cfg* out);
 
 /* CryptoInvSqrt slot by slot (Sec. 4, Alg. 2-3; Sec. 6.2, Exp. 1): each of
@@ -458,11 +468,13 @@ int ppst_stat_pearson(ppst_context* ctx, const ppst_eval_keys* evk,
  * integer the correctly rounded one), then transformed on the device;
  * ppst_boot_create takes seconds at N = 2^16 and holds about 3.3 GiB there.
  * Every call is enqueued on the context's stream; outputs are new handles. */
-typedef struct ppst_boot ppst_boot;
 /* coeffs: EvalMod's c_0..c_27 (NULL: the library's interpolation, see
  * ppst_evalmod_coeffs); ncoeffs must be 28 when coeffs is given */
 int ppst_boot_create(ppst_context* ctx, const double* coeffs, size_t ncoeffs, ppst_boot** out);
 int ppst_boot_destroy(ppst_boot* bt);
+/* the number of bootstraps enqueued with bt so far (ppst_bootstrap and the
+ * refreshes of statistics whose cfg carries bt) */
+int ppst_boot_count(const ppst_boot* bt, uint64_t* n);
 /* the Galois keys bootstrapping needs: every rotation step of
  * ppst_boot_rotations and conjugation (Galois element 2N - 1) */
 int ppst_evk_add_boot(ppst_context* ctx, const ppst_secret_key* sk, uint64_t seed,
@@ -573,6 +585,8 @@ int ppst_server_info(ppst_server* srv, uint64_t* budget, uint64_t* merged_launch
  * (e.g. an asynchronous encryption) are complete when they are copied */
 int ppst_server_register_column(ppst_server* srv, const ppst_ciphertext* const* cts, size_t nct,
                                 size_t nrows, uint64_t* col_id);
+/* EINVAL for a query whose cfg carries a bootstrapper (the admission
+ * estimates do not cover bootstrapping) */
 int ppst_server_submit(ppst_server* srv, const ppst_query* q, uint64_t* ticket);
 /* *done = 1 once the query has finished, 0 while it is pending or running;
  * never blocks.  The result stays with the server until ppst_server_wait

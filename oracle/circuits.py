@@ -54,6 +54,9 @@ class InvSqrtCfg:
     degree: int = 7
     iters: int = 3
     coeffs: np.ndarray | None = None   # optional explicit c_0..c_d for B' = 1
+    # refresh levels by bootstrapping inside InvSqrt (the evaluator's
+    # ``refresh``): see ``Circuits.inv_sqrt``
+    boot: bool = False
 
     def coeffs_for(self, Bp: float) -> np.ndarray:
         if self.coeffs is not None:
@@ -66,11 +69,19 @@ class InvSqrtCfg:
 # evaluators: encrypted (over the C oracle) and plain FP64 slots with levels
 # ----------------------------------------------------------------------------
 class EncEval:
-    """Evaluator over encrypted oracle ciphertexts."""
+    """Evaluator over encrypted oracle ciphertexts.  ``booter``: an
+    ``oracle.boot.Bootstrapper`` for InvSqrt's refreshes."""
 
-    def __init__(self, O: Oracle, rlk, gkeys):
+    def __init__(self, O: Oracle, rlk, gkeys, booter=None):
         self.O, self.rlk, self.gkeys = O, rlk, gkeys
         self.slots = O.P.slots
+        self.booter = booter
+
+    def refresh(self, x):
+        """Level 0, then bootstrapped to the top computation level."""
+        if self.booter is None:
+            raise ValueError("no bootstrapper")
+        return self.booter.bootstrap(self.O.level_align(x, 0))
 
     def level(self, x):
         return x.level
@@ -119,8 +130,12 @@ class PlainEval:
         v: np.ndarray
         level: int
 
-    def __init__(self, L, slots):
+    def __init__(self, L, slots, Lc=None):
         self.L, self.slots = L, slots
+        self.Lc = L if Lc is None else Lc
+
+    def refresh(self, x):
+        return PlainEval.V(x.v, self.Lc)
 
     def fresh(self, values):
         v = np.zeros(self.slots)
@@ -250,22 +265,43 @@ class Circuits:
                        min(ev.level(T[k]) for k in range(1, d + 1)) - 1)
         return ev.add_const(y, float(coeffs[0]))
 
-    def inv_sqrt(self, v, Bp, cfg: InvSqrtCfg):
-        """y ~ 1/sqrt(Bp v); returns (y, w2) with w2 = (Bp/2) v."""
+    def inv_sqrt(self, v, Bp, cfg: InvSqrtCfg, reserve: int = 0):
+        """y ~ 1/sqrt(Bp v); returns (y, w2) with w2 = (Bp/2) v.
+
+        With cfg.boot, levels are refreshed (level 0, then bootstrap; Alg. 3
+        bootstraps the initial value, the rest is the reading of where the
+        chain runs out): v when it has fewer levels than the affine map, the
+        ladder (T_d lies ceil(log2 d) levels down) and the weighted sum take;
+        the initial value always; w2 and y before a Newton step when either
+        has fewer than the step's two levels; y at the end when fewer than
+        `reserve` levels (what the statistic uses after InvSqrt) remain."""
         ev = self.ev
         a, b, d = cfg.a, cfg.b, cfg.degree
         coeffs = cfg.coeffs_for(Bp)
         # the affine map onto [-1, 1]; a pure shift (b - a = 2, Eq. 1's
         # x - 1 on [0, 2]) needs no product and no level
         g = 2.0 / (b - a)
+        if cfg.boot:
+            ladder = (d - 1).bit_length()          # ceil(log2 d)
+            if ev.level(v) < (0 if g == 1.0 else 1) + ladder + 1:
+                v = ev.refresh(v)
         t = ev.add_const(v if g == 1.0 else ev.mul_const(v, g), -(a + b) / (b - a))
         y = self.cheb_series(t, coeffs, d)
+        if cfg.boot:
+            y = ev.refresh(y)
         w2 = ev.mul_const(v, Bp / 2.0)
         for _ in range(cfg.iters):
+            if cfg.boot:
+                if ev.level(w2) < 2:
+                    w2 = ev.refresh(w2)
+                if ev.level(y) < 2:
+                    y = ev.refresh(y)
             y2 = ev.mul(y, y)
             p1 = self.mulx(w2, y)
             p2 = self.mulx(p1, y2)
             y = self.subx(ev.lincomb([y], [1.5], ev.level(p2)), p2)
+        if cfg.boot and ev.level(y) < reserve:
+            y = ev.refresh(y)
         return y, w2
 
     def invsqrt(self, X, B, cfg: InvSqrtCfg):
@@ -319,7 +355,7 @@ class Circuits:
     def zscore(self, X, n, B, cfg: InvSqrtCfg):
         """Alg. 4: (X - mu) * InvSqrt(Variance(X, B); B^2), one output per ciphertext."""
         _, var, mu = self._moments_prefix(X, n, B)
-        b, _ = self.inv_sqrt(var, B * B, cfg)
+        b, _ = self.inv_sqrt(var, B * B, cfg, 1)
         return [self.mulx(self.subx(x, mu), b) for x in X]
 
     def kurtosis(self, X, n, B, cfg: InvSqrtCfg, excess=False):
@@ -330,7 +366,7 @@ class Circuits:
         x2 = [ev.mul(x, x) for x in x1]
         x4 = [ev.mul(x, x) for x in x2]
         num = self.mask_mean(x4, n)
-        i, _ = self.inv_sqrt(var, B * B, cfg)
+        i, _ = self.inv_sqrt(var, B * B, cfg, 3)
         i2 = ev.mul(i, i)
         # (num i^2) i^2: every partial product stays near the result's size
         # (i^4 alone is ~1/Var^2, small enough to lose digits to the noise)
@@ -345,12 +381,14 @@ class Circuits:
         x2 = [ev.mul(x, x) for x in x1]
         x3 = [self.mulx(a, b) for a, b in zip(x2, x1)]
         num = self.mask_mean(x3, n)
-        i, _ = self.inv_sqrt(var, B * B, cfg)
+        i, _ = self.inv_sqrt(var, B * B, cfg, 2)
         i2 = ev.mul(i, i)
         return self.mulx(self.mulx(num, i), i2)
 
     def cv(self, X, n, B_mean, B_var, cfg: InvSqrtCfg, sign_k=2):
         """Alg. 6: Std * InvSqrt(mu * sign(mu); B_mean)^2 * sign(mu)."""
+        if cfg.boot:
+            raise ValueError("CV runs without bootstrapping")
         ev = self.ev
         muB, var = self.moments_B(X, n, B_mean, B_var)
         sg = self.sign(muB, sign_k)
@@ -380,6 +418,6 @@ class Circuits:
         varx = self.subx(exx, ev.mul(mx, mx))
         vary = self.subx(eyy, ev.mul(my, my))
         cov = self.subx(exy, ev.mul(mx, my))
-        ix, _ = self.inv_sqrt(varx, 1.0, cfg)
-        iy, _ = self.inv_sqrt(vary, 1.0, cfg)
+        ix, _ = self.inv_sqrt(varx, 1.0, cfg, 2)
+        iy, _ = self.inv_sqrt(vary, 1.0, cfg, 2)
         return self.mulx(cov, ev.mul(ix, iy))

@@ -245,6 +245,7 @@ CtPtr slot_to_coeff(Context& cx, const EvalKeys& evk, const Bootstrapper& bt, co
 
 CtPtr bootstrap(Context& cx, const EvalKeys& evk, const Bootstrapper& bt, const Ciphertext& a) {
   CtPtr w = coeff_to_slot(cx, evk, bt, *mod_raise(cx, a));
+  bt.runs.fetch_add(1, std::memory_order_relaxed);
   auto ri = boot_split(cx, evk, bt, *w);
   w.reset();
   auto y = eval_mod(cx, evk, bt, {ri.first, ri.second});

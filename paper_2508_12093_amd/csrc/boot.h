@@ -12,6 +12,8 @@
 //                (q_0 / (2 pi Delta_0))^(1/3) each: the message at Delta_Lc
 #pragma once
 
+#include <atomic>
+
 #include "boot_host.h"
 #include "eval.h"
 
@@ -45,6 +47,7 @@ struct Bootstrapper {
   std::vector<BootLevel> cts, stc;
   std::vector<double> coeffs;   // EvalMod's c_0..c_degree
   PtPtr neg_xn, pos_xn;         // -X^n at CoeffToSlot's output level, X^n at EvalMod's
+  mutable std::atomic<u64> runs{0};   // bootstraps enqueued with this material
 };
 
 // the plaintexts of every group (host binary128 encoding, then the device's

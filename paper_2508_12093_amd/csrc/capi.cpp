@@ -31,6 +31,10 @@ InvSqrtCfg cfg_from(const ppst_invsqrt_cfg* c) {
     r.degree = c->degree;
     r.iters = c->iters;
     if (c->coeffs) r.coeffs.assign(c->coeffs, c->coeffs + c->degree + 1);
+    if (c->boot) {
+      if (!c->boot->b) PPST_THROW(ST_EINVAL, "empty bootstrapping handle");
+      r.boot = c->boot->b.get();
+    }
   }
   return r;
 }
@@ -835,6 +839,7 @@ int ppst_invsqrt_cfg_default(ppst_invsqrt_cfg* out) {
     out->iters = 3;
     out->sign_k = 2;
     out->coeffs = nullptr;
+    out->boot = nullptr;
   });
 }
 
@@ -1001,6 +1006,8 @@ int ppst_server_register_column(ppst_server* srv, const ppst_ciphertext* const* 
 int ppst_server_submit(ppst_server* srv, const ppst_query* q, uint64_t* ticket) {
   return guard([&] {
     NEED(srv); NEED(q); NEED(ticket);
+    // admission estimates cover the statistics' own working sets only
+    if (q->cfg.boot) PPST_THROW(ST_EINVAL, "served queries run without bootstrapping");
     Query Q;
     Q.kind = q->kind;
     Q.col_x = q->col_x;

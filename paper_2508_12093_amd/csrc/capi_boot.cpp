@@ -41,6 +41,13 @@ int ppst_boot_destroy(ppst_boot* bt) {
   return guard([&] { delete bt; });
 }
 
+int ppst_boot_count(const ppst_boot* bt, uint64_t* n) {
+  return guard([&] {
+    NEED(n);
+    *n = boot_of(bt).runs.load(std::memory_order_relaxed);
+  });
+}
+
 int ppst_evk_add_boot(ppst_context* ctx, const ppst_secret_key* sk, uint64_t seed,
                       ppst_eval_keys* evk) {
   return guard([&] {

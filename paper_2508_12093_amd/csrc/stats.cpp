@@ -19,6 +19,8 @@
 //     a constant when a ciphertext is full and a plaintext vector otherwise.
 #include "stats.h"
 
+#include "boot.h"
+
 #include <future>
 #include <map>
 #include <tuple>
@@ -232,8 +234,11 @@ struct Circ {
     return base;
   }
 
-  std::pair<CtPtr, CtPtr> inv_sqrt(const CtPtr& v, double Bp, const InvSqrtCfg& cfg) {
-    return inv_sqrt_n({v}, {Bp}, cfg)[0];
+  // a refresh: down to level 0, then bootstrapped to the top computation level
+  CtPtr refresh(const CtPtr& x, const Bootstrapper& bt) { return bootstrap(cx, evk, bt, *at(x, 0)); }
+
+  std::pair<CtPtr, CtPtr> inv_sqrt(const CtPtr& v, double Bp, const InvSqrtCfg& cfg, int reserve = 0) {
+    return inv_sqrt_n({v}, {Bp}, cfg, reserve)[0];
   }
 
   CtPtr sqrt_(const CtPtr& v, double Bp, const InvSqrtCfg& cfg) {
@@ -319,12 +324,23 @@ struct Circ {
     return y;
   }
 
-  std::vector<std::pair<CtPtr, CtPtr>> inv_sqrt_n(const std::vector<CtPtr>& vs,
+  std::vector<std::pair<CtPtr, CtPtr>> inv_sqrt_n(const std::vector<CtPtr>& vs_in,
                                                   const std::vector<double>& Bps,
-                                                  const InvSqrtCfg& cfg) {
+                                                  const InvSqrtCfg& cfg, int reserve = 0) {
     const double a = cfg.a, b = cfg.b;
     const int d = cfg.degree;
-    const size_t nl = vs.size();
+    const size_t nl = vs_in.size();
+    const Bootstrapper* bt = cfg.boot;
+    std::vector<CtPtr> vs(vs_in);
+    if (bt) {
+      // the affine map, the ladder (T_d lies ceil(log2 d) levels down) and
+      // the weighted sum must fit above level 0
+      int ladder = 0;
+      while ((1 << ladder) < d) ++ladder;
+      const int need = (2.0 / (b - a) == 1.0 ? 0 : 1) + ladder + 1;
+      for (size_t l = 0; l < nl; ++l)
+        if (vs[l]->level < need) vs[l] = refresh(vs[l], *bt);
+    }
     std::vector<std::vector<double>> c(nl);
     std::vector<CtPtr> ts(nl);
     for (size_t l = 0; l < nl; ++l) {
@@ -333,8 +349,15 @@ struct Circ {
       ts[l] = affine(vs[l], a, b);
     }
     std::vector<CtPtr> y = cheb_series_n(ts, c, d), w2(nl);
+    if (bt)   // Alg. 3: the initial value is bootstrapped
+      for (size_t l = 0; l < nl; ++l) y[l] = refresh(y[l], *bt);
     for (size_t l = 0; l < nl; ++l) w2[l] = mc(vs[l], Bps[l] / 2.0);
     for (int it = 0; it < cfg.iters; ++it) {
+      if (bt)   // a step takes two levels below min(level w2, level y)
+        for (size_t l = 0; l < nl; ++l) {
+          if (w2[l]->level < 2) w2[l] = refresh(w2[l], *bt);
+          if (y[l]->level < 2) y[l] = refresh(y[l], *bt);
+        }
       // y^2 and w2 y side by side, then their product
       std::vector<CtPtr> A(y), B(y);
       A.insert(A.end(), w2.begin(), w2.end());
@@ -344,6 +367,9 @@ struct Circ {
       auto p2 = mulx_n(p1, y2);
       for (size_t l = 0; l < nl; ++l) y[l] = subx(lin1(y[l], 1.5, p2[l]->level), p2[l]);
     }
+    if (bt)
+      for (size_t l = 0; l < nl; ++l)
+        if (y[l]->level < reserve) y[l] = refresh(y[l], *bt);
     std::vector<std::pair<CtPtr, CtPtr>> out;
     for (size_t l = 0; l < nl; ++l) out.push_back({y[l], w2[l]});
     return out;
@@ -435,7 +461,7 @@ std::vector<CtPtr> stat_invsqrt(Context& cx, const EvalKeys& evk, const std::vec
     if (x->level != X[0]->level) PPST_THROW(ST_ESCALE, "input ciphertexts at different levels");
   check_cfg(cfg);
   Circ c{cx, evk};
-  c.check_depth(X, 1 + invsqrt_depth(cfg));
+  c.check_depth(X, 1 + (cfg.boot ? 0 : invsqrt_depth(cfg)));
   auto vs = c.mc_n(X, 1.0 / B);
   auto r = c.inv_sqrt_n(vs, std::vector<double>(X.size(), B), cfg);
   std::vector<CtPtr> out;
@@ -448,10 +474,10 @@ std::vector<CtPtr> stat_zscore(Context& cx, const EvalKeys& evk, const std::vect
   check_column(cx.P(), X, n);
   check_cfg(cfg);
   Circ c{cx, evk};
-  c.check_depth(X, 4 + invsqrt_depth(cfg));
+  c.check_depth(X, 4 + (cfg.boot ? 0 : invsqrt_depth(cfg)));
   auto mv = c.moments(X, n, B, B);
   auto mu = c.mc(mv.first, B);
-  auto b = c.inv_sqrt(mv.second, B * B, cfg).first;
+  auto b = c.inv_sqrt(mv.second, B * B, cfg, 1).first;
   auto dx = c.sub_each(X, mu);
   return c.mulx_n(dx, std::vector<CtPtr>(dx.size(), b));
 }
@@ -461,7 +487,7 @@ CtPtr stat_kurtosis(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& 
   check_column(cx.P(), X, n);
   check_cfg(cfg);
   Circ c{cx, evk};
-  c.check_depth(X, 6 + invsqrt_depth(cfg));
+  c.check_depth(X, 6 + (cfg.boot ? 0 : invsqrt_depth(cfg)));
   c.prefetch_mask(n);
   auto mv = c.moments(X, n, B, B);
   auto var = mv.second;
@@ -469,7 +495,7 @@ CtPtr stat_kurtosis(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& 
   auto x1 = c.sub_each(X, mu);
   auto x2 = c.mulx_n(x1, x1);
   auto num = c.mask_mean(c.mulx_n(x2, x2), n);
-  auto i = c.inv_sqrt(var, B * B, cfg).first;
+  auto i = c.inv_sqrt(var, B * B, cfg, 3).first;
   auto i2 = c.sq(i);
   // (num i^2) i^2 keeps every partial product near the result's size
   auto k = c.mulx(c.mulx(num, i2), i2);
@@ -481,7 +507,7 @@ CtPtr stat_skewness(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& 
   check_column(cx.P(), X, n);
   check_cfg(cfg);
   Circ c{cx, evk};
-  c.check_depth(X, 5 + invsqrt_depth(cfg));
+  c.check_depth(X, 5 + (cfg.boot ? 0 : invsqrt_depth(cfg)));
   c.prefetch_mask(n);
   auto mv = c.moments(X, n, B, B);
   auto var = mv.second;
@@ -489,7 +515,7 @@ CtPtr stat_skewness(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& 
   auto x1 = c.sub_each(X, mu);
   auto x2 = c.mulx_n(x1, x1);
   auto num = c.mask_mean(c.mulx_n(x2, x1), n);
-  auto i = c.inv_sqrt(var, B * B, cfg).first;
+  auto i = c.inv_sqrt(var, B * B, cfg, 2).first;
   auto i2 = c.sq(i);
   return c.mulx(c.mulx(num, i), i2);
 }
@@ -499,6 +525,7 @@ CtPtr stat_cv(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& X, siz
   check_column(cx.P(), X, n);
   check_cfg(cfg);
   if (sign_k < 0 || sign_k > 8) PPST_THROW(ST_EDOMAIN, "sign composition count out of range");
+  if (cfg.boot) PPST_THROW(ST_EINVAL, "CV runs without bootstrapping (its sign polynomial is not refreshed)");
   Circ c{cx, evk};
   c.check_depth(X, 2 + 3 * sign_k + 1 + invsqrt_depth(cfg) + 3);
   auto mv = c.moments(X, n, B_mean, B_var);
@@ -520,7 +547,7 @@ CtPtr stat_pearson(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& X
     PPST_THROW(ST_EINVAL, "the two columns differ in length or level");
   check_cfg(cfg);
   Circ c{cx, evk};
-  c.check_depth(X, 5 + invsqrt_depth(cfg));
+  c.check_depth(X, 5 + (cfg.boot ? 0 : invsqrt_depth(cfg)));
   // Eq. 2's pre-scaled moments: Mean(x, B), E[x^2]/B^2 and E[xy]/(Bx By) are
   // five independent slot sums, summed together at one level (one batched
   // RotSum); Var_B = E2 - Mean^2, Cov_B = Exy - Mean(x) Mean(y) = Cov/(Bx By)
@@ -544,7 +571,7 @@ CtPtr stat_pearson(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& X
   auto varx = c.subx(r[2], mm[0]);
   auto vary = c.subx(r[3], mm[1]);
   auto cov = c.subx(r[4], mm[2]);
-  auto is = c.inv_sqrt_n({varx, vary}, {1.0, 1.0}, cfg);
+  auto is = c.inv_sqrt_n({varx, vary}, {1.0, 1.0}, cfg, 2);
   return c.mulx(cov, c.mulx(is[0].first, is[1].first));
 }
 

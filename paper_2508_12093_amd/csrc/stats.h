@@ -10,11 +10,19 @@ namespace ppst {
 // degree-d initial value holds d + 1 ciphertexts per input at once.
 constexpr int kMaxChebDegree = 511;
 
+struct Bootstrapper;
+
 struct InvSqrtCfg {
   double a = 1e-3, b = 1.0;    // interval of the Chebyshev initial value
   int degree = 7;              // Chebyshev degree
   int iters = 3;               // Newton iterations
   std::vector<double> coeffs;  // optional c_0..c_d of 1/sqrt(v) on [a, b] (B' = 1)
+  // With a bootstrapper the chain's levels are refreshed inside InvSqrt
+  // (each refresh: level_align to 0, then bootstrap): the argument when it
+  // has fewer levels than the initial value's polynomial needs, the initial
+  // value itself (Alg. 3), w2 or y before a Newton step that lacks its two
+  // levels, and the result when fewer remain than the statistic needs after.
+  const Bootstrapper* boot = nullptr;
 };
 
 // first-kind Chebyshev interpolation coefficients of 1/sqrt(Bp v) on [a, b]

@@ -46,7 +46,7 @@ class Info(ctypes.Structure):
 class InvSqrtCfg(ctypes.Structure):
     _fields_ = [("a", ctypes.c_double), ("b", ctypes.c_double), ("degree", ctypes.c_int32),
                 ("iters", ctypes.c_int32), ("sign_k", ctypes.c_int32),
-                ("coeffs", ctypes.POINTER(ctypes.c_double))]
+                ("coeffs", ctypes.POINTER(ctypes.c_double)), ("boot", ctypes.c_void_p)]
 
 
 class Query(ctypes.Structure):
@@ -143,6 +143,7 @@ _SIGS = {
     "ppst_boot_create": (ctypes.c_int, [_vp, _vp, _sz, _pp]),
     "ppst_boot_destroy": (ctypes.c_int, [_vp]),
     "ppst_evk_add_boot": (ctypes.c_int, [_vp, _vp, _u64, _vp]),
+    "ppst_boot_count": (ctypes.c_int, [_vp, ctypes.POINTER(_u64)]),
     "ppst_boot_rotations": (ctypes.c_int, [_vp, _vp, _sz, ctypes.POINTER(ctypes.c_size_t)]),
     "ppst_boot_group_info": (ctypes.c_int, [_vp, _i32, _i32, _vp]),
     "ppst_boot_group_coeffs": (ctypes.c_int, [_vp, _i32, _i32, _vp, _vp, _sz]),
@@ -663,6 +664,12 @@ def ppst_boot_create(ctx, coeffs=None):
     return Boot(out.value, ctx)
 
 
+def ppst_boot_count(bt) -> int:
+    n = _u64()
+    _chk(lib().ppst_boot_count(bt, ctypes.byref(n)))
+    return int(n.value)
+
+
 def ppst_evk_add_boot(ctx, sk, seed, evk):
     _chk(lib().ppst_evk_add_boot(ctx, sk, seed, evk))
 
@@ -783,11 +790,15 @@ def ppst_graph_end(ctx) -> Graph:
     return Graph(out.value, ctx)
 
 
-def ppst_invsqrt_cfg_default(coeffs=None, **kw) -> InvSqrtCfg:
+def ppst_invsqrt_cfg_default(coeffs=None, boot=None, **kw) -> InvSqrtCfg:
+    """boot: a Boot handle (ppst_boot_create) for InvSqrt with refreshes."""
     cfg = InvSqrtCfg()
     _chk(lib().ppst_invsqrt_cfg_default(ctypes.byref(cfg)))
     for k, v in kw.items():
         setattr(cfg, k, v)
+    if boot is not None:
+        cfg._boot = boot
+        cfg.boot = boot.ptr
     if coeffs is not None:
         arr = np.ascontiguousarray(coeffs, dtype=np.float64)
         cfg._keep = arr

@@ -18,7 +18,8 @@ import pytest
 sys.path.insert(0, os.path.dirname(__file__))
 from gpu_common import Pair  # noqa: E402
 
-from oracle import boot, cheb, ref  # noqa: E402
+from oracle import boot, cheb, ref, stats64  # noqa: E402
+from oracle import circuits as C  # noqa: E402
 from paper_2508_12093_amd import ffi, synth  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -138,6 +139,67 @@ def test_bootstrap_errors(bp):
     del e, other, raised, ct
 
 
+EXP1_COEFFS = cheb.paper_invsqrt_coeffs(31, 1.0)
+
+
+def exp2_columns(seed, n):
+    """Sec. 6.3's kurtosis / PCC data: x ~ U[0, 20], y = (x + u) / 2, u ~ U[0, 20]."""
+    x = synth.uniform_column(seed, n, 0.0, 20.0)
+    y = 0.5 * (x + synth.uniform_column(seed + 1, n, 0.0, 20.0))
+    return x, y
+
+
+@pytest.fixture(scope="module")
+def bstat(bp):
+    """bp with the RotSum keys the statistics need: the library adds them
+    after the bootstrapping keys (existing Galois elements keep their key),
+    the oracle's dictionary is built the same way."""
+    p = bp
+    p.ogk = dict(p.OB.gkeys)
+    p.add_rotsum_keys()
+    p.ev = C.EncEval(p.O, p.orlk, p.ogk, booter=p.OB)
+    p.circ = C.Circuits(p.ev)
+    return p
+
+
+def test_b1_statistics_with_refreshes_bit_exact(bstat):
+    """Kurtosis and PCC over a two-ciphertext column at the paper's InvSqrt
+    (Eq. 3's degree 31 on [0, 2], six Newton steps, B = 20): 11 levels do
+    not hold it, so InvSqrt refreshes by bootstrapping.  The library and
+    the oracle agree bit for bit; the values agree with FP64 to 1e-4."""
+    p = bstat
+    n = 3000
+    x, y = exp2_columns(50, n)
+
+    def enc(v, seed):
+        cts, octs = [], []
+        for k in range(0, n, p.P.slots):
+            c, o = p.encrypt(v[k:k + p.P.slots], seed + k, level=p.P.Lc)
+            cts.append(c)
+            octs.append(o)
+        return cts, octs
+
+    X, OX = enc(x, 600)
+    Y, OY = enc(y, 700)
+    cfg = ffi.ppst_invsqrt_cfg_default(coeffs=EXP1_COEFFS, a=0.0, b=2.0, degree=31, iters=6, boot=p.bt)
+    ocfg = C.InvSqrtCfg(a=0.0, b=2.0, degree=31, iters=6, coeffs=EXP1_COEFFS, boot=True)
+    print("b1 kurtosis with refreshes", flush=True)
+    k = ffi.ppst_stat_kurtosis(p.ctx, p.evk, X, n, 20.0, cfg)
+    ok = p.circ.kurtosis(OX, n, 20.0, ocfg)
+    p.same(k, ok)
+    assert abs(p.decrypt(k)[0] / stats64.kurtosis(x) - 1) < 1e-4
+    print("b1 PCC with refreshes", flush=True)
+    r = ffi.ppst_stat_pearson(p.ctx, p.evk, X, Y, n, 20.0, 20.0, cfg)
+    orr = p.circ.pearson(OX, OY, n, 20.0, 20.0, ocfg)
+    p.same(r, orr)
+    assert abs(p.decrypt(r)[0] / stats64.pearson(x, y) - 1) < 1e-4
+    # CV has no refreshing form
+    with pytest.raises(ffi.PpstError) as e:
+        ffi.ppst_stat_cv(p.ctx, p.evk, X, n, 16.0, 20.0, cfg)
+    assert e.value.name == "EINVAL"
+    del e
+
+
 def test_b2_bootstrap_refreshes():
     """N = 2^16: the refresh of a full [-1, 1] column decrypts to it (max
     error 2^-15, about 2^-17 measured), lands on level 11 and computes on;
@@ -163,3 +225,39 @@ def test_b2_bootstrap_refreshes():
     sq = ffi.ppst_mul(ctx, evk, out, out)
     got2 = ffi.ppst_decode(ctx, ffi.ppst_decrypt(ctx, sk, sq), n)
     assert np.max(np.abs(got2 - m * m)) < 2.0 ** -14
+
+
+def test_b2_statistics_with_bootstrapping_one_million_rows():
+    """The full pipeline at N = 2^16: kurtosis and PCC of 2^20-row columns
+    (32 ciphertexts at level 11) with the paper's InvSqrt (degree 31, six
+    Newton steps), which 11 levels cannot hold, so InvSqrt bootstraps.
+    Decrypted values within 1e-3 relative of FP64."""
+    _torch()
+    print("b2 pipeline: keys, plaintexts", flush=True)
+    ctx = ffi.ppst_context_create("b2")
+    sk, pk = ffi.ppst_keygen(ctx, 41)
+    evk = ffi.ppst_evk_create(ctx)
+    ffi.ppst_evk_add_relin(ctx, sk, 42, evk)
+    ffi.ppst_evk_add_boot(ctx, sk, 43, evk)
+    ffi.ppst_evk_add_rotsum(ctx, sk, 44, evk)
+    bt = ffi.ppst_boot_create(ctx)
+    n = 1 << 20
+    slots = ctx.info.slots
+    x, y = exp2_columns(60, n)
+
+    def enc(v, seed):
+        return [ffi.ppst_encrypt(ctx, pk, ffi.ppst_encode(ctx, c, 11), seed + k)
+                for k, c in enumerate(synth.split_column(v, slots))]
+
+    X, Y = enc(x, 800), enc(y, 900)
+    cfg = ffi.ppst_invsqrt_cfg_default(coeffs=EXP1_COEFFS, a=0.0, b=2.0, degree=31, iters=6, boot=bt)
+    print("b2 pipeline: kurtosis", flush=True)
+    k = ffi.ppst_stat_kurtosis(ctx, evk, X, n, 20.0, cfg)
+    kv = ffi.ppst_decode(ctx, ffi.ppst_decrypt(ctx, sk, k), 1)[0]
+    print("b2 kurtosis %.6f fp64 %.6f" % (kv, stats64.kurtosis(x)), flush=True)
+    assert abs(kv / stats64.kurtosis(x) - 1) < 1e-3
+    print("b2 pipeline: PCC", flush=True)
+    r = ffi.ppst_stat_pearson(ctx, evk, X, Y, n, 20.0, 20.0, cfg)
+    rv = ffi.ppst_decode(ctx, ffi.ppst_decrypt(ctx, sk, r), 1)[0]
+    print("b2 PCC %.6f fp64 %.6f" % (rv, stats64.pearson(x, y)), flush=True)
+    assert abs(rv / stats64.pearson(x, y) - 1) < 1e-3

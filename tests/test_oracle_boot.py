@@ -232,3 +232,25 @@ def test_bootstrap_refreshes(b1):
     assert np.max(np.abs(got - m)) < 2.0 ** -19
     sq = O.mul(out, out, B.rlk)
     assert np.max(np.abs(O.decrypt(sq, sk) - m * m)) < 2.0 ** -18
+
+
+def test_kurtosis_with_refreshes(b1):
+    """Kurtosis at the paper's InvSqrt (degree 31 on [0, 2], six Newton
+    steps, B = 20) on 11 computation levels: InvSqrt refreshes by
+    bootstrapping and the result agrees with the FP64 closed form to 1e-4;
+    without the refreshes the circuit runs out of levels."""
+    from oracle import circuits as C, stats64
+    P, O, sk, pk, B = b1
+    gk = dict(B.gkeys)
+    gk.update(O.rotation_keys(sk, 12, [s for s in O.rotsum_hoisted8_steps()
+                                       if ref.galois_element(s, P.N) not in gk]))
+    circ = C.Circuits(C.EncEval(O, B.rlk, gk, booter=B))
+    n = 3000
+    x = np.random.default_rng(3).uniform(0, 20, n)
+    X = [O.encrypt(O.encode(x[k:k + P.slots], P.Lc), pk, 100 + k) for k in range(0, n, P.slots)]
+    coeffs = cheb.paper_invsqrt_coeffs(31, 1.0)
+    cfg = C.InvSqrtCfg(a=0.0, b=2.0, degree=31, iters=6, coeffs=coeffs, boot=True)
+    k = circ.kurtosis(X, n, 20.0, cfg)
+    assert abs(O.decrypt(k, sk)[0] / stats64.kurtosis(x) - 1) < 1e-4
+    with pytest.raises(ref.LevelError):
+        circ.kurtosis(X, n, 20.0, C.InvSqrtCfg(a=0.0, b=2.0, degree=31, iters=6, coeffs=coeffs))
