@@ -59,6 +59,17 @@ def build(force: bool = False) -> str:
     return _SO
 
 
+def build_sanitized(out: str) -> str:
+    """The same sources with AddressSanitizer and UndefinedBehaviorSanitizer
+    (gcc; UB aborts).  Load it by starting a process with PPST_ORACLE_SO set
+    to `out` and gcc's libasan preloaded (``gcc -print-file-name=libasan.so``)."""
+    cmd = ["gcc", "-O1", "-g", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+           "-fno-omit-frame-pointer", "-I" + _HERE, "-o", out] + _SRCS + ["-lquadmath", "-lm"]
+    subprocess.check_call(cmd)
+    return out
+
+
 def build_native(out: str) -> str:
     """The same source for the host that builds it (never shipped
     elsewhere): -O2 -march=native, the fastest of -O2 / -O3 with and without

@@ -35,21 +35,21 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=o
          "-Wall", "-Wno-unused-function", "-I" + os.path.join(ROOT, "include")]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, "-x", "hip"] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(src: str, build_dir: str = BUILD, extra=()) -> str:
+    obj = os.path.join(build_dir, os.path.basename(src) + ".o")
+    cmd = [HIPCC, "-x", "hip"] + FLAGS + list(extra) + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed on %s:\n%s%s" % (src, r.stdout, r.stderr))
     return obj
 
 
-def _compile_host(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [CXX] + HOST_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+def _compile_host(src: str, build_dir: str = BUILD, cxx: str = CXX, extra=()) -> str:
+    obj = os.path.join(build_dir, os.path.basename(src) + ".o")
+    cmd = [cxx] + HOST_FLAGS + list(extra) + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError("%s failed on %s:\n%s%s" % (CXX, src, r.stdout, r.stderr))
+        raise RuntimeError("%s failed on %s:\n%s%s" % (cxx, src, r.stdout, r.stderr))
     return obj
 
 
@@ -77,6 +77,64 @@ def build(verbose: bool = False) -> str:
     return OUT
 
 
+# Sanitizer builds of the host code (the device code is built as usual):
+# "address" = AddressSanitizer + UndefinedBehaviorSanitizer, "thread" =
+# ThreadSanitizer.  Every flag goes to the host pass only (-Xarch_host); the
+# binary128 file is built with the same clang so that one sanitizer runtime
+# serves the whole library.  Load the result with that runtime preloaded
+# (sanitizer_runtime(kind)); tests/test_sanitizers.py runs the CPU suite's
+# host-only library tests against it.
+SAN_FLAGS = {
+    "address": ["-fsanitize=address", "-fsanitize=undefined", "-fno-sanitize-recover=undefined",
+                "-fno-omit-frame-pointer"],
+    "thread": ["-fsanitize=thread"],
+}
+CLANGXX = "/opt/rocm/llvm/bin/clang++"
+
+
+def _gcc_private_include() -> list:
+    """gcc's own include directory (quadmath.h lives there), searched after
+    clang's headers."""
+    r = subprocess.run(["gcc", "-print-file-name=include"], capture_output=True, text=True)
+    d = r.stdout.strip()
+    return ["-idirafter", d] if d and os.path.isdir(d) else []
+
+
+def sanitizer_runtime(kind: str) -> str:
+    lib = {"address": "libclang_rt.asan-x86_64.so", "thread": "libclang_rt.tsan-x86_64.so"}[kind]
+    base = "/opt/rocm/llvm/lib/clang"
+    for v in sorted(os.listdir(base), reverse=True):
+        p = os.path.join(base, v, "lib", "linux", lib)
+        if os.path.exists(p):
+            return p
+    raise RuntimeError("no %s runtime under %s" % (kind, base))
+
+
+def build_sanitized(kind: str, verbose: bool = False) -> str:
+    flags = SAN_FLAGS[kind]
+    bdir = os.path.join(BUILD, "san_" + kind)
+    out = os.path.join(bdir, "libppstat.so")
+    os.makedirs(bdir, exist_ok=True)
+    host_extra = []
+    for f in flags:
+        host_extra += ["-Xarch_host", f]
+    jobs = min(len(SOURCES), int(os.environ.get("MAX_JOBS", "8")))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        host = [ex.submit(_compile_host, h, bdir, CLANGXX, flags + _gcc_private_include())
+                for h in HOST_SOURCES]
+        objs = list(ex.map(lambda src: _compile(src, bdir, host_extra), SOURCES))
+        hobjs = [f.result() for f in host]
+    # the sanitizer symbols stay undefined in the shared object and resolve
+    # to the preloaded runtime
+    _link(objs + hobjs, out, ["-lpthread", "-lquadmath"])
+    if verbose:
+        print("built", out)
+    return out
+
+
 if __name__ == "__main__":
-    build(verbose=True)
+    if len(sys.argv) > 2 and sys.argv[1] == "--sanitize":
+        build_sanitized(sys.argv[2], verbose=True)
+    else:
+        build(verbose=True)
     sys.exit(0)

@@ -14,7 +14,9 @@ import re
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libppstat.so")
+# PPST_LIBRARY: another build of the same library (the sanitizer builds of
+# build.py); the in-tree one otherwise
+LIB_PATH = os.environ.get("PPST_LIBRARY") or os.path.join(_HERE, "libppstat.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "ppstat.h")
 
 PPST_OK = 0
