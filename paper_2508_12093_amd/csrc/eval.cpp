@@ -543,6 +543,24 @@ void ks_accumulate_into(Context& cx, const KsKey& key, const u64* d, size_t sd, 
     ntt(sh, L, true, cx.stream);
   }
   k_modup(sh, x, ext, level, nbatch, sx, sext, cx.stream);
+  if (ks_fused_ok(P, level)) {
+    // the digits' row pass and the inner product in one kernel
+    KsTail kt{};
+    kt.ext = ext;
+    kt.d = d;
+    kt.sd = sd;
+    kt.key = key.k.p;
+    kt.u = u;
+    kt.pd = prep_d;
+    kt.spd = sd;
+    if (prep_d) {
+      kt.pmod = sh.tab.pmod_host[2 * level];
+      kt.pmods = sh.tab.pmod_host[2 * level + 1];
+    }
+    kt.gd = g;
+    ntt_fwd_ks_fused(sh, kt, level, nbatch, cx.stream);
+    return;
+  }
   ntt_ext_digits(cx, ext, level, nbatch);
   k_ks_inner(sh, d, ext, key.k.p, u, level, nbatch, sd, sext, su, g, 0, cx.stream, prep_d, sd);
 }

@@ -72,6 +72,27 @@ struct MdTail {
   u64* const* out;
   uint32_t gadd;
 };
+// The extended digits' forward NTT fused with the key inner product: the
+// column pass of ext ([nbatch][beta][ne][N], ModUp output, digit mode), then
+// one row pass per digit whose results are multiplied by the key and summed
+// in registers: u ([nbatch][2][ne][N]) as k_ks_inner computes it from the
+// fully transformed digits (d: the input in NTT form for the digits' own
+// limbs, read through X -> X^gd; pd: the tensor for the product's P d0, P d1
+// on limb q_l, or null).  ks_fused_ok: N = 2^16, at most 4 digits, and not
+// switched off by PPST_KS_FUSED=0.
+struct KsTail {
+  u64* ext;
+  const u64* d;
+  size_t sd;
+  const u64* key;
+  u64* u;
+  const u64* pd;
+  size_t spd;
+  u64 pmod, pmods;
+  uint32_t gd;
+};
+bool ks_fused_ok(const Params& P, int level);
+void ntt_fwd_ks_fused(const Shared& sh, const KsTail& tail, int level, int nbatch, hipStream_t st);
 void ntt_fwd_md_final(const Shared& sh, u64* conv, int level, int nbatch, const MdTail& tail,
                       hipStream_t st);
 

@@ -19,6 +19,8 @@
 // fits one workgroup and runs as a single row pass.
 #include "dev.h"
 #include "kern.h"
+
+#include <cstdlib>
 #include "tables.h"
 
 namespace ppst {
@@ -627,6 +629,142 @@ void run_row_md(const NttArgs& base, const MdEpi& e, int nlimbs, int nbatch, hip
   hipLaunchKernelGGL((k_ntt_row_md<LOGM, LOGE, SB>), grid, block, 0, st, a, e);
 }
 
+// ---- forward row pass of the extended digits fused with the key inner product
+// A workgroup owns SB rows of one extended limb t (prime p) and a run of
+// batch items.  For each item it transforms the rows of every digit j
+// (column pass already done; a digit's own limbs come from the input d in
+// NTT form, read through X -> X^gd) and accumulates v * key_j in the
+// epilogue, so the transformed digits never go back to memory and the key
+// rows, held in registers, are read once per workgroup:
+//   u_c[t] = sum_j ext_j[t] * key_{j,c}[t]   (c = 0: the b half, 1: the a half)
+// plus, for products (pd), (P mod q_l) times d0 / d1 on limb q_l — the
+// operations and order of the separate inner-product kernel.
+constexpr int kKsFusedDigits = 4;
+
+struct KsEpi {
+  const u64* ext;    // [item][beta][ne][N], columns transformed
+  size_t sext;
+  const u64* d;      // [item] input in NTT form (limbs 0..l), stride sd
+  size_t sd;
+  const u64* key;    // [beta][2][nprimes][N]
+  u64* u;            // [item][2][ne][N]
+  size_t su;
+  const u64* pd;     // [item][3][nl][N] tensor (d0, d1) or null
+  size_t spd;
+  u64 pmod, pmods;
+  uint32_t gd;
+  int nl, ne, beta, alpha, pofs, nprimes, nbatch, items, logN;
+};
+
+// 128-bit sums of at most kKsFusedDigits products of residues below 2^60
+template <int E>
+struct KsAccStore {
+  Acc s0[E], s1[E];
+  const u64* kb;     // the digit's key rows on this limb's prime
+  const u64* ka;
+  u64 pb[E], pa[E];
+  __device__ __forceinline__ void prefetch(int i, size_t at) {
+    pb[i] = kb[at];
+    pa[i] = ka[at];
+  }
+  __device__ __forceinline__ void put(int i, size_t, u64 v) {
+    s0[i].mac(v, pb[i]);
+    s1[i].mac(v, pa[i]);
+  }
+};
+
+template <class A, int LOGM, int LOGE, int SB>
+__device__ __forceinline__ void ks_tile(const A ar, u64* lds, const NttArgs& a, const KsEpi& e,
+                                        int t, int prime, int first, int item0, int item1) {
+  constexpr int M = 1 << LOGM;
+  constexpr int E = 1 << LOGE;
+  constexpr int TPS = M / E;
+  constexpr int NP = (LOGM + LOGE - 1) / LOGE;
+  const int N = a.N;
+  const size_t NN = (size_t)N;
+  // the slots this thread finishes in the last register pass (ntt_body_dio's map)
+  const int tid = threadIdx.x;
+  const int sp = tid / TPS, lane = tid - sp * TPS;
+  const size_t rowbase = (size_t)(first + sp) * M;
+  uint32_t at[E];     // within the limb (N <= 2^16)
+  {
+    constexpr int s0 = (NP - 1) * LOGE;
+    constexpr int ls = (LOGM - s0) < LOGE ? (LOGM - s0) : LOGE;
+    constexpr int GS = 1 << ls, G = E / GS, si = M >> (s0 + ls);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int gi = g * TPS + lane;
+      const int e0 = (gi / si) * (M >> s0) + gi % si;
+#pragma unroll
+      for (int k = 0; k < GS; ++k) at[g * GS + k] = (uint32_t)(rowbase + e0 + k * si);
+    }
+  }
+  const int own = t < e.nl ? t / e.alpha : -1;
+  const ulonglong2* tw = (const ulonglong2*)(a.tw + (size_t)prime * NN * 2);
+  const u64* ni = a.ninv + 2 * prime;
+  const Mod m = a.mods[prime];
+  const bool prep = e.pd != nullptr && t == e.nl - 1;
+  for (int item = item0; item < item1; ++item) {
+    KsAccStore<E> st;
+    // one copy of the transform serves every digit (the key rows of later
+    // items come from L2)
+#pragma unroll 1
+    for (int j = 0; j < e.beta; ++j) {
+      st.kb = e.key + ((size_t)(2 * j) * e.nprimes + prime) * NN;
+      st.ka = e.key + ((size_t)(2 * j + 1) * e.nprimes + prime) * NN;
+      if (j == own) {
+        const u64* dt = e.d + (size_t)item * e.sd + (size_t)t * NN;
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+          st.prefetch(i, at[i]);
+          st.put(i, 0, dt[galois_src(at[i], e.gd, e.logN)]);
+        }
+      } else {
+        const u64* src = e.ext + (size_t)item * e.sext + ((size_t)j * e.ne + t) * NN;
+        ntt_body_dio<A, LOGM, LOGE, SB, true, false>(ar, (typename A::T*)lds, src, st, tw, ni, N,
+                                                     a.logR, first, a.logR == 0, true, 0u, a.logN);
+        __syncthreads();   // the next digit's exchanges reuse the LDS rows
+      }
+    }
+    u64* u0 = e.u + (size_t)item * e.su + (size_t)t * NN;
+    u64* u1 = u0 + (size_t)e.ne * NN;
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      u64 v0 = reduce128(st.s0[i].hi, st.s0[i].lo, m), v1 = reduce128(st.s1[i].hi, st.s1[i].lo, m);
+      if (prep) {
+        const u64* dp = e.pd + (size_t)item * e.spd + (size_t)t * NN + at[i];
+        v0 = addm(v0, mul_shoup(dp[0], e.pmod, e.pmods, m.q), m.q);
+        v1 = addm(v1, mul_shoup(dp[(size_t)e.nl * NN], e.pmod, e.pmods, m.q), m.q);
+      }
+      u0[at[i]] = v0;
+      u1[at[i]] = v1;
+    }
+  }
+}
+
+// grid: (item group fastest, then row group, then limb)
+// At most 168 VGPRs for three waves per SIMD (it spills 36 bytes per lane):
+// faster than two waves without spills, the kernel being latency-bound.
+template <int LOGM, int LOGE, int SB>
+__global__ void __launch_bounds__(SB * (1 << (LOGM - LOGE)), 3)
+k_ntt_row_ks(NttArgs a, KsEpi e) {
+  constexpr int M = 1 << LOGM;
+  __shared__ u64 lds[SB * (M + 1)];
+  const int groups = (1 << a.logR) / SB;
+  const int nig = (e.nbatch + e.items - 1) / e.items;
+  const unsigned b = blockIdx.x;
+  const int ig = (int)(b % (unsigned)nig);
+  const int rg = (int)((b / (unsigned)nig) % (unsigned)groups);
+  const int t = (int)(b / ((unsigned)nig * (unsigned)groups));
+  const int prime = t < e.nl ? t : e.pofs + (t - e.nl);
+  const int item0 = ig * e.items, item1 = min(item0 + e.items, e.nbatch);
+  const u64 q = a.mods[prime].q;
+  if (q < kFpPrimeBound)
+    ks_tile<FpArith, LOGM, LOGE, SB>(FpArith(q), lds, a, e, t, prime, rg * SB, item0, item1);
+  else
+    ks_tile<IntArith, LOGM, LOGE, SB>(IntArith(q), lds, a, e, t, prime, rg * SB, item0, item1);
+}
+
 // ---- forward row pass that finishes a rescale
 // For limb i < l of polynomial c the stored element is
 //   ((k_i a_c,i or a_c,i) - corr_i) q_l^-1 mod q_i
@@ -940,6 +1078,72 @@ static MdFn md_variant(int logN, int row_index) {
     case 3: case 7: case 11: return run_row_md<8, 2, 4>;
     default: return run_row_md<8, 3, 4>;
   }
+}
+
+bool ks_fused_ok(const Params& P, int level) {
+  static const bool enabled = [] {
+    const char* v = std::getenv("PPST_KS_FUSED");
+    return !(v && v[0] == '0');
+  }();
+  return enabled && P.logN == 16 && P.beta(level) <= kKsFusedDigits;
+}
+
+void ntt_fwd_ks_fused(const Shared& sh, const KsTail& tail, int level, int nbatch, hipStream_t st) {
+  const Params& P = sh.P;
+  if (nbatch <= 0) return;
+  if (!ks_fused_ok(P, level)) PPST_THROW(ST_EINVAL, "fused key switch needs N = 2^16 and at most 4 digits");
+  const int nl = level + 1, ne = nl + P.K, beta = P.beta(level);
+  const size_t N = P.N;
+  NttArgs a{};
+  a.mods = (const Mod*)sh.tab.mods.p;
+  a.tw = sh.tab.fwd.p;
+  a.ninv = sh.tab.ninv.p;
+  a.N = P.N;
+  a.logN = P.logN;
+  a.logR = 8;
+  a.nq = nl;
+  a.pofs = P.L + 1;
+  a.skip_lo = a.skip_hi = 1 << 30;
+  a.dalpha = P.alpha;
+  a.dcount = beta;
+  a.dtotal = ne;
+  a.galois = 0;
+  a.batch_stride = a.dst_stride = (size_t)ne * N;
+  int most = 0;
+  for (int j = 0; j < beta; ++j) most = std::max(most, ne - (P.digit_hi(j, level) - P.digit_lo(j)));
+  const int b = ntt_bucket(most * nbatch * beta);
+  a.src = tail.ext;
+  a.dst = tail.ext;
+  kCol16[sh.ntt_plan.v[0][0][b]].fwd(a, most, nbatch * beta, st);
+  KsEpi e{};
+  e.ext = tail.ext;
+  e.sext = (size_t)beta * ne * N;
+  e.d = tail.d;
+  e.sd = tail.sd;
+  e.key = tail.key;
+  e.u = tail.u;
+  e.su = 2 * (size_t)ne * N;
+  e.pd = tail.pd;
+  e.spd = tail.spd;
+  e.pmod = tail.pmod;
+  e.pmods = tail.pmods;
+  e.gd = tail.gd;
+  e.nl = nl;
+  e.ne = ne;
+  e.beta = beta;
+  e.alpha = P.alpha;
+  e.pofs = P.L + 1;
+  e.nprimes = P.nprimes;
+  e.nbatch = nbatch;
+  e.logN = P.logN;
+  e.items = std::min(nbatch, 8);
+  constexpr int LOGM = 8, LOGE = 2, SB = 4;
+  const int groups = (1 << a.logR) / SB;
+  const int nig = (nbatch + e.items - 1) / e.items;
+  dim3 grid((unsigned)(nig * groups * ne));
+  dim3 block(SB * (1 << (LOGM - LOGE)));
+  hipLaunchKernelGGL((k_ntt_row_ks<LOGM, LOGE, SB>), grid, block, 0, st, a, e);
+  HIP_CHECK(hipGetLastError());
 }
 
 void ntt_fwd_md_final(const Shared& sh, u64* conv, int level, int nbatch, const MdTail& tail,
