@@ -646,7 +646,94 @@ def boot_bench(stream, runs: int):
         log("config 5 %-8s %8.2f ms, %d bootstraps, rel err %.2e" % (
             name, ms_s, pipe[name]["bootstraps"], pipe[name]["rel_err"]))
     res["pipeline"] = pipe
-    del X, Y, bt, evk, sk, pk, bctx
+    del X, Y
+    res["exp1"] = exp1_boot(bctx, pk, sk, evk, bt, sync)
+    res["exp2"] = exp2_boot(bctx, pk, sk, evk, bt, sync)
+    del bt, evk, sk, pk, bctx
+    return res
+
+
+def _timed_stat(bt, sync, fn):
+    from paper_2508_12093_amd import ffi
+    fn()
+    sync()
+    b0 = ffi.ppst_boot_count(bt)
+    t = time.perf_counter()
+    r = fn()
+    sync()
+    return r, (time.perf_counter() - t) * 1e3, ffi.ppst_boot_count(bt) - b0
+
+
+def exp1_boot(ctx, pk, sk, evk, bt, sync):
+    """Sec. 6.2 (Tab. 2) at the paper's settings on the bootstrappable chain:
+    the 32768-point grid on [0.001, 100], B = 100; CryptoInvSqrt = Eq. 3's
+    degree 31 on [0, 2] and six Newton steps, and the HEaaN-STAT comparator
+    (y_0 = 1, 21 Newton steps on x / 100), both with refreshes; MRE against
+    1/sqrt(x), bootstraps counted."""
+    import numpy as np
+
+    from paper_2508_12093_amd import ffi, synth
+    grid = synth.exp1_grid(ctx.info.slots)
+    cg = ffi.ppst_encrypt(ctx, pk, ffi.ppst_encode(ctx, grid, 11), 5100)
+    out = {"workload": "32768-point grid on [0.001, 100] at level 11 of b2, B = 100"}
+    for name, cfg in (
+            ("cryptoinvsqrt", ffi.ppst_invsqrt_cfg_default(a=0.0, b=2.0, degree=31, iters=6, boot=bt)),
+            ("heaan_stat", ffi.ppst_invsqrt_cfg_default(coeffs=np.array([1.0]), a=0.0, b=2.0, degree=0,
+                                                         iters=21, boot=bt))):
+        r, ms, nb = _timed_stat(bt, sync, lambda: ffi.ppst_stat_invsqrt(ctx, evk, [cg], 100.0, cfg))
+        v = ffi.ppst_decode(ctx, ffi.ppst_decrypt(ctx, sk, r[0]))
+        mre = float(np.mean(np.abs(v * np.sqrt(grid) - 1.0)))
+        out[name] = {"ms": round(ms, 2), "bootstraps": nb, "mre": mre}
+        log("Exp. 1 with bootstrapping %-14s %8.2f ms, %d bootstraps, MRE %.3e" % (name, ms, nb, mre))
+    return out
+
+
+def exp2_boot(ctx, pk, sk, evk, bt, sync, n: int = 1_000_000):
+    """Sec. 6.3 (Tab. 3) at the paper's settings on the bootstrappable chain:
+    10^6 rows (31 ciphertexts at level 11); ZNorm on U[0, 100] with B = 100;
+    skewness, kurtosis, CV (three-fold g_3 sign) and PCC on U[0, 20] with
+    B = 20; CryptoInvSqrt of Exp. 1; refreshes where the 11 levels run out."""
+    import numpy as np
+
+    from paper_2508_12093_amd import ffi, synth
+    slots = ctx.info.slots
+    x100 = synth.uniform_column(5211, n, 0.0, 100.0)
+    x20 = synth.uniform_column(5212, n, 0.0, 20.0)
+    y20 = 0.5 * (x20 + synth.uniform_column(5213, n, 0.0, 20.0))
+
+    def enc(v, seed):
+        return [ffi.ppst_encrypt(ctx, pk, ffi.ppst_encode(ctx, c, 11), seed + k)
+                for k, c in enumerate(synth.split_column(v, slots))]
+
+    c100, c20, cy = enc(x100, 52000), enc(x20, 53000), enc(y20, 54000)
+    cfg = ffi.ppst_invsqrt_cfg_default(a=0.0, b=2.0, degree=31, iters=6, sign_k=3, boot=bt)
+
+    def moments(v):
+        d = v - v.mean()
+        m2, m3, m4 = np.mean(d ** 2), np.mean(d ** 3), np.mean(d ** 4)
+        return d / np.sqrt(m2), m3 / m2 ** 1.5, m4 / m2 ** 2, np.sqrt(m2) / v.mean()
+
+    z_ref = moments(x100)[0]
+    _, sk_ref, ku_ref, cv_ref = moments(x20)
+    dec = lambda c: ffi.ppst_decode(ctx, ffi.ppst_decrypt(ctx, sk, c))
+    runs = {
+        "zscore": (lambda: ffi.ppst_stat_zscore(ctx, evk, c100, n, 100.0, cfg), z_ref),
+        "skewness": (lambda: ffi.ppst_stat_skewness(ctx, evk, c20, n, 20.0, cfg), sk_ref),
+        "kurtosis": (lambda: ffi.ppst_stat_kurtosis(ctx, evk, c20, n, 20.0, cfg), ku_ref),
+        "cv": (lambda: ffi.ppst_stat_cv(ctx, evk, c20, n, 20.0, 20.0, cfg), cv_ref),
+        "pearson": (lambda: ffi.ppst_stat_pearson(ctx, evk, c20, cy, n, 20.0, 20.0, cfg),
+                    float(np.corrcoef(x20, y20)[0, 1])),
+    }
+    res = {"workload": "10^6 rows (31 ciphertexts at level 11 of b2), Sec. 6.3 settings, "
+                       "InvSqrt degree 31 + 6 Newton steps with refreshes, CV sign g_3^(3)"}
+    for name, (fn, ref) in runs.items():
+        r, ms, nb = _timed_stat(bt, sync, fn)
+        got = np.concatenate([dec(c) for c in r])[:n] if isinstance(r, list) else dec(r)[0]
+        err = _mre(got, ref)
+        res[name] = {"ms": round(ms, 2), "bootstraps": nb, "mre": err,
+                     "abs_err": float(np.max(np.abs(got - ref)))}
+        log("Exp. 2 with bootstrapping %-8s %8.2f ms, %d bootstraps, MRE %.3e" % (name, ms, nb, err))
+        del r
     return res
 
 

@@ -382,7 +382,8 @@ int ppst_graph_destroy(ppst_graph* g);
 typedef struct ppst_boot ppst_boot;   /* bootstrapping material, see below */
 /* CryptoInvSqrt configuration (Sec. 4, Alg. 2-3; Sec. 5.1, Eq. 3): Chebyshev
  * initial value of degree `degree` for 1/sqrt(B' v) on [a, b] (first-kind
- * interpolation), then `iters` Newton steps.  coeffs, when non-NULL, gives
+ * interpolation; degree 0..511), then `iters` Newton steps (0..32; EDOMAIN
+ * outside these ranges).  coeffs, when non-NULL, gives
  * c_0..c_degree of 1/sqrt(v) on [a, b] (B' = 1), divided by sqrt(B') per call.
  * sign_k: number of g_3 compositions of the sign in CV (Sec. 6.2).
  * boot, when non-NULL (a bootstrappable context's ppst_boot, its keys in the
@@ -391,8 +392,11 @@ typedef struct ppst_boot ppst_boot;   /* bootstrapping material, see below */
  * bootstraps it): the argument when it lacks the levels of the initial
  * value's polynomial, the initial value itself, w = (B'/2) v or y before a
  * Newton step that lacks its two levels, and the result when the statistic
- * needs more levels after it than remain.  The statistics then need only
- * their own levels around InvSqrt; CV refuses it (EINVAL). */
+ * needs more levels after it than remain; CV also refreshes its sign
+ * before a g_3 step it lacks the levels for.  The statistics then need only
+ * their own levels around InvSqrt.
+ * degree 0: the initial value is the constant c_0 (with coeffs = {1}, the
+ * y_0 = 1 of HEaaN-STAT's Newton iteration, the paper's Tab. 2 baseline). */
 typedef struct {
   double a, b;
   int32_t degree, iters, sign_k;

@@ -253,6 +253,8 @@ class Circuits:
         T_k sits ceil(log2 k) levels below t), then c_1..c_d combined at one
         level below the lowest T_k with one rescale, and c_0 added."""
         ev = self.ev
+        if d == 0:      # a constant initial value: 0 t + c_0 (t's level)
+            return ev.add_const(ev.mul_int(t, 0), float(coeffs[0]))
         T = {1: t}
         for k in range(2, d + 1):
             if k % 2 == 0:
@@ -282,12 +284,12 @@ class Circuits:
         # x - 1 on [0, 2]) needs no product and no level
         g = 2.0 / (b - a)
         if cfg.boot:
-            ladder = (d - 1).bit_length()          # ceil(log2 d)
-            if ev.level(v) < (0 if g == 1.0 else 1) + ladder + 1:
+            ladder = (d - 1).bit_length() if d >= 1 else 0      # ceil(log2 d)
+            if ev.level(v) < (0 if g == 1.0 else 1) + (ladder + 1 if d >= 1 else 0):
                 v = ev.refresh(v)
         t = ev.add_const(v if g == 1.0 else ev.mul_const(v, g), -(a + b) / (b - a))
         y = self.cheb_series(t, coeffs, d)
-        if cfg.boot:
+        if cfg.boot and d >= 1:
             y = ev.refresh(y)
         w2 = ev.mul_const(v, Bp / 2.0)
         for _ in range(cfg.iters):
@@ -310,9 +312,9 @@ class Circuits:
         y ~ 1/sqrt(x).  One output per input ciphertext."""
         return [self.inv_sqrt(self.ev.mul_const(x, 1.0 / B), B, cfg)[0] for x in X]
 
-    def sqrt(self, v, Bp, cfg: InvSqrtCfg):
+    def sqrt(self, v, Bp, cfg: InvSqrtCfg, reserve: int = 0):
         """sqrt(Bp v) = 2 * w2 * InvSqrt(v; Bp)."""
-        y, w2 = self.inv_sqrt(v, Bp, cfg)
+        y, w2 = self.inv_sqrt(v, Bp, cfg, reserve)
         return self.ev.mul_int(self.mulx(w2, y), 2)
 
     def g3(self, x):
@@ -386,15 +388,22 @@ class Circuits:
         return self.mulx(self.mulx(num, i), i2)
 
     def cv(self, X, n, B_mean, B_var, cfg: InvSqrtCfg, sign_k=2):
-        """Alg. 6: Std * InvSqrt(mu * sign(mu); B_mean)^2 * sign(mu)."""
-        if cfg.boot:
-            raise ValueError("CV runs without bootstrapping")
+        """Alg. 6: Std * InvSqrt(mu * sign(mu); B_mean)^2 * sign(mu).  With
+        cfg.boot the sign is refreshed before a g_3 step (depth 3) it lacks
+        the levels for and after the last step when below 3 levels; the
+        inverse mean and the standard deviation keep 3 levels."""
         ev = self.ev
         muB, var = self.moments_B(X, n, B_mean, B_var)
-        sg = self.sign(muB, sign_k)
-        ia, _ = self.inv_sqrt(self.mulx(muB, sg), B_mean, cfg)
+        sg = muB
+        for _ in range(sign_k):
+            if cfg.boot and ev.level(sg) < 3:
+                sg = ev.refresh(sg)
+            sg = self.g3(sg)
+        if cfg.boot and ev.level(sg) < 3:
+            sg = ev.refresh(sg)
+        ia, _ = self.inv_sqrt(self.mulx(muB, sg), B_mean, cfg, 3)
         mu_inv = ev.mul(ia, ia)
-        sigma = self.sqrt(var, B_var * B_var, cfg)
+        sigma = self.sqrt(var, B_var * B_var, cfg, 3)
         return self.mulx(self.mulx(sigma, mu_inv), sg)
 
     def pearson(self, X, Y, n, Bx, By, cfg: InvSqrtCfg):

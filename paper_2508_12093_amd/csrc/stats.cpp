@@ -241,8 +241,8 @@ struct Circ {
     return inv_sqrt_n({v}, {Bp}, cfg, reserve)[0];
   }
 
-  CtPtr sqrt_(const CtPtr& v, double Bp, const InvSqrtCfg& cfg) {
-    auto yw = inv_sqrt(v, Bp, cfg);
+  CtPtr sqrt_(const CtPtr& v, double Bp, const InvSqrtCfg& cfg, int reserve = 0) {
+    auto yw = inv_sqrt(v, Bp, cfg, reserve);
     return mul_int(cx, *mulx(yw.second, yw.first), 2);
   }
 
@@ -296,6 +296,11 @@ struct Circ {
   std::vector<CtPtr> cheb_series_n(const std::vector<CtPtr>& ts,
                                    const std::vector<std::vector<double>>& c, int d) {
     const size_t nl = ts.size();
+    if (d == 0) {   // a constant initial value: 0 t + c_0 (t's level, no product)
+      std::vector<CtPtr> y(nl);
+      for (size_t l = 0; l < nl; ++l) y[l] = add_const(cx, *mul_int(cx, *ts[l], 0), c[l][0]);
+      return y;
+    }
     std::vector<std::vector<CtPtr>> T(nl, std::vector<CtPtr>(d + 1));
     for (size_t l = 0; l < nl; ++l) T[l][1] = ts[l];
     std::vector<LevelCache> t1(nl, LevelCache{this});
@@ -337,7 +342,7 @@ struct Circ {
       // the weighted sum must fit above level 0
       int ladder = 0;
       while ((1 << ladder) < d) ++ladder;
-      const int need = (2.0 / (b - a) == 1.0 ? 0 : 1) + ladder + 1;
+      const int need = (2.0 / (b - a) == 1.0 ? 0 : 1) + (d >= 1 ? ladder + 1 : 0);
       for (size_t l = 0; l < nl; ++l)
         if (vs[l]->level < need) vs[l] = refresh(vs[l], *bt);
     }
@@ -349,7 +354,7 @@ struct Circ {
       ts[l] = affine(vs[l], a, b);
     }
     std::vector<CtPtr> y = cheb_series_n(ts, c, d), w2(nl);
-    if (bt)   // Alg. 3: the initial value is bootstrapped
+    if (bt && d >= 1)   // Alg. 3: the Chebyshev initial value is bootstrapped
       for (size_t l = 0; l < nl; ++l) y[l] = refresh(y[l], *bt);
     for (size_t l = 0; l < nl; ++l) w2[l] = mc(vs[l], Bps[l] / 2.0);
     for (int it = 0; it < cfg.iters; ++it) {
@@ -395,9 +400,9 @@ void check_column(const Params& P, const std::vector<CtPtr>& X, size_t nrows) {
 
 void check_cfg(const InvSqrtCfg& cfg) {
   if (!(cfg.a >= 0.0) || !(cfg.b > cfg.a)) PPST_THROW(ST_EDOMAIN, "InvSqrt interval needs 0 <= a < b");
-  if (cfg.degree < 1 || cfg.degree > kMaxChebDegree)
+  if (cfg.degree < 0 || cfg.degree > kMaxChebDegree)
     PPST_THROW(ST_EDOMAIN, "Chebyshev degree out of range");
-  if (cfg.iters < 0 || cfg.iters > 16) PPST_THROW(ST_EDOMAIN, "Newton iteration count out of range");
+  if (cfg.iters < 0 || cfg.iters > 32) PPST_THROW(ST_EDOMAIN, "Newton iteration count out of range");
 }
 
 // levels consumed by InvSqrt: affine map, ladder, coefficient products, Newton
@@ -405,7 +410,7 @@ int invsqrt_depth(const InvSqrtCfg& cfg) {
   int ladder = 0;
   while ((1 << ladder) < cfg.degree + 1) ++ladder;
   const int affine = 2.0 / (cfg.b - cfg.a) == 1.0 ? 0 : 1;
-  return affine + ladder + 1 + 2 * cfg.iters;
+  return affine + (cfg.degree >= 1 ? ladder + 1 : 0) + 2 * cfg.iters;
 }
 
 }  // namespace
@@ -525,16 +530,24 @@ CtPtr stat_cv(Context& cx, const EvalKeys& evk, const std::vector<CtPtr>& X, siz
   check_column(cx.P(), X, n);
   check_cfg(cfg);
   if (sign_k < 0 || sign_k > 8) PPST_THROW(ST_EDOMAIN, "sign composition count out of range");
-  if (cfg.boot) PPST_THROW(ST_EINVAL, "CV runs without bootstrapping (its sign polynomial is not refreshed)");
   Circ c{cx, evk};
-  c.check_depth(X, 2 + 3 * sign_k + 1 + invsqrt_depth(cfg) + 3);
+  const Bootstrapper* bt = cfg.boot;
+  c.check_depth(X, bt ? 2 : 2 + 3 * sign_k + 1 + invsqrt_depth(cfg) + 3);
   auto mv = c.moments(X, n, B_mean, B_var);
   auto muB = mv.first;
   CtPtr sg = muB;
-  for (int k = 0; k < sign_k; ++k) sg = c.g3(sg);
-  auto ia = c.inv_sqrt(c.mulx(muB, sg), B_mean, cfg).first;
+  // with a bootstrapper: the sign is refreshed before a g_3 step (depth 3)
+  // that it lacks the levels for, and after the last one when it has fewer
+  // than 3 (the product with mu and the final product); the inverse mean
+  // and the standard deviation keep the 3 levels their products need
+  for (int k = 0; k < sign_k; ++k) {
+    if (bt && sg->level < 3) sg = c.refresh(sg, *bt);
+    sg = c.g3(sg);
+  }
+  if (bt && sg->level < 3) sg = c.refresh(sg, *bt);
+  auto ia = c.inv_sqrt(c.mulx(muB, sg), B_mean, cfg, 3).first;
   auto mu_inv = c.sq(ia);
-  auto sigma = c.sqrt_(mv.second, B_var * B_var, cfg);
+  auto sigma = c.sqrt_(mv.second, B_var * B_var, cfg, 3);
   return c.mulx(c.mulx(sigma, mu_inv), sg);
 }
 

@@ -193,11 +193,39 @@ def test_b1_statistics_with_refreshes_bit_exact(bstat):
     orr = p.circ.pearson(OX, OY, n, 20.0, 20.0, ocfg)
     p.same(r, orr)
     assert abs(p.decrypt(r)[0] / stats64.pearson(x, y) - 1) < 1e-4
-    # CV has no refreshing form
-    with pytest.raises(ffi.PpstError) as e:
-        ffi.ppst_stat_cv(p.ctx, p.evk, X, n, 16.0, 20.0, cfg)
-    assert e.value.name == "EINVAL"
-    del e
+
+
+def test_b1_cv_and_comparator_with_refreshes_bit_exact(bstat):
+    """CV at Exp. 2's B = 20 with a three-fold g_3 sign (mu / B = 0.5) and
+    the paper's InvSqrt, its sign refreshed between compositions; and the
+    HEaaN-STAT comparator of Exp. 1 (y_0 = 1, a degree-0 initial value, 21
+    Newton steps on x / 100).  Bit-exact with the oracle; CV within 1e-4 of
+    FP64, the comparator's MRE below 1e-6 on a 2048-point Exp. 1 grid."""
+    p = bstat
+    n = 3000
+    x, _ = exp2_columns(70, n)
+    X, OX = [], []
+    for k in range(0, n, p.P.slots):
+        c, o = p.encrypt(x[k:k + p.P.slots], 1000 + k, level=p.P.Lc)
+        X.append(c)
+        OX.append(o)
+    cfg = ffi.ppst_invsqrt_cfg_default(coeffs=EXP1_COEFFS, a=0.0, b=2.0, degree=31, iters=6,
+                                       sign_k=3, boot=p.bt)
+    ocfg = C.InvSqrtCfg(a=0.0, b=2.0, degree=31, iters=6, coeffs=EXP1_COEFFS, boot=True)
+    print("b1 CV with refreshes", flush=True)
+    r = ffi.ppst_stat_cv(p.ctx, p.evk, X, n, 20.0, 20.0, cfg)
+    p.same(r, p.circ.cv(OX, n, 20.0, 20.0, ocfg, sign_k=3))
+    assert abs(p.decrypt(r)[0] / stats64.cv(x) - 1) < 1e-4
+    print("b1 HEaaN-STAT comparator", flush=True)
+    g = np.concatenate([np.linspace(0.001, 1.0, 1024), np.linspace(1.0, 100.0, 1024)])
+    cg, og = p.encrypt(g, 1100, level=p.P.Lc)
+    hcfg = ffi.ppst_invsqrt_cfg_default(coeffs=np.array([1.0]), a=0.0, b=2.0, degree=0, iters=21,
+                                        boot=p.bt)
+    y = ffi.ppst_stat_invsqrt(p.ctx, p.evk, [cg], 100.0, hcfg)[0]
+    oy = p.circ.invsqrt([og], 100.0, C.InvSqrtCfg(a=0.0, b=2.0, degree=0, iters=21,
+                                                   coeffs=np.array([1.0]), boot=True))[0]
+    p.same(y, oy)
+    assert np.mean(np.abs(p.decrypt(y) * np.sqrt(g) - 1.0)) < 1e-6
 
 
 def test_b2_bootstrap_refreshes():
