@@ -41,16 +41,18 @@ BFLY_PEAK_G = VALU_PEAK / OPS_PER_BFLY / 1e9
 # plain copy of known size.  The figure belongs to the NTT source it was taken
 # with (its SHA-256 below); for any other source the traffic is reported as
 # null.
-NTT_TRAFFIC = {"bytes": 79871872,
-               "source_sha256": "125cdbd2da275fad871489166c72fc30d2ce2ca4abaf98ed85b3e415ab02d652"}
+NTT_TRAFFIC = {"bytes": 79874562,
+               "source_sha256": "e375c16f2dd1c5dbbe3fe236b2fd1d1695b6c8658f098045a6f3d2ff76c2cf78"}
 # Algorithmic HBM bytes of the other key-switching kernels of one plain
 # product at level 24 (N = 2^16, K = 7, dnum = 3; a limb is 512 KiB): the key
 # inner product reads 3 digit limbs and 6 key limbs per extended limb (32)
-# and writes 2 (352 limbs); ModUp reads d2's 25 limbs and writes the 71
+# and writes 2 (352 limbs), alone or fused with the row pass of the digits'
+# forward NTT (the pass's own input is the same 3 digit limbs); ModUp reads d2's 25 limbs and writes the 71
 # extension limbs; the ModDown correction reads 2 x 8 limbs and writes
 # 2 x 24; the tensor reads 4 x 25 and writes 3 x 25.
 LIMB = 1 << 19
-KS_KERNELS = {"k_ks_inner_kernel<1>": ("hbm", 352 * LIMB), "k_modup_kernel<9>": ("alu", 96 * LIMB),
+KS_KERNELS = {"k_ks_inner_kernel<1>": ("hbm", 352 * LIMB), "k_ntt_row_ks<8, 2, 4>": ("hbm", 352 * LIMB),
+              "k_modup_kernel<9>": ("alu", 96 * LIMB),
               "k_mdr_corr_kernel<8>": ("alu", 64 * LIMB), "k_tensor_kernel": ("hbm", 175 * LIMB)}
 
 
