@@ -250,6 +250,12 @@ struct Tables {
   Buf mods;        // Mod[nprimes]
   Buf fwd;         // [nprimes][N][2] (w, w') with w = psi^brv(k)
   Buf inv;         // [nprimes][N][2] (w, w') with w = psi^-brv(k)
+  // row passes of the two-pass transform (N = 2^16, rows of 2^8 points) form
+  // the entries they need from two small tables (ntt.hip, row_twiddles):
+  // rowf [nprimes][2^8][8] = entry (2^8 + r) 2^s as a double (FP64 primes),
+  // comm [nprimes][2^8][2] = (psi^(brv_s(j) N / 2^s), its quotient by q) at
+  // index 2^s + j; the _inv tables the same for psi^-1
+  Buf rowf_fwd, rowf_inv, comm_fwd, comm_inv;
   Buf ninv;        // [nprimes][2] (N^-1, Shoup)
   // ModUp constants per level: see modup_table()
   std::map<int, std::shared_ptr<Buf>> modup;

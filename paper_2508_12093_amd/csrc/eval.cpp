@@ -288,6 +288,53 @@ void build_tables(Shared& sh) {
   sh.tab.inv = upload(pool, inv);
   sh.tab.ninv = upload(pool, ninv);
 
+  // Row-pass factor tables of N = 2^16 (rows of M = 2^8 points, R = 2^8
+  // rows).  Entry (R + r) 2^s + j (j < 2^s) of the table is psi^e with
+  // e = brv((R + r) 2^s) + brv_s(j) N / 2^s (the two bit fields reverse
+  // separately), i.e. rowf[r][s] times comm[2^s + j]; every product is
+  // checked against the full table here.
+  if (P.logN == 16) {
+    constexpr int LM = 8, M = 1 << LM, R = 1 << LM;
+    std::vector<double> rf((size_t)np * R * LM, 0.0), ri((size_t)np * R * LM, 0.0);
+    std::vector<u64> cf((size_t)np * M * 2, 0), ci((size_t)np * M * 2, 0);
+    for (int p = 0; p < np; ++p) {
+      const u64 q = P.q[p];
+      if (q >= kFpPrimeBound) continue;       // only the FP64 path forms its entries
+      const u64 psi = P.psi[p], ipsi = h_invmod(psi, q);
+      auto tab_w = [&](const std::vector<u64>& t, size_t m) {
+        double d;
+        std::memcpy(&d, &t[((size_t)p * N + m) * 2], 8);
+        return (u64)d;
+      };
+      for (int dir = 0; dir < 2; ++dir) {
+        const std::vector<u64>& full = dir ? inv : fwd;
+        std::vector<double>& rowf = dir ? ri : rf;
+        std::vector<u64>& comm = dir ? ci : cf;
+        const u64 root = dir ? ipsi : psi;
+        std::vector<u64> cw(M, 1);
+        for (int s = 0; s < LM; ++s) {
+          const u64 b = h_powmod(root, (u64)N >> s, q);   // a primitive 2^(s+1)-th root
+          for (int j = 0; j < (1 << s); ++j) {
+            cw[(1 << s) + j] = h_powmod(b, brv((unsigned)j, s), q);
+            pair(cw[(1 << s) + j], q, &comm[((size_t)p * M + (1 << s) + j) * 2]);
+          }
+        }
+        for (int r = 0; r < R; ++r)
+          for (int s = 0; s < LM; ++s) {
+            const u64 f = tab_w(full, (size_t)(R + r) << s);
+            rowf[((size_t)p * R + r) * LM + s] = (double)f;
+            for (int j = 0; j < (1 << s); ++j)
+              if (h_mulmod(f, cw[(1 << s) + j], q) != tab_w(full, ((size_t)(R + r) << s) + j))
+                PPST_THROW(ST_EINVAL, "row twiddle factorisation does not reproduce the table");
+          }
+      }
+    }
+    sh.tab.rowf_fwd = upload(pool, std::vector<u64>((const u64*)rf.data(), (const u64*)rf.data() + rf.size()));
+    sh.tab.rowf_inv = upload(pool, std::vector<u64>((const u64*)ri.data(), (const u64*)ri.data() + ri.size()));
+    sh.tab.comm_fwd = upload(pool, cf);
+    sh.tab.comm_inv = upload(pool, ci);
+  }
+
   // ModDown
   const int L = P.L, K = P.K;
   MdLayout lay(K, L);

@@ -33,6 +33,8 @@ struct NttArgs {
   const Mod* mods;
   const u64* tw;     // [nprimes][N][2]
   const u64* ninv;   // [nprimes][2]
+  const double* rowf;  // row-pass factor tables of N = 2^16 (row_twiddles), or null
+  const u64* comm;
   size_t batch_stride, dst_stride;
   int N, logN, logR, nq, pofs, skip_lo, skip_hi, blocks_per_limb;
   int dalpha, dcount, dtotal;
@@ -124,6 +126,10 @@ struct FpArith {
   __device__ __forceinline__ T in(u64 v) const { return (double)v; }
   __device__ __forceinline__ T in_mid(u64 v) const { return __longlong_as_double((long long)v); }
   __device__ __forceinline__ u64 mid(T v) const { return (u64)__double_as_longlong(v); }
+  // a formed twiddle w as a table entry (w, w/q)
+  __device__ __forceinline__ ulonglong2 pair(double w) const {
+    return make_ulonglong2((u64)__double_as_longlong(w), (u64)__double_as_longlong(w * qinv));
+  }
   // v - q rint(v / q): exact (an integer of magnitude below q), |.| <= q/2 + 1
   __device__ __forceinline__ void centre(T& v) const { v = __fma_rn(-rint(v * qinv), q, v); }
   // the canonical residue of v
@@ -151,6 +157,55 @@ struct FpArith {
   }
 };
 
+// Row twiddles formed in LDS.  Sub-problem r of a row pass (N = R M with
+// R = M = 2^8) reads table entry (R + r) 2^s + j at its local stage s
+// (j < 2^s); bit reversal maps the two fields separately, so that entry is
+// rowf[r][s] * comm[2^s + j]: a factor per (row, stage) and one shared by
+// every row.  A workgroup of SB rows forms its SB (M - 1) entries with one
+// exact FP64 product each (FpArith::mulmod, |w| <= 0.51 q, signed) instead
+// of reading them from the N-entry table (1 MiB per prime, a third of the
+// pass's traffic); the butterflies read w there and form w * (1/q).  The butterfly bound of FpArith holds for such w: the
+// quotient estimate y * w/q then carries three roundings, at most
+// 3 * 2^-53 * 0.51 * 2^47.4 < 0.032 off for |y| < 2^47.4, so
+// |y w - k q| <= 0.532 q < 0.55 q.
+// Only FP64 primes use it; lds null: the table in memory.
+constexpr int kRowTwLogM = 8;
+struct RowTw {
+  double* lds;            // [SB][M] entries w of the workgroup's rows, or null
+  const double* rowf;     // the prime's [R][LOGM] row factors
+  const ulonglong2* comm; // the prime's [M] shared factors (w, w/q)
+  bool make;              // form them first (false: an earlier body did)
+};
+
+// whether a row kernel of this shape forms its twiddles (bounded LDS)
+template <int LOGM, int SB, bool ROWS>
+struct RowTwShape {
+  static constexpr bool on = ROWS && LOGM == kRowTwLogM && SB <= 8;
+  static constexpr int size = on ? SB << LOGM : 1;   // doubles
+};
+
+// every thread forms SB M / NT entries, their loads issued together (entry
+// 0 of a row, never read, comes out 0 from comm's zero entry)
+template <int LOGM, int SB, int NT>
+__device__ __forceinline__ void row_twiddles(const FpArith& ar, const RowTw& rt, int first) {
+  constexpr int M = 1 << LOGM;
+  constexpr int PER = SB * M / NT;
+  static_assert(PER * NT == SB * M, "workgroup shape");
+  double f[PER];
+  ulonglong2 c[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int idx = (int)threadIdx.x + k * NT;
+    const int r = idx >> LOGM, i = idx & (M - 1);
+    const int s = i ? 31 - __clz(i) : 0;
+    f[k] = rt.rowf[(first + r) * LOGM + s];
+    c[k] = rt.comm[i];
+  }
+#pragma unroll
+  for (int k = 0; k < PER; ++k)
+    rt.lds[(int)threadIdx.x + k * NT] =
+        ar.mulmod(f[k], __longlong_as_double((long long)c[k].x), __longlong_as_double((long long)c[k].y));
+}
 
 // One pass of LOGM stages over SB independent sub-problems of M = 2^LOGM
 // points.  ROWS: sub-problem r = row (contiguous), twiddle base R + r;
@@ -162,11 +217,11 @@ struct FpArith {
 // stages the sub-problem splits into M / 2^ls independent groups of 2^ls
 // elements; each of the T = M / E threads owns E / 2^ls groups (E registers)
 // and exchanges them through LDS between passes.
-template <class A, int LOGM, int LOGE, int SB, bool ROWS, bool INV>
+template <class A, int LOGM, int LOGE, int SB, bool ROWS, bool INV, bool TL = false>
 __device__ __forceinline__ void ntt_body(const A ar, typename A::T* lds, const u64* src, u64* dst,
                                          const ulonglong2* tw, const u64* ninv2, int N, int logR,
                                          int first, bool firstp, bool last, uint32_t galois,
-                                         int logN) {
+                                         int logN, const RowTw rt = RowTw{}) {
   typedef typename A::T T;
   constexpr int M = 1 << LOGM;
   constexpr int E = 1 << LOGE;
@@ -199,6 +254,9 @@ __device__ __forceinline__ void ntt_body(const A ar, typename A::T* lds, const u
       const u64 v = src[(size_t)e * C + first + sp];
       lds[sp * PAD + e] = firstp ? ar.in(v) : ar.in_mid(v);
     }
+  }
+  if constexpr (TL) {
+    if (rt.make) row_twiddles<LOGM, SB, NT>(ar, rt, first);
   }
   __syncthreads();
 
@@ -241,8 +299,10 @@ __device__ __forceinline__ void ntt_body(const A ar, typename A::T* lds, const u
         for (int k = 0; k < GS; ++k) {
           if (k & half) continue;
           const int e = e0[g] + k * si;
-          const uint32_t idx = (base0 << s) + (uint32_t)(e >> (LOGM - s));
-          const ulonglong2 w = tw[idx];
+          const uint32_t j = (uint32_t)(e >> (LOGM - s));
+          ulonglong2 w;
+          if constexpr (TL) w = ar.pair(rt.lds[((uint32_t)sp << LOGM) + (1u << s) + j]);
+          else w = tw[(base0 << s) + j];
           if (INV) ar.gs(x[g * GS + k], x[g * GS + k + half], w);
           else ar.ct(x[g * GS + k], x[g * GS + k + half], w);
         }
@@ -290,11 +350,13 @@ struct PlainStore {
   __device__ __forceinline__ void put(int, size_t at, u64 v) const { dst[at] = v; }
 };
 
-template <class A, int LOGM, int LOGE, int SB, bool ROWS, bool INV, class Store = PlainStore>
+template <class A, int LOGM, int LOGE, int SB, bool ROWS, bool INV, bool TL = false,
+          class Store = PlainStore>
 __device__ __forceinline__ void ntt_body_dio(const A ar, typename A::T* lds, const u64* src,
                                              Store& store, const ulonglong2* tw,
                                              const u64* ninv2, int N, int logR, int first,
-                                             bool firstp, bool last, uint32_t galois, int logN) {
+                                             bool firstp, bool last, uint32_t galois, int logN,
+                                             const RowTw rt = RowTw{}) {
   typedef typename A::T T;
   constexpr int M = 1 << LOGM;
   constexpr int E = 1 << LOGE;
@@ -338,6 +400,13 @@ __device__ __forceinline__ void ntt_body_dio(const A ar, typename A::T* lds, con
           if (ROWS && INV && galois != 0) at = galois_src((uint32_t)at, galois, logN);
           x[g * GS + k] = firstp ? ar.in(src[at]) : ar.in_mid(src[at]);
         }
+      // the row twiddles form while the loads are in flight
+      if constexpr (TL) {
+        if (rt.make) {
+          row_twiddles<LOGM, SB, SB * TPS>(ar, rt, first);
+          __syncthreads();
+        }
+      }
     } else {
 #pragma unroll
       for (int g = 0; g < G; ++g)
@@ -369,8 +438,10 @@ __device__ __forceinline__ void ntt_body_dio(const A ar, typename A::T* lds, con
         for (int k = 0; k < GS; ++k) {
           if (k & half) continue;
           const int e = e0[g] + k * si;
-          const uint32_t idx = (base0 << s) + (uint32_t)(e >> (LOGM - s));
-          const ulonglong2 w = tw[idx];
+          const uint32_t j = (uint32_t)(e >> (LOGM - s));
+          ulonglong2 w;
+          if constexpr (TL) w = ar.pair(rt.lds[((uint32_t)sp << LOGM) + (1u << s) + j]);
+          else w = tw[(base0 << s) + j];
           if (INV) ar.gs(x[g * GS + k], x[g * GS + k + half], w);
           else ar.ct(x[g * GS + k], x[g * GS + k + half], w);
         }
@@ -407,8 +478,22 @@ __device__ __forceinline__ BlockPos tile_pos(unsigned b, int blocks_per_limb, in
 }
 
 // One tile of a pass: SB sub-problems of one limb of one batch item.
+// the RowTw of a row pass on `prime` (lds null where the table is read)
+template <int LOGM, int SB, bool ROWS>
+__device__ __forceinline__ RowTw row_tw(const NttArgs& a, double* twl, int prime, u64 q) {
+  RowTw rt{};
+  if (RowTwShape<LOGM, SB, ROWS>::on && a.rowf != nullptr && q < kFpPrimeBound && a.logR == kRowTwLogM) {
+    rt.lds = twl;
+    rt.rowf = a.rowf + (size_t)prime * ((size_t)kRowTwLogM << a.logR);
+    rt.comm = (const ulonglong2*)(a.comm + (size_t)prime * (2u << LOGM));
+    rt.make = true;
+  }
+  return rt;
+}
+
 template <int LOGM, int LOGE, int SB, bool ROWS, bool INV, bool DIO>
-__device__ __forceinline__ void ntt_tile(const NttArgs& a, u64* lds, const BlockPos bp) {
+__device__ __forceinline__ void ntt_tile(const NttArgs& a, u64* lds, double* twl,
+                                         const BlockPos bp) {
   const int N = a.N;
   const int limb_u = bp.limb;
   const int grp = bp.grp;
@@ -428,9 +513,15 @@ __device__ __forceinline__ void ntt_tile(const NttArgs& a, u64* lds, const Block
   const bool last = INV ? (!ROWS || a.logR == 0) : ROWS;
   const bool firstp = INV ? ROWS : (!ROWS || a.logR == 0);   // reads the transform's input
   const int first = grp * SB;        // first sub-problem of this workgroup
+  constexpr bool TLS = RowTwShape<LOGM, SB, ROWS>::on;
+  const RowTw rt = row_tw<LOGM, SB, ROWS>(a, twl, prime, q);
   if (DIO) {
     PlainStore store{dst};
-    if (q < kFpPrimeBound)
+    if (rt.lds)
+      ntt_body_dio<FpArith, LOGM, LOGE, SB, ROWS, INV, TLS>(FpArith(q), (double*)lds, src, store, tw,
+                                                             ni, N, a.logR, first, firstp, last,
+                                                             a.galois, a.logN, rt);
+    else if (q < kFpPrimeBound)
       ntt_body_dio<FpArith, LOGM, LOGE, SB, ROWS, INV>(FpArith(q), (double*)lds, src, store, tw,
                                                         ni, N, a.logR, first, firstp, last, a.galois,
                                                         a.logN);
@@ -438,7 +529,11 @@ __device__ __forceinline__ void ntt_tile(const NttArgs& a, u64* lds, const Block
       ntt_body_dio<IntArith, LOGM, LOGE, SB, ROWS, INV>(IntArith(q), lds, src, store, tw, ni, N,
                                                          a.logR, first, firstp, last, a.galois, a.logN);
   } else {
-    if (q < kFpPrimeBound)
+    if (rt.lds)
+      ntt_body<FpArith, LOGM, LOGE, SB, ROWS, INV, TLS>(FpArith(q), (double*)lds, src, dst, tw, ni, N,
+                                                         a.logR, first, firstp, last, a.galois,
+                                                         a.logN, rt);
+    else if (q < kFpPrimeBound)
       ntt_body<FpArith, LOGM, LOGE, SB, ROWS, INV>(FpArith(q), (double*)lds, src, dst, tw, ni, N,
                                                     a.logR, first, firstp, last, a.galois, a.logN);
     else
@@ -451,7 +546,8 @@ template <int LOGM, int LOGE, int SB, bool ROWS, bool INV, bool DIO>
 __global__ void __launch_bounds__(SB * (1 << (LOGM - LOGE)))
 k_ntt_pass(NttArgs a) {
   __shared__ u64 lds[SB * ((1 << LOGM) + 1)];
-  ntt_tile<LOGM, LOGE, SB, ROWS, INV, DIO>(a, lds, block_pos(a.blocks_per_limb, a.nbatch));
+  __shared__ double twl[RowTwShape<LOGM, SB, ROWS>::size];
+  ntt_tile<LOGM, LOGE, SB, ROWS, INV, DIO>(a, lds, twl, block_pos(a.blocks_per_limb, a.nbatch));
 }
 
 // Persistent form: a grid sized to what the device holds at once walks the
@@ -461,8 +557,9 @@ template <int LOGM, int LOGE, int SB, bool ROWS, bool INV, bool DIO>
 __global__ void __launch_bounds__(SB * (1 << (LOGM - LOGE)))
 k_ntt_pass_persistent(NttArgs a, unsigned ntiles) {
   __shared__ u64 lds[SB * ((1 << LOGM) + 1)];
+  __shared__ double twl[RowTwShape<LOGM, SB, ROWS>::size];
   for (unsigned b = blockIdx.x; b < ntiles; b += gridDim.x) {
-    ntt_tile<LOGM, LOGE, SB, ROWS, INV, DIO>(a, lds, tile_pos(b, a.blocks_per_limb, a.nbatch));
+    ntt_tile<LOGM, LOGE, SB, ROWS, INV, DIO>(a, lds, twl, tile_pos(b, a.blocks_per_limb, a.nbatch));
     __syncthreads();
   }
 }
@@ -506,6 +603,7 @@ __global__ void __launch_bounds__(SB * (1 << (LOGM - LOGE)))
 k_ntt_row_mdr(NttArgs a, MdrEpi e) {
   constexpr int M = 1 << LOGM;
   __shared__ u64 lds[SB * (M + 1)];
+  __shared__ double twl[RowTwShape<LOGM, SB, true>::size];
   const int N = a.N;
   const BlockPos bp = block_pos(a.blocks_per_limb, a.nbatch);
   const int t = bp.limb;                                 // limb = prime index, t < level
@@ -526,7 +624,12 @@ k_ntt_row_mdr(NttArgs a, MdrEpi e) {
   store.qlinv = e.rc[3 * t];
   store.qlinvs = e.rc[3 * t + 1];
   const int first = grp * SB;
-  if (q < kFpPrimeBound)
+  const RowTw rt = row_tw<LOGM, SB, true>(a, twl, t, q);
+  if (rt.lds)
+    ntt_body_dio<FpArith, LOGM, LOGE, SB, true, false, RowTwShape<LOGM, SB, true>::on>(
+        FpArith(q), (double*)lds, src, store, tw, ni, N, a.logR, first, a.logR == 0, true, 0u,
+        a.logN, rt);
+  else if (q < kFpPrimeBound)
     ntt_body_dio<FpArith, LOGM, LOGE, SB, true, false>(FpArith(q), (double*)lds, src, store, tw,
                                                         ni, N, a.logR, first, a.logR == 0, true, 0u, a.logN);
   else
@@ -589,6 +692,7 @@ __global__ void __launch_bounds__(SB * (1 << (LOGM - LOGE)))
 k_ntt_row_md(NttArgs a, MdEpi e) {
   constexpr int M = 1 << LOGM;
   __shared__ u64 lds[SB * (M + 1)];
+  __shared__ double twl[RowTwShape<LOGM, SB, true>::size];
   const int N = a.N;
   const BlockPos bp = block_pos(a.blocks_per_limb, a.nbatch);
   const int t = bp.limb;                                 // limb = prime index, t < nl
@@ -611,7 +715,12 @@ k_ntt_row_md(NttArgs a, MdEpi e) {
   store.gadd = e.gadd;
   store.logN = e.logN;
   const int first = grp * SB;
-  if (q < kFpPrimeBound)
+  const RowTw rt = row_tw<LOGM, SB, true>(a, twl, t, q);
+  if (rt.lds)
+    ntt_body_dio<FpArith, LOGM, LOGE, SB, true, false, RowTwShape<LOGM, SB, true>::on>(
+        FpArith(q), (double*)lds, src, store, tw, ni, N, a.logR, first, a.logR == 0, true, 0u,
+        a.logN, rt);
+  else if (q < kFpPrimeBound)
     ntt_body_dio<FpArith, LOGM, LOGE, SB, true, false>(FpArith(q), (double*)lds, src, store, tw,
                                                         ni, N, a.logR, first, a.logR == 0, true, 0u, a.logN);
   else
@@ -673,9 +782,10 @@ struct KsAccStore {
   }
 };
 
-template <class A, int LOGM, int LOGE, int SB>
+template <class A, int LOGM, int LOGE, int SB, bool TL = false>
 __device__ __forceinline__ void ks_tile(const A ar, u64* lds, const NttArgs& a, const KsEpi& e,
-                                        int t, int prime, int first, int item0, int item1) {
+                                        int t, int prime, int first, int item0, int item1,
+                                        RowTw rt = RowTw{}) {
   constexpr int M = 1 << LOGM;
   constexpr int E = 1 << LOGE;
   constexpr int TPS = M / E;
@@ -704,6 +814,13 @@ __device__ __forceinline__ void ks_tile(const A ar, u64* lds, const NttArgs& a, 
   const u64* ni = a.ninv + 2 * prime;
   const Mod m = a.mods[prime];
   const bool prep = e.pd != nullptr && t == e.nl - 1;
+  // the rows' twiddles serve every digit and item: formed once, up front,
+  // where few registers are live
+  if constexpr (TL) {
+    row_twiddles<LOGM, SB, SB * TPS>(ar, rt, first);
+    rt.make = false;
+    __syncthreads();
+  }
   for (int item = item0; item < item1; ++item) {
     KsAccStore<E> st;
     // one copy of the transform serves every digit (the key rows of later
@@ -721,8 +838,9 @@ __device__ __forceinline__ void ks_tile(const A ar, u64* lds, const NttArgs& a, 
         }
       } else {
         const u64* src = e.ext + (size_t)item * e.sext + ((size_t)j * e.ne + t) * NN;
-        ntt_body_dio<A, LOGM, LOGE, SB, true, false>(ar, (typename A::T*)lds, src, st, tw, ni, N,
-                                                     a.logR, first, a.logR == 0, true, 0u, a.logN);
+        ntt_body_dio<A, LOGM, LOGE, SB, true, false, TL>(ar, (typename A::T*)lds, src, st, tw, ni, N,
+                                                         a.logR, first, a.logR == 0, true, 0u,
+                                                         a.logN, rt);
         __syncthreads();   // the next digit's exchanges reuse the LDS rows
       }
     }
@@ -750,6 +868,7 @@ __global__ void __launch_bounds__(SB * (1 << (LOGM - LOGE)), 3)
 k_ntt_row_ks(NttArgs a, KsEpi e) {
   constexpr int M = 1 << LOGM;
   __shared__ u64 lds[SB * (M + 1)];
+  __shared__ double twl[RowTwShape<LOGM, SB, true>::size];
   const int groups = (1 << a.logR) / SB;
   const int nig = (e.nbatch + e.items - 1) / e.items;
   const unsigned b = blockIdx.x;
@@ -759,7 +878,11 @@ k_ntt_row_ks(NttArgs a, KsEpi e) {
   const int prime = t < e.nl ? t : e.pofs + (t - e.nl);
   const int item0 = ig * e.items, item1 = min(item0 + e.items, e.nbatch);
   const u64 q = a.mods[prime].q;
-  if (q < kFpPrimeBound)
+  const RowTw rt = row_tw<LOGM, SB, true>(a, twl, prime, q);
+  if (rt.lds)
+    ks_tile<FpArith, LOGM, LOGE, SB, RowTwShape<LOGM, SB, true>::on>(FpArith(q), lds, a, e, t, prime,
+                                                                      rg * SB, item0, item1, rt);
+  else if (q < kFpPrimeBound)
     ks_tile<FpArith, LOGM, LOGE, SB>(FpArith(q), lds, a, e, t, prime, rg * SB, item0, item1);
   else
     ks_tile<IntArith, LOGM, LOGE, SB>(IntArith(q), lds, a, e, t, prime, rg * SB, item0, item1);
@@ -798,6 +921,7 @@ __global__ void __launch_bounds__(SB * (1 << (LOGM - LOGE)))
 k_ntt_row_rs(NttArgs a, RsEpi e) {
   constexpr int M = 1 << LOGM;
   __shared__ u64 lds[SB * (M + 1)];
+  __shared__ double twl[RowTwShape<LOGM, SB, true>::size];
   const int N = a.N;
   const BlockPos bp = block_pos(a.blocks_per_limb, a.nbatch);
   const int t = bp.limb;                                 // limb = prime index, t < l
@@ -817,7 +941,12 @@ k_ntt_row_rs(NttArgs a, RsEpi e) {
   store.k = e.k[t];
   store.kp = e.kp[t];
   const int first = grp * SB;
-  if (q < kFpPrimeBound)
+  const RowTw rt = row_tw<LOGM, SB, true>(a, twl, t, q);
+  if (rt.lds)
+    ntt_body_dio<FpArith, LOGM, LOGE, SB, true, false, RowTwShape<LOGM, SB, true>::on>(
+        FpArith(q), (double*)lds, src, store, tw, ni, N, a.logR, first, a.logR == 0, true, 0u,
+        a.logN, rt);
+  else if (q < kFpPrimeBound)
     ntt_body_dio<FpArith, LOGM, LOGE, SB, true, false>(FpArith(q), (double*)lds, src, store, tw,
                                                         ni, N, a.logR, first, a.logR == 0, true, 0u, a.logN);
   else
@@ -911,6 +1040,23 @@ constexpr int kNFull12 = sizeof(kFull12) / sizeof(kFull12[0]);
 
 }  // namespace
 
+// twiddle tables of one direction; PPST_NTT_ROW_TWIDDLES=0 makes the row
+// passes read every entry from the full table
+static bool row_twiddles_enabled() {
+  static const bool on = [] {
+    const char* e = std::getenv("PPST_NTT_ROW_TWIDDLES");
+    return !(e && e[0] == '0');
+  }();
+  return on;
+}
+
+static void set_tables(NttArgs& a, const Shared& sh, bool inverse) {
+  a.tw = inverse ? sh.tab.inv.p : sh.tab.fwd.p;
+  const bool rows = row_twiddles_enabled() && sh.P.logN == 16;
+  a.rowf = rows ? (const double*)(inverse ? sh.tab.rowf_inv.p : sh.tab.rowf_fwd.p) : nullptr;
+  a.comm = rows ? (inverse ? sh.tab.comm_inv.p : sh.tab.comm_fwd.p) : nullptr;
+}
+
 int ntt_bucket(int nlimbs_total) {
   if (nlimbs_total <= 4) return 0;
   if (nlimbs_total <= 16) return 1;
@@ -975,7 +1121,7 @@ void ntt(const Shared& sh, const NttLaunch& L, bool inverse, hipStream_t st) {
   }
   NttArgs a{};
   a.mods = (const Mod*)sh.tab.mods.p;
-  a.tw = inverse ? sh.tab.inv.p : sh.tab.fwd.p;
+  set_tables(a, sh, inverse);
   a.ninv = sh.tab.ninv.p;
   a.batch_stride = L.batch_stride;
   a.dst_stride = L.dst_stride == ~(size_t)0 ? L.batch_stride : L.dst_stride;
@@ -1019,7 +1165,7 @@ void ntt_fwd_mdr_final(const Shared& sh, u64* corr, int level, int nbatch, const
   const size_t N = P.N;
   NttArgs a{};
   a.mods = (const Mod*)sh.tab.mods.p;
-  a.tw = sh.tab.fwd.p;
+  set_tables(a, sh, false);
   a.ninv = sh.tab.ninv.p;
   a.N = P.N;
   a.logN = P.logN;
@@ -1096,7 +1242,7 @@ void ntt_fwd_ks_fused(const Shared& sh, const KsTail& tail, int level, int nbatc
   const size_t N = P.N;
   NttArgs a{};
   a.mods = (const Mod*)sh.tab.mods.p;
-  a.tw = sh.tab.fwd.p;
+  set_tables(a, sh, false);
   a.ninv = sh.tab.ninv.p;
   a.N = P.N;
   a.logN = P.logN;
@@ -1154,7 +1300,7 @@ void ntt_fwd_md_final(const Shared& sh, u64* conv, int level, int nbatch, const 
   const size_t N = P.N;
   NttArgs a{};
   a.mods = (const Mod*)sh.tab.mods.p;
-  a.tw = sh.tab.fwd.p;
+  set_tables(a, sh, false);
   a.ninv = sh.tab.ninv.p;
   a.N = P.N;
   a.logN = P.logN;
@@ -1226,7 +1372,7 @@ void ntt_fwd_rescale_final(const Shared& sh, u64* corr, int level, int npoly, co
   const size_t N = P.N;
   NttArgs a{};
   a.mods = (const Mod*)sh.tab.mods.p;
-  a.tw = sh.tab.fwd.p;
+  set_tables(a, sh, false);
   a.ninv = sh.tab.ninv.p;
   a.N = P.N;
   a.logN = P.logN;
@@ -1289,7 +1435,7 @@ void ntt_autotune(Shared& sh, hipStream_t st, u64* scratch, int max_limbs) {
     for (int inv = 0; inv < 2; ++inv) {
       NttArgs a{};
       a.mods = (const Mod*)sh.tab.mods.p;
-      a.tw = inv ? sh.tab.inv.p : sh.tab.fwd.p;
+      set_tables(a, sh, inv != 0);
       a.ninv = sh.tab.ninv.p;
       a.N = P.N;
       a.logN = P.logN;
