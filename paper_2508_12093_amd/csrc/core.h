@@ -133,7 +133,8 @@ void decode_coeffs(const Params& P, const long double* coeffs, double scale, dou
 // -------------------------------------------------------------------------
 struct Mod {
   u64 q;
-  u64 r_hi, r_lo;
+  u64 r_hi, r_lo;   // floor(2^128 / q)
+  u64 mneg;         // -q^-1 mod 2^64 (Montgomery reduction)
 };
 
 // -------------------------------------------------------------------------

@@ -83,6 +83,21 @@ struct Acc30 {
     const u64 hi = (a1 >> 34) + (a2 >> 4) + c;
     return reduce128(hi, lo, m);
   }
+  // the sum times 2^-64 mod q (Montgomery's REDC), for sums below q 2^64:
+  // at most 16 terms whose first factors are below 2^60 and whose second
+  // factors (constants stored as c 2^64 mod q) are below q.  With
+  // mm = lo (-q^-1) mod 2^64, x + mm q is a multiple of 2^64 whose low word
+  // carries exactly when lo != 0, and (x + mm q) / 2^64 < 2q.
+  __device__ __forceinline__ u64 redc(const Mod& m) const {
+    const u64 t1 = a1 << 30, t2 = a2 << 60;
+    u64 lo = a0 + t1;
+    u64 c = lo < t1;
+    lo += t2;
+    c += lo < t2;
+    const u64 hi = (a1 >> 34) + (a2 >> 4) + c;
+    const u64 mm = lo * m.mneg;
+    return csub(hi + mulhi(mm, m.q) + (lo != 0), m.q);
+  }
 };
 
 // x < 2^64 reduced mod q by one Barrett step (floor(2^64/q) = r_hi)

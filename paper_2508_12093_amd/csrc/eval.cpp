@@ -236,6 +236,10 @@ Buf upload(const std::shared_ptr<Pool>& pool, const std::vector<u64>& v) {
   return b;
 }
 
+// 2^64 mod q: a constant c stored as c 2^64 mod q comes out of Acc30::redc
+// as c itself
+u64 mont_r(u64 q) { return (u64)(((u128)1 << 64) % q); }
+
 unsigned brv(unsigned x, int bits) {
   unsigned r = 0;
   for (int i = 0; i < bits; ++i) r |= ((x >> i) & 1u) << (bits - 1 - i);
@@ -249,12 +253,18 @@ void build_tables(Shared& sh) {
   const Params& P = sh.P;
   const int N = P.N, np = P.nprimes;
   auto& pool = sh.const_pool;
-  std::vector<u64> mods(3 * np);
+  static_assert(sizeof(Mod) == 4 * sizeof(u64), "Mod layout");
+  std::vector<u64> mods(4 * np);
   for (int i = 0; i < np; ++i) {
-    u128 R = (~(u128)0) / P.q[i];
-    mods[3 * i] = P.q[i];
-    mods[3 * i + 1] = (u64)(R >> 64);
-    mods[3 * i + 2] = (u64)R;
+    const u64 q = P.q[i];
+    u128 R = (~(u128)0) / q;
+    u64 inv = q;                            // q^-1 mod 2^64 by Newton (q odd)
+    for (int k = 0; k < 6; ++k) inv *= 2 - q * inv;
+    if (q * inv != 1) PPST_THROW(ST_EINVAL, "Montgomery inverse");
+    mods[4 * i] = q;
+    mods[4 * i + 1] = (u64)(R >> 64);
+    mods[4 * i + 2] = (u64)R;
+    mods[4 * i + 3] = 0 - inv;
   }
   sh.tab.mods = upload(pool, mods);
 
@@ -351,7 +361,7 @@ void build_tables(Shared& sh) {
       u64 qi = P.q[i], v = 1;
       for (int k2 = 0; k2 < K; ++k2)
         if (k2 != k) v = h_mulmod(v, P.q[L + 1 + k2] % qi, qi);
-      md[lay.phat(k, i)] = v;
+      md[lay.phat(k, i)] = h_mulmod(v, mont_r(qi), qi);   // Montgomery form
     }
   }
   for (int i = 0; i <= L; ++i) {
@@ -396,7 +406,8 @@ void build_tables(Shared& sh) {
           u64 qt = P.q[p], v = 1;
           for (int i2 = lo; i2 < hi; ++i2)
             if (i2 != i) v = h_mulmod(v, P.q[i2] % qt, qt);
-          t[2 * kMaxAlpha + (size_t)tt * kMaxAlpha + (i - lo)] = v;
+          // Montgomery form: the kernel's sum comes out times 2^-64
+          t[2 * kMaxAlpha + (size_t)tt * kMaxAlpha + (i - lo)] = h_mulmod(v, mont_r(qt), qt);
         }
       }
     }

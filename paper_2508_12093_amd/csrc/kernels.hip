@@ -188,7 +188,7 @@ k_modup_kernel(const u64* __restrict__ xin, u64* __restrict__ extout,
       acc.mac(z[i], Split30(qhat[i]));
       if ((i & 7) == 7) acc.fold();
     }
-    ext[(size_t)t * N + k] = acc.reduce(mods[p]);
+    ext[(size_t)t * N + k] = acc.redc(mods[p]);   // the table is in Montgomery form
   }
 }
 
@@ -479,7 +479,7 @@ k_moddown_conv_kernel(const u64* __restrict__ uin, u64* __restrict__ convout,
     Acc30 acc;
 #pragma unroll
     for (int j = 0; j < MAXK; ++j) acc.mac(w[j], Split30(md[lay.phat(j, i)]));
-    u64 v = acc.reduce(m);
+    u64 v = acc.redc(m);   // Phat_k mod q_i is stored in Montgomery form
     conv[(size_t)i * N + k] = subm(v, md[lay.hmod(i)], m.q);
   }
 }
@@ -512,7 +512,7 @@ k_mdr_corr_kernel(const u64* __restrict__ u, u64* __restrict__ corr, const Mod* 
     Acc30 acc;
 #pragma unroll
     for (int j = 0; j < MAXK; ++j) acc.mac(w[j], Split30(md[lay.phat(j, level)]));
-    u64 conv = acc.reduce(ml);
+    u64 conv = acc.redc(ml);
     u64 v = subm(addm(uc[(size_t)level * N + k], md[lay.hmod(level)], ml.q), conv, ml.q);
     cl = mul_shoup(v, md[lay.pinv(level)], md[lay.pinv(level) + 1], ml.q);
   }
@@ -524,7 +524,7 @@ k_mdr_corr_kernel(const u64* __restrict__ u, u64* __restrict__ corr, const Mod* 
     Acc30 acc;
 #pragma unroll
     for (int j = 0; j < MAXK; ++j) acc.mac(w[j], Split30(md[lay.phat(j, i)]));
-    u64 conv = acc.reduce(m);
+    u64 conv = acc.redc(m);
     u64 v = mul_shoup(subm(md[lay.hmod(i)], conv, m.q), md[lay.pinv(i)], md[lay.pinv(i) + 1], m.q);
     u64 t = reduce64(cl, m);
     if (neg) t = subm(t, rc[3 * i + 2], m.q);       // t = c_l - q_l when c_l > q_l / 2

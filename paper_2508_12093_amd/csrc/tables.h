@@ -15,7 +15,9 @@ constexpr int kMaxSpecial = 8;    // special primes
 // two blocks are padded with zeros to kMaxSpecial so that kernels can run
 // their loops over special primes to a compile-time bound:
 //   [kMaxSpecial][2]      (Phat_k^-1 mod p_k, Shoup companion), Phat_k = P / p_k
-//   [L+1][kMaxSpecial]    Phat_k mod q_i (the K values of one q_i contiguous)
+//   [L+1][kMaxSpecial]    Phat_k 2^64 mod q_i (Montgomery form: the kernels'
+//                         sums over k come out of Acc30::redc as sum Phat_k ...;
+//                         the K values of one q_i contiguous)
 //   [L+1][2]              (P^-1 mod q_i, Shoup companion)
 //   [nprimes]             h mod (prime), h = (P - 1) / 2, the rounding offset
 //   [L+1][2]              (P mod q_i, Shoup companion)
@@ -31,9 +33,9 @@ struct MdLayout {
 };
 
 // ModUp table of one level: for each digit j, [kMaxAlpha][2] (Qhat_i^-1 mod
-// q_i, Shoup) for the digit's limbs i, then [ne][kMaxAlpha] Qhat_i mod p(t)
-// for every extended limb t (one target's values contiguous); entries past
-// the digit's limbs are zero.
+// q_i, Shoup) for the digit's limbs i, then [ne][kMaxAlpha] Qhat_i 2^64 mod
+// p(t) (Montgomery form, for Acc30::redc) for every extended limb t (one
+// target's values contiguous); entries past the digit's limbs are zero.
 __host__ __device__ inline size_t modup_digit_words(int ne) {
   return 2 * kMaxAlpha + (size_t)kMaxAlpha * ne;
 }
