@@ -384,6 +384,11 @@ void build_tables(Shared& sh) {
     for (int k = 0; k < K; ++k) pm = h_mulmod(pm, P.q[L + 1 + k] % q, q);
     md[lay.hmod(p)] = h_mulmod(h_submod(pm, 1, q), h_invmod(2, q), q);
   }
+  for (int i = 0; i <= L; ++i) {   // the same constants times P^-1 mod q_i
+    const u64 qi = P.q[i], pinv = md[lay.pinv(i)];
+    for (int k = 0; k < K; ++k) md[lay.phatp(k, i)] = h_mulmod(md[lay.phat(k, i)], pinv, qi);
+    md[lay.hpinv(i)] = h_mulmod(md[lay.hmod(i)], pinv, qi);
+  }
   sh.tab.moddown = upload(pool, md);
 
   // ModUp per (level, digit)

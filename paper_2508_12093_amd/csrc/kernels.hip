@@ -523,9 +523,9 @@ k_mdr_corr_kernel(const u64* __restrict__ u, u64* __restrict__ corr, const Mod* 
     const Mod m = mods[i];
     Acc30 acc;
 #pragma unroll
-    for (int j = 0; j < MAXK; ++j) acc.mac(w[j], Split30(md[lay.phat(j, i)]));
-    u64 conv = acc.redc(m);
-    u64 v = mul_shoup(subm(md[lay.hmod(i)], conv, m.q), md[lay.pinv(i)], md[lay.pinv(i) + 1], m.q);
+    for (int j = 0; j < MAXK; ++j) acc.mac(w[j], Split30(md[lay.phatp(j, i)]));
+    // (h - conv) P^-1 with P^-1 folded into the constants
+    u64 v = subm(md[lay.hpinv(i)], acc.redc(m), m.q);
     u64 t = reduce64(cl, m);
     if (neg) t = subm(t, rc[3 * i + 2], m.q);       // t = c_l - q_l when c_l > q_l / 2
     cc[(size_t)i * N + k] = subm(v, t, m.q);

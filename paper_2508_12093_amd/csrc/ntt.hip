@@ -345,6 +345,7 @@ __device__ __forceinline__ void ntt_body(const A ar, typename A::T* lds, const u
 // for element slot i (0..E-1) before the last pass's butterflies
 // (prefetch), so that their latency overlaps the arithmetic.
 struct PlainStore {
+  static constexpr bool kRaw = false;
   u64* dst;
   __device__ __forceinline__ void prefetch(int, size_t) {}
   __device__ __forceinline__ void put(int, size_t at, u64 v) const { dst[at] = v; }
@@ -455,7 +456,10 @@ __device__ __forceinline__ void ntt_body_dio(const A ar, typename A::T* lds, con
           const int e = e0[g] + k * si;
           const size_t at = ROWS ? rowbase + e : (size_t)e * C + col;
           const T v = x[g * GS + k];
-          store.put(g * GS + k, at, last ? (INV ? ar.out_inv(v, ni, nip) : ar.out_fwd(v)) : ar.mid(v));
+          if constexpr (Store::kRaw)
+            store.put_raw(g * GS + k, at, v);   // the store takes the unreduced value
+          else
+            store.put(g * GS + k, at, last ? (INV ? ar.out_inv(v, ni, nip) : ar.out_fwd(v)) : ar.mid(v));
         }
     } else {
 #pragma unroll
@@ -581,6 +585,7 @@ struct MdrEpi {
 
 template <int E>
 struct MdrStore {
+  static constexpr bool kRaw = false;
   const u64* u;
   const u64* d;
   u64* out;
@@ -666,6 +671,7 @@ struct MdEpi {
 
 template <int E>
 struct MdStore {
+  static constexpr bool kRaw = false;
   const u64* u;
   const u64* add;
   const u64* acc;
@@ -768,6 +774,7 @@ struct KsEpi {
 // 128-bit sums of at most kKsFusedDigits products of residues below 2^60
 template <int E>
 struct KsAccStore {
+  static constexpr bool kRaw = false;
   Acc s0[E], s1[E];
   const u64* kb;     // the digit's key rows on this limb's prime
   const u64* ka;
@@ -780,6 +787,51 @@ struct KsAccStore {
     s0[i].mac(v, pb[i]);
     s1[i].mac(v, pa[i]);
   }
+  __device__ __forceinline__ u64 out0(int i, const Mod& m) const { return reduce128(s0[i].hi, s0[i].lo, m); }
+  __device__ __forceinline__ u64 out1(int i, const Mod& m) const { return reduce128(s1[i].hi, s1[i].lo, m); }
+};
+
+// FP64 primes: each digit's product v * key mod q is taken exactly in FP64
+// on the transform's unreduced output (FpArith::mulmod with |v| < 10 q and
+// the key below q: the quotient estimate is at most 3 * 2^-53 * 10 q < 0.07
+// off, so each product lands in (-0.57 q, 0.57 q)), the at most four digits
+// summed as doubles (exact integers below 2.3 q) and rounded once to [0, q)
+// at the end, in place of two 128-bit sums and reductions.
+template <int E>
+struct KsFpStore {
+  static constexpr bool kRaw = true;
+  FpArith ar;
+  double s0[E], s1[E];
+  const u64* kb;
+  const u64* ka;
+  u64 pb[E], pa[E];
+  __device__ __forceinline__ explicit KsFpStore(const FpArith& a) : ar(a) {
+#pragma unroll
+    for (int i = 0; i < E; ++i) s0[i] = s1[i] = 0.0;
+  }
+  __device__ __forceinline__ void prefetch(int i, size_t at) {
+    pb[i] = kb[at];
+    pa[i] = ka[at];
+  }
+  __device__ __forceinline__ void put_raw(int i, size_t, double v) {
+    const double b = (double)pb[i], c = (double)pa[i];
+    s0[i] += ar.mulmod(v, b, b * ar.qinv);
+    s1[i] += ar.mulmod(v, c, c * ar.qinv);
+  }
+  __device__ __forceinline__ void put(int i, size_t at, u64 v) { put_raw(i, at, (double)v); }
+  __device__ __forceinline__ u64 out0(int i, const Mod&) const { return ar.out_fwd(s0[i]); }
+  __device__ __forceinline__ u64 out1(int i, const Mod&) const { return ar.out_fwd(s1[i]); }
+};
+
+template <class A, int E>
+struct KsStoreOf {
+  typedef KsAccStore<E> type;
+  __device__ __forceinline__ static type make(const A&) { return type(); }
+};
+template <int E>
+struct KsStoreOf<FpArith, E> {
+  typedef KsFpStore<E> type;
+  __device__ __forceinline__ static type make(const FpArith& ar) { return type(ar); }
 };
 
 template <class A, int LOGM, int LOGE, int SB, bool TL = false>
@@ -822,7 +874,7 @@ __device__ __forceinline__ void ks_tile(const A ar, u64* lds, const NttArgs& a, 
     __syncthreads();
   }
   for (int item = item0; item < item1; ++item) {
-    KsAccStore<E> st;
+    typename KsStoreOf<A, E>::type st = KsStoreOf<A, E>::make(ar);
     // one copy of the transform serves every digit (the key rows of later
     // items come from L2)
 #pragma unroll 1
@@ -848,7 +900,7 @@ __device__ __forceinline__ void ks_tile(const A ar, u64* lds, const NttArgs& a, 
     u64* u1 = u0 + (size_t)e.ne * NN;
 #pragma unroll
     for (int i = 0; i < E; ++i) {
-      u64 v0 = reduce128(st.s0[i].hi, st.s0[i].lo, m), v1 = reduce128(st.s1[i].hi, st.s1[i].lo, m);
+      u64 v0 = st.out0(i, m), v1 = st.out1(i, m);
       if (prep) {
         const u64* dp = e.pd + (size_t)item * e.spd + (size_t)t * NN + at[i];
         v0 = addm(v0, mul_shoup(dp[0], e.pmod, e.pmods, m.q), m.q);
@@ -904,6 +956,7 @@ struct RsEpi {
 
 template <int E>
 struct RsStore {
+  static constexpr bool kRaw = false;
   const u64* a;
   u64* out;
   u64 q, qlinv, qlinvs, k, kp;

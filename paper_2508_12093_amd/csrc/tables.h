@@ -21,6 +21,9 @@ constexpr int kMaxSpecial = 8;    // special primes
 //   [L+1][2]              (P^-1 mod q_i, Shoup companion)
 //   [nprimes]             h mod (prime), h = (P - 1) / 2, the rounding offset
 //   [L+1][2]              (P mod q_i, Shoup companion)
+//   [L+1][kMaxSpecial]    Phat_k P^-1 2^64 mod q_i (Montgomery form, for the
+//                         fused ModDown + rescale: the sum comes out times P^-1)
+//   [L+1]                 h P^-1 mod q_i
 struct MdLayout {
   int K, L;
   __host__ __device__ MdLayout(int k, int l) : K(k), L(l) {}
@@ -29,7 +32,9 @@ struct MdLayout {
   __host__ __device__ int pinv(int i) const { return 2 * kMaxSpecial + kMaxSpecial * (L + 1) + 2 * i; }
   __host__ __device__ int hmod(int p) const { return pinv(L + 1) + p; }
   __host__ __device__ int pmod(int i) const { return hmod(L + 1 + K) + 2 * i; }
-  __host__ __device__ int size() const { return pmod(L + 1); }
+  __host__ __device__ int phatp(int k, int i) const { return pmod(L + 1) + i * kMaxSpecial + k; }
+  __host__ __device__ int hpinv(int i) const { return phatp(0, L + 1) + i; }
+  __host__ __device__ int size() const { return hpinv(L + 1); }
 };
 
 // ModUp table of one level: for each digit j, [kMaxAlpha][2] (Qhat_i^-1 mod
