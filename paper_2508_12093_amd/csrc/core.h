@@ -260,6 +260,9 @@ struct Tables {
   Buf ninv;        // [nprimes][2] (N^-1, Shoup)
   // ModUp constants per level: see modup_table()
   std::map<int, std::shared_ptr<Buf>> modup;
+  // per level: [l+1][2] final factors N^-1 Qhat_i^-1 mod q_i (digit of limb i)
+  // of the inverse transforms that feed ModUp, in the twiddle table format
+  std::map<int, std::shared_ptr<Buf>> modup_ninv;
   // ModDown constants (one table for all levels)
   Buf moddown;
   // host copy of (P mod q_i, Shoup companion), i = 0..L, for kernel arguments

@@ -395,7 +395,7 @@ void build_tables(Shared& sh) {
   for (int l = 0; l <= L; ++l) {
     const int nl = l + 1, ne = nl + K;
     const size_t dw = modup_digit_words(ne);
-    std::vector<u64> all(dw * P.beta(l), 0);
+    std::vector<u64> all(dw * P.beta(l), 0), nv(2 * (size_t)nl, 0);
     for (int j = 0; j < P.beta(l); ++j) {
       const int lo = P.digit_lo(j), hi = P.digit_hi(j, l);
       u64* t = all.data() + dw * j;
@@ -406,6 +406,7 @@ void build_tables(Shared& sh) {
         u64 inv_ = h_invmod(qh, qi);
         t[2 * (i - lo)] = inv_;
         t[2 * (i - lo) + 1] = shoup(inv_, qi);
+        pair(h_mulmod(h_invmod((u64)N % qi, qi), inv_, qi), qi, &nv[2 * (size_t)i]);
         for (int tt = 0; tt < ne; ++tt) {
           int p = tt < nl ? tt : L + 1 + (tt - nl);
           u64 qt = P.q[p], v = 1;
@@ -417,6 +418,7 @@ void build_tables(Shared& sh) {
       }
     }
     sh.tab.modup[l] = std::make_shared<Buf>(upload(pool, all));
+    sh.tab.modup_ninv[l] = std::make_shared<Buf>(upload(pool, nv));
   }
   // rescale per level
   for (int l = 1; l <= L; ++l) {
@@ -436,6 +438,11 @@ void build_tables(Shared& sh) {
 const u64* modup_table(const Shared& sh, int level) {
   auto it = sh.tab.modup.find(level);
   if (it == sh.tab.modup.end()) PPST_THROW(ST_EINVAL, "no ModUp table");
+  return it->second->p;
+}
+const u64* modup_ninv(const Shared& sh, int level) {
+  auto it = sh.tab.modup_ninv.find(level);
+  if (it == sh.tab.modup_ninv.end()) PPST_THROW(ST_EINVAL, "no ModUp factor table");
   return it->second->p;
 }
 const u64* rescale_table(const Shared& sh, int level) {
@@ -603,6 +610,7 @@ void ks_accumulate_into(Context& cx, const KsKey& key, const u64* d, size_t sd, 
     L.nq = nl;
     L.pofs = P.L + 1;
     L.galois = g;
+    L.ninv = modup_ninv(sh, level);
     ntt(sh, L, true, cx.stream);
   }
   k_modup(sh, x, ext, level, nbatch, sx, sext, cx.stream);
@@ -1374,6 +1382,7 @@ std::vector<CtPtr> rotate_hoisted(Context& cx, const EvalKeys& evk, const Cipher
     L.nlimbs = nl;
     L.nq = nl;
     L.pofs = P.L + 1;
+    L.ninv = modup_ninv(sh, level);
     ntt(sh, L, true, cx.stream);
   }
   k_modup(sh, x.p, ext.p, level, 1, per, sext, cx.stream);
@@ -1451,6 +1460,7 @@ std::vector<CtPtr> rotate_hoisted_batch(Context& cx, const EvalKeys& evk,
       L.batch_stride = per;
       L.nq = nl;
       L.pofs = P.L + 1;
+      L.ninv = modup_ninv(sh, level);
       ntt(sh, L, true, cx.stream);
       k_modup(sh, x.p, e0, level, nb, per, sext, cx.stream);
     }
@@ -1596,6 +1606,7 @@ std::vector<CtPtr> rotsum_step(Context& cx, const EvalKeys& evk,
       L.nlimbs = nl;
       L.nq = nl;
       L.pofs = P.L + 1;
+      L.ninv = modup_ninv(sh, level);
       ntt(sh, L, true, cx.stream);
     } else {
       k_gather_rows(sh, d.data(), x.p, nb, cx.stream, per);
@@ -1607,6 +1618,7 @@ std::vector<CtPtr> rotsum_step(Context& cx, const EvalKeys& evk,
       L.batch_stride = per;
       L.nq = nl;
       L.pofs = P.L + 1;
+      L.ninv = modup_ninv(sh, level);
       ntt(sh, L, true, cx.stream);
     }
     k_modup(sh, x.p, ext.p, level, nb, per, sext, cx.stream);

@@ -29,6 +29,9 @@ struct NttLaunch {
   // inverse, out-of-place only: transform the input permuted by X -> X^galois
   // (canonical NTT order); 0 for none
   uint32_t galois = 0;
+  // inverse: per-prime final factors in the table format ([nprimes][2]);
+  // null for N^-1 (modup_ninv: N^-1 Qhat_i^-1, the input scaling of ModUp)
+  const u64* ninv = nullptr;
 };
 void ntt(const Shared& sh, const NttLaunch& L, bool inverse, hipStream_t st);
 

@@ -141,12 +141,13 @@ struct ModUpArgs {
 
 constexpr int kModUpChunk = 8;   // target limbs per thread
 
-// Thread (k, chunk, digit j): z_i = x_i Qhat_i^-1 mod q_i for the digit's limbs,
-// then y_t = sum_i z_i (Qhat_i mod t) mod t for the chunk's target limbs t
-// outside the digit (fast base conversion without correction).  The loops run
-// to MAXA with z_i = 0 past the digit (the table rows there are zero), so the
-// loads of a thread issue together; the restrict-qualified table is read
-// through the scalar unit.
+// Thread (k, chunk, digit j): y_t = sum_i z_i (Qhat_i mod t) mod t for the
+// chunk's target limbs t outside the digit (fast base conversion without
+// correction), where z_i = x_i Qhat_i^-1 mod q_i is the input itself: the
+// inverse transform that produces it ends with N^-1 Qhat_i^-1 instead of
+// N^-1 (modup_ninv).  The loops run to MAXA with z_i = 0 past the digit (the
+// table rows there are zero), so the loads of a thread issue together; the
+// restrict-qualified table is read through the scalar unit.
 template <int MAXA>
 __global__ void __launch_bounds__(kBlock)
 k_modup_kernel(const u64* __restrict__ xin, u64* __restrict__ extout,
@@ -171,11 +172,7 @@ k_modup_kernel(const u64* __restrict__ xin, u64* __restrict__ extout,
   for (int i = 0; i < MAXA; ++i) xv[i] = x[(size_t)(lo + min(i, da - 1)) * N + k];
   Split30 z[MAXA];
 #pragma unroll
-  for (int i = 0; i < MAXA; ++i) {
-    const u64 q = mods[lo + min(i, da - 1)].q;
-    const u64 v = mul_shoup(xv[i], cst[2 * i], cst[2 * i + 1], q);
-    z[i] = Split30(i < da ? v : 0);
-  }
+  for (int i = 0; i < MAXA; ++i) z[i] = Split30(i < da ? xv[i] : 0);
   for (int c = 0; c < kModUpChunk; ++c) {
     const int u = tfirst + c;
     if (u >= ntarget) break;

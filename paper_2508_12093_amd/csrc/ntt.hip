@@ -1175,7 +1175,7 @@ void ntt(const Shared& sh, const NttLaunch& L, bool inverse, hipStream_t st) {
   NttArgs a{};
   a.mods = (const Mod*)sh.tab.mods.p;
   set_tables(a, sh, inverse);
-  a.ninv = sh.tab.ninv.p;
+  a.ninv = L.ninv ? L.ninv : sh.tab.ninv.p;
   a.batch_stride = L.batch_stride;
   a.dst_stride = L.dst_stride == ~(size_t)0 ? L.batch_stride : L.dst_stride;
   a.N = P.N;

@@ -50,6 +50,9 @@ void build_tables(Shared& sh);
 
 // ModUp table of a level: [beta][modup_digit_words(ne)]
 const u64* modup_table(const Shared& sh, int level);
+// final factors of the inverse transform whose output ModUp reads at a level:
+// that output is then x_i Qhat_i^-1 mod q_i, the scaled digit ModUp sums
+const u64* modup_ninv(const Shared& sh, int level);
 // Rescale table for dropping q_level: [level][3] = (q_level^-1 mod q_i, Shoup, q_level mod q_i)
 const u64* rescale_table(const Shared& sh, int level);
 
