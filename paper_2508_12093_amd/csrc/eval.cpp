@@ -613,10 +613,17 @@ void ks_accumulate_into(Context& cx, const KsKey& key, const u64* d, size_t sd, 
     L.ninv = modup_ninv(sh, level);
     ntt(sh, L, true, cx.stream);
   }
-  k_modup(sh, x, ext, level, nbatch, sx, sext, cx.stream);
-  if (ks_fused_ok(P, level)) {
-    // the digits' row pass and the inner product in one kernel
+  // ModUp inside the column pass saves the extended digits' round trip
+  // through memory but re-reads each digit limb once per target (from L2):
+  // a gain for a few items, a loss for large batches
+  const bool fused = ks_fused_ok(P, level), modup_in_col = fused && nbatch <= 4 && modup_col_ok();
+  if (!modup_in_col) k_modup(sh, x, ext, level, nbatch, sx, sext, cx.stream);
+  if (fused) {
+    // the digits' row pass and the inner product in one kernel (and ModUp
+    // in their column pass)
     KsTail kt{};
+    kt.x = modup_in_col ? x : nullptr;
+    kt.sx = sx;
     kt.ext = ext;
     kt.d = d;
     kt.sd = sd;

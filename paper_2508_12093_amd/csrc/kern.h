@@ -84,6 +84,11 @@ struct MdTail {
 // on limb q_l, or null).  ks_fused_ok: N = 2^16, at most 4 digits, and not
 // switched off by PPST_KS_FUSED=0.
 struct KsTail {
+  // x non-null: ModUp runs inside the digits' column pass, from the scaled
+  // coefficients x ([nbatch][l+1][N] at stride sx, modup_ninv); else ext
+  // holds ModUp's output
+  const u64* x;
+  size_t sx;
   u64* ext;
   const u64* d;
   size_t sd;
@@ -95,6 +100,8 @@ struct KsTail {
   uint32_t gd;
 };
 bool ks_fused_ok(const Params& P, int level);
+// ModUp fused into the fused key switch's column pass (PPST_MODUP_COL=0: off)
+bool modup_col_ok();
 void ntt_fwd_ks_fused(const Shared& sh, const KsTail& tail, int level, int nbatch, hipStream_t st);
 void ntt_fwd_md_final(const Shared& sh, u64* conv, int level, int nbatch, const MdTail& tail,
                       hipStream_t st);

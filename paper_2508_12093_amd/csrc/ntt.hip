@@ -21,6 +21,7 @@
 #include "kern.h"
 
 #include <cstdlib>
+#include <cstring>
 #include "tables.h"
 
 namespace ppst {
@@ -344,6 +345,13 @@ __device__ __forceinline__ void ntt_body(const A ar, typename A::T* lds, const u
 // Stores finished elements of a limb.  A store may load operands of its own
 // for element slot i (0..E-1) before the last pass's butterflies
 // (prefetch), so that their latency overlaps the arithmetic.
+// Loads of the first register pass: PlainLoad reads the pass's source; a
+// custom load (kCustom) computes each element from its index instead.
+struct PlainLoad {
+  static constexpr bool kCustom = false;
+  __device__ __forceinline__ u64 get(size_t) const { return 0; }
+};
+
 struct PlainStore {
   static constexpr bool kRaw = false;
   u64* dst;
@@ -352,12 +360,12 @@ struct PlainStore {
 };
 
 template <class A, int LOGM, int LOGE, int SB, bool ROWS, bool INV, bool TL = false,
-          class Store = PlainStore>
+          class Store = PlainStore, class Load = PlainLoad>
 __device__ __forceinline__ void ntt_body_dio(const A ar, typename A::T* lds, const u64* src,
                                              Store& store, const ulonglong2* tw,
                                              const u64* ninv2, int N, int logR, int first,
                                              bool firstp, bool last, uint32_t galois, int logN,
-                                             const RowTw rt = RowTw{}) {
+                                             const RowTw rt = RowTw{}, const Load& ld = Load()) {
   typedef typename A::T T;
   constexpr int M = 1 << LOGM;
   constexpr int E = 1 << LOGE;
@@ -398,8 +406,12 @@ __device__ __forceinline__ void ntt_body_dio(const A ar, typename A::T* lds, con
         for (int k = 0; k < GS; ++k) {
           const int e = e0[g] + k * si;
           size_t at = ROWS ? rowbase + e : (size_t)e * C + col;
-          if (ROWS && INV && galois != 0) at = galois_src((uint32_t)at, galois, logN);
-          x[g * GS + k] = firstp ? ar.in(src[at]) : ar.in_mid(src[at]);
+          if constexpr (Load::kCustom) {
+            x[g * GS + k] = ar.in(ld.get(at));
+          } else {
+            if (ROWS && INV && galois != 0) at = galois_src((uint32_t)at, galois, logN);
+            x[g * GS + k] = firstp ? ar.in(src[at]) : ar.in_mid(src[at]);
+          }
         }
       // the row twiddles form while the loads are in flight
       if constexpr (TL) {
@@ -940,6 +952,104 @@ k_ntt_row_ks(NttArgs a, KsEpi e) {
     ks_tile<IntArith, LOGM, LOGE, SB>(IntArith(q), lds, a, e, t, prime, rg * SB, item0, item1);
 }
 
+// ---- ModUp fused into the forward column pass of the extended digits
+// Element at of target limb t (prime p) of digit j is the digit's fast base
+// conversion  sum_i z_i[at] (Qhat_i 2^64 mod p)  reduced by REDC, z_i the
+// scaled coefficients x_i Qhat_i^-1 mod q_i that the inverse transform wrote
+// (modup_ninv).  The column pass forms it where it would load the ModUp
+// kernel's output, so the digits' coefficient form never goes to memory;
+// the digit's limbs at a tile's columns are read by every target of the
+// digit, mostly from L2.
+struct ModUpSrc {
+  const u64* x;      // [nbatch][nl][N] scaled coefficients
+  size_t sx;
+  const u64* tab;    // modup_table of the level
+  int ne;
+};
+
+template <int MAXA>
+struct ModUpLoad {
+  static constexpr bool kCustom = true;
+  const u64* z;      // the digit's first limb (limbs at stride N)
+  const u64* cst;    // the target's kMaxAlpha constants, Montgomery form
+  Mod m;
+  int da, N;
+  __device__ __forceinline__ u64 get(size_t at) const {
+    Acc30 acc;
+#pragma unroll
+    for (int i = 0; i < MAXA; ++i) {
+      const u64 v = z[(size_t)min(i, da - 1) * N + at];
+      acc.mac(Split30(i < da ? v : 0), Split30(cst[i]));
+      if ((i & 7) == 7) acc.fold();
+    }
+    return acc.redc(m);
+  }
+};
+
+// Grid: tiles (batch item b, digit j, column group) times the digit's
+// targets, XCD-aware.  Workgroups are dealt round-robin to the 8 XCDs, so
+// workgroup w runs on XCD w mod 8; the targets of one tile take consecutive
+// slots w / 8 of one XCD and re-read the tile's digit limbs from that XCD's
+// L2.  The grid is padded to whole tiles per XCD (extra workgroups exit).
+constexpr unsigned kXcds = 8;
+template <int LOGE, int SB, int MAXA>
+__global__ void __launch_bounds__(SB * (1 << (8 - LOGE)))
+k_ntt_col_modup(NttArgs a, ModUpSrc mu, int ntargets) {
+  constexpr int LOGM = 8;
+  __shared__ u64 lds[SB * ((1 << LOGM) + 1)];
+  const unsigned slot = blockIdx.x / kXcds;
+  const unsigned tile = (slot / (unsigned)ntargets) * kXcds + blockIdx.x % kXcds;
+  if (tile >= (unsigned)(a.nbatch * a.blocks_per_limb)) return;
+  BlockPos bp;
+  bp.limb = (int)(slot % (unsigned)ntargets);
+  bp.item = (int)(tile % (unsigned)a.nbatch);
+  bp.grp = (int)(tile / (unsigned)a.nbatch);
+  const int N = a.N;
+  const int j = bp.item % a.dcount, b = bp.item / a.dcount;
+  const int lo = j * a.dalpha, hi = min(lo + a.dalpha, a.nq), da = hi - lo;
+  if (bp.limb >= a.dtotal - da) return;
+  const int t = bp.limb >= lo ? bp.limb + da : bp.limb;
+  const int prime = t < a.nq ? t : a.pofs + (t - a.nq);
+  const u64 q = a.mods[prime].q;
+  ModUpLoad<MAXA> ld;
+  ld.z = mu.x + (size_t)b * mu.sx + (size_t)lo * N;
+  ld.cst = mu.tab + modup_digit_words(mu.ne) * j + 2 * kMaxAlpha + (size_t)t * kMaxAlpha;
+  ld.m = a.mods[prime];
+  ld.da = da;
+  ld.N = N;
+  PlainStore store{a.dst + (size_t)bp.item * a.dst_stride + (size_t)t * N};
+  const ulonglong2* tw = (const ulonglong2*)(a.tw + (size_t)prime * N * 2);
+  const u64* ni = a.ninv + 2 * prime;
+  const int first = bp.grp * SB;
+  if (q < kFpPrimeBound)
+    ntt_body_dio<FpArith, LOGM, LOGE, SB, false, false>(FpArith(q), (double*)lds, nullptr, store,
+                                                         tw, ni, N, a.logR, first, true, false, 0u,
+                                                         a.logN, RowTw{}, ld);
+  else
+    ntt_body_dio<IntArith, LOGM, LOGE, SB, false, false>(IntArith(q), lds, nullptr, store, tw, ni,
+                                                          N, a.logR, first, true, false, 0u, a.logN,
+                                                          RowTw{}, ld);
+}
+
+template <int LOGE, int SB>
+void run_col_modup(const NttArgs& base, const ModUpSrc& mu, int alpha, int nlimbs, int nbatch,
+                   hipStream_t st) {
+  NttArgs a = base;
+  a.blocks_per_limb = (a.N >> a.logR) / SB;
+  a.nbatch = nbatch;
+  const unsigned tiles = (unsigned)(a.blocks_per_limb * nbatch);
+  dim3 grid(((tiles + kXcds - 1) / kXcds) * kXcds * (unsigned)nlimbs);
+  dim3 block(SB * (1 << (8 - LOGE)));
+  if (alpha <= 4)
+    hipLaunchKernelGGL((k_ntt_col_modup<LOGE, SB, 4>), grid, block, 0, st, a, mu, nlimbs);
+  else if (alpha <= 9)
+    hipLaunchKernelGGL((k_ntt_col_modup<LOGE, SB, 9>), grid, block, 0, st, a, mu, nlimbs);
+  else if (alpha <= kMaxAlpha)
+    hipLaunchKernelGGL((k_ntt_col_modup<LOGE, SB, 16>), grid, block, 0, st, a, mu, nlimbs);
+  else
+    PPST_THROW(ST_EINVAL, "digit size above 16 limbs");
+}
+
 // ---- forward row pass that finishes a rescale
 // For limb i < l of polynomial c the stored element is
 //   ((k_i a_c,i or a_c,i) - corr_i) q_l^-1 mod q_i
@@ -1279,6 +1389,28 @@ static MdFn md_variant(int logN, int row_index) {
   }
 }
 
+bool modup_col_ok() {
+  static const bool enabled = [] {
+    const char* v = std::getenv("PPST_MODUP_COL");
+    return !(v && v[0] == '0');
+  }();
+  return enabled;
+}
+
+// the fused ModUp + column pass shape: PPST_MODUP_COL=E,SB (log2 of the
+// register radix, workgroup columns) picks another
+static int modup_col_variant() {
+  static const int v = [] {
+    const char* e = std::getenv("PPST_MODUP_COL");
+    if (!e || !e[0] || e[0] == '1') return 0;
+    if (!std::strcmp(e, "2,16")) return 1;
+    if (!std::strcmp(e, "4,16")) return 2;
+    if (!std::strcmp(e, "3,8")) return 3;
+    return 0;
+  }();
+  return v;
+}
+
 bool ks_fused_ok(const Params& P, int level) {
   static const bool enabled = [] {
     const char* v = std::getenv("PPST_KS_FUSED");
@@ -1313,7 +1445,17 @@ void ntt_fwd_ks_fused(const Shared& sh, const KsTail& tail, int level, int nbatc
   const int b = ntt_bucket(most * nbatch * beta);
   a.src = tail.ext;
   a.dst = tail.ext;
-  kCol16[sh.ntt_plan.v[0][0][b]].fwd(a, most, nbatch * beta, st);
+  if (tail.x) {
+    const ModUpSrc mu{tail.x, tail.sx, modup_table(sh, level), ne};
+    switch (modup_col_variant()) {
+      case 1: run_col_modup<2, 16>(a, mu, P.alpha, most, nbatch * beta, st); break;
+      case 2: run_col_modup<4, 16>(a, mu, P.alpha, most, nbatch * beta, st); break;
+      case 3: run_col_modup<3, 8>(a, mu, P.alpha, most, nbatch * beta, st); break;
+      default: run_col_modup<3, 16>(a, mu, P.alpha, most, nbatch * beta, st); break;
+    }
+  } else {
+    kCol16[sh.ntt_plan.v[0][0][b]].fwd(a, most, nbatch * beta, st);
+  }
   KsEpi e{};
   e.ext = tail.ext;
   e.sext = (size_t)beta * ne * N;

@@ -228,6 +228,27 @@ def test_b1_cv_and_comparator_with_refreshes_bit_exact(bstat):
     assert np.mean(np.abs(p.decrypt(y) * np.sqrt(g) - 1.0)) < 1e-6
 
 
+def test_b1_cv_full_range_sign_bit_exact(bstat):
+    """CV with a negative mean and with a mean near zero: the sign of mu / B
+    by Exp. 1's seven-fold g_3 composition (G_3^(7), 21 levels, so it
+    refreshes twice), mu / B = -0.5 and -0.1.  Bit-exact with the oracle;
+    within 1e-3 of FP64 (the sign's error at 0.1 is below 1e-9)."""
+    p = bstat
+    n = 2048
+    cfg = ffi.ppst_invsqrt_cfg_default(coeffs=EXP1_COEFFS, a=0.0, b=2.0, degree=31, iters=6,
+                                       sign_k=7, boot=p.bt)
+    ocfg = C.InvSqrtCfg(a=0.0, b=2.0, degree=31, iters=6, coeffs=EXP1_COEFFS, boot=True)
+    for lo, hi, seed in ((-18.0, -2.0, 1200), (-12.0, 8.0, 1300)):
+        x = synth.uniform_column(seed, n, lo, hi)
+        c, o = p.encrypt(x, seed + 1, level=p.P.Lc)
+        print("b1 CV with G_3^(7), mean %.3f" % float(np.mean(x)), flush=True)
+        r = ffi.ppst_stat_cv(p.ctx, p.evk, [c], n, 20.0, 20.0, cfg)
+        p.same(r, p.circ.cv([o], n, 20.0, 20.0, ocfg, sign_k=7))
+        want = stats64.cv(x)                     # sigma / mu, negative here
+        assert want < 0
+        assert abs(p.decrypt(r)[0] / want - 1) < 1e-3
+
+
 def test_b2_bootstrap_refreshes():
     """N = 2^16: the refresh of a full [-1, 1] column decrypts to it (max
     error 2^-15, about 2^-17 measured), lands on level 11 and computes on;
