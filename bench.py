@@ -31,28 +31,30 @@ HBM_PEAK_GBS = 8000.0
 # (FP64 fused multiply-add issues at that full rate: 78.6 TFLOP/s).
 VALU_PEAK = 256 * 64 * 2.4e9
 # One forward butterfly on the FP64 path (every 40-bit prime of the chain):
-# 6 operations for the exact product y w - k q (mul, fma, mul, rint, fma,
-# add), 3 for the two outputs (a + q, a + q + r, a + q - r) and 4 for the lazy
-# reduction of x into [0, 2q) (subtract, compare, two 32-bit selects).
-OPS_PER_BFLY = 13
+# 6 operations for the exact product r = y w - k q (mul, fma, mul, rint, fma,
+# add) and 2 for the outputs x + r, x - r (the path keeps residues unreduced
+# between stages, so there is no reduction step).
+OPS_PER_BFLY = 8
 BFLY_PEAK_G = VALU_PEAK / OPS_PER_BFLY / 1e9
 # HBM bytes per 25-limb forward NTT from FETCH_SIZE + WRITE_SIZE counters
 # (rocprofv3 --pmc, one counter per run), scaled by the same counters on a
 # plain copy of known size.  The figure belongs to the NTT source it was taken
 # with (its SHA-256 below); for any other source the traffic is reported as
 # null.
-NTT_TRAFFIC = {"bytes": 79874562,
-               "source_sha256": "e375c16f2dd1c5dbbe3fe236b2fd1d1695b6c8658f098045a6f3d2ff76c2cf78"}
+NTT_TRAFFIC = {"bytes": 55839019,
+               "source_sha256": "8c15f05bb2e06748a5608625453f61c6bcc28ed8ee97960f096689891ea59960"}
 # Algorithmic HBM bytes of the other key-switching kernels of one plain
 # product at level 24 (N = 2^16, K = 7, dnum = 3; a limb is 512 KiB): the key
 # inner product reads 3 digit limbs and 6 key limbs per extended limb (32)
 # and writes 2 (352 limbs), alone or fused with the row pass of the digits'
 # forward NTT (the pass's own input is the same 3 digit limbs); ModUp reads d2's 25 limbs and writes the 71
 # extension limbs; the ModDown correction reads 2 x 8 limbs and writes
-# 2 x 24; the tensor reads 4 x 25 and writes 3 x 25.
+# 2 x 24; the tensor reads 4 x 25 and writes 3 x 25; ModUp inside the
+# digits' column pass reads the 25 scaled limbs and writes the 69 extension
+# limbs column-transformed.
 LIMB = 1 << 19
 KS_KERNELS = {"k_ks_inner_kernel<1>": ("hbm", 352 * LIMB), "k_ntt_row_ks<8, 2, 4>": ("hbm", 352 * LIMB),
-              "k_modup_kernel<9>": ("alu", 96 * LIMB),
+              "k_ntt_col_modup<3, 16, 9>": ("alu", 94 * LIMB), "k_modup_kernel<9>": ("alu", 96 * LIMB),
               "k_mdr_corr_kernel<8>": ("alu", 64 * LIMB), "k_tensor_kernel": ("hbm", 175 * LIMB)}
 
 
@@ -69,6 +71,9 @@ def parse():
     ap.add_argument("--quick", action="store_true", help="short run for profiling")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the roofline kernel and a copy of known size")
+    ap.add_argument("--ntt-variants", default=None,
+                    help="column,row variant indices of the roofline kernel (default %d,%d)"
+                    % (NTT_COL_VARIANT, NTT_ROW_VARIANT))
     ap.add_argument("--boot-runs", type=int, default=5,
                     help="timed bootstraps at N=2^16 (0: skip the bootstrapping leg)")
     ap.add_argument("--only", choices=["plain", "batched", "pearson", "boot"], default=None,
@@ -484,25 +489,34 @@ def serving_bench(ctx, pk, sk, evk, nq: int, loads, seed: int = 4, nslots: int =
         tickets = [None] * len(queries)
         gaps = rng.exponential(1.0 / rate, len(queries)) if rate else np.zeros(len(queries))
 
+        failure = []
+
         def feeder():
             t0 = time.perf_counter()
             at = 0.0
-            for i, q in enumerate(queries):
-                at += gaps[i]
-                d = t0 + at - time.perf_counter()
-                if d > 0:
-                    time.sleep(d)
-                tickets[i] = submit(q)
+            try:
+                for i, q in enumerate(queries):
+                    at += gaps[i]
+                    d = t0 + at - time.perf_counter()
+                    if d > 0:
+                        time.sleep(d)
+                    tickets[i] = submit(q)
+            except BaseException as e:        # a refused submission ends the run
+                failure.append(e)
 
         th = threading.Thread(target=feeder)
         t_start = time.perf_counter()
         th.start()
         res = []
         for i in range(len(queries)):
-            while tickets[i] is None:
+            while tickets[i] is None and not failure:
                 time.sleep(1e-4)
+            if tickets[i] is None:
+                break
             res.append(ffi.ppst_server_wait(srv, tickets[i]))
         th.join()
+        if failure:
+            raise failure[0]
         wall = time.perf_counter() - t_start
         failed = [r[0] for r in res if r[0] != 0]
         if failed:
@@ -524,6 +538,7 @@ def serving_bench(ctx, pk, sk, evk, nq: int, loads, seed: int = 4, nslots: int =
         got = float(ffi.ppst_decode(ctx, ffi.ppst_decrypt(ctx, sk, r[1]))[0])
         want = fp64(kind, B, x, y)
         errs.append(abs(got - want) / max(abs(want), 1.0))   # relative, absolute below 1
+    del res                                   # the results' blocks go back to the pools
     points = []
     for f in loads:
         rate = f * sat_rate
@@ -558,7 +573,7 @@ def serving_bench(ctx, pk, sk, evk, nq: int, loads, seed: int = 4, nslots: int =
 # The roofline kernel is timed under a fixed variant pair (the one the
 # autotuner picks for 25-limb forward transforms on MI355X in most runs), so
 # that the same kernels appear in the rocprofv3 profiles of --kernels-only.
-NTT_COL_VARIANT, NTT_ROW_VARIANT = 5, 6      # col:E3,SB16,D / row:E3,SB4,D
+NTT_COL_VARIANT, NTT_ROW_VARIANT = 5, 7      # col:E3,SB16,D / row:E2,SB4,D
 
 
 def boot_bench(stream, runs: int):
@@ -746,7 +761,7 @@ def _ntt_source_sha():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def measure_ntt(ctx, stream, reps: int):
+def measure_ntt(ctx, stream, reps: int, variants=None):
     """Forward NTT (column pass + row pass) of one 25-limb polynomial at
     N = 2^16, timed with HIP events on the library's stream.  Leaves the
     context on the fixed plan.
@@ -765,7 +780,7 @@ def measure_ntt(ctx, stream, reps: int):
     limbs = L + 1
     rng = np.random.default_rng(5)
     primes = ctx.primes
-    ffi.ppst_ntt_set_plan(ctx, NTT_COL_VARIANT, NTT_ROW_VARIANT)
+    ffi.ppst_ntt_set_plan(ctx, *(variants or (NTT_COL_VARIANT, NTT_ROW_VARIANT)))
     plan = ffi.ppst_ntt_plan(ctx).split(";")[0]
     host = np.stack([rng.integers(0, primes[i % limbs], N, dtype=np.uint64) for i in range(2 * limbs)])
     dev = torch.from_numpy(host.view(np.int64).copy()).cuda()
@@ -793,13 +808,16 @@ def measure_ntt(ctx, stream, reps: int):
         "%.0f GB/s of algorithmic bytes (%.3f of HBM)" % (
             sec * 1e6, g_bfly, g_bfly / BFLY_PEAK_G, BFLY_PEAK_G, alg_bytes / sec / 1e9,
             alg_bytes / sec / 1e9 / HBM_PEAK_GBS))
+    alu = alu_floor >= hbm_floor
+    gbs = alg_bytes / sec / 1e9
     return {
         "kernel": "forward NTT of 25 limbs at N=2^16 (column pass + row pass; %s)" % plan.strip(),
-        "bound": "alu" if alu_floor >= hbm_floor else "hbm",
-        "achieved": round(g_bfly, 1),
-        "peak": round(BFLY_PEAK_G, 1),
-        "unit": "G butterflies/s",
-        "frac": round(g_bfly / BFLY_PEAK_G, 4),
+        "bound": "alu" if alu else "hbm",
+        "achieved": round(g_bfly, 1) if alu else round(gbs, 1),
+        "peak": round(BFLY_PEAK_G, 1) if alu else HBM_PEAK_GBS,
+        "unit": "G butterflies/s" if alu else "GB/s",
+        "frac": round(g_bfly / BFLY_PEAK_G, 4) if alu else round(gbs / HBM_PEAK_GBS, 4),
+        "alu_frac": round(g_bfly / BFLY_PEAK_G, 4),
         "traffic": None if stale else NTT_TRAFFIC["bytes"],
         "us_per_launch_pair": round(sec * 1e6, 3),
         "butterflies_per_launch_pair": butterflies,
@@ -900,7 +918,8 @@ def kernels_only(args):
     torch.cuda.set_stream(stream)
     os.environ["PPST_NTT_AUTOTUNE"] = "0"      # the profile holds only the timed launches
     ctx = ffi.ppst_context_create("c2", stream=ctypes.c_void_p(stream.cuda_stream))
-    rf = measure_ntt(ctx, stream, reps=20)
+    variants = tuple(int(v) for v in args.ntt_variants.split(",")) if args.ntt_variants else None
+    rf = measure_ntt(ctx, stream, reps=20, variants=variants)
     n = 64 << 20                                             # 64 Mi int64 = 512 MiB
     a = torch.ones(n, dtype=torch.int64, device="cuda")
     b = torch.empty_like(a)

@@ -508,8 +508,12 @@ std::unique_ptr<Context> make_context(std::shared_ptr<Shared> sh, hipStream_t st
 void destroy_context(Context* cx) {
   if (!cx) return;
   (void)hipStreamSynchronize(cx->stream);
-  // ciphertexts the caller still holds keep the pool alive past the stream
-  if (cx->pool) cx->pool->detach();
+  // ciphertexts the caller still holds keep the pool alive past the stream;
+  // its cache of free blocks goes back to the device now
+  if (cx->pool) {
+    cx->pool->trim();
+    cx->pool->detach();
+  }
   cx->pool.reset();
   if (cx->own_stream) (void)hipStreamDestroy(cx->stream);
 }
