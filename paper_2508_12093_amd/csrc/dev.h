@@ -108,6 +108,14 @@ __device__ __forceinline__ u64 reduce64(u64 x, const Mod& m) {
   return csub(r, m.q);
 }
 
+// a0 b1 + a1 b0 mod q (the tensor's middle term; below 2 q^2 < 2^124)
+__device__ __forceinline__ u64 mul2_add(u64 a0, u64 b1, u64 a1, u64 b0, const Mod& m) {
+  Acc acc;
+  acc.mac(a0, b1);
+  acc.mac(a1, b0);
+  return reduce128(acc.hi, acc.lo, m);
+}
+
 // Automorphism X -> X^g in canonical NTT order: output slot j takes input
 // slot j' with 2 brv(j') + 1 = (2 brv(j) + 1) g mod 2N.  g = 0 stands for the
 // identity.  The map sends every aligned block of 2^s slots onto one aligned

@@ -597,13 +597,21 @@ void ntt_ext_digits(Context& cx, u64* ext, int level, int nbatch) {
 // of the fused ModDown + rescale.
 // The scratch is caller memory: x ([nbatch][l+1][N], free again once this
 // returns), ext ([nbatch][beta][ne][N]) and the result u.
+// With pa, pb (a product on the fused path; d, sd, prep_d unused) the input
+// is the operands' d2 = a1 b1, formed in the inverse transform's first pass
+// and, for the digits' own limbs and P d0, P d1, in the fused kernel: the
+// tensor is never written.
 void ks_accumulate_into(Context& cx, const KsKey& key, const u64* d, size_t sd, int level,
-                        int nbatch, uint32_t g, const u64* prep_d, u64* x, u64* ext, u64* u) {
+                        int nbatch, uint32_t g, const u64* prep_d, u64* x, u64* ext, u64* u,
+                        const u64* const* pa = nullptr, const u64* const* pb = nullptr) {
   const Params& P = cx.P();
   const Shared& sh = *cx.sh;
   const int N = P.N, nl = level + 1, K = P.K, ne = nl + K, beta = P.beta(level);
   const size_t sx = (size_t)nl * N, sext = (size_t)beta * ne * N, su = 2 * (size_t)ne * N;
-  {
+  if (pa) {
+    if (!ks_fused_ok(P, level) || g != 0) PPST_THROW(ST_EINVAL, "operand form needs the fused key switch");
+    ntt_inv_prod(sh, pa, pb, x, level, nbatch, modup_ninv(sh, level), cx.stream);
+  } else {
     NttLaunch L{};
     L.src = d;
     L.dst = x;
@@ -629,13 +637,15 @@ void ks_accumulate_into(Context& cx, const KsKey& key, const u64* d, size_t sd, 
     kt.x = modup_in_col ? x : nullptr;
     kt.sx = sx;
     kt.ext = ext;
-    kt.d = d;
+    kt.d = pa ? nullptr : d;
     kt.sd = sd;
+    kt.pa = pa;
+    kt.pb = pb;
     kt.key = key.k.p;
     kt.u = u;
     kt.pd = prep_d;
     kt.spd = sd;
-    if (prep_d) {
+    if (prep_d || pa) {
       kt.pmod = sh.tab.pmod_host[2 * level];
       kt.pmods = sh.tab.pmod_host[2 * level + 1];
     }
@@ -713,8 +723,11 @@ void keyswitch(Context& cx, const KsKey& key, const u64* d, size_t sd, int level
 // tensor [3][nl][N] per item (stride sd); out: one device pointer per item,
 // each [2][l][N].
 // corr: caller scratch of [nbatch][2][l][N] words
+// pa, pb: a product's operands in place of the tensor D (d0, d1 formed in
+// the last pass)
 void ks_moddown_rescale_into(Context& cx, u64* u, const u64* D, size_t sd, int level,
-                             u64* const* out, int nbatch, u64* corr) {
+                             u64* const* out, int nbatch, u64* corr,
+                             const u64* const* pa = nullptr, const u64* const* pb = nullptr) {
   const Params& P = cx.P();
   const Shared& sh = *cx.sh;
   const int N = P.N, nl = level + 1, K = P.K, ne = nl + K;
@@ -733,14 +746,31 @@ void ks_moddown_rescale_into(Context& cx, u64* u, const u64* D, size_t sd, int l
     ntt(sh, L, true, cx.stream);
   }
   k_mdr_corr(sh, u, corr, level, nbatch, su, sc, cx.stream);
-  MdrTail tail{u, D, su, sd, rescale_table(sh, level), out};
+  MdrTail tail{u, pa ? nullptr : D, su, sd, rescale_table(sh, level), out, pa, pb};
   ntt_fwd_mdr_final(sh, corr, level, nbatch, tail, cx.stream);
 }
 
 void ks_moddown_rescale(Context& cx, Buf& u, const u64* D, size_t sd, int level,
-                        u64* const* out, int nbatch) {
+                        u64* const* out, int nbatch, const u64* const* pa = nullptr,
+                        const u64* const* pb = nullptr) {
   Buf corr = dev_buf(cx.pool, 2 * (size_t)level * cx.P().N * nbatch);
-  ks_moddown_rescale_into(cx, u.p, D, sd, level, out, nbatch, corr.p);
+  ks_moddown_rescale_into(cx, u.p, D, sd, level, out, nbatch, corr.p, pa, pb);
+}
+
+// A product on the fused path straight from its operands (pa[b], pb[b]):
+// out[b] = rescale(relin(tensor)) with the tensor never written
+void mul_from_operands(Context& cx, const KsKey& key, const u64* const* pa, const u64* const* pb,
+                       int level, u64* const* out, int nbatch) {
+  const Params& P = cx.P();
+  const int N = P.N, nl = level + 1, ne = nl + P.K, beta = P.beta(level);
+  const size_t sx = (size_t)nl * N, sext = (size_t)beta * ne * N, su = 2 * (size_t)ne * N;
+  Buf u = dev_buf(cx.pool, su * nbatch);
+  {
+    Buf x = dev_buf(cx.pool, sx * nbatch);
+    Buf ext = dev_buf(cx.pool, sext * nbatch);
+    ks_accumulate_into(cx, key, nullptr, 0, level, nbatch, 0, nullptr, x.p, ext.p, u.p, pa, pb);
+  }
+  ks_moddown_rescale(cx, u, nullptr, 0, level, out, nbatch, pa, pb);
 }
 
 // ciphertexts per batched launch group
@@ -1280,10 +1310,16 @@ CtPtr mul(Context& cx, const EvalKeys& evk, const Ciphertext& a, const Ciphertex
   require_canon(cx.P(), a.level);
   const KsKey& key = relin_key(evk);
   const Params& P = cx.P();
-  auto d = tensor(cx, a, b);
-  Buf u = ks_accumulate(cx, key, d->poly(2), 0, a.level, 1, 0, d->buf.p);
   auto out = new_ct(cx, a.level - 1, P.scale[a.level - 1]);
   u64* op = out->buf.p;
+  if (ks_fused_ok(P, a.level)) {
+    const u64* pa = a.buf.p;
+    const u64* pb = b.buf.p;
+    mul_from_operands(cx, key, &pa, &pb, a.level, &op, 1);
+    return out;
+  }
+  auto d = tensor(cx, a, b);
+  Buf u = ks_accumulate(cx, key, d->poly(2), 0, a.level, 1, 0, d->buf.p);
   ks_moddown_rescale(cx, u, d->buf.p, 0, a.level, &op, 1);
   return out;
 }
@@ -1304,6 +1340,11 @@ void mul_into(Context& cx, const EvalKeys& evk, const u64* a, const u64* b, int 
   u64* ext = D + 3 * nl * N;                          // extended digits [beta][ne][N]
   u64* u = ext + (size_t)P.beta(level) * ne * N;      // accumulators [2][ne][N]
   u64* xc = u + 2 * ne * N;                           // d2's coefficients, later the correction
+  if (ks_fused_ok(P, level)) {                        // the tensor region stays unused
+    ks_accumulate_into(cx, key, nullptr, 0, level, 1, 0, nullptr, xc, ext, u, &a, &b);
+    ks_moddown_rescale_into(cx, u, nullptr, 0, level, &out, 1, xc, &a, &b);
+    return;
+  }
   k_tensor(*cx.sh, &a, &b, D, (int)nl, 1, 0, cx.stream);
   ks_accumulate_into(cx, key, D + 2 * nl * N, 0, level, 1, 0, D, xc, ext, u);
   ks_moddown_rescale_into(cx, u, D, 0, level, &out, 1, xc);
@@ -1758,8 +1799,15 @@ std::vector<CtPtr> mul_batch(Context& cx, const EvalKeys& evk,
   for (size_t i = 0; i < n; ++i) outs.push_back(new_ct(cx, level - 1, P.scale[level - 1]));
   // groups of kMulBatchGroup products: one launch per stage and one read of
   // the key per group
+  const bool operands = ks_fused_ok(P, level);
   for (size_t b0 = 0; b0 < n; b0 += kMulBatchGroup) {
     const int nb = (int)std::min<size_t>(kMulBatchGroup, n - b0);
+    if (operands) {
+      std::vector<u64*> po(nb);
+      for (int i = 0; i < nb; ++i) po[i] = outs[b0 + i]->buf.p;
+      mul_from_operands(cx, key, pa.data() + b0, pb.data() + b0, level, po.data(), nb);
+      continue;
+    }
     Buf D = dev_buf(cx.pool, 3 * per * nb);
     k_tensor(*cx.sh, pa.data() + b0, pb.data() + b0, D.p, nl, nb, 3 * per, cx.stream);
     Buf u = ks_accumulate(cx, key, D.p + 2 * per, 3 * per, level, nb, 0, D.p);

@@ -51,10 +51,12 @@ struct PtrsIn {
 // [nbatch][3][nl][N] at stride sd, rc: the rescale table of the level.
 struct MdrTail {
   const u64* u;
-  const u64* d;
+  const u64* d;                 // the tensor [3][nl][N] per item, or null: pa, pb
   size_t su, sd;
   const u64* rc;
   u64* const* out;
+  const u64* const* pa = nullptr;   // a product's operands (d0, d1 formed from them)
+  const u64* const* pb = nullptr;
 };
 void ntt_fwd_mdr_final(const Shared& sh, u64* corr, int level, int nbatch, const MdrTail& tail,
                        hipStream_t st);
@@ -90,8 +92,10 @@ struct KsTail {
   const u64* x;
   size_t sx;
   u64* ext;
-  const u64* d;
+  const u64* d;                 // null for a product: d2 = a1 b1 from pa, pb
   size_t sd;
+  const u64* const* pa;
+  const u64* const* pb;
   const u64* key;
   u64* u;
   const u64* pd;
@@ -100,6 +104,11 @@ struct KsTail {
   uint32_t gd;
 };
 bool ks_fused_ok(const Params& P, int level);
+// Inverse NTT of a product's d2 = a1 b1 (operands pa[b], pb[b]: [2][l+1][N])
+// into x ([nbatch][l+1][N]), the product formed in the first pass's loads;
+// ninv: the final factors (null: N^-1).  N = 2^16.
+void ntt_inv_prod(const Shared& sh, const u64* const* pa, const u64* const* pb, u64* x, int level,
+                  int nbatch, const u64* ninv, hipStream_t st);
 // ModUp fused into the fused key switch's column pass (PPST_MODUP_COL=0: off)
 bool modup_col_ok();
 void ntt_fwd_ks_fused(const Shared& sh, const KsTail& tail, int level, int nbatch, hipStream_t st);

@@ -349,7 +349,18 @@ __device__ __forceinline__ void ntt_body(const A ar, typename A::T* lds, const u
 // custom load (kCustom) computes each element from its index instead.
 struct PlainLoad {
   static constexpr bool kCustom = false;
-  __device__ __forceinline__ u64 get(size_t) const { return 0; }
+  __device__ __forceinline__ u64 get(int, size_t) const { return 0; }
+};
+
+// A product's d2 = a1 b1 mod q, formed where the inverse transform of the
+// tensor's d2 would load it: the key switch of a product starts from a1 and
+// b1 themselves and d2 is never written.
+struct ProdLoad {
+  static constexpr bool kCustom = true;
+  const u64* a;
+  const u64* b;
+  Mod m;
+  __device__ __forceinline__ u64 get(int, size_t at) const { return mulm(a[at], b[at], m); }
 };
 
 struct PlainStore {
@@ -407,7 +418,7 @@ __device__ __forceinline__ void ntt_body_dio(const A ar, typename A::T* lds, con
           const int e = e0[g] + k * si;
           size_t at = ROWS ? rowbase + e : (size_t)e * C + col;
           if constexpr (Load::kCustom) {
-            x[g * GS + k] = ar.in(ld.get(at));
+            x[g * GS + k] = ar.in(ld.get(g * GS + k, at));
           } else {
             if (ROWS && INV && galois != 0) at = galois_src((uint32_t)at, galois, logN);
             x[g * GS + k] = firstp ? ar.in(src[at]) : ar.in_mid(src[at]);
@@ -587,7 +598,8 @@ k_ntt_pass_persistent(NttArgs a, unsigned ntiles) {
 // the same operations in the same order as the separate final kernel.
 struct MdrEpi {
   const u64* u;      // [item][2][ne][N]  key-switch accumulators (NTT form)
-  const u64* d;      // [item][3][nl][N]  tensor (d0, d1 used)
+  const u64* d;      // [item][3][nl][N]  tensor (d0, d1 used), or null:
+  PtrsIn pa, pb;     //   the operands (item: [2][nl][N]), d0 = a0 b0, d1 = a0 b1 + a1 b0
   size_t su, sd;
   OutPtrs out;       // item b writes [2][level][N] at out.p[b]
   const u64* md;     // ModDown table
@@ -595,34 +607,51 @@ struct MdrEpi {
   int K, L, level, ne, nl;
 };
 
-template <int E>
+// OPS: d_c from the operands (OPS = 1 + c: d0 = a0 b0, d1 = a0 b1 + a1 b0)
+// instead of the tensor's d_c (OPS = 0)
+template <int E, int OPS>
 struct MdrStore {
   static constexpr bool kRaw = false;
   const u64* u;
   const u64* d;
+  const u64* a0;
+  const u64* a1;
+  const u64* b0;
+  const u64* b1;
+  Mod m;
   u64* out;
   u64 q, pinv, pinvs, qlinv, qlinvs;
-  u64 pu[E], pd[E];
+  u64 pu[E], pd[E], pe[E], pf[E], pg[E];
   __device__ __forceinline__ void prefetch(int i, size_t at) {
     pu[i] = u[at];
-    pd[i] = d[at];
+    if constexpr (OPS == 0) {
+      pd[i] = d[at];
+    } else if constexpr (OPS == 1) {
+      pd[i] = a0[at];
+      pe[i] = b0[at];
+    } else {
+      pd[i] = a0[at];
+      pe[i] = b1[at];
+      pf[i] = a1[at];
+      pg[i] = b0[at];
+    }
   }
   __device__ __forceinline__ void put(int i, size_t at, u64 corr) const {
     u64 v = mul_shoup(pu[i], pinv, pinvs, q);
-    v = addm(v, pd[i], q);
+    u64 dv;
+    if constexpr (OPS == 0) dv = pd[i];
+    else if constexpr (OPS == 1) dv = mulm(pd[i], pe[i], m);
+    else dv = mul2_add(pd[i], pe[i], pf[i], pg[i], m);
+    v = addm(v, dv, q);
     v = addm(v, corr, q);
     out[at] = mul_shoup(v, qlinv, qlinvs, q);
   }
 };
 
-template <int LOGM, int LOGE, int SB>
-__global__ void __launch_bounds__(SB * (1 << (LOGM - LOGE)))
-k_ntt_row_mdr(NttArgs a, MdrEpi e) {
-  constexpr int M = 1 << LOGM;
-  __shared__ u64 lds[SB * (M + 1)];
-  __shared__ double twl[RowTwShape<LOGM, SB, true>::size];
+template <int LOGM, int LOGE, int SB, int OPS>
+__device__ __forceinline__ void mdr_tile(const NttArgs& a, const MdrEpi& e, u64* lds, double* twl,
+                                         const BlockPos bp) {
   const int N = a.N;
-  const BlockPos bp = block_pos(a.blocks_per_limb, a.nbatch);
   const int t = bp.limb;                                 // limb = prime index, t < level
   const int grp = bp.grp;
   const int item = bp.item >> 1, c = bp.item & 1;
@@ -631,9 +660,17 @@ k_ntt_row_mdr(NttArgs a, MdrEpi e) {
   const ulonglong2* tw = (const ulonglong2*)(a.tw + (size_t)t * N * 2);
   const u64* ni = a.ninv + 2 * t;
   const MdLayout lay(e.K, e.L);
-  MdrStore<(1 << LOGE)> store;
+  MdrStore<(1 << LOGE), OPS> store;
   store.u = e.u + (size_t)item * e.su + ((size_t)c * e.ne + t) * N;
-  store.d = e.d + (size_t)item * e.sd + ((size_t)c * e.nl + t) * N;
+  if (OPS == 0) {
+    store.d = e.d + (size_t)item * e.sd + ((size_t)c * e.nl + t) * N;
+  } else {
+    store.a0 = e.pa.p[item] + (size_t)t * N;
+    store.a1 = store.a0 + (size_t)e.nl * N;
+    store.b0 = e.pb.p[item] + (size_t)t * N;
+    store.b1 = store.b0 + (size_t)e.nl * N;
+  }
+  store.m = a.mods[t];
   store.out = e.out.p[item] + ((size_t)c * e.level + t) * N;
   store.q = q;
   store.pinv = e.md[lay.pinv(t)];
@@ -652,6 +689,24 @@ k_ntt_row_mdr(NttArgs a, MdrEpi e) {
   else
     ntt_body_dio<IntArith, LOGM, LOGE, SB, true, false>(IntArith(q), lds, src, store, tw, ni, N,
                                                          a.logR, first, a.logR == 0, true, 0u, a.logN);
+}
+
+template <int LOGM, int LOGE, int SB>
+__global__ void __launch_bounds__(SB * (1 << (LOGM - LOGE)))
+k_ntt_row_mdr(NttArgs a, MdrEpi e) {
+  constexpr int M = 1 << LOGM;
+  __shared__ u64 lds[SB * (M + 1)];
+  __shared__ double twl[RowTwShape<LOGM, SB, true>::size];
+  const BlockPos bp = block_pos(a.blocks_per_limb, a.nbatch);
+  const int c = bp.item & 1;
+  if constexpr (LOGM == kRowTwLogM) {   // products from operands: N = 2^16 only
+    if (!e.d) {
+      if (c == 0) mdr_tile<LOGM, LOGE, SB, 1>(a, e, lds, twl, bp);
+      else mdr_tile<LOGM, LOGE, SB, 2>(a, e, lds, twl, bp);
+      return;
+    }
+  }
+  mdr_tile<LOGM, LOGE, SB, 0>(a, e, lds, twl, bp);
 }
 
 template <int LOGM, int LOGE, int SB>
@@ -771,8 +826,9 @@ constexpr int kKsFusedDigits = 4;
 struct KsEpi {
   const u64* ext;    // [item][beta][ne][N], columns transformed
   size_t sext;
-  const u64* d;      // [item] input in NTT form (limbs 0..l), stride sd
-  size_t sd;
+  const u64* d;      // [item] input in NTT form (limbs 0..l), stride sd; null for
+  size_t sd;         //   a product: d = a1 b1 and (d0, d1) formed from the operands
+  PtrsIn pa, pb;     //   (item: [2][nl][N])
   const u64* key;    // [beta][2][nprimes][N]
   u64* u;            // [item][2][ne][N]
   size_t su;
@@ -877,7 +933,7 @@ __device__ __forceinline__ void ks_tile(const A ar, u64* lds, const NttArgs& a, 
   const ulonglong2* tw = (const ulonglong2*)(a.tw + (size_t)prime * NN * 2);
   const u64* ni = a.ninv + 2 * prime;
   const Mod m = a.mods[prime];
-  const bool prep = e.pd != nullptr && t == e.nl - 1;
+  const bool prep = (e.pd != nullptr || e.d == nullptr) && t == e.nl - 1;
   // the rows' twiddles serve every digit and item: formed once, up front,
   // where few registers are live
   if constexpr (TL) {
@@ -893,7 +949,15 @@ __device__ __forceinline__ void ks_tile(const A ar, u64* lds, const NttArgs& a, 
     for (int j = 0; j < e.beta; ++j) {
       st.kb = e.key + ((size_t)(2 * j) * e.nprimes + prime) * NN;
       st.ka = e.key + ((size_t)(2 * j + 1) * e.nprimes + prime) * NN;
-      if (j == own) {
+      if (j == own && e.d == nullptr) {
+        const u64* a1 = e.pa.p[item] + ((size_t)e.nl + t) * NN;
+        const u64* b1 = e.pb.p[item] + ((size_t)e.nl + t) * NN;
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+          st.prefetch(i, at[i]);
+          st.put(i, 0, mulm(a1[at[i]], b1[at[i]], m));
+        }
+      } else if (j == own) {
         const u64* dt = e.d + (size_t)item * e.sd + (size_t)t * NN;
 #pragma unroll
         for (int i = 0; i < E; ++i) {
@@ -914,9 +978,20 @@ __device__ __forceinline__ void ks_tile(const A ar, u64* lds, const NttArgs& a, 
     for (int i = 0; i < E; ++i) {
       u64 v0 = st.out0(i, m), v1 = st.out1(i, m);
       if (prep) {
-        const u64* dp = e.pd + (size_t)item * e.spd + (size_t)t * NN + at[i];
-        v0 = addm(v0, mul_shoup(dp[0], e.pmod, e.pmods, m.q), m.q);
-        v1 = addm(v1, mul_shoup(dp[(size_t)e.nl * NN], e.pmod, e.pmods, m.q), m.q);
+        u64 d0, d1;
+        if (e.d == nullptr) {
+          const u64* pa0 = e.pa.p[item] + (size_t)t * NN + at[i];
+          const u64* pb0 = e.pb.p[item] + (size_t)t * NN + at[i];
+          const u64 x0 = pa0[0], x1 = pa0[(size_t)e.nl * NN], y0 = pb0[0], y1 = pb0[(size_t)e.nl * NN];
+          d0 = mulm(x0, y0, m);
+          d1 = mul2_add(x0, y1, x1, y0, m);
+        } else {
+          const u64* dp = e.pd + (size_t)item * e.spd + (size_t)t * NN + at[i];
+          d0 = dp[0];
+          d1 = dp[(size_t)e.nl * NN];
+        }
+        v0 = addm(v0, mul_shoup(d0, e.pmod, e.pmods, m.q), m.q);
+        v1 = addm(v1, mul_shoup(d1, e.pmod, e.pmods, m.q), m.q);
       }
       u0[at[i]] = v0;
       u1[at[i]] = v1;
@@ -974,7 +1049,7 @@ struct ModUpLoad {
   const u64* cst;    // the target's kMaxAlpha constants, Montgomery form
   Mod m;
   int da, N;
-  __device__ __forceinline__ u64 get(size_t at) const {
+  __device__ __forceinline__ u64 get(int, size_t at) const {
     Acc30 acc;
 #pragma unroll
     for (int i = 0; i < MAXA; ++i) {
@@ -1048,6 +1123,40 @@ void run_col_modup(const NttArgs& base, const ModUpSrc& mu, int alpha, int nlimb
     hipLaunchKernelGGL((k_ntt_col_modup<LOGE, SB, 16>), grid, block, 0, st, a, mu, nlimbs);
   else
     PPST_THROW(ST_EINVAL, "digit size above 16 limbs");
+}
+
+// ---- inverse row pass of a product's d2 = a1 b1, formed on load
+template <int LOGE, int SB>
+__global__ void __launch_bounds__(SB * (1 << (8 - LOGE)))
+k_ntt_row_prod(NttArgs a, PtrsIn pa, PtrsIn pb) {
+  constexpr int LOGM = 8;
+  __shared__ u64 lds[SB * ((1 << LOGM) + 1)];
+  __shared__ double twl[RowTwShape<LOGM, SB, true>::size];
+  const BlockPos bp = block_pos(a.blocks_per_limb, a.nbatch);
+  const int N = a.N;
+  const int t = bp.limb;                                 // limb = prime index, t <= l
+  ProdLoad ld;
+  ld.a = pa.p[bp.item] + ((size_t)a.nq + t) * N;         // a1 (a.nq = l + 1 limbs)
+  ld.b = pb.p[bp.item] + ((size_t)a.nq + t) * N;         // b1
+  ld.m = a.mods[t];
+  const u64 q = ld.m.q;
+  PlainStore store{a.dst + (size_t)bp.item * a.dst_stride + (size_t)t * N};
+  const ulonglong2* tw = (const ulonglong2*)(a.tw + (size_t)t * N * 2);
+  const u64* ni = a.ninv + 2 * t;
+  const int first = bp.grp * SB;
+  const RowTw rt = row_tw<LOGM, SB, true>(a, twl, t, q);
+  if (rt.lds)
+    ntt_body_dio<FpArith, LOGM, LOGE, SB, true, true, RowTwShape<LOGM, SB, true>::on>(
+        FpArith(q), (double*)lds, nullptr, store, tw, ni, N, a.logR, first, true, false, 0u, a.logN,
+        rt, ld);
+  else if (q < kFpPrimeBound)
+    ntt_body_dio<FpArith, LOGM, LOGE, SB, true, true>(FpArith(q), (double*)lds, nullptr, store, tw,
+                                                       ni, N, a.logR, first, true, false, 0u,
+                                                       a.logN, RowTw{}, ld);
+  else
+    ntt_body_dio<IntArith, LOGM, LOGE, SB, true, true>(IntArith(q), lds, nullptr, store, tw, ni, N,
+                                                        a.logR, first, true, false, 0u, a.logN,
+                                                        RowTw{}, ld);
 }
 
 // ---- forward row pass that finishes a rescale
@@ -1367,7 +1476,15 @@ void ntt_fwd_mdr_final(const Shared& sh, u64* corr, int level, int nbatch, const
     const int nb = std::min(kPtrBatch, nbatch - b0);
     for (int i = 0; i < nb; ++i) e.out.p[i] = tail.out[b0 + i];
     e.u = tail.u + (size_t)b0 * tail.su;
-    e.d = tail.d + (size_t)b0 * tail.sd;
+    if (tail.d) {
+      e.d = tail.d + (size_t)b0 * tail.sd;
+    } else {
+      e.d = nullptr;
+      for (int i = 0; i < nb; ++i) {
+        e.pa.p[i] = tail.pa[b0 + i];
+        e.pb.p[i] = tail.pb[b0 + i];
+      }
+    }
     a.src = corr + (size_t)b0 * 2 * level * N;
     f(a, e, level, 2 * nb, st);
   }
@@ -1419,6 +1536,49 @@ bool ks_fused_ok(const Params& P, int level) {
   return enabled && P.logN == 16 && P.beta(level) <= kKsFusedDigits;
 }
 
+void ntt_inv_prod(const Shared& sh, const u64* const* pa, const u64* const* pb, u64* x, int level,
+                  int nbatch, const u64* ninv, hipStream_t st) {
+  const Params& P = sh.P;
+  if (nbatch <= 0) return;
+  if (P.logN != 16) PPST_THROW(ST_EINVAL, "the product's inverse transform needs N = 2^16");
+  const int nl = level + 1;
+  NttArgs a{};
+  a.mods = (const Mod*)sh.tab.mods.p;
+  set_tables(a, sh, true);
+  a.ninv = ninv ? ninv : sh.tab.ninv.p;
+  a.N = P.N;
+  a.logN = P.logN;
+  a.logR = 8;
+  a.nq = nl;
+  a.pofs = P.L + 1;
+  a.skip_lo = a.skip_hi = 1 << 30;
+  a.dalpha = 0;
+  a.dcount = 1;
+  a.dtotal = 0;
+  a.galois = 0;
+  a.batch_stride = a.dst_stride = (size_t)nl * P.N;
+  constexpr int LOGE = 2, SB = 4;
+  a.blocks_per_limb = (1 << a.logR) / SB;
+  for (int b0 = 0; b0 < nbatch; b0 += kPtrBatch) {
+    const int nb = std::min(kPtrBatch, nbatch - b0);
+    PtrsIn A, B;
+    for (int i = 0; i < nb; ++i) {
+      A.p[i] = pa[b0 + i];
+      B.p[i] = pb[b0 + i];
+    }
+    a.dst = x + (size_t)b0 * a.dst_stride;
+    a.nbatch = nb;
+    dim3 grid((unsigned)(a.blocks_per_limb * nl * nb));
+    hipLaunchKernelGGL((k_ntt_row_prod<LOGE, SB>), grid, dim3(SB * (1 << (8 - LOGE))), 0, st, a,
+                       A, B);
+  }
+  // the column pass of the plan, in place
+  a.src = x;
+  a.dst = x;
+  kCol16[sh.ntt_plan.v[1][0][ntt_bucket(nl * nbatch)]].inv(a, nl, nbatch, st);
+  HIP_CHECK(hipGetLastError());
+}
+
 void ntt_fwd_ks_fused(const Shared& sh, const KsTail& tail, int level, int nbatch, hipStream_t st) {
   const Params& P = sh.P;
   if (nbatch <= 0) return;
@@ -1461,6 +1621,13 @@ void ntt_fwd_ks_fused(const Shared& sh, const KsTail& tail, int level, int nbatc
   e.sext = (size_t)beta * ne * N;
   e.d = tail.d;
   e.sd = tail.sd;
+  if (!tail.d) {
+    if (!tail.pa || !tail.pb || nbatch > kPtrBatch) PPST_THROW(ST_EINVAL, "product operands missing");
+    for (int i = 0; i < nbatch; ++i) {
+      e.pa.p[i] = tail.pa[i];
+      e.pb.p[i] = tail.pb[i];
+    }
+  }
   e.key = tail.key;
   e.u = tail.u;
   e.su = 2 * (size_t)ne * N;
