@@ -648,6 +648,98 @@ struct MdrStore {
   }
 };
 
+// A product's item in one workgroup: both polynomials' row passes in turn,
+// the operands a0, a1, b0, b1 loaded once (with the first) for d0 and d1.
+template <int E>
+struct MdrOps {
+  u64 x0[E], x1[E], y0[E], y1[E];
+};
+
+template <int E, int C>
+struct MdrPairStore {
+  static constexpr bool kRaw = false;
+  MdrOps<E>* o;
+  const u64* u;
+  const u64* a0;
+  const u64* a1;
+  const u64* b0;
+  const u64* b1;
+  Mod m;
+  u64* out;
+  u64 q, pinv, pinvs, qlinv, qlinvs;
+  u64 pu[E];
+  __device__ __forceinline__ void prefetch(int i, size_t at) {
+    pu[i] = u[at];
+    if constexpr (C == 0) {
+      o->x0[i] = a0[at];
+      o->x1[i] = a1[at];
+      o->y0[i] = b0[at];
+      o->y1[i] = b1[at];
+    }
+  }
+  __device__ __forceinline__ void put(int i, size_t at, u64 corr) const {
+    u64 v = mul_shoup(pu[i], pinv, pinvs, q);
+    const u64 dv = C == 0 ? mulm(o->x0[i], o->y0[i], m)
+                          : mul2_add(o->x0[i], o->y1[i], o->x1[i], o->y0[i], m);
+    v = addm(v, dv, q);
+    v = addm(v, corr, q);
+    out[at] = mul_shoup(v, qlinv, qlinvs, q);
+  }
+};
+
+template <class A, int LOGM, int LOGE, int SB, bool TL, int C>
+__device__ __forceinline__ void mdr_pair_poly(const A ar, const NttArgs& a, const MdrEpi& e,
+                                              u64* lds, RowTw rt, MdrOps<(1 << LOGE)>* ops,
+                                              int t, int item, int first) {
+  const int N = a.N;
+  const MdLayout lay(e.K, e.L);
+  MdrPairStore<(1 << LOGE), C> st;
+  st.o = ops;
+  st.u = e.u + (size_t)item * e.su + ((size_t)C * e.ne + t) * N;
+  st.a0 = e.pa.p[item] + (size_t)t * N;
+  st.a1 = st.a0 + (size_t)e.nl * N;
+  st.b0 = e.pb.p[item] + (size_t)t * N;
+  st.b1 = st.b0 + (size_t)e.nl * N;
+  st.m = a.mods[t];
+  st.out = e.out.p[item] + ((size_t)C * e.level + t) * N;
+  st.q = st.m.q;
+  st.pinv = e.md[lay.pinv(t)];
+  st.pinvs = e.md[lay.pinv(t) + 1];
+  st.qlinv = e.rc[3 * t];
+  st.qlinvs = e.rc[3 * t + 1];
+  const u64* src = a.src + (size_t)(2 * item + C) * a.batch_stride + (size_t)t * N;
+  const ulonglong2* tw = (const ulonglong2*)(a.tw + (size_t)t * N * 2);
+  ntt_body_dio<A, LOGM, LOGE, SB, true, false, TL>(ar, (typename A::T*)lds, src, st, tw,
+                                                   a.ninv + 2 * t, N, a.logR, first, a.logR == 0,
+                                                   true, 0u, a.logN, rt);
+}
+
+template <class A, int LOGM, int LOGE, int SB, bool TL>
+__device__ __forceinline__ void mdr_pair_body(const A ar, const NttArgs& a, const MdrEpi& e,
+                                              u64* lds, RowTw rt, int t, int item, int first) {
+  MdrOps<(1 << LOGE)> ops;
+  mdr_pair_poly<A, LOGM, LOGE, SB, TL, 0>(ar, a, e, lds, rt, &ops, t, item, first);
+  __syncthreads();   // the second row pass reuses the LDS rows (and the formed twiddles)
+  rt.make = false;
+  mdr_pair_poly<A, LOGM, LOGE, SB, TL, 1>(ar, a, e, lds, rt, &ops, t, item, first);
+}
+
+template <int LOGM, int LOGE, int SB>
+__device__ __forceinline__ void mdr_pair_tile(const NttArgs& a, const MdrEpi& e, u64* lds,
+                                              double* twl, const BlockPos bp) {
+  const int t = bp.limb;                                 // limb = prime index, t < level
+  const u64 q = a.mods[t].q;
+  const int first = bp.grp * SB;
+  const RowTw rt = row_tw<LOGM, SB, true>(a, twl, t, q);
+  if (rt.lds)
+    mdr_pair_body<FpArith, LOGM, LOGE, SB, RowTwShape<LOGM, SB, true>::on>(FpArith(q), a, e, lds, rt,
+                                                                          t, bp.item, first);
+  else if (q < kFpPrimeBound)
+    mdr_pair_body<FpArith, LOGM, LOGE, SB, false>(FpArith(q), a, e, lds, rt, t, bp.item, first);
+  else
+    mdr_pair_body<IntArith, LOGM, LOGE, SB, false>(IntArith(q), a, e, lds, rt, t, bp.item, first);
+}
+
 template <int LOGM, int LOGE, int SB, int OPS>
 __device__ __forceinline__ void mdr_tile(const NttArgs& a, const MdrEpi& e, u64* lds, double* twl,
                                          const BlockPos bp) {
@@ -698,11 +790,9 @@ k_ntt_row_mdr(NttArgs a, MdrEpi e) {
   __shared__ u64 lds[SB * (M + 1)];
   __shared__ double twl[RowTwShape<LOGM, SB, true>::size];
   const BlockPos bp = block_pos(a.blocks_per_limb, a.nbatch);
-  const int c = bp.item & 1;
-  if constexpr (LOGM == kRowTwLogM) {   // products from operands: N = 2^16 only
-    if (!e.d) {
-      if (c == 0) mdr_tile<LOGM, LOGE, SB, 1>(a, e, lds, twl, bp);
-      else mdr_tile<LOGM, LOGE, SB, 2>(a, e, lds, twl, bp);
+  if constexpr (LOGM == kRowTwLogM) {   // products from operands (N = 2^16): items, not
+    if (!e.d) {                         // (item, polynomial) pairs
+      mdr_pair_tile<LOGM, LOGE, SB>(a, e, lds, twl, bp);
       return;
     }
   }
@@ -1486,7 +1576,7 @@ void ntt_fwd_mdr_final(const Shared& sh, u64* corr, int level, int nbatch, const
       }
     }
     a.src = corr + (size_t)b0 * 2 * level * N;
-    f(a, e, level, 2 * nb, st);
+    f(a, e, level, tail.d ? 2 * nb : nb, st);   // operand form: one workgroup per item
   }
   HIP_CHECK(hipGetLastError());
 }
