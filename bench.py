@@ -41,8 +41,8 @@ BFLY_PEAK_G = VALU_PEAK / OPS_PER_BFLY / 1e9
 # plain copy of known size.  The figure belongs to the NTT source it was taken
 # with (its SHA-256 below); for any other source the traffic is reported as
 # null.
-NTT_TRAFFIC = {"bytes": 55839019,
-               "source_sha256": "8c15f05bb2e06748a5608625453f61c6bcc28ed8ee97960f096689891ea59960"}
+NTT_TRAFFIC = {"bytes": 55833857,
+               "source_sha256": "fb44460fb80f91c6757d784c8954e48e1948861cdf6f307c38d6060e3f0b5f71"}
 # Algorithmic HBM bytes of the other key-switching kernels of one plain
 # product at level 24 (N = 2^16, K = 7, dnum = 3; a limb is 512 KiB): the key
 # inner product reads 3 digit limbs and 6 key limbs per extended limb (32)
@@ -53,7 +53,10 @@ NTT_TRAFFIC = {"bytes": 55839019,
 # digits' column pass reads the 25 scaled limbs and writes the 69 extension
 # limbs column-transformed.
 LIMB = 1 << 19
-KS_KERNELS = {"k_ks_inner_kernel<1>": ("hbm", 352 * LIMB), "k_ntt_row_ks<8, 2, 4>": ("hbm", 352 * LIMB),
+# (a product from its operands: the ModDown + rescale's last pass reads
+# corr, u, a0, a1, b0, b1 and writes the output, 2 x 24 limbs each but the
+# operands' 4 x 24, per item: 240 limbs)
+KS_KERNELS = {"k_ntt_row_mdr<8, 2, 4>": ("hbm", 240 * LIMB), "k_ks_inner_kernel<1>": ("hbm", 352 * LIMB), "k_ntt_row_ks<8, 2, 4>": ("hbm", 352 * LIMB),
               "k_ntt_col_modup<3, 16, 9>": ("alu", 94 * LIMB), "k_modup_kernel<9>": ("alu", 96 * LIMB),
               "k_mdr_corr_kernel<8>": ("alu", 64 * LIMB), "k_tensor_kernel": ("hbm", 175 * LIMB)}
 
