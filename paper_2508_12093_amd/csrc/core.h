@@ -265,6 +265,9 @@ struct Tables {
   std::map<int, std::shared_ptr<Buf>> modup_ninv;
   // ModDown constants (one table for all levels)
   Buf moddown;
+  // [nprimes][2] final factors of the inverse NTT before a ModDown's
+  // conversion: N^-1 Phat_k^-1 on special prime p_k, N^-1 elsewhere
+  Buf md_ninv;
   // host copy of (P mod q_i, Shoup companion), i = 0..L, for kernel arguments
   std::vector<u64> pmod_host;
   // rescale constants per level

@@ -389,7 +389,15 @@ void build_tables(Shared& sh) {
     for (int k = 0; k < K; ++k) md[lay.phatp(k, i)] = h_mulmod(md[lay.phat(k, i)], pinv, qi);
     md[lay.hpinv(i)] = h_mulmod(md[lay.hmod(i)], pinv, qi);
   }
+  std::vector<u64> mdn(ninv);   // N^-1 in the table format, special primes scaled
+  for (int k = 0; k < K; ++k) {
+    const int p = L + 1 + k;
+    const u64 pk = P.q[p], phi = md[lay.phinv(k)];
+    md[lay.hphinv(k)] = h_mulmod(md[lay.hmod(p)], phi, pk);
+    pair(h_mulmod(h_invmod((u64)N % pk, pk), phi, pk), pk, &mdn[2 * (size_t)p]);
+  }
   sh.tab.moddown = upload(pool, md);
+  sh.tab.md_ninv = upload(pool, mdn);
 
   // ModUp per (level, digit)
   for (int l = 0; l <= L; ++l) {
@@ -688,6 +696,7 @@ void ks_moddown_ptr(Context& cx, Buf& u, int level, int nbatch, const u64* const
     L.batch_stride = (size_t)ne * N;   // [batch][2][ne][N] is [2 nbatch][ne][N]
     L.nq = 0;
     L.pofs = P.L + 1;
+    L.ninv = sh.tab.md_ninv.p;         // the conversion's weights need z_k Phat_k^-1
     ntt(sh, L, true, cx.stream);
   }
   Buf conv = dev_buf(cx.pool, sc * nbatch);
@@ -743,6 +752,7 @@ void ks_moddown_rescale_into(Context& cx, u64* u, const u64* D, size_t sd, int l
     L.pofs = P.L + 1;
     L.skip_lo = 0;
     L.skip_hi = level;
+    L.ninv = sh.tab.md_ninv.p;         // N^-1 on q_l, N^-1 Phat_k^-1 on the special limbs
     ntt(sh, L, true, cx.stream);
   }
   k_mdr_corr(sh, u, corr, level, nbatch, su, sc, cx.stream);

@@ -432,7 +432,9 @@ struct ModDownArgs {
 constexpr int kModDownChunk = 8;   // output limbs per thread
 
 // w_k = (z_k + h) Phat_k^-1 mod p_k for the special limbs z of one polynomial
-// in coefficient form (w_k = 0 for k >= K), split for Acc30.
+// in coefficient form (w_k = 0 for k >= K), split for Acc30.  The inverse
+// NTT that produced the limbs ended with N^-1 Phat_k^-1 (md_ninv), so they
+// hold z_k Phat_k^-1 and a weight is that plus h Phat_k^-1.
 template <int MAXK>
 __device__ __forceinline__ void moddown_weights(const u64* __restrict__ u, int nl, int K, int L,
                                                 int N, int k, const Mod* __restrict__ mods,
@@ -443,10 +445,8 @@ __device__ __forceinline__ void moddown_weights(const u64* __restrict__ u, int n
   for (int i = 0; i < MAXK; ++i) zv[i] = u[(size_t)(nl + min(i, K - 1)) * N + k];
 #pragma unroll
   for (int i = 0; i < MAXK; ++i) {
-    const int p = L + 1 + min(i, K - 1);
-    const u64 q = mods[p].q;
-    const u64 z = addm(zv[i], md[lay.hmod(p)], q);
-    const u64 v = mul_shoup(z, md[lay.phinv(i)], md[lay.phinv(i) + 1], q);
+    const int kk = min(i, K - 1);
+    const u64 v = addm(zv[i], md[lay.hphinv(kk)], mods[L + 1 + kk].q);
     w[i] = Split30(i < K ? v : 0);
   }
 }

@@ -24,6 +24,10 @@ constexpr int kMaxSpecial = 8;    // special primes
 //   [L+1][kMaxSpecial]    Phat_k P^-1 2^64 mod q_i (Montgomery form, for the
 //                         fused ModDown + rescale: the sum comes out times P^-1)
 //   [L+1]                 h P^-1 mod q_i
+//   [kMaxSpecial]         h Phat_k^-1 mod p_k (the ModDown weights' offset: the
+//                         inverse NTT before the conversion ends with
+//                         N^-1 Phat_k^-1 on the special limbs, so a weight is
+//                         its output plus this)
 struct MdLayout {
   int K, L;
   __host__ __device__ MdLayout(int k, int l) : K(k), L(l) {}
@@ -34,7 +38,8 @@ struct MdLayout {
   __host__ __device__ int pmod(int i) const { return hmod(L + 1 + K) + 2 * i; }
   __host__ __device__ int phatp(int k, int i) const { return pmod(L + 1) + i * kMaxSpecial + k; }
   __host__ __device__ int hpinv(int i) const { return phatp(0, L + 1) + i; }
-  __host__ __device__ int size() const { return hpinv(L + 1); }
+  __host__ __device__ int hphinv(int k) const { return hpinv(L + 1) + k; }
+  __host__ __device__ int size() const { return hphinv(kMaxSpecial); }
 };
 
 // ModUp table of one level: for each digit j, [kMaxAlpha][2] (Qhat_i^-1 mod
