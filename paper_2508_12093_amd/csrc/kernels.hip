@@ -876,6 +876,8 @@ void k_modup(const Shared& sh, const u64* x, u64* ext, int level, int nbatch, si
   g.z = nbatch;
   if (P.alpha <= 4)
     hipLaunchKernelGGL(k_modup_kernel<4>, g, dim3(kBlock), 0, st, x, ext, M(sh), tab, a);
+  else if (P.alpha == 7)   // the bootstrappable presets' digits: no padding terms
+    hipLaunchKernelGGL(k_modup_kernel<7>, g, dim3(kBlock), 0, st, x, ext, M(sh), tab, a);
   else if (P.alpha <= 9)
     hipLaunchKernelGGL(k_modup_kernel<9>, g, dim3(kBlock), 0, st, x, ext, M(sh), tab, a);
   else if (P.alpha <= kMaxAlpha)

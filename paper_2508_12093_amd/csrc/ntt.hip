@@ -1207,6 +1207,8 @@ void run_col_modup(const NttArgs& base, const ModUpSrc& mu, int alpha, int nlimb
   dim3 block(SB * (1 << (8 - LOGE)));
   if (alpha <= 4)
     hipLaunchKernelGGL((k_ntt_col_modup<LOGE, SB, 4>), grid, block, 0, st, a, mu, nlimbs);
+  else if (alpha == 7)
+    hipLaunchKernelGGL((k_ntt_col_modup<LOGE, SB, 7>), grid, block, 0, st, a, mu, nlimbs);
   else if (alpha <= 9)
     hipLaunchKernelGGL((k_ntt_col_modup<LOGE, SB, 9>), grid, block, 0, st, a, mu, nlimbs);
   else if (alpha <= kMaxAlpha)
