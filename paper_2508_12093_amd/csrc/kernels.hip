@@ -173,9 +173,10 @@ k_modup_kernel(const u64* __restrict__ xin, u64* __restrict__ extout,
   Split30 z[MAXA];
 #pragma unroll
   for (int i = 0; i < MAXA; ++i) z[i] = Split30(i < da ? xv[i] : 0);
+#pragma unroll
   for (int c = 0; c < kModUpChunk; ++c) {
     const int u = tfirst + c;
-    if (u >= ntarget) break;
+    if (u >= ntarget) continue;
     const int t = u < lo ? u : u + da;
     const int p = t < a.nl ? t : a.pofs + (t - a.nl);
     const u64* qhat = cst + 2 * kMaxAlpha + (size_t)t * kMaxAlpha;
@@ -469,9 +470,10 @@ k_moddown_conv_kernel(const u64* __restrict__ uin, u64* __restrict__ convout,
   const MdLayout lay(a.K, a.L);
   Split30 w[MAXK];
   moddown_weights<MAXK>(u, a.nl, a.K, a.L, N, k, mods, md, w);
+#pragma unroll
   for (int cc = 0; cc < kModDownChunk; ++cc) {
     const int i = ifirst + cc;
-    if (i >= a.nl) break;
+    if (i >= a.nl) continue;
     const Mod m = mods[i];
     Acc30 acc;
 #pragma unroll
@@ -514,9 +516,12 @@ k_mdr_corr_kernel(const u64* __restrict__ u, u64* __restrict__ corr, const Mod* 
     cl = mul_shoup(v, md[lay.pinv(level)], md[lay.pinv(level) + 1], ml.q);
   }
   const bool neg = cl > (ml.q >> 1);
+  // unrolled with a uniform guard (no early exit), so every target's
+  // constants load up front
+#pragma unroll
   for (int ii = 0; ii < kMdrChunk; ++ii) {
     const int i = ifirst + ii;
-    if (i >= level) break;
+    if (i >= level) continue;
     const Mod m = mods[i];
     Acc30 acc;
 #pragma unroll
