@@ -41,8 +41,8 @@ BFLY_PEAK_G = VALU_PEAK / OPS_PER_BFLY / 1e9
 # plain copy of known size.  The figure belongs to the NTT source it was taken
 # with (its SHA-256 below); for any other source the traffic is reported as
 # null.
-NTT_TRAFFIC = {"bytes": 55833857,
-               "source_sha256": "fb44460fb80f91c6757d784c8954e48e1948861cdf6f307c38d6060e3f0b5f71"}
+NTT_TRAFFIC = {"bytes": 55822593,
+               "source_sha256": "e460ddb7a9b399a3fd076e2ec4177c19bd889bb00934f636820aabda21d804f8"}
 # Algorithmic HBM bytes of the other key-switching kernels of one plain
 # product at level 24 (N = 2^16, K = 7, dnum = 3; a limb is 512 KiB): the key
 # inner product reads 3 digit limbs and 6 key limbs per extended limb (32)
