@@ -71,6 +71,9 @@ def parse():
     ap.add_argument("--cpu-runs", type=int, default=5,
                     help="repetitions per operation of the oracle timed on the host")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-pearson", action="store_true",
+                    help="skip timing the oracle's encrypted Pearson on the config-2 columns "
+                         "(about 20 s at 16 host threads, plus its key generation)")
     ap.add_argument("--quick", action="store_true", help="short run for profiling")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the roofline kernel and a copy of known size")
@@ -359,7 +362,7 @@ def main():
     if boot is not None:
         out["bootstrap"] = boot
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_runs)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_runs, not args.no_cpu_pearson)
     print(json.dumps(out), flush=True)
 
 
@@ -950,12 +953,13 @@ def _cpu_model():
     return "unknown"
 
 
-def cpu_baseline(runs: int):
+def cpu_baseline(runs: int, pearson: bool = False):
     """The CPU reference (the plain C oracle, built on this host at -O2
     -march=native) timed on the host at N = 2^16, level 24: medians of `runs`
     repetitions of a 25-limb NTT, an HMult+relin+rescale and a rotation, at
     one OpenMP thread and at every core of the process's CPU share, each in a
-    child process (oracle/timing.py)."""
+    child process (oracle/timing.py).  With `pearson`, also one encrypted
+    Pearson on the config-2 columns at every core, beside FP64 NumPy."""
     import subprocess
     import tempfile
 
@@ -976,6 +980,21 @@ def cpu_baseline(runs: int):
         log("oracle at %d thread(s): NTT(25 limbs) %.1f ms, HMult %.0f ms, rotation %.0f ms" % (
             threads, legs[threads]["ntt25_ms"], legs[threads]["hmult_ms"], legs[threads]["rotation_ms"]))
     top, one = legs[cores], legs[1]
+    extra = {}
+    if pearson:
+        import numpy as np
+
+        from paper_2508_12093_amd import synth
+        cols = os.path.join(tmp, "c2_columns.npy")
+        np.save(cols, np.stack(synth.binary_cost_pair(0)))
+        env = dict(os.environ, OMP_NUM_THREADS=str(cores), PPST_ORACLE_SO=so)
+        r = subprocess.run([sys.executable, os.path.join(ROOT, "oracle", "timing.py"), "--pearson", cols],
+                           env=env, capture_output=True, text=True, timeout=900)
+        if r.returncode != 0:
+            raise RuntimeError("oracle Pearson timing failed:\n" + r.stderr[-2000:])
+        extra["pearson"] = json.loads(r.stdout.strip().splitlines()[-1])
+        log("oracle Pearson at %d threads: %.1f s (FP64 NumPy %.0f us)" % (
+            cores, extra["pearson"]["pearson_s"], extra["pearson"]["fp64_numpy_pearson_us"]))
     return {"value": top["hmult_per_s"], "unit": "HMult+relin/s", "cores": cores, "kind": "oracle",
             "sample": "median of %d runs each of a 25-limb NTT, an HMult+relin+rescale and a rotation "
                       "at N=2^16, level 24 (%.1f s timed at %d threads, %.1f s at 1)" % (
@@ -985,7 +1004,7 @@ def cpu_baseline(runs: int):
             "rotations_per_s": top["rotations_per_s"],
             "single_thread": {"hmult_per_s": one["hmult_per_s"], "rotations_per_s": one["rotations_per_s"],
                               "per_op_ms": {"ntt25": one["ntt25_ms"], "hmult": one["hmult_ms"],
-                                            "rotation": one["rotation_ms"]}}}
+                                            "rotation": one["rotation_ms"]}}, **extra}
 
 
 if __name__ == "__main__":
