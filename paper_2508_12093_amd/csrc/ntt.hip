@@ -1089,23 +1089,40 @@ __device__ __forceinline__ void ks_tile(const A ar, u64* lds, const NttArgs& a, 
   }
 }
 
-// grid: (item group fastest, then row group, then limb)
-// At most 168 VGPRs for three waves per SIMD (it spills 36 bytes per lane):
-// faster than two waves without spills, the kernel being latency-bound.
+// Workgroups run on XCD (workgroup index) mod 8, each XCD with its own L2.
+constexpr unsigned kXcds = 8;
+
+// grid: one workgroup per (tile = row group + groups * limb, item group).
+// The item groups of a tile read the same key rows; they take consecutive
+// slots (workgroup index / 8) of one XCD, so that they run together and
+// share those rows in its L2 (a round-robin order would fetch the key once
+// per item from HBM).  Grids whose tile count is not a multiple of 8 keep
+// the item group fastest.
+// At most 168 VGPRs for three waves per SIMD: faster than two waves, the
+// kernel being latency-bound.
 template <int LOGM, int LOGE, int SB>
 __global__ void __launch_bounds__(SB * (1 << (LOGM - LOGE)), 3)
 k_ntt_row_ks(NttArgs a, KsEpi e) {
   constexpr int M = 1 << LOGM;
   __shared__ u64 lds[SB * (M + 1)];
   __shared__ double twl[RowTwShape<LOGM, SB, true>::size];
-  const int groups = (1 << a.logR) / SB;
-  const int nig = (e.nbatch + e.items - 1) / e.items;
+  const unsigned groups = (1u << a.logR) / SB;
+  const unsigned nig = (unsigned)((e.nbatch + e.items - 1) / e.items);
+  const unsigned tiles = groups * (unsigned)e.ne;
   const unsigned b = blockIdx.x;
-  const int ig = (int)(b % (unsigned)nig);
-  const int rg = (int)((b / (unsigned)nig) % (unsigned)groups);
-  const int t = (int)(b / ((unsigned)nig * (unsigned)groups));
+  unsigned ig, tile;
+  if (nig > 1 && tiles % kXcds == 0) {
+    const unsigned slot = b / kXcds;
+    ig = slot % nig;
+    tile = (slot / nig) * kXcds + b % kXcds;
+  } else {
+    ig = b % nig;
+    tile = b / nig;
+  }
+  const int rg = (int)(tile % groups);
+  const int t = (int)(tile / groups);
   const int prime = t < e.nl ? t : e.pofs + (t - e.nl);
-  const int item0 = ig * e.items, item1 = min(item0 + e.items, e.nbatch);
+  const int item0 = (int)ig * e.items, item1 = min(item0 + e.items, e.nbatch);
   const u64 q = a.mods[prime].q;
   const RowTw rt = row_tw<LOGM, SB, true>(a, twl, prime, q);
   if (rt.lds)
@@ -1156,7 +1173,6 @@ struct ModUpLoad {
 // workgroup w runs on XCD w mod 8; the targets of one tile take consecutive
 // slots w / 8 of one XCD and re-read the tile's digit limbs from that XCD's
 // L2.  The grid is padded to whole tiles per XCD (extra workgroups exit).
-constexpr unsigned kXcds = 8;
 template <int LOGE, int SB, int MAXA>
 __global__ void __launch_bounds__(SB * (1 << (8 - LOGE)))
 k_ntt_col_modup(NttArgs a, ModUpSrc mu, int ntargets) {
