@@ -158,6 +158,26 @@ struct FpArith {
   }
 };
 
+// Orders the LDS accesses of one wavefront's lanes (which run in lockstep):
+// all the barrier a row pass's exchange needs when each sub-problem (row)
+// lies within one wave, so that the waves of a workgroup never wait for
+// each other.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+// whether the rows of a row pass with TPS threads per row are wave-private
+template <int TPS>
+struct WaveRows {
+  static constexpr bool on = TPS <= 64 && 64 % TPS == 0;
+};
+template <bool WAVE>
+__device__ __forceinline__ void exchange_sync() {
+  if constexpr (WAVE) wave_sync();
+  else __syncthreads();
+}
+
 // Row twiddles formed in LDS.  Sub-problem r of a row pass (N = R M with
 // R = M = 2^8) reads table entry (R + r) 2^s + j at its local stage s
 // (j < 2^s); bit reversal maps the two fields separately, so that entry is
@@ -489,7 +509,7 @@ __device__ __forceinline__ void ntt_body_dio(const A ar, typename A::T* lds, con
       for (int g = 0; g < G; ++g)
 #pragma unroll
         for (int k = 0; k < GS; ++k) my[e0[g] + k * si] = x[g * GS + k];
-      __syncthreads();
+      exchange_sync<ROWS && WaveRows<TPS>::on>();
     }
   }
 }
@@ -719,7 +739,9 @@ __device__ __forceinline__ void mdr_pair_body(const A ar, const NttArgs& a, cons
                                               u64* lds, RowTw rt, int t, int item, int first) {
   MdrOps<(1 << LOGE)> ops;
   mdr_pair_poly<A, LOGM, LOGE, SB, TL, 0>(ar, a, e, lds, rt, &ops, t, item, first);
-  __syncthreads();   // the second row pass reuses the LDS rows (and the formed twiddles)
+  // the second row pass reuses the LDS rows (the twiddles, formed behind a
+  // workgroup barrier in the first, are only read)
+  exchange_sync<WaveRows<(1 << (LOGM - LOGE))>::on>();
   rt.make = false;
   mdr_pair_poly<A, LOGM, LOGE, SB, TL, 1>(ar, a, e, lds, rt, &ops, t, item, first);
 }
@@ -1059,7 +1081,7 @@ __device__ __forceinline__ void ks_tile(const A ar, u64* lds, const NttArgs& a, 
         ntt_body_dio<A, LOGM, LOGE, SB, true, false, TL>(ar, (typename A::T*)lds, src, st, tw, ni, N,
                                                          a.logR, first, a.logR == 0, true, 0u,
                                                          a.logN, rt);
-        __syncthreads();   // the next digit's exchanges reuse the LDS rows
+        exchange_sync<WaveRows<TPS>::on>();   // the next digit's exchanges reuse the LDS rows
       }
     }
     u64* u0 = e.u + (size_t)item * e.su + (size_t)t * NN;
