@@ -22,6 +22,7 @@
 
 #include <cstdlib>
 #include <cstring>
+#include <type_traits>
 #include "tables.h"
 
 namespace ppst {
@@ -369,7 +370,8 @@ __device__ __forceinline__ void ntt_body(const A ar, typename A::T* lds, const u
 // custom load (kCustom) computes each element from its index instead.
 struct PlainLoad {
   static constexpr bool kCustom = false;
-  __device__ __forceinline__ u64 get(int, size_t) const { return 0; }
+  template <class A>
+  __device__ __forceinline__ typename A::T get_t(const A& ar, int, size_t) const { return ar.in(0); }
 };
 
 // A product's d2 = a1 b1 mod q, formed where the inverse transform of the
@@ -380,7 +382,17 @@ struct ProdLoad {
   const u64* a;
   const u64* b;
   Mod m;
-  __device__ __forceinline__ u64 get(int, size_t at) const { return mulm(a[at], b[at], m); }
+  // FP64 primes: the exact FP64 product, signed (|.| < 0.57 q), which the
+  // inverse pass centres like any input
+  template <class A>
+  __device__ __forceinline__ typename A::T get_t(const A& ar, int, size_t at) const {
+    if constexpr (std::is_same<A, FpArith>::value) {
+      const double x = ar.in(a[at]), y = ar.in(b[at]);
+      return ar.mulmod(x, y, y * ar.qinv);
+    } else {
+      return ar.in(mulm(a[at], b[at], m));
+    }
+  }
 };
 
 struct PlainStore {
@@ -438,7 +450,7 @@ __device__ __forceinline__ void ntt_body_dio(const A ar, typename A::T* lds, con
           const int e = e0[g] + k * si;
           size_t at = ROWS ? rowbase + e : (size_t)e * C + col;
           if constexpr (Load::kCustom) {
-            x[g * GS + k] = ar.in(ld.get(g * GS + k, at));
+            x[g * GS + k] = ld.get_t(ar, g * GS + k, at);
           } else {
             if (ROWS && INV && galois != 0) at = galois_src((uint32_t)at, galois, logN);
             x[g * GS + k] = firstp ? ar.in(src[at]) : ar.in_mid(src[at]);
@@ -669,16 +681,21 @@ struct MdrStore {
 };
 
 // A product's item in one workgroup: both polynomials' row passes in turn,
-// the operands a0, a1, b0, b1 loaded once (with the first) for d0 and d1.
-template <int E>
+// the operands a0, a1, b0, b1 loaded once (with the first) for d0 and d1,
+// kept in the arithmetic's own type.
+template <int E, class T>
 struct MdrOps {
-  u64 x0[E], x1[E], y0[E], y1[E];
+  T x0[E], x1[E], y0[E], y1[E];
 };
 
+template <class A, int E, int C>
+struct MdrPairStore;
+
+// 60-bit primes: Shoup and 128-bit products
 template <int E, int C>
-struct MdrPairStore {
+struct MdrPairStore<IntArith, E, C> {
   static constexpr bool kRaw = false;
-  MdrOps<E>* o;
+  MdrOps<E, u64>* o;
   const u64* u;
   const u64* a0;
   const u64* a1;
@@ -705,15 +722,68 @@ struct MdrPairStore {
     v = addm(v, corr, q);
     out[at] = mul_shoup(v, qlinv, qlinvs, q);
   }
+  __device__ __forceinline__ void init(const IntArith&) {}
+};
+
+// FP64 primes: every product exact in FP64 (FpArith::mulmod), on the
+// transform's unreduced output (|corr| < 10 q): u P^-1 and each operand
+// product land in (-0.57 q, 0.57 q), so the sum s stays below 12 q < 2^47.6
+// and the last product by q_l^-1 (quotient estimate at most 0.07 off) in
+// (-0.57 q, 0.57 q); one conditional addition of q makes it canonical.
+template <int E, int C>
+struct MdrPairStore<FpArith, E, C> {
+  static constexpr bool kRaw = true;
+  MdrOps<E, double>* o;
+  const u64* u;
+  const u64* a0;
+  const u64* a1;
+  const u64* b0;
+  const u64* b1;
+  Mod m;
+  u64* out;
+  u64 q, pinv, pinvs, qlinv, qlinvs;
+  FpArith ar{1};
+  double pinvd, pinvq, qlinvd, qlinvq;
+  u64 pu[E];
+  __device__ __forceinline__ void init(const FpArith& a) {
+    ar = a;
+    pinvd = (double)pinv;
+    pinvq = pinvd * ar.qinv;
+    qlinvd = (double)qlinv;
+    qlinvq = qlinvd * ar.qinv;
+  }
+  __device__ __forceinline__ void prefetch(int i, size_t at) {
+    pu[i] = u[at];
+    if constexpr (C == 0) {
+      o->x0[i] = ar.in(a0[at]);
+      o->x1[i] = ar.in(a1[at]);
+      o->y0[i] = ar.in(b0[at]);
+      o->y1[i] = ar.in(b1[at]);
+    }
+  }
+  __device__ __forceinline__ void put_raw(int i, size_t at, double corr) const {
+    const double v = ar.mulmod(ar.in(pu[i]), pinvd, pinvq);
+    double dv;
+    if constexpr (C == 0) {
+      dv = ar.mulmod(o->x0[i], o->y0[i], o->y0[i] * ar.qinv);
+    } else {
+      dv = ar.mulmod(o->x0[i], o->y1[i], o->y1[i] * ar.qinv) +
+           ar.mulmod(o->x1[i], o->y0[i], o->y0[i] * ar.qinv);
+    }
+    double r = ar.mulmod(v + dv + corr, qlinvd, qlinvq);
+    r = r < 0.0 ? r + ar.q : r;
+    out[at] = (u64)r;
+  }
 };
 
 template <class A, int LOGM, int LOGE, int SB, bool TL, int C>
 __device__ __forceinline__ void mdr_pair_poly(const A ar, const NttArgs& a, const MdrEpi& e,
-                                              u64* lds, RowTw rt, MdrOps<(1 << LOGE)>* ops,
+                                              u64* lds, RowTw rt,
+                                              MdrOps<(1 << LOGE), typename A::T>* ops,
                                               int t, int item, int first) {
   const int N = a.N;
   const MdLayout lay(e.K, e.L);
-  MdrPairStore<(1 << LOGE), C> st;
+  MdrPairStore<A, (1 << LOGE), C> st;
   st.o = ops;
   st.u = e.u + (size_t)item * e.su + ((size_t)C * e.ne + t) * N;
   st.a0 = e.pa.p[item] + (size_t)t * N;
@@ -727,6 +797,7 @@ __device__ __forceinline__ void mdr_pair_poly(const A ar, const NttArgs& a, cons
   st.pinvs = e.md[lay.pinv(t) + 1];
   st.qlinv = e.rc[3 * t];
   st.qlinvs = e.rc[3 * t + 1];
+  st.init(ar);
   const u64* src = a.src + (size_t)(2 * item + C) * a.batch_stride + (size_t)t * N;
   const ulonglong2* tw = (const ulonglong2*)(a.tw + (size_t)t * N * 2);
   ntt_body_dio<A, LOGM, LOGE, SB, true, false, TL>(ar, (typename A::T*)lds, src, st, tw,
@@ -737,7 +808,7 @@ __device__ __forceinline__ void mdr_pair_poly(const A ar, const NttArgs& a, cons
 template <class A, int LOGM, int LOGE, int SB, bool TL>
 __device__ __forceinline__ void mdr_pair_body(const A ar, const NttArgs& a, const MdrEpi& e,
                                               u64* lds, RowTw rt, int t, int item, int first) {
-  MdrOps<(1 << LOGE)> ops;
+  MdrOps<(1 << LOGE), typename A::T> ops;
   mdr_pair_poly<A, LOGM, LOGE, SB, TL, 0>(ar, a, e, lds, rt, &ops, t, item, first);
   // the second row pass reuses the LDS rows (the twiddles, formed behind a
   // workgroup barrier in the first, are only read)
@@ -1067,7 +1138,13 @@ __device__ __forceinline__ void ks_tile(const A ar, u64* lds, const NttArgs& a, 
 #pragma unroll
         for (int i = 0; i < E; ++i) {
           st.prefetch(i, at[i]);
-          st.put(i, 0, mulm(a1[at[i]], b1[at[i]], m));
+          if constexpr (std::is_same<A, FpArith>::value) {
+            // exact FP64 product (|.| < 0.57 q), as the store takes the transform's output
+            const double x = ar.in(a1[at[i]]), y = ar.in(b1[at[i]]);
+            st.put_raw(i, 0, ar.mulmod(x, y, y * ar.qinv));
+          } else {
+            st.put(i, 0, mulm(a1[at[i]], b1[at[i]], m));
+          }
         }
       } else if (j == own) {
         const u64* dt = e.d + (size_t)item * e.sd + (size_t)t * NN;
@@ -1187,6 +1264,10 @@ struct ModUpLoad {
       if ((i & 7) == 7) acc.fold();
     }
     return acc.redc(m);
+  }
+  template <class A>
+  __device__ __forceinline__ typename A::T get_t(const A& ar, int i, size_t at) const {
+    return ar.in(get(i, at));
   }
 };
 

@@ -157,3 +157,27 @@ def test_fp64_product_with_formed_twiddles():
         exact = int(y) * int(w) / int(q)
         assert abs(exact - y * ws) < 0.032
     assert worst <= 0.532
+
+
+def test_fp64_moddown_store_bounds():
+    """The fused ModDown row pass on an FP64 prime sums u P^-1, the operand
+    products (each an exact FP64 product of canonical residues) and the
+    transform's unreduced output (below 10 q) into s, |s| < 12 q, and takes
+    s q_l^-1 with one more exact product: the quotient estimate stays within
+    0.07 of s w / q, so the result is exact and below 0.57 q in magnitude
+    and one conditional addition of q makes it canonical."""
+    rng = random.Random(21)
+    for q in (float((1 << 40) - 87), float((1 << 44) - 17)):
+        qinv = 1.0 / q
+        worst = 0.0
+        for _ in range(20000):
+            w = float(rng.randrange(int(q)))
+            ws = w * qinv
+            s = float(rng.randrange(-12 * int(q) + 1, 12 * int(q)))
+            r, _ = fp_mulmod(s, w, ws, q)
+            assert (int(r) - int(s) * int(w)) % int(q) == 0
+            assert abs(int(s) * int(w) / int(q) - s * ws) < 0.07
+            worst = max(worst, abs(r) / q)
+            c = r + q if r < 0 else r
+            assert 0 <= c < q and int(c) == int(s) * int(w) % int(q)
+        assert worst < 0.57
