@@ -108,6 +108,12 @@ __device__ __forceinline__ u64 reduce64(u64 x, const Mod& m) {
   return csub(r, m.q);
 }
 
+// x < bound reduced mod q: one conditional subtraction where bound <= 2 q
+// (the test is the same for every lane of a limb), else a Barrett step
+__device__ __forceinline__ u64 reduce_below(u64 x, u64 bound, const Mod& m) {
+  return bound <= 2 * m.q ? csub(x, m.q) : reduce64(x, m);
+}
+
 // a0 b1 + a1 b0 mod q (the tensor's middle term; below 2 q^2 < 2^124)
 __device__ __forceinline__ u64 mul2_add(u64 a0, u64 b1, u64 a1, u64 b0, const Mod& m) {
   Acc acc;

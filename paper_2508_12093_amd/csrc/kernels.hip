@@ -528,7 +528,7 @@ k_mdr_corr_kernel(const u64* __restrict__ u, u64* __restrict__ corr, const Mod* 
     for (int j = 0; j < MAXK; ++j) acc.mac(w[j], Split30(md[lay.phatp(j, i)]));
     // (h - conv) P^-1 with P^-1 folded into the constants
     u64 v = subm(md[lay.hpinv(i)], acc.redc(m), m.q);
-    u64 t = reduce64(cl, m);
+    u64 t = reduce_below(cl, ml.q, m);
     if (neg) t = subm(t, rc[3 * i + 2], m.q);       // t = c_l - q_l when c_l > q_l / 2
     cc[(size_t)i * N + k] = subm(v, t, m.q);
   }
@@ -548,7 +548,7 @@ __global__ void k_rescale_conv_kernel(const u64* __restrict__ top, u64* tmp, con
   u64 x = top[c * ts + k];
   if (mulk) x = mul_shoup(x, kl, klp, ql);
   const Mod m = mods[i];
-  u64 v = reduce64(x, m);
+  u64 v = reduce_below(x, ql, m);
   if (x > (ql >> 1)) v = subm(v, rc[3 * i + 2], m.q);   // centred: x - q_l
   tmp[((size_t)c * level << logN) + r] = v;
 }
