@@ -774,7 +774,7 @@ def measure_ntt(ctx, stream, reps: int, variants=None):
 
     Algorithmic work per launch pair: 25 (N/2) log2 N butterflies and
     25 MiB of HBM traffic (one read and one write of each 512 KiB limb).
-    Floors: 13 FP64 VALU operations per butterfly at 39.3 T/s, and 25 MiB at
+    Floors: 8 FP64 VALU operations per butterfly at 39.3 T/s, and 25 MiB at
     8 TB/s; the larger floor names the bound."""
     import numpy as np
     import torch
