@@ -88,13 +88,13 @@ struct Acc30 {
   // factors (constants stored as c 2^64 mod q) are below q.  With
   // mm = lo (-q^-1) mod 2^64, x + mm q is a multiple of 2^64 whose low word
   // carries exactly when lo != 0, and (x + mm q) / 2^64 < 2q.
+  // After a fold the fields a0, a1 < 2^30 and a2 no longer overlap, so the
+  // 128-bit sum's words are plain shifts and ORs, with no carries.
   __device__ __forceinline__ u64 redc(const Mod& m) const {
-    const u64 t1 = a1 << 30, t2 = a2 << 60;
-    u64 lo = a0 + t1;
-    u64 c = lo < t1;
-    lo += t2;
-    c += lo < t2;
-    const u64 hi = (a1 >> 34) + (a2 >> 4) + c;
+    Acc30 f = *this;
+    f.fold();
+    const u64 lo = f.a0 | (f.a1 << 30) | (f.a2 << 60);
+    const u64 hi = f.a2 >> 4;
     const u64 mm = lo * m.mneg;
     return csub(hi + mulhi(mm, m.q) + (lo != 0), m.q);
   }

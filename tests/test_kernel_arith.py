@@ -76,8 +76,8 @@ def test_row_twiddle_product_matches_the_table():
 
 def acc30_redc(zs, cs, q):
     """The device's Acc30 sum of z_i c_i in 30-bit halves (a fold after
-    every 8 terms), its 128-bit combination and Montgomery's REDC with
-    mneg = -q^-1 mod 2^64."""
+    every 8 terms), its 128-bit words after a last fold and Montgomery's
+    REDC with mneg = -q^-1 mod 2^64."""
     m64 = (1 << 64) - 1
     mask = (1 << 30) - 1
     a0 = a1 = a2 = 0
@@ -92,12 +92,14 @@ def acc30_redc(zs, cs, q):
             a0 &= mask
             a2 += a1 >> 30
             a1 &= mask
-    t1, t2 = (a1 << 30) & m64, (a2 << 60) & m64
-    lo = (a0 + t1) & m64
-    c = int(lo < t1)
-    lo2 = (lo + t2) & m64
-    c += int(lo2 < t2)
-    hi = (a1 >> 34) + (a2 >> 4) + c
+    # REDC's final fold: the three fields then occupy disjoint bits
+    a1 += a0 >> 30
+    a0 &= mask
+    a2 += a1 >> 30
+    a1 &= mask
+    assert a2 < 1 << 64
+    lo2 = (a0 | (a1 << 30) | (a2 << 60)) & m64
+    hi = a2 >> 4
     assert (hi << 64) + lo2 == sum(z * c for z, c in zip(zs, cs))
     mneg = (-pow(q, -1, 1 << 64)) % (1 << 64)
     mm = (lo2 * mneg) & m64
