@@ -75,13 +75,9 @@ struct Acc30 {
   }
   // the sum a0 + a1 2^30 + a2 2^60 (below 2^124 for up to 16 terms) mod q
   __device__ __forceinline__ u64 reduce(const Mod& m) const {
-    const u64 t1 = a1 << 30, t2 = a2 << 60;
-    u64 lo = a0 + t1;
-    u64 c = lo < t1;
-    lo += t2;
-    c += lo < t2;
-    const u64 hi = (a1 >> 34) + (a2 >> 4) + c;
-    return reduce128(hi, lo, m);
+    Acc30 f = *this;
+    f.fold();    // disjoint fields: the 128-bit words without a carry chain
+    return reduce128(f.a2 >> 4, f.a0 | (f.a1 << 30) | (f.a2 << 60), m);
   }
   // the sum times 2^-64 mod q (Montgomery's REDC), for sums below q 2^64:
   // at most 16 terms whose first factors are below 2^60 and whose second
