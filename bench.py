@@ -41,7 +41,7 @@ BFLY_PEAK_G = VALU_PEAK / OPS_PER_BFLY / 1e9
 # plain copy of known size.  The figure belongs to the NTT source it was taken
 # with (its SHA-256 below); for any other source the traffic is reported as
 # null.
-NTT_TRAFFIC = {"bytes": 55823636,
+NTT_TRAFFIC = {"bytes": 55823626,
                "source_sha256": "b44b006d8ebd757dc0c360ac372d09d4a5aa0a0f663dff2da86641f7f81acfb4"}
 # Algorithmic HBM bytes of the other key-switching kernels of one plain
 # product at level 24 (N = 2^16, K = 7, dnum = 3; a limb is 512 KiB): the key
